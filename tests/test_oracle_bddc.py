@@ -1,0 +1,175 @@
+"""Pins of the oracle's BDDC-SO preconditioner and PCG (CPU)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import bddc, classify, definitional, pcg, q1
+
+
+def _tiny_cases():
+    rho2 = np.random.default_rng(4).uniform(0.1, 10.0, 12 * 12)
+    return [
+        ("fig1", W.fig1_problem()),
+        ("2d_rho", W.config1_like(n=12, H=6, L=3, cfg=11, rho=rho2)),
+        ("3d_L2", W.config2_like(n=8, H=4, L=2, cfg=12)),
+        ("3d_L3", W.config2_like(n=12, H=6, L=3, cfg=13)),
+    ]
+
+
+@pytest.mark.parametrize("name,p", _tiny_cases(), ids=[c[0] for c in _tiny_cases()])
+def test_algorithmic_equals_definitional(name, p):
+    """The step-by-step B equals Definition 1 assembled densely (no vertex
+    elimination, no coarse basis, no coarse matrix on that side)."""
+    for weighting in (0, 1):
+        alg = bddc.from_problem(p, weighting=weighting).dense()
+        ref = definitional.bddc_dense(p.n_el, p.h, p.elem_sub, p.elem_subsub, p.rho,
+                                      primal_mask=p.primal_mask, weighting=weighting)
+        assert np.linalg.norm(alg - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_partial_primal_sets():
+    # Edges-only and faces-only selections (Remark on acceptable paths) still match Definition 1.
+    p = W.config2_like(n=12, H=6, L=3, cfg=14, log_range=None)
+    for mask in (2, 3, 4, 5):
+        alg = bddc.from_problem(p, primal_mask=mask).dense()
+        ref = definitional.bddc_dense(p.n_el, p.h, p.elem_sub, p.elem_subsub, p.rho, primal_mask=mask)
+        assert np.linalg.norm(alg - ref) <= 1e-11 * np.linalg.norm(ref), mask
+
+
+@pytest.mark.parametrize("p", [W.config1_like(n=16, H=8, L=2, cfg=15), W.config2_like(n=8, H=4, L=2, cfg=16)],
+                         ids=["2d", "3d"])
+def test_every_interface_dof_primal_gives_exact_inverse(p):
+    """L = 2h: each subobject has one interior node, so W~ = U, B = A^{-1}
+    and PCG stops after one iteration."""
+    o = bddc.from_problem(p)
+    cls = o.cls
+    assert all(len(cls.obj_nodes[c]) == 1 for c in cls.coarse_objects)
+    A = o.A.toarray()
+    assert np.abs(o.dense() @ A - np.eye(A.shape[0])).max() < 1e-10
+    res = pcg.solve(o, p.f[0], rtol=1e-8)
+    assert res.iters == 1
+
+
+@pytest.mark.parametrize("name,p", _tiny_cases(), ids=[c[0] for c in _tiny_cases()])
+def test_lower_bound_theorem1(name, p):
+    """Theorem 1: the spectrum of BA lies in [1, kappa]."""
+    o = bddc.from_problem(p)
+    ev = np.linalg.eigvals(o.dense() @ o.A.toarray()).real
+    assert ev.min() >= 1.0 - 1e-10
+
+
+def test_lanczos_lower_bound_cfg1():
+    p = W.config1()
+    o = bddc.from_problem(p)
+    res = pcg.solve(o, p.f[0], rtol=1e-10)
+    lo, hi = res.eig_extremes()
+    assert lo >= 1.0 - 1e-8 and hi >= lo
+
+
+def test_lanczos_matrix_recovers_spectrum():
+    """Unpreconditioned CG on a diagonal matrix: after n steps the Lanczos
+    matrix built from (alpha, beta) has exactly the matrix's eigenvalues."""
+    lam = np.array([1.0, 2.0, 3.5, 7.0, 11.0, 20.0])
+    D = np.diag(lam)
+    b = np.ones(len(lam))
+    res = pcg.pcg(lambda v: D @ v, lambda v: v, b, fixed_iters=len(lam))
+    ev = sla.eigvalsh(res.lanczos())
+    assert np.allclose(np.sort(ev), lam, rtol=1e-9)
+
+
+def test_pcg_matches_direct_solve():
+    p = W.config1()
+    o = bddc.from_problem(p)
+    res = pcg.solve(o, p.f[0], rtol=1e-10)
+    u = spla.spsolve(o.A.tocsc(), p.f[0])
+    assert res.converged
+    assert np.linalg.norm(p.f[0] - o.A @ res.x) <= 1e-10 * np.linalg.norm(p.f[0]) * 1.0001
+    # error bounded by kappa(A) * rtol
+    kA = np.linalg.cond(o.A.toarray())
+    assert np.linalg.norm(res.x - u) <= 1e-10 * kA * np.linalg.norm(u)
+
+
+def test_kappa_decreases_with_L():
+    """Theorem 1 at fixed H = 32h (2D 128^2, 4x4 subdomains): kappa falls as
+    L shrinks, L = H is standard BDDC, L = 2h is exact, and kappa follows
+    C (1 + log(L/h))^2 with one constant."""
+    n, H = 128, 32
+    Ls = [32, 16, 8, 4, 2]
+    kappas = []
+    for L in Ls:
+        p = W.config1_like(n=n, H=H, L=L, cfg=17)
+        o = bddc.from_problem(p)
+        res = pcg.solve(o, p.f[0], rtol=1e-12, maxit=200)
+        kappas.append(res.kappa)
+    assert all(a > b for a, b in zip(kappas, kappas[1:]))
+    assert abs(kappas[-1] - 1.0) < 1e-6
+    # C estimated on L >= 4h; every point within a factor 2 of C (1+log L)^2
+    x = np.array([(1 + np.log(L)) ** 2 for L in Ls[:-1]])
+    y = np.array(kappas[:-1])
+    C = float(x @ y / (x @ x))
+    assert np.all(y <= 2.0 * C * x) and np.all(y >= 0.5 * C * x)
+
+
+def test_kappa_bounded_at_fixed_L_over_h():
+    """Fixed L/h = 4 while H/h grows: iterations stay bounded (Section 5.1)."""
+    its = []
+    for H in (8, 16, 32):
+        p = W.config1_like(n=4 * H, H=H, L=4, cfg=18)
+        o = bddc.from_problem(p)
+        its.append(pcg.solve(o, p.f[0], rtol=1e-6).iters)
+    assert max(its) - min(its) <= 1
+
+
+def test_contrast_robustness_aligned():
+    """Remark 1: rho constant per subdomain (so per subsubdomain) with the
+    coefficient weights; iterations do not grow with the contrast."""
+    its = []
+    for hi in (0.0, 2.0, 4.0, 6.0):
+        p = W.config2_like(n=16, H=4, L=2, cfg=19, log_range=(-hi / 2, hi / 2))
+        p2 = W.tensor_problem(p.n_el, [W.uniform_cuts(16, 4)] * 3, [W.uniform_cuts(16, 2)] * 3, cfg=19)
+        p2.rho = p.rho
+        o = bddc.from_problem(p2, weighting=1)
+        its.append(pcg.solve(o, p2.f[0], rtol=1e-8).iters)
+    assert max(its) - min(its) <= 1
+
+
+def test_local_invariants():
+    """C Phi = I; Phi is energy-minimal (K Phi orthogonal to ker C); K_c SPD."""
+    p = W.config2_like(n=12, H=6, L=3, cfg=20)
+    o = bddc.from_problem(p)
+    for L in o.locals[:4]:
+        assert np.abs(L.C @ L.Phi - np.eye(len(L.coarse))).max() < 1e-12
+        Cd = L.C.toarray()
+        Zc = sla.null_space(Cd)
+        assert np.abs(Zc.T @ (L.K @ L.Phi)).max() < 1e-10 * np.abs(L.K.toarray()).max()
+        assert np.allclose(L.Kc, L.Kc.T, atol=1e-12 * np.abs(L.Kc).max())
+    assert np.linalg.eigvalsh(o.Kc)[0] > 0
+
+
+def test_bddc_a_bound():
+    """Section 4: lambda_max(B_SO A) <= lambda_max(B_A A) (rho = 1)."""
+    p = W.config1_like(n=12, H=6, L=3, cfg=21)
+    so = bddc.from_problem(p).dense()
+    ba = definitional.bddc_a_dense(p.n_el, p.h, p.elem_sub, p.elem_subsub, p.rho)
+    A = q1.assemble(p.n_el, p.h, p.rho).toarray()
+    e_so = np.linalg.eigvals(so @ A).real
+    e_a = np.linalg.eigvals(ba @ A).real
+    assert e_a.min() >= 1 - 1e-9
+    assert e_so.max() <= e_a.max() + 1e-9
+
+
+def test_counting_weights_equal_rho_weights_for_constant_rho():
+    p = W.config1_like(n=12, H=6, L=3, cfg=22)
+    a = bddc.from_problem(p, weighting=0).dense()
+    b = bddc.from_problem(p, weighting=1).dense()
+    assert np.allclose(a, b, atol=1e-13)
+
+
+def test_fixed_iters_equals_free_run_prefix():
+    p = W.config1()
+    o = bddc.from_problem(p)
+    free = pcg.solve(o, p.f[0], rtol=1e-8)
+    fixed = pcg.solve(o, p.f[0], fixed_iters=free.iters)
+    assert np.array_equal(free.x, fixed.x)

@@ -1,0 +1,133 @@
+"""Pins of the oracle's subobject classification and weights (CPU)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import workloads as W
+from conftest import golden_path
+from oracle import classify, q1
+
+
+def _read_golden(name):
+    rows = []
+    with open(golden_path(name)) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+def test_fig1_subobjects_and_weights():
+    """Figure 1 right panel: 8 subedges and 5 vertices; eq. (W) example values."""
+    p = W.fig1_problem()
+    c = classify.classify(p.n_el, p.elem_sub, p.elem_subsub)
+    g = q1.Grid(p.n_el)
+    alpha = classify.subsub_alpha(p.elem_subsub, p.rho, 0)
+    counts = c.counts_by_type(selected_only=False)
+    verts = set()
+    for o in range(len(c.obj_nodes)):
+        if c.obj_type[o] == classify.TYPE_V:
+            assert len(c.obj_nodes[o]) == 1
+            verts.add(tuple(g.free_coords()[c.obj_nodes[o][0]]))
+    for row in _read_golden("fig1.txt"):
+        if row[0] == "subedges":
+            assert counts["e"] == int(row[1])
+        elif row[0] == "vertices":
+            assert counts["v"] == int(row[1])
+        elif row[0] == "vertex":
+            assert (int(row[1]), int(row[2])) in verts
+        elif row[0] == "delta":
+            xi = g.free_index(np.array([int(row[1]), int(row[2])]))
+            assert classify.weight(c, alpha, xi, int(row[4])) == pytest.approx(float(Fraction(row[5])))
+
+
+def test_fig1_multiplicity_differs():
+    # The paper contrasts delta_1(xi) = 2/3 with the multiplicity weight 1/2 at xi = (10, 5).
+    p = W.fig1_problem()
+    c = classify.classify(p.n_el, p.elem_sub, p.elem_subsub)
+    xi = q1.Grid(p.n_el).free_index(np.array([10, 5]))
+    assert len(c.node_subs[xi]) == 2          # multiplicity 2 -> weight 1/2
+    assert len(c.node_keys[int(xi)]) == 3     # three subsubdomains
+
+
+def closed_form_vef(N, k, L):
+    """Every fine vertex, edge and face on Gamma for a 3D tensor partition:
+    N subdomains per axis, n = N k / L subsubdomains per axis."""
+    n = N * k // L
+    faces = 3 * (N - 1) * n * n
+    edges = 3 * n * ((n - 1) ** 2 - (n - N) ** 2)
+    verts = (n - 1) ** 3 - (n - N) ** 3
+    return faces + edges + verts, (verts, edges, faces)
+
+
+@pytest.mark.parametrize("k", [4, 8])
+def test_table1_coarse_size_brute_force(k):
+    """Table 1, BDDC-SO(vef): brute-force classification equals the printed size."""
+    golden = {(r[0], int(r[1])): int(r[2]) for r in _read_golden("table1.txt")}
+    p = W.table1_problem(k)
+    c = classify.classify(p.n_el, p.elem_sub, p.elem_subsub)
+    total, (v, e, f) = closed_form_vef(10, k, 4)
+    assert c.n_coarse == golden[("BDDC-SO(vef)", k)] == total
+    assert c.counts_by_type() == {"v": v, "e": e, "f": f}
+
+
+def test_table1_closed_form_matches_printed():
+    golden = {(r[0], int(r[1])): int(r[2]) for r in _read_golden("table1.txt")}
+    for k in (4, 8, 16, 24):
+        assert closed_form_vef(10, k, 4)[0] == golden[("BDDC-SO(vef)", k)]
+    # L = H: subobjects are the standard objects, the coarse size does not depend on k
+    for k in (4, 8, 16):
+        assert closed_form_vef(10, k, k)[0] == golden[("BDDC(vef)", k)]
+
+
+def test_standard_bddc_is_L_equals_H():
+    p = W.table1_problem(4, L=4, subs_per_axis=3)
+    q = W.tensor_problem(p.n_el, p.extra["sub_cuts"], p.extra["sub_cuts"])
+    c = classify.classify(q.n_el, q.elem_sub, q.elem_subsub)
+    # 3x3x3 subdomains: 54 faces, 36 edges, 8 vertices
+    assert c.counts_by_type() == {"v": 8, "e": 36, "f": 54}
+
+
+def test_config_sizes():
+    """Coarse sizes of the 2D config and a reduced 3D config (H = 12h, L = 4h)."""
+    c1 = classify.classify(*(lambda p: (p.n_el, p.elem_sub, p.elem_subsub))(W.config1()))
+    assert c1.n_coarse == 177 and c1.counts_by_type() == {"v": 81, "e": 96, "f": 0}
+    p = W.config2_like(n=24, H=12, L=4)
+    c = classify.classify(p.n_el, p.elem_sub, p.elem_subsub)
+    assert c.n_coarse == closed_form_vef(2, 12, 4)[0]
+
+
+def test_weights_partition_of_unity():
+    rng = np.random.default_rng(1)
+    for p in (W.fig1_problem(), W.config2_like(n=12, H=6, L=3, cfg=9)):
+        c = classify.classify(p.n_el, p.elem_sub, p.elem_subsub)
+        for weighting in (0, 1):
+            alpha = classify.subsub_alpha(p.elem_subsub, p.rho * (1 + rng.random(p.n_elements)), weighting)
+            for node in np.nonzero(c.is_gamma)[0][::7]:
+                s = sum(classify.weight(c, alpha, node, i) for i in c.node_subs[node])
+                assert s == pytest.approx(1.0)
+
+
+def test_symmetric_split_weights_are_multiplicity():
+    # For a tensor fine partition every Gamma node's key is split evenly, so
+    # the eq. (W) weight is 1 / multiplicity.
+    p = W.config2_like(n=12, H=6, L=3, cfg=9)
+    c = classify.classify(p.n_el, p.elem_sub, p.elem_subsub)
+    alpha = classify.subsub_alpha(p.elem_subsub, p.rho, 0)
+    for node in np.nonzero(c.is_gamma)[0]:
+        for i in c.node_subs[node]:
+            assert classify.weight(c, alpha, node, i) == pytest.approx(1.0 / len(c.node_subs[node]))
+
+
+def test_objects_partition_gamma():
+    p = W.config2_like(n=12, H=6, L=3, cfg=9)
+    c = classify.classify(p.n_el, p.elem_sub, p.elem_subsub)
+    allnodes = np.concatenate(c.obj_nodes)
+    assert len(allnodes) == len(np.unique(allnodes)) == int(c.is_gamma.sum())
+    # every node of an object has the same key and the same subdomain set
+    for o, nodes in enumerate(c.obj_nodes):
+        for v in nodes:
+            assert c.node_keys[int(v)] == c.obj_key[o]
+            assert list(c.node_subs[v]) == list(c.obj_subs[o])
