@@ -1,0 +1,204 @@
+/*
+ * bddcso.h -- C ABI of the MI355X (gfx950) BDDC-SO solver.
+ *
+ * Solves the Q1 finite-element discretisation of -div(rho grad u) = f on the
+ * unit square / cube with zero Dirichlet data (the model problem of Section 2,
+ * with the variable coefficient of Remark 1) by preconditioned conjugate
+ * gradients, the preconditioner being BDDC-SO (Section 3): BDDC whose coarse
+ * degrees of freedom are point values at, or averages over, subobjects --
+ * the vertices, edges and faces of a finer partition (the subsubdomains)
+ * that lie on the interface of the subdomain partition.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Mesh: structured, n_el[0] x n_el[1] (x n_el[2]) elements, spacing h[a]
+ *    per axis.  For dim = 2, n_el[2] and h[2] are ignored.  Elements are
+ *    numbered lexicographically with x fastest.
+ *  - Unknowns: the free (non-boundary) grid nodes, numbered lexicographically
+ *    with x fastest over 1..n_el[a]-1 per axis.  n_free is their count.
+ *  - Vectors of several right-hand sides are stored [nrhs][n_free],
+ *    contiguous, FP64.
+ *  - Device pointers (suffix _dev) are HIP device memory owned by the caller;
+ *    the library never frees them.  Host pointers are read during the call
+ *    only, unless stated otherwise.
+ *  - stream: a hipStream_t passed as void*; NULL means the default stream.
+ *    Work is enqueued on that stream; calls return once it is enqueued,
+ *    except where a call says it synchronises.
+ *  - Every function returns a bddcso_status.  On error nothing is left
+ *    half-built, and bddcso_last_error() returns a message for this thread.
+ *  - Subdomains must be axis-aligned boxes of elements (every config of the
+ *    paper's experiments is); subsubdomains may have any shape but each must
+ *    lie inside one subdomain (Section 3).
+ */
+#ifndef BDDCSO_H
+#define BDDCSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BDDCSO_OK = 0,
+  BDDCSO_EINVAL = -1,     /* invalid argument or descriptor                  */
+  BDDCSO_ENOMEM = -2,     /* device or host allocation failed                */
+  BDDCSO_ESINGULAR = -3,  /* a local, constraint or coarse pivot was <= 0    */
+  BDDCSO_EBREAKDOWN = -4, /* PCG breakdown: p^T A p <= 0 or r^T z <= 0       */
+  BDDCSO_ENOCONV = -5,    /* maxit reached without meeting rtol              */
+  BDDCSO_EHIP = -6        /* a HIP runtime call failed                       */
+} bddcso_status;
+
+typedef struct bddcso_problem bddcso_problem; /* host descriptors + classification */
+typedef struct bddcso_precond bddcso_precond; /* device factors of one setup      */
+
+/* Primal object kinds (Section 3 and the remark on acceptable paths). */
+#define BDDCSO_PRIMAL_V 1
+#define BDDCSO_PRIMAL_E 2
+#define BDDCSO_PRIMAL_F 4
+
+typedef struct {
+  int primal_mask;   /* OR of BDDCSO_PRIMAL_*; 7 = every subobject ("vef")   */
+  int weighting;     /* 0: eq. (W) counting weights; 1: Remark 1, weights by
+                        the coefficient averaged over each subsubdomain       */
+  int precision;     /* 0: FP64 throughout; 1: local factors, local solves
+                        and Phi^T K Phi in FP32 (coarse problem, outer PCG
+                        recurrences and dot products stay FP64)               */
+  int coarse_solver; /* 0: nested-dissection multifrontal; 1: one dense front */
+  int max_nrhs;      /* right-hand sides the workspace is sized for (>= 1)    */
+  int maxit;         /* PCG iteration limit                                   */
+  double rtol;       /* stop when ||r_k||_2 <= rtol ||b||_2 (x0 = 0)          */
+  int fixed_iters;   /* > 0: run exactly this many iterations, no test        */
+  int flexible;      /* 1: flexible CG, beta = z_{k+1}.(r_{k+1}-r_k)/rho_k;
+                        used automatically when precision = 1               */
+  int block_target;  /* target size of the dense diagonal blocks of the local
+                        block-tridiagonal factors; 0 = default (192)          */
+} bddcso_options;
+
+/* Fills the defaults: vef, coefficient weights, FP64, multifrontal coarse,
+ * 1 RHS, maxit 1000, rtol 1e-8, no fixed count, standard CG. */
+void bddcso_default_options(bddcso_options* opts);
+
+#define BDDCSO_MAX_RHS 64
+typedef struct {
+  int nrhs;
+  int iters[BDDCSO_MAX_RHS];        /* operator applications in the loop     */
+  int converged[BDDCSO_MAX_RHS];
+  double relres[BDDCSO_MAX_RHS];    /* final ||r_k|| / ||b|| (recurrence)   */
+  double lambda_min[BDDCSO_MAX_RHS];/* extreme Lanczos eigenvalues of BA     */
+  double lambda_max[BDDCSO_MAX_RHS];
+  double kappa[BDDCSO_MAX_RHS];     /* lambda_max / lambda_min               */
+  int64_t n_coarse;
+  double t_solve_ms;                /* host wall time of the solve call      */
+} bddcso_stats;
+
+/*
+ * Creates the host descriptors and classifies the interface (Section 3):
+ * Gamma = free nodes shared by two or more subdomains; each Gamma node is
+ * keyed by the set of subsubdomains containing it (the remark on
+ * classification); connected sets of nodes with one key are the subobjects.
+ * Host only (no device work).
+ *   dim          2 or 3
+ *   n_el[3]      elements per axis (n_el[a] >= 2)
+ *   h[3]         mesh spacing per axis (> 0)
+ *   elem_sub     [n_elements] subdomain id of each element, 0..n_sub-1
+ *   elem_subsub  [n_elements] subsubdomain id, 0..n_subsub-1
+ * Errors: EINVAL for ids out of range, a subdomain that is not a box, or a
+ * subsubdomain that spans two subdomains.
+ */
+bddcso_status bddcso_problem_create(int dim, const int64_t n_el[3], const double h[3],
+                                    const int32_t* elem_sub, const int32_t* elem_subsub,
+                                    bddcso_problem** out);
+
+/* Sizes after classification; any output pointer may be NULL.  n_coarse is
+ * the number of subobjects selected by primal_mask (Table 1's "size of the
+ * coarse problem"); counts[3] receives the selected vertices, edges, faces. */
+bddcso_status bddcso_problem_info(const bddcso_problem* p, int primal_mask, int64_t* n_free,
+                                  int64_t* n_gamma, int64_t* n_coarse, int* n_sub,
+                                  int64_t counts[3]);
+
+/*
+ * Builds the preconditioner for coefficient rho (Remark 1), on the device:
+ * local matrices, block factorizations of K_II and K_rr (primal vertices
+ * eliminated), the constraint Schur complement, the coarse basis Phi_i, the
+ * local coarse matrices Phi_i^T K_i Phi_i and the factorization of the
+ * assembled coarse matrix (Section 3 with Definition 1).  Allocates the
+ * device memory it needs (freed by bddcso_precond_destroy) and synchronises
+ * the stream before returning.
+ *   rho_dev  [n_elements] FP64 device array, > 0
+ * Errors: EINVAL, ENOMEM, ESINGULAR (a pivot <= 0, e.g. a floating
+ * subdomain left without enough primal constraints), EHIP.
+ */
+bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcso_options* opts,
+                           void* stream, bddcso_precond** out);
+
+/* Recomputes every numeric factor of an existing preconditioner for a new
+ * coefficient field, reusing its plan and device memory: no allocation.
+ * Enqueued on stream; pivot failures are reported by the next
+ * bddcso_check_pivots or bddcso_solve. */
+bddcso_status bddcso_refactor(bddcso_precond* pc, const double* rho_dev, void* stream);
+
+/* Synchronises stream and returns ESINGULAR if the last setup/refactor met a
+ * non-positive pivot. */
+bddcso_status bddcso_check_pivots(bddcso_precond* pc, void* stream);
+
+/* y = A x, the matrix-free Q1 operator with the preconditioner's rho
+ * (Section 2, Remark 1).  x_dev, y_dev: [nrhs][n_free] FP64, distinct. */
+bddcso_status bddcso_operator_apply(const bddcso_precond* pc, const double* x_dev, double* y_dev,
+                                    int nrhs, void* stream);
+
+/* z = B r, the BDDC-SO preconditioner (Definition 1 with V1 = U_I,
+ * V2 = W~, Q1 = I, Q2 = (I - P) E; Section 3).  r_dev, z_dev:
+ * [nrhs][n_free] FP64, distinct; nrhs <= max_nrhs. */
+bddcso_status bddcso_apply(bddcso_precond* pc, const double* r_dev, double* z_dev, int nrhs,
+                           void* stream);
+
+/*
+ * Solves A x = b by PCG preconditioned with BDDC-SO (Section 5's solver),
+ * from x0 = 0, every right-hand side with its own recurrence, in lockstep;
+ * converged columns are frozen.  Synchronises the stream once per iteration
+ * for the convergence test (not in fixed_iters mode).
+ *   b_dev, x_dev: [nrhs][n_free] FP64 device arrays; nrhs <= max_nrhs.
+ *   stats: host struct filled on return (may be NULL).
+ * Errors: EBREAKDOWN, ENOCONV (x holds the last iterate), ESINGULAR.
+ */
+bddcso_status bddcso_solve(bddcso_precond* pc, const double* b_dev, double* x_dev, int nrhs,
+                           bddcso_stats* stats, void* stream);
+
+/* Element gradient of a loss through the solve:
+ *   g_e = -rho_e * sum_k lam_k,e^T K^_e u_k,e
+ * with K^_e the unit-coefficient Q1 element matrix and u_e, lam_e the
+ * element's nodal values (zero at boundary nodes); the sum runs over the
+ * nrhs columns.  u_dev, lam_dev: [nrhs][n_free]; g_dev: [n_elements]. */
+bddcso_status bddcso_element_grad(const bddcso_precond* pc, const double* u_dev,
+                                  const double* lam_dev, double* g_dev, int nrhs, void* stream);
+
+/* 3^dim box mean of an element field over in-domain neighbours (normalised
+ * by their count), or its transpose when transpose != 0.
+ * in_dev, out_dev: [n_elements] FP64, distinct. */
+bddcso_status bddcso_box_filter(const bddcso_problem* p, const double* in_dev, double* out_dev,
+                                int transpose, void* stream);
+
+/* Sizes of one preconditioner: coarse dofs, fronts of the coarse factor,
+ * device bytes held.  Any pointer may be NULL. */
+bddcso_status bddcso_precond_info(const bddcso_precond* pc, int64_t* n_coarse, int64_t* n_fronts,
+                                  int64_t* device_bytes, int64_t* coarse_factor_entries);
+
+/* Copies subdomain sub's local coarse matrix Phi_i^T K_i Phi_i (column-major,
+ * n_c x n_c, FP64) and the global coarse ids of its rows to host buffers of
+ * at least cap_nc entries (resp. cap_nc^2).  Synchronises the stream.
+ * *nc receives n_c.  For checks of the setup one subdomain at a time. */
+bddcso_status bddcso_local_coarse(const bddcso_precond* pc, int sub, double* kc_host,
+                                  int64_t* ids_host, int64_t cap_nc, int64_t* nc, void* stream);
+
+void bddcso_precond_destroy(bddcso_precond* pc);
+void bddcso_problem_destroy(bddcso_problem* p);
+
+/* Message of the last non-OK status returned on this thread ("" if none). */
+const char* bddcso_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDDCSO_H */

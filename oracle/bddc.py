@@ -86,7 +86,7 @@ class BDDCSO:
     application of the BDDC-SO preconditioner."""
 
     def __init__(self, n_el, h, elem_sub, elem_subsub, rho, primal_mask: int = 7,
-                 weighting: int = 1, cls: Classification = None):
+                 weighting: int = 1, cls: Classification = None, local_only: bool = False):
         self.grid = q1.Grid(n_el)
         self.n_el = tuple(n_el)
         self.h = h
@@ -108,43 +108,55 @@ class BDDCSO:
             for s in cls.obj_subs[o]:
                 sub_coarse[s].append(c)
 
+        self.sub_coarse = sub_coarse
+        self._Ke = Ke
+        self._elem_order = (order, bounds)
         self.locals: List[Local] = []
+        if local_only:
+            return
         Kc = np.zeros((cls.n_coarse, cls.n_coarse))
         for i in range(cls.n_sub):
-            nodes = cls.sub_nodes[i]
-            elements = order[bounds[i]:bounds[i + 1]]
-            K = _local_matrix(self.grid, Ke, self.rho, elements, nodes)
-            gmask = cls.is_gamma[nodes]
-            interior = np.nonzero(~gmask)[0]
-            gamma = np.nonzero(gmask)[0]
-            delta = np.array([weight(cls, self.alpha, nodes[k], i) for k in gamma])
-            coarse = np.array(sorted(sub_coarse[i]), dtype=np.int64)
-            # one row per selected functional: value at a node or mean over an object
-            rows, cols, vals = [], [], []
-            for a, c in enumerate(coarse):
-                onodes = cls.obj_nodes[cls.coarse_objects[c]]
-                li = np.searchsorted(nodes, onodes)
-                rows.extend([a] * len(li))
-                cols.extend(li.tolist())
-                vals.extend([1.0 / len(li)] * len(li))
-            nc = len(coarse)
-            n = len(nodes)
-            C = sp.coo_matrix((vals, (rows, cols)), shape=(nc, n)).tocsr()
-            K_II = K[interior][:, interior].tocsc()
-            lu_II = spla.splu(K_II) if len(interior) else None
-            kkt = sp.bmat([[K, C.T], [C, None]]).tocsc()
-            lu_kkt = spla.splu(kkt)
-            # coarse basis: min energy with C Phi = I (one column per local coarse dof)
-            rhs = np.zeros((n + nc, nc))
-            rhs[n:, :] = np.eye(nc)
-            Phi = lu_kkt.solve(rhs)[:n, :] if nc else np.zeros((n, 0))
-            Kc_i = Phi.T @ (K @ Phi)
-            Kc[np.ix_(coarse, coarse)] += Kc_i
-            self.locals.append(Local(nodes, K, interior, gamma, delta, coarse, C, lu_II,
-                                     lu_kkt, Phi, Kc_i,
-                                     K[gamma][:, interior].tocsr(), K[interior][:, gamma].tocsr()))
+            L = self.local(i)
+            Kc[np.ix_(L.coarse, L.coarse)] += L.Kc
+            self.locals.append(L)
         self.Kc = Kc
         self.Kc_factor = sla.cho_factor(Kc, lower=True) if cls.n_coarse else None
+
+    def local(self, i: int) -> Local:
+        """Setup of subdomain i alone: K_i, K_II factor, constrained Neumann
+        KKT factor, coarse basis Phi_i and Phi_i^T K_i Phi_i (Section 3)."""
+        cls = self.cls
+        order, bounds = self._elem_order
+        nodes = cls.sub_nodes[i]
+        elements = order[bounds[i]:bounds[i + 1]]
+        K = _local_matrix(self.grid, self._Ke, self.rho, elements, nodes)
+        gmask = cls.is_gamma[nodes]
+        interior = np.nonzero(~gmask)[0]
+        gamma = np.nonzero(gmask)[0]
+        delta = np.array([weight(cls, self.alpha, nodes[k], i) for k in gamma])
+        coarse = np.array(sorted(self.sub_coarse[i]), dtype=np.int64)
+        # one row per selected functional: value at a node or mean over an object
+        rows, cols, vals = [], [], []
+        for a, c in enumerate(coarse):
+            onodes = cls.obj_nodes[cls.coarse_objects[c]]
+            li = np.searchsorted(nodes, onodes)
+            rows.extend([a] * len(li))
+            cols.extend(li.tolist())
+            vals.extend([1.0 / len(li)] * len(li))
+        nc = len(coarse)
+        n = len(nodes)
+        C = sp.coo_matrix((vals, (rows, cols)), shape=(nc, n)).tocsr()
+        K_II = K[interior][:, interior].tocsc()
+        lu_II = spla.splu(K_II) if len(interior) else None
+        kkt = sp.bmat([[K, C.T], [C, None]]).tocsc()
+        lu_kkt = spla.splu(kkt)
+        # coarse basis: min energy with C Phi = I (one column per local coarse dof)
+        rhs = np.zeros((n + nc, nc))
+        rhs[n:, :] = np.eye(nc)
+        Phi = lu_kkt.solve(rhs)[:n, :] if nc else np.zeros((n, 0))
+        Kc_i = Phi.T @ (K @ Phi)
+        return Local(nodes, K, interior, gamma, delta, coarse, C, lu_II, lu_kkt, Phi, Kc_i,
+                     K[gamma][:, interior].tocsr(), K[interior][:, gamma].tocsr())
 
     # ------------------------------------------------------------------
     def apply(self, r: np.ndarray, return_parts: bool = False):

@@ -1,0 +1,943 @@
+// C ABI of the BDDC-SO solver: planning, device memory, setup, the
+// preconditioner application and the PCG driver.  Every numeric step runs in
+// the kernels of kernels.hip on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/bddcso.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace bddcso;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bddcso_status set_err(bddcso_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+struct HipFail {
+  hipError_t e;
+  std::string where;
+};
+
+#define HIPCHK(x)                                                        \
+  do {                                                                   \
+    hipError_t e_ = (x);                                                 \
+    if (e_ != hipSuccess) throw HipFail{e_, std::string(#x)};            \
+  } while (0)
+
+// The unit-coefficient Q1 element matrix, indexed [a*8+b] with local node
+// a = bit x + 2 bit y + 4 bit z.  It is the tensor sum of 1D stiffness
+// (1/h)[1 -1; -1 1] and mass h/6 [2 1; 1 2] factors.  In 2D the z bit is
+// ignored (the table is replicated over it).
+void element_table(int dim, const double h[3], double out[64]) {
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b) {
+      double k[3], m[3];
+      for (int d = 0; d < 3; ++d) {
+        bool same = ((a >> d) & 1) == ((b >> d) & 1);
+        k[d] = (same ? 1.0 : -1.0) / h[d];
+        m[d] = h[d] * (same ? 2.0 : 1.0) / 6.0;
+      }
+      out[a * 8 + b] = dim == 3 ? k[0] * m[1] * m[2] + m[0] * k[1] * m[2] + m[0] * m[1] * k[2]
+                                : k[0] * m[1] + m[0] * k[1];
+    }
+}
+
+// Extreme eigenvalues of a symmetric tridiagonal matrix by Sturm-sequence
+// bisection (Wilkinson, The Algebraic Eigenvalue Problem, ch. 5).
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < d.size(); ++i) {
+    double off = i ? e[i - 1] * e[i - 1] : 0.0;
+    q = d[i] - x - (i ? off / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e, double& lo, double& hi) {
+  const int n = (int)d.size();
+  if (n == 0) {
+    lo = hi = 1.0;
+    return;
+  }
+  double a = 1e300, b = -1e300;
+  for (int i = 0; i < n; ++i) {
+    double r = (i ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+    a = std::min(a, d[i] - r);
+    b = std::max(b, d[i] + r);
+  }
+  auto kth = [&](int k) {  // k-th smallest eigenvalue, 0-based
+    double l = a, u = b;
+    for (int it = 0; it < 200; ++it) {
+      double mid = 0.5 * (l + u);
+      if (sturm_count(d, e, mid) > k) u = mid;
+      else l = mid;
+      if (u - l <= 1e-15 * std::max(std::fabs(l), std::fabs(u))) break;
+    }
+    return 0.5 * (l + u);
+  };
+  lo = kth(0);
+  hi = kth(n - 1);
+}
+
+struct DevMem {
+  std::vector<void*> ptrs;
+  int64_t bytes = 0;
+  template <typename T>
+  T* alloc(int64_t n) {
+    if (n <= 0) n = 1;
+    void* p = nullptr;
+    size_t b = (size_t)n * sizeof(T);
+    HIPCHK(hipMalloc(&p, b));
+    ptrs.push_back(p);
+    bytes += (int64_t)b;
+    return (T*)p;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v, hipStream_t s) {
+    T* p = alloc<T>((int64_t)v.size());
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+struct Batch {
+  void* desc = nullptr;  // device descriptor array
+  int n = 0, maxm = 0, maxn = 0, maxp = 0;
+};
+
+}  // namespace
+
+struct bddcso_problem {
+  Classification c;
+  std::map<std::tuple<int, int, int>, std::shared_ptr<Plan>> plans;
+  double khat[64];
+};
+
+namespace {
+
+template <typename T>
+struct Numeric {
+  T *G = nullptr, *Z = nullptr, *XG = nullptr, *Sc = nullptr, *Tm = nullptr, *Lam = nullptr,
+    *Phi = nullptr, *KPhi = nullptr, *PhiG = nullptr, *Kc = nullptr;
+  T *W = nullptr, *tmp = nullptr, *sw = nullptr;
+  int64_t wstride = 0, tmp_stride = 0, sw_stride = 0;
+  // per-iteration
+  T *vI = nullptr, *vR = nullptr, *q = nullptr, *gv = nullptr, *v2 = nullptr, *mu = nullptr, *bci = nullptr;
+};
+
+}  // namespace
+
+struct bddcso_precond {
+  bddcso_problem* prob = nullptr;
+  std::shared_ptr<Plan> plan;
+  bddcso_options opt{};
+  Geo geo{};
+  PlanDev P{};
+  DevMem mem;
+  int precision = 0;
+  Numeric<double> nd;
+  Numeric<float> nf;
+  double *rho = nullptr, *alpha = nullptr, *delta = nullptr, *khat = nullptr;
+  double *fpool = nullptr, *fsw = nullptr, *bc = nullptr, *uc = nullptr, *fvec = nullptr, *xh = nullptr;
+  int64_t fsw_stride = 0;
+  int32_t* status = nullptr;
+  // batches
+  std::vector<Batch> swI, swR, gfwd, gbwd;
+  Batch swSc, gLam, gPhiR, gKc;
+  std::vector<Batch> swFront;                       // per level
+  std::vector<int32_t*> color_dev;                  // per colour
+  std::vector<int> color_n;
+  std::vector<std::vector<int32_t*>> slot_dev;      // [level][slot]
+  std::vector<std::vector<int>> slot_n, slot_maxn;
+  std::vector<int32_t*> level_dev;
+  std::vector<int> level_n, level_maxn, level_maxp, level_maxb;
+  // PCG
+  double *r = nullptr, *p = nullptr, *qv = nullptr, *z = nullptr, *rold = nullptr, *dtmp = nullptr;
+  double* partial = nullptr;
+  int dot_blocks = 512;
+  double* sc = nullptr;  // scalar slots, 8 x max_nrhs
+  double *hist_a = nullptr, *hist_b = nullptr;
+  int32_t *active = nullptr, *iters = nullptr, *flags = nullptr, *nactive = nullptr;
+  int32_t* h_nactive = nullptr;  // pinned
+  int max_nrhs = 1;
+};
+
+namespace {
+
+template <typename T>
+Numeric<T>& num(bddcso_precond* pc);
+template <>
+Numeric<double>& num<double>(bddcso_precond* pc) {
+  return pc->nd;
+}
+template <>
+Numeric<float>& num<float>(bddcso_precond* pc) {
+  return pc->nf;
+}
+
+Batch make_gemm_batch(DevMem& mem, const std::vector<GemmDesc>& v, hipStream_t s) {
+  Batch b;
+  b.n = (int)v.size();
+  for (auto& d : v) {
+    b.maxm = std::max(b.maxm, d.m);
+    b.maxn = std::max(b.maxn, d.n);
+  }
+  b.desc = mem.upload(v, s);
+  return b;
+}
+
+Batch make_sweep_batch(DevMem& mem, const std::vector<SweepDesc>& v, hipStream_t s) {
+  Batch b;
+  b.n = (int)v.size();
+  for (auto& d : v) {
+    b.maxn = std::max(b.maxn, d.n);
+    b.maxp = std::max(b.maxp, d.p);
+  }
+  b.desc = mem.upload(v, s);
+  return b;
+}
+
+template <typename T>
+void alloc_numeric(bddcso_precond* pc, hipStream_t s) {
+  const Plan& pl = *pc->plan;
+  Numeric<T>& N = num<T>(pc);
+  DevMem& m = pc->mem;
+  const int nr = pc->max_nrhs;
+  N.G = m.alloc<T>(pl.pool_G);
+  N.Z = m.alloc<T>(pl.pool_Z);
+  N.XG = m.alloc<T>(pl.pool_XG);
+  N.Sc = m.alloc<T>(pl.pool_Sc);
+  N.Tm = m.alloc<T>(pl.pool_T);
+  N.Lam = m.alloc<T>(pl.pool_T);
+  N.Phi = m.alloc<T>(pl.pool_Phi);
+  N.KPhi = m.alloc<T>(pl.pool_Phi);
+  N.PhiG = m.alloc<T>(pl.pool_PhiG);
+  N.Kc = m.alloc<T>(pl.pool_Kc);
+  int max_plane = pc->P.max_plane;
+  N.wstride = (int64_t)max_plane * max_plane;
+  N.W = m.alloc<T>(N.wstride * pl.subs.size());
+  N.tmp_stride = (int64_t)pl.max_block * std::max(pl.max_zcols, 1);
+  N.tmp = m.alloc<T>(N.tmp_stride * pl.subs.size());
+  int maxsw = std::max(pl.max_block, pl.max_na);
+  N.sw_stride = (int64_t)maxsw * 32 + 32 * 32;
+  N.sw = m.alloc<T>(N.sw_stride * pl.subs.size());
+  N.vI = m.alloc<T>(pl.tot_I * nr);
+  N.vR = m.alloc<T>(pl.tot_r * nr);
+  N.q = m.alloc<T>(pl.tot_g * nr);
+  N.gv = m.alloc<T>(pl.tot_g * nr);
+  N.v2 = m.alloc<T>(pl.tot_g * nr);
+  N.mu = m.alloc<T>(pl.tot_a * nr);
+  N.bci = m.alloc<T>(pl.tot_c * nr);
+  (void)s;
+}
+
+// Builds every descriptor batch of the plan (static for the precond's life).
+void build_batches(bddcso_precond* pc, hipStream_t s) {
+  const Plan& pl = *pc->plan;
+  DevMem& m = pc->mem;
+  const int ns = (int)pl.subs.size();
+  const int64_t tmp_stride = (int64_t)pl.max_block * std::max(pl.max_zcols, 1);
+  for (int setR = 0; setR < 2; ++setR) {
+    int nbmax = setR ? pl.max_nbR : pl.max_nbI;
+    auto& vec = setR ? pc->swR : pc->swI;
+    for (int k = 0; k < nbmax; ++k) {
+      std::vector<SweepDesc> d;
+      for (int sidx = 0; sidx < ns; ++sidx) {
+        const SubDev& S = pl.subs[sidx];
+        int nb = setR ? S.nbR : S.nbI;
+        if (k >= nb) continue;
+        const BlockDev& B = pl.blocks[(setR ? S.bR_off : S.bI_off) + k];
+        d.push_back({B.G_off, B.size, B.size, B.size});
+      }
+      vec.push_back(make_sweep_batch(m, d, s));
+    }
+  }
+  for (int k = 0; k < pl.max_nbR; ++k) {
+    std::vector<GemmDesc> f, b;
+    for (int sidx = 0; sidx < ns; ++sidx) {
+      const SubDev& S = pl.subs[sidx];
+      int ncols = S.n_a + S.n_v;
+      if (k >= S.nbR || ncols == 0) continue;
+      const BlockDev& B = pl.blocks[S.bR_off + k];
+      f.push_back({B.G_off, sidx * tmp_stride, S.Z_off + B.start, B.size, ncols, B.size, B.size, B.size, S.n_r});
+      if (k + 1 < S.nbR) {
+        const BlockDev& N = pl.blocks[S.bR_off + k + 1];
+        if (B.plane_hi == N.plane_lo)
+          b.push_back({B.G_off + (int64_t)B.size * (B.size - B.last_n), sidx * tmp_stride, S.Z_off + B.start,
+                       B.size, ncols, B.last_n, B.size, B.last_n, S.n_r});
+      }
+    }
+    pc->gfwd.push_back(make_gemm_batch(m, f, s));
+    pc->gbwd.push_back(make_gemm_batch(m, b, s));
+  }
+  {
+    std::vector<SweepDesc> d;
+    std::vector<GemmDesc> lam, phir, kc;
+    for (int sidx = 0; sidx < ns; ++sidx) {
+      const SubDev& S = pl.subs[sidx];
+      if (S.n_a > 0) {
+        d.push_back({S.Sc_off, S.n_a, S.n_a, S.n_a});
+        if (S.n_c > 0) {
+          lam.push_back({S.Sc_off, S.T_off, S.T_off, S.n_a, S.n_c, S.n_a, S.n_a, S.n_a, S.n_a});
+          phir.push_back({S.Z_off, S.T_off, S.KPhi_off, S.n_r, S.n_c, S.n_a, S.n_r, S.n_a, S.n_r});
+        }
+      }
+      if (S.n_c > 0) kc.push_back({S.Phi_off, S.KPhi_off, S.Kc_off, S.n_c, S.n_c, S.n_loc, S.n_loc, S.n_loc, S.n_c});
+    }
+    pc->swSc = make_sweep_batch(m, d, s);
+    pc->gLam = make_gemm_batch(m, lam, s);
+    pc->gPhiR = make_gemm_batch(m, phir, s);
+    pc->gKc = make_gemm_batch(m, kc, s);
+  }
+  // colours
+  for (auto& cs : pl.color_subs) {
+    pc->color_dev.push_back(m.upload(cs, s));
+    pc->color_n.push_back((int)cs.size());
+  }
+  // fronts per level
+  const int nlev = (int)pl.level_fronts.size();
+  pc->slot_dev.assign(nlev, {});
+  pc->slot_n.assign(nlev, {});
+  pc->slot_maxn.assign(nlev, {});
+  int maxfn = 0;
+  for (int L = 0; L < nlev; ++L) {
+    std::vector<SweepDesc> d;
+    int mn = 0, mp = 0, mb = 0;
+    for (int t : pl.level_fronts[L]) {
+      const FrontDev& F = pl.fronts[t];
+      d.push_back({F.off, F.n, F.p, F.n});
+      mn = std::max(mn, F.n);
+      mp = std::max(mp, F.p);
+      mb = std::max(mb, F.n - F.p);
+      maxfn = std::max(maxfn, F.n);
+    }
+    pc->swFront.push_back(make_sweep_batch(m, d, s));
+    pc->level_dev.push_back(m.upload(pl.level_fronts[L], s));
+    pc->level_n.push_back((int)pl.level_fronts[L].size());
+    pc->level_maxn.push_back(mn);
+    pc->level_maxp.push_back(mp);
+    pc->level_maxb.push_back(mb);
+    for (auto& ch : pl.level_slot_children[L]) {
+      int cm = 0;
+      for (int c : ch) cm = std::max(cm, pl.fronts[c].n - pl.fronts[c].p);
+      pc->slot_dev[L].push_back(m.upload(ch, s));
+      pc->slot_n[L].push_back((int)ch.size());
+      pc->slot_maxn[L].push_back(cm);
+    }
+  }
+  int maxlev = 1;
+  for (int L = 0; L < nlev; ++L) maxlev = std::max(maxlev, pc->level_n[L]);
+  pc->fsw_stride = (int64_t)std::max(maxfn, 1) * 32 + 32 * 32;
+  pc->fsw = m.alloc<double>(pc->fsw_stride * maxlev);
+}
+
+template <typename T>
+void numeric_setup(bddcso_precond* pc, hipStream_t s) {
+  const Plan& pl = *pc->plan;
+  Numeric<T>& N = num<T>(pc);
+  const PlanDev& P = pc->P;
+  const Geo& g = pc->geo;
+  const double* rho = pc->rho;
+  launch_fill_i32(pc->status, 1, 0, s);
+  launch_alpha(P, pc->prob->c.n_ss, rho, pc->opt.weighting, pc->alpha, s);
+  launch_delta(P, pc->alpha, pc->delta, s);
+  // local block-tridiagonal factors of K_II and K_rr
+  if (sizeof(T) == 8) launch_fill_f64((double*)N.G, pl.pool_G, 0.0, s);
+  else launch_fill_f32((float*)N.G, pl.pool_G, 0.0f, s);
+  for (int setR = 0; setR < 2; ++setR) {
+    Kern<T>::block_assemble(P, g, rho, setR, N.G, s);
+    auto& sw = setR ? pc->swR : pc->swI;
+    for (int k = 0; k < (int)sw.size(); ++k) {
+      if (k > 0) Kern<T>::schur_couple(P, g, rho, setR, k, N.G, N.W, N.wstride, s);
+      Kern<T>::sweep((SweepDesc*)sw[k].desc, sw[k].n, sw[k].maxn, sw[k].maxp, N.G, N.sw, N.sw_stride,
+                     pc->status, setR ? 2 : 1, s);
+    }
+  }
+  // [X | Y'] = K_rr^{-1} [C_r^T | -K_rv]
+  if (sizeof(T) == 8) launch_fill_f64((double*)N.Z, pl.pool_Z, 0.0, s);
+  else launch_fill_f32((float*)N.Z, pl.pool_Z, 0.0f, s);
+  Kern<T>::rhs_fill(P, g, rho, N.Z, s);
+  const int nk = (int)pc->gfwd.size();
+  for (int k = 0; k < nk; ++k) {
+    if (k > 0) Kern<T>::couple_multi(P, g, rho, k, 1, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
+    Kern<T>::copy_block_rows(P, k, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
+    const Batch& b = pc->gfwd[k];
+    Kern<T>::gemm((GemmDesc*)b.desc, b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)-1, (T)0, s);
+  }
+  for (int k = nk - 2; k >= 0; --k) {
+    Kern<T>::couple_multi(P, g, rho, k, 0, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
+    const Batch& b = pc->gbwd[k];
+    Kern<T>::gemm((GemmDesc*)b.desc, b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)1, (T)1, s);
+  }
+  // constraint Schur complement and the coarse basis
+  Kern<T>::sc_assemble(P, N.Z, N.Sc, s);
+  Kern<T>::sweep((SweepDesc*)pc->swSc.desc, pc->swSc.n, pc->swSc.maxn, pc->swSc.maxp, N.Sc, N.sw, N.sw_stride,
+                 pc->status, 3, s);
+  Kern<T>::lambda_rhs(P, N.Z, N.Tm, s);
+  Kern<T>::gemm((GemmDesc*)pc->gLam.desc, pc->gLam.n, pc->gLam.maxm, pc->gLam.maxn, N.Sc, 0, N.Tm, 0, N.Lam,
+                (T)-1, (T)0, s);
+  Kern<T>::phi_r_init(P, N.Z, N.KPhi, s);
+  Kern<T>::gemm((GemmDesc*)pc->gPhiR.desc, pc->gPhiR.n, pc->gPhiR.maxm, pc->gPhiR.maxn, N.Z, 0, N.Lam, 0,
+                N.KPhi, (T)-1, (T)1, s);
+  Kern<T>::phi_scatter(P, N.KPhi, N.Phi, s);
+  Kern<T>::local_apply_multi(P, g, rho, N.Phi, N.KPhi, s);
+  Kern<T>::gemm((GemmDesc*)pc->gKc.desc, pc->gKc.n, pc->gKc.maxm, pc->gKc.maxn, N.Phi, 1, N.KPhi, 0, N.Kc,
+                (T)1, (T)0, s);
+  Kern<T>::extract_gamma(P, N.Phi, N.Z, N.PhiG, N.XG, s);
+  // coarse: assemble into the fronts and factor level by level (FP64)
+  launch_fill_f64(pc->fpool, pl.front_pool, 0.0, s);
+  for (size_t c = 0; c < pc->color_dev.size(); ++c)
+    Kern<T>::kc_to_front(P, pc->color_dev[c], pc->color_n[c], N.Kc, pc->fpool, s);
+  for (size_t L = 0; L < pc->swFront.size(); ++L) {
+    for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
+      launch_front_child_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fpool, s);
+    const Batch& b = pc->swFront[L];
+    Kern<double>::sweep((SweepDesc*)b.desc, b.n, b.maxn, b.maxp, pc->fpool, pc->fsw, pc->fsw_stride, pc->status,
+                        4, s);
+  }
+}
+
+void coarse_solve(bddcso_precond* pc, int nrhs, hipStream_t s) {
+  const PlanDev& P = pc->P;
+  const Plan& pl = *pc->plan;
+  const int nlev = (int)pc->level_dev.size();
+  const int64_t stride = pl.front_vec;
+  for (int L = 0; L < nlev; ++L)
+    launch_front_vec_init(P, pc->level_dev[L], pc->level_n[L], pc->level_maxn[L], pc->bc, pc->fvec, stride, nrhs,
+                          s);
+  for (int L = 0; L < nlev; ++L) {
+    for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
+      launch_front_vec_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fvec, stride,
+                               nrhs, s);
+    launch_front_fwd(P, pc->level_dev[L], pc->level_n[L], pc->level_maxn[L], pc->level_maxp[L], pc->fpool,
+                     pc->fvec, pc->xh, stride, nrhs, s);
+  }
+  for (int L = nlev - 1; L >= 0; --L)
+    launch_front_bwd(P, pc->level_dev[L], pc->level_n[L], pc->level_maxp[L], pc->level_maxb[L], pc->fpool, pc->xh,
+                     stride, pc->uc, nrhs, s);
+}
+
+template <typename T>
+void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream_t s) {
+  const Plan& pl = *pc->plan;
+  Numeric<T>& N = num<T>(pc);
+  const PlanDev& P = pc->P;
+  const Geo& g = pc->geo;
+  const double* rho = pc->rho;
+  // 1-2: Dirichlet solves and (I - P)^T on Gamma
+  Kern<T>::gather_I(P, g, r, N.vI, nrhs, s);
+  Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s);
+  Kern<T>::gamma_kgi(P, g, rho, N.vI, N.q, nrhs, s);
+  // 3: E^T
+  Kern<T>::gamma_t(P, g, r, N.q, pc->delta, N.gv, nrhs, s);
+  // 4: constrained Neumann solves
+  if (sizeof(T) == 8) launch_fill_f64((double*)N.vR, pl.tot_r * nrhs, 0.0, s);
+  else launch_fill_f32((float*)N.vR, pl.tot_r * nrhs, 0.0f, s);
+  Kern<T>::neumann_rhs(P, N.gv, N.vR, nrhs, s);
+  Kern<T>::block_solve(P, g, rho, 1, N.G, N.vR, nrhs, s);
+  Kern<T>::mu(P, N.vR, N.Sc, N.mu, nrhs, s);
+  // 5-6: coarse problem
+  Kern<T>::coarse_rhs_local(P, N.PhiG, N.gv, N.bci, nrhs, s);
+  if (sizeof(T) == 8) launch_coarse_rhs_gather(P, (const double*)N.bci, nullptr, pc->bc, nrhs, s);
+  else launch_coarse_rhs_gather(P, nullptr, (const float*)N.bci, pc->bc, nrhs, s);
+  coarse_solve(pc, nrhs, s);
+  // 7-8: v2 on Gamma and E
+  Kern<T>::v2(P, N.vR, N.XG, N.mu, N.PhiG, pc->uc, N.v2, nrhs, s);
+  if (sizeof(T) == 8) launch_gamma_w(P, g, (const double*)N.v2, nullptr, pc->delta, z, nrhs, s);
+  else launch_gamma_w(P, g, nullptr, (const float*)N.v2, pc->delta, z, nrhs, s);
+  // 9-10: harmonic extension into the interiors
+  Kern<T>::interior_rhs(P, g, rho, r, z, N.vI, nrhs, s);
+  Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s);
+  Kern<T>::scatter_I(P, g, N.vI, z, nrhs, s);
+}
+
+void apply_B_any(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream_t s) {
+  if (pc->precision == 1) apply_B<float>(pc, r, z, nrhs, s);
+  else apply_B<double>(pc, r, z, nrhs, s);
+}
+
+std::shared_ptr<Plan> get_plan(bddcso_problem* p, const bddcso_options& o, Error& err) {
+  int bt = o.block_target > 0 ? o.block_target : 192;
+  auto key = std::make_tuple(o.primal_mask, bt, o.coarse_solver);
+  auto it = p->plans.find(key);
+  if (it != p->plans.end()) return it->second;
+  auto pl = std::make_shared<Plan>();
+  if (!build_plan(p->c, o.primal_mask, bt, o.coarse_solver, *pl, err)) return nullptr;
+  p->plans[key] = pl;
+  return pl;
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+}  // namespace
+
+extern "C" {
+
+void bddcso_default_options(bddcso_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->primal_mask = 7;
+  o->weighting = 1;
+  o->precision = 0;
+  o->coarse_solver = 0;
+  o->max_nrhs = 1;
+  o->maxit = 1000;
+  o->rtol = 1e-8;
+  o->fixed_iters = 0;
+  o->flexible = 0;
+  o->block_target = 0;
+}
+
+const char* bddcso_last_error(void) { return g_last_error.c_str(); }
+
+bddcso_status bddcso_problem_create(int dim, const int64_t n_el[3], const double h[3], const int32_t* elem_sub,
+                                    const int32_t* elem_subsub, bddcso_problem** out) {
+  if (!out) return set_err(BDDCSO_EINVAL, "null output pointer");
+  *out = nullptr;
+  auto* p = new (std::nothrow) bddcso_problem();
+  if (!p) return set_err(BDDCSO_ENOMEM, "host allocation failed");
+  Error err;
+  try {
+    if (!classify(dim, n_el, h, elem_sub, elem_subsub, p->c, err)) {
+      delete p;
+      return set_err(BDDCSO_EINVAL, err.msg);
+    }
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return set_err(BDDCSO_ENOMEM, "host allocation failed during classification");
+  }
+  element_table(dim, p->c.h, p->khat);
+  *out = p;
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_problem_info(const bddcso_problem* p, int primal_mask, int64_t* n_free, int64_t* n_gamma,
+                                  int64_t* n_coarse, int* n_sub, int64_t counts[3]) {
+  if (!p) return set_err(BDDCSO_EINVAL, "null problem");
+  if (n_free) *n_free = p->c.n_free;
+  if (n_gamma) *n_gamma = (int64_t)p->c.gam_node.size();
+  if (n_sub) *n_sub = p->c.n_sub;
+  int64_t cnt[3] = {0, 0, 0};
+  for (int o = 0; o < p->c.n_obj(); ++o)
+    if (p->c.obj_type[o] & primal_mask) {
+      int t = p->c.obj_type[o];
+      cnt[t == 1 ? 0 : (t == 2 ? 1 : 2)]++;
+    }
+  if (n_coarse) *n_coarse = cnt[0] + cnt[1] + cnt[2];
+  if (counts) {
+    counts[0] = cnt[0];
+    counts[1] = cnt[1];
+    counts[2] = cnt[2];
+  }
+  return BDDCSO_OK;
+}
+
+void bddcso_precond_destroy(bddcso_precond* pc) {
+  if (!pc) return;
+  pc->mem.release();
+  if (pc->h_nactive) (void)hipHostFree(pc->h_nactive);
+  delete pc;
+}
+
+void bddcso_problem_destroy(bddcso_problem* p) { delete p; }
+
+bddcso_status bddcso_refactor(bddcso_precond* pc, const double* rho_dev, void* stream) {
+  if (!pc || !rho_dev) return set_err(BDDCSO_EINVAL, "null argument");
+  hipStream_t s = as_stream(stream);
+  try {
+    HIPCHK(hipMemcpyAsync(pc->rho, rho_dev, pc->geo.n_elem * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (pc->precision == 1) numeric_setup<float>(pc, s);
+    else numeric_setup<double>(pc, s);
+    HIPCHK(hipGetLastError());
+  } catch (const HipFail& f) {
+    return set_err(BDDCSO_EHIP, f.where + ": " + hipGetErrorString(f.e));
+  }
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_check_pivots(bddcso_precond* pc, void* stream) {
+  if (!pc) return set_err(BDDCSO_EINVAL, "null precond");
+  int st = 0;
+  hipStream_t s = as_stream(stream);
+  if (hipMemcpyAsync(&st, pc->status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_err(BDDCSO_EHIP, "status copy failed");
+  static const char* what[] = {"", "an interior (Dirichlet) block", "a constrained Neumann block",
+                               "the constraint Schur complement", "the coarse matrix"};
+  if (st > 0)
+    return set_err(BDDCSO_ESINGULAR, std::string("non-positive pivot in ") + what[std::min(st, 4)] +
+                                         " (not enough primal constraints, or rho <= 0)");
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcso_options* opts, void* stream,
+                           bddcso_precond** out) {
+  if (!p || !rho_dev || !out) return set_err(BDDCSO_EINVAL, "null argument");
+  *out = nullptr;
+  bddcso_options o;
+  if (opts) o = *opts;
+  else bddcso_default_options(&o);
+  if (o.max_nrhs < 1 || o.max_nrhs > BDDCSO_MAX_RHS) return set_err(BDDCSO_EINVAL, "max_nrhs out of range");
+  if (o.precision != 0 && o.precision != 1) return set_err(BDDCSO_EINVAL, "precision must be 0 or 1");
+  if (o.primal_mask <= 0 || o.primal_mask > 7) return set_err(BDDCSO_EINVAL, "primal_mask must be in 1..7");
+  if (o.coarse_solver != 0 && o.coarse_solver != 1) return set_err(BDDCSO_EINVAL, "coarse_solver must be 0 or 1");
+  hipStream_t s = as_stream(stream);
+  Error err;
+  std::shared_ptr<Plan> plan;
+  try {
+    plan = get_plan(p, o, err);
+  } catch (const std::bad_alloc&) {
+    return set_err(BDDCSO_ENOMEM, "host allocation failed while planning");
+  }
+  if (!plan) return set_err(BDDCSO_EINVAL, err.msg);
+  auto* pc = new (std::nothrow) bddcso_precond();
+  if (!pc) return set_err(BDDCSO_ENOMEM, "host allocation failed");
+  pc->prob = p;
+  pc->plan = plan;
+  pc->opt = o;
+  pc->precision = o.precision;
+  pc->max_nrhs = o.max_nrhs;
+  const Classification& c = p->c;
+  const Plan& pl = *plan;
+  Geo& g = pc->geo;
+  g.dim = c.dim;
+  for (int a = 0; a < 3; ++a) {
+    g.ne[a] = (int)c.ne[a];
+    g.nf[a] = (int)c.nf[a];
+  }
+  g.n_free = c.n_free;
+  g.n_elem = c.n_elem;
+  try {
+    DevMem& m = pc->mem;
+    PlanDev& P = pc->P;
+    P.subs = m.upload(pl.subs, s);
+    P.blocks = m.upload(pl.blocks, s);
+    P.loc_I = m.upload(pl.loc_I, s);
+    P.loc_r = m.upload(pl.loc_r, s);
+    P.loc_g = m.upload(pl.loc_g, s);
+    P.I_loc = m.upload(pl.I_loc, s);
+    P.r_loc = m.upload(pl.r_loc, s);
+    P.g_loc = m.upload(pl.g_loc, s);
+    P.g_gam = m.upload(pl.g_gam, s);
+    P.g_r = m.upload(pl.g_r, s);
+    P.g_v = m.upload(pl.g_v, s);
+    P.g_sub = m.upload(pl.g_sub, s);
+    P.v_loc = m.upload(pl.v_loc, s);
+    P.v_c = m.upload(pl.v_c, s);
+    P.a_ptr = m.upload(pl.a_ptr, s);
+    P.a_r = m.upload(pl.a_r, s);
+    P.a_c = m.upload(pl.a_c, s);
+    P.c_glob = m.upload(pl.c_glob, s);
+    P.c_kind = m.upload(pl.c_kind, s);
+    P.gam_eptr = m.upload(pl.gam_eptr, s);
+    P.gam_ent = m.upload(pl.gam_ent, s);
+    P.gam_node = m.upload(c.gam_node, s);
+    P.gam_kptr = m.upload(c.gam_kptr, s);
+    P.gam_key = m.upload(c.gam_key, s);
+    P.ss_parent = m.upload(c.ss_parent, s);
+    P.ss_eptr = m.upload(c.ss_eptr, s);
+    P.ss_elem = m.upload(c.ss_elem, s);
+    P.crs_eptr = m.upload(pl.crs_eptr, s);
+    P.crs_ent = m.upload(pl.crs_ent, s);
+    P.fronts = m.upload(pl.fronts, s);
+    P.front_idx = m.upload(pl.front_idx, s);
+    P.front_pmap = m.upload(pl.front_pmap, s);
+    P.sub_fmap = m.upload(pl.sub_fmap, s);
+    std::vector<double> kh(p->khat, p->khat + 64);
+    pc->khat = m.upload(kh, s);
+    P.khat = pc->khat;
+    HIPCHK(hipStreamSynchronize(s));
+    P.n_sub = c.n_sub;
+    P.tot_I = pl.tot_I;
+    P.tot_r = pl.tot_r;
+    P.tot_g = pl.tot_g;
+    P.tot_c = pl.tot_c;
+    P.tot_a = pl.tot_a;
+    P.n_gam = (int64_t)c.gam_node.size();
+    P.n_coarse = pl.n_coarse;
+    P.max_block = pl.max_block;
+    P.max_na = pl.max_na;
+    P.max_nc = pl.max_nc;
+    P.max_ng = pl.max_ng;
+    P.max_nloc = pl.max_nloc;
+    P.max_nr = pl.max_nr;
+    int max_nI = 0, max_plane = 0;
+    for (auto& S : pl.subs) max_nI = std::max(max_nI, S.n_I);
+    for (auto& B : pl.blocks) max_plane = std::max(max_plane, std::max(B.first_n, B.last_n));
+    P.max_nI = max_nI;
+    P.max_zcols = pl.max_zcols;
+    P.max_plane = max_plane;
+
+    pc->rho = m.alloc<double>(c.n_elem);
+    pc->alpha = m.alloc<double>(c.n_ss);
+    pc->delta = m.alloc<double>(pl.tot_g);
+    pc->status = m.alloc<int32_t>(1);
+    pc->fpool = m.alloc<double>(pl.front_pool);
+    const int nr = pc->max_nrhs;
+    pc->bc = m.alloc<double>(pl.n_coarse * nr);
+    pc->uc = m.alloc<double>(pl.n_coarse * nr);
+    pc->fvec = m.alloc<double>(pl.front_vec * nr);
+    pc->xh = m.alloc<double>(pl.front_vec * nr);
+    if (o.precision == 1) alloc_numeric<float>(pc, s);
+    else alloc_numeric<double>(pc, s);
+    build_batches(pc, s);
+    const int64_t n = c.n_free;
+    pc->r = m.alloc<double>(n * nr);
+    pc->p = m.alloc<double>(n * nr);
+    pc->qv = m.alloc<double>(n * nr);
+    pc->z = m.alloc<double>(n * nr);
+    pc->rold = m.alloc<double>(n * nr);
+    pc->dtmp = m.alloc<double>(n * nr);
+    pc->partial = m.alloc<double>((int64_t)pc->dot_blocks * nr);
+    pc->sc = m.alloc<double>(8 * BDDCSO_MAX_RHS);
+    int maxit = std::max(o.maxit, o.fixed_iters) + 1;
+    pc->hist_a = m.alloc<double>((int64_t)maxit * nr);
+    pc->hist_b = m.alloc<double>((int64_t)maxit * nr);
+    pc->active = m.alloc<int32_t>(nr);
+    pc->iters = m.alloc<int32_t>(nr);
+    pc->flags = m.alloc<int32_t>(nr);
+    pc->nactive = m.alloc<int32_t>(1);
+    HIPCHK(hipHostMalloc((void**)&pc->h_nactive, sizeof(int32_t) * 4, hipHostMallocDefault));
+  } catch (const HipFail& f) {
+    bddcso_precond_destroy(pc);
+    if (f.e == hipErrorOutOfMemory)
+      return set_err(BDDCSO_ENOMEM, "device allocation failed: " + f.where);
+    return set_err(BDDCSO_EHIP, f.where + ": " + hipGetErrorString(f.e));
+  }
+  bddcso_status st = bddcso_refactor(pc, rho_dev, stream);
+  if (st == BDDCSO_OK) st = bddcso_check_pivots(pc, stream);
+  if (st != BDDCSO_OK) {
+    std::string msg = g_last_error;
+    bddcso_precond_destroy(pc);
+    return set_err(st, msg);
+  }
+  *out = pc;
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_operator_apply(const bddcso_precond* pc, const double* x, double* y, int nrhs, void* stream) {
+  if (!pc || !x || !y) return set_err(BDDCSO_EINVAL, "null argument");
+  if (nrhs < 1) return set_err(BDDCSO_EINVAL, "nrhs must be >= 1");
+  if (x == y) return set_err(BDDCSO_EINVAL, "x and y must be distinct");
+  launch_q1_apply(pc->geo, pc->khat, pc->rho, x, y, nrhs, as_stream(stream));
+  if (hipGetLastError() != hipSuccess) return set_err(BDDCSO_EHIP, "q1 apply launch failed");
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_apply(bddcso_precond* pc, const double* r, double* z, int nrhs, void* stream) {
+  if (!pc || !r || !z) return set_err(BDDCSO_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > pc->max_nrhs) return set_err(BDDCSO_EINVAL, "nrhs must be in 1..max_nrhs");
+  if (r == z) return set_err(BDDCSO_EINVAL, "r and z must be distinct");
+  apply_B_any(pc, r, z, nrhs, as_stream(stream));
+  if (hipGetLastError() != hipSuccess) return set_err(BDDCSO_EHIP, "kernel launch failed in apply");
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_solve(bddcso_precond* pc, const double* b, double* x, int nrhs, bddcso_stats* stats,
+                           void* stream) {
+  if (!pc || !b || !x) return set_err(BDDCSO_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > pc->max_nrhs) return set_err(BDDCSO_EINVAL, "nrhs must be in 1..max_nrhs");
+  if (b == x) return set_err(BDDCSO_EINVAL, "b and x must be distinct");
+  hipStream_t s = as_stream(stream);
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = pc->geo.n_free;
+  const int nr = nrhs;
+  const bddcso_options& o = pc->opt;
+  const bool flex = o.flexible || pc->precision == 1;
+  const int limit = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
+  double* SC = pc->sc;
+  double *s_bb = SC, *s_rz = SC + 64, *s_pq = SC + 128, *s_rr = SC + 192, *s_rzn = SC + 256, *s_num = SC + 320,
+         *s_tol = SC + 384;
+  std::vector<double> hbb(nr), htol(nr);
+  std::vector<int32_t> hact(nr);
+  int k_done = 0;
+  try {
+    bddcso_status pst = bddcso_check_pivots(pc, stream);
+    if (pst != BDDCSO_OK) return pst;
+    launch_fill_f64(x, n * nr, 0.0, s);
+    HIPCHK(hipMemcpyAsync(pc->r, b, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_dot(b, b, n, nr, pc->partial, pc->dot_blocks, s_bb, s);
+    HIPCHK(hipMemcpyAsync(hbb.data(), s_bb, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int j = 0; j < nr; ++j) {
+      if (!std::isfinite(hbb[j])) return set_err(BDDCSO_EINVAL, "right-hand side is not finite");
+      htol[j] = o.fixed_iters > 0 ? -1.0 : o.rtol * o.rtol * hbb[j];
+      hact[j] = hbb[j] > 0.0 ? 1 : 0;
+    }
+    HIPCHK(hipMemcpyAsync(s_tol, htol.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(pc->active, hact.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    launch_fill_i32(pc->iters, nr, 0, s);
+    launch_fill_i32(pc->flags, nr, 0, s);
+    apply_B_any(pc, pc->r, pc->z, nr, s);
+    HIPCHK(hipMemcpyAsync(pc->p, pc->z, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_dot(pc->r, pc->z, n, nr, pc->partial, pc->dot_blocks, s_rz, s);
+    int any = 0;
+    for (int j = 0; j < nr; ++j) any |= hact[j];
+    for (int k = 0; any && k < limit; ++k) {
+      launch_q1_apply(pc->geo, pc->khat, pc->rho, pc->p, pc->qv, nr, s);
+      launch_dot(pc->p, pc->qv, n, nr, pc->partial, pc->dot_blocks, s_pq, s);
+      if (flex) HIPCHK(hipMemcpyAsync(pc->rold, pc->r, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_pcg_xr(x, pc->r, pc->p, pc->qv, s_rz, s_pq, pc->active, n, nr, s);
+      launch_dot(pc->r, pc->r, n, nr, pc->partial, pc->dot_blocks, s_rr, s);
+      launch_pcg_book1(nr, k, s_rz, s_pq, s_rr, s_tol, pc->active, pc->iters, pc->flags, pc->hist_a, pc->nactive, s);
+      k_done = k + 1;
+      if (o.fixed_iters <= 0) {
+        HIPCHK(hipMemcpyAsync(pc->h_nactive, pc->nactive, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (*pc->h_nactive == 0) break;
+      }
+      if (k + 1 == limit) break;
+      apply_B_any(pc, pc->r, pc->z, nr, s);
+      launch_dot(pc->r, pc->z, n, nr, pc->partial, pc->dot_blocks, s_rzn, s);
+      if (flex) {
+        launch_sub(pc->r, pc->rold, pc->dtmp, n * nr, s);
+        launch_dot(pc->z, pc->dtmp, n, nr, pc->partial, pc->dot_blocks, s_num, s);
+        launch_pcg_p(pc->p, pc->z, s_num, s_rz, pc->active, n, nr, s);
+        launch_pcg_book2(nr, k, s_rz, s_num, s_rzn, pc->active, pc->hist_b, s);
+      } else {
+        launch_pcg_p(pc->p, pc->z, s_rzn, s_rz, pc->active, n, nr, s);
+        launch_pcg_book2(nr, k, s_rz, s_rzn, s_rzn, pc->active, pc->hist_b, s);
+      }
+    }
+    HIPCHK(hipGetLastError());
+    // results
+    std::vector<int32_t> it(nr), fl(nr);
+    std::vector<double> rr(nr), ha((size_t)std::max(k_done, 1) * nr), hb((size_t)std::max(k_done, 1) * nr);
+    HIPCHK(hipMemcpyAsync(it.data(), pc->iters, nr * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(fl.data(), pc->flags, nr * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rr.data(), s_rr, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (k_done > 0) {
+      HIPCHK(hipMemcpyAsync(ha.data(), pc->hist_a, (size_t)k_done * nr * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hb.data(), pc->hist_b, (size_t)k_done * nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    bool breakdown = false, noconv = false;
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->nrhs = nr;
+      stats->n_coarse = pc->plan->n_coarse;
+      stats->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    for (int j = 0; j < nr; ++j) {
+      if (fl[j] & 2) breakdown = true;
+      bool conv = (fl[j] & 1) || hbb[j] == 0.0;
+      if (o.fixed_iters > 0) conv = rr[j] <= o.rtol * o.rtol * hbb[j];
+      if (!conv && o.fixed_iters <= 0) noconv = true;
+      if (stats) {
+        stats->iters[j] = it[j];
+        stats->converged[j] = conv ? 1 : 0;
+        stats->relres[j] = hbb[j] > 0 ? std::sqrt(std::max(rr[j], 0.0) / hbb[j]) : 0.0;
+        int m = it[j];
+        std::vector<double> d(m), e(m > 0 ? m - 1 : 0);
+        for (int i = 0; i < m; ++i) {
+          double a = ha[(size_t)i * nr + j];
+          d[i] = 1.0 / a;
+          if (i > 0) {
+            double ap = ha[(size_t)(i - 1) * nr + j], bp = hb[(size_t)(i - 1) * nr + j];
+            d[i] += bp / ap;
+            e[i - 1] = std::sqrt(std::max(bp, 0.0)) / ap;
+          }
+        }
+        double lo = 1, hi = 1;
+        tridiag_extremes(d, e, lo, hi);
+        stats->lambda_min[j] = lo;
+        stats->lambda_max[j] = hi;
+        stats->kappa[j] = hi / lo;
+      }
+    }
+    if (breakdown) return set_err(BDDCSO_EBREAKDOWN, "PCG breakdown (p^T A p <= 0 or r^T z <= 0)");
+    if (noconv) return set_err(BDDCSO_ENOCONV, "maxit reached before rtol");
+  } catch (const HipFail& f) {
+    return set_err(BDDCSO_EHIP, f.where + ": " + hipGetErrorString(f.e));
+  }
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_element_grad(const bddcso_precond* pc, const double* u, const double* lam, double* g,
+                                  int nrhs, void* stream) {
+  if (!pc || !u || !lam || !g) return set_err(BDDCSO_EINVAL, "null argument");
+  if (nrhs < 1) return set_err(BDDCSO_EINVAL, "nrhs must be >= 1");
+  launch_element_grad(pc->geo, pc->khat, pc->rho, u, lam, g, nrhs, as_stream(stream));
+  if (hipGetLastError() != hipSuccess) return set_err(BDDCSO_EHIP, "element grad launch failed");
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_box_filter(const bddcso_problem* p, const double* in, double* out, int transpose,
+                                void* stream) {
+  if (!p || !in || !out) return set_err(BDDCSO_EINVAL, "null argument");
+  if (in == out) return set_err(BDDCSO_EINVAL, "in and out must be distinct");
+  Geo g{};
+  g.dim = p->c.dim;
+  for (int a = 0; a < 3; ++a) {
+    g.ne[a] = (int)p->c.ne[a];
+    g.nf[a] = (int)p->c.nf[a];
+  }
+  g.n_free = p->c.n_free;
+  g.n_elem = p->c.n_elem;
+  launch_box_filter(g, in, out, transpose, as_stream(stream));
+  if (hipGetLastError() != hipSuccess) return set_err(BDDCSO_EHIP, "box filter launch failed");
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_precond_info(const bddcso_precond* pc, int64_t* n_coarse, int64_t* n_fronts,
+                                  int64_t* device_bytes, int64_t* coarse_factor_entries) {
+  if (!pc) return set_err(BDDCSO_EINVAL, "null precond");
+  if (n_coarse) *n_coarse = pc->plan->n_coarse;
+  if (n_fronts) *n_fronts = (int64_t)pc->plan->fronts.size();
+  if (device_bytes) *device_bytes = pc->mem.bytes;
+  if (coarse_factor_entries) {
+    int64_t t = 0;
+    for (auto& F : pc->plan->fronts) t += (int64_t)F.n * F.p;
+    *coarse_factor_entries = t;
+  }
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_local_coarse(const bddcso_precond* pc, int sub, double* kc, int64_t* ids, int64_t cap_nc,
+                                  int64_t* nc, void* stream) {
+  if (!pc || !kc || !ids || !nc) return set_err(BDDCSO_EINVAL, "null argument");
+  const Plan& pl = *pc->plan;
+  if (sub < 0 || sub >= (int)pl.subs.size()) return set_err(BDDCSO_EINVAL, "subdomain out of range");
+  const SubDev& S = pl.subs[sub];
+  *nc = S.n_c;
+  if (S.n_c > cap_nc) return set_err(BDDCSO_EINVAL, "output buffers too small");
+  hipStream_t s = as_stream(stream);
+  const size_t cnt = (size_t)S.n_c * S.n_c;
+  if (pc->precision == 1) {
+    std::vector<float> tmp(cnt);
+    if (cnt && hipMemcpyAsync(tmp.data(), pc->nf.Kc + S.Kc_off, cnt * sizeof(float), hipMemcpyDeviceToHost, s))
+      return set_err(BDDCSO_EHIP, "copy failed");
+    if (hipStreamSynchronize(s) != hipSuccess) return set_err(BDDCSO_EHIP, "sync failed");
+    for (size_t i = 0; i < cnt; ++i) kc[i] = tmp[i];
+  } else {
+    if (cnt && hipMemcpyAsync(kc, pc->nd.Kc + S.Kc_off, cnt * sizeof(double), hipMemcpyDeviceToHost, s))
+      return set_err(BDDCSO_EHIP, "copy failed");
+    if (hipStreamSynchronize(s) != hipSuccess) return set_err(BDDCSO_EHIP, "sync failed");
+  }
+  for (int k = 0; k < S.n_c; ++k) ids[k] = pl.c_glob[S.c_off + k];
+  return BDDCSO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Device kernels of the BDDC-SO path and their host launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "types.h"
+
+namespace bddcso {
+
+// Geometry passed by value to kernels.
+struct Geo {
+  int dim;
+  int ne[3];        // elements per axis (ne[2] = 1 in 2D)
+  int nf[3];        // free nodes per axis (nf[2] = 1 in 2D)
+  int64_t n_free, n_elem;
+};
+
+// Device views of the plan tables.
+struct PlanDev {
+  const SubDev* subs;
+  const BlockDev* blocks;
+  const int32_t *loc_I, *loc_r, *loc_g;
+  const int32_t *I_loc, *r_loc;
+  const int32_t *g_loc, *g_gam, *g_r, *g_v, *g_sub;
+  const int32_t *v_loc, *v_c;
+  const int32_t *a_ptr, *a_r, *a_c;
+  const int32_t *c_glob, *c_kind;
+  const int32_t *gam_eptr, *gam_ent;
+  const int64_t* gam_node;
+  const int32_t *gam_kptr, *gam_key, *ss_parent, *ss_eptr, *ss_elem;
+  const int32_t *crs_eptr, *crs_ent;
+  const FrontDev* fronts;
+  const int32_t *front_idx, *front_pmap, *sub_fmap;
+  const double* khat;  // 8x8 unit-coefficient element matrix (2D replicated over the z bit)
+  int n_sub;
+  int64_t tot_I, tot_r, tot_g, tot_c, tot_a, n_gam, n_coarse;
+  int max_block, max_na, max_nc, max_ng, max_nloc, max_nr, max_nI, max_zcols, max_plane;
+};
+
+// ---- launchers (defined in kernels.hip) ---------------------------------
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+void launch_q1_apply(const Geo& g, const double* khat, const double* rho, const double* x,
+                     double* y, int nrhs, hipStream_t s);
+void launch_alpha(const PlanDev& P, int n_ss, const double* rho, int weighting, double* alpha,
+                  hipStream_t s);
+void launch_delta(const PlanDev& P, const double* alpha, double* delta, hipStream_t s);
+
+template <typename T>
+struct Kern {
+  // setup
+  static void block_assemble(const PlanDev& P, const Geo& g, const double* rho, int setR, T* G,
+                             hipStream_t s);
+  static void schur_couple(const PlanDev& P, const Geo& g, const double* rho, int setR, int k,
+                           T* G, T* W, int64_t wstride, hipStream_t s);
+  static void sweep(SweepDesc* d_desc, int nprob, int maxn, int maxp, T* pool, T* scratch,
+                    int64_t scr_stride, int* status, int status_code, hipStream_t s);
+  static void gemm(const GemmDesc* d_desc, int nprob, int maxm, int maxn, const T* A, int transA,
+                   const T* B, int transB, T* C, T alpha, T beta, hipStream_t s);
+  static void rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, hipStream_t s);
+  static void couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
+                           int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s);
+  static void copy_block_rows(const PlanDev& P, int k, int ncols_max, const T* Z, T* tmp,
+                              int64_t tmp_stride, hipStream_t s);
+  static void sc_assemble(const PlanDev& P, const T* Z, T* Sc, hipStream_t s);
+  static void lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s);
+  static void phi_r_init(const PlanDev& P, const T* Z, T* PhiR, hipStream_t s);
+  static void phi_scatter(const PlanDev& P, const T* PhiR, T* Phi, hipStream_t s);
+  static void local_apply_multi(const PlanDev& P, const Geo& g, const double* rho, const T* Phi,
+                                T* KPhi, hipStream_t s);
+  static void extract_gamma(const PlanDev& P, const T* Phi, const T* Z, T* PhiG, T* XG,
+                            hipStream_t s);
+  static void kc_to_front(const PlanDev& P, const int32_t* subs_of_color, int ns, const T* Kc,
+                          double* fpool, hipStream_t s);
+  // per-iteration
+  static void gather_I(const PlanDev& P, const Geo& g, const double* r, T* vI, int nrhs, hipStream_t s);
+  static void block_solve(const PlanDev& P, const Geo& g, const double* rho, int setR, const T* G,
+                          T* v, int nrhs, hipStream_t s);
+  static void gamma_kgi(const PlanDev& P, const Geo& g, const double* rho, const T* vI, T* q,
+                        int nrhs, hipStream_t s);
+  static void gamma_t(const PlanDev& P, const Geo& g, const double* r, const T* q, const double* delta,
+                      T* gv, int nrhs, hipStream_t s);
+  static void neumann_rhs(const PlanDev& P, const T* gv, T* vR, int nrhs, hipStream_t s);
+  static void mu(const PlanDev& P, const T* vR, const T* Sc, T* mu_out, int nrhs, hipStream_t s);
+  static void coarse_rhs_local(const PlanDev& P, const T* PhiG, const T* gv, T* bci, int nrhs,
+                               hipStream_t s);
+  static void v2(const PlanDev& P, const T* vR, const T* XG, const T* mu_in, const T* PhiG,
+                 const double* uc, T* v2_out, int nrhs, hipStream_t s);
+  static void interior_rhs(const PlanDev& P, const Geo& g, const double* rho, const double* r,
+                           const double* w, T* vI, int nrhs, hipStream_t s);
+  static void scatter_I(const PlanDev& P, const Geo& g, const T* vI, double* z, int nrhs, hipStream_t s);
+};
+
+void launch_coarse_rhs_gather(const PlanDev& P, const double* bci_d, const float* bci_f,
+                              double* bc, int nrhs, hipStream_t s);
+void launch_gamma_w(const PlanDev& P, const Geo& g, const double* v2_d, const float* v2_f,
+                    const double* delta, double* z, int nrhs, hipStream_t s);
+void launch_front_child_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
+                                double* fpool, hipStream_t s);
+void launch_front_vec_init(const PlanDev& P, const int32_t* fr, int nfr, int maxn, const double* bc,
+                           double* fvec, int64_t fvec_stride, int nrhs, hipStream_t s);
+void launch_front_vec_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
+                              double* fvec, int64_t fvec_stride, int nrhs, hipStream_t s);
+void launch_front_fwd(const PlanDev& P, const int32_t* fr, int nfr, int maxn, int maxp,
+                      const double* fpool, double* fvec, double* xh, int64_t fvec_stride,
+                      int nrhs, hipStream_t s);
+void launch_front_bwd(const PlanDev& P, const int32_t* fr, int nfr, int maxp, int maxb,
+                      const double* fpool, const double* xh, int64_t fvec_stride, double* uc,
+                      int nrhs, hipStream_t s);
+void launch_kc_to_f64(const float* src, double* dst, int64_t n, hipStream_t s);
+
+// PCG helpers.  Scalars live on the device: dots[slot*nrhs + j].
+void launch_dot(const double* a, const double* b, int64_t n, int nrhs, double* partial,
+                int nblocks, double* out, hipStream_t s);
+void launch_pcg_xr(double* x, double* r, const double* p, const double* q, const double* rz,
+                   const double* pq, const int32_t* active, int64_t n, int nrhs, hipStream_t s);
+void launch_pcg_p(double* p, const double* z, const double* rz_new, const double* rz_old,
+                  const int32_t* active, int64_t n, int nrhs, hipStream_t s);
+void launch_pcg_p_flex(double* p, const double* z, const double* zdr, const double* rz_old,
+                       const int32_t* active, int64_t n, int nrhs, hipStream_t s);
+void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);
+
+void launch_element_grad(const Geo& g, const double* khat, const double* rho, const double* u,
+                         const double* lam, double* out, int nrhs, hipStream_t s);
+void launch_box_filter(const Geo& g, const double* in, double* out, int transpose, hipStream_t s);
+
+}  // namespace bddcso
+
+namespace bddcso {
+void launch_pcg_book1(int nrhs, int k, const double* rz, const double* pq, const double* rr, const double* tol2,
+                      int32_t* active, int32_t* iters, int32_t* flags, double* hist_alpha, int32_t* nactive,
+                      hipStream_t s);
+void launch_pcg_book2(int nrhs, int k, double* rz, const double* num, const double* rz_new,
+                      const int32_t* active, double* hist_beta, hipStream_t s);
+}  // namespace bddcso

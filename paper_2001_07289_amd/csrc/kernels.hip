@@ -1,0 +1,1639 @@
+// HIP kernels for gfx950 (CDNA4): the BDDC-SO setup, the preconditioner
+// application, the Q1 operator and the PCG vector work.
+//
+// Dense contractions (the rank-k updates of the block inversions and the
+// batched GEMMs of the setup) run on MFMA: v_mfma_f64_16x16x4_f64 in FP64,
+// v_mfma_f32_16x16x4_f32 in FP32, 64x64 tiles per 256-thread workgroup (four
+// 64-wide waves, 32x32 each).  Everything else is HBM-bound streaming:
+// coalesced along the fastest index, reductions in fixed order (no
+// floating-point atomics), so results are bitwise repeatable.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+
+#include "kernels.h"
+
+namespace bddcso {
+
+namespace {
+
+constexpr int TILE = 64;
+constexpr int BK = 16;
+constexpr int PAD = 4;
+constexpr int SWEEP_NB = 32;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+// Inputs of both 16x16x4 forms: lane l holds A[l%16][l/16] and B[l/16][l%16].
+// Outputs: lane l, register r holds D[row(l/16, r)][l%16]; the FP64 form
+// interleaves the rows (l/16 + 4r), the FP32 form blocks them (4(l/16) + r).
+template <>
+struct Mfma<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t mac(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int r) { return kq + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+};
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+inline int64_t hmin(int64_t a, int64_t b) { return a < b ? a : b; }
+inline int64_t hmax(int64_t a, int64_t b) { return a > b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// geometry helpers
+
+__device__ __forceinline__ void loc_coords(const SubDev& S, int l, int c[3]) {
+  c[0] = l % S.m[0];
+  c[1] = (l / S.m[0]) % S.m[1];
+  c[2] = l / (S.m[0] * S.m[1]);
+}
+
+__device__ __forceinline__ int loc_index(const SubDev& S, const int c[3]) {
+  if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] >= S.m[0] || c[1] >= S.m[1] || c[2] >= S.m[2])
+    return -1;
+  return c[0] + S.m[0] * (c[1] + S.m[1] * c[2]);
+}
+
+// Free-node index of local node l of S.
+__device__ __forceinline__ int64_t free_of_local(const SubDev& S, const Geo& g, int l) {
+  int c[3];
+  loc_coords(S, l, c);
+  return (int64_t)(S.lo[0] + c[0] - 1) +
+         (int64_t)g.nf[0] * ((int64_t)(S.lo[1] + c[1] - 1) + (int64_t)g.nf[1] * (S.lo[2] + c[2] - 1));
+}
+
+// Entry of the local stiffness matrix K_i between two local nodes (local
+// coordinates ca, cb, at most one step apart per axis): the sum over the
+// elements of this subdomain that contain both of rho_e K^_e[a, b].
+__device__ __forceinline__ double kloc(const SubDev& S, const Geo& g, const double* __restrict__ rho,
+                                       const double* __restrict__ khat, const int ca[3],
+                                       const int cb[3]) {
+  int ga[3], gb[3], lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ga[a] = S.lo[a] + ca[a];
+    gb[a] = S.lo[a] + cb[a];
+    lo[a] = max(max(ga[a], gb[a]) - 1, S.elo[a]);
+    hi[a] = min(min(ga[a], gb[a]), S.ehi[a] - 1);
+  }
+  double s = 0.0;
+  for (int ez = lo[2]; ez <= hi[2]; ++ez)
+    for (int ey = lo[1]; ey <= hi[1]; ++ey)
+      for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+        int64_t e = ex + (int64_t)g.ne[0] * (ey + (int64_t)g.ne[1] * ez);
+        int ia = (ga[0] - ex) + 2 * (ga[1] - ey) + 4 * (ga[2] - ez);
+        int ib = (gb[0] - ex) + 2 * (gb[1] - ey) + 4 * (gb[2] - ez);
+        s += rho[e] * khat[ia * 8 + ib];
+      }
+  return s;
+}
+
+// t-th neighbour (t < 9 in 3D, < 3 in 2D) of c in the adjacent plane c[pa]+dir.
+__device__ __forceinline__ bool plane_nbr(const SubDev& S, int dim, const int c[3], int dir, int t,
+                                          int out[3]) {
+  out[0] = c[0];
+  out[1] = c[1];
+  out[2] = c[2];
+  if (dim == 3) {
+    out[2] += dir;
+    out[0] += t % 3 - 1;
+    out[1] += t / 3 - 1;
+  } else {
+    if (t >= 3) return false;
+    out[1] += dir;
+    out[0] += t - 1;
+  }
+  return out[0] >= 0 && out[1] >= 0 && out[2] >= 0 && out[0] < S.m[0] && out[1] < S.m[1] &&
+         out[2] < S.m[2];
+}
+
+__device__ __forceinline__ const int32_t* set_loc_of(const PlanDev& P, const SubDev& S, int setR) {
+  return setR ? P.r_loc + S.r_off : P.I_loc + S.I_off;
+}
+__device__ __forceinline__ const int32_t* loc_set_of(const PlanDev& P, const SubDev& S, int setR) {
+  return (setR ? P.loc_r : P.loc_I) + S.loc_off;
+}
+
+// ---------------------------------------------------------------------------
+// elementwise
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) b[i] = (double)a[i];
+}
+
+__global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ o, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) o[i] = a[i] - b[i];
+}
+
+// ---------------------------------------------------------------------------
+// global Q1 operator: y = A x, one thread per free node (and right-hand side).
+// Each row sums the 2^dim surrounding elements' contributions; boundary
+// nodes carry zero.  Reads x and rho through the cache: about 24 B per dof
+// of HBM traffic.
+
+__global__ __launch_bounds__(256) void k_q1_apply(Geo g, const double* __restrict__ khat,
+                                                  const double* __restrict__ rho,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ y) {
+  __shared__ double kh[64];
+  if (threadIdx.x < 64) kh[threadIdx.x] = khat[threadIdx.x];
+  __syncthreads();
+  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int rhs = blockIdx.y;
+  if (f >= g.n_free) return;
+  const double* xr = x + rhs * g.n_free;
+  int gx = (int)(f % g.nf[0]) + 1;
+  int64_t t = f / g.nf[0];
+  int gy = (int)(t % g.nf[1]) + 1;
+  int gz = g.dim == 3 ? (int)(t / g.nf[1]) + 1 : 1;
+  const int nz_el = g.dim == 3 ? 2 : 1;
+  double acc = 0.0;
+  for (int cz = 0; cz < nz_el; ++cz) {
+    int ez = g.dim == 3 ? gz - 1 + cz : 0;
+    for (int cy = 0; cy < 2; ++cy) {
+      int ey = gy - 1 + cy;
+      for (int cx = 0; cx < 2; ++cx) {
+        int ex = gx - 1 + cx;
+        int64_t e = ex + (int64_t)g.ne[0] * (ey + (int64_t)g.ne[1] * ez);
+        int a = (gx - ex) + 2 * (gy - ey) + 4 * (gz - ez);
+        double s = 0.0;
+        for (int b = 0; b < (g.dim == 3 ? 8 : 4); ++b) {
+          int nx = ex + (b & 1), ny = ey + ((b >> 1) & 1);
+          int nzc = g.dim == 3 ? ez + ((b >> 2) & 1) : 1;
+          if (nx < 1 || ny < 1 || nx > g.nf[0] || ny > g.nf[1]) continue;
+          if (g.dim == 3 && (nzc < 1 || nzc > g.nf[2])) continue;
+          int64_t fb = (nx - 1) + (int64_t)g.nf[0] * ((ny - 1) + (int64_t)g.nf[1] * (nzc - 1));
+          int bb = g.dim == 3 ? b : (b | 4);
+          s += kh[a * 8 + bb] * xr[fb];
+        }
+        acc += rho[e] * s;
+      }
+    }
+  }
+  y[rhs * g.n_free + f] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// weights (eq. W / Remark 1)
+
+__global__ void k_alpha(PlanDev P, int n_ss, const double* __restrict__ rho, int weighting,
+                        double* __restrict__ alpha) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_ss) return;
+  if (!weighting) {
+    alpha[j] = 1.0;
+    return;
+  }
+  double s = 0.0;
+  int b = P.ss_eptr[j], e = P.ss_eptr[j + 1];
+  for (int k = b; k < e; ++k) s += rho[P.ss_elem[k]];
+  alpha[j] = s / (double)(e - b);
+}
+
+__global__ void k_delta(PlanDev P, const double* __restrict__ alpha, double* __restrict__ delta) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= P.tot_g) return;
+  int q = P.g_gam[e];
+  int sub = P.g_sub[e];
+  double num = 0.0, den = 0.0;
+  for (int k = P.gam_kptr[q]; k < P.gam_kptr[q + 1]; ++k) {
+    int j = P.gam_key[k];
+    double a = alpha[j];
+    den += a;
+    if (P.ss_parent[j] == sub) num += a;
+  }
+  delta[e] = num / den;
+}
+
+// ---------------------------------------------------------------------------
+// local matrices: dense diagonal blocks of K_II / K_rr (entries within a block)
+
+template <typename T>
+__global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rho, int setR,
+                                 T* __restrict__ G) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int nset = setR ? S.n_r : S.n_I;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nset) return;
+  const int32_t* sl = set_loc_of(P, S, setR);
+  const int32_t* ls = loc_set_of(P, S, setR);
+  const int nb = setR ? S.nbR : S.nbI;
+  const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
+  const int pa = g.dim - 1;
+  int c[3];
+  loc_coords(S, sl[i], c);
+  int k = 0;
+  while (k < nb && !(c[pa] >= blk[k].plane_lo && c[pa] < blk[k].plane_hi)) ++k;
+  if (k == nb) return;
+  const BlockDev B = blk[k];
+  const int zr = g.dim == 3 ? 1 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int cn[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+        int ln = loc_index(S, cn);
+        if (ln < 0) continue;
+        int j = ls[ln];
+        if (j < 0) continue;
+        if (cn[pa] < B.plane_lo || cn[pa] >= B.plane_hi) continue;
+        G[B.G_off + (int64_t)(i - B.start) + (int64_t)B.size * (j - B.start)] =
+            (T)kloc(S, g, rho, P.khat, c, cn);
+      }
+}
+
+// Stage 1 of the block Schur update S_k -= A_{k,k-1} G_{k-1} A_{k-1,k}:
+// W[l', j'] = sum_m Gs[l, m] A[m, j] over the last plane of block k-1 (l, m)
+// and the first plane of block k (j).  Gs is the swept block (= -G).
+template <typename T>
+__global__ void k_schur_w(PlanDev P, Geo g, const double* __restrict__ rho, int setR, int k,
+                          const T* __restrict__ G, T* __restrict__ W, int64_t wstride) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int nb = setR ? S.nbR : S.nbI;
+  if (k >= nb || k == 0) return;
+  const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
+  const BlockDev Bp = blk[k - 1], B = blk[k];
+  if (Bp.plane_hi != B.plane_lo) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Bp.last_n * B.first_n) return;
+  const int lp = idx % Bp.last_n, jp = idx / Bp.last_n;
+  const int32_t* sl = set_loc_of(P, S, setR);
+  const int32_t* ls = loc_set_of(P, S, setR);
+  int cj[3];
+  loc_coords(S, sl[B.start + jp], cj);
+  const int lrow = Bp.size - Bp.last_n + lp;  // row inside block k-1
+  const T* Gp = G + Bp.G_off;
+  double acc = 0.0;
+  const int nt = g.dim == 3 ? 9 : 3;
+  for (int t = 0; t < nt; ++t) {
+    int cm[3];
+    if (!plane_nbr(S, g.dim, cj, -1, t, cm)) continue;
+    int m = ls[loc_index(S, cm)];
+    if (m < 0) continue;
+    double a = kloc(S, g, rho, P.khat, cm, cj);
+    acc += (double)Gp[lrow + (int64_t)Bp.size * (m - Bp.start)] * a;
+  }
+  W[sub * wstride + lp + (int64_t)Bp.last_n * jp] = (T)acc;
+}
+
+// Stage 2: S_k[i', j'] += sum_l A[i, l] W[l', j'] (first-plane rows/columns).
+template <typename T>
+__global__ void k_schur_apply(PlanDev P, Geo g, const double* __restrict__ rho, int setR, int k,
+                              T* __restrict__ G, const T* __restrict__ W, int64_t wstride) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int nb = setR ? S.nbR : S.nbI;
+  if (k >= nb || k == 0) return;
+  const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
+  const BlockDev Bp = blk[k - 1], B = blk[k];
+  if (Bp.plane_hi != B.plane_lo) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B.first_n * B.first_n) return;
+  const int ip = idx % B.first_n, jp = idx / B.first_n;
+  const int32_t* sl = set_loc_of(P, S, setR);
+  const int32_t* ls = loc_set_of(P, S, setR);
+  int ci[3];
+  loc_coords(S, sl[B.start + ip], ci);
+  double acc = 0.0;
+  const int nt = g.dim == 3 ? 9 : 3;
+  const T* Wp = W + sub * wstride;
+  for (int t = 0; t < nt; ++t) {
+    int cl[3];
+    if (!plane_nbr(S, g.dim, ci, -1, t, cl)) continue;
+    int l = ls[loc_index(S, cl)];
+    if (l < 0) continue;
+    double a = kloc(S, g, rho, P.khat, ci, cl);
+    int lp = l - (Bp.start + Bp.size - Bp.last_n);
+    acc += a * (double)Wp[lp + (int64_t)Bp.last_n * jp];
+  }
+  T* Gk = G + B.G_off;
+  Gk[ip + (int64_t)B.size * jp] += (T)acc;
+}
+
+// ---------------------------------------------------------------------------
+// Batched symmetric sweep (Gauss-Jordan on an SPD matrix, in place).
+// Sweeping pivot set Q of a symmetric matrix M replaces M_QQ by -M_QQ^{-1},
+// M_iQ by M_iQ M_QQ^{-1} and M_ij by M_ij - M_iQ M_QQ^{-1} M_Qj.  A full
+// sweep gives -M^{-1}; sweeping the first p pivots of a front gives
+// -F_PP^{-1}, F_BP F_PP^{-1} and the Schur complement F_BB - F_BP F_PP^{-1} F_PB.
+// Pivots are swept in panels of SWEEP_NB: k_sweep_panel (one workgroup per
+// matrix) writes back the previous panel, inverts the new pivot block in LDS
+// and forms CD = M_{:,Q} D^{-1}; k_sweep_update applies the rank-NB update
+// to every entry outside the panel on MFMA.
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep_panel(const SweepDesc* __restrict__ desc, T* pool,
+                                                     int j0, int prev_j0, T* scratch,
+                                                     int64_t scr_stride, int* status,
+                                                     int status_code) {
+  __shared__ double D[SWEEP_NB][SWEEP_NB + 1];
+  const SweepDesc d = desc[blockIdx.x];
+  const int n = d.n, p = d.p, ld = d.ld;
+  T* A = pool + d.off;
+  T* CD = scratch + blockIdx.x * scr_stride;       // n x NB, ld n
+  T* Dinv = CD + (int64_t)n * SWEEP_NB;            // NB x NB
+  const int tid = threadIdx.x;
+  if (prev_j0 >= 0 && prev_j0 < p) {
+    const int pb = min(SWEEP_NB, p - prev_j0);
+    for (int64_t idx = tid; idx < (int64_t)n * pb; idx += blockDim.x) {
+      int i = (int)(idx % n), q = (int)(idx / n);
+      int col = prev_j0 + q;
+      if (i >= prev_j0 && i < prev_j0 + pb) {
+        A[i + (int64_t)ld * col] = -Dinv[(i - prev_j0) + SWEEP_NB * q];
+      } else {
+        T v = CD[i + (int64_t)n * q];
+        A[i + (int64_t)ld * col] = v;
+        A[col + (int64_t)ld * i] = v;
+      }
+    }
+    __threadfence();
+    __syncthreads();
+  }
+  if (j0 < 0 || j0 >= p) return;
+  const int jb = min(SWEEP_NB, p - j0);
+  for (int idx = tid; idx < jb * jb; idx += blockDim.x) {
+    int i = idx % jb, j = idx / jb;
+    D[i][j] = (double)A[(j0 + i) + (int64_t)ld * (j0 + j)];
+  }
+  __syncthreads();
+  // sweep the pivot block in LDS (FP64 for the small block in both precisions)
+  for (int q = 0; q < jb; ++q) {
+    double dq = D[q][q];
+    if (!(dq > 0.0)) {
+      if (tid == 0) atomicMax(status, status_code);
+      dq = 1.0;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < jb * jb; idx += blockDim.x) {
+      int i = idx % jb, j = idx / jb;
+      if (i != q && j != q) D[i][j] -= D[i][q] * D[q][j] / dq;
+    }
+    __syncthreads();
+    if (tid < jb && tid != q) {
+      D[tid][q] /= dq;
+      D[q][tid] /= dq;
+    }
+    if (tid == 0) D[q][q] = -1.0 / dq;
+    __syncthreads();
+  }
+  // D holds -D^{-1}
+  for (int idx = tid; idx < jb * jb; idx += blockDim.x) {
+    int i = idx % jb, j = idx / jb;
+    Dinv[i + SWEEP_NB * j] = (T)(-D[i][j]);
+  }
+  // CD = C D^{-1} for the rows outside the panel
+  for (int64_t idx = tid; idx < (int64_t)n * jb; idx += blockDim.x) {
+    int i = (int)(idx % n), q = (int)(idx / n);
+    if (i >= j0 && i < j0 + jb) continue;
+    double acc = 0.0;
+    for (int t = 0; t < jb; ++t) acc -= (double)A[i + (int64_t)ld * (j0 + t)] * D[t][q];
+    CD[i + (int64_t)n * q] = (T)acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep_update(const SweepDesc* __restrict__ desc, T* pool,
+                                                      int j0, const T* __restrict__ scratch,
+                                                      int64_t scr_stride, int tiles_n) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T As[SWEEP_NB][TILE + PAD];
+  __shared__ T Bs[SWEEP_NB][TILE + PAD];
+  const SweepDesc d = desc[blockIdx.y];
+  const int n = d.n, p = d.p, ld = d.ld;
+  if (j0 >= p) return;
+  const int jb = min(SWEEP_NB, p - j0);
+  const int ti = blockIdx.x % tiles_n, tj = blockIdx.x / tiles_n;
+  const int i0 = ti * TILE, c0 = tj * TILE;
+  if (i0 >= n || c0 >= n) return;
+  T* A = pool + d.off;
+  const T* CD = scratch + blockIdx.y * scr_stride;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < TILE * SWEEP_NB; idx += 256) {
+    int r = idx % TILE, q = idx / TILE;
+    int i = i0 + r, j = c0 + r;
+    T a = 0, b = 0;
+    if (q < jb) {
+      if (i < n && !(i >= j0 && i < j0 + jb)) a = CD[i + (int64_t)n * q];
+      if (j < n) b = A[j + (int64_t)ld * (j0 + q)];
+    }
+    As[q][r] = a;
+    Bs[q][r] = b;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  const int kq = lane >> 4, rr = lane & 15;
+  const int ksteps = (jb + 3) / 4;
+  for (int ks = 0; ks < ksteps; ++ks) {
+    int kk = ks * 4 + kq;
+    T av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = As[kk][wr + a * 16 + rr];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wc + b * 16 + rr];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(av[a], bv[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i = i0 + wr + a * 16 + Mfma<T>::row(kq, r);
+        int j = c0 + wc + b * 16 + rr;
+        if (i < n && j < n && !(i >= j0 && i < j0 + jb) && !(j >= j0 && j < j0 + jb))
+          A[i + (int64_t)ld * j] -= acc[a][b][r];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Batched GEMM on MFMA: C = beta C + alpha op(A) op(B), column-major, with one
+// descriptor per problem (uneven sizes).  grid = (tiles of the largest
+// problem, problems); out-of-range tiles exit at once.
+
+template <typename T, int TA, int TB>
+__global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
+                                              const T* __restrict__ Ap, const T* __restrict__ Bp,
+                                              T* __restrict__ Cp, T alpha, T beta, int tiles_m) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T As[BK][TILE + PAD];
+  __shared__ T Bs[BK][TILE + PAD];
+  const GemmDesc d = desc[blockIdx.y];
+  const int ti = blockIdx.x % tiles_m, tj = blockIdx.x / tiles_m;
+  const int m0 = ti * TILE, n0 = tj * TILE;
+  if (m0 >= d.m || n0 >= d.n) return;
+  const T* A = Ap + d.a;
+  const T* B = Bp + d.b;
+  T* C = Cp + d.c;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int kq = lane >> 4, rr = lane & 15;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  for (int k0 = 0; k0 < d.k; k0 += BK) {
+    for (int idx = tid; idx < TILE * BK; idx += 256) {
+      int r, q;
+      if (TA) {  // op(A)[i, k] = A[k, i]: coalesce along k
+        q = idx % BK;
+        r = idx / BK;
+      } else {
+        r = idx % TILE;
+        q = idx / TILE;
+      }
+      int i = m0 + r, kk = k0 + q;
+      T v = 0;
+      if (i < d.m && kk < d.k) v = TA ? A[kk + (int64_t)d.lda * i] : A[i + (int64_t)d.lda * kk];
+      As[q][r] = v;
+    }
+    for (int idx = tid; idx < TILE * BK; idx += 256) {
+      int r, q;
+      if (TB) {  // op(B)[k, j] = B[j, k]: coalesce along j
+        r = idx % TILE;
+        q = idx / TILE;
+      } else {
+        q = idx % BK;
+        r = idx / BK;
+      }
+      int j = n0 + r, kk = k0 + q;
+      T v = 0;
+      if (j < d.n && kk < d.k) v = TB ? B[j + (int64_t)d.ldb * kk] : B[kk + (int64_t)d.ldb * j];
+      Bs[q][r] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      int kk = ks * 4 + kq;
+      T av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[kk][wr + a * 16 + rr];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wc + b * 16 + rr];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i = m0 + wr + a * 16 + Mfma<T>::row(kq, r);
+        int j = n0 + wc + b * 16 + rr;
+        if (i < d.m && j < d.n) {
+          T* c = C + i + (int64_t)d.ldc * j;
+          T v = alpha * acc[a][b][r];
+          *c = beta == (T)0 ? v : beta * *c + v;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// constrained Neumann setup: right-hand sides [C_r^T | -K_rv], couplings
+
+template <typename T>
+__global__ void k_rhs_fill(PlanDev P, Geo g, const double* __restrict__ rho, T* __restrict__ Z) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= S.n_a + S.n_v) return;
+  T* z = Z + S.Z_off + (int64_t)S.n_r * col;
+  if (col < S.n_a) {
+    const int b = P.a_ptr[S.a_off + col], e = P.a_ptr[S.a_off + col + 1];
+    const T w = (T)(1.0 / (double)(e - b));
+    for (int t = b; t < e; ++t) z[P.a_r[t]] = w;
+  } else {
+    const int v = col - S.n_a;
+    const int lv = P.v_loc[S.v_off + v];
+    int cv[3];
+    loc_coords(S, lv, cv);
+    const int32_t* lr = P.loc_r + S.loc_off;
+    const int zr = g.dim == 3 ? 1 : 0;
+    for (int dz = -zr; dz <= zr; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int cn[3] = {cv[0] + dx, cv[1] + dy, cv[2] + dz};
+          int ln = loc_index(S, cn);
+          if (ln < 0) continue;
+          int j = lr[ln];
+          if (j < 0) continue;
+          z[j] = (T)(-kloc(S, g, rho, P.khat, cn, cv));
+        }
+  }
+}
+
+// fwd (fwd = 1): Z[first plane of block k, :] -= A_{k,k-1} Z[last plane of k-1, :]
+// bwd (fwd = 0): tmp[0:last_n, :] = A_{k,k+1} Z[first plane of k+1, :]
+template <typename T>
+__global__ void k_couple_multi(PlanDev P, Geo g, const double* __restrict__ rho, int k, int fwd,
+                               T* __restrict__ Z, T* __restrict__ tmp, int64_t tmp_stride) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int nb = S.nbR;
+  const BlockDev* blk = P.blocks + S.bR_off;
+  const int ncols = S.n_a + S.n_v;
+  if (fwd ? (k >= nb || k == 0) : (k + 1 >= nb)) return;
+  const BlockDev B = blk[k];
+  const BlockDev O = fwd ? blk[k - 1] : blk[k + 1];
+  const int rows = fwd ? B.first_n : B.last_n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const int row = fwd ? B.start + i : B.start + B.size - B.last_n + i;
+  const int32_t* sl = P.r_loc + S.r_off;
+  const int32_t* ls = P.loc_r + S.loc_off;
+  int ci[3];
+  loc_coords(S, sl[row], ci);
+  const bool adj = fwd ? (O.plane_hi == B.plane_lo) : (B.plane_hi == O.plane_lo);
+  double a[9];
+  int nbr[9];
+  int cnt = 0;
+  const int nt = g.dim == 3 ? 9 : 3;
+  if (adj)
+    for (int t = 0; t < nt; ++t) {
+      int cl[3];
+      if (!plane_nbr(S, g.dim, ci, fwd ? -1 : 1, t, cl)) continue;
+      int l = ls[loc_index(S, cl)];
+      if (l < 0) continue;
+      a[cnt] = kloc(S, g, rho, P.khat, ci, cl);
+      nbr[cnt++] = l;
+    }
+  T* z = Z + S.Z_off;
+  T* tp = tmp + sub * tmp_stride;
+  const int c0 = blockIdx.z;
+  for (int c = c0; c < ncols; c += gridDim.z) {
+    double acc = 0.0;
+    for (int t = 0; t < cnt; ++t) acc += a[t] * (double)z[nbr[t] + (int64_t)S.n_r * c];
+    if (fwd) z[row + (int64_t)S.n_r * c] -= (T)acc;
+    else tp[i + (int64_t)B.last_n * c] = (T)acc;
+  }
+}
+
+template <typename T>
+__global__ void k_copy_block_rows(PlanDev P, int k, const T* __restrict__ Z, T* __restrict__ tmp,
+                                  int64_t tmp_stride) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  if (k >= S.nbR) return;
+  const BlockDev B = P.blocks[S.bR_off + k];
+  const int ncols = S.n_a + S.n_v;
+  const int64_t tot = (int64_t)B.size * ncols;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx % B.size), c = (int)(idx / B.size);
+    tmp[sub * tmp_stride + idx] = Z[S.Z_off + B.start + i + (int64_t)S.n_r * c];
+  }
+}
+
+// S_c[a, b] = (C_r X)[a, b]: mean of X's column b over object a's nodes.
+template <typename T>
+__global__ void k_sc_assemble(PlanDev P, const T* __restrict__ Z, T* __restrict__ Sc) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= S.n_a * S.n_a) return;
+  const int a = idx % S.n_a, b = idx / S.n_a;
+  const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
+  double s = 0.0;
+  for (int t = pb; t < pe; ++t) s += (double)Z[S.Z_off + P.a_r[t] + (int64_t)S.n_r * b];
+  Sc[S.Sc_off + idx] = (T)(s / (double)(pe - pb));
+}
+
+// T[a, c] = (C_r Y)[a, c] - [0 I][a, c]: Y is -K_rr^{-1} K_rv at vertex
+// columns and 0 at average columns.
+template <typename T>
+__global__ void k_lambda_rhs(PlanDev P, const T* __restrict__ Z, T* __restrict__ Tm) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= S.n_a * S.n_c) return;
+  const int a = idx % S.n_a, c = idx / S.n_a;
+  const int kind = P.c_kind[S.c_off + c];
+  double v;
+  if (kind >= 0) {
+    const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
+    double s = 0.0;
+    for (int t = pb; t < pe; ++t) s += (double)Z[S.Z_off + P.a_r[t] + (int64_t)S.n_r * (S.n_a + kind)];
+    v = s / (double)(pe - pb);
+  } else {
+    v = (-kind - 1 == a) ? -1.0 : 0.0;
+  }
+  Tm[S.T_off + idx] = (T)v;
+}
+
+template <typename T>
+__global__ void k_phi_r_init(PlanDev P, const T* __restrict__ Z, T* __restrict__ PhiR) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int64_t tot = (int64_t)S.n_r * S.n_c;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx % S.n_r), c = (int)(idx / S.n_r);
+    int kind = P.c_kind[S.c_off + c];
+    PhiR[S.KPhi_off + idx] = kind >= 0 ? Z[S.Z_off + i + (int64_t)S.n_r * (S.n_a + kind)] : (T)0;
+  }
+}
+
+template <typename T>
+__global__ void k_phi_scatter(PlanDev P, const T* __restrict__ PhiR, T* __restrict__ Phi) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int64_t tot = (int64_t)S.n_loc * S.n_c;
+  const int32_t* lr = P.loc_r + S.loc_off;
+  const int32_t* lg = P.loc_g + S.loc_off;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int l = (int)(idx % S.n_loc), c = (int)(idx / S.n_loc);
+    int r = lr[l];
+    T v;
+    if (r >= 0) {
+      v = PhiR[S.KPhi_off + r + (int64_t)S.n_r * c];
+    } else {
+      int vi = P.g_v[S.g_off + lg[l]];
+      v = P.v_c[S.v_off + vi] == c ? (T)1 : (T)0;
+    }
+    Phi[S.Phi_off + idx] = v;
+  }
+}
+
+// KPhi = K_i Phi, matrix-free on the local grid, all columns.
+template <typename T>
+__global__ void k_local_apply_multi(PlanDev P, Geo g, const double* __restrict__ rho,
+                                    const T* __restrict__ Phi, T* __restrict__ KPhi) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= S.n_loc) return;
+  int c[3];
+  loc_coords(S, l, c);
+  double a[27];
+  int nbr[27];
+  int cnt = 0;
+  const int zr = g.dim == 3 ? 1 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int cn[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+        int ln = loc_index(S, cn);
+        if (ln < 0) continue;
+        double v = kloc(S, g, rho, P.khat, c, cn);
+        if (v == 0.0) continue;
+        a[cnt] = v;
+        nbr[cnt++] = ln;
+      }
+  const T* ph = Phi + S.Phi_off;
+  T* kp = KPhi + S.KPhi_off;
+  for (int col = blockIdx.z; col < S.n_c; col += gridDim.z) {
+    double acc = 0.0;
+    for (int t = 0; t < cnt; ++t) acc += a[t] * (double)ph[nbr[t] + (int64_t)S.n_loc * col];
+    kp[l + (int64_t)S.n_loc * col] = (T)acc;
+  }
+}
+
+template <typename T>
+__global__ void k_extract_gamma(PlanDev P, const T* __restrict__ Phi, const T* __restrict__ Z,
+                                T* __restrict__ PhiG, T* __restrict__ XG) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int64_t totp = (int64_t)S.n_g * S.n_c, totx = (int64_t)S.n_g * S.n_a;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < totp + totx;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    if (idx < totp) {
+      int e = (int)(idx % S.n_g), c = (int)(idx / S.n_g);
+      PhiG[S.PhiG_off + idx] = Phi[S.Phi_off + P.g_loc[S.g_off + e] + (int64_t)S.n_loc * c];
+    } else {
+      int64_t j = idx - totp;
+      int e = (int)(j % S.n_g), a = (int)(j / S.n_g);
+      int r = P.g_r[S.g_off + e];
+      XG[S.XG_off + j] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * a] : (T)0;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_kc_to_front(PlanDev P, const int32_t* __restrict__ subs_c, const T* __restrict__ Kc,
+                              double* __restrict__ fpool) {
+  const int sub = subs_c[blockIdx.y];
+  const SubDev S = P.subs[sub];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= S.n_c * S.n_c) return;
+  const int a = idx % S.n_c, b = idx / S.n_c;
+  const FrontDev F = P.fronts[S.front];
+  const int pa = P.sub_fmap[S.c_off + a], pb = P.sub_fmap[S.c_off + b];
+  fpool[F.off + pa + (int64_t)F.n * pb] += (double)Kc[S.Kc_off + idx];
+}
+
+__global__ void k_front_child_scatter(PlanDev P, const int32_t* __restrict__ children,
+                                      double* __restrict__ fpool) {
+  const int ch = children[blockIdx.y];
+  const FrontDev C = P.fronts[ch];
+  const FrontDev F = P.fronts[C.parent];
+  const int nb = C.n - C.p;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nb * nb) return;
+  const int a = (int)(idx % nb), b = (int)(idx / nb);
+  const int pa = P.front_pmap[C.pmap_off + a], pb = P.front_pmap[C.pmap_off + b];
+  fpool[F.off + pa + (int64_t)F.n * pb] += fpool[C.off + (C.p + a) + (int64_t)C.n * (C.p + b)];
+}
+
+// ---------------------------------------------------------------------------
+// per-iteration kernels
+
+template <typename T>
+__global__ void k_gather_I(PlanDev P, Geo g, const double* __restrict__ r, T* __restrict__ vI) {
+  const int sub = blockIdx.y, rhs = blockIdx.z;
+  const SubDev S = P.subs[sub];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n_I) return;
+  vI[rhs * P.tot_I + S.I_off + i] = (T)r[rhs * g.n_free + free_of_local(S, g, P.I_loc[S.I_off + i])];
+}
+
+// Block-tridiagonal solve with explicitly inverted diagonal blocks, one
+// workgroup per (subdomain, right-hand side):
+//   forward  c_k = b_k - A_{k,k-1} xh_{k-1},  xh_k = G_k c_k
+//   backward x_k = xh_k - G_k A_{k,k+1} x_{k+1}
+// (G_k = -Gs_k, the swept block).  The couplings A_{k,k+-1} are applied
+// matrix-free from rho; each G_k is streamed once forward, and its last-plane
+// columns once backward.
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_solve(PlanDev P, Geo g, const double* __restrict__ rho,
+                                                     int setR, const T* __restrict__ G,
+                                                     T* __restrict__ vec) {
+  extern __shared__ char smem_raw[];
+  T* cl = reinterpret_cast<T*>(smem_raw);
+  const int sub = blockIdx.x, rhs = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int nb = setR ? S.nbR : S.nbI;
+  const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
+  const int32_t* sl = set_loc_of(P, S, setR);
+  const int32_t* ls = loc_set_of(P, S, setR);
+  T* v = vec + rhs * (setR ? P.tot_r : P.tot_I) + (setR ? S.r_off : S.I_off);
+  const int tid = threadIdx.x;
+  const int nt = g.dim == 3 ? 9 : 3;
+  for (int k = 0; k < nb; ++k) {
+    const BlockDev B = blk[k];
+    for (int i = tid; i < B.size; i += blockDim.x) cl[i] = v[B.start + i];
+    __syncthreads();
+    if (k > 0 && blk[k - 1].plane_hi == B.plane_lo) {
+      for (int i = tid; i < B.first_n; i += blockDim.x) {
+        int ci[3];
+        loc_coords(S, sl[B.start + i], ci);
+        double acc = 0.0;
+        for (int t = 0; t < nt; ++t) {
+          int cn[3];
+          if (!plane_nbr(S, g.dim, ci, -1, t, cn)) continue;
+          int j = ls[loc_index(S, cn)];
+          if (j < 0) continue;
+          acc += kloc(S, g, rho, P.khat, ci, cn) * (double)v[j];
+        }
+        cl[i] -= (T)acc;
+      }
+    }
+    __syncthreads();
+    const T* Gk = G + B.G_off;
+    for (int i = tid; i < B.size; i += blockDim.x) {
+      T acc = 0;
+      for (int j = 0; j < B.size; ++j) acc += Gk[i + (int64_t)B.size * j] * cl[j];
+      v[B.start + i] = -acc;
+    }
+    __syncthreads();
+  }
+  for (int k = nb - 2; k >= 0; --k) {
+    const BlockDev B = blk[k];
+    const BlockDev N = blk[k + 1];
+    if (B.plane_hi != N.plane_lo) continue;
+    const int base = B.size - B.last_n;
+    for (int i = tid; i < B.last_n; i += blockDim.x) {
+      int ci[3];
+      loc_coords(S, sl[B.start + base + i], ci);
+      double acc = 0.0;
+      for (int t = 0; t < nt; ++t) {
+        int cn[3];
+        if (!plane_nbr(S, g.dim, ci, 1, t, cn)) continue;
+        int j = ls[loc_index(S, cn)];
+        if (j < 0) continue;
+        acc += kloc(S, g, rho, P.khat, ci, cn) * (double)v[j];
+      }
+      cl[i] = (T)acc;
+    }
+    __syncthreads();
+    const T* Gk = G + B.G_off + (int64_t)B.size * base;
+    for (int i = tid; i < B.size; i += blockDim.x) {
+      T acc = 0;
+      for (int q = 0; q < B.last_n; ++q) acc += Gk[i + (int64_t)B.size * q] * cl[q];
+      v[B.start + i] += acc;
+    }
+    __syncthreads();
+  }
+}
+
+// q[e] = (K_{Gamma I} y_I)[e] for the Gamma entries of each subdomain.
+template <typename T>
+__global__ void k_gamma_kgi(PlanDev P, Geo g, const double* __restrict__ rho, const T* __restrict__ vI,
+                            T* __restrict__ q) {
+  const int sub = blockIdx.y, rhs = blockIdx.z;
+  const SubDev S = P.subs[sub];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S.n_g) return;
+  int c[3];
+  loc_coords(S, P.g_loc[S.g_off + e], c);
+  const int32_t* li = P.loc_I + S.loc_off;
+  const T* y = vI + rhs * P.tot_I + S.I_off;
+  double acc = 0.0;
+  const int zr = g.dim == 3 ? 1 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int cn[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+        int ln = loc_index(S, cn);
+        if (ln < 0) continue;
+        int j = li[ln];
+        if (j < 0) continue;
+        acc += kloc(S, g, rho, P.khat, c, cn) * (double)y[j];
+      }
+  q[rhs * P.tot_g + S.g_off + e] = (T)acc;
+}
+
+// t = r_Gamma - sum_i q_i (I - P)^T, then g_e = delta_e t (E^T).
+template <typename T>
+__global__ void k_gamma_t(PlanDev P, Geo g, const double* __restrict__ r, const T* __restrict__ q,
+                          const double* __restrict__ delta, T* __restrict__ gv) {
+  const int64_t qg = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (qg >= P.n_gam) return;
+  double t = r[rhs * g.n_free + P.gam_node[qg]];
+  const int b = P.gam_eptr[qg], e = P.gam_eptr[qg + 1];
+  for (int k = b; k < e; ++k) t -= (double)q[rhs * P.tot_g + P.gam_ent[k]];
+  for (int k = b; k < e; ++k) {
+    int ent = P.gam_ent[k];
+    gv[rhs * P.tot_g + ent] = (T)(delta[ent] * t);
+  }
+}
+
+template <typename T>
+__global__ void k_neumann_rhs(PlanDev P, const T* __restrict__ gv, T* __restrict__ vR) {
+  const int sub = blockIdx.y, rhs = blockIdx.z;
+  const SubDev S = P.subs[sub];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S.n_g) return;
+  const int r = P.g_r[S.g_off + e];
+  if (r >= 0) vR[rhs * P.tot_r + S.r_off + r] = gv[rhs * P.tot_g + S.g_off + e];
+}
+
+// mu = S_c^{-1} C_r u, one workgroup per (subdomain, rhs).  Sc holds the
+// swept matrix -S_c^{-1}.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mu(PlanDev P, const T* __restrict__ vR, const T* __restrict__ Sc,
+                                            T* __restrict__ mu) {
+  extern __shared__ char smem_raw[];
+  T* av = reinterpret_cast<T*>(smem_raw);
+  const int sub = blockIdx.x, rhs = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const T* u = vR + rhs * P.tot_r + S.r_off;
+  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x) {
+    const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
+    double s = 0.0;
+    for (int t = pb; t < pe; ++t) s += (double)u[P.a_r[t]];
+    av[a] = (T)(s / (double)(pe - pb));
+  }
+  __syncthreads();
+  const T* M = Sc + S.Sc_off;
+  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x) {
+    T acc = 0;
+    for (int b = 0; b < S.n_a; ++b) acc += M[a + (int64_t)S.n_a * b] * av[b];
+    mu[rhs * P.tot_a + S.am_off + a] = -acc;
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// bci = Phi_Gamma^T g_Gamma, one workgroup per (subdomain, rhs), one wave per column.
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_rhs_local(PlanDev P, const T* __restrict__ PhiG,
+                                                          const T* __restrict__ gv, T* __restrict__ bci) {
+  extern __shared__ char smem_raw[];
+  T* gl = reinterpret_cast<T*>(smem_raw);
+  const int sub = blockIdx.x, rhs = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const T* g = gv + rhs * P.tot_g + S.g_off;
+  for (int e = threadIdx.x; e < S.n_g; e += blockDim.x) gl[e] = g[e];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const T* M = PhiG + S.PhiG_off;
+  for (int c = wave; c < S.n_c; c += blockDim.x >> 6) {
+    double acc = 0.0;
+    for (int e = lane; e < S.n_g; e += 64) acc += (double)(M[e + (int64_t)S.n_g * c] * gl[e]);
+    acc = wave_sum(acc);
+    if (lane == 0) bci[rhs * P.tot_c + S.c_off + c] = (T)acc;
+  }
+}
+
+// v2 on Gamma = u - X mu + Phi_Gamma u_c (v_Delta plus the coarse correction).
+template <typename T>
+__global__ __launch_bounds__(256) void k_v2(PlanDev P, const T* __restrict__ vR, const T* __restrict__ XG,
+                                            const T* __restrict__ mu, const T* __restrict__ PhiG,
+                                            const double* __restrict__ uc, T* __restrict__ v2) {
+  extern __shared__ char smem_raw[];
+  T* sh = reinterpret_cast<T*>(smem_raw);
+  const int sub = blockIdx.x, rhs = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  T* mul = sh;
+  T* ucl = sh + S.n_a;
+  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x) mul[a] = mu[rhs * P.tot_a + S.am_off + a];
+  for (int c = threadIdx.x; c < S.n_c; c += blockDim.x)
+    ucl[c] = (T)uc[rhs * P.n_coarse + P.c_glob[S.c_off + c]];
+  __syncthreads();
+  const T* u = vR + rhs * P.tot_r + S.r_off;
+  const T* X = XG + S.XG_off;
+  const T* F = PhiG + S.PhiG_off;
+  for (int e = threadIdx.x; e < S.n_g; e += blockDim.x) {
+    const int r = P.g_r[S.g_off + e];
+    T acc = r >= 0 ? u[r] : (T)0;
+    for (int a = 0; a < S.n_a; ++a) acc -= X[e + (int64_t)S.n_g * a] * mul[a];
+    for (int c = 0; c < S.n_c; ++c) acc += F[e + (int64_t)S.n_g * c] * ucl[c];
+    v2[rhs * P.tot_g + S.g_off + e] = acc;
+  }
+}
+
+// Interior right-hand side of the second Dirichlet solve: r_I - K_{I Gamma} w.
+template <typename T>
+__global__ void k_interior_rhs(PlanDev P, Geo g, const double* __restrict__ rho,
+                               const double* __restrict__ r, const double* __restrict__ w,
+                               T* __restrict__ vI) {
+  const int sub = blockIdx.y, rhs = blockIdx.z;
+  const SubDev S = P.subs[sub];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n_I) return;
+  const int l = P.I_loc[S.I_off + i];
+  int c[3];
+  loc_coords(S, l, c);
+  const int32_t* lg = P.loc_g + S.loc_off;
+  double acc = r[rhs * g.n_free + free_of_local(S, g, l)];
+  const int zr = g.dim == 3 ? 1 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int cn[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+        int ln = loc_index(S, cn);
+        if (ln < 0 || lg[ln] < 0) continue;
+        acc -= kloc(S, g, rho, P.khat, c, cn) * w[rhs * g.n_free + free_of_local(S, g, ln)];
+      }
+  vI[rhs * P.tot_I + S.I_off + i] = (T)acc;
+}
+
+template <typename T>
+__global__ void k_scatter_I(PlanDev P, Geo g, const T* __restrict__ vI, double* __restrict__ z) {
+  const int sub = blockIdx.y, rhs = blockIdx.z;
+  const SubDev S = P.subs[sub];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n_I) return;
+  z[rhs * g.n_free + free_of_local(S, g, P.I_loc[S.I_off + i])] =
+      (double)vI[rhs * P.tot_I + S.I_off + i];
+}
+
+template <typename T>
+__global__ void k_coarse_rhs_gather(PlanDev P, const T* __restrict__ bci, double* __restrict__ bc) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (c >= P.n_coarse) return;
+  double s = 0.0;
+  for (int k = P.crs_eptr[c]; k < P.crs_eptr[c + 1]; ++k) s += (double)bci[rhs * P.tot_c + P.crs_ent[k]];
+  bc[rhs * P.n_coarse + c] = s;
+}
+
+// w = E v2 on Gamma (weighted sum over the subdomains sharing each node).
+template <typename T>
+__global__ void k_gamma_w(PlanDev P, Geo g, const T* __restrict__ v2, const double* __restrict__ delta,
+                          double* __restrict__ z) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (q >= P.n_gam) return;
+  double w = 0.0;
+  for (int k = P.gam_eptr[q]; k < P.gam_eptr[q + 1]; ++k) {
+    int ent = P.gam_ent[k];
+    w += delta[ent] * (double)v2[rhs * P.tot_g + ent];
+  }
+  z[rhs * g.n_free + P.gam_node[q]] = w;
+}
+
+// ---- coarse multifrontal solve ------------------------------------------
+
+__global__ void k_front_vec_init(PlanDev P, const int32_t* __restrict__ fr, const double* __restrict__ bc,
+                                 double* __restrict__ fvec, int64_t stride) {
+  const FrontDev F = P.fronts[fr[blockIdx.y]];
+  const int rhs = blockIdx.z;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= F.n) return;
+  fvec[rhs * stride + F.voff + k] = k < F.p ? bc[rhs * P.n_coarse + P.front_idx[F.idx_off + k]] : 0.0;
+}
+
+__global__ void k_front_vec_scatter(PlanDev P, const int32_t* __restrict__ ch, double* __restrict__ fvec,
+                                    int64_t stride) {
+  const FrontDev C = P.fronts[ch[blockIdx.y]];
+  const FrontDev F = P.fronts[C.parent];
+  const int rhs = blockIdx.z;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= C.n - C.p) return;
+  fvec[rhs * stride + F.voff + P.front_pmap[C.pmap_off + k]] += fvec[rhs * stride + C.voff + C.p + k];
+}
+
+// z = F[:, :p] y_P; xh_P = -z_P (F_PP holds -G); y_B -= z_B (F_BP holds L~).
+__global__ __launch_bounds__(256) void k_front_fwd(PlanDev P, const int32_t* __restrict__ fr,
+                                                   const double* __restrict__ fpool,
+                                                   double* __restrict__ fvec, double* __restrict__ xh,
+                                                   int64_t stride) {
+  __shared__ double yl[2048];
+  const FrontDev F = P.fronts[fr[blockIdx.y]];
+  const int rhs = blockIdx.z;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int64_t)blockIdx.x * blockDim.x >= F.n || F.p == 0) return;
+  const double* M = fpool + F.off;
+  double* y = fvec + rhs * stride + F.voff;
+  double acc = 0.0;
+  for (int j0 = 0; j0 < F.p; j0 += 2048) {
+    const int jn = min(2048, F.p - j0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < jn; j += blockDim.x) yl[j] = y[j0 + j];
+    __syncthreads();
+    if (i < F.n)
+      for (int j = 0; j < jn; ++j) acc += M[i + (int64_t)F.n * (j0 + j)] * yl[j];
+  }
+  __syncthreads();
+  if (i >= F.n) return;
+  if (i < F.p) xh[rhs * stride + F.voff + i] = -acc;
+  else y[i] -= acc;
+}
+
+// x_P = xh_P - L~^T x_B, x_B from ancestors; one wave per pivot column.
+__global__ __launch_bounds__(256) void k_front_bwd(PlanDev P, const int32_t* __restrict__ fr,
+                                                   const double* __restrict__ fpool,
+                                                   const double* __restrict__ xh, int64_t stride,
+                                                   double* __restrict__ uc) {
+  __shared__ double xb[2048];
+  const FrontDev F = P.fronts[fr[blockIdx.y]];
+  const int rhs = blockIdx.z;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k = blockIdx.x * (blockDim.x >> 6) + wave;
+  if ((int64_t)blockIdx.x * (blockDim.x >> 6) >= F.p) return;
+  const int nb = F.n - F.p;
+  const double* M = fpool + F.off;
+  double acc = 0.0;
+  for (int b0 = 0; b0 < nb; b0 += 2048) {
+    const int bn = min(2048, nb - b0);
+    __syncthreads();
+    for (int b = threadIdx.x; b < bn; b += blockDim.x)
+      xb[b] = uc[rhs * P.n_coarse + P.front_idx[F.idx_off + F.p + b0 + b]];
+    __syncthreads();
+    if (k < F.p)
+      for (int b = lane; b < bn; b += 64) acc += M[(F.p + b0 + b) + (int64_t)F.n * k] * xb[b];
+  }
+  acc = wave_sum(acc);
+  if (k < F.p && lane == 0)
+    uc[rhs * P.n_coarse + P.front_idx[F.idx_off + k]] = xh[rhs * stride + F.voff + k] - acc;
+}
+
+// ---- PCG vectors ----------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ a,
+                                                     const double* __restrict__ b, int64_t n,
+                                                     double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int rhs = blockIdx.y;
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const double* ar = a + rhs * n;
+  const double* br = b + rhs * n;
+  double s = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += ar[i] * br[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[rhs * gridDim.x + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ partial, int nb,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int rhs = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[rhs * nb + i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[rhs] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ void k_pcg_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                         const double* __restrict__ q, const double* __restrict__ rz,
+                         const double* __restrict__ pq, const int32_t* __restrict__ active, int64_t n) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const double alpha = rz[rhs] / pq[rhs];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t k = rhs * n + i;
+  x[k] += alpha * p[k];
+  r[k] -= alpha * q[k];
+}
+
+__global__ void k_pcg_p(double* __restrict__ p, const double* __restrict__ z,
+                        const double* __restrict__ num, const double* __restrict__ den,
+                        const int32_t* __restrict__ active, int64_t n) {
+  const int rhs = blockIdx.y;
+  if (!active[rhs]) return;
+  const double beta = num[rhs] / den[rhs];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t k = rhs * n + i;
+  p[k] = z[k] + beta * p[k];
+}
+
+// ---- gradient and filter ---------------------------------------------------
+
+__global__ void k_element_grad(Geo g, const double* __restrict__ khat, const double* __restrict__ rho,
+                               const double* __restrict__ u, const double* __restrict__ lam,
+                               double* __restrict__ out, int nrhs) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= g.n_elem) return;
+  const int ex = (int)(e % g.ne[0]);
+  const int ey = (int)((e / g.ne[0]) % g.ne[1]);
+  const int ez = (int)(e / ((int64_t)g.ne[0] * g.ne[1]));
+  const int nn = g.dim == 3 ? 8 : 4;
+  int64_t fid[8];
+  for (int a = 0; a < nn; ++a) {
+    int x = ex + (a & 1), y = ey + ((a >> 1) & 1), z = g.dim == 3 ? ez + ((a >> 2) & 1) : 1;
+    bool ok = x >= 1 && y >= 1 && x <= g.nf[0] && y <= g.nf[1] && (g.dim == 2 || (z >= 1 && z <= g.nf[2]));
+    fid[a] = ok ? (x - 1) + (int64_t)g.nf[0] * ((y - 1) + (int64_t)g.nf[1] * (z - 1)) : -1;
+  }
+  double s = 0.0;
+  for (int rhs = 0; rhs < nrhs; ++rhs) {
+    double ue[8], le[8];
+    for (int a = 0; a < nn; ++a) {
+      ue[a] = fid[a] >= 0 ? u[rhs * g.n_free + fid[a]] : 0.0;
+      le[a] = fid[a] >= 0 ? lam[rhs * g.n_free + fid[a]] : 0.0;
+    }
+    for (int a = 0; a < nn; ++a) {
+      double t = 0.0;
+      for (int b = 0; b < nn; ++b) t += khat[(a | (g.dim == 2 ? 4 : 0)) * 8 + (b | (g.dim == 2 ? 4 : 0))] * ue[b];
+      s += le[a] * t;
+    }
+  }
+  out[e] = -rho[e] * s;
+}
+
+__device__ __forceinline__ int filter_count(const Geo& g, int ex, int ey, int ez) {
+  int cx = (ex > 0) + 1 + (ex < g.ne[0] - 1);
+  int cy = (ey > 0) + 1 + (ey < g.ne[1] - 1);
+  int cz = g.dim == 3 ? (ez > 0) + 1 + (ez < g.ne[2] - 1) : 1;
+  return cx * cy * cz;
+}
+
+__global__ void k_box_filter(Geo g, const double* __restrict__ in, double* __restrict__ out, int transpose) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= g.n_elem) return;
+  const int ex = (int)(e % g.ne[0]);
+  const int ey = (int)((e / g.ne[0]) % g.ne[1]);
+  const int ez = (int)(e / ((int64_t)g.ne[0] * g.ne[1]));
+  const int zr = g.dim == 3 ? 1 : 0;
+  double s = 0.0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int x = ex + dx, y = ey + dy, z = ez + dz;
+        if (x < 0 || y < 0 || z < 0 || x >= g.ne[0] || y >= g.ne[1] || z >= g.ne[2]) continue;
+        int64_t e2 = x + (int64_t)g.ne[0] * (y + (int64_t)g.ne[1] * z);
+        s += transpose ? in[e2] / (double)filter_count(g, x, y, z) : in[e2];
+      }
+  out[e] = transpose ? s : s / (double)filter_count(g, ex, ey, ez);
+}
+
+}  // namespace
+
+// ===========================================================================
+// launchers
+
+#define LAUNCH_CHECK() (void)hipGetLastError()
+
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<double><<<hmin(cdiv(n, 256), 65536), 256, 0, s>>>(p, n, v);
+}
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<float><<<hmin(cdiv(n, 256), 65536), 256, 0, s>>>(p, n, v);
+}
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<int32_t><<<hmin(cdiv(n, 256), 65536), 256, 0, s>>>(p, n, v);
+}
+void launch_kc_to_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_f32_to_f64<<<hmin(cdiv(n, 256), 65536), 256, 0, s>>>(src, dst, n);
+}
+void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_sub<<<hmin(cdiv(n, 256), 65536), 256, 0, s>>>(a, b, out, n);
+}
+
+void launch_q1_apply(const Geo& g, const double* khat, const double* rho, const double* x,
+                     double* y, int nrhs, hipStream_t s) {
+  k_q1_apply<<<dim3(cdiv(g.n_free, 256), nrhs), 256, 0, s>>>(g, khat, rho, x, y);
+}
+
+void launch_alpha(const PlanDev& P, int n_ss, const double* rho, int weighting, double* alpha,
+                  hipStream_t s) {
+  k_alpha<<<cdiv(n_ss, 256), 256, 0, s>>>(P, n_ss, rho, weighting, alpha);
+}
+void launch_delta(const PlanDev& P, const double* alpha, double* delta, hipStream_t s) {
+  if (P.tot_g == 0) return;
+  k_delta<<<cdiv(P.tot_g, 256), 256, 0, s>>>(P, alpha, delta);
+}
+
+template <typename T>
+void Kern<T>::block_assemble(const PlanDev& P, const Geo& g, const double* rho, int setR, T* G,
+                             hipStream_t s) {
+  int mx = setR ? P.max_nr : P.max_nI;
+  if (mx == 0) return;
+  k_block_assemble<T><<<dim3(cdiv(mx, 128), P.n_sub), 128, 0, s>>>(P, g, rho, setR, G);
+}
+
+template <typename T>
+void Kern<T>::schur_couple(const PlanDev& P, const Geo& g, const double* rho, int setR, int k, T* G,
+                           T* W, int64_t wstride, hipStream_t s) {
+  int mp = P.max_plane;
+  k_schur_w<T><<<dim3(cdiv((int64_t)mp * mp, 256), P.n_sub), 256, 0, s>>>(P, g, rho, setR, k, G, W, wstride);
+  k_schur_apply<T><<<dim3(cdiv((int64_t)mp * mp, 256), P.n_sub), 256, 0, s>>>(P, g, rho, setR, k, G, W, wstride);
+}
+
+template <typename T>
+void Kern<T>::sweep(SweepDesc* d_desc, int nprob, int maxn, int maxp, T* pool, T* scratch,
+                    int64_t scr_stride, int* status, int status_code, hipStream_t s) {
+  if (nprob == 0 || maxp == 0) return;
+  int tiles = (int)cdiv(maxn, TILE);
+  int prev = -1;
+  for (int j0 = 0; j0 < maxp; j0 += SWEEP_NB) {
+    k_sweep_panel<T><<<nprob, 256, 0, s>>>(d_desc, pool, j0, prev, scratch, scr_stride, status, status_code);
+    k_sweep_update<T><<<dim3(tiles * tiles, nprob), 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, tiles);
+    prev = j0;
+  }
+  k_sweep_panel<T><<<nprob, 256, 0, s>>>(d_desc, pool, -1, prev, scratch, scr_stride, status, status_code);
+}
+
+template <typename T>
+void Kern<T>::gemm(const GemmDesc* d_desc, int nprob, int maxm, int maxn, const T* A, int transA,
+                   const T* B, int transB, T* C, T alpha, T beta, hipStream_t s) {
+  if (nprob == 0 || maxm == 0 || maxn == 0) return;
+  int tm = (int)cdiv(maxm, TILE), tn = (int)cdiv(maxn, TILE);
+  dim3 grid(tm * tn, nprob);
+  if (!transA && !transB) k_gemm<T, 0, 0><<<grid, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm);
+  else if (transA && !transB) k_gemm<T, 1, 0><<<grid, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm);
+  else if (!transA && transB) k_gemm<T, 0, 1><<<grid, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm);
+  else k_gemm<T, 1, 1><<<grid, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm);
+}
+
+template <typename T>
+void Kern<T>::rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, hipStream_t s) {
+  if (P.max_zcols == 0) return;
+  k_rhs_fill<T><<<dim3(cdiv(P.max_zcols, 64), P.n_sub), 64, 0, s>>>(P, g, rho, Z);
+}
+
+template <typename T>
+void Kern<T>::couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
+                           int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s) {
+  if (ncols_max == 0) return;
+  int zc = hmin(ncols_max, 16);
+  k_couple_multi<T><<<dim3(cdiv(P.max_plane, 64), P.n_sub, zc), 64, 0, s>>>(P, g, rho, k, fwd, Z, tmp, tmp_stride);
+}
+
+template <typename T>
+void Kern<T>::copy_block_rows(const PlanDev& P, int k, int ncols_max, const T* Z, T* tmp,
+                              int64_t tmp_stride, hipStream_t s) {
+  int64_t tot = (int64_t)P.max_block * ncols_max;
+  if (tot == 0) return;
+  k_copy_block_rows<T><<<dim3(hmin(cdiv(tot, 256), 1024), P.n_sub), 256, 0, s>>>(P, k, Z, tmp, tmp_stride);
+}
+
+template <typename T>
+void Kern<T>::sc_assemble(const PlanDev& P, const T* Z, T* Sc, hipStream_t s) {
+  if (P.max_na == 0) return;
+  k_sc_assemble<T><<<dim3(cdiv((int64_t)P.max_na * P.max_na, 256), P.n_sub), 256, 0, s>>>(P, Z, Sc);
+}
+
+template <typename T>
+void Kern<T>::lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s) {
+  if (P.max_na == 0 || P.max_nc == 0) return;
+  k_lambda_rhs<T><<<dim3(cdiv((int64_t)P.max_na * P.max_nc, 256), P.n_sub), 256, 0, s>>>(P, Z, Tm);
+}
+
+template <typename T>
+void Kern<T>::phi_r_init(const PlanDev& P, const T* Z, T* PhiR, hipStream_t s) {
+  int64_t tot = (int64_t)P.max_nr * P.max_nc;
+  if (tot == 0) return;
+  k_phi_r_init<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, PhiR);
+}
+
+template <typename T>
+void Kern<T>::phi_scatter(const PlanDev& P, const T* PhiR, T* Phi, hipStream_t s) {
+  int64_t tot = (int64_t)P.max_nloc * P.max_nc;
+  if (tot == 0) return;
+  k_phi_scatter<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, PhiR, Phi);
+}
+
+template <typename T>
+void Kern<T>::local_apply_multi(const PlanDev& P, const Geo& g, const double* rho, const T* Phi,
+                                T* KPhi, hipStream_t s) {
+  if (P.max_nc == 0) return;
+  int zc = hmin(P.max_nc, 16);
+  k_local_apply_multi<T><<<dim3(cdiv(P.max_nloc, 128), P.n_sub, zc), 128, 0, s>>>(P, g, rho, Phi, KPhi);
+}
+
+template <typename T>
+void Kern<T>::extract_gamma(const PlanDev& P, const T* Phi, const T* Z, T* PhiG, T* XG, hipStream_t s) {
+  int64_t tot = (int64_t)P.max_ng * (P.max_nc + P.max_na);
+  if (tot == 0) return;
+  k_extract_gamma<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Phi, Z, PhiG, XG);
+}
+
+template <typename T>
+void Kern<T>::kc_to_front(const PlanDev& P, const int32_t* subs_c, int ns, const T* Kc, double* fpool,
+                          hipStream_t s) {
+  if (ns == 0 || P.max_nc == 0) return;
+  k_kc_to_front<T><<<dim3(cdiv((int64_t)P.max_nc * P.max_nc, 256), ns), 256, 0, s>>>(P, subs_c, Kc, fpool);
+}
+
+template <typename T>
+void Kern<T>::gather_I(const PlanDev& P, const Geo& g, const double* r, T* vI, int nrhs, hipStream_t s) {
+  if (P.max_nI == 0) return;
+  k_gather_I<T><<<dim3(cdiv(P.max_nI, 256), P.n_sub, nrhs), 256, 0, s>>>(P, g, r, vI);
+}
+
+template <typename T>
+void Kern<T>::block_solve(const PlanDev& P, const Geo& g, const double* rho, int setR, const T* G,
+                          T* v, int nrhs, hipStream_t s) {
+  size_t sm = (size_t)hmax(P.max_block, 1) * sizeof(T);
+  k_block_solve<T><<<dim3(P.n_sub, nrhs), 256, sm, s>>>(P, g, rho, setR, G, v);
+}
+
+template <typename T>
+void Kern<T>::gamma_kgi(const PlanDev& P, const Geo& g, const double* rho, const T* vI, T* q, int nrhs,
+                        hipStream_t s) {
+  if (P.max_ng == 0) return;
+  k_gamma_kgi<T><<<dim3(cdiv(P.max_ng, 128), P.n_sub, nrhs), 128, 0, s>>>(P, g, rho, vI, q);
+}
+
+template <typename T>
+void Kern<T>::gamma_t(const PlanDev& P, const Geo& g, const double* r, const T* q, const double* delta, T* gv,
+                      int nrhs, hipStream_t s) {
+  if (P.n_gam == 0) return;
+  k_gamma_t<T><<<dim3(cdiv(P.n_gam, 256), nrhs), 256, 0, s>>>(P, g, r, q, delta, gv);
+}
+
+template <typename T>
+void Kern<T>::neumann_rhs(const PlanDev& P, const T* gv, T* vR, int nrhs, hipStream_t s) {
+  if (P.max_ng == 0) return;
+  k_neumann_rhs<T><<<dim3(cdiv(P.max_ng, 128), P.n_sub, nrhs), 128, 0, s>>>(P, gv, vR);
+}
+
+template <typename T>
+void Kern<T>::mu(const PlanDev& P, const T* vR, const T* Sc, T* mu_out, int nrhs, hipStream_t s) {
+  if (P.max_na == 0) return;
+  k_mu<T><<<dim3(P.n_sub, nrhs), 256, (size_t)P.max_na * sizeof(T), s>>>(P, vR, Sc, mu_out);
+}
+
+template <typename T>
+void Kern<T>::coarse_rhs_local(const PlanDev& P, const T* PhiG, const T* gv, T* bci, int nrhs, hipStream_t s) {
+  if (P.max_nc == 0) return;
+  k_coarse_rhs_local<T><<<dim3(P.n_sub, nrhs), 256, (size_t)hmax(P.max_ng, 1) * sizeof(T), s>>>(P, PhiG, gv, bci);
+}
+
+template <typename T>
+void Kern<T>::v2(const PlanDev& P, const T* vR, const T* XG, const T* mu_in, const T* PhiG, const double* uc,
+                 T* v2_out, int nrhs, hipStream_t s) {
+  if (P.max_ng == 0) return;
+  size_t sm = (size_t)(P.max_na + P.max_nc + 1) * sizeof(T);
+  k_v2<T><<<dim3(P.n_sub, nrhs), 256, sm, s>>>(P, vR, XG, mu_in, PhiG, uc, v2_out);
+}
+
+template <typename T>
+void Kern<T>::interior_rhs(const PlanDev& P, const Geo& g, const double* rho, const double* r, const double* w,
+                           T* vI, int nrhs, hipStream_t s) {
+  if (P.max_nI == 0) return;
+  k_interior_rhs<T><<<dim3(cdiv(P.max_nI, 128), P.n_sub, nrhs), 128, 0, s>>>(P, g, rho, r, w, vI);
+}
+
+template <typename T>
+void Kern<T>::scatter_I(const PlanDev& P, const Geo& g, const T* vI, double* z, int nrhs, hipStream_t s) {
+  if (P.max_nI == 0) return;
+  k_scatter_I<T><<<dim3(cdiv(P.max_nI, 256), P.n_sub, nrhs), 256, 0, s>>>(P, g, vI, z);
+}
+
+void launch_gamma_w(const PlanDev& P, const Geo& g, const double* v2_d, const float* v2_f,
+                    const double* delta, double* z, int nrhs, hipStream_t s) {
+  if (P.n_gam == 0) return;
+  dim3 grid(cdiv(P.n_gam, 256), nrhs);
+  if (v2_d) k_gamma_w<double><<<grid, 256, 0, s>>>(P, g, v2_d, delta, z);
+  else k_gamma_w<float><<<grid, 256, 0, s>>>(P, g, v2_f, delta, z);
+}
+
+void launch_coarse_rhs_gather(const PlanDev& P, const double* bci_d, const float* bci_f, double* bc,
+                              int nrhs, hipStream_t s) {
+  if (P.n_coarse == 0) return;
+  dim3 grid(cdiv(P.n_coarse, 256), nrhs);
+  if (bci_d) k_coarse_rhs_gather<double><<<grid, 256, 0, s>>>(P, bci_d, bc);
+  else k_coarse_rhs_gather<float><<<grid, 256, 0, s>>>(P, bci_f, bc);
+}
+
+void launch_front_child_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
+                                double* fpool, hipStream_t s) {
+  if (nchild == 0 || maxn == 0) return;
+  k_front_child_scatter<<<dim3(cdiv((int64_t)maxn * maxn, 256), nchild), 256, 0, s>>>(P, children, fpool);
+}
+void launch_front_vec_init(const PlanDev& P, const int32_t* fr, int nfr, int maxn, const double* bc,
+                           double* fvec, int64_t stride, int nrhs, hipStream_t s) {
+  if (nfr == 0 || maxn == 0) return;
+  k_front_vec_init<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, bc, fvec, stride);
+}
+void launch_front_vec_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
+                              double* fvec, int64_t stride, int nrhs, hipStream_t s) {
+  if (nchild == 0 || maxn == 0) return;
+  k_front_vec_scatter<<<dim3(cdiv(maxn, 256), nchild, nrhs), 256, 0, s>>>(P, children, fvec, stride);
+}
+void launch_front_fwd(const PlanDev& P, const int32_t* fr, int nfr, int maxn, int maxp, const double* fpool,
+                      double* fvec, double* xh, int64_t stride, int nrhs, hipStream_t s) {
+  if (nfr == 0 || maxp == 0) return;
+  k_front_fwd<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, fpool, fvec, xh, stride);
+}
+void launch_front_bwd(const PlanDev& P, const int32_t* fr, int nfr, int maxp, int maxb, const double* fpool,
+                      const double* xh, int64_t stride, double* uc, int nrhs, hipStream_t s) {
+  (void)maxb;
+  if (nfr == 0 || maxp == 0) return;
+  k_front_bwd<<<dim3(cdiv(maxp, 4), nfr, nrhs), 256, 0, s>>>(P, fr, fpool, xh, stride, uc);
+}
+
+void launch_dot(const double* a, const double* b, int64_t n, int nrhs, double* partial, int nblocks,
+                double* out, hipStream_t s) {
+  k_dot_partial<<<dim3(nblocks, nrhs), 256, 0, s>>>(a, b, n, partial);
+  k_dot_final<<<nrhs, 256, 0, s>>>(partial, nblocks, out);
+}
+void launch_pcg_xr(double* x, double* r, const double* p, const double* q, const double* rz, const double* pq,
+                   const int32_t* active, int64_t n, int nrhs, hipStream_t s) {
+  k_pcg_xr<<<dim3(cdiv(n, 256), nrhs), 256, 0, s>>>(x, r, p, q, rz, pq, active, n);
+}
+void launch_pcg_p(double* p, const double* z, const double* num, const double* den, const int32_t* active,
+                  int64_t n, int nrhs, hipStream_t s) {
+  k_pcg_p<<<dim3(cdiv(n, 256), nrhs), 256, 0, s>>>(p, z, num, den, active, n);
+}
+void launch_pcg_p_flex(double* p, const double* z, const double* zdr, const double* rz_old,
+                       const int32_t* active, int64_t n, int nrhs, hipStream_t s) {
+  k_pcg_p<<<dim3(cdiv(n, 256), nrhs), 256, 0, s>>>(p, z, zdr, rz_old, active, n);
+}
+
+void launch_element_grad(const Geo& g, const double* khat, const double* rho, const double* u,
+                         const double* lam, double* out, int nrhs, hipStream_t s) {
+  k_element_grad<<<cdiv(g.n_elem, 256), 256, 0, s>>>(g, khat, rho, u, lam, out, nrhs);
+}
+void launch_box_filter(const Geo& g, const double* in, double* out, int transpose, hipStream_t s) {
+  k_box_filter<<<cdiv(g.n_elem, 256), 256, 0, s>>>(g, in, out, transpose);
+}
+
+template struct Kern<double>;
+template struct Kern<float>;
+
+}  // namespace bddcso
+
+namespace bddcso {
+namespace {
+// PCG bookkeeping on the device, one thread per right-hand side.
+// After r is updated and rr = r.r: count the iteration, record alpha, test
+// convergence (rr <= tol2), flag breakdown (p.q <= 0 or r.z <= 0).
+__global__ void k_pcg_book1(int nrhs, int k, const double* __restrict__ rz, const double* __restrict__ pq,
+                            const double* __restrict__ rr, const double* __restrict__ tol2,
+                            int32_t* __restrict__ active, int32_t* __restrict__ iters,
+                            int32_t* __restrict__ flags, double* __restrict__ hist_alpha,
+                            int32_t* __restrict__ nactive) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const int j = threadIdx.x;
+  if (j < nrhs) {
+    if (active[j]) {
+      iters[j] = k + 1;
+      const double a = rz[j] / pq[j];
+      hist_alpha[k * nrhs + j] = a;
+      if (!(pq[j] > 0.0) || !(rz[j] > 0.0) || !isfinite(a)) {
+        flags[j] |= 2;  // breakdown
+        active[j] = 0;
+      } else if (rr[j] <= tol2[j]) {
+        flags[j] |= 1;  // converged
+        active[j] = 0;
+      }
+    }
+    if (active[j]) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *nactive = cnt;
+}
+
+// After p = z + beta p: record beta = num/rz and move rz <- rz_new.
+__global__ void k_pcg_book2(int nrhs, int k, double* __restrict__ rz, const double* __restrict__ num,
+                            const double* __restrict__ rz_new, const int32_t* __restrict__ active,
+                            double* __restrict__ hist_beta) {
+  const int j = threadIdx.x;
+  if (j >= nrhs || !active[j]) return;
+  hist_beta[k * nrhs + j] = num[j] / rz[j];
+  rz[j] = rz_new[j];
+}
+}  // namespace
+
+void launch_pcg_book1(int nrhs, int k, const double* rz, const double* pq, const double* rr, const double* tol2,
+                      int32_t* active, int32_t* iters, int32_t* flags, double* hist_alpha, int32_t* nactive,
+                      hipStream_t s) {
+  k_pcg_book1<<<1, 64, 0, s>>>(nrhs, k, rz, pq, rr, tol2, active, iters, flags, hist_alpha, nactive);
+}
+void launch_pcg_book2(int nrhs, int k, double* rz, const double* num, const double* rz_new,
+                      const int32_t* active, double* hist_beta, hipStream_t s) {
+  k_pcg_book2<<<1, 64, 0, s>>>(nrhs, k, rz, num, rz_new, active, hist_beta);
+}
+}  // namespace bddcso

@@ -1,0 +1,103 @@
+// Host-side descriptors, interface classification and the solve plan.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "types.h"
+
+namespace bddcso {
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+// Mesh, partitions and the classification of Gamma into subobjects
+// (Section 3 and its remark on classification).  Independent of the primal
+// selection.
+struct Classification {
+  int dim = 3;
+  int64_t ne[3] = {1, 1, 1};   // elements per axis (ne[2] = 1 in 2D)
+  double h[3] = {1, 1, 1};
+  int64_t nf[3] = {1, 1, 1};   // free nodes per axis (nf[2] = 1 in 2D)
+  int64_t n_free = 0, n_elem = 0;
+  int n_sub = 0, n_ss = 0;
+  std::vector<int32_t> elem_sub, elem_subsub, ss_parent;
+  std::vector<std::array<int, 6>> ebox;   // per subdomain: elo[3], ehi[3]
+  std::vector<int32_t> ss_eptr, ss_elem;  // elements of each subsubdomain
+  // Gamma nodes (free nodes shared by >= 2 subdomains), ascending free index
+  std::vector<int64_t> gam_node;
+  std::vector<int32_t> node_gam;          // free index -> Gamma index or -1
+  std::vector<int32_t> gam_kptr, gam_key; // key: sorted subsubdomain ids
+  std::vector<int32_t> gam_obj;           // Gamma index -> object
+  // objects, numbered by their smallest free index
+  std::vector<int32_t> obj_ptr, obj_gam;  // Gamma indices of each object
+  std::vector<int8_t> obj_type;           // 1 vertex, 2 edge, 4 face
+  std::vector<int32_t> obj_sptr, obj_subs;// subdomains of each object
+
+  int n_obj() const { return (int)obj_type.size(); }
+  void node_coords(int64_t free_idx, int g[3]) const {
+    g[0] = (int)(free_idx % nf[0]) + 1;
+    int64_t t = free_idx / nf[0];
+    g[1] = (int)(t % nf[1]) + 1;
+    g[2] = dim == 3 ? (int)(t / nf[1]) + 1 : 1;
+  }
+  int64_t free_index(const int g[3]) const {
+    return (int64_t)(g[0] - 1) + nf[0] * ((int64_t)(g[1] - 1) + nf[1] * (int64_t)(g[2] - 1));
+  }
+};
+
+// Everything that depends on the primal selection and the options but not on
+// the coefficient: per-subdomain index tables, blocks, coarse numbering, the
+// nested-dissection tree of the coarse problem, pool sizes.
+struct Plan {
+  int primal_mask = 7;
+  int block_target = 192;
+  int coarse_solver = 0;
+  int64_t n_coarse = 0;
+  std::vector<int32_t> coarse_obj;   // coarse id -> object
+  std::vector<int32_t> obj_coarse;   // object -> coarse id or -1
+
+  std::vector<SubDev> subs;
+  std::vector<int32_t> loc_I, loc_r, loc_g;   // per local node: rank in I / r / Gamma entries, -1
+  std::vector<int32_t> I_loc, r_loc;          // set order -> local node
+  std::vector<int32_t> g_loc, g_gam, g_r, g_v, g_sub; // per Gamma entry
+  std::vector<int32_t> v_loc, v_c;            // per vertex: local node, local coarse index
+  std::vector<int32_t> a_ptr, a_r, a_c;       // averages: CSR of r ranks; local coarse index
+  std::vector<int32_t> c_glob, c_kind;        // per local coarse: global id; vertex idx or -(a+1)
+  std::vector<BlockDev> blocks;
+
+  std::vector<int32_t> gam_eptr, gam_ent;     // Gamma index -> Gamma entries
+  std::vector<int32_t> crs_eptr, crs_ent;     // coarse id -> local coarse entries
+  std::vector<std::vector<int32_t>> color_subs;
+
+  // coarse tree
+  std::vector<FrontDev> fronts;
+  std::vector<int32_t> front_idx;             // coarse ids of front positions
+  std::vector<int32_t> front_pmap;            // positions p..n-1 -> parent positions
+  std::vector<int32_t> sub_fmap;              // local coarse entry -> position in its front
+  std::vector<std::vector<int32_t>> level_fronts;       // fronts per level (bottom-up)
+  std::vector<std::vector<std::vector<int32_t>>> level_slot_children; // [level][slot] children
+  int64_t front_pool = 0, front_vec = 0, front_idx_total = 0;
+
+  // totals
+  int64_t tot_loc = 0, tot_I = 0, tot_r = 0, tot_g = 0, tot_v = 0, tot_a = 0, tot_c = 0;
+  int64_t pool_G = 0, pool_Z = 0, pool_XG = 0, pool_Sc = 0, pool_T = 0, pool_Phi = 0,
+          pool_PhiG = 0, pool_Kc = 0;
+  int max_block = 0, max_na = 0, max_nc = 0, max_nr = 0, max_nloc = 0, max_ng = 0;
+  int max_nbI = 0, max_nbR = 0;
+  int max_zcols = 0;
+};
+
+// Builds the classification; returns false and fills err on invalid input.
+bool classify(int dim, const int64_t n_el[3], const double h[3], const int32_t* elem_sub,
+              const int32_t* elem_subsub, Classification& c, Error& err);
+
+bool build_plan(const Classification& c, int primal_mask, int block_target, int coarse_solver,
+                Plan& plan, Error& err);
+
+int object_type(int dim, int key_size);
+
+}  // namespace bddcso

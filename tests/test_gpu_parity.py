@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, on the
+same seeded inputs, element by element.
+
+Sizes span several diagonal blocks and subdomains with ragged (uneven)
+boxes.  Tolerances: the operator to 1e-14 relative, the preconditioner and
+local coarse matrices to 1e-11 relative (different summation orders on both
+sides), PCG iterates at an equal iteration count to 1e-10 relative, the
+free-running iteration count within 1 and the Lanczos kappa within 1%.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bddc, pcg, q1
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def pk():
+    import paper_2001_07289_amd as m
+    return m
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def uneven_3d(cfg=31):
+    """Boxes of 3..6 elements, fine cuts of about 2; rho random per element."""
+    cuts = [[0, 5, 8, 14], [0, 4, 10, 13], [0, 6, 9, 13]]
+    fine = [W.refine_cuts(c, 2) for c in cuts]
+    p = W.tensor_problem((14, 13, 13), cuts, fine, cfg=cfg, name="uneven3d")
+    p.rho = W.rng(cfg, 1).uniform(0.5, 2.0, p.n_elements)
+    return p
+
+
+def cases():
+    rho2 = W.rng(11, 1).uniform(0.1, 10.0, 12 * 12)
+    return {
+        "fig1": W.fig1_problem(),
+        "2d_rho": W.config1_like(n=12, H=6, L=3, cfg=11, rho=rho2),
+        "cfg1": W.config1(),
+        "3d_L3": W.config2_like(n=12, H=6, L=3, cfg=13),
+        "3d_L2_exact": W.config2_like(n=8, H=4, L=2, cfg=12),
+        "uneven3d": uneven_3d(),
+    }
+
+
+CASES = cases()
+
+
+def setup_both(p, **kw):
+    opts = dict(primal_mask=p.primal_mask, weighting=p.weighting)
+    opts.update(kw)
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    pc = m.Preconditioner(prob, dev(p.rho), **opts)
+    orc = bddc.BDDCSO(p.n_el, p.h, p.elem_sub, p.elem_subsub, p.rho,
+                      primal_mask=opts["primal_mask"], weighting=opts["weighting"])
+    return prob, pc, orc
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_operator_apply(name):
+    p = CASES[name]
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    pc = m.Preconditioner(prob, dev(p.rho), weighting=p.weighting)
+    A = q1.assemble(p.n_el, p.h, p.rho)
+    x = W.rng(99, 0).standard_normal((2, p.n_free))
+    y = host(pc.operator(dev(x))).reshape(2, -1)
+    for k in range(2):
+        assert relerr(y[k], A @ x[k]) <= 1e-14
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("coarse_solver", [0, 1], ids=["nd", "dense"])
+def test_preconditioner_apply(name, coarse_solver):
+    p = CASES[name]
+    for weighting in (0, 1):
+        _, pc, orc = setup_both(p, weighting=weighting, coarse_solver=coarse_solver)
+        r = W.rng(98, 0).standard_normal(p.n_free)
+        z = host(pc.apply(dev(r)))
+        zo = orc.apply(r)
+        assert relerr(z, zo) <= 1e-11, (name, weighting, relerr(z, zo))
+
+
+@pytest.mark.parametrize("name", ["cfg1", "3d_L3", "uneven3d"])
+def test_local_coarse_matrices(name):
+    p = CASES[name]
+    _, pc, orc = setup_both(p)
+    for sub in range(orc.cls.n_sub):
+        kc, ids = pc.local_coarse(sub)
+        L = orc.locals[sub]
+        assert np.array_equal(ids, L.coarse)
+        assert np.abs(kc - L.Kc).max() <= 1e-11 * np.abs(L.Kc).max(), sub
+
+
+@pytest.mark.parametrize("name", ["cfg1", "3d_L3", "uneven3d", "2d_rho"])
+def test_pcg_parity(name):
+    p = CASES[name]
+    _, pc, orc = setup_both(p)
+    ref = pcg.solve(orc, p.f[0], rtol=1e-8)
+    m = pk()
+    pcf = m.Preconditioner(m.Problem.from_workload(p), dev(p.rho), fixed_iters=ref.iters)
+    x_fixed, _ = pcf.solve(dev(p.f[0]))
+    assert relerr(host(x_fixed), ref.x) <= 1e-10
+    x, st = pc.solve(dev(p.f[0]))
+    assert abs(st["iters"][0] - ref.iters) <= 1
+    assert st["converged"][0] == 1
+    if ref.iters >= 2:
+        assert abs(st["kappa"][0] - ref.kappa) <= 0.01 * ref.kappa
+    A = q1.assemble(p.n_el, p.h, p.rho)
+    xr = host(x)
+    assert np.linalg.norm(p.f[0] - A @ xr) <= 1.0001e-8 * np.linalg.norm(p.f[0])
+
+
+def test_exact_case_one_iteration():
+    p = CASES["3d_L2_exact"]
+    m = pk()
+    pc = m.Preconditioner(m.Problem.from_workload(p), dev(p.rho))
+    x, st = pc.solve(dev(p.f[0]))
+    assert st["iters"][0] == 1
+    A = q1.assemble(p.n_el, p.h, p.rho).tocsc()
+    import scipy.sparse.linalg as spla
+    assert relerr(host(x), spla.spsolve(A, p.f[0])) <= 1e-10
+
+
+def test_multiple_rhs_lockstep():
+    p = W.config1_like(n=32, H=8, L=4, cfg=40, nrhs=3)
+    p.f[1] *= 1e-3  # different scales converge at different iterations
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    pc = m.Preconditioner(prob, dev(p.rho), max_nrhs=3)
+    x, st = pc.solve(dev(p.f))
+    orc = bddc.BDDCSO(p.n_el, p.h, p.elem_sub, p.elem_subsub, p.rho)
+    xh = host(x).reshape(3, -1)
+    for k in range(3):
+        ref = pcg.solve(orc, p.f[k], rtol=1e-8)
+        assert abs(st["iters"][k] - ref.iters) <= 1
+        assert relerr(xh[k], ref.x) <= 1e-7
+
+
+def test_zero_rhs():
+    p = CASES["cfg1"]
+    m = pk()
+    pc = m.Preconditioner(m.Problem.from_workload(p), dev(p.rho))
+    x, st = pc.solve(dev(np.zeros(p.n_free)))
+    assert st["iters"][0] == 0 and float(host(x).max()) == 0.0
+
+
+def test_repeatable_bits():
+    p = CASES["uneven3d"]
+    m = pk()
+    pc = m.Preconditioner(m.Problem.from_workload(p), dev(p.rho))
+    r = dev(W.rng(97, 0).standard_normal(p.n_free))
+    z1 = host(pc.apply(r))
+    pc.refactor(dev(p.rho))
+    z2 = host(pc.apply(r))
+    assert np.array_equal(z1, z2)
+
+
+def test_singular_setup_is_reported():
+    # a non-positive coefficient on one subdomain gives non-positive pivots
+    p = W.config1_like(n=16, H=8, L=4, cfg=41)
+    rho = p.rho.copy()
+    rho[p.elem_sub == 0] = -1.0
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    with pytest.raises(m.BDDCSOError) as e:
+        m.Preconditioner(prob, dev(rho))
+    assert e.value.name == "ESINGULAR"
+
+
+def test_maxit_exhaustion_is_reported():
+    p = CASES["cfg1"]
+    m = pk()
+    pc = m.Preconditioner(m.Problem.from_workload(p), dev(p.rho), maxit=1)
+    with pytest.raises(m.BDDCSOError) as e:
+        pc.solve(dev(p.f[0]))
+    assert e.value.name == "ENOCONV"
