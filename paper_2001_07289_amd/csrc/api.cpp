@@ -139,7 +139,7 @@ namespace {
 template <typename T>
 struct Numeric {
   T *G = nullptr, *Z = nullptr, *XG = nullptr, *Sc = nullptr, *Tm = nullptr, *Lam = nullptr,
-    *Phi = nullptr, *KPhi = nullptr, *PhiG = nullptr, *Kc = nullptr;
+    *Phi = nullptr, *PhiG = nullptr, *Kc = nullptr;
   T *W = nullptr, *tmp = nullptr, *sw = nullptr;
   int64_t wstride = 0, tmp_stride = 0, sw_stride = 0;
   // per-iteration
@@ -158,13 +158,13 @@ struct bddcso_precond {
   int precision = 0;
   Numeric<double> nd;
   Numeric<float> nf;
-  double *rho = nullptr, *alpha = nullptr, *delta = nullptr, *khat = nullptr;
+  double *rho = nullptr, *alpha = nullptr, *delta = nullptr, *khat = nullptr, *cpl_coef = nullptr;
   double *fpool = nullptr, *fsw = nullptr, *bc = nullptr, *uc = nullptr, *fvec = nullptr, *xh = nullptr;
   int64_t fsw_stride = 0;
   int32_t* status = nullptr;
   // batches
   std::vector<Batch> swI, swR, gfwd, gbwd;
-  Batch swSc, gLam, gPhiR, gKc;
+  Batch swSc, gLam, gPhiR;
   std::vector<Batch> swFront;                       // per level
   std::vector<int32_t*> color_dev;                  // per colour
   std::vector<int> color_n;
@@ -231,7 +231,6 @@ void alloc_numeric(bddcso_precond* pc, hipStream_t s) {
   N.Tm = m.alloc<T>(pl.pool_T);
   N.Lam = m.alloc<T>(pl.pool_T);
   N.Phi = m.alloc<T>(pl.pool_Phi);
-  N.KPhi = m.alloc<T>(pl.pool_Phi);
   N.PhiG = m.alloc<T>(pl.pool_PhiG);
   N.Kc = m.alloc<T>(pl.pool_Kc);
   int max_plane = pc->P.max_plane;
@@ -240,7 +239,7 @@ void alloc_numeric(bddcso_precond* pc, hipStream_t s) {
   N.tmp_stride = (int64_t)pl.max_block * std::max(pl.max_zcols, 1);
   N.tmp = m.alloc<T>(N.tmp_stride * pl.subs.size());
   int maxsw = std::max(pl.max_block, pl.max_na);
-  N.sw_stride = (int64_t)maxsw * 32 + 32 * 32;
+  N.sw_stride = 2 * ((int64_t)maxsw * 32 + 32 * 32);
   N.sw = m.alloc<T>(N.sw_stride * pl.subs.size());
   N.vI = m.alloc<T>(pl.tot_I * nr);
   N.vR = m.alloc<T>(pl.tot_r * nr);
@@ -293,22 +292,20 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
   }
   {
     std::vector<SweepDesc> d;
-    std::vector<GemmDesc> lam, phir, kc;
+    std::vector<GemmDesc> lam, phir;
     for (int sidx = 0; sidx < ns; ++sidx) {
       const SubDev& S = pl.subs[sidx];
       if (S.n_a > 0) {
         d.push_back({S.Sc_off, S.n_a, S.n_a, S.n_a});
         if (S.n_c > 0) {
           lam.push_back({S.Sc_off, S.T_off, S.T_off, S.n_a, S.n_c, S.n_a, S.n_a, S.n_a, S.n_a});
-          phir.push_back({S.Z_off, S.T_off, S.KPhi_off, S.n_r, S.n_c, S.n_a, S.n_r, S.n_a, S.n_r});
+          phir.push_back({S.Z_off, S.T_off, S.Phi_off, S.n_r, S.n_c, S.n_a, S.n_r, S.n_a, S.n_r});
         }
       }
-      if (S.n_c > 0) kc.push_back({S.Phi_off, S.KPhi_off, S.Kc_off, S.n_c, S.n_c, S.n_loc, S.n_loc, S.n_loc, S.n_c});
     }
     pc->swSc = make_sweep_batch(m, d, s);
     pc->gLam = make_gemm_batch(m, lam, s);
     pc->gPhiR = make_gemm_batch(m, phir, s);
-    pc->gKc = make_gemm_batch(m, kc, s);
   }
   // colours
   for (auto& cs : pl.color_subs) {
@@ -348,7 +345,7 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
   }
   int maxlev = 1;
   for (int L = 0; L < nlev; ++L) maxlev = std::max(maxlev, pc->level_n[L]);
-  pc->fsw_stride = (int64_t)std::max(maxfn, 1) * 32 + 32 * 32;
+  pc->fsw_stride = 2 * ((int64_t)std::max(maxfn, 1) * 32 + 32 * 32);
   pc->fsw = m.alloc<double>(pc->fsw_stride * maxlev);
 }
 
@@ -362,6 +359,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   launch_fill_i32(pc->status, 1, 0, s);
   launch_alpha(P, pc->prob->c.n_ss, rho, pc->opt.weighting, pc->alpha, s);
   launch_delta(P, pc->alpha, pc->delta, s);
+  launch_coupling_coefs(P, g, rho, pc->cpl_coef, s);
   // local block-tridiagonal factors of K_II and K_rr
   if (sizeof(T) == 8) launch_fill_f64((double*)N.G, pl.pool_G, 0.0, s);
   else launch_fill_f32((float*)N.G, pl.pool_G, 0.0f, s);
@@ -397,13 +395,10 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   Kern<T>::lambda_rhs(P, N.Z, N.Tm, s);
   Kern<T>::gemm((GemmDesc*)pc->gLam.desc, pc->gLam.n, pc->gLam.maxm, pc->gLam.maxn, N.Sc, 0, N.Tm, 0, N.Lam,
                 (T)-1, (T)0, s);
-  Kern<T>::phi_r_init(P, N.Z, N.KPhi, s);
+  Kern<T>::phi_r_init(P, N.Z, N.Phi, s);
   Kern<T>::gemm((GemmDesc*)pc->gPhiR.desc, pc->gPhiR.n, pc->gPhiR.maxm, pc->gPhiR.maxn, N.Z, 0, N.Lam, 0,
-                N.KPhi, (T)-1, (T)1, s);
-  Kern<T>::phi_scatter(P, N.KPhi, N.Phi, s);
-  Kern<T>::local_apply_multi(P, g, rho, N.Phi, N.KPhi, s);
-  Kern<T>::gemm((GemmDesc*)pc->gKc.desc, pc->gKc.n, pc->gKc.maxm, pc->gKc.maxn, N.Phi, 1, N.KPhi, 0, N.Kc,
-                (T)1, (T)0, s);
+                N.Phi, (T)-1, (T)1, s);
+  Kern<T>::kc_identity(P, g, rho, N.Phi, N.Lam, N.Kc, s);
   Kern<T>::extract_gamma(P, N.Phi, N.Z, N.PhiG, N.XG, s);
   // coarse: assemble into the fronts and factor level by level (FP64)
   launch_fill_f64(pc->fpool, pl.front_pool, 0.0, s);
@@ -664,6 +659,13 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     P.front_idx = m.upload(pl.front_idx, s);
     P.front_pmap = m.upload(pl.front_pmap, s);
     P.sub_fmap = m.upload(pl.sub_fmap, s);
+    P.cpl_rank = m.upload(pl.cpl_rank, s);
+    P.cpl_sub = m.upload(pl.cpl_sub, s);
+    P.cpl_loc = m.upload(pl.cpl_loc, s);
+    P.cpl_dir = m.upload(pl.cpl_dir, s);
+    P.n_cpl = (int64_t)pl.cpl_sub.size();
+    pc->cpl_coef = m.alloc<double>(P.n_cpl * 9);
+    P.cpl_coef = pc->cpl_coef;
     std::vector<double> kh(p->khat, p->khat + 64);
     pc->khat = m.upload(kh, s);
     P.khat = pc->khat;

@@ -33,6 +33,9 @@ struct PlanDev {
   const FrontDev* fronts;
   const int32_t *front_idx, *front_pmap, *sub_fmap;
   const double* khat;  // 8x8 unit-coefficient element matrix (2D replicated over the z bit)
+  const int32_t *cpl_rank, *cpl_sub, *cpl_loc, *cpl_dir;
+  const double* cpl_coef;  // 9 coefficients per coupling row (filled at setup)
+  int64_t n_cpl;
   int n_sub;
   int64_t tot_I, tot_r, tot_g, tot_c, tot_a, n_gam, n_coarse;
   int max_block, max_na, max_nc, max_ng, max_nloc, max_nr, max_nI, max_zcols, max_plane;
@@ -48,6 +51,7 @@ void launch_q1_apply(const Geo& g, const double* khat, const double* rho, const 
 void launch_alpha(const PlanDev& P, int n_ss, const double* rho, int weighting, double* alpha,
                   hipStream_t s);
 void launch_delta(const PlanDev& P, const double* alpha, double* delta, hipStream_t s);
+void launch_coupling_coefs(const PlanDev& P, const Geo& g, const double* rho, double* coef, hipStream_t s);
 
 template <typename T>
 struct Kern {
@@ -68,10 +72,9 @@ struct Kern {
   static void sc_assemble(const PlanDev& P, const T* Z, T* Sc, hipStream_t s);
   static void lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s);
   static void phi_r_init(const PlanDev& P, const T* Z, T* PhiR, hipStream_t s);
-  static void phi_scatter(const PlanDev& P, const T* PhiR, T* Phi, hipStream_t s);
-  static void local_apply_multi(const PlanDev& P, const Geo& g, const double* rho, const T* Phi,
-                                T* KPhi, hipStream_t s);
-  static void extract_gamma(const PlanDev& P, const T* Phi, const T* Z, T* PhiG, T* XG,
+  static void kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PhiR,
+                          const T* Lam, T* Kc, hipStream_t s);
+  static void extract_gamma(const PlanDev& P, const T* PhiR, const T* Z, T* PhiG, T* XG,
                             hipStream_t s);
   static void kc_to_front(const PlanDev& P, const int32_t* subs_of_color, int ns, const T* Kc,
                           double* fpool, hipStream_t s);

@@ -229,6 +229,26 @@ __global__ void k_delta(PlanDev P, const double* __restrict__ alpha, double* __r
   delta[e] = num / den;
 }
 
+// Plane-coupling coefficients A[i, j] between a block's boundary plane node i
+// and its neighbours j in the adjacent block, from rho (one thread per row).
+__global__ void k_coupling_coefs(PlanDev P, Geo g, const double* __restrict__ rho, double* __restrict__ coef) {
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (row >= P.n_cpl) return;
+  const SubDev S = P.subs[P.cpl_sub[row]];
+  int c[3];
+  loc_coords(S, P.cpl_loc[row], c);
+  const int dir = P.cpl_dir[row];
+  for (int t = 0; t < 9; ++t) {
+    double v = 0.0;
+    if (P.cpl_rank[row * 9 + t] >= 0) {
+      int cn[3];
+      plane_nbr(S, g.dim, c, dir, t, cn);
+      v = kloc(S, g, rho, P.khat, c, cn);
+    }
+    coef[row * 9 + t] = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // local matrices: dense diagonal blocks of K_II / K_rr (entries within a block)
 
@@ -269,70 +289,68 @@ __global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rh
 // Stage 1 of the block Schur update S_k -= A_{k,k-1} G_{k-1} A_{k-1,k}:
 // W[l', j'] = sum_m Gs[l, m] A[m, j] over the last plane of block k-1 (l, m)
 // and the first plane of block k (j).  Gs is the swept block (= -G).
+// Stage 1 of the block Schur update S_k -= A_{k,k-1} G_{k-1} A_{k-1,k}:
+// W[l', j'] = sum_m Gs[l, m] A[m, j] over the last plane of block k-1 (l, m)
+// and the first plane of block k (j); Gs is the swept block (= -G).  One
+// thread per row l', columns j' strided over blockIdx.z.
 template <typename T>
-__global__ void k_schur_w(PlanDev P, Geo g, const double* __restrict__ rho, int setR, int k,
-                          const T* __restrict__ G, T* __restrict__ W, int64_t wstride) {
+__global__ void k_schur_w(PlanDev P, int setR, int k, const T* __restrict__ G, T* __restrict__ W,
+                          int64_t wstride) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int nb = setR ? S.nbR : S.nbI;
   if (k >= nb || k == 0) return;
   const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
   const BlockDev Bp = blk[k - 1], B = blk[k];
-  if (Bp.plane_hi != B.plane_lo) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= Bp.last_n * B.first_n) return;
-  const int lp = idx % Bp.last_n, jp = idx / Bp.last_n;
-  const int32_t* sl = set_loc_of(P, S, setR);
-  const int32_t* ls = loc_set_of(P, S, setR);
-  int cj[3];
-  loc_coords(S, sl[B.start + jp], cj);
-  const int lrow = Bp.size - Bp.last_n + lp;  // row inside block k-1
-  const T* Gp = G + Bp.G_off;
-  double acc = 0.0;
-  const int nt = g.dim == 3 ? 9 : 3;
-  for (int t = 0; t < nt; ++t) {
-    int cm[3];
-    if (!plane_nbr(S, g.dim, cj, -1, t, cm)) continue;
-    int m = ls[loc_index(S, cm)];
-    if (m < 0) continue;
-    double a = kloc(S, g, rho, P.khat, cm, cj);
-    acc += (double)Gp[lrow + (int64_t)Bp.size * (m - Bp.start)] * a;
+  if (B.cf_off < 0) return;
+  const int lp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lp >= Bp.last_n) return;
+  const T* Gr = G + Bp.G_off + (Bp.size - Bp.last_n + lp);
+  T* Wp = W + sub * wstride + lp;
+  for (int jp = blockIdx.z; jp < B.first_n; jp += gridDim.z) {
+    const int64_t row = B.cf_off + jp;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int m = P.cpl_rank[row * 9 + t];
+      if (m >= 0) acc += (double)Gr[(int64_t)Bp.size * (m - Bp.start)] * P.cpl_coef[row * 9 + t];
+    }
+    Wp[(int64_t)Bp.last_n * jp] = (T)acc;
   }
-  W[sub * wstride + lp + (int64_t)Bp.last_n * jp] = (T)acc;
 }
 
-// Stage 2: S_k[i', j'] += sum_l A[i, l] W[l', j'] (first-plane rows/columns).
+// Stage 2: S_k[i', j'] += sum_l A[i, l] W[l', j'] (first-plane rows/columns),
+// one thread per row i', columns j' strided over blockIdx.z.
 template <typename T>
-__global__ void k_schur_apply(PlanDev P, Geo g, const double* __restrict__ rho, int setR, int k,
-                              T* __restrict__ G, const T* __restrict__ W, int64_t wstride) {
+__global__ void k_schur_apply(PlanDev P, int setR, int k, T* __restrict__ G, const T* __restrict__ W,
+                              int64_t wstride) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int nb = setR ? S.nbR : S.nbI;
   if (k >= nb || k == 0) return;
   const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
   const BlockDev Bp = blk[k - 1], B = blk[k];
-  if (Bp.plane_hi != B.plane_lo) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= B.first_n * B.first_n) return;
-  const int ip = idx % B.first_n, jp = idx / B.first_n;
-  const int32_t* sl = set_loc_of(P, S, setR);
-  const int32_t* ls = loc_set_of(P, S, setR);
-  int ci[3];
-  loc_coords(S, sl[B.start + ip], ci);
-  double acc = 0.0;
-  const int nt = g.dim == 3 ? 9 : 3;
-  const T* Wp = W + sub * wstride;
-  for (int t = 0; t < nt; ++t) {
-    int cl[3];
-    if (!plane_nbr(S, g.dim, ci, -1, t, cl)) continue;
-    int l = ls[loc_index(S, cl)];
-    if (l < 0) continue;
-    double a = kloc(S, g, rho, P.khat, ci, cl);
-    int lp = l - (Bp.start + Bp.size - Bp.last_n);
-    acc += a * (double)Wp[lp + (int64_t)Bp.last_n * jp];
+  if (B.cf_off < 0) return;
+  const int ip = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ip >= B.first_n) return;
+  const int base = Bp.start + Bp.size - Bp.last_n;
+  const int64_t row = B.cf_off + ip;
+  double a[9];
+  int l[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int r = P.cpl_rank[row * 9 + t];
+    a[t] = r >= 0 ? P.cpl_coef[row * 9 + t] : 0.0;
+    l[t] = r >= 0 ? r - base : 0;
   }
-  T* Gk = G + B.G_off;
-  Gk[ip + (int64_t)B.size * jp] += (T)acc;
+  const T* Wp = W + sub * wstride;
+  T* Gk = G + B.G_off + ip;
+  for (int jp = blockIdx.z; jp < B.first_n; jp += gridDim.z) {
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc += a[t] * (double)Wp[l[t] + (int64_t)Bp.last_n * jp];
+    Gk[(int64_t)B.size * jp] += (T)acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -346,107 +364,201 @@ __global__ void k_schur_apply(PlanDev P, Geo g, const double* __restrict__ rho, 
 // and forms CD = M_{:,Q} D^{-1}; k_sweep_update applies the rank-NB update
 // to every entry outside the panel on MFMA.
 
+// Scratch per problem and panel parity: CD (n x NB, ld n) then Dinv (NB x NB).
+template <typename T>
+__device__ __forceinline__ T* sweep_slot(T* scratch, int64_t scr_stride, int prob, int j0) {
+  return scratch + prob * scr_stride + ((j0 / SWEEP_NB) & 1) * (scr_stride / 2);
+}
+
+// Sweeps the pivot block (jb <= 32) held in LDS by one wave, in registers:
+// lane l keeps column l%32, rows 16*(l/32) .. +15.  Each pivot step takes the
+// pivot row and column through cross-lane shuffles; no barriers.  Entries
+// beyond jb are padded with the identity.  On return D holds -D^{-1}.
+__device__ __forceinline__ bool wave_sweep32(double (*D)[SWEEP_NB + 1], int jb, int lane) {
+  const int j = lane & 31, h = lane >> 5;
+  double m[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int i = h * 16 + t;
+    m[t] = (i < jb && j < jb) ? D[i][j] : (i == j ? 1.0 : 0.0);
+  }
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < SWEEP_NB; ++q) {
+    const int qh = q >> 4, qt = q & 15;
+    const double rowq = __shfl(m[qt], j + 32 * qh, 64);  // D[q][j]
+    double dq = __shfl(m[qt], q + 32 * qh, 64);          // D[q][q]
+    if (!(dq > 0.0)) {
+      bad = true;
+      dq = 1.0;
+    }
+    const double inv = 1.0 / dq;
+    double colq[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) colq[t] = __shfl(m[t], q + 32 * h, 64);  // D[16h+t][q]
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int i = h * 16 + t;
+      double v;
+      if (i == q && j == q) v = -inv;
+      else if (i == q) v = rowq * inv;
+      else if (j == q) v = colq[t] * inv;
+      else v = m[t] - colq[t] * rowq * inv;
+      m[t] = v;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) D[h * 16 + t][j] = m[t];
+  return bad;
+}
+
+// One workgroup per (chunk of SWEEP_ROWS rows, matrix).  Only the lower
+// triangle is kept current during the sweep (the update is symmetric); a
+// final pass mirrors it.
+//  1. writes back the previous panel for its rows, into the lower triangle;
+//  2. loads the new pivot block and sweeps it in LDS (every workgroup of the
+//     matrix does this redundantly; it is NB x NB, one barrier per pivot);
+//  3. stages its rows of the column panel in LDS and forms CD = C D^{-1}.
+// Rows of the previous panel read their column-panel values from the
+// previous scratch slot, so no workgroup depends on another's writeback.
+constexpr int SWEEP_ROWS = 256;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_sweep_panel(const SweepDesc* __restrict__ desc, T* pool,
                                                      int j0, int prev_j0, T* scratch,
                                                      int64_t scr_stride, int* status,
                                                      int status_code) {
-  __shared__ double D[SWEEP_NB][SWEEP_NB + 1];
-  const SweepDesc d = desc[blockIdx.x];
+  __shared__ double D[1][SWEEP_NB][SWEEP_NB + 1];
+  extern __shared__ char smem_raw[];
+  T(*Cl)[SWEEP_NB + 1] = reinterpret_cast<T(*)[SWEEP_NB + 1]>(smem_raw);  // [chunk rows][NB+1]
+  const SweepDesc d = desc[blockIdx.y];
   const int n = d.n, p = d.p, ld = d.ld;
+  const int r0 = blockIdx.x * SWEEP_ROWS;
+  if (r0 >= n) return;
+  const int rows = min(SWEEP_ROWS, n - r0);
   T* A = pool + d.off;
-  T* CD = scratch + blockIdx.x * scr_stride;       // n x NB, ld n
-  T* Dinv = CD + (int64_t)n * SWEEP_NB;            // NB x NB
   const int tid = threadIdx.x;
-  if (prev_j0 >= 0 && prev_j0 < p) {
-    const int pb = min(SWEEP_NB, p - prev_j0);
-    for (int64_t idx = tid; idx < (int64_t)n * pb; idx += blockDim.x) {
-      int i = (int)(idx % n), q = (int)(idx / n);
-      int col = prev_j0 + q;
+  const bool have_prev = prev_j0 >= 0 && prev_j0 < p;
+  const T* CDp = have_prev ? sweep_slot(scratch, scr_stride, blockIdx.y, prev_j0) : nullptr;
+  const int pb = have_prev ? min(SWEEP_NB, p - prev_j0) : 0;
+  if (have_prev) {
+    const T* Dip = CDp + (int64_t)n * SWEEP_NB;
+    for (int idx = tid; idx < rows * pb; idx += blockDim.x) {
+      const int i = r0 + idx % rows, q = idx / rows;
+      const int col = prev_j0 + q;
       if (i >= prev_j0 && i < prev_j0 + pb) {
-        A[i + (int64_t)ld * col] = -Dinv[(i - prev_j0) + SWEEP_NB * q];
+        A[i + (int64_t)ld * col] = -Dip[(i - prev_j0) + SWEEP_NB * q];
       } else {
-        T v = CD[i + (int64_t)n * q];
-        A[i + (int64_t)ld * col] = v;
-        A[col + (int64_t)ld * i] = v;
+        const T v = CDp[i + (int64_t)n * q];
+        if (i > col) A[i + (int64_t)ld * col] = v;
+        else A[col + (int64_t)ld * i] = v;
       }
     }
-    __threadfence();
-    __syncthreads();
   }
   if (j0 < 0 || j0 >= p) return;
   const int jb = min(SWEEP_NB, p - j0);
   for (int idx = tid; idx < jb * jb; idx += blockDim.x) {
-    int i = idx % jb, j = idx / jb;
-    D[i][j] = (double)A[(j0 + i) + (int64_t)ld * (j0 + j)];
+    const int i = idx % jb, j = idx / jb;
+    const int gi = max(i, j), gj = min(i, j);
+    D[0][i][j] = (double)A[(j0 + gi) + (int64_t)ld * (j0 + gj)];
+  }
+  // stage this chunk's rows of the column panel (rows above the panel from
+  // the lower-triangle mirror, previous-panel rows from its scratch slot)
+  const bool above = r0 + rows <= j0;  // whole chunk above the panel: read the row panel along t
+  for (int idx = tid; idx < rows * jb; idx += blockDim.x) {
+    const int t = above ? idx % jb : idx / rows, r = above ? idx / jb : idx % rows;
+    const int i = r0 + r;
+    T v = 0;
+    if (have_prev && i >= prev_j0 && i < prev_j0 + pb) v = CDp[(j0 + t) + (int64_t)n * (i - prev_j0)];
+    else if (i < j0) v = A[(j0 + t) + (int64_t)ld * i];
+    else if (i >= j0 + jb) v = A[i + (int64_t)ld * (j0 + t)];
+    Cl[r][t] = v;
   }
   __syncthreads();
-  // sweep the pivot block in LDS (FP64 for the small block in both precisions)
-  for (int q = 0; q < jb; ++q) {
-    double dq = D[q][q];
-    if (!(dq > 0.0)) {
-      if (tid == 0) atomicMax(status, status_code);
-      dq = 1.0;
-    }
-    __syncthreads();
+  const int cur = 0;
+  if (tid < 64) {
+    const bool bad = wave_sweep32(D[0], jb, tid);
+    if (bad && tid == 0) atomicMax(status, status_code);
+  }
+  __syncthreads();
+  // D[cur] holds -D^{-1}
+  T* CD = sweep_slot(scratch, scr_stride, blockIdx.y, j0);
+  T* Dinv = CD + (int64_t)n * SWEEP_NB;
+  if (blockIdx.x == 0)
     for (int idx = tid; idx < jb * jb; idx += blockDim.x) {
-      int i = idx % jb, j = idx / jb;
-      if (i != q && j != q) D[i][j] -= D[i][q] * D[q][j] / dq;
+      const int i = idx % jb, j = idx / jb;
+      Dinv[i + SWEEP_NB * j] = (T)(-D[cur][i][j]);
     }
-    __syncthreads();
-    if (tid < jb && tid != q) {
-      D[tid][q] /= dq;
-      D[q][tid] /= dq;
-    }
-    if (tid == 0) D[q][q] = -1.0 / dq;
-    __syncthreads();
-  }
-  // D holds -D^{-1}
-  for (int idx = tid; idx < jb * jb; idx += blockDim.x) {
-    int i = idx % jb, j = idx / jb;
-    Dinv[i + SWEEP_NB * j] = (T)(-D[i][j]);
-  }
-  // CD = C D^{-1} for the rows outside the panel
-  for (int64_t idx = tid; idx < (int64_t)n * jb; idx += blockDim.x) {
-    int i = (int)(idx % n), q = (int)(idx / n);
+  // CD row by row: the row's 32 panel values in registers, D read as broadcasts
+  for (int r = tid; r < rows; r += blockDim.x) {
+    const int i = r0 + r;
     if (i >= j0 && i < j0 + jb) continue;
-    double acc = 0.0;
-    for (int t = 0; t < jb; ++t) acc -= (double)A[i + (int64_t)ld * (j0 + t)] * D[t][q];
-    CD[i + (int64_t)n * q] = (T)acc;
+    double c[SWEEP_NB];
+#pragma unroll
+    for (int t = 0; t < SWEEP_NB; ++t) c[t] = t < jb ? (double)Cl[r][t] : 0.0;
+    for (int q = 0; q < jb; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < SWEEP_NB; ++t) acc -= c[t] * D[cur][t][q];
+      CD[i + (int64_t)n * q] = (T)acc;
+    }
   }
 }
 
+// Rank-NB update of the lower triangle outside the panel:
+// A_ij -= CD_i . C_j for i >= j (tiles on or below the diagonal).  C_j comes
+// from the lower triangle: the column panel below it, its mirror (the row
+// panel) above it.  The MFMA takes C as its A operand and CD as its B
+// operand, so each lane's output runs along i and the stores are coalesced.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sweep_update(const SweepDesc* __restrict__ desc, T* pool,
                                                       int j0, const T* __restrict__ scratch,
-                                                      int64_t scr_stride, int tiles_n) {
+                                                      int64_t scr_stride) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[SWEEP_NB][TILE + PAD];
-  __shared__ T Bs[SWEEP_NB][TILE + PAD];
+  __shared__ T As[SWEEP_NB][TILE + PAD];  // CD rows i
+  __shared__ T Bs[SWEEP_NB][TILE + PAD];  // C rows j
   const SweepDesc d = desc[blockIdx.y];
   const int n = d.n, p = d.p, ld = d.ld;
   if (j0 >= p) return;
   const int jb = min(SWEEP_NB, p - j0);
-  const int ti = blockIdx.x % tiles_n, tj = blockIdx.x / tiles_n;
+  // linear index -> lower-triangular tile (ti >= tj)
+  const int lin = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= lin) ++ti;
+  while (ti * (ti + 1) / 2 > lin) --ti;
+  const int tj = lin - ti * (ti + 1) / 2;
   const int i0 = ti * TILE, c0 = tj * TILE;
   if (i0 >= n || c0 >= n) return;
   T* A = pool + d.off;
-  const T* CD = scratch + blockIdx.y * scr_stride;
+  const T* CD = sweep_slot(const_cast<T*>(scratch), scr_stride, blockIdx.y, j0);
   const int tid = threadIdx.x;
   for (int idx = tid; idx < TILE * SWEEP_NB; idx += 256) {
-    int r = idx % TILE, q = idx / TILE;
-    int i = i0 + r, j = c0 + r;
-    T a = 0, b = 0;
-    if (q < jb) {
-      if (i < n && !(i >= j0 && i < j0 + jb)) a = CD[i + (int64_t)n * q];
-      if (j < n) b = A[j + (int64_t)ld * (j0 + q)];
-    }
+    const int r = idx % TILE, q = idx / TILE;
+    const int i = i0 + r;
+    T a = 0;
+    if (q < jb && i < n && !(i >= j0 && i < j0 + jb)) a = CD[i + (int64_t)n * q];
     As[q][r] = a;
+  }
+  for (int idx = tid; idx < TILE * SWEEP_NB; idx += 256) {
+    int r, q;
+    if (c0 + TILE <= j0) {  // whole tile above the panel: read the row panel, coalesced along q
+      q = idx % SWEEP_NB;
+      r = idx / SWEEP_NB;
+    } else {
+      r = idx % TILE;
+      q = idx / TILE;
+    }
+    const int j = c0 + r;
+    T b = 0;
+    if (q < jb && j < n) {
+      if (j < j0) b = A[(j0 + q) + (int64_t)ld * j];
+      else if (j >= j0 + jb) b = A[j + (int64_t)ld * (j0 + q)];
+    }
     Bs[q][r] = b;
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
-  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
   acc_t acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -455,16 +567,16 @@ __global__ __launch_bounds__(256) void k_sweep_update(const SweepDesc* __restric
   const int kq = lane >> 4, rr = lane & 15;
   const int ksteps = (jb + 3) / 4;
   for (int ks = 0; ks < ksteps; ++ks) {
-    int kk = ks * 4 + kq;
+    const int kk = ks * 4 + kq;
     T av[2], bv[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) av[a] = As[kk][wr + a * 16 + rr];
+    for (int a = 0; a < 2; ++a) av[a] = As[kk][wi + a * 16 + rr];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wc + b * 16 + rr];
+    for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wj + b * 16 + rr];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(av[a], bv[b], acc[a][b]);
+      for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(bv[b], av[a], acc[a][b]);
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -472,25 +584,42 @@ __global__ __launch_bounds__(256) void k_sweep_update(const SweepDesc* __restric
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int i = i0 + wr + a * 16 + Mfma<T>::row(kq, r);
-        int j = c0 + wc + b * 16 + rr;
-        if (i < n && j < n && !(i >= j0 && i < j0 + jb) && !(j >= j0 && j < j0 + jb))
+        const int j = c0 + wj + b * 16 + Mfma<T>::row(kq, r);
+        const int i = i0 + wi + a * 16 + rr;
+        if (i < n && j <= i && !(i >= j0 && i < j0 + jb) && !(j >= j0 && j < j0 + jb))
           A[i + (int64_t)ld * j] -= acc[a][b][r];
       }
+}
+
+// Mirrors the lower triangle into the upper one after a sweep.
+template <typename T>
+__global__ void k_symmetrize(const SweepDesc* __restrict__ desc, T* pool) {
+  const SweepDesc d = desc[blockIdx.y];
+  T* A = pool + d.off;
+  const int64_t tot = (int64_t)d.n * d.n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % d.n), j = (int)(idx / d.n);
+    if (i < j) A[i + (int64_t)d.ld * j] = A[j + (int64_t)d.ld * i];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Batched GEMM on MFMA: C = beta C + alpha op(A) op(B), column-major, with one
 // descriptor per problem (uneven sizes).  grid = (tiles of the largest
-// problem, problems); out-of-range tiles exit at once.
+// problem, problems); out-of-range tiles exit at once.  The MFMA computes the
+// transposed tile (op(B) as its A operand) so each lane's outputs run down a
+// column of C and the stores are coalesced.
+
+constexpr int GBK = 32;  // K chunk of the batched GEMM
 
 template <typename T, int TA, int TB>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
                                               const T* __restrict__ Ap, const T* __restrict__ Bp,
                                               T* __restrict__ Cp, T alpha, T beta, int tiles_m) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[BK][TILE + PAD];
-  __shared__ T Bs[BK][TILE + PAD];
+  __shared__ T As[2][GBK][TILE + PAD];
+  __shared__ T Bs[2][GBK][TILE + PAD];
   const GemmDesc d = desc[blockIdx.y];
   const int ti = blockIdx.x % tiles_m, tj = blockIdx.x / tiles_m;
   const int m0 = ti * TILE, n0 = tj * TILE;
@@ -502,55 +631,94 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
   const int kq = lane >> 4, rr = lane & 15;
+  constexpr int PER = TILE * GBK / 256;  // elements per thread per operand
+  T ra[PER], rb[PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + 256 * u;
+      int r, q;
+      if (TA) {
+        q = idx % GBK;
+        r = idx / GBK;
+      } else {
+        r = idx % TILE;
+        q = idx / TILE;
+      }
+      const int i = m0 + r, kk = k0 + q;
+      ra[u] = (i < d.m && kk < d.k) ? (TA ? A[kk + (int64_t)d.lda * i] : A[i + (int64_t)d.lda * kk]) : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + 256 * u;
+      int r, q;
+      if (TB) {
+        r = idx % TILE;
+        q = idx / TILE;
+      } else {
+        q = idx % GBK;
+        r = idx / GBK;
+      }
+      const int j = n0 + r, kk = k0 + q;
+      rb[u] = (j < d.n && kk < d.k) ? (TB ? B[j + (int64_t)d.ldb * kk] : B[kk + (int64_t)d.ldb * j]) : (T)0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + 256 * u;
+      int r, q;
+      if (TA) {
+        q = idx % GBK;
+        r = idx / GBK;
+      } else {
+        r = idx % TILE;
+        q = idx / TILE;
+      }
+      As[buf][q][r] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + 256 * u;
+      int r, q;
+      if (TB) {
+        r = idx % TILE;
+        q = idx / TILE;
+      } else {
+        q = idx % GBK;
+        r = idx / GBK;
+      }
+      Bs[buf][q][r] = rb[u];
+    }
+  };
   acc_t acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-  for (int k0 = 0; k0 < d.k; k0 += BK) {
-    for (int idx = tid; idx < TILE * BK; idx += 256) {
-      int r, q;
-      if (TA) {  // op(A)[i, k] = A[k, i]: coalesce along k
-        q = idx % BK;
-        r = idx / BK;
-      } else {
-        r = idx % TILE;
-        q = idx / TILE;
-      }
-      int i = m0 + r, kk = k0 + q;
-      T v = 0;
-      if (i < d.m && kk < d.k) v = TA ? A[kk + (int64_t)d.lda * i] : A[i + (int64_t)d.lda * kk];
-      As[q][r] = v;
-    }
-    for (int idx = tid; idx < TILE * BK; idx += 256) {
-      int r, q;
-      if (TB) {  // op(B)[k, j] = B[j, k]: coalesce along j
-        r = idx % TILE;
-        q = idx / TILE;
-      } else {
-        q = idx % BK;
-        r = idx / BK;
-      }
-      int j = n0 + r, kk = k0 + q;
-      T v = 0;
-      if (j < d.n && kk < d.k) v = TB ? B[j + (int64_t)d.ldb * kk] : B[kk + (int64_t)d.ldb * j];
-      Bs[q][r] = v;
-    }
-    __syncthreads();
+  load(0);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = 0; k0 < d.k; k0 += GBK) {
+    const bool more = k0 + GBK < d.k;
+    if (more) load(k0 + GBK);
 #pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      int kk = ks * 4 + kq;
+    for (int ks = 0; ks < GBK / 4; ++ks) {
+      const int kk = ks * 4 + kq;
       T av[2], bv[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[kk][wr + a * 16 + rr];
+      for (int a = 0; a < 2; ++a) av[a] = As[cur][kk][wr + a * 16 + rr];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wc + b * 16 + rr];
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[cur][kk][wc + b * 16 + rr];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(bv[b], av[a], acc[a][b]);
     }
+    if (more) store(cur ^ 1);
     __syncthreads();
+    cur ^= 1;
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -558,8 +726,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int i = m0 + wr + a * 16 + Mfma<T>::row(kq, r);
-        int j = n0 + wc + b * 16 + rr;
+        int i = m0 + wr + a * 16 + rr;
+        int j = n0 + wc + b * 16 + Mfma<T>::row(kq, r);
         if (i < d.m && j < d.n) {
           T* c = C + i + (int64_t)d.ldc * j;
           T v = alpha * acc[a][b][r];
@@ -605,45 +773,36 @@ __global__ void k_rhs_fill(PlanDev P, Geo g, const double* __restrict__ rho, T* 
 // fwd (fwd = 1): Z[first plane of block k, :] -= A_{k,k-1} Z[last plane of k-1, :]
 // bwd (fwd = 0): tmp[0:last_n, :] = A_{k,k+1} Z[first plane of k+1, :]
 template <typename T>
-__global__ void k_couple_multi(PlanDev P, Geo g, const double* __restrict__ rho, int k, int fwd,
-                               T* __restrict__ Z, T* __restrict__ tmp, int64_t tmp_stride) {
+__global__ void k_couple_multi(PlanDev P, int k, int fwd, T* __restrict__ Z, T* __restrict__ tmp,
+                               int64_t tmp_stride) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int nb = S.nbR;
-  const BlockDev* blk = P.blocks + S.bR_off;
   const int ncols = S.n_a + S.n_v;
   if (fwd ? (k >= nb || k == 0) : (k + 1 >= nb)) return;
-  const BlockDev B = blk[k];
-  const BlockDev O = fwd ? blk[k - 1] : blk[k + 1];
+  const BlockDev B = P.blocks[S.bR_off + k];
+  const int64_t roff = fwd ? B.cf_off : B.cb_off;
+  if (roff < 0) return;
   const int rows = fwd ? B.first_n : B.last_n;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rows) return;
-  const int row = fwd ? B.start + i : B.start + B.size - B.last_n + i;
-  const int32_t* sl = P.r_loc + S.r_off;
-  const int32_t* ls = P.loc_r + S.loc_off;
-  int ci[3];
-  loc_coords(S, sl[row], ci);
-  const bool adj = fwd ? (O.plane_hi == B.plane_lo) : (B.plane_hi == O.plane_lo);
+  const int rowrank = fwd ? B.start + i : B.start + B.size - B.last_n + i;
+  const int64_t row = roff + i;
   double a[9];
   int nbr[9];
-  int cnt = 0;
-  const int nt = g.dim == 3 ? 9 : 3;
-  if (adj)
-    for (int t = 0; t < nt; ++t) {
-      int cl[3];
-      if (!plane_nbr(S, g.dim, ci, fwd ? -1 : 1, t, cl)) continue;
-      int l = ls[loc_index(S, cl)];
-      if (l < 0) continue;
-      a[cnt] = kloc(S, g, rho, P.khat, ci, cl);
-      nbr[cnt++] = l;
-    }
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    nbr[t] = P.cpl_rank[row * 9 + t];
+    a[t] = nbr[t] >= 0 ? P.cpl_coef[row * 9 + t] : 0.0;
+    if (nbr[t] < 0) nbr[t] = 0;
+  }
   T* z = Z + S.Z_off;
   T* tp = tmp + sub * tmp_stride;
-  const int c0 = blockIdx.z;
-  for (int c = c0; c < ncols; c += gridDim.z) {
+  for (int c = blockIdx.z; c < ncols; c += gridDim.z) {
     double acc = 0.0;
-    for (int t = 0; t < cnt; ++t) acc += a[t] * (double)z[nbr[t] + (int64_t)S.n_r * c];
-    if (fwd) z[row + (int64_t)S.n_r * c] -= (T)acc;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc += a[t] * (double)z[nbr[t] + (int64_t)S.n_r * c];
+    if (fwd) z[rowrank + (int64_t)S.n_r * c] -= (T)acc;
     else tp[i + (int64_t)B.last_n * c] = (T)acc;
   }
 }
@@ -709,68 +868,59 @@ __global__ void k_phi_r_init(PlanDev P, const T* __restrict__ Z, T* __restrict__
        idx += (int64_t)gridDim.x * blockDim.x) {
     int i = (int)(idx % S.n_r), c = (int)(idx / S.n_r);
     int kind = P.c_kind[S.c_off + c];
-    PhiR[S.KPhi_off + idx] = kind >= 0 ? Z[S.Z_off + i + (int64_t)S.n_r * (S.n_a + kind)] : (T)0;
+    PhiR[S.Phi_off + idx] = kind >= 0 ? Z[S.Z_off + i + (int64_t)S.n_r * (S.n_a + kind)] : (T)0;
   }
 }
 
+// Local coarse matrix from the equations that define Phi.  With the
+// saddle-point system K_rr Phi_r + K_rv Phi_v + C_r^T Lambda = 0 and
+// C_r Phi_r = [0 I], (K Phi)_r = -C_r^T Lambda, so Phi^T K Phi has the rows
+// (K Phi)_v at vertex dofs and -Lambda at average dofs.  The two triangles
+// are averaged so the result is symmetric to the last bit.
 template <typename T>
-__global__ void k_phi_scatter(PlanDev P, const T* __restrict__ PhiR, T* __restrict__ Phi) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  const int64_t tot = (int64_t)S.n_loc * S.n_c;
+__device__ __forceinline__ double kc_entry(const PlanDev& P, const SubDev& S, const Geo& g,
+                                           const double* __restrict__ rho, const T* __restrict__ PhiR,
+                                           const T* __restrict__ Lam, int c, int c2) {
+  const int kind = P.c_kind[S.c_off + c];
+  if (kind < 0) return -(double)Lam[S.T_off + (-kind - 1) + (int64_t)S.n_a * c2];
+  const int lv = P.v_loc[S.v_off + kind];
+  int cv[3];
+  loc_coords(S, lv, cv);
   const int32_t* lr = P.loc_r + S.loc_off;
   const int32_t* lg = P.loc_g + S.loc_off;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    int l = (int)(idx % S.n_loc), c = (int)(idx / S.n_loc);
-    int r = lr[l];
-    T v;
-    if (r >= 0) {
-      v = PhiR[S.KPhi_off + r + (int64_t)S.n_r * c];
-    } else {
-      int vi = P.g_v[S.g_off + lg[l]];
-      v = P.v_c[S.v_off + vi] == c ? (T)1 : (T)0;
-    }
-    Phi[S.Phi_off + idx] = v;
-  }
-}
-
-// KPhi = K_i Phi, matrix-free on the local grid, all columns.
-template <typename T>
-__global__ void k_local_apply_multi(PlanDev P, Geo g, const double* __restrict__ rho,
-                                    const T* __restrict__ Phi, T* __restrict__ KPhi) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= S.n_loc) return;
-  int c[3];
-  loc_coords(S, l, c);
-  double a[27];
-  int nbr[27];
-  int cnt = 0;
   const int zr = g.dim == 3 ? 1 : 0;
+  double acc = 0.0;
   for (int dz = -zr; dz <= zr; ++dz)
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
-        int cn[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+        int cn[3] = {cv[0] + dx, cv[1] + dy, cv[2] + dz};
         int ln = loc_index(S, cn);
         if (ln < 0) continue;
-        double v = kloc(S, g, rho, P.khat, c, cn);
-        if (v == 0.0) continue;
-        a[cnt] = v;
-        nbr[cnt++] = ln;
+        double phi;
+        const int r = lr[ln];
+        if (r >= 0) phi = (double)PhiR[S.Phi_off + r + (int64_t)S.n_r * c2];
+        else phi = P.v_c[S.v_off + P.g_v[S.g_off + lg[ln]]] == c2 ? 1.0 : 0.0;
+        if (phi != 0.0) acc += kloc(S, g, rho, P.khat, cv, cn) * phi;
       }
-  const T* ph = Phi + S.Phi_off;
-  T* kp = KPhi + S.KPhi_off;
-  for (int col = blockIdx.z; col < S.n_c; col += gridDim.z) {
-    double acc = 0.0;
-    for (int t = 0; t < cnt; ++t) acc += a[t] * (double)ph[nbr[t] + (int64_t)S.n_loc * col];
-    kp[l + (int64_t)S.n_loc * col] = (T)acc;
-  }
+  return acc;
 }
 
 template <typename T>
-__global__ void k_extract_gamma(PlanDev P, const T* __restrict__ Phi, const T* __restrict__ Z,
+__global__ void k_kc_identity(PlanDev P, Geo g, const double* __restrict__ rho, const T* __restrict__ PhiR,
+                              const T* __restrict__ Lam, T* __restrict__ Kc) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= S.n_c * S.n_c) return;
+  const int c = idx % S.n_c, c2 = idx / S.n_c;
+  if (c2 < c) return;
+  const double v = 0.5 * (kc_entry(P, S, g, rho, PhiR, Lam, c, c2) + kc_entry(P, S, g, rho, PhiR, Lam, c2, c));
+  Kc[S.Kc_off + c + (int64_t)S.n_c * c2] = (T)v;
+  Kc[S.Kc_off + c2 + (int64_t)S.n_c * c] = (T)v;
+}
+
+template <typename T>
+__global__ void k_extract_gamma(PlanDev P, const T* __restrict__ PhiR, const T* __restrict__ Z,
                                 T* __restrict__ PhiG, T* __restrict__ XG) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
@@ -778,12 +928,16 @@ __global__ void k_extract_gamma(PlanDev P, const T* __restrict__ Phi, const T* _
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < totp + totx;
        idx += (int64_t)gridDim.x * blockDim.x) {
     if (idx < totp) {
-      int e = (int)(idx % S.n_g), c = (int)(idx / S.n_g);
-      PhiG[S.PhiG_off + idx] = Phi[S.Phi_off + P.g_loc[S.g_off + e] + (int64_t)S.n_loc * c];
+      const int e = (int)(idx % S.n_g), c = (int)(idx / S.n_g);
+      const int r = P.g_r[S.g_off + e];
+      T v;
+      if (r >= 0) v = PhiR[S.Phi_off + r + (int64_t)S.n_r * c];
+      else v = P.v_c[S.v_off + P.g_v[S.g_off + e]] == c ? (T)1 : (T)0;
+      PhiG[S.PhiG_off + idx] = v;
     } else {
-      int64_t j = idx - totp;
-      int e = (int)(j % S.n_g), a = (int)(j / S.n_g);
-      int r = P.g_r[S.g_off + e];
+      const int64_t j = idx - totp;
+      const int e = (int)(j % S.n_g), a = (int)(j / S.n_g);
+      const int r = P.g_r[S.g_off + e];
       XG[S.XG_off + j] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * a] : (T)0;
     }
   }
@@ -831,77 +985,91 @@ __global__ void k_gather_I(PlanDev P, Geo g, const double* __restrict__ r, T* __
 // workgroup per (subdomain, right-hand side):
 //   forward  c_k = b_k - A_{k,k-1} xh_{k-1},  xh_k = G_k c_k
 //   backward x_k = xh_k - G_k A_{k,k+1} x_{k+1}
-// (G_k = -Gs_k, the swept block).  The couplings A_{k,k+-1} are applied
-// matrix-free from rho; each G_k is streamed once forward, and its last-plane
-// columns once backward.
+// (G_k = -Gs_k, the swept block).  The couplings A_{k,k+-1} come from the
+// coupling table.  Each G_k is streamed once forward and its last-plane
+// columns once backward; a GEMV splits the columns over thread groups so all
+// 1024 threads keep loads in flight, then reduces the groups in fixed order.
+constexpr int BS_THREADS = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_block_solve(PlanDev P, Geo g, const double* __restrict__ rho,
-                                                     int setR, const T* __restrict__ G,
-                                                     T* __restrict__ vec) {
+__device__ __forceinline__ void block_gemv(const T* __restrict__ M, int s, int ncols, const T* __restrict__ x,
+                                           T* __restrict__ part, int tid, T* __restrict__ out, bool accumulate,
+                                           T sign) {
+  // out[i] (+)= sign * sum_{j < ncols} M[i + s j] x[j], i < s
+  const int groups = s >= BS_THREADS ? 1 : min(BS_THREADS / s, max(ncols, 1));
+  const int chunk = (ncols + groups - 1) / groups;
+  if (groups == 1) {
+    for (int i = tid; i < s; i += BS_THREADS) {
+      T acc = 0;
+      for (int j = 0; j < ncols; ++j) acc += M[i + (int64_t)s * j] * x[j];
+      out[i] = accumulate ? out[i] + sign * acc : sign * acc;
+    }
+    return;
+  }
+  const int i = tid % s, g = tid / s;
+  if (g < groups) {
+    const int jlo = g * chunk, jhi = min(ncols, jlo + chunk);
+    T acc = 0;
+    for (int j = jlo; j < jhi; ++j) acc += M[i + (int64_t)s * j] * x[j];
+    part[g * s + i] = acc;
+  }
+  __syncthreads();
+  for (int r = tid; r < s; r += BS_THREADS) {
+    T acc = 0;
+    for (int q = 0; q < groups; ++q) acc += part[q * s + r];
+    out[r] = accumulate ? out[r] + sign * acc : sign * acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, Geo g, const double* __restrict__ rho,
+                                                            int setR, const T* __restrict__ G,
+                                                            T* __restrict__ vec) {
   extern __shared__ char smem_raw[];
-  T* cl = reinterpret_cast<T*>(smem_raw);
+  T* cl = reinterpret_cast<T*>(smem_raw);          // max_block
+  T* part = cl + P.max_block;                      // max(BS_THREADS, max_block)
   const int sub = blockIdx.x, rhs = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int nb = setR ? S.nbR : S.nbI;
   const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
-  const int32_t* sl = set_loc_of(P, S, setR);
-  const int32_t* ls = loc_set_of(P, S, setR);
   T* v = vec + rhs * (setR ? P.tot_r : P.tot_I) + (setR ? S.r_off : S.I_off);
   const int tid = threadIdx.x;
-  const int nt = g.dim == 3 ? 9 : 3;
   for (int k = 0; k < nb; ++k) {
     const BlockDev B = blk[k];
-    for (int i = tid; i < B.size; i += blockDim.x) cl[i] = v[B.start + i];
-    __syncthreads();
-    if (k > 0 && blk[k - 1].plane_hi == B.plane_lo) {
-      for (int i = tid; i < B.first_n; i += blockDim.x) {
-        int ci[3];
-        loc_coords(S, sl[B.start + i], ci);
+    for (int i = tid; i < B.size; i += BS_THREADS) {
+      T c = v[B.start + i];
+      if (B.cf_off >= 0 && i < B.first_n) {
+        const int64_t row = B.cf_off + i;
         double acc = 0.0;
-        for (int t = 0; t < nt; ++t) {
-          int cn[3];
-          if (!plane_nbr(S, g.dim, ci, -1, t, cn)) continue;
-          int j = ls[loc_index(S, cn)];
-          if (j < 0) continue;
-          acc += kloc(S, g, rho, P.khat, ci, cn) * (double)v[j];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int j = P.cpl_rank[row * 9 + t];
+          if (j >= 0) acc += P.cpl_coef[row * 9 + t] * (double)v[j];
         }
-        cl[i] -= (T)acc;
+        c -= (T)acc;
       }
+      cl[i] = c;
     }
     __syncthreads();
-    const T* Gk = G + B.G_off;
-    for (int i = tid; i < B.size; i += blockDim.x) {
-      T acc = 0;
-      for (int j = 0; j < B.size; ++j) acc += Gk[i + (int64_t)B.size * j] * cl[j];
-      v[B.start + i] = -acc;
-    }
+    block_gemv(G + B.G_off, B.size, B.size, cl, part, tid, v + B.start, false, (T)-1);
     __syncthreads();
   }
   for (int k = nb - 2; k >= 0; --k) {
     const BlockDev B = blk[k];
-    const BlockDev N = blk[k + 1];
-    if (B.plane_hi != N.plane_lo) continue;
+    if (B.cb_off < 0) continue;
     const int base = B.size - B.last_n;
-    for (int i = tid; i < B.last_n; i += blockDim.x) {
-      int ci[3];
-      loc_coords(S, sl[B.start + base + i], ci);
+    for (int i = tid; i < B.last_n; i += BS_THREADS) {
+      const int64_t row = B.cb_off + i;
       double acc = 0.0;
-      for (int t = 0; t < nt; ++t) {
-        int cn[3];
-        if (!plane_nbr(S, g.dim, ci, 1, t, cn)) continue;
-        int j = ls[loc_index(S, cn)];
-        if (j < 0) continue;
-        acc += kloc(S, g, rho, P.khat, ci, cn) * (double)v[j];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int j = P.cpl_rank[row * 9 + t];
+        if (j >= 0) acc += P.cpl_coef[row * 9 + t] * (double)v[j];
       }
       cl[i] = (T)acc;
     }
     __syncthreads();
-    const T* Gk = G + B.G_off + (int64_t)B.size * base;
-    for (int i = tid; i < B.size; i += blockDim.x) {
-      T acc = 0;
-      for (int q = 0; q < B.last_n; ++q) acc += Gk[i + (int64_t)B.size * q] * cl[q];
-      v[B.start + i] += acc;
-    }
+    block_gemv(G + B.G_off + (int64_t)B.size * base, B.size, B.last_n, cl, part, tid, v + B.start, true, (T)1);
     __syncthreads();
   }
 }
@@ -1330,6 +1498,10 @@ void launch_delta(const PlanDev& P, const double* alpha, double* delta, hipStrea
   if (P.tot_g == 0) return;
   k_delta<<<cdiv(P.tot_g, 256), 256, 0, s>>>(P, alpha, delta);
 }
+void launch_coupling_coefs(const PlanDev& P, const Geo& g, const double* rho, double* coef, hipStream_t s) {
+  if (P.n_cpl == 0) return;
+  k_coupling_coefs<<<cdiv(P.n_cpl, 256), 256, 0, s>>>(P, g, rho, coef);
+}
 
 template <typename T>
 void Kern<T>::block_assemble(const PlanDev& P, const Geo& g, const double* rho, int setR, T* G,
@@ -1342,23 +1514,30 @@ void Kern<T>::block_assemble(const PlanDev& P, const Geo& g, const double* rho, 
 template <typename T>
 void Kern<T>::schur_couple(const PlanDev& P, const Geo& g, const double* rho, int setR, int k, T* G,
                            T* W, int64_t wstride, hipStream_t s) {
-  int mp = P.max_plane;
-  k_schur_w<T><<<dim3(cdiv((int64_t)mp * mp, 256), P.n_sub), 256, 0, s>>>(P, g, rho, setR, k, G, W, wstride);
-  k_schur_apply<T><<<dim3(cdiv((int64_t)mp * mp, 256), P.n_sub), 256, 0, s>>>(P, g, rho, setR, k, G, W, wstride);
+  (void)g;
+  (void)rho;
+  const int mp = P.max_plane;
+  const dim3 grid(cdiv(mp, 64), P.n_sub, 16);
+  k_schur_w<T><<<grid, 64, 0, s>>>(P, setR, k, G, W, wstride);
+  k_schur_apply<T><<<grid, 64, 0, s>>>(P, setR, k, G, W, wstride);
 }
 
 template <typename T>
 void Kern<T>::sweep(SweepDesc* d_desc, int nprob, int maxn, int maxp, T* pool, T* scratch,
                     int64_t scr_stride, int* status, int status_code, hipStream_t s) {
   if (nprob == 0 || maxp == 0) return;
-  int tiles = (int)cdiv(maxn, TILE);
+  const int64_t tiles = cdiv(maxn, TILE);
+  const dim3 pgrid(cdiv(maxn, SWEEP_ROWS), nprob);
+  const size_t psm = (size_t)hmin(maxn, SWEEP_ROWS) * (SWEEP_NB + 1) * sizeof(T);
   int prev = -1;
   for (int j0 = 0; j0 < maxp; j0 += SWEEP_NB) {
-    k_sweep_panel<T><<<nprob, 256, 0, s>>>(d_desc, pool, j0, prev, scratch, scr_stride, status, status_code);
-    k_sweep_update<T><<<dim3(tiles * tiles, nprob), 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, tiles);
+    k_sweep_panel<T><<<pgrid, 256, psm, s>>>(d_desc, pool, j0, prev, scratch, scr_stride, status, status_code);
+    k_sweep_update<T><<<dim3((unsigned)(tiles * (tiles + 1) / 2), nprob), 256, 0, s>>>(d_desc, pool, j0, scratch,
+                                                                                      scr_stride);
     prev = j0;
   }
-  k_sweep_panel<T><<<nprob, 256, 0, s>>>(d_desc, pool, -1, prev, scratch, scr_stride, status, status_code);
+  k_sweep_panel<T><<<pgrid, 256, psm, s>>>(d_desc, pool, -1, prev, scratch, scr_stride, status, status_code);
+  k_symmetrize<T><<<dim3((unsigned)hmin(cdiv((int64_t)maxn * maxn, 256), 4096), nprob), 256, 0, s>>>(d_desc, pool);
 }
 
 template <typename T>
@@ -1384,7 +1563,9 @@ void Kern<T>::couple_multi(const PlanDev& P, const Geo& g, const double* rho, in
                            int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s) {
   if (ncols_max == 0) return;
   int zc = hmin(ncols_max, 16);
-  k_couple_multi<T><<<dim3(cdiv(P.max_plane, 64), P.n_sub, zc), 64, 0, s>>>(P, g, rho, k, fwd, Z, tmp, tmp_stride);
+  (void)g;
+  (void)rho;
+  k_couple_multi<T><<<dim3(cdiv(P.max_plane, 64), P.n_sub, zc), 64, 0, s>>>(P, k, fwd, Z, tmp, tmp_stride);
 }
 
 template <typename T>
@@ -1415,25 +1596,17 @@ void Kern<T>::phi_r_init(const PlanDev& P, const T* Z, T* PhiR, hipStream_t s) {
 }
 
 template <typename T>
-void Kern<T>::phi_scatter(const PlanDev& P, const T* PhiR, T* Phi, hipStream_t s) {
-  int64_t tot = (int64_t)P.max_nloc * P.max_nc;
-  if (tot == 0) return;
-  k_phi_scatter<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, PhiR, Phi);
-}
-
-template <typename T>
-void Kern<T>::local_apply_multi(const PlanDev& P, const Geo& g, const double* rho, const T* Phi,
-                                T* KPhi, hipStream_t s) {
+void Kern<T>::kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PhiR, const T* Lam, T* Kc,
+                          hipStream_t s) {
   if (P.max_nc == 0) return;
-  int zc = hmin(P.max_nc, 16);
-  k_local_apply_multi<T><<<dim3(cdiv(P.max_nloc, 128), P.n_sub, zc), 128, 0, s>>>(P, g, rho, Phi, KPhi);
+  k_kc_identity<T><<<dim3(cdiv((int64_t)P.max_nc * P.max_nc, 256), P.n_sub), 256, 0, s>>>(P, g, rho, PhiR, Lam, Kc);
 }
 
 template <typename T>
-void Kern<T>::extract_gamma(const PlanDev& P, const T* Phi, const T* Z, T* PhiG, T* XG, hipStream_t s) {
+void Kern<T>::extract_gamma(const PlanDev& P, const T* PhiR, const T* Z, T* PhiG, T* XG, hipStream_t s) {
   int64_t tot = (int64_t)P.max_ng * (P.max_nc + P.max_na);
   if (tot == 0) return;
-  k_extract_gamma<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Phi, Z, PhiG, XG);
+  k_extract_gamma<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, PhiR, Z, PhiG, XG);
 }
 
 template <typename T>
@@ -1452,8 +1625,8 @@ void Kern<T>::gather_I(const PlanDev& P, const Geo& g, const double* r, T* vI, i
 template <typename T>
 void Kern<T>::block_solve(const PlanDev& P, const Geo& g, const double* rho, int setR, const T* G,
                           T* v, int nrhs, hipStream_t s) {
-  size_t sm = (size_t)hmax(P.max_block, 1) * sizeof(T);
-  k_block_solve<T><<<dim3(P.n_sub, nrhs), 256, sm, s>>>(P, g, rho, setR, G, v);
+  size_t sm = (size_t)(hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * sizeof(T);
+  k_block_solve<T><<<dim3(P.n_sub, nrhs), BS_THREADS, sm, s>>>(P, g, rho, setR, G, v);
 }
 
 template <typename T>

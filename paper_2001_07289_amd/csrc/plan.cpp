@@ -495,6 +495,56 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     S.bR_off = (int64_t)plan.blocks.size();
     make_blocks(cntR, plan.block_target, 0, plan.blocks);
     S.nbR = (int)(plan.blocks.size() - S.bR_off);
+    // coupling rows between consecutive blocks of each set
+    for (int setR = 0; setR < 2; ++setR) {
+      const int64_t b0 = setR ? S.bR_off : S.bI_off;
+      const int nbs = setR ? S.nbR : S.nbI;
+      const std::vector<int32_t>& ls = setR ? lr : lI;
+      std::vector<int32_t> sl;
+      for (int l = 0; l < S.n_loc; ++l)
+        if (ls[l] >= 0) sl.push_back(l);
+      const int nt = dim == 3 ? 9 : 3;
+      auto add_rows = [&](const BlockDev& B, bool first, int dir) {
+        const int cnt = first ? B.first_n : B.last_n;
+        const int base = first ? B.start : B.start + B.size - B.last_n;
+        for (int i = 0; i < cnt; ++i) {
+          const int l = sl[base + i];
+          int c[3] = {l % S.m[0], (l / S.m[0]) % S.m[1], l / (S.m[0] * S.m[1])};
+          plan.cpl_sub.push_back(s);
+          plan.cpl_loc.push_back(l);
+          plan.cpl_dir.push_back(dir);
+          for (int t = 0; t < 9; ++t) {
+            int cn[3] = {c[0], c[1], c[2]};
+            bool ok = t < nt;
+            if (dim == 3) {
+              cn[2] += dir;
+              cn[0] += t % 3 - 1;
+              cn[1] += t / 3 - 1;
+            } else {
+              cn[1] += dir;
+              cn[0] += t - 1;
+            }
+            for (int a = 0; a < 3; ++a) ok = ok && cn[a] >= 0 && cn[a] < S.m[a];
+            int32_t rk = -1;
+            if (ok) rk = ls[cn[0] + S.m[0] * (cn[1] + S.m[1] * cn[2])];
+            plan.cpl_rank.push_back(rk);
+          }
+        }
+      };
+      for (int k = 0; k < nbs; ++k) {
+        BlockDev& B = plan.blocks[b0 + k];
+        B.cf_off = -1;
+        B.cb_off = -1;
+        if (k > 0 && plan.blocks[b0 + k - 1].plane_hi == B.plane_lo) {
+          B.cf_off = (int64_t)plan.cpl_sub.size();
+          add_rows(B, true, -1);
+        }
+        if (k + 1 < nbs && B.plane_hi == plan.blocks[b0 + k + 1].plane_lo) {
+          B.cb_off = (int64_t)plan.cpl_sub.size();
+          add_rows(B, false, 1);
+        }
+      }
+    }
     for (int64_t k = S.bI_off; k < (int64_t)plan.blocks.size(); ++k) {
       BlockDev& B = plan.blocks[k];
       B.G_off = G_off;
@@ -513,7 +563,7 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     S.T_off = T_off;
     T_off += (int64_t)S.n_a * S.n_c;
     S.Phi_off = Phi_off;
-    Phi_off += (int64_t)S.n_loc * S.n_c;
+    Phi_off += (int64_t)S.n_r * S.n_c;
     S.PhiG_off = PhiG_off;
     PhiG_off += (int64_t)S.n_g * S.n_c;
     S.Kc_off = Kc_off;
@@ -547,8 +597,6 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
   plan.pool_Phi = Phi_off;
   plan.pool_PhiG = PhiG_off;
   plan.pool_Kc = Kc_off;
-  // KPhi shares the Phi layout in a second pool
-  for (auto& S : plan.subs) S.KPhi_off = S.Phi_off;
 
   // Gamma index -> entries; coarse id -> local coarse entries
   const int64_t ng = (int64_t)c.gam_node.size();

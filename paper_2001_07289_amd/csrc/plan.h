@@ -68,6 +68,10 @@ struct Plan {
   std::vector<int32_t> a_ptr, a_r, a_c;       // averages: CSR of r ranks; local coarse index
   std::vector<int32_t> c_glob, c_kind;        // per local coarse: global id; vertex idx or -(a+1)
   std::vector<BlockDev> blocks;
+  // plane couplings between consecutive blocks: per row (a node of a block's
+  // first or last plane) the set ranks of its 9 (3 in 2D) neighbours in the
+  // adjacent plane, -1 where absent
+  std::vector<int32_t> cpl_rank, cpl_sub, cpl_loc, cpl_dir;
 
   std::vector<int32_t> gam_eptr, gam_ent;     // Gamma index -> Gamma entries
   std::vector<int32_t> crs_eptr, crs_ent;     // coarse id -> local coarse entries

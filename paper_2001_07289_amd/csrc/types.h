@@ -30,8 +30,7 @@ struct SubDev {
   int64_t XG_off;    // n_g x n_a: rows of X at Gamma entries (0 at vertices)
   int64_t Sc_off;    // n_a x n_a: constraint Schur complement, swept
   int64_t T_off;     // n_a x n_c: C_r Y - [0 I], then Lambda
-  int64_t Phi_off;   // n_loc x n_c coarse basis; reused for K Phi
-  int64_t KPhi_off;  // n_loc x n_c
+  int64_t Phi_off;   // n_r x n_c: rows of the coarse basis on the r set
   int64_t PhiG_off;  // n_g x n_c: rows of Phi at Gamma entries
   int64_t Kc_off;    // n_c x n_c local coarse matrix
 };
@@ -43,6 +42,8 @@ struct BlockDev {
   int plane_lo, plane_hi;   // local plane range
   int first_n, last_n;      // nodes in the first / last plane of the block
   int64_t G_off;            // offset of its size x size matrix in the pool
+  int64_t cf_off;           // coupling rows of the first plane to block k-1 (-1: none)
+  int64_t cb_off;           // coupling rows of the last plane to block k+1 (-1: none)
 };
 
 // One front of the multifrontal coarse factorization.  Positions 0..p-1 are
