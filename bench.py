@@ -1,13 +1,22 @@
 """Benchmark: BDDC-SO PCG DoF/s to a relative residual of 1e-8 on one MI355X.
 
 A step is one pass of the whole hot path over one synthetic input: the
-numeric setup from rho (local factors, coarse basis, coarse factorization)
-followed by the PCG solve to rtol.  Inputs (rho, f) are resident in HBM before
-the timed region; the host classification and the device allocations happen
-once, before it.
+numeric setup from rho (local block factors, constraint Schur complements,
+coarse basis, local coarse matrices, coarse multifrontal factorization)
+followed by the PCG solve to rtol 1e-8.  Inputs (rho, f) are resident in HBM
+before the timed region; the host classification, the plan and the device
+allocations happen once, before it (they do not depend on rho or f).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
-                    [--precision fp64|mixed] [--no-cpu-baseline]
+                    [--precision fp64|mixed] [--no-cpu-baseline] [--no-extras]
+
+The default workload is the 3D Q1 problem on a 96^3 mesh (857,375 unknowns),
+8x8x8 subdomains of 12^3 elements, subobjects of 4h, log10(rho) uniform in
+[-3, 3] per subdomain, plain FP64.  The JSON line also carries the dominant
+kernel class's roofline (HIP events around its launches in the timed region,
+algorithmic bytes or flops per launch), the oracle's rate on a bounded sample
+on the host cores, the mixed-precision form of the same workload and the
+gradient rate of the adjoint workload.
 """
 from __future__ import annotations
 
@@ -24,15 +33,17 @@ import numpy as np  # noqa: E402
 
 import workloads as W  # noqa: E402
 
+HBM_GBS = 8000.0                       # MI355X HBM3E peak, GB/s
+MFMA_TFLOPS = {"f64": 78.6, "f32": 157.3}  # dense matrix peaks, TFLOP/s
+
 WORKLOADS = {
-    # name: (builder, description)
     "cfg2": (W.config2, "3D Q1 96^3 (857,375 dofs), 8x8x8 subdomains of 12^3, subobjects 4h, "
                         "log10 rho ~ U[-3,3] per subdomain"),
-    "cfg4": (W.config4, "cfg2 mesh and rho with subobjects of 2h"),
+    "cfg4": (W.config4, "cfg2 mesh, partition and rho with subobjects of 2h (every interface dof primal)"),
     "cfg1": (W.config1, "2D Q1 64^2, 4x4 subdomains of 16^2, subobjects 4h, rho = 1"),
-    "cfg5": (W.config5, "3D Q1 64^3, 8x8x8 subdomains of 8^3, subobjects 4h"),
-    "cfg2_small": (lambda: W.config2_like(48, 12, 4, cfg=2, name="cfg2_small"),
-                   "cfg2 shapes on a 48^3 mesh (4x4x4 subdomains of 12^3)"),
+    "cfg5": (W.config5, "3D Q1 64^3, 8x8x8 subdomains of 8^3, subobjects 4h, rho = exp(box(theta))"),
+    "cfg3": (lambda: W.config3(nrhs=32), "3D Q1 128^3, 1000 uneven subdomains of 8^3..16^3, subobjects "
+                                         "2h/4h/8h, 1e6 channels, 32 right-hand sides"),
 }
 
 
@@ -45,7 +56,9 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--coarse", default="nd", choices=["nd", "dense"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phases", action="store_true", help="also time setup and solve separately")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run the library's copy kernel over MIB MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -63,16 +76,124 @@ def cpu_baseline():
     t2 = time.perf_counter()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": p.n_free / (t2 - t0), "unit": "DoF/s", "cores": threads, "kind": "oracle",
-            "sample": f"cfg2 shapes on 48^3 ({p.n_free} dofs, 64 subdomains), setup {t1 - t0:.1f} s "
-                      f"+ solve {t2 - t1:.1f} s, {r.iters} iterations"}
+            "sample": f"cfg2 shapes on a 48^3 mesh ({p.n_free} dofs, 64 subdomains of 12^3, L=4h): "
+                      f"setup {t1 - t0:.1f} s + PCG {t2 - t1:.1f} s, {r.iters} iterations"}
+
+
+def roofline(prof, dtype):
+    """Roofline of the dominant kernel class (largest event time in the
+    warmup steps), from its events in the timed steps."""
+    name = prof["dominant"]
+    rec = prof["timed"][name]
+    if rec["launches"] == 0 or rec["total_ms"] <= 0:
+        return None
+    avg_s = rec["total_ms"] / rec["launches"] * 1e-3
+    flops = rec["flops"] / rec["launches"]
+    nbytes = rec["bytes"] / rec["launches"]
+    peak_f = MFMA_TFLOPS[dtype] * 1e12
+    ai = flops / max(nbytes, 1.0)
+    mfma_bound = name in ("sweep_update", "gemm", "sweep_panel") and ai * HBM_GBS * 1e9 >= peak_f
+    if mfma_bound:
+        ach = flops / avg_s / 1e12
+        out = {"bound": "mfma", "achieved": ach, "peak": MFMA_TFLOPS[dtype], "unit": "TFLOP/s",
+               "frac": ach / MFMA_TFLOPS[dtype]}
+    else:
+        ach = nbytes / avg_s / 1e9
+        out = {"bound": "hbm", "achieved": ach, "peak": HBM_GBS, "unit": "GB/s", "frac": ach / HBM_GBS}
+    out.update({"traffic": None, "kernel": name, "launches": rec["launches"],
+                "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": nbytes,
+                "algorithmic_flops_per_launch": flops})
+    return out
+
+
+def run_steps(pc, rho, b, steps, warmup, profile=False):
+    """Warmup (profiling every kernel class to find the dominant one), then
+    the timed steps with events around the dominant class's launches only."""
+    import torch
+
+    if profile:
+        pc.profile()
+    for _ in range(warmup):
+        pc.refactor(rho)
+        x, st = pc.solve(b)
+    torch.cuda.synchronize()
+    if profile:
+        warm = pc.profile_read()
+        dominant = max(warm, key=lambda k: warm[k]["total_ms"])
+        pc.profile([dominant])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pc.refactor(rho)
+        x, st = pc.solve(b)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = None
+    if profile:
+        prof = {"timed": pc.profile_read(), "warmup": warm, "dominant": dominant}
+        pc.profile([])
+    return (t1 - t0) / steps, x, st, prof
+
+
+def grads_rate(steps=3):
+    """Gradients per second of the adjoint workload (64^3, 512 subdomains of
+    8^3, L = 4h): setup from theta, forward solve, adjoint solve, element
+    kernel and filter transpose, FP64 outer with FP32 local factors."""
+    import torch
+
+    import paper_2001_07289_amd as pk
+
+    p = W.config5()
+    prob = pk.Problem.from_workload(p)
+    dev = torch.device("cuda:0")
+    f = torch.as_tensor(p.f[0], device=dev)
+    theta = torch.as_tensor(p.extra["theta"], device=dev)
+    theta_obs = torch.as_tensor(p.extra["theta_obs"], device=dev)
+    pc = pk.Preconditioner(prob, torch.ones(p.n_elements, dtype=torch.float64, device=dev), precision=1,
+                           rtol=1e-8)
+    with torch.no_grad():
+        u_obs = pk.BDDCSOSolve.apply(theta_obs, f, pc).clone()
+
+    def one():
+        th = theta.clone().requires_grad_(True)
+        u = pk.BDDCSOSolve.apply(th, f, pc)
+        loss = 0.5 * torch.sum((u - u_obs) ** 2)
+        loss.backward()
+        return th.grad
+
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g = one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"value": 1.0 / dt, "unit": "grads/s", "ms_per_grad": dt * 1e3, "workload": "cfg5 adjoint, 64^3",
+            "grad_norm": float(torch.linalg.norm(g))}
+
+
+def copy_probe(mib):
+    import torch
+
+    import paper_2001_07289_amd as pk
+
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        pk.copy_probe(a, b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU "
-                                   "sharding is a design only)"}))
+        print(json.dumps({"error": "this build runs on one GPU: only --gpus 1 is supported (the multi-GPU "
+                                   "sharding of the subdomain batch is a design, not built)"}))
         sys.exit(2)
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
     import torch
 
     import paper_2001_07289_amd as pk
@@ -81,64 +202,68 @@ def main():
     p = build()
     prob = pk.Problem.from_workload(p)
     dev = torch.device("cuda:0")
-    rho = torch.as_tensor(p.rho, device=dev)
-    b = torch.as_tensor(np.ascontiguousarray(p.f[0]), device=dev)
+    nrhs = p.f.shape[0]
+    if a.workload == "cfg5":
+        rho = torch.exp(prob.box_filter(torch.as_tensor(p.extra["theta"], device=dev)))
+    else:
+        rho = torch.as_tensor(p.rho, device=dev)
+    b = torch.as_tensor(np.ascontiguousarray(p.f.reshape(-1)), device=dev)
     opts = dict(precision=1 if a.precision == "mixed" else 0, coarse_solver=1 if a.coarse == "dense" else 0,
-                rtol=1e-8, maxit=500)
+                rtol=1e-8, maxit=500, max_nrhs=nrhs)
     t0 = time.perf_counter()
     pc = pk.Preconditioner(prob, rho, **opts)
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
-
-    def step():
-        pc.refactor(rho)
-        return pc.solve(b)
-
-    for _ in range(a.warmup):
-        x, st = step()
+    dt, x, st, prof = run_steps(pc, rho, b, a.steps, a.warmup, profile=True)
+    n = p.n_free * nrhs
+    res = float(torch.linalg.norm(b - pc.operator(x)) / torch.linalg.norm(b))
+    # phase split (outside the timed region)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
-        x, st = step()
+    pc.refactor(rho)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / a.steps
-    n = p.n_free
-    # true residual of the last solve, on the device
-    res = float(torch.linalg.norm(b - pc.operator(x)) / torch.linalg.norm(b))
+    pc.solve(b)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    dtype = "f64" if a.precision == "fp64" else "f32"
+    rf = roofline(prof, "f64" if a.precision == "fp64" else "f32")
+    warm = prof["warmup"]
+    tot = sum(r["total_ms"] for r in warm.values())
+    if rf:
+        rf["share_of_profiled_kernel_time"] = warm[rf["kernel"]]["total_ms"] / max(tot, 1e-12)
     out = {
         "metric": "BDDC-SO PCG DoF/s to rel.res 1e-8",
-        "value": n * a.steps / (t1 - t0),
+        "value": n / dt,
         "unit": "DoF/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": dt * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32-local/f64-outer",
         "data": "synthetic",
-        "config": {"workload": a.workload, "description": desc, "n_free": n, "n_sub": prob.info()["n_sub"],
-                   "n_coarse": pc.info()["n_coarse"], "precision": a.precision, "coarse": a.coarse,
-                   "rtol": 1e-8},
-        "iters": st["iters"][0], "kappa": st["kappa"][0], "true_relres": res,
+        "config": {"workload": a.workload, "description": desc, "n_free": p.n_free, "nrhs": nrhs,
+                   "n_sub": prob.info()["n_sub"], "n_coarse": pc.info()["n_coarse"], "precision": a.precision,
+                   "coarse": a.coarse, "rtol": 1e-8},
+        "roofline": rf,
+        "iters": st["iters"][:4], "kappa": st["kappa"][:4], "true_relres": res,
+        "setup_ms": (t1 - t0) * 1e3, "solve_ms": (t2 - t1) * 1e3,
         "first_setup_s": t_first, "device_bytes": pc.info()["device_bytes"],
+        "kernel_classes_ms_per_warmup_step": {k: v["total_ms"] / max(a.warmup, 1) for k, v in warm.items()},
+        "dtype_kernels": dtype,
     }
-    if a.phases:
-        reps = max(1, a.steps)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            pc.refactor(rho)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(reps):
-            pc.solve(b)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        out["setup_ms"] = (t1 - t0) * 1e3 / reps
-        out["solve_ms"] = (t2 - t1) * 1e3 / reps
+    if not a.no_extras and a.workload == "cfg2" and a.precision == "fp64":
+        # same workload, FP32 local factors with flexible FP64 CG
+        pcm = pk.Preconditioner(prob, rho, precision=1, rtol=1e-8, maxit=500)
+        dtm, xm, stm, _ = run_steps(pcm, rho, b, max(2, a.steps // 2), 1)
+        out["mixed"] = {"value": n / dtm, "unit": "DoF/s", "ms_per_step": dtm * 1e3, "iters": stm["iters"][0],
+                        "true_relres": float(torch.linalg.norm(b - pc.operator(xm)) / torch.linalg.norm(b)),
+                        "rel_diff_vs_fp64_solution": float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))}
+        del pcm
+        out["grads"] = grads_rate()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -180,6 +180,42 @@ bddcso_status bddcso_element_grad(const bddcso_precond* pc, const double* u_dev,
 bddcso_status bddcso_box_filter(const bddcso_problem* p, const double* in_dev, double* out_dev,
                                 int transpose, void* stream);
 
+/* Sizes and algorithmic work of the plan for these options (host only; no
+ * device work).  Flop counts are those of the symmetric sweeps (n^2 p per
+ * matrix of size n with p pivots, lower triangle). */
+typedef struct {
+  int64_t n_coarse;
+  int64_t n_fronts;            /* fronts of the coarse factorization            */
+  int64_t levels;              /* levels of the nested-dissection tree          */
+  int64_t max_front;           /* largest front size                            */
+  int64_t max_front_pivots;    /* largest pivot count of a front                */
+  int64_t n_blocks;            /* diagonal blocks of all local factors          */
+  int64_t max_block;           /* largest diagonal block                        */
+  double coarse_factor_entries;/* sum over fronts of n * p                      */
+  double coarse_sweep_flops;   /* sum over fronts of n^2 p                      */
+  double local_sweep_flops;    /* sum over local blocks of size^3               */
+  double device_bytes;         /* device memory a setup with these options holds */
+} bddcso_plan_stats;
+
+bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bddcso_plan_stats* out);
+
+/* Timing of kernel classes with HIP events recorded around each of their
+ * launches on the launching stream, from this call on.  class_mask: bit c
+ * selects class c (0 switches it off and clears the record).  Classes: 1 the
+ * rank-32 sweep updates (MFMA), 2 the block-tridiagonal solves (HBM), 3 the
+ * batched GEMMs (MFMA), 4 the sweep panels.  bddcso_profile_read waits for
+ * the recorded events, then returns for one class the launches seen, their
+ * summed duration and their summed algorithmic flops and bytes (the minimum
+ * traffic: each operand read once, each output written once). */
+bddcso_status bddcso_profile(bddcso_precond* pc, int class_mask);
+bddcso_status bddcso_profile_read(bddcso_precond* pc, int kernel_class, int64_t* launches, double* total_ms,
+                                  double* flops, double* bytes);
+
+/* Plain device copy of `bytes` (a multiple of 16) from src_dev to dst_dev by
+ * a streaming kernel: a known traffic against which hardware byte counters
+ * are calibrated.  Not part of the solver. */
+bddcso_status bddcso_copy_probe(const void* src_dev, void* dst_dev, int64_t bytes, void* stream);
+
 /* Sizes of one preconditioner: coarse dofs, fronts of the coarse factor,
  * device bytes held.  Any pointer may be NULL. */
 bddcso_status bddcso_precond_info(const bddcso_precond* pc, int64_t* n_coarse, int64_t* n_fronts,

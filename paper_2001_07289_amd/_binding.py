@@ -21,6 +21,7 @@ EXPORTED = [
     "bddcso_refactor", "bddcso_check_pivots", "bddcso_operator_apply", "bddcso_apply", "bddcso_solve",
     "bddcso_element_grad", "bddcso_box_filter", "bddcso_precond_info", "bddcso_local_coarse",
     "bddcso_precond_destroy", "bddcso_problem_destroy", "bddcso_last_error",
+    "bddcso_plan_info", "bddcso_profile", "bddcso_profile_read", "bddcso_copy_probe",
 ]
 
 
@@ -36,6 +37,14 @@ class Stats(C.Structure):
                 ("relres", C.c_double * MAX_RHS), ("lambda_min", C.c_double * MAX_RHS),
                 ("lambda_max", C.c_double * MAX_RHS), ("kappa", C.c_double * MAX_RHS),
                 ("n_coarse", C.c_int64), ("t_solve_ms", C.c_double)]
+
+
+class PlanStats(C.Structure):
+    _fields_ = [("n_coarse", C.c_int64), ("n_fronts", C.c_int64), ("levels", C.c_int64),
+                ("max_front", C.c_int64), ("max_front_pivots", C.c_int64), ("n_blocks", C.c_int64),
+                ("max_block", C.c_int64), ("coarse_factor_entries", C.c_double),
+                ("coarse_sweep_flops", C.c_double), ("local_sweep_flops", C.c_double),
+                ("device_bytes", C.c_double)]
 
 
 class BDDCSOError(RuntimeError):
@@ -75,6 +84,10 @@ def load() -> C.CDLL:
         "bddcso_precond_destroy": (None, [vp]),
         "bddcso_problem_destroy": (None, [vp]),
         "bddcso_last_error": (C.c_char_p, []),
+        "bddcso_plan_info": (C.c_int, [vp, C.POINTER(Options), C.POINTER(PlanStats)]),
+        "bddcso_profile": (C.c_int, [vp, C.c_int]),
+        "bddcso_copy_probe": (C.c_int, [vp, vp, C.c_int64, vp]),
+        "bddcso_profile_read": (C.c_int, [vp, C.c_int, i64p, dp, dp, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

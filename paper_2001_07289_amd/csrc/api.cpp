@@ -124,6 +124,51 @@ struct DevMem {
 struct Batch {
   void* desc = nullptr;  // device descriptor array
   int n = 0, maxm = 0, maxn = 0, maxp = 0;
+  std::vector<GemmDesc> hg;   // host copies (work accounting)
+  std::vector<SweepDesc> hs;
+};
+
+struct EventProfiler : Profiler {
+  int mask = 0;  // bit c: record class c
+  struct Rec {
+    std::vector<hipEvent_t> ev;  // begin/end pairs
+    size_t used = 0;
+    double flops = 0, bytes = 0;
+    int64_t launches = 0;
+  } rec[5];
+  hipEvent_t next(Rec& r) {
+    if (r.used == r.ev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      r.ev.push_back(e);
+    }
+    return r.ev[r.used++];
+  }
+  void begin(int c, hipStream_t s) override {
+    if (c < 1 || c > 4 || !(mask & (1 << c))) return;
+    hipEvent_t e = next(rec[c]);
+    if (e) (void)hipEventRecord(e, s);
+  }
+  void end(int c, double f, double b, hipStream_t s) override {
+    if (c < 1 || c > 4 || !(mask & (1 << c))) return;
+    hipEvent_t e = next(rec[c]);
+    if (e) (void)hipEventRecord(e, s);
+    rec[c].flops += f;
+    rec[c].bytes += b;
+    ++rec[c].launches;
+  }
+  void reset(int m) {
+    mask = m;
+    for (auto& r : rec) {
+      r.used = 0;
+      r.flops = r.bytes = 0;
+      r.launches = 0;
+    }
+  }
+  ~EventProfiler() override {
+    for (auto& r : rec)
+      for (hipEvent_t e : r.ev) (void)hipEventDestroy(e);
+  }
 };
 
 }  // namespace
@@ -140,7 +185,7 @@ template <typename T>
 struct Numeric {
   T *G = nullptr, *Z = nullptr, *XG = nullptr, *Sc = nullptr, *Tm = nullptr, *Lam = nullptr,
     *Phi = nullptr, *PhiG = nullptr, *Kc = nullptr;
-  T *W = nullptr, *tmp = nullptr, *sw = nullptr;
+  T *W = nullptr, *W2 = nullptr, *tmp = nullptr, *sw = nullptr, *sw2 = nullptr;
   int64_t wstride = 0, tmp_stride = 0, sw_stride = 0;
   // per-iteration
   T *vI = nullptr, *vR = nullptr, *q = nullptr, *gv = nullptr, *v2 = nullptr, *mu = nullptr, *bci = nullptr;
@@ -159,6 +204,9 @@ struct bddcso_precond {
   Numeric<double> nd;
   Numeric<float> nf;
   double *rho = nullptr, *alpha = nullptr, *delta = nullptr, *khat = nullptr, *cpl_coef = nullptr;
+  double* vcoef = nullptr;    // stencil rows of the primal vertices (27 per vertex)
+  int32_t* vcode = nullptr;
+  int max_nv = 0;
   double *fpool = nullptr, *fsw = nullptr, *bc = nullptr, *uc = nullptr, *fvec = nullptr, *xh = nullptr;
   int64_t fsw_stride = 0;
   int32_t* status = nullptr;
@@ -181,6 +229,11 @@ struct bddcso_precond {
   int32_t *active = nullptr, *iters = nullptr, *flags = nullptr, *nactive = nullptr;
   int32_t* h_nactive = nullptr;  // pinned
   int max_nrhs = 1;
+  EventProfiler prof;
+  hipStream_t s2 = nullptr;                 // second stream of the setup
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  double gI_entries = 0, gR_entries = 0;  // G entries streamed by one block solve
+  Profiler* P_() { return prof.mask ? &prof : nullptr; }
 };
 
 namespace {
@@ -204,6 +257,7 @@ Batch make_gemm_batch(DevMem& mem, const std::vector<GemmDesc>& v, hipStream_t s
     b.maxn = std::max(b.maxn, d.n);
   }
   b.desc = mem.upload(v, s);
+  b.hg = v;
   return b;
 }
 
@@ -215,6 +269,7 @@ Batch make_sweep_batch(DevMem& mem, const std::vector<SweepDesc>& v, hipStream_t
     b.maxp = std::max(b.maxp, d.p);
   }
   b.desc = mem.upload(v, s);
+  b.hs = v;
   return b;
 }
 
@@ -236,11 +291,13 @@ void alloc_numeric(bddcso_precond* pc, hipStream_t s) {
   int max_plane = pc->P.max_plane;
   N.wstride = (int64_t)max_plane * max_plane;
   N.W = m.alloc<T>(N.wstride * pl.subs.size());
+  N.W2 = m.alloc<T>(N.wstride * pl.subs.size());
   N.tmp_stride = (int64_t)pl.max_block * std::max(pl.max_zcols, 1);
   N.tmp = m.alloc<T>(N.tmp_stride * pl.subs.size());
   int maxsw = std::max(pl.max_block, pl.max_na);
-  N.sw_stride = 2 * ((int64_t)maxsw * 32 + 32 * 32);
+  N.sw_stride = 2 * ((int64_t)maxsw * kSweepNB + kSweepNB * kSweepNB);
   N.sw = m.alloc<T>(N.sw_stride * pl.subs.size());
+  N.sw2 = m.alloc<T>(N.sw_stride * pl.subs.size());
   N.vI = m.alloc<T>(pl.tot_I * nr);
   N.vR = m.alloc<T>(pl.tot_r * nr);
   N.q = m.alloc<T>(pl.tot_g * nr);
@@ -307,6 +364,16 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
     pc->gLam = make_gemm_batch(m, lam, s);
     pc->gPhiR = make_gemm_batch(m, phir, s);
   }
+  // G entries streamed by one block solve of each set
+  for (const SubDev& S : pl.subs)
+    for (int setR = 0; setR < 2; ++setR) {
+      const int nb = setR ? S.nbR : S.nbI;
+      for (int k = 0; k < nb; ++k) {
+        const BlockDev& B = pl.blocks[(setR ? S.bR_off : S.bI_off) + k];
+        double e = (double)B.size * B.size + (B.cb_off >= 0 ? (double)B.size * B.last_n : 0.0);
+        (setR ? pc->gR_entries : pc->gI_entries) += e;
+      }
+    }
   // colours
   for (auto& cs : pl.color_subs) {
     pc->color_dev.push_back(m.upload(cs, s));
@@ -345,7 +412,7 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
   }
   int maxlev = 1;
   for (int L = 0; L < nlev; ++L) maxlev = std::max(maxlev, pc->level_n[L]);
-  pc->fsw_stride = 2 * ((int64_t)std::max(maxfn, 1) * 32 + 32 * 32);
+  pc->fsw_stride = 2 * ((int64_t)std::max(maxfn, 1) * kSweepNB + kSweepNB * kSweepNB);
   pc->fsw = m.alloc<double>(pc->fsw_stride * maxlev);
 }
 
@@ -363,15 +430,25 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   // local block-tridiagonal factors of K_II and K_rr
   if (sizeof(T) == 8) launch_fill_f64((double*)N.G, pl.pool_G, 0.0, s);
   else launch_fill_f32((float*)N.G, pl.pool_G, 0.0f, s);
-  for (int setR = 0; setR < 2; ++setR) {
-    Kern<T>::block_assemble(P, g, rho, setR, N.G, s);
+  Kern<T>::block_assemble(P, g, rho, 0, N.G, s);
+  Kern<T>::block_assemble(P, g, rho, 1, N.G, s);
+  // The interior (Dirichlet) factors are needed only when the preconditioner
+  // is applied, so they are built on a second stream, overlapping the rest
+  // of the setup; the caller's stream waits for them at the end.
+  HIPCHK(hipEventRecord(pc->ev_fork, s));
+  HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_fork, 0));
+  for (int setR = 1; setR >= 0; --setR) {
+    hipStream_t ss = setR ? s : pc->s2;
+    T* W = setR ? N.W : N.W2;
+    T* sws = setR ? N.sw : N.sw2;
     auto& sw = setR ? pc->swR : pc->swI;
     for (int k = 0; k < (int)sw.size(); ++k) {
-      if (k > 0) Kern<T>::schur_couple(P, g, rho, setR, k, N.G, N.W, N.wstride, s);
-      Kern<T>::sweep((SweepDesc*)sw[k].desc, sw[k].n, sw[k].maxn, sw[k].maxp, N.G, N.sw, N.sw_stride,
-                     pc->status, setR ? 2 : 1, s);
+      if (k > 0) Kern<T>::schur_couple(P, g, rho, setR, k, N.G, W, N.wstride, ss);
+      Kern<T>::sweep((SweepDesc*)sw[k].desc, sw[k].hs.data(), sw[k].n, sw[k].maxn, sw[k].maxp, N.G, sws,
+                     N.sw_stride, pc->status, setR ? 2 : 1, ss, pc->P_());
     }
   }
+  HIPCHK(hipEventRecord(pc->ev_join, pc->s2));
   // [X | Y'] = K_rr^{-1} [C_r^T | -K_rv]
   if (sizeof(T) == 8) launch_fill_f64((double*)N.Z, pl.pool_Z, 0.0, s);
   else launch_fill_f32((float*)N.Z, pl.pool_Z, 0.0f, s);
@@ -381,24 +458,26 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
     if (k > 0) Kern<T>::couple_multi(P, g, rho, k, 1, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
     Kern<T>::copy_block_rows(P, k, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
     const Batch& b = pc->gfwd[k];
-    Kern<T>::gemm((GemmDesc*)b.desc, b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)-1, (T)0, s);
+    Kern<T>::gemm((GemmDesc*)b.desc, b.hg.data(), b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)-1, (T)0, s,
+                  pc->P_());
   }
   for (int k = nk - 2; k >= 0; --k) {
     Kern<T>::couple_multi(P, g, rho, k, 0, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
     const Batch& b = pc->gbwd[k];
-    Kern<T>::gemm((GemmDesc*)b.desc, b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)1, (T)1, s);
+    Kern<T>::gemm((GemmDesc*)b.desc, b.hg.data(), b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)1, (T)1, s,
+                  pc->P_());
   }
   // constraint Schur complement and the coarse basis
   Kern<T>::sc_assemble(P, N.Z, N.Sc, s);
-  Kern<T>::sweep((SweepDesc*)pc->swSc.desc, pc->swSc.n, pc->swSc.maxn, pc->swSc.maxp, N.Sc, N.sw, N.sw_stride,
-                 pc->status, 3, s);
+  Kern<T>::sweep((SweepDesc*)pc->swSc.desc, pc->swSc.hs.data(), pc->swSc.n, pc->swSc.maxn, pc->swSc.maxp, N.Sc,
+                 N.sw, N.sw_stride, pc->status, 3, s, pc->P_());
   Kern<T>::lambda_rhs(P, N.Z, N.Tm, s);
-  Kern<T>::gemm((GemmDesc*)pc->gLam.desc, pc->gLam.n, pc->gLam.maxm, pc->gLam.maxn, N.Sc, 0, N.Tm, 0, N.Lam,
-                (T)-1, (T)0, s);
+  Kern<T>::gemm((GemmDesc*)pc->gLam.desc, pc->gLam.hg.data(), pc->gLam.n, pc->gLam.maxm, pc->gLam.maxn, N.Sc, 0,
+                N.Tm, 0, N.Lam, (T)-1, (T)0, s, pc->P_());
   Kern<T>::phi_r_init(P, N.Z, N.Phi, s);
-  Kern<T>::gemm((GemmDesc*)pc->gPhiR.desc, pc->gPhiR.n, pc->gPhiR.maxm, pc->gPhiR.maxn, N.Z, 0, N.Lam, 0,
-                N.Phi, (T)-1, (T)1, s);
-  Kern<T>::kc_identity(P, g, rho, N.Phi, N.Lam, N.Kc, s);
+  Kern<T>::gemm((GemmDesc*)pc->gPhiR.desc, pc->gPhiR.hg.data(), pc->gPhiR.n, pc->gPhiR.maxm, pc->gPhiR.maxn,
+                N.Z, 0, N.Lam, 0, N.Phi, (T)-1, (T)1, s, pc->P_());
+  Kern<T>::kc_identity(P, g, rho, N.Phi, N.Lam, N.Kc, pc->vcoef, pc->vcode, pc->max_nv, s);
   Kern<T>::extract_gamma(P, N.Phi, N.Z, N.PhiG, N.XG, s);
   // coarse: assemble into the fronts and factor level by level (FP64)
   launch_fill_f64(pc->fpool, pl.front_pool, 0.0, s);
@@ -408,9 +487,10 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
     for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
       launch_front_child_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fpool, s);
     const Batch& b = pc->swFront[L];
-    Kern<double>::sweep((SweepDesc*)b.desc, b.n, b.maxn, b.maxp, pc->fpool, pc->fsw, pc->fsw_stride, pc->status,
-                        4, s);
+    Kern<double>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, pc->fpool, pc->fsw, pc->fsw_stride,
+                        pc->status, 4, s, pc->P_());
   }
+  HIPCHK(hipStreamWaitEvent(s, pc->ev_join, 0));
 }
 
 void coarse_solve(bddcso_precond* pc, int nrhs, hipStream_t s) {
@@ -442,7 +522,7 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   const double* rho = pc->rho;
   // 1-2: Dirichlet solves and (I - P)^T on Gamma
   Kern<T>::gather_I(P, g, r, N.vI, nrhs, s);
-  Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s);
+  Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s, pc->P_(), pc->gI_entries, (double)pl.tot_I);
   Kern<T>::gamma_kgi(P, g, rho, N.vI, N.q, nrhs, s);
   // 3: E^T
   Kern<T>::gamma_t(P, g, r, N.q, pc->delta, N.gv, nrhs, s);
@@ -450,7 +530,7 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   if (sizeof(T) == 8) launch_fill_f64((double*)N.vR, pl.tot_r * nrhs, 0.0, s);
   else launch_fill_f32((float*)N.vR, pl.tot_r * nrhs, 0.0f, s);
   Kern<T>::neumann_rhs(P, N.gv, N.vR, nrhs, s);
-  Kern<T>::block_solve(P, g, rho, 1, N.G, N.vR, nrhs, s);
+  Kern<T>::block_solve(P, g, rho, 1, N.G, N.vR, nrhs, s, pc->P_(), pc->gR_entries, (double)pl.tot_r);
   Kern<T>::mu(P, N.vR, N.Sc, N.mu, nrhs, s);
   // 5-6: coarse problem
   Kern<T>::coarse_rhs_local(P, N.PhiG, N.gv, N.bci, nrhs, s);
@@ -463,7 +543,7 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   else launch_gamma_w(P, g, nullptr, (const float*)N.v2, pc->delta, z, nrhs, s);
   // 9-10: harmonic extension into the interiors
   Kern<T>::interior_rhs(P, g, rho, r, z, N.vI, nrhs, s);
-  Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s);
+  Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s, pc->P_(), pc->gI_entries, (double)pl.tot_I);
   Kern<T>::scatter_I(P, g, N.vI, z, nrhs, s);
 }
 
@@ -550,7 +630,11 @@ bddcso_status bddcso_problem_info(const bddcso_problem* p, int primal_mask, int6
 
 void bddcso_precond_destroy(bddcso_precond* pc) {
   if (!pc) return;
+  if (pc->s2) (void)hipStreamSynchronize(pc->s2);
   pc->mem.release();
+  if (pc->ev_fork) (void)hipEventDestroy(pc->ev_fork);
+  if (pc->ev_join) (void)hipEventDestroy(pc->ev_join);
+  if (pc->s2) (void)hipStreamDestroy(pc->s2);
   if (pc->h_nactive) (void)hipHostFree(pc->h_nactive);
   delete pc;
 }
@@ -692,6 +776,9 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     P.max_plane = max_plane;
 
     pc->rho = m.alloc<double>(c.n_elem);
+    for (auto& S : pl.subs) pc->max_nv = std::max(pc->max_nv, S.n_v);
+    pc->vcoef = m.alloc<double>(pl.tot_v * 27);
+    pc->vcode = m.alloc<int32_t>(pl.tot_v * 27);
     pc->alpha = m.alloc<double>(c.n_ss);
     pc->delta = m.alloc<double>(pl.tot_g);
     pc->status = m.alloc<int32_t>(1);
@@ -721,6 +808,9 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     pc->flags = m.alloc<int32_t>(nr);
     pc->nactive = m.alloc<int32_t>(1);
     HIPCHK(hipHostMalloc((void**)&pc->h_nactive, sizeof(int32_t) * 4, hipHostMallocDefault));
+    HIPCHK(hipStreamCreateWithFlags(&pc->s2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
   } catch (const HipFail& f) {
     bddcso_precond_destroy(pc);
     if (f.e == hipErrorOutOfMemory)
@@ -900,6 +990,83 @@ bddcso_status bddcso_box_filter(const bddcso_problem* p, const double* in, doubl
   g.n_elem = p->c.n_elem;
   launch_box_filter(g, in, out, transpose, as_stream(stream));
   if (hipGetLastError() != hipSuccess) return set_err(BDDCSO_EHIP, "box filter launch failed");
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bddcso_plan_stats* out) {
+  if (!p || !out) return set_err(BDDCSO_EINVAL, "null argument");
+  bddcso_options o;
+  if (opts) o = *opts;
+  else bddcso_default_options(&o);
+  Error err;
+  std::shared_ptr<Plan> plan;
+  try {
+    plan = get_plan(p, o, err);
+  } catch (const std::bad_alloc&) {
+    return set_err(BDDCSO_ENOMEM, "host allocation failed while planning");
+  }
+  if (!plan) return set_err(BDDCSO_EINVAL, err.msg);
+  const Plan& pl = *plan;
+  std::memset(out, 0, sizeof(*out));
+  out->n_coarse = pl.n_coarse;
+  out->n_fronts = (int64_t)pl.fronts.size();
+  out->levels = (int64_t)pl.level_fronts.size() - 1;
+  for (const FrontDev& F : pl.fronts) {
+    out->max_front = std::max<int64_t>(out->max_front, F.n);
+    out->max_front_pivots = std::max<int64_t>(out->max_front_pivots, F.p);
+    out->coarse_factor_entries += (double)F.n * F.p;
+    out->coarse_sweep_flops += (double)F.n * F.n * F.p;
+  }
+  out->n_blocks = (int64_t)pl.blocks.size();
+  out->max_block = pl.max_block;
+  for (const BlockDev& B : pl.blocks) out->local_sweep_flops += (double)B.size * B.size * B.size;
+  for (const SubDev& S : pl.subs) out->local_sweep_flops += (double)S.n_a * S.n_a * S.n_a;
+  const double ts = o.precision == 1 ? 4.0 : 8.0;
+  const double nr = std::max(o.max_nrhs, 1);
+  const double ns = (double)pl.subs.size();
+  int max_plane = 0;
+  for (auto& B : pl.blocks) max_plane = std::max(max_plane, std::max(B.first_n, B.last_n));
+  double tpool = pl.pool_G + pl.pool_Z + pl.pool_XG + pl.pool_Sc + 2.0 * pl.pool_T + pl.pool_Phi + pl.pool_PhiG +
+                 pl.pool_Kc + ns * ((double)max_plane * max_plane + (double)pl.max_block * std::max(pl.max_zcols, 1) +
+                                    2.0 * ((double)std::max(pl.max_block, pl.max_na) * kSweepNB + kSweepNB * kSweepNB)) +
+                 nr * (pl.tot_I + pl.tot_r + 3.0 * pl.tot_g + pl.tot_a + pl.tot_c);
+  double dpool = (double)pl.front_pool + 2.0 * nr * pl.front_vec + 2.0 * nr * pl.n_coarse +
+                 9.0 * pl.cpl_sub.size() + 6.0 * nr * p->c.n_free + p->c.n_elem + pl.tot_g;
+  out->device_bytes = ts * tpool + 8.0 * dpool;
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_profile(bddcso_precond* pc, int class_mask) {
+  if (!pc) return set_err(BDDCSO_EINVAL, "null precond");
+  if (class_mask < 0 || class_mask > 0x1e) return set_err(BDDCSO_EINVAL, "class mask must use bits 1..4");
+  pc->prof.reset(class_mask);
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_profile_read(bddcso_precond* pc, int kernel_class, int64_t* launches, double* total_ms,
+                                  double* flops, double* bytes) {
+  if (!pc) return set_err(BDDCSO_EINVAL, "null precond");
+  if (kernel_class < 1 || kernel_class > 4) return set_err(BDDCSO_EINVAL, "kernel class must be in 1..4");
+  auto& R = pc->prof.rec[kernel_class];
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < R.used; i += 2) {
+    if (hipEventSynchronize(R.ev[i + 1]) != hipSuccess) return set_err(BDDCSO_EHIP, "event sync failed");
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, R.ev[i], R.ev[i + 1]) != hipSuccess)
+      return set_err(BDDCSO_EHIP, "event timing failed");
+    ms += t;
+  }
+  if (launches) *launches = R.launches;
+  if (total_ms) *total_ms = ms;
+  if (flops) *flops = R.flops;
+  if (bytes) *bytes = R.bytes;
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_copy_probe(const void* src_dev, void* dst_dev, int64_t bytes, void* stream) {
+  if (!src_dev || !dst_dev || bytes < 0 || bytes % 16) return set_err(BDDCSO_EINVAL, "bytes must be a multiple of 16");
+  launch_copy16(src_dev, dst_dev, bytes / 16, as_stream(stream));
+  if (hipGetLastError() != hipSuccess) return set_err(BDDCSO_EHIP, "copy launch failed");
   return BDDCSO_OK;
 }
 

@@ -8,12 +8,25 @@
 
 namespace bddcso {
 
+// Pivots per panel of the batched sweeps (scratch per matrix: 2 slots of
+// n x kSweepNB + kSweepNB^2 entries).
+constexpr int kSweepNB = 32;
+
 // Geometry passed by value to kernels.
 struct Geo {
   int dim;
   int ne[3];        // elements per axis (ne[2] = 1 in 2D)
   int nf[3];        // free nodes per axis (nf[2] = 1 in 2D)
   int64_t n_free, n_elem;
+};
+
+// Records HIP events around the launches of one kernel class, with the
+// algorithmic flops and bytes of each launch.  Classes: 1 sweep update,
+// 2 block solve, 3 batched GEMM, 4 sweep panel.
+struct Profiler {
+  virtual ~Profiler() {}
+  virtual void begin(int cls, hipStream_t s) = 0;
+  virtual void end(int cls, double flops, double bytes, hipStream_t s) = 0;
 };
 
 // Device views of the plan tables.
@@ -60,10 +73,12 @@ struct Kern {
                              hipStream_t s);
   static void schur_couple(const PlanDev& P, const Geo& g, const double* rho, int setR, int k,
                            T* G, T* W, int64_t wstride, hipStream_t s);
-  static void sweep(SweepDesc* d_desc, int nprob, int maxn, int maxp, T* pool, T* scratch,
-                    int64_t scr_stride, int* status, int status_code, hipStream_t s);
-  static void gemm(const GemmDesc* d_desc, int nprob, int maxm, int maxn, const T* A, int transA,
-                   const T* B, int transB, T* C, T alpha, T beta, hipStream_t s);
+  static void sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int maxn, int maxp, T* pool,
+                    T* scratch, int64_t scr_stride, int* status, int status_code, hipStream_t s,
+                    Profiler* prof);
+  static void gemm(const GemmDesc* d_desc, const GemmDesc* h_desc, int nprob, int maxm, int maxn,
+                   const T* A, int transA, const T* B, int transB, T* C, T alpha, T beta, hipStream_t s,
+                   Profiler* prof);
   static void rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, hipStream_t s);
   static void couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
                            int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s);
@@ -73,7 +88,7 @@ struct Kern {
   static void lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s);
   static void phi_r_init(const PlanDev& P, const T* Z, T* PhiR, hipStream_t s);
   static void kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PhiR,
-                          const T* Lam, T* Kc, hipStream_t s);
+                          const T* Lam, T* Kc, double* vcoef, int32_t* vcode, int max_nv, hipStream_t s);
   static void extract_gamma(const PlanDev& P, const T* PhiR, const T* Z, T* PhiG, T* XG,
                             hipStream_t s);
   static void kc_to_front(const PlanDev& P, const int32_t* subs_of_color, int ns, const T* Kc,
@@ -81,7 +96,8 @@ struct Kern {
   // per-iteration
   static void gather_I(const PlanDev& P, const Geo& g, const double* r, T* vI, int nrhs, hipStream_t s);
   static void block_solve(const PlanDev& P, const Geo& g, const double* rho, int setR, const T* G,
-                          T* v, int nrhs, hipStream_t s);
+                          T* v, int nrhs, hipStream_t s, Profiler* prof, double g_entries,
+                          double vec_entries);
   static void gamma_kgi(const PlanDev& P, const Geo& g, const double* rho, const T* vI, T* q,
                         int nrhs, hipStream_t s);
   static void gamma_t(const PlanDev& P, const Geo& g, const double* r, const T* q, const double* delta,
@@ -125,6 +141,7 @@ void launch_pcg_p(double* p, const double* z, const double* rz_new, const double
 void launch_pcg_p_flex(double* p, const double* z, const double* zdr, const double* rz_old,
                        const int32_t* active, int64_t n, int nrhs, hipStream_t s);
 void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);
+void launch_copy16(const void* a, void* b, int64_t n16, hipStream_t s);
 
 void launch_element_grad(const Geo& g, const double* khat, const double* rho, const double* u,
                          const double* lam, double* out, int nrhs, hipStream_t s);

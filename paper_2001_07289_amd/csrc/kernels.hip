@@ -9,6 +9,7 @@
 // floating-point atomics), so results are bitwise repeatable.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 
 #include "kernels.h"
@@ -20,7 +21,7 @@ namespace {
 constexpr int TILE = 64;
 constexpr int BK = 16;
 constexpr int PAD = 4;
-constexpr int SWEEP_NB = 32;
+constexpr int SWEEP_NB = kSweepNB;  // pivots per panel
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -140,6 +141,14 @@ __global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) b[i] = (double)a[i];
+}
+
+// Plain streaming copy (16 B per thread and step), used to calibrate the
+// hardware byte counters against a known traffic.
+__global__ void k_copy16(const int4* __restrict__ a, int4* __restrict__ b, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) b[i] = a[i];
 }
 
 __global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b,
@@ -370,24 +379,25 @@ __device__ __forceinline__ T* sweep_slot(T* scratch, int64_t scr_stride, int pro
   return scratch + prob * scr_stride + ((j0 / SWEEP_NB) & 1) * (scr_stride / 2);
 }
 
-// Sweeps the pivot block (jb <= 32) held in LDS by one wave, in registers:
-// lane l keeps column l%32, rows 16*(l/32) .. +15.  Each pivot step takes the
-// pivot row and column through cross-lane shuffles; no barriers.  Entries
-// beyond jb are padded with the identity.  On return D holds -D^{-1}.
-__device__ __forceinline__ bool wave_sweep32(double (*D)[SWEEP_NB + 1], int jb, int lane) {
+// Sweeps a 32x32 block (jb <= 32 used entries) held in LDS at D (row i at
+// D + i*ld) by one wave, in registers: lane l keeps column l%32, rows
+// 16*(l/32) .. +15.  Each pivot step takes the pivot row and column through
+// cross-lane shuffles; no barriers.  Entries beyond jb are padded with the
+// identity.  On return the block holds -B^{-1}.  Returns true on a pivot <= 0.
+__device__ __forceinline__ bool wave_sweep32(double* D, int ld, int jb, int lane) {
   const int j = lane & 31, h = lane >> 5;
   double m[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int i = h * 16 + t;
-    m[t] = (i < jb && j < jb) ? D[i][j] : (i == j ? 1.0 : 0.0);
+    m[t] = (i < jb && j < jb) ? D[i * ld + j] : (i == j ? 1.0 : 0.0);
   }
   bool bad = false;
 #pragma unroll
-  for (int q = 0; q < SWEEP_NB; ++q) {
+  for (int q = 0; q < 32; ++q) {
     const int qh = q >> 4, qt = q & 15;
-    const double rowq = __shfl(m[qt], j + 32 * qh, 64);  // D[q][j]
-    double dq = __shfl(m[qt], q + 32 * qh, 64);          // D[q][q]
+    const double rowq = __shfl(m[qt], j + 32 * qh, 64);  // B[q][j]
+    double dq = __shfl(m[qt], q + 32 * qh, 64);          // B[q][q]
     if (!(dq > 0.0)) {
       bad = true;
       dq = 1.0;
@@ -395,7 +405,7 @@ __device__ __forceinline__ bool wave_sweep32(double (*D)[SWEEP_NB + 1], int jb, 
     const double inv = 1.0 / dq;
     double colq[16];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) colq[t] = __shfl(m[t], q + 32 * h, 64);  // D[16h+t][q]
+    for (int t = 0; t < 16; ++t) colq[t] = __shfl(m[t], q + 32 * h, 64);  // B[16h+t][q]
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
       const int i = h * 16 + t;
@@ -408,7 +418,69 @@ __device__ __forceinline__ bool wave_sweep32(double (*D)[SWEEP_NB + 1], int jb, 
     }
   }
 #pragma unroll
-  for (int t = 0; t < 16; ++t) D[h * 16 + t][j] = m[t];
+  for (int t = 0; t < 16; ++t) D[(h * 16 + t) * ld + j] = m[t];
+  return bad;
+}
+
+// Sweeps the full SWEEP_NB x SWEEP_NB pivot block in LDS (entries beyond jb
+// padded with the identity): the first 32 pivots by one wave, the Schur
+// complement of the other 32 by GEMM-like updates over the workgroup, then
+// its 32 pivots by one wave, then the first block's correction.  Sweeping
+// two pivot sets in turn equals sweeping their union.  Every thread of the
+// workgroup must call it.  tmp holds 32 x 33 doubles.
+__device__ bool block_sweep(double (*D)[SWEEP_NB + 1], double (*tmp)[33], int jb, int tid, int nthreads) {
+  constexpr int ld = SWEEP_NB + 1;
+  bool bad = false;
+  if (tid < 64) bad |= wave_sweep32(&D[0][0], ld, min(jb, 32), tid);
+  __syncthreads();
+  if (jb > 32) {
+    // T21 = D21 D11^{-1} = -D21 * (swept D11)
+    for (int idx = tid; idx < 32 * 32; idx += nthreads) {
+      const int i = idx / 32, j = idx % 32;
+      double s = 0.0;
+      for (int k = 0; k < 32; ++k) s -= D[32 + i][k] * D[k][j];
+      tmp[i][j] = s;
+    }
+    __syncthreads();
+    // D22 -= T21 D12 (D12 = D21^T, still unchanged)
+    for (int idx = tid; idx < 32 * 32; idx += nthreads) {
+      const int i = idx / 32, j = idx % 32;
+      double s = 0.0;
+      for (int k = 0; k < 32; ++k) s += tmp[i][k] * D[32 + j][k];
+      D[32 + i][32 + j] -= s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 32 * 32; idx += nthreads) {
+      const int i = idx / 32, j = idx % 32;
+      D[32 + i][j] = tmp[i][j];
+      D[j][32 + i] = tmp[i][j];
+    }
+    __syncthreads();
+    if (tid < 64) bad |= wave_sweep32(&D[32][32], ld, jb - 32, tid);
+    __syncthreads();
+    // U = D12 S^{-1} = -D12 * (swept D22)
+    for (int idx = tid; idx < 32 * 32; idx += nthreads) {
+      const int i = idx / 32, j = idx % 32;
+      double s = 0.0;
+      for (int k = 0; k < 32; ++k) s -= D[i][32 + k] * D[32 + k][32 + j];
+      tmp[i][j] = s;
+    }
+    __syncthreads();
+    // D11 -= U D21
+    for (int idx = tid; idx < 32 * 32; idx += nthreads) {
+      const int i = idx / 32, j = idx % 32;
+      double s = 0.0;
+      for (int k = 0; k < 32; ++k) s += tmp[i][k] * D[32 + k][j];
+      D[i][j] -= s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 32 * 32; idx += nthreads) {
+      const int i = idx / 32, j = idx % 32;
+      D[i][32 + j] = tmp[i][j];
+      D[32 + j][i] = tmp[i][j];
+    }
+    __syncthreads();
+  }
   return bad;
 }
 
@@ -429,6 +501,7 @@ __global__ __launch_bounds__(256) void k_sweep_panel(const SweepDesc* __restrict
                                                      int64_t scr_stride, int* status,
                                                      int status_code) {
   __shared__ double D[1][SWEEP_NB][SWEEP_NB + 1];
+  __shared__ double tmp[32][33];
   extern __shared__ char smem_raw[];
   T(*Cl)[SWEEP_NB + 1] = reinterpret_cast<T(*)[SWEEP_NB + 1]>(smem_raw);  // [chunk rows][NB+1]
   const SweepDesc d = desc[blockIdx.y];
@@ -457,10 +530,10 @@ __global__ __launch_bounds__(256) void k_sweep_panel(const SweepDesc* __restrict
   }
   if (j0 < 0 || j0 >= p) return;
   const int jb = min(SWEEP_NB, p - j0);
-  for (int idx = tid; idx < jb * jb; idx += blockDim.x) {
-    const int i = idx % jb, j = idx / jb;
+  for (int idx = tid; idx < SWEEP_NB * SWEEP_NB; idx += blockDim.x) {
+    const int i = idx % SWEEP_NB, j = idx / SWEEP_NB;
     const int gi = max(i, j), gj = min(i, j);
-    D[0][i][j] = (double)A[(j0 + gi) + (int64_t)ld * (j0 + gj)];
+    D[0][i][j] = (i < jb && j < jb) ? (double)A[(j0 + gi) + (int64_t)ld * (j0 + gj)] : (i == j ? 1.0 : 0.0);
   }
   // stage this chunk's rows of the column panel (rows above the panel from
   // the lower-triangle mirror, previous-panel rows from its scratch slot)
@@ -476,11 +549,7 @@ __global__ __launch_bounds__(256) void k_sweep_panel(const SweepDesc* __restrict
   }
   __syncthreads();
   const int cur = 0;
-  if (tid < 64) {
-    const bool bad = wave_sweep32(D[0], jb, tid);
-    if (bad && tid == 0) atomicMax(status, status_code);
-  }
-  __syncthreads();
+  if (block_sweep(D[0], tmp, jb, tid, blockDim.x)) atomicMax(status, status_code);
   // D[cur] holds -D^{-1}
   T* CD = sweep_slot(scratch, scr_stride, blockIdx.y, j0);
   T* Dinv = CD + (int64_t)n * SWEEP_NB;
@@ -489,18 +558,39 @@ __global__ __launch_bounds__(256) void k_sweep_panel(const SweepDesc* __restrict
       const int i = idx % jb, j = idx / jb;
       Dinv[i + SWEEP_NB * j] = (T)(-D[cur][i][j]);
     }
-  // CD row by row: the row's 32 panel values in registers, D read as broadcasts
-  for (int r = tid; r < rows; r += blockDim.x) {
-    const int i = r0 + r;
-    if (i >= j0 && i < j0 + jb) continue;
-    double c[SWEEP_NB];
+  // CD = C D^{-1} on MFMA: each wave takes 16-row tiles of the chunk and
+  // computes CD^T[q][r] = sum_t Dinv[q][t] C[r][t] (D is symmetric), so the
+  // lanes run along the rows and the stores are coalesced.
+  {
+    typedef typename Mfma<T>::acc_t acc_t;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int kq = lane >> 4, rr = lane & 15;
+    const int rtiles = (rows + 15) / 16;
+    for (int rt = wave; rt < rtiles; rt += blockDim.x >> 6) {
+      constexpr int QB = SWEEP_NB / 16;
+      acc_t acc[QB];
 #pragma unroll
-    for (int t = 0; t < SWEEP_NB; ++t) c[t] = t < jb ? (double)Cl[r][t] : 0.0;
-    for (int q = 0; q < jb; ++q) {
-      double acc = 0.0;
+      for (int qb = 0; qb < QB; ++qb) acc[qb] = acc_t{0, 0, 0, 0};
+      const int r = rt * 16 + rr;
 #pragma unroll
-      for (int t = 0; t < SWEEP_NB; ++t) acc -= c[t] * D[cur][t][q];
-      CD[i + (int64_t)n * q] = (T)acc;
+      for (int ks = 0; ks < SWEEP_NB / 4; ++ks) {
+        const int t = ks * 4 + kq;
+        const T b = (r < rows && t < jb) ? Cl[r][t] : (T)0;
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+          const int q = qb * 16 + rr;
+          const T a = (q < jb && t < jb) ? (T)(-D[cur][q][t]) : (T)0;
+          acc[qb] = Mfma<T>::mac(a, b, acc[qb]);
+        }
+      }
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int q = qb * 16 + Mfma<T>::row(kq, e);
+          const int i = r0 + rt * 16 + rr;
+          if (q < jb && rt * 16 + rr < rows && !(i >= j0 && i < j0 + jb)) CD[i + (int64_t)n * q] = acc[qb][e];
+        }
     }
   }
 }
@@ -513,16 +603,21 @@ __global__ __launch_bounds__(256) void k_sweep_panel(const SweepDesc* __restrict
 template <typename T>
 __global__ __launch_bounds__(256) void k_sweep_update(const SweepDesc* __restrict__ desc, T* pool,
                                                       int j0, const T* __restrict__ scratch,
-                                                      int64_t scr_stride) {
+                                                      int64_t scr_stride, int ntri, int nprob) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T As[SWEEP_NB][TILE + PAD];  // CD rows i
   __shared__ T Bs[SWEEP_NB][TILE + PAD];  // C rows j
-  const SweepDesc d = desc[blockIdx.y];
+  const int64_t nblk = gridDim.x;
+  const int64_t glin = blockIdx.x;
+  const int64_t logical = (glin % 8) * (nblk / 8) + glin / 8;  // XCD-aware, as in k_gemm
+  if (logical >= (int64_t)nprob * ntri) return;
+  const int prob = (int)(logical / ntri);
+  const SweepDesc d = desc[prob];
   const int n = d.n, p = d.p, ld = d.ld;
   if (j0 >= p) return;
   const int jb = min(SWEEP_NB, p - j0);
   // linear index -> lower-triangular tile (ti >= tj)
-  const int lin = blockIdx.x;
+  const int lin = (int)(logical % ntri);
   int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
   while ((ti + 1) * (ti + 2) / 2 <= lin) ++ti;
   while (ti * (ti + 1) / 2 > lin) --ti;
@@ -530,7 +625,7 @@ __global__ __launch_bounds__(256) void k_sweep_update(const SweepDesc* __restric
   const int i0 = ti * TILE, c0 = tj * TILE;
   if (i0 >= n || c0 >= n) return;
   T* A = pool + d.off;
-  const T* CD = sweep_slot(const_cast<T*>(scratch), scr_stride, blockIdx.y, j0);
+  const T* CD = sweep_slot(const_cast<T*>(scratch), scr_stride, prob, j0);
   const int tid = threadIdx.x;
   for (int idx = tid; idx < TILE * SWEEP_NB; idx += 256) {
     const int r = idx % TILE, q = idx / TILE;
@@ -591,17 +686,33 @@ __global__ __launch_bounds__(256) void k_sweep_update(const SweepDesc* __restric
       }
 }
 
-// Mirrors the lower triangle into the upper one after a sweep.
+// Mirrors the lower triangle into the upper one after a sweep, by 32x32
+// tiles through LDS so both the read and the write run along columns.
 template <typename T>
-__global__ void k_symmetrize(const SweepDesc* __restrict__ desc, T* pool) {
+__global__ void k_symmetrize(const SweepDesc* __restrict__ desc, T* pool, int ntri) {
+  __shared__ T tile[32][33];
   const SweepDesc d = desc[blockIdx.y];
   T* A = pool + d.off;
-  const int64_t tot = (int64_t)d.n * d.n;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(idx % d.n), j = (int)(idx / d.n);
-    if (i < j) A[i + (int64_t)d.ld * j] = A[j + (int64_t)d.ld * i];
+  const int nt = (d.n + 31) / 32;
+  for (int lin = blockIdx.x; lin < nt * (nt + 1) / 2; lin += gridDim.x) {
+    int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= lin) ++ti;
+    while (ti * (ti + 1) / 2 > lin) --ti;
+    const int tj = lin - ti * (ti + 1) / 2;  // tile (ti, tj) of the lower triangle, ti >= tj
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 32 * 32; idx += blockDim.x) {
+      const int r = idx % 32, c = idx / 32;
+      const int i = ti * 32 + r, j = tj * 32 + c;
+      tile[c][r] = (i < d.n && j < d.n) ? A[i + (int64_t)d.ld * j] : (T)0;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 32 * 32; idx += blockDim.x) {
+      const int r = idx % 32, c = idx / 32;   // upper entry (tj*32 + r, ti*32 + c) = lower (ti*32 + c, tj*32 + r)
+      const int i = tj * 32 + r, j = ti * 32 + c;
+      if (i < d.n && j < d.n && i < j) A[i + (int64_t)d.ld * j] = tile[r][c];
+    }
   }
+  (void)ntri;
 }
 
 // ---------------------------------------------------------------------------
@@ -616,12 +727,22 @@ constexpr int GBK = 32;  // K chunk of the batched GEMM
 template <typename T, int TA, int TB>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
                                               const T* __restrict__ Ap, const T* __restrict__ Bp,
-                                              T* __restrict__ Cp, T alpha, T beta, int tiles_m) {
+                                              T* __restrict__ Cp, T alpha, T beta, int tiles_m, int tiles_n,
+                                              int nprob) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[2][GBK][TILE + PAD];
-  __shared__ T Bs[2][GBK][TILE + PAD];
-  const GemmDesc d = desc[blockIdx.y];
-  const int ti = blockIdx.x % tiles_m, tj = blockIdx.x / tiles_m;
+  __shared__ T As[1][GBK][TILE + PAD];
+  __shared__ T Bs[1][GBK][TILE + PAD];
+  // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
+  // so consecutive logical tiles (one problem's) are given to one XCD and
+  // share its L2.
+  const int64_t nblk = gridDim.x;
+  const int64_t lin = blockIdx.x;
+  const int64_t logical = (lin % 8) * (nblk / 8) + lin / 8;
+  const int tiles = tiles_m * tiles_n;
+  if (logical >= (int64_t)nprob * tiles) return;
+  const int prob = (int)(logical / tiles), tile = (int)(logical % tiles);
+  const GemmDesc d = desc[prob];
+  const int ti = tile % tiles_m, tj = tile / tiles_m;
   const int m0 = ti * TILE, n0 = tj * TILE;
   if (m0 >= d.m || n0 >= d.n) return;
   const T* A = Ap + d.a;
@@ -699,10 +820,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
   load(0);
   store(0);
   __syncthreads();
-  int cur = 0;
+  const int cur = 0;
   for (int k0 = 0; k0 < d.k; k0 += GBK) {
     const bool more = k0 + GBK < d.k;
-    if (more) load(k0 + GBK);
+    if (more) load(k0 + GBK);  // next chunk in flight while this one is multiplied
 #pragma unroll
     for (int ks = 0; ks < GBK / 4; ++ks) {
       const int kk = ks * 4 + kq;
@@ -716,9 +837,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(bv[b], av[a], acc[a][b]);
     }
-    if (more) store(cur ^ 1);
     __syncthreads();
-    cur ^= 1;
+    if (more) store(0);
+    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -772,38 +893,56 @@ __global__ void k_rhs_fill(PlanDev P, Geo g, const double* __restrict__ rho, T* 
 
 // fwd (fwd = 1): Z[first plane of block k, :] -= A_{k,k-1} Z[last plane of k-1, :]
 // bwd (fwd = 0): tmp[0:last_n, :] = A_{k,k+1} Z[first plane of k+1, :]
+// One workgroup per (column chunk of CPL_COLS, subdomain): the source plane's
+// rows of the chunk are staged in LDS once, then every output row takes its
+// (up to) 9 neighbours from LDS.
+constexpr int CPL_COLS = 16;
+
 template <typename T>
-__global__ void k_couple_multi(PlanDev P, int k, int fwd, T* __restrict__ Z, T* __restrict__ tmp,
-                               int64_t tmp_stride) {
+__global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd, T* __restrict__ Z,
+                                                      T* __restrict__ tmp, int64_t tmp_stride) {
+  extern __shared__ char smem_raw[];
+  T(*src)[CPL_COLS + 1] = reinterpret_cast<T(*)[CPL_COLS + 1]>(smem_raw);
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int nb = S.nbR;
   const int ncols = S.n_a + S.n_v;
   if (fwd ? (k >= nb || k == 0) : (k + 1 >= nb)) return;
+  const int c0 = blockIdx.x * CPL_COLS;
+  if (c0 >= ncols) return;
+  const int nc = min(CPL_COLS, ncols - c0);
   const BlockDev B = P.blocks[S.bR_off + k];
   const int64_t roff = fwd ? B.cf_off : B.cb_off;
   if (roff < 0) return;
-  const int rows = fwd ? B.first_n : B.last_n;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows) return;
-  const int rowrank = fwd ? B.start + i : B.start + B.size - B.last_n + i;
-  const int64_t row = roff + i;
-  double a[9];
-  int nbr[9];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    nbr[t] = P.cpl_rank[row * 9 + t];
-    a[t] = nbr[t] >= 0 ? P.cpl_coef[row * 9 + t] : 0.0;
-    if (nbr[t] < 0) nbr[t] = 0;
-  }
+  const BlockDev O = P.blocks[S.bR_off + (fwd ? k - 1 : k + 1)];
+  const int sbase = fwd ? O.start + O.size - O.last_n : O.start;  // first rank of the source plane
+  const int sn = fwd ? O.last_n : O.first_n;
   T* z = Z + S.Z_off;
+  for (int idx = threadIdx.x; idx < sn * nc; idx += blockDim.x) {
+    const int r = idx % sn, c = idx / sn;
+    src[r][c] = z[sbase + r + (int64_t)S.n_r * (c0 + c)];
+  }
+  __syncthreads();
+  const int rows = fwd ? B.first_n : B.last_n;
+  const int rowbase = fwd ? B.start : B.start + B.size - B.last_n;
   T* tp = tmp + sub * tmp_stride;
-  for (int c = blockIdx.z; c < ncols; c += gridDim.z) {
-    double acc = 0.0;
+  for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+    const int64_t row = roff + i;
+    double a[9];
+    int l[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) acc += a[t] * (double)z[nbr[t] + (int64_t)S.n_r * c];
-    if (fwd) z[rowrank + (int64_t)S.n_r * c] -= (T)acc;
-    else tp[i + (int64_t)B.last_n * c] = (T)acc;
+    for (int t = 0; t < 9; ++t) {
+      const int rk = P.cpl_rank[row * 9 + t];
+      a[t] = rk >= 0 ? P.cpl_coef[row * 9 + t] : 0.0;
+      l[t] = rk >= 0 ? rk - sbase : 0;
+    }
+    for (int c = 0; c < nc; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) acc += a[t] * (double)src[l[t]][c];
+      if (fwd) z[rowbase + i + (int64_t)S.n_r * (c0 + c)] -= (T)acc;
+      else tp[i + (int64_t)B.last_n * (c0 + c)] = (T)acc;
+    }
   }
 }
 
@@ -877,44 +1016,64 @@ __global__ void k_phi_r_init(PlanDev P, const T* __restrict__ Z, T* __restrict__
 // C_r Phi_r = [0 I], (K Phi)_r = -C_r^T Lambda, so Phi^T K Phi has the rows
 // (K Phi)_v at vertex dofs and -Lambda at average dofs.  The two triangles
 // are averaged so the result is symmetric to the last bit.
-template <typename T>
-__device__ __forceinline__ double kc_entry(const PlanDev& P, const SubDev& S, const Geo& g,
-                                           const double* __restrict__ rho, const T* __restrict__ PhiR,
-                                           const T* __restrict__ Lam, int c, int c2) {
-  const int kind = P.c_kind[S.c_off + c];
-  if (kind < 0) return -(double)Lam[S.T_off + (-kind - 1) + (int64_t)S.n_a * c2];
-  const int lv = P.v_loc[S.v_off + kind];
+// Stencil rows of the primal vertices: for vertex v of a subdomain and its
+// 27 neighbour offsets, the coefficient K[v, j] and a code: the r rank of j,
+// or -(c+1) when j is the vertex of local coarse dof c, or INT32_MIN when j
+// is not a local node.  Filled once per setup.
+__global__ void k_vertex_stencil(PlanDev P, Geo g, const double* __restrict__ rho, int64_t* __restrict__ vcode_unused,
+                                 double* __restrict__ vcoef, int32_t* __restrict__ vcode) {
+  (void)vcode_unused;
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= S.n_v * 27) return;
+  const int v = idx / 27, t = idx % 27;
+  const int lv = P.v_loc[S.v_off + v];
   int cv[3];
   loc_coords(S, lv, cv);
-  const int32_t* lr = P.loc_r + S.loc_off;
-  const int32_t* lg = P.loc_g + S.loc_off;
-  const int zr = g.dim == 3 ? 1 : 0;
+  const int dz = g.dim == 3 ? t / 9 - 1 : 0, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+  int cn[3] = {cv[0] + dx, cv[1] + dy, cv[2] + dz};
+  const int64_t out = (S.v_off + v) * 27 + t;
+  const int ln = (g.dim == 2 && t >= 9) ? -1 : loc_index(S, cn);
+  if (ln < 0) {
+    vcode[out] = INT32_MIN;
+    vcoef[out] = 0.0;
+    return;
+  }
+  const int r = P.loc_r[S.loc_off + ln];
+  vcode[out] = r >= 0 ? r : -(P.v_c[S.v_off + P.g_v[S.g_off + P.loc_g[S.loc_off + ln]]] + 1);
+  vcoef[out] = kloc(S, g, rho, P.khat, cv, cn);
+}
+
+template <typename T>
+__device__ __forceinline__ double kc_entry(const PlanDev& P, const SubDev& S, const T* __restrict__ PhiR,
+                                           const T* __restrict__ Lam, const double* __restrict__ vcoef,
+                                           const int32_t* __restrict__ vcode, int c, int c2) {
+  const int kind = P.c_kind[S.c_off + c];
+  if (kind < 0) return -(double)Lam[S.T_off + (-kind - 1) + (int64_t)S.n_a * c2];
+  const int64_t base = (S.v_off + kind) * 27;
   double acc = 0.0;
-  for (int dz = -zr; dz <= zr; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        int cn[3] = {cv[0] + dx, cv[1] + dy, cv[2] + dz};
-        int ln = loc_index(S, cn);
-        if (ln < 0) continue;
-        double phi;
-        const int r = lr[ln];
-        if (r >= 0) phi = (double)PhiR[S.Phi_off + r + (int64_t)S.n_r * c2];
-        else phi = P.v_c[S.v_off + P.g_v[S.g_off + lg[ln]]] == c2 ? 1.0 : 0.0;
-        if (phi != 0.0) acc += kloc(S, g, rho, P.khat, cv, cn) * phi;
-      }
+  for (int t = 0; t < 27; ++t) {
+    const int code = vcode[base + t];
+    if (code == INT32_MIN) continue;
+    const double phi = code >= 0 ? (double)PhiR[S.Phi_off + code + (int64_t)S.n_r * c2] : (-code - 1 == c2 ? 1.0 : 0.0);
+    acc += vcoef[base + t] * phi;
+  }
   return acc;
 }
 
 template <typename T>
-__global__ void k_kc_identity(PlanDev P, Geo g, const double* __restrict__ rho, const T* __restrict__ PhiR,
-                              const T* __restrict__ Lam, T* __restrict__ Kc) {
+__global__ void k_kc_identity(PlanDev P, const T* __restrict__ PhiR, const T* __restrict__ Lam,
+                              const double* __restrict__ vcoef, const int32_t* __restrict__ vcode,
+                              T* __restrict__ Kc) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= S.n_c * S.n_c) return;
   const int c = idx % S.n_c, c2 = idx / S.n_c;
   if (c2 < c) return;
-  const double v = 0.5 * (kc_entry(P, S, g, rho, PhiR, Lam, c, c2) + kc_entry(P, S, g, rho, PhiR, Lam, c2, c));
+  const double v = 0.5 * (kc_entry(P, S, PhiR, Lam, vcoef, vcode, c, c2) +
+                          kc_entry(P, S, PhiR, Lam, vcoef, vcode, c2, c));
   Kc[S.Kc_off + c + (int64_t)S.n_c * c2] = (T)v;
   Kc[S.Kc_off + c2 + (int64_t)S.n_c * c] = (T)v;
 }
@@ -1157,20 +1316,25 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// bci = Phi_Gamma^T g_Gamma, one workgroup per (subdomain, rhs), one wave per column.
+// bci = Phi_Gamma^T g_Gamma: one workgroup per (column chunk, subdomain,
+// rhs), one wave per column.
+constexpr int CRL_COLS = 16;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_rhs_local(PlanDev P, const T* __restrict__ PhiG,
                                                           const T* __restrict__ gv, T* __restrict__ bci) {
   extern __shared__ char smem_raw[];
   T* gl = reinterpret_cast<T*>(smem_raw);
-  const int sub = blockIdx.x, rhs = blockIdx.y;
+  const int sub = blockIdx.y, rhs = blockIdx.z;
   const SubDev S = P.subs[sub];
+  const int cb = blockIdx.x * CRL_COLS;
+  if (cb >= S.n_c) return;
   const T* g = gv + rhs * P.tot_g + S.g_off;
   for (int e = threadIdx.x; e < S.n_g; e += blockDim.x) gl[e] = g[e];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const T* M = PhiG + S.PhiG_off;
-  for (int c = wave; c < S.n_c; c += blockDim.x >> 6) {
+  for (int c = cb + wave; c < min(S.n_c, cb + CRL_COLS); c += blockDim.x >> 6) {
     double acc = 0.0;
     for (int e = lane; e < S.n_g; e += 64) acc += (double)(M[e + (int64_t)S.n_g * c] * gl[e]);
     acc = wave_sum(acc);
@@ -1178,31 +1342,33 @@ __global__ __launch_bounds__(256) void k_coarse_rhs_local(PlanDev P, const T* __
   }
 }
 
-// v2 on Gamma = u - X mu + Phi_Gamma u_c (v_Delta plus the coarse correction).
+// v2 on Gamma = u - X mu + Phi_Gamma u_c (v_Delta plus the coarse
+// correction): one workgroup per (chunk of 256 Gamma rows, subdomain, rhs).
 template <typename T>
 __global__ __launch_bounds__(256) void k_v2(PlanDev P, const T* __restrict__ vR, const T* __restrict__ XG,
                                             const T* __restrict__ mu, const T* __restrict__ PhiG,
                                             const double* __restrict__ uc, T* __restrict__ v2) {
   extern __shared__ char smem_raw[];
   T* sh = reinterpret_cast<T*>(smem_raw);
-  const int sub = blockIdx.x, rhs = blockIdx.y;
+  const int sub = blockIdx.y, rhs = blockIdx.z;
   const SubDev S = P.subs[sub];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int)(blockIdx.x * blockDim.x) >= S.n_g) return;
   T* mul = sh;
   T* ucl = sh + S.n_a;
   for (int a = threadIdx.x; a < S.n_a; a += blockDim.x) mul[a] = mu[rhs * P.tot_a + S.am_off + a];
   for (int c = threadIdx.x; c < S.n_c; c += blockDim.x)
     ucl[c] = (T)uc[rhs * P.n_coarse + P.c_glob[S.c_off + c]];
   __syncthreads();
+  if (e >= S.n_g) return;
   const T* u = vR + rhs * P.tot_r + S.r_off;
   const T* X = XG + S.XG_off;
   const T* F = PhiG + S.PhiG_off;
-  for (int e = threadIdx.x; e < S.n_g; e += blockDim.x) {
-    const int r = P.g_r[S.g_off + e];
-    T acc = r >= 0 ? u[r] : (T)0;
-    for (int a = 0; a < S.n_a; ++a) acc -= X[e + (int64_t)S.n_g * a] * mul[a];
-    for (int c = 0; c < S.n_c; ++c) acc += F[e + (int64_t)S.n_g * c] * ucl[c];
-    v2[rhs * P.tot_g + S.g_off + e] = acc;
-  }
+  const int r = P.g_r[S.g_off + e];
+  T acc = r >= 0 ? u[r] : (T)0;
+  for (int a = 0; a < S.n_a; ++a) acc -= X[e + (int64_t)S.n_g * a] * mul[a];
+  for (int c = 0; c < S.n_c; ++c) acc += F[e + (int64_t)S.n_g * c] * ucl[c];
+  v2[rhs * P.tot_g + S.g_off + e] = acc;
 }
 
 // Interior right-hand side of the second Dirichlet solve: r_I - K_{I Gamma} w.
@@ -1480,6 +1646,10 @@ void launch_kc_to_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_f32_to_f64<<<hmin(cdiv(n, 256), 65536), 256, 0, s>>>(src, dst, n);
 }
+void launch_copy16(const void* a, void* b, int64_t n16, hipStream_t s) {
+  if (n16 <= 0) return;
+  k_copy16<<<hmin(cdiv(n16, 256), 65536), 256, 0, s>>>((const int4*)a, (int4*)b, n16);
+}
 void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_sub<<<hmin(cdiv(n, 256), 65536), 256, 0, s>>>(a, b, out, n);
@@ -1523,33 +1693,61 @@ void Kern<T>::schur_couple(const PlanDev& P, const Geo& g, const double* rho, in
 }
 
 template <typename T>
-void Kern<T>::sweep(SweepDesc* d_desc, int nprob, int maxn, int maxp, T* pool, T* scratch,
-                    int64_t scr_stride, int* status, int status_code, hipStream_t s) {
+void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int maxn, int maxp, T* pool,
+                    T* scratch, int64_t scr_stride, int* status, int status_code, hipStream_t s,
+                    Profiler* prof) {
   if (nprob == 0 || maxp == 0) return;
   const int64_t tiles = cdiv(maxn, TILE);
   const dim3 pgrid(cdiv(maxn, SWEEP_ROWS), nprob);
   const size_t psm = (size_t)hmin(maxn, SWEEP_ROWS) * (SWEEP_NB + 1) * sizeof(T);
   int prev = -1;
   for (int j0 = 0; j0 < maxp; j0 += SWEEP_NB) {
+    double pf = 0, pby = 0, uf = 0, uby = 0;
+    if (prof && h_desc)
+      for (int q = 0; q < nprob; ++q) {
+        const double n = h_desc[q].n, p = h_desc[q].p;
+        if (j0 >= p) continue;
+        const double jb = std::min<double>(SWEEP_NB, p - j0), m = n - jb;
+        const double low = m * (m + 1) / 2;  // lower-triangle entries outside the panel
+        pf += 2.0 * m * jb * jb;
+        pby += sizeof(T) * (2.0 * m * jb + jb * jb);
+        uf += 2.0 * jb * low;
+        uby += sizeof(T) * (2.0 * low + 2.0 * n * jb);
+      }
+    if (prof) prof->begin(4, s);
     k_sweep_panel<T><<<pgrid, 256, psm, s>>>(d_desc, pool, j0, prev, scratch, scr_stride, status, status_code);
-    k_sweep_update<T><<<dim3((unsigned)(tiles * (tiles + 1) / 2), nprob), 256, 0, s>>>(d_desc, pool, j0, scratch,
-                                                                                      scr_stride);
+    if (prof) prof->end(4, pf, pby, s);
+    if (prof) prof->begin(1, s);
+    const int64_t ntri = tiles * (tiles + 1) / 2;
+    k_sweep_update<T><<<(unsigned)((ntri * nprob + 7) / 8 * 8), 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride,
+                                                                            (int)ntri, nprob);
+    if (prof) prof->end(1, uf, uby, s);
     prev = j0;
   }
   k_sweep_panel<T><<<pgrid, 256, psm, s>>>(d_desc, pool, -1, prev, scratch, scr_stride, status, status_code);
-  k_symmetrize<T><<<dim3((unsigned)hmin(cdiv((int64_t)maxn * maxn, 256), 4096), nprob), 256, 0, s>>>(d_desc, pool);
+  const int64_t st = cdiv(maxn, 32);
+  k_symmetrize<T><<<dim3((unsigned)hmin(st * (st + 1) / 2, 4096), nprob), 256, 0, s>>>(d_desc, pool, 0);
 }
 
 template <typename T>
-void Kern<T>::gemm(const GemmDesc* d_desc, int nprob, int maxm, int maxn, const T* A, int transA,
-                   const T* B, int transB, T* C, T alpha, T beta, hipStream_t s) {
+void Kern<T>::gemm(const GemmDesc* d_desc, const GemmDesc* h_desc, int nprob, int maxm, int maxn, const T* A,
+                   int transA, const T* B, int transB, T* C, T alpha, T beta, hipStream_t s, Profiler* prof) {
   if (nprob == 0 || maxm == 0 || maxn == 0) return;
   int tm = (int)cdiv(maxm, TILE), tn = (int)cdiv(maxn, TILE);
-  dim3 grid(tm * tn, nprob);
-  if (!transA && !transB) k_gemm<T, 0, 0><<<grid, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm);
-  else if (transA && !transB) k_gemm<T, 1, 0><<<grid, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm);
-  else if (!transA && transB) k_gemm<T, 0, 1><<<grid, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm);
-  else k_gemm<T, 1, 1><<<grid, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm);
+  double f = 0, by = 0;
+  if (prof && h_desc)
+    for (int q = 0; q < nprob; ++q) {
+      const double m = h_desc[q].m, n = h_desc[q].n, kk = h_desc[q].k;
+      f += 2.0 * m * n * kk;
+      by += sizeof(T) * (m * kk + kk * n + m * n * (beta == (T)0 ? 1.0 : 2.0));
+    }
+  const unsigned nb = (unsigned)(((int64_t)tm * tn * nprob + 7) / 8 * 8);
+  if (prof) prof->begin(3, s);
+  if (!transA && !transB) k_gemm<T, 0, 0><<<nb, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm, tn, nprob);
+  else if (transA && !transB) k_gemm<T, 1, 0><<<nb, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm, tn, nprob);
+  else if (!transA && transB) k_gemm<T, 0, 1><<<nb, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm, tn, nprob);
+  else k_gemm<T, 1, 1><<<nb, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm, tn, nprob);
+  if (prof) prof->end(3, f, by, s);
 }
 
 template <typename T>
@@ -1561,11 +1759,11 @@ void Kern<T>::rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, 
 template <typename T>
 void Kern<T>::couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
                            int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s) {
-  if (ncols_max == 0) return;
-  int zc = hmin(ncols_max, 16);
   (void)g;
   (void)rho;
-  k_couple_multi<T><<<dim3(cdiv(P.max_plane, 64), P.n_sub, zc), 64, 0, s>>>(P, k, fwd, Z, tmp, tmp_stride);
+  if (ncols_max == 0) return;
+  const size_t sm = (size_t)hmax(P.max_plane, 1) * (CPL_COLS + 1) * sizeof(T);
+  k_couple_multi<T><<<dim3(cdiv(ncols_max, CPL_COLS), P.n_sub), 256, sm, s>>>(P, k, fwd, Z, tmp, tmp_stride);
 }
 
 template <typename T>
@@ -1597,9 +1795,12 @@ void Kern<T>::phi_r_init(const PlanDev& P, const T* Z, T* PhiR, hipStream_t s) {
 
 template <typename T>
 void Kern<T>::kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PhiR, const T* Lam, T* Kc,
-                          hipStream_t s) {
+                          double* vcoef, int32_t* vcode, int max_nv, hipStream_t s) {
   if (P.max_nc == 0) return;
-  k_kc_identity<T><<<dim3(cdiv((int64_t)P.max_nc * P.max_nc, 256), P.n_sub), 256, 0, s>>>(P, g, rho, PhiR, Lam, Kc);
+  if (max_nv > 0)
+    k_vertex_stencil<<<dim3(cdiv((int64_t)max_nv * 27, 256), P.n_sub), 256, 0, s>>>(P, g, rho, nullptr, vcoef, vcode);
+  k_kc_identity<T><<<dim3(cdiv((int64_t)P.max_nc * P.max_nc, 256), P.n_sub), 256, 0, s>>>(P, PhiR, Lam, vcoef,
+                                                                                          vcode, Kc);
 }
 
 template <typename T>
@@ -1624,9 +1825,12 @@ void Kern<T>::gather_I(const PlanDev& P, const Geo& g, const double* r, T* vI, i
 
 template <typename T>
 void Kern<T>::block_solve(const PlanDev& P, const Geo& g, const double* rho, int setR, const T* G,
-                          T* v, int nrhs, hipStream_t s) {
+                          T* v, int nrhs, hipStream_t s, Profiler* prof, double g_entries, double vec_entries) {
   size_t sm = (size_t)(hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * sizeof(T);
+  if (prof) prof->begin(2, s);
   k_block_solve<T><<<dim3(P.n_sub, nrhs), BS_THREADS, sm, s>>>(P, g, rho, setR, G, v);
+  // each G entry streamed once per rhs (2 flops), the vector read and written once
+  if (prof) prof->end(2, 2.0 * g_entries * nrhs, sizeof(T) * (g_entries + 2.0 * vec_entries) * nrhs, s);
 }
 
 template <typename T>
@@ -1658,7 +1862,8 @@ void Kern<T>::mu(const PlanDev& P, const T* vR, const T* Sc, T* mu_out, int nrhs
 template <typename T>
 void Kern<T>::coarse_rhs_local(const PlanDev& P, const T* PhiG, const T* gv, T* bci, int nrhs, hipStream_t s) {
   if (P.max_nc == 0) return;
-  k_coarse_rhs_local<T><<<dim3(P.n_sub, nrhs), 256, (size_t)hmax(P.max_ng, 1) * sizeof(T), s>>>(P, PhiG, gv, bci);
+  k_coarse_rhs_local<T><<<dim3(cdiv(P.max_nc, CRL_COLS), P.n_sub, nrhs), 256, (size_t)hmax(P.max_ng, 1) * sizeof(T), s>>>(
+      P, PhiG, gv, bci);
 }
 
 template <typename T>
@@ -1666,7 +1871,7 @@ void Kern<T>::v2(const PlanDev& P, const T* vR, const T* XG, const T* mu_in, con
                  T* v2_out, int nrhs, hipStream_t s) {
   if (P.max_ng == 0) return;
   size_t sm = (size_t)(P.max_na + P.max_nc + 1) * sizeof(T);
-  k_v2<T><<<dim3(P.n_sub, nrhs), 256, sm, s>>>(P, vR, XG, mu_in, PhiG, uc, v2_out);
+  k_v2<T><<<dim3(cdiv(P.max_ng, 256), P.n_sub, nrhs), 256, sm, s>>>(P, vR, XG, mu_in, PhiG, uc, v2_out);
 }
 
 template <typename T>

@@ -30,6 +30,14 @@ def _f64_cuda(t: torch.Tensor, name: str) -> torch.Tensor:
     return t
 
 
+def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """Streaming copy of src into dst (same byte size) by the library's copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst sizes differ")
+    B.check(B.load().bddcso_copy_probe(_ptr(src), _ptr(dst), nbytes, _stream(stream)))
+
+
 def default_options(**kw) -> B.Options:
     o = B.Options()
     B.load().bddcso_default_options(C.byref(o))
@@ -76,6 +84,12 @@ class Problem:
     @property
     def n_free(self) -> int:
         return self.info()["n_free"]
+
+    def plan_stats(self, options: Optional[B.Options] = None, **kw) -> dict:
+        o = options if options is not None else default_options(**kw)
+        st = B.PlanStats()
+        B.check(B.load().bddcso_plan_info(self._h, C.byref(o), C.byref(st)))
+        return {name: getattr(st, name) for name, _ in B.PlanStats._fields_}
 
     def box_filter(self, x: torch.Tensor, transpose: bool = False, stream=None) -> torch.Tensor:
         _f64_cuda(x, "x")
@@ -157,6 +171,24 @@ class Preconditioner:
         B.check(B.load().bddcso_precond_info(self._h, C.byref(nc), C.byref(nf), C.byref(nb), C.byref(ce)))
         return {"n_coarse": nc.value, "n_fronts": nf.value, "device_bytes": nb.value,
                 "coarse_factor_entries": ce.value}
+
+    KERNEL_CLASSES = {"sweep_update": 1, "block_solve": 2, "gemm": 3, "sweep_panel": 4}
+
+    def profile(self, classes=None) -> None:
+        """Start event timing of the named kernel classes (all when None); [] stops it."""
+        names = list(self.KERNEL_CLASSES) if classes is None else list(classes)
+        mask = 0
+        for c in names:
+            mask |= 1 << self.KERNEL_CLASSES[c]
+        B.check(B.load().bddcso_profile(self._h, mask))
+
+    def profile_read(self) -> dict:
+        out = {}
+        for name, c in self.KERNEL_CLASSES.items():
+            n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+            B.check(B.load().bddcso_profile_read(self._h, c, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)))
+            out[name] = {"launches": n.value, "total_ms": ms.value, "flops": fl.value, "bytes": by.value}
+        return out
 
     def local_coarse(self, sub: int, cap: int = 4096, stream=None):
         kc = np.zeros(cap * cap)

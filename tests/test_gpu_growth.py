@@ -1,0 +1,158 @@
+"""GPU tests of the growth rows against the oracle: FP32 local factors with a
+flexible FP64 outer CG, the adjoint gradient (element kernel, box filter,
+autograd through the solve, finite differences), and several right-hand
+sides in one solve."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint, bddc, pcg, q1
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def pk():
+    import paper_2001_07289_amd as m
+    return m
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+MIXED_CASES = {
+    "cfg1": W.config1(),
+    "3d_rho": W.config2_like(n=24, H=6, L=3, cfg=51),
+    "3d_L2": W.config2_like(n=24, H=6, L=2, cfg=52),
+}
+
+
+@pytest.mark.parametrize("name", list(MIXED_CASES))
+def test_mixed_preconditioner_close_to_fp64(name):
+    """FP32 locals change B by about the FP32 unit roundoff times the local
+    condition numbers; the coarse problem stays FP64."""
+    p = MIXED_CASES[name]
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    pc = m.Preconditioner(prob, dev(p.rho), precision=1)
+    orc = bddc.from_problem(p)
+    r = W.rng(61, 0).standard_normal(p.n_free)
+    assert relerr(host(pc.apply(dev(r))), orc.apply(r)) <= 2e-4
+
+
+@pytest.mark.parametrize("name", list(MIXED_CASES))
+def test_mixed_solve_reaches_fp64_residual(name):
+    """Flexible FP64 CG around the FP32 preconditioner reaches rtol 1e-8 in
+    the true residual; the solution agrees with the oracle's FP64 solve to
+    the accuracy the tolerance allows."""
+    p = MIXED_CASES[name]
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    pc = m.Preconditioner(prob, dev(p.rho), precision=1)
+    x, st = pc.solve(dev(p.f[0]))
+    orc = bddc.from_problem(p)
+    ref = pcg.solve(orc, p.f[0], rtol=1e-8)
+    A = q1.assemble(p.n_el, p.h, p.rho)
+    xr = host(x)
+    assert np.linalg.norm(p.f[0] - A @ xr) <= 1.0001e-8 * np.linalg.norm(p.f[0])
+    assert st["iters"][0] <= ref.iters + 3
+    assert relerr(xr, ref.x) <= 1e-6
+
+
+def adj_problem():
+    return W.config5_like(n=16, H=4, L=2, cfg=53, name="adj16")
+
+
+def test_box_filter_matches_oracle():
+    p = adj_problem()
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    th = p.extra["theta"]
+    out = host(prob.box_filter(dev(th)))
+    assert np.abs(out - adjoint.box_filter(th, p.n_el)).max() <= 1e-14
+    outT = host(prob.box_filter(dev(th), transpose=True))
+    assert np.abs(outT - adjoint.box_filter_T(th, p.n_el)).max() <= 1e-14
+
+
+def test_element_grad_matches_oracle():
+    p = adj_problem()
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    rng = W.rng(54, 0)
+    rho = rng.uniform(0.5, 2.0, p.n_elements)
+    pc = m.Preconditioner(prob, dev(rho))
+    u, lam = rng.standard_normal(p.n_free), rng.standard_normal(p.n_free)
+    g = host(pc.element_grad(dev(u), dev(lam)))
+    ref = rho * adjoint.element_grad(p.n_el, p.h, u, lam)
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_adjoint_gradient_matches_oracle(precision):
+    """dL/dtheta through BDDCSOSolve (forward solve, adjoint solve with the
+    same preconditioner, element kernel, filter transpose) against the
+    oracle's direct-solve gradient."""
+    p = adj_problem()
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    theta = p.extra["theta"]
+    rho_obs = adjoint.rho_of_theta(p.extra["theta_obs"], p.n_el)
+    u_obs, _ = adjoint.direct_solve(p.n_el, p.h, rho_obs, p.f[0])
+    pc = m.Preconditioner(prob, dev(np.ones(p.n_elements)), rtol=1e-12, precision=precision)
+    th = dev(theta).requires_grad_(True)
+    u = m.BDDCSOSolve.apply(th, dev(p.f[0]), pc)
+    loss = 0.5 * torch.sum((u - dev(u_obs)) ** 2)
+    loss.backward()
+    L_ref, g_ref, _ = adjoint.loss_and_grad(theta, p.n_el, p.h, p.f[0], u_obs)
+    assert abs(float(loss) - L_ref) <= 1e-9 * abs(L_ref)
+    assert relerr(host(th.grad), g_ref) <= 1e-8
+
+
+def test_adjoint_gradient_central_differences():
+    p = adj_problem()
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    theta = p.extra["theta"]
+    rho_obs = adjoint.rho_of_theta(p.extra["theta_obs"], p.n_el)
+    u_obs = dev(adjoint.direct_solve(p.n_el, p.h, rho_obs, p.f[0])[0])
+    f = dev(p.f[0])
+    pc = m.Preconditioner(prob, dev(np.ones(p.n_elements)), rtol=1e-12)
+
+    def L(t):
+        u = m.BDDCSOSolve.apply(t, f, pc)
+        return 0.5 * torch.sum((u - u_obs) ** 2)
+
+    th = dev(theta).requires_grad_(True)
+    L(th).backward()
+    g = host(th.grad)
+    for d in W.fd_directions(53, 4, p.n_elements):
+        eps = 1e-5
+        dd = dev(d)
+        with torch.no_grad():
+            fd = (float(L(dev(theta) + eps * dd)) - float(L(dev(theta) - eps * dd))) / (2 * eps)
+        assert abs(fd - g @ d) <= 1e-5 * abs(fd)
+
+
+def test_many_rhs_match_single_solves():
+    """Several right-hand sides in one lockstep solve equal the single solves
+    at the same iteration counts."""
+    p = W.config2_like(n=24, H=6, L=3, cfg=55)
+    F = W.rng(55, 0).uniform(-1, 1, (5, p.n_free))
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    pc = m.Preconditioner(prob, dev(p.rho), max_nrhs=5)
+    X, st = pc.solve(dev(F))
+    Xh = host(X).reshape(5, -1)
+    for k in range(5):
+        pc1 = m.Preconditioner(prob, dev(p.rho), fixed_iters=st["iters"][k])
+        x1, _ = pc1.solve(dev(F[k]))
+        assert relerr(Xh[k], host(x1)) <= 1e-12
