@@ -3,7 +3,7 @@
  *
  * Solves the Q1 finite-element discretisation of -div(rho grad u) = f on the
  * unit square / cube with zero Dirichlet data (the model problem of Section 2,
- * with the variable coefficient of Remark 1) by preconditioned conjugate
+ * with the variable coefficient of Remark 4) by preconditioned conjugate
  * gradients, the preconditioner being BDDC-SO (Section 3): BDDC whose coarse
  * degrees of freedom are point values at, or averages over, subobjects --
  * the vertices, edges and faces of a finer partition (the subsubdomains)
@@ -53,14 +53,14 @@ typedef enum {
 typedef struct bddcso_problem bddcso_problem; /* host descriptors + classification */
 typedef struct bddcso_precond bddcso_precond; /* device factors of one setup      */
 
-/* Primal object kinds (Section 3 and the remark on acceptable paths). */
+/* Primal object kinds (Section 3; Remark 5 on acceptable paths). */
 #define BDDCSO_PRIMAL_V 1
 #define BDDCSO_PRIMAL_E 2
 #define BDDCSO_PRIMAL_F 4
 
 typedef struct {
   int primal_mask;   /* OR of BDDCSO_PRIMAL_*; 7 = every subobject ("vef")   */
-  int weighting;     /* 0: eq. (W) counting weights; 1: Remark 1, weights by
+  int weighting;     /* 0: eq. (W) counting weights; 1: Remark 4, weights by
                         the coefficient averaged over each subsubdomain       */
   int precision;     /* 0: FP64 throughout; 1: local factors, local solves
                         and Phi^T K Phi in FP32 (coarse problem, outer PCG
@@ -96,7 +96,7 @@ typedef struct {
 /*
  * Creates the host descriptors and classifies the interface (Section 3):
  * Gamma = free nodes shared by two or more subdomains; each Gamma node is
- * keyed by the set of subsubdomains containing it (the remark on
+ * keyed by the set of subsubdomains containing it (Remark 2 on
  * classification); connected sets of nodes with one key are the subobjects.
  * Host only (no device work).
  *   dim          2 or 3
@@ -119,7 +119,7 @@ bddcso_status bddcso_problem_info(const bddcso_problem* p, int primal_mask, int6
                                   int64_t counts[3]);
 
 /*
- * Builds the preconditioner for coefficient rho (Remark 1), on the device:
+ * Builds the preconditioner for coefficient rho (Remark 4), on the device:
  * local matrices, block factorizations of K_II and K_rr (primal vertices
  * eliminated), the constraint Schur complement, the coarse basis Phi_i, the
  * local coarse matrices Phi_i^T K_i Phi_i and the factorization of the
@@ -144,7 +144,7 @@ bddcso_status bddcso_refactor(bddcso_precond* pc, const double* rho_dev, void* s
 bddcso_status bddcso_check_pivots(bddcso_precond* pc, void* stream);
 
 /* y = A x, the matrix-free Q1 operator with the preconditioner's rho
- * (Section 2, Remark 1).  x_dev, y_dev: [nrhs][n_free] FP64, distinct. */
+ * (Section 2, Remark 4).  x_dev, y_dev: [nrhs][n_free] FP64, distinct. */
 bddcso_status bddcso_operator_apply(const bddcso_precond* pc, const double* x_dev, double* y_dev,
                                     int nrhs, void* stream);
 

@@ -8,7 +8,7 @@ where U_I are the functions vanishing on Gamma, P is the a^Theta-orthogonal
 projection onto U_I, W~ is the subspace of W = W_1 x ... x W_N that is
 continuous at the selected coarse degrees of freedom (values at, or averages
 over, the selected subobjects), and E is the weighted average of eq. (W)
-(Remark 1 with coefficients).  Definition 1 gives
+(Remark 4 with coefficients).  Definition 1 gives
 
     B r = v1 + (I - P) E v2,  a(v1, z) = <r, z> on U_I,
                                a^Theta(v2, z) = <r, (I - P) E z> on W~.

@@ -2,7 +2,7 @@
 
 Section 3: the partition Theta = {Omega_i} has interface Gamma; a finer
 partition Theta^ = {Omega^_j} (the subsubdomains) splits subdomain faces and
-edges into subfaces, subedges and the vertices between them.  The remark on
+edges into subfaces, subedges and the vertices between them.  Remark 2 on
 classification in Section 3 groups each interface degree of freedom by the
 list of subsubdomains that contain it.  This module does exactly that:
 
@@ -19,11 +19,11 @@ list of subsubdomains that contain it.  This module does exactly that:
   (1 = v, 2 = e, 4 = f; 7 = "vef", every object); they are numbered by their
   smallest global free-node index, which is the coarse numbering.
 
-Weights, eq. (W) and Remark 1: for a Gamma node xi and a subdomain i that
+Weights, eq. (W) and Remark 4: for a Gamma node xi and a subdomain i that
 contains it, delta_i(xi) = sum of alpha_j over the subsubdomains j of key(xi)
 that lie in Omega_i, divided by the sum of alpha_j over all of key(xi).  With
 alpha_j = 1 this is eq. (W) (card ratio); with alpha_j = the coefficient on
-Omega^_j it is Remark 1.  Where rho is not constant on a subsubdomain the
+Omega^_j it is Remark 4.  Where rho is not constant on a subsubdomain the
 mean of rho over its elements is used.
 """
 from __future__ import annotations
@@ -165,7 +165,7 @@ def classify(n_el, elem_sub, elem_subsub, primal_mask: int = 7) -> Classificatio
 
 
 def subsub_alpha(elem_subsub, rho, weighting: int) -> np.ndarray:
-    """alpha_j per subsubdomain: 1 (eq. W) or the mean of rho over it (Remark 1)."""
+    """alpha_j per subsubdomain: 1 (eq. W) or the mean of rho over it (Remark 4)."""
     elem_subsub = np.asarray(elem_subsub, dtype=np.int64)
     n_ss = int(elem_subsub.max()) + 1
     if weighting == 0:
@@ -176,7 +176,7 @@ def subsub_alpha(elem_subsub, rho, weighting: int) -> np.ndarray:
 
 
 def weight(cls: Classification, alpha: np.ndarray, node: int, sub: int) -> float:
-    """delta_sub(node), eq. (W) / Remark 1; 1 for nodes inside one subdomain."""
+    """delta_sub(node), eq. (W) / Remark 4; 1 for nodes inside one subdomain."""
     if not cls.is_gamma[node]:
         return 1.0
     key = cls.node_keys[int(node)]

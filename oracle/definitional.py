@@ -7,7 +7,7 @@ Definition 1 with V1 = U_I, V2 = W~, Q1 = I, Q2 = (I - P) E (Section 3):
 
 with Z a basis of W~ (the null space of the jumps of every selected coarse
 functional between the subdomains sharing its object), A~ = Z^T diag(K_i) Z,
-M = (I - P) E Z, E the weighted average of eq. (W) / Remark 1, and (I - P)
+M = (I - P) E Z, E the weighted average of eq. (W) / Remark 4, and (I - P)
 the discrete-harmonic extension from Gamma: ((I-P)u)_Gamma = u_Gamma,
 ((I-P)u)_I = -A_II^{-1} A_I,Gamma u_Gamma.  Nothing here eliminates
 vertices, builds coarse basis functions or a coarse matrix, so it pins the
@@ -15,7 +15,7 @@ step-by-step ``bddc`` module from a different direction.
 
 The BDDC-A operator of Section 4 is built the same way on the fine partition
 Theta^ (full continuity on Gamma^ minus Gamma, the selected subobjects on
-Gamma, counting weights of eq. (W2)), for the bound of Theorem 1.
+Gamma, counting weights of eq. (W2)), for the bound of Theorem 3.
 """
 from __future__ import annotations
 

@@ -10,7 +10,7 @@ The condition number is estimated from the CG coefficients (the Lanczos
 tridiagonal matrix of the preconditioned operator; Saad, Iterative Methods
 for Sparse Linear Systems, Section 6.7.3): diagonal 1/alpha_0, then
 1/alpha_j + beta_{j-1}/alpha_{j-1}, off-diagonal sqrt(beta_{j-1})/alpha_{j-1}.
-Theorem 1 bounds the spectrum of BA below by 1.
+Theorem 3 bounds the spectrum of BA below by 1.
 """
 from __future__ import annotations
 

@@ -2,7 +2,7 @@
 
 Model problem, Section 2: -div(alpha grad u) = f with zero Dirichlet data on
 the whole boundary; the bilinear form is a(u, v) = sum_e alpha_e int_e grad u .
-grad v (Remark 1 for the per-element coefficient).  The paper's experiments
+grad v (Remark 4 for the per-element coefficient).  The paper's experiments
 use hexahedra (Section 5), so the space is bi/trilinear Q1.
 
 The element stiffness matrix of a Q1 box is the tensor sum of 1D stiffness

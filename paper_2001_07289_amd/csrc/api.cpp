@@ -249,6 +249,33 @@ Numeric<float>& num<float>(bddcso_precond* pc) {
   return pc->nf;
 }
 
+// Host-side guard run once per setup: every descriptor a batched kernel will
+// index must lie inside the pool it addresses, so a planning mistake is an
+// error status rather than an out-of-bounds device access.
+struct PlanFail {
+  std::string what;
+};
+
+int64_t extent(int64_t off, int rows, int cols, int ld) {
+  return rows <= 0 || cols <= 0 ? off : off + (int64_t)(cols - 1) * ld + rows;
+}
+
+void check_sweeps(const std::vector<SweepDesc>& v, int64_t pool, int64_t scratch_slots, const char* name) {
+  if ((int64_t)v.size() > scratch_slots)
+    throw PlanFail{std::string(name) + ": more problems than sweep scratch slots"};
+  for (const SweepDesc& d : v)
+    if (d.off < 0 || d.p < 0 || d.p > d.n || d.ld < d.n || extent(d.off, d.n, d.n, d.ld) > pool)
+      throw PlanFail{std::string(name) + ": sweep descriptor outside its pool"};
+}
+
+// Non-transposed operands: A is m x k, B is k x n, C is m x n (column-major).
+void check_gemms(const std::vector<GemmDesc>& v, int64_t pa, int64_t pb, int64_t pcx, const char* name) {
+  for (const GemmDesc& d : v)
+    if (d.a < 0 || d.b < 0 || d.c < 0 || d.lda < d.m || d.ldb < d.k || d.ldc < d.m ||
+        extent(d.a, d.m, d.k, d.lda) > pa || extent(d.b, d.k, d.n, d.ldb) > pb || extent(d.c, d.m, d.n, d.ldc) > pcx)
+      throw PlanFail{std::string(name) + ": GEMM descriptor outside its pools"};
+}
+
 Batch make_gemm_batch(DevMem& mem, const std::vector<GemmDesc>& v, hipStream_t s) {
   Batch b;
   b.n = (int)v.size();
@@ -326,6 +353,7 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
         const BlockDev& B = pl.blocks[(setR ? S.bR_off : S.bI_off) + k];
         d.push_back({B.G_off, B.size, B.size, B.size});
       }
+      check_sweeps(d, pl.pool_G, ns, setR ? "K_rr blocks" : "K_II blocks");
       vec.push_back(make_sweep_batch(m, d, s));
     }
   }
@@ -344,6 +372,8 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
                        B.size, ncols, B.last_n, B.size, B.last_n, S.n_r});
       }
     }
+    check_gemms(f, pl.pool_G, tmp_stride * ns, pl.pool_Z, "forward block GEMM");
+    check_gemms(b, pl.pool_G, tmp_stride * ns, pl.pool_Z, "backward block GEMM");
     pc->gfwd.push_back(make_gemm_batch(m, f, s));
     pc->gbwd.push_back(make_gemm_batch(m, b, s));
   }
@@ -360,6 +390,9 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
         }
       }
     }
+    check_sweeps(d, pl.pool_Sc, ns, "S_c");
+    check_gemms(lam, pl.pool_Sc, pl.pool_T, pl.pool_T, "Lambda GEMM");
+    check_gemms(phir, pl.pool_Z, pl.pool_T, pl.pool_Phi, "Phi GEMM");
     pc->swSc = make_sweep_batch(m, d, s);
     pc->gLam = make_gemm_batch(m, lam, s);
     pc->gPhiR = make_gemm_batch(m, phir, s);
@@ -396,6 +429,7 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       mb = std::max(mb, F.n - F.p);
       maxfn = std::max(maxfn, F.n);
     }
+    check_sweeps(d, pl.front_pool, (int64_t)d.size(), "coarse fronts");
     pc->swFront.push_back(make_sweep_batch(m, d, s));
     pc->level_dev.push_back(m.upload(pl.level_fronts[L], s));
     pc->level_n.push_back((int)pl.level_fronts[L].size());
@@ -811,6 +845,9 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     HIPCHK(hipStreamCreateWithFlags(&pc->s2, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
+  } catch (const PlanFail& f) {
+    bddcso_precond_destroy(pc);
+    return set_err(BDDCSO_EINVAL, "inconsistent plan: " + f.what);
   } catch (const HipFail& f) {
     bddcso_precond_destroy(pc);
     if (f.e == hipErrorOutOfMemory)

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(Geo g, const double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// weights (eq. W / Remark 1)
+// weights (eq. W / Remark 4)
 
 __global__ void k_alpha(PlanDev P, int n_ss, const double* __restrict__ rho, int weighting,
                         double* __restrict__ alpha) {
@@ -1829,8 +1829,9 @@ void Kern<T>::block_solve(const PlanDev& P, const Geo& g, const double* rho, int
   size_t sm = (size_t)(hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * sizeof(T);
   if (prof) prof->begin(2, s);
   k_block_solve<T><<<dim3(P.n_sub, nrhs), BS_THREADS, sm, s>>>(P, g, rho, setR, G, v);
-  // each G entry streamed once per rhs (2 flops), the vector read and written once
-  if (prof) prof->end(2, 2.0 * g_entries * nrhs, sizeof(T) * (g_entries + 2.0 * vec_entries) * nrhs, s);
+  // the method must stream each G entry once per launch (2 flops per rhs) and
+  // read and write each vector once
+  if (prof) prof->end(2, 2.0 * g_entries * nrhs, sizeof(T) * (g_entries + 2.0 * vec_entries * nrhs), s);
 }
 
 template <typename T>

@@ -1,5 +1,5 @@
 // Host planner: validates the descriptors, classifies the interface into
-// subobjects (Section 3, remark on classification), and lays out every
+// subobjects (Section 3, Remark 2 on classification), and lays out every
 // per-subdomain table, block and coarse-tree front the device path uses.
 #include "plan.h"
 

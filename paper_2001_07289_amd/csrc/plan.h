@@ -15,7 +15,7 @@ struct Error {
 };
 
 // Mesh, partitions and the classification of Gamma into subobjects
-// (Section 3 and its remark on classification).  Independent of the primal
+// (Section 3 and Remark 2 on classification).  Independent of the primal
 // selection.
 struct Classification {
   int dim = 3;

@@ -54,7 +54,7 @@ def test_every_interface_dof_primal_gives_exact_inverse(p):
 
 @pytest.mark.parametrize("name,p", _tiny_cases(), ids=[c[0] for c in _tiny_cases()])
 def test_lower_bound_theorem1(name, p):
-    """Theorem 1: the spectrum of BA lies in [1, kappa]."""
+    """Theorem 3: the spectrum of BA lies in [1, kappa]."""
     o = bddc.from_problem(p)
     ev = np.linalg.eigvals(o.dense() @ o.A.toarray()).real
     assert ev.min() >= 1.0 - 1e-10
@@ -92,7 +92,7 @@ def test_pcg_matches_direct_solve():
 
 
 def test_kappa_decreases_with_L():
-    """Theorem 1 at fixed H = 32h (2D 128^2, 4x4 subdomains): kappa falls as
+    """Theorem 3 at fixed H = 32h (2D 128^2, 4x4 subdomains): kappa falls as
     L shrinks, L = H is standard BDDC, L = 2h is exact, and kappa follows
     C (1 + log(L/h))^2 with one constant."""
     n, H = 128, 32
@@ -123,7 +123,7 @@ def test_kappa_bounded_at_fixed_L_over_h():
 
 
 def test_contrast_robustness_aligned():
-    """Remark 1: rho constant per subdomain (so per subsubdomain) with the
+    """Remark 4: rho constant per subdomain (so per subsubdomain) with the
     coefficient weights; iterations do not grow with the contrast."""
     its = []
     for hi in (0.0, 2.0, 4.0, 6.0):

@@ -19,7 +19,7 @@ Conventions (both consumers rely on them):
   partition used to define subobjects, Section 3).  Every subsubdomain lies in
   one subdomain.
 * ``rho`` (float64, one value per element) is the diffusion coefficient of
-  Remark 1; ``f`` (float64, ``[nrhs, n_free]``) is the nodal load vector.
+  Remark 4; ``f`` (float64, ``[nrhs, n_free]``) is the nodal load vector.
 
 Random streams: ``numpy.random.default_rng(SeedSequence([cfg, stream]))`` with
 stream 0 = f, 1 = rho, 2 = cut planes, 3 = subobject lengths, 4 = channels,
@@ -52,7 +52,7 @@ class Problem:
     f: np.ndarray                  # float64 [nrhs, n_free]
     name: str = ""
     primal_mask: int = 7           # 1 = vertices, 2 = edges, 4 = faces
-    weighting: int = 1             # 0 = counting (eq. W), 1 = coefficient (Remark 1)
+    weighting: int = 1             # 0 = counting (eq. W), 1 = coefficient (Remark 4)
     extra: dict = dataclasses.field(default_factory=dict)
 
     @property
