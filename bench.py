@@ -92,7 +92,7 @@ def roofline(prof, dtype):
     nbytes = rec["bytes"] / rec["launches"]
     peak_f = MFMA_TFLOPS[dtype] * 1e12
     ai = flops / max(nbytes, 1.0)
-    mfma_bound = name in ("sweep_update", "gemm", "sweep_panel") and ai * HBM_GBS * 1e9 >= peak_f
+    mfma_bound = name in ("sweep_update", "gemm", "sweep_panel", "sweep_small") and ai * HBM_GBS * 1e9 >= peak_f
     if mfma_bound:
         ach = flops / avg_s / 1e12
         out = {"bound": "mfma", "achieved": ach, "peak": MFMA_TFLOPS[dtype], "unit": "TFLOP/s",

@@ -135,7 +135,7 @@ struct EventProfiler : Profiler {
     size_t used = 0;
     double flops = 0, bytes = 0;
     int64_t launches = 0;
-  } rec[5];
+  } rec[6];
   hipEvent_t next(Rec& r) {
     if (r.used == r.ev.size()) {
       hipEvent_t e;
@@ -145,12 +145,12 @@ struct EventProfiler : Profiler {
     return r.ev[r.used++];
   }
   void begin(int c, hipStream_t s) override {
-    if (c < 1 || c > 4 || !(mask & (1 << c))) return;
+    if (c < 1 || c > 5 || !(mask & (1 << c))) return;
     hipEvent_t e = next(rec[c]);
     if (e) (void)hipEventRecord(e, s);
   }
   void end(int c, double f, double b, hipStream_t s) override {
-    if (c < 1 || c > 4 || !(mask & (1 << c))) return;
+    if (c < 1 || c > 5 || !(mask & (1 << c))) return;
     hipEvent_t e = next(rec[c]);
     if (e) (void)hipEventRecord(e, s);
     rec[c].flops += f;
@@ -808,6 +808,8 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     P.max_nI = max_nI;
     P.max_zcols = pl.max_zcols;
     P.max_plane = max_plane;
+    if (max_lds_bytes(P, o.precision == 1 ? 4 : 8) > 160 * 1024)
+      throw PlanFail{"a subdomain plane or block is too large for the LDS staging of the local kernels"};
 
     pc->rho = m.alloc<double>(c.n_elem);
     for (auto& S : pl.subs) pc->max_nv = std::max(pc->max_nv, S.n_v);
@@ -1075,7 +1077,7 @@ bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bd
 
 bddcso_status bddcso_profile(bddcso_precond* pc, int class_mask) {
   if (!pc) return set_err(BDDCSO_EINVAL, "null precond");
-  if (class_mask < 0 || class_mask > 0x1e) return set_err(BDDCSO_EINVAL, "class mask must use bits 1..4");
+  if (class_mask < 0 || class_mask > 0x3e) return set_err(BDDCSO_EINVAL, "class mask must use bits 1..5");
   pc->prof.reset(class_mask);
   return BDDCSO_OK;
 }
@@ -1083,7 +1085,7 @@ bddcso_status bddcso_profile(bddcso_precond* pc, int class_mask) {
 bddcso_status bddcso_profile_read(bddcso_precond* pc, int kernel_class, int64_t* launches, double* total_ms,
                                   double* flops, double* bytes) {
   if (!pc) return set_err(BDDCSO_EINVAL, "null precond");
-  if (kernel_class < 1 || kernel_class > 4) return set_err(BDDCSO_EINVAL, "kernel class must be in 1..4");
+  if (kernel_class < 1 || kernel_class > 5) return set_err(BDDCSO_EINVAL, "kernel class must be in 1..5");
   auto& R = pc->prof.rec[kernel_class];
   double ms = 0.0;
   for (size_t i = 0; i + 1 < R.used; i += 2) {

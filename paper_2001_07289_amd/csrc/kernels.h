@@ -142,6 +142,7 @@ void launch_pcg_p_flex(double* p, const double* z, const double* zdr, const doub
                        const int32_t* active, int64_t n, int nrhs, hipStream_t s);
 void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);
 void launch_copy16(const void* a, void* b, int64_t n16, hipStream_t s);
+int64_t max_lds_bytes(const PlanDev& P, int elt);
 
 void launch_element_grad(const Geo& g, const double* khat, const double* rho, const double* u,
                          const double* lam, double* out, int nrhs, hipStream_t s);

@@ -8,6 +8,7 @@
 // coalesced along the fastest index, reductions in fixed order (no
 // floating-point atomics), so results are bitwise repeatable.
 #include <hip/hip_runtime.h>
+#include <utility>
 
 #include <algorithm>
 #include <cstdio>
@@ -295,16 +296,21 @@ __global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rh
       }
 }
 
-// Stage 1 of the block Schur update S_k -= A_{k,k-1} G_{k-1} A_{k-1,k}:
-// W[l', j'] = sum_m Gs[l, m] A[m, j] over the last plane of block k-1 (l, m)
-// and the first plane of block k (j).  Gs is the swept block (= -G).
-// Stage 1 of the block Schur update S_k -= A_{k,k-1} G_{k-1} A_{k-1,k}:
-// W[l', j'] = sum_m Gs[l, m] A[m, j] over the last plane of block k-1 (l, m)
-// and the first plane of block k (j); Gs is the swept block (= -G).  One
-// thread per row l', columns j' strided over blockIdx.z.
+// Block Schur update S_k = A_kk - A_{k,k-1} G_{k-1} A_{k-1,k} of the
+// block-tridiagonal factorization, restricted to the first-plane rows and
+// columns of block k (the only ones the plane coupling reaches).  One
+// workgroup per (subdomain, chunk of SC_COLS columns j'):
+//   W[l', j'] = sum_m Gs[l', m] A[m, j']  over the last plane of block k-1,
+//   S_k[i', j'] += sum_l A[i', l] W[l, j'],
+// with Gs = -G_{k-1} the swept block, so the sum adds -A G A.  W stays in LDS.
+constexpr int SC_COLS = 16;
+
 template <typename T>
-__global__ void k_schur_w(PlanDev P, int setR, int k, const T* __restrict__ G, T* __restrict__ W,
-                          int64_t wstride) {
+__global__ __launch_bounds__(256) void k_schur_couple(PlanDev P, int setR, int k, T* __restrict__ G) {
+  extern __shared__ char smem_raw[];
+  T(*W)[SC_COLS + 1] = reinterpret_cast<T(*)[SC_COLS + 1]>(smem_raw);  // [last_n][cols]
+  __shared__ int crk[SC_COLS][9];
+  __shared__ double ccf[SC_COLS][9];
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int nb = setR ? S.nbR : S.nbI;
@@ -312,53 +318,63 @@ __global__ void k_schur_w(PlanDev P, int setR, int k, const T* __restrict__ G, T
   const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
   const BlockDev Bp = blk[k - 1], B = blk[k];
   if (B.cf_off < 0) return;
-  const int lp = blockIdx.x * blockDim.x + threadIdx.x;
-  if (lp >= Bp.last_n) return;
-  const T* Gr = G + Bp.G_off + (Bp.size - Bp.last_n + lp);
-  T* Wp = W + sub * wstride + lp;
-  for (int jp = blockIdx.z; jp < B.first_n; jp += gridDim.z) {
-    const int64_t row = B.cf_off + jp;
-    double acc = 0.0;
+  const int c0 = blockIdx.x * SC_COLS;
+  if (c0 >= B.first_n) return;
+  const int cols = min(SC_COLS, B.first_n - c0);
+  // coupling rows of this chunk's columns (first-plane rows of block k)
+  for (int e = threadIdx.x; e < SC_COLS * 9; e += blockDim.x) {
+    const int c = e / 9, t = e % 9;
+    const int64_t row = B.cf_off + c0 + c;
+    const int m = c < cols ? P.cpl_rank[row * 9 + t] : -1;
+    crk[c][t] = m >= 0 ? m - Bp.start : -1;
+    ccf[c][t] = m >= 0 ? P.cpl_coef[row * 9 + t] : 0.0;
+  }
+  __syncthreads();
+  // W[l'][c] = sum_t Gs[l', m_t] a_t, four columns' gathers in flight at a time
+  const T* Gr = G + Bp.G_off + (Bp.size - Bp.last_n);
+  for (int lp = threadIdx.x; lp < Bp.last_n; lp += blockDim.x) {
+    for (int cb = 0; cb < SC_COLS; cb += 4) {
+      T gv[4][9];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int m = crk[cb + cc][t];
+          gv[cc][t] = m >= 0 ? Gr[lp + (int64_t)Bp.size * m] : (T)0;
+        }
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc += (double)gv[cc][t] * ccf[cb + cc][t];
+        W[lp][cb + cc] = (T)acc;
+      }
+    }
+  }
+  __syncthreads();
+  // S_k[i'][c] += sum_t A[i', l_t] W[l_t][c], all of the row's columns at once
+  const int base = Bp.start + Bp.size - Bp.last_n;
+  T* Gk = G + B.G_off + (int64_t)B.size * c0;
+  for (int ip = threadIdx.x; ip < B.first_n; ip += blockDim.x) {
+    const int64_t row = B.cf_off + ip;
+    double a[9];
+    int l[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const int m = P.cpl_rank[row * 9 + t];
-      if (m >= 0) acc += (double)Gr[(int64_t)Bp.size * (m - Bp.start)] * P.cpl_coef[row * 9 + t];
+      const int r = P.cpl_rank[row * 9 + t];
+      a[t] = r >= 0 ? P.cpl_coef[row * 9 + t] : 0.0;
+      l[t] = r >= 0 ? r - base : 0;
     }
-    Wp[(int64_t)Bp.last_n * jp] = (T)acc;
-  }
-}
-
-// Stage 2: S_k[i', j'] += sum_l A[i, l] W[l', j'] (first-plane rows/columns),
-// one thread per row i', columns j' strided over blockIdx.z.
-template <typename T>
-__global__ void k_schur_apply(PlanDev P, int setR, int k, T* __restrict__ G, const T* __restrict__ W,
-                              int64_t wstride) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  const int nb = setR ? S.nbR : S.nbI;
-  if (k >= nb || k == 0) return;
-  const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
-  const BlockDev Bp = blk[k - 1], B = blk[k];
-  if (B.cf_off < 0) return;
-  const int ip = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ip >= B.first_n) return;
-  const int base = Bp.start + Bp.size - Bp.last_n;
-  const int64_t row = B.cf_off + ip;
-  double a[9];
-  int l[9];
+    T old[SC_COLS];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int r = P.cpl_rank[row * 9 + t];
-    a[t] = r >= 0 ? P.cpl_coef[row * 9 + t] : 0.0;
-    l[t] = r >= 0 ? r - base : 0;
-  }
-  const T* Wp = W + sub * wstride;
-  T* Gk = G + B.G_off + ip;
-  for (int jp = blockIdx.z; jp < B.first_n; jp += gridDim.z) {
-    double acc = 0.0;
+    for (int c = 0; c < SC_COLS; ++c) old[c] = c < cols ? Gk[ip + (int64_t)B.size * c] : (T)0;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) acc += a[t] * (double)Wp[l[t] + (int64_t)Bp.last_n * jp];
-    Gk[(int64_t)B.size * jp] += (T)acc;
+    for (int c = 0; c < SC_COLS; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) acc += a[t] * (double)W[l[t]][c];
+      if (c < cols) Gk[ip + (int64_t)B.size * c] = old[c] + (T)acc;
+    }
   }
 }
 
@@ -514,38 +530,81 @@ __global__ __launch_bounds__(256) void k_sweep_panel(const SweepDesc* __restrict
   const bool have_prev = prev_j0 >= 0 && prev_j0 < p;
   const T* CDp = have_prev ? sweep_slot(scratch, scr_stride, blockIdx.y, prev_j0) : nullptr;
   const int pb = have_prev ? min(SWEEP_NB, p - prev_j0) : 0;
+  // Each phase issues PU independent loads per thread before it stores any of
+  // them, so the latency of one HBM round trip is paid per PU elements.
+  constexpr int NT = 256, PU = 8;
   if (have_prev) {
     const T* Dip = CDp + (int64_t)n * SWEEP_NB;
-    for (int idx = tid; idx < rows * pb; idx += blockDim.x) {
-      const int i = r0 + idx % rows, q = idx / rows;
-      const int col = prev_j0 + q;
-      if (i >= prev_j0 && i < prev_j0 + pb) {
-        A[i + (int64_t)ld * col] = -Dip[(i - prev_j0) + SWEEP_NB * q];
-      } else {
-        const T v = CDp[i + (int64_t)n * q];
-        if (i > col) A[i + (int64_t)ld * col] = v;
-        else A[col + (int64_t)ld * i] = v;
+    const int tot = rows * pb;
+    for (int base = tid; base < tot; base += NT * PU) {
+      T v[PU];
+      int64_t dst[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int idx = base + u * NT;
+        dst[u] = -1;
+        if (idx < tot) {
+          const int i = r0 + idx % rows, q = idx / rows;
+          const int col = prev_j0 + q;
+          if (i >= prev_j0 && i < prev_j0 + pb) {
+            v[u] = -Dip[(i - prev_j0) + SWEEP_NB * q];
+            dst[u] = i + (int64_t)ld * col;
+          } else {
+            v[u] = CDp[i + (int64_t)n * q];
+            dst[u] = i > col ? i + (int64_t)ld * col : col + (int64_t)ld * i;
+          }
+        }
       }
+#pragma unroll
+      for (int u = 0; u < PU; ++u)
+        if (dst[u] >= 0) A[dst[u]] = v[u];
     }
   }
   if (j0 < 0 || j0 >= p) return;
   const int jb = min(SWEEP_NB, p - j0);
-  for (int idx = tid; idx < SWEEP_NB * SWEEP_NB; idx += blockDim.x) {
-    const int i = idx % SWEEP_NB, j = idx / SWEEP_NB;
-    const int gi = max(i, j), gj = min(i, j);
-    D[0][i][j] = (i < jb && j < jb) ? (double)A[(j0 + gi) + (int64_t)ld * (j0 + gj)] : (i == j ? 1.0 : 0.0);
+  {
+    double dv[SWEEP_NB * SWEEP_NB / NT];
+#pragma unroll
+    for (int u = 0; u < SWEEP_NB * SWEEP_NB / NT; ++u) {
+      const int idx = tid + u * NT;
+      const int i = idx % SWEEP_NB, j = idx / SWEEP_NB;
+      const int gi = max(i, j), gj = min(i, j);
+      dv[u] = (i < jb && j < jb) ? (double)A[(j0 + gi) + (int64_t)ld * (j0 + gj)] : (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < SWEEP_NB * SWEEP_NB / NT; ++u) {
+      const int idx = tid + u * NT;
+      D[0][idx % SWEEP_NB][idx / SWEEP_NB] = dv[u];
+    }
   }
   // stage this chunk's rows of the column panel (rows above the panel from
   // the lower-triangle mirror, previous-panel rows from its scratch slot)
   const bool above = r0 + rows <= j0;  // whole chunk above the panel: read the row panel along t
-  for (int idx = tid; idx < rows * jb; idx += blockDim.x) {
-    const int t = above ? idx % jb : idx / rows, r = above ? idx / jb : idx % rows;
-    const int i = r0 + r;
-    T v = 0;
-    if (have_prev && i >= prev_j0 && i < prev_j0 + pb) v = CDp[(j0 + t) + (int64_t)n * (i - prev_j0)];
-    else if (i < j0) v = A[(j0 + t) + (int64_t)ld * i];
-    else if (i >= j0 + jb) v = A[i + (int64_t)ld * (j0 + t)];
-    Cl[r][t] = v;
+  {
+    const int tot = rows * jb;
+    for (int base = tid; base < tot; base += NT * PU) {
+      T v[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int idx = base + u * NT;
+        v[u] = 0;
+        if (idx < tot) {
+          const int t = above ? idx % jb : idx / rows, r = above ? idx / jb : idx % rows;
+          const int i = r0 + r;
+          if (have_prev && i >= prev_j0 && i < prev_j0 + pb) v[u] = CDp[(j0 + t) + (int64_t)n * (i - prev_j0)];
+          else if (i < j0) v[u] = A[(j0 + t) + (int64_t)ld * i];
+          else if (i >= j0 + jb) v[u] = A[i + (int64_t)ld * (j0 + t)];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int idx = base + u * NT;
+        if (idx < tot) {
+          const int t = above ? idx % jb : idx / rows, r = above ? idx / jb : idx % rows;
+          Cl[r][t] = v[u];
+        }
+      }
+    }
   }
   __syncthreads();
   const int cur = 0;
@@ -673,6 +732,19 @@ __global__ __launch_bounds__(256) void k_sweep_update(const SweepDesc* __restric
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(bv[b], av[a], acc[a][b]);
   }
+  // read every old value of the wave's 32x32 block first, then write
+  T old[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = c0 + wj + b * 16 + Mfma<T>::row(kq, r);
+        const int i = i0 + wi + a * 16 + rr;
+        const bool on = i < n && j <= i && !(i >= j0 && i < j0 + jb) && !(j >= j0 && j < j0 + jb);
+        old[a][b][r] = on ? A[i + (int64_t)ld * j] : (T)0;
+      }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -682,7 +754,7 @@ __global__ __launch_bounds__(256) void k_sweep_update(const SweepDesc* __restric
         const int j = c0 + wj + b * 16 + Mfma<T>::row(kq, r);
         const int i = i0 + wi + a * 16 + rr;
         if (i < n && j <= i && !(i >= j0 && i < j0 + jb) && !(j >= j0 && j < j0 + jb))
-          A[i + (int64_t)ld * j] -= acc[a][b][r];
+          A[i + (int64_t)ld * j] = old[a][b][r] - acc[a][b][r];
       }
 }
 
@@ -713,6 +785,228 @@ __global__ void k_symmetrize(const SweepDesc* __restrict__ desc, T* pool, int nt
     }
   }
   (void)ntri;
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident sweep for matrices of at most 16*MT rows: one workgroup
+// of RS_WAVES waves per matrix holds its lower triangle as 16x16 MFMA
+// accumulator tiles (tile t = wave + RS_WAVES * slot), so the matrix is read
+// from HBM once and written once.  Pivots go in panels of 16 (one tile
+// column).  Per panel:
+//   1. the owners of the panel's tiles stage its column C (n x 16, with the
+//      row panel mirrored) and the 16x16 pivot block D in LDS;
+//   2. every wave sweeps D in registers (the same arithmetic in each wave,
+//      so all hold the same -D^{-1});
+//   3. the waves form CD = C D^{-1} on MFMA, one 16-row tile at a time;
+//   4. every tile takes the rank-16 update M_ij -= CD_i C_j^T on MFMA, and the
+//      panel's own entries become CD (rows or columns in the panel) or
+//      -D^{-1} (the pivot block).
+// Only the lower triangle is read; both triangles are written.
+constexpr int RS_MAX_TILES = 17;  // largest matrix: 272 rows
+
+// Wave-uniform broadcast of lane l's value (l a compile-time or uniform index).
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+// 1/x by the hardware reciprocal refined with two Newton steps
+// (r <- r + r (1 - x r)), accurate to the last bit or one ulp.
+__device__ __forceinline__ double recip_f64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+// Lane l of a wave reads lane Q of its own row of 16 lanes (DPP row share).
+template <int Q>
+__device__ __forceinline__ double row_share_f64(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x150 + Q, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x150 + Q, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// One pivot step of the 16x16 sweep below.
+template <int Q>
+__device__ __forceinline__ void sweep16_step(double m[4], int jb, int kq, int rr, bool& bad) {
+  double dq = readlane_f64(m[Q & 3], (Q >> 2) * 16 + Q);        // X[Q][Q]
+  if (!(dq > 0.0)) {
+    if (Q < jb) bad = true;
+    dq = 1.0;
+  }
+  const double inv = recip_f64(dq);
+  const double rowq = __shfl(m[Q & 3], (Q >> 2) * 16 + rr, 64);  // X[Q][rr]
+  const double rs = rowq * inv;
+  const bool qcol = rr == Q, qrow = kq == (Q >> 2);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const double colq = row_share_f64<Q>(m[t]);                   // X[4kq+t][Q]
+    const double upd = qcol ? colq * inv : m[t] - colq * rs;
+    m[t] = (t == (Q & 3) && qrow) ? (qcol ? -inv : rs) : upd;
+  }
+}
+
+template <int... Qs>
+__device__ __forceinline__ void sweep16_all(double m[4], int jb, int kq, int rr, bool& bad,
+                                            std::integer_sequence<int, Qs...>) {
+  (sweep16_step<Qs>(m, jb, kq, rr, bad), ...);
+}
+
+// A wave holds a 16x16 symmetric block X as m[t] = X[4 kq + t][rr]
+// (kq = lane/16, rr = lane%16).  Sweeps pivots 0..15 (pivots >= jb are
+// identity padding).  Per pivot q: X[q][q] comes by a wave-uniform
+// broadcast, the pivot column X[4 kq + t][q] from lane q of the lane's own
+// row of 16 (DPP), the pivot row X[q][rr] by one cross-lane permute.  On
+// return m holds the swept block (-X^{-1} on the pivots).  Returns true on a
+// pivot <= 0.
+__device__ __forceinline__ bool quad_sweep16(double m[4], int jb, int lane) {
+  bool bad = false;
+  sweep16_all(m, jb, lane >> 4, lane & 15, bad, std::make_integer_sequence<int, 16>{});
+  return bad;
+}
+
+template <typename T, int MT, int RS_WAVES>
+__global__ __launch_bounds__(RS_WAVES * 64) void k_sweep_reg(const SweepDesc* __restrict__ desc, T* pool,
+                                                             int* status, int status_code) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int NTILE = MT * (MT + 1) / 2;
+  constexpr int TPW = (NTILE + RS_WAVES - 1) / RS_WAVES;
+  __shared__ T Cs[MT * 16][17];     // panel column C (rows of the pivot columns), 0 on the pivot rows
+  __shared__ T CDs[MT * 16][17];    // C D^{-1}
+  __shared__ double Ds[16][17];     // pivot block before the sweep
+  __shared__ double Dw[16][17];     // swept pivot block (-D^{-1})
+  __shared__ int tab[NTILE];
+  const SweepDesc d = desc[blockIdx.x];
+  const int n = d.n, p = d.p, ld = d.ld;
+  T* A = pool + d.off;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int kq = lane >> 4, rr = lane & 15;
+  for (int t = tid; t < NTILE; t += RS_WAVES * 64) {
+    int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    while (ti * (ti + 1) / 2 > t) --ti;
+    tab[t] = (ti << 8) | (t - ti * (ti + 1) / 2);
+  }
+  __syncthreads();
+  const int nt = (n + 15) >> 4;
+  // wave-uniform tile coordinates of each slot (ti = -1: no tile)
+  int sti[TPW], stj[TPW];
+#pragma unroll
+  for (int sl = 0; sl < TPW; ++sl) {
+    const int t = wave + RS_WAVES * sl;
+    const int code = t < NTILE ? __builtin_amdgcn_readfirstlane(tab[t]) : -1;
+    sti[sl] = (code >= 0 && (code >> 8) < nt) ? (code >> 8) : -1;
+    stj[sl] = code & 255;
+  }
+  acc_t acc[TPW];
+  // load the lower triangle (padding beyond n is 0), branch-free per element
+#pragma unroll
+  for (int sl = 0; sl < TPW; ++sl) {
+    acc[sl] = acc_t{0, 0, 0, 0};
+    if (sti[sl] < 0) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * sti[sl] + Mfma<T>::row(kq, r), j = 16 * stj[sl] + rr;
+      const int hi = min(max(i, j), n - 1), lo = min(min(i, j), n - 1);
+      const T v = A[(int64_t)lo * ld + hi];
+      acc[sl][r] = (i < n && j < n) ? v : (T)0;
+    }
+  }
+  bool bad = false;
+  const int npan = (p + 15) >> 4;
+  for (int tq = 0; tq < npan; ++tq) {
+    const int j0 = 16 * tq, jb = min(16, p - j0);
+    __syncthreads();  // the previous panel's readers of Cs / CDs / Dw are done
+    // 1. stage C and D from the tiles of tile row / column tq
+#pragma unroll
+    for (int sl = 0; sl < TPW; ++sl) {
+      const int ti = sti[sl], tj = stj[sl];
+      if (ti < 0) continue;
+      if (ti == tq && tj == tq) {  // pivot rows carry no C
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = Mfma<T>::row(kq, r);
+          const T v = acc[sl][r];
+          if (a < jb && rr < jb) Ds[a][rr] = (double)v;
+          Cs[j0 + a][rr] = (a >= jb && rr < jb) ? v : (T)0;
+        }
+      } else if (tj == tq) {        // column panel, rows 16 ti + a
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Cs[16 * ti + Mfma<T>::row(kq, r)][rr] = rr < jb ? acc[sl][r] : (T)0;
+      } else if (ti == tq) {        // row panel: M[j0 + a][16 tj + b] = C[16 tj + b][a]
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = Mfma<T>::row(kq, r);
+          Cs[16 * tj + rr][a] = a < jb ? acc[sl][r] : (T)0;
+        }
+      }
+    }
+    __syncthreads();
+    // 2. wave 0 sweeps the pivot block
+    if (wave == 0) {
+      double m[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = 4 * kq + t;
+        m[t] = (i < jb && rr < jb) ? Ds[i][rr] : (i == rr ? 1.0 : 0.0);
+      }
+      bad |= quad_sweep16(m, jb, lane);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) Dw[4 * kq + t][rr] = m[t];
+    }
+    __syncthreads();
+    // 3. CD = C D^{-1} with D^{-1} = -Dw
+    for (int ti = wave; ti < nt; ti += RS_WAVES) {
+      acc_t c = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+        c = Mfma<T>::mac(Cs[16 * ti + rr][4 * s4 + kq], (T)(-Dw[4 * s4 + kq][rr]), c);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) CDs[16 * ti + Mfma<T>::row(kq, r)][rr] = c[r];
+    }
+    __syncthreads();
+    // 4. rank-16 update and the panel's new entries
+#pragma unroll
+    for (int sl = 0; sl < TPW; ++sl) {
+      const int ti = sti[sl], tj = stj[sl];
+      if (ti < 0) continue;
+      acc_t c = acc[sl];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+        c = Mfma<T>::mac(-CDs[16 * ti + rr][4 * s4 + kq], Cs[16 * tj + rr][4 * s4 + kq], c);
+      if (ti == tq || tj == tq) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * ti + Mfma<T>::row(kq, r), j = 16 * tj + rr;
+          const bool iq = i >= j0 && i < j0 + jb, jq = j >= j0 && j < j0 + jb;
+          const T dv = (T)Dw[(i - j0) & 15][(j - j0) & 15];
+          const T c1 = CDs[i][(j - j0) & 15], c2 = CDs[j][(i - j0) & 15];
+          c[r] = (iq && jq) ? dv : jq ? c1 : iq ? c2 : c[r];
+        }
+      }
+      acc[sl] = c;
+      // keep each slot's operand loads next to its MFMAs (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if (bad && lane == 0) atomicMax(status, status_code);
+  // write both triangles
+#pragma unroll
+  for (int sl = 0; sl < TPW; ++sl) {
+    const int ti = sti[sl], tj = stj[sl];
+    if (ti < 0) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * ti + Mfma<T>::row(kq, r), j = 16 * tj + rr;
+      if (i < n && j < n) {
+        A[(int64_t)i * ld + j] = acc[sl][r];
+        if (ti != tj) A[(int64_t)j * ld + i] = acc[sl][r];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1646,6 +1940,20 @@ void launch_kc_to_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_f32_to_f64<<<hmin(cdiv(n, 256), 65536), 256, 0, s>>>(src, dst, n);
 }
+// Largest LDS footprint (static + dynamic, bytes) of any kernel launched for
+// a plan with these maxima and element size; LDS per workgroup is 160 KiB.
+int64_t max_lds_bytes(const PlanDev& P, int elt) {
+  const int64_t mp = hmax(P.max_plane, 1);
+  int64_t need = 0;
+  need = hmax(need, mp * (SC_COLS + 1) * elt);                                         // schur couple
+  need = hmax(need, mp * (CPL_COLS + 1) * elt);                                        // couple multi
+  need = hmax(need, (hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * elt);     // block solve
+  need = hmax(need, (int64_t)(P.max_na + P.max_nc + 1) * elt);                         // v2
+  need = hmax(need, (int64_t)hmax(P.max_ng, 1) * elt);                                 // coarse rhs
+  need = hmax(need, (int64_t)SWEEP_ROWS * (SWEEP_NB + 1) * elt + 2 * 32 * 33 * 8);   // sweep panel
+  return need;
+}
+
 void launch_copy16(const void* a, void* b, int64_t n16, hipStream_t s) {
   if (n16 <= 0) return;
   k_copy16<<<hmin(cdiv(n16, 256), 65536), 256, 0, s>>>((const int4*)a, (int4*)b, n16);
@@ -1686,10 +1994,11 @@ void Kern<T>::schur_couple(const PlanDev& P, const Geo& g, const double* rho, in
                            T* W, int64_t wstride, hipStream_t s) {
   (void)g;
   (void)rho;
+  (void)W;
+  (void)wstride;
   const int mp = P.max_plane;
-  const dim3 grid(cdiv(mp, 64), P.n_sub, 16);
-  k_schur_w<T><<<grid, 64, 0, s>>>(P, setR, k, G, W, wstride);
-  k_schur_apply<T><<<grid, 64, 0, s>>>(P, setR, k, G, W, wstride);
+  const size_t sm = (size_t)hmax(mp, 1) * (SC_COLS + 1) * sizeof(T);
+  k_schur_couple<T><<<dim3(cdiv(mp, SC_COLS), P.n_sub), 256, sm, s>>>(P, setR, k, G);
 }
 
 template <typename T>
@@ -1697,6 +2006,27 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
                     T* scratch, int64_t scr_stride, int* status, int status_code, hipStream_t s,
                     Profiler* prof) {
   if (nprob == 0 || maxp == 0) return;
+  if (maxn <= 16 * RS_MAX_TILES) {
+    // register-resident: one workgroup per matrix, read once, written once
+    double f = 0, by = 0;
+    if (prof && h_desc)
+      for (int q = 0; q < nprob; ++q) {
+        const double n = h_desc[q].n, p = h_desc[q].p;
+        f += n * n * p;
+        by += sizeof(T) * (n * (n + 1) / 2 + n * n);
+      }
+    if (prof) prof->begin(5, s);
+    // waves per workgroup: more waves for mid sizes, where the tiles per wave
+    // and so the registers per lane stay low enough
+    const int mt = (int)cdiv(maxn, 16);
+    if (mt <= 4) k_sweep_reg<T, 4, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code);
+    else if (mt <= 8) k_sweep_reg<T, 8, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code);
+    else if (mt <= 11) k_sweep_reg<T, 11, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code);
+    else if (mt <= 12) k_sweep_reg<T, 12, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code);
+    else k_sweep_reg<T, RS_MAX_TILES, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code);
+    if (prof) prof->end(5, f, by, s);
+    return;
+  }
   const int64_t tiles = cdiv(maxn, TILE);
   const dim3 pgrid(cdiv(maxn, SWEEP_ROWS), nprob);
   const size_t psm = (size_t)hmin(maxn, SWEEP_ROWS) * (SWEEP_NB + 1) * sizeof(T);

@@ -172,7 +172,7 @@ class Preconditioner:
         return {"n_coarse": nc.value, "n_fronts": nf.value, "device_bytes": nb.value,
                 "coarse_factor_entries": ce.value}
 
-    KERNEL_CLASSES = {"sweep_update": 1, "block_solve": 2, "gemm": 3, "sweep_panel": 4}
+    KERNEL_CLASSES = {"sweep_update": 1, "block_solve": 2, "gemm": 3, "sweep_panel": 4, "sweep_small": 5}
 
     def profile(self, classes=None) -> None:
         """Start event timing of the named kernel classes (all when None); [] stops it."""
