@@ -322,7 +322,7 @@ void alloc_numeric(bddcso_precond* pc, hipStream_t s) {
   N.tmp_stride = (int64_t)pl.max_block * std::max(pl.max_zcols, 1);
   N.tmp = m.alloc<T>(N.tmp_stride * pl.subs.size());
   int maxsw = std::max(pl.max_block, pl.max_na);
-  N.sw_stride = 2 * ((int64_t)maxsw * kSweepNB + kSweepNB * kSweepNB);
+  N.sw_stride = std::max<int64_t>(2 * ((int64_t)maxsw * kSweepNB + kSweepNB * kSweepNB), (int64_t)maxsw * kSlab);
   N.sw = m.alloc<T>(N.sw_stride * pl.subs.size());
   N.sw2 = m.alloc<T>(N.sw_stride * pl.subs.size());
   N.vI = m.alloc<T>(pl.tot_I * nr);
@@ -446,7 +446,8 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
   }
   int maxlev = 1;
   for (int L = 0; L < nlev; ++L) maxlev = std::max(maxlev, pc->level_n[L]);
-  pc->fsw_stride = 2 * ((int64_t)std::max(maxfn, 1) * kSweepNB + kSweepNB * kSweepNB);
+  pc->fsw_stride = std::max<int64_t>(2 * ((int64_t)std::max(maxfn, 1) * kSweepNB + kSweepNB * kSweepNB),
+                                     (int64_t)std::max(maxfn, 1) * kSlab);
   pc->fsw = m.alloc<double>(pc->fsw_stride * maxlev);
 }
 

@@ -11,6 +11,9 @@ namespace bddcso {
 // Pivots per panel of the batched sweeps (scratch per matrix: 2 slots of
 // n x kSweepNB + kSweepNB^2 entries).
 constexpr int kSweepNB = 32;
+// Pivots per slab when sweeping matrices above 272 rows; their scratch needs
+// n x kSlab entries per matrix.
+constexpr int kSlab = 192;
 
 // Geometry passed by value to kernels.
 struct Geo {

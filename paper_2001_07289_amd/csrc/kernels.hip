@@ -395,6 +395,143 @@ __device__ __forceinline__ T* sweep_slot(T* scratch, int64_t scr_stride, int pro
   return scratch + prob * scr_stride + ((j0 / SWEEP_NB) & 1) * (scr_stride / 2);
 }
 
+// Wave-uniform broadcast of lane l's value (l a compile-time or uniform index).
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+// 1/x by the hardware reciprocal refined with two Newton steps
+// (r <- r + r (1 - x r)), accurate to the last bit or one ulp.
+__device__ __forceinline__ double recip_f64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+// Lane l of a wave reads lane Q of its own row of 16 lanes (DPP row share).
+template <int Q>
+__device__ __forceinline__ double row_share_f64(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x150 + Q, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x150 + Q, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// One pivot step of the 16x16 sweep below.
+template <int Q>
+__device__ __forceinline__ void sweep16_step(double m[4], int jb, int kq, int rr, bool& bad) {
+  double dq = readlane_f64(m[Q & 3], (Q >> 2) * 16 + Q);        // X[Q][Q]
+  if (!(dq > 0.0)) {
+    if (Q < jb) bad = true;
+    dq = 1.0;
+  }
+  const double inv = recip_f64(dq);
+  const double rowq = __shfl(m[Q & 3], (Q >> 2) * 16 + rr, 64);  // X[Q][rr]
+  const double rs = rowq * inv;
+  const bool qcol = rr == Q, qrow = kq == (Q >> 2);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const double colq = row_share_f64<Q>(m[t]);                   // X[4kq+t][Q]
+    const double upd = qcol ? colq * inv : m[t] - colq * rs;
+    m[t] = (t == (Q & 3) && qrow) ? (qcol ? -inv : rs) : upd;
+  }
+}
+
+template <int... Qs>
+__device__ __forceinline__ void sweep16_all(double m[4], int jb, int kq, int rr, bool& bad,
+                                            std::integer_sequence<int, Qs...>) {
+  (sweep16_step<Qs>(m, jb, kq, rr, bad), ...);
+}
+
+// A wave holds a 16x16 symmetric block X as m[t] = X[4 kq + t][rr]
+// (kq = lane/16, rr = lane%16).  Sweeps pivots 0..15 (pivots >= jb are
+// identity padding).  Per pivot q: X[q][q] comes by a wave-uniform
+// broadcast, the pivot column X[4 kq + t][q] from lane q of the lane's own
+// row of 16 (DPP), the pivot row X[q][rr] by one cross-lane permute.  On
+// return m holds the swept block (-X^{-1} on the pivots).  Returns true on a
+// pivot <= 0.
+__device__ __forceinline__ bool quad_sweep16(double m[4], int jb, int lane) {
+  bool bad = false;
+  sweep16_all(m, jb, lane >> 4, lane & 15, bad, std::make_integer_sequence<int, 16>{});
+  return bad;
+}
+
+// Sweeps a 32x32 symmetric block held in LDS at D (row i at D + i*ld; jb
+// used pivots, the rest padded with the identity) by one wave, as two 16x16
+// pivot sweeps and 16x16 MFMA products:
+//   N11 = -D11^{-1};  T = D21 D11^{-1};  S = D22 - T D21^T;  N22 = -S^{-1};
+//   V = N22 T;  result [N11 + T^T V, -V^T; -V, N22]  (= -D^{-1}).
+// T points to 32 x 33 doubles of LDS scratch.  No workgroup barrier: LDS
+// accesses of one wave are ordered.  Returns true on a pivot <= 0.
+__device__ bool sweep32_fast(double* D, int ld, double* T, int jb, int lane) {
+  typedef Mfma<double>::acc_t acc_t;
+  const int kq = lane >> 4, rr = lane & 15;
+  auto at = [&](int i, int j) -> double& { return D[i * ld + j]; };
+  auto tt = [&](int i, int j) -> double& { return T[i * 33 + j]; };
+  bool bad = false;
+  double m[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) m[t] = at(4 * kq + t, rr);
+  bad |= quad_sweep16(m, min(jb, 16), lane);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) at(4 * kq + t, rr) = m[t];  // N11
+  __builtin_amdgcn_wave_barrier();
+  // T = D21 (-N11)
+  acc_t c = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) c = Mfma<double>::mac(at(16 + rr, 4 * s4 + kq), -at(4 * s4 + kq, rr), c);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) tt(Mfma<double>::row(kq, r), rr) = c[r];
+  __builtin_amdgcn_wave_barrier();
+  // S = D22 - T D21^T, written over D22
+  c = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) c = Mfma<double>::mac(tt(rr, 4 * s4 + kq), at(16 + rr, 4 * s4 + kq), c);
+  double sv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) sv[r] = at(16 + Mfma<double>::row(kq, r), 16 + rr) - c[r];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) at(16 + Mfma<double>::row(kq, r), 16 + rr) = sv[r];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int t = 0; t < 4; ++t) m[t] = at(16 + 4 * kq + t, 16 + rr);
+  bad |= quad_sweep16(m, max(jb - 16, 0), lane);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) at(16 + 4 * kq + t, 16 + rr) = m[t];  // N22
+  __builtin_amdgcn_wave_barrier();
+  // V = N22 T, into T's rows 16..31
+  c = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) c = Mfma<double>::mac(at(16 + rr, 16 + 4 * s4 + kq), tt(4 * s4 + kq, rr), c);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) tt(16 + Mfma<double>::row(kq, r), rr) = c[r];
+  __builtin_amdgcn_wave_barrier();
+  // D11 = N11 + T^T V;  D21 = -V, D12 = -V^T
+  acc_t w = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) w = Mfma<double>::mac(tt(4 * s4 + kq, rr), tt(16 + 4 * s4 + kq, rr), w);
+  double n11[4], vv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = Mfma<double>::row(kq, r);
+    n11[r] = at(i, rr);
+    vv[r] = tt(16 + i, rr);
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = Mfma<double>::row(kq, r);
+    at(i, rr) = n11[r] + w[r];
+    at(16 + i, rr) = -vv[r];
+    at(rr, 16 + i) = -vv[r];
+  }
+  __builtin_amdgcn_wave_barrier();
+  return bad;
+}
+
 // Sweeps a 32x32 block (jb <= 32 used entries) held in LDS at D (row i at
 // D + i*ld) by one wave, in registers: lane l keeps column l%32, rows
 // 16*(l/32) .. +15.  Each pivot step takes the pivot row and column through
@@ -447,7 +584,7 @@ __device__ __forceinline__ bool wave_sweep32(double* D, int ld, int jb, int lane
 __device__ bool block_sweep(double (*D)[SWEEP_NB + 1], double (*tmp)[33], int jb, int tid, int nthreads) {
   constexpr int ld = SWEEP_NB + 1;
   bool bad = false;
-  if (tid < 64) bad |= wave_sweep32(&D[0][0], ld, min(jb, 32), tid);
+  if (tid < 64) bad |= sweep32_fast(&D[0][0], ld, &tmp[0][0], min(jb, 32), tid);
   __syncthreads();
   if (jb > 32) {
     // T21 = D21 D11^{-1} = -D21 * (swept D11)
@@ -803,73 +940,11 @@ __global__ void k_symmetrize(const SweepDesc* __restrict__ desc, T* pool, int nt
 //      -D^{-1} (the pivot block).
 // Only the lower triangle is read; both triangles are written.
 constexpr int RS_MAX_TILES = 17;  // largest matrix: 272 rows
-
-// Wave-uniform broadcast of lane l's value (l a compile-time or uniform index).
-__device__ __forceinline__ double readlane_f64(double x, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
-  return __hiloint2double(hi, lo);
-}
-
-// 1/x by the hardware reciprocal refined with two Newton steps
-// (r <- r + r (1 - x r)), accurate to the last bit or one ulp.
-__device__ __forceinline__ double recip_f64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
-
-// Lane l of a wave reads lane Q of its own row of 16 lanes (DPP row share).
-template <int Q>
-__device__ __forceinline__ double row_share_f64(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x150 + Q, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x150 + Q, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-
-// One pivot step of the 16x16 sweep below.
-template <int Q>
-__device__ __forceinline__ void sweep16_step(double m[4], int jb, int kq, int rr, bool& bad) {
-  double dq = readlane_f64(m[Q & 3], (Q >> 2) * 16 + Q);        // X[Q][Q]
-  if (!(dq > 0.0)) {
-    if (Q < jb) bad = true;
-    dq = 1.0;
-  }
-  const double inv = recip_f64(dq);
-  const double rowq = __shfl(m[Q & 3], (Q >> 2) * 16 + rr, 64);  // X[Q][rr]
-  const double rs = rowq * inv;
-  const bool qcol = rr == Q, qrow = kq == (Q >> 2);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const double colq = row_share_f64<Q>(m[t]);                   // X[4kq+t][Q]
-    const double upd = qcol ? colq * inv : m[t] - colq * rs;
-    m[t] = (t == (Q & 3) && qrow) ? (qcol ? -inv : rs) : upd;
-  }
-}
-
-template <int... Qs>
-__device__ __forceinline__ void sweep16_all(double m[4], int jb, int kq, int rr, bool& bad,
-                                            std::integer_sequence<int, Qs...>) {
-  (sweep16_step<Qs>(m, jb, kq, rr, bad), ...);
-}
-
-// A wave holds a 16x16 symmetric block X as m[t] = X[4 kq + t][rr]
-// (kq = lane/16, rr = lane%16).  Sweeps pivots 0..15 (pivots >= jb are
-// identity padding).  Per pivot q: X[q][q] comes by a wave-uniform
-// broadcast, the pivot column X[4 kq + t][q] from lane q of the lane's own
-// row of 16 (DPP), the pivot row X[q][rr] by one cross-lane permute.  On
-// return m holds the swept block (-X^{-1} on the pivots).  Returns true on a
-// pivot <= 0.
-__device__ __forceinline__ bool quad_sweep16(double m[4], int jb, int lane) {
-  bool bad = false;
-  sweep16_all(m, jb, lane >> 4, lane & 15, bad, std::make_integer_sequence<int, 16>{});
-  return bad;
-}
+constexpr int SLAB = kSlab;       // pivots per slab of the large-matrix sweep
 
 template <typename T, int MT, int RS_WAVES>
 __global__ __launch_bounds__(RS_WAVES * 64) void k_sweep_reg(const SweepDesc* __restrict__ desc, T* pool,
-                                                             int* status, int status_code) {
+                                                             int* status, int status_code, int slab_j0) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int NTILE = MT * (MT + 1) / 2;
   constexpr int TPW = (NTILE + RS_WAVES - 1) / RS_WAVES;
@@ -879,8 +954,13 @@ __global__ __launch_bounds__(RS_WAVES * 64) void k_sweep_reg(const SweepDesc* __
   __shared__ double Dw[16][17];     // swept pivot block (-D^{-1})
   __shared__ int tab[NTILE];
   const SweepDesc d = desc[blockIdx.x];
-  const int n = d.n, p = d.p, ld = d.ld;
-  T* A = pool + d.off;
+  // slab mode (slab_j0 >= 0): the diagonal block of pivots slab_j0 ..
+  // slab_j0 + SLAB - 1 of the matrix, swept completely
+  const int ld = d.ld;
+  const int n = slab_j0 < 0 ? d.n : min(SLAB, d.p - slab_j0);
+  const int p = slab_j0 < 0 ? d.p : n;
+  if (slab_j0 >= 0 && n <= 0) return;
+  T* A = pool + d.off + (slab_j0 < 0 ? 0 : (int64_t)slab_j0 * (ld + 1));
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int kq = lane >> 4, rr = lane & 15;
@@ -1006,6 +1086,208 @@ __global__ __launch_bounds__(RS_WAVES * 64) void k_sweep_reg(const SweepDesc* __
         if (ti != tj) A[(int64_t)j * ld + i] = acc[sl][r];
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sweep of matrices above 272 rows, by slabs of SLAB pivots S = j0..j0+sb-1.
+// Sweeping S at once equals sweeping its pivots in turn, so per slab:
+//   1. k_sweep_reg (slab mode) replaces M_SS by -M_SS^{-1} in place;
+//   2. k_slab_cd forms CD = M_{:,S} M_SS^{-1} for the rows outside S;
+//   3. k_slab_update applies M_ij -= CD_i M_{j,S}^T to the lower triangle
+//      outside S (rank-sb, on MFMA; M_{j,S} still holds the old values);
+//   4. k_slab_writeback stores CD into the slab's rows and columns.
+// Only the lower triangle is kept current; k_symmetrize mirrors it at the end.
+// CD lives in scratch, n x SLAB per matrix (column-major, ld n).
+
+// C[i][t] = M[i][j0 + t] from the lower triangle (the row panel above j0).
+template <typename T>
+__device__ __forceinline__ T slab_c(const T* A, int ld, int j0, int i, int t) {
+  return i >= j0 ? A[i + (int64_t)ld * (j0 + t)] : A[(j0 + t) + (int64_t)ld * i];
+}
+
+// 2. CD[i][q] = -sum_t C[i][t] W[t][q], W = M_SS after step 1 (= -M_SS^{-1}).
+// One workgroup per (64-row tile, 64-column tile of the slab, matrix).
+template <typename T>
+__global__ __launch_bounds__(256) void k_slab_cd(const SweepDesc* __restrict__ desc, const T* __restrict__ pool,
+                                                 int j0, T* __restrict__ scratch, int64_t scr_stride) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T As[32][TILE + PAD];  // C rows i, K chunk
+  __shared__ T Bs[32][TILE + PAD];  // W columns q, K chunk
+  const SweepDesc d = desc[blockIdx.z];
+  const int n = d.n, ld = d.ld;
+  const int sb = min(SLAB, d.p - j0);
+  if (sb <= 0) return;
+  const int i0 = blockIdx.x * TILE, q0 = blockIdx.y * TILE;
+  if (i0 >= n || q0 >= sb) return;
+  const T* A = pool + d.off;
+  T* CD = scratch + (int64_t)blockIdx.z * scr_stride;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int kq = lane >> 4, rr = lane & 15;
+  const int wi = (wave & 1) * 32, wq = (wave >> 1) * 32;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  for (int k0 = 0; k0 < sb; k0 += 32) {
+    T av[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = tid + u * 256;
+      const int r = idx % TILE, t = idx / TILE;   // 64 rows x 32 K
+      const int i = i0 + r, kk = k0 + t;
+      const bool ok = i < n && kk < sb && !(i >= j0 && i < j0 + sb);
+      av[u] = ok ? slab_c(A, ld, j0, i, kk) : (T)0;
+      const int q = q0 + r;                        // W[kk][q] = M[j0+q][j0+kk] (both triangles valid)
+      bv[u] = (q < sb && kk < sb) ? A[(j0 + q) + (int64_t)ld * (j0 + kk)] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = tid + u * 256;
+      As[idx / TILE][idx % TILE] = av[u];
+      Bs[idx / TILE][idx % TILE] = bv[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int kk = ks * 4 + kq;
+      T x[2], y[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) x[a] = As[kk][wi + a * 16 + rr];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) y[b] = Bs[kk][wq + b * 16 + rr];
+      // output tile transposed (W as the A operand) so lanes run along i
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(y[b], x[a], acc[a][b]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = q0 + wq + b * 16 + Mfma<T>::row(kq, r);
+        const int i = i0 + wi + a * 16 + rr;
+        if (i < n && q < sb && !(i >= j0 && i < j0 + sb)) CD[i + (int64_t)n * q] = -acc[a][b][r];
+      }
+}
+
+// 3. Lower-triangle tiles outside S: M_ij -= sum_q CD[i][q] C[j][q].
+template <typename T>
+__global__ __launch_bounds__(256) void k_slab_update(const SweepDesc* __restrict__ desc, T* pool, int j0,
+                                                     const T* __restrict__ scratch, int64_t scr_stride,
+                                                     int ntri, int nprob) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T As[32][TILE + PAD];  // CD rows i
+  __shared__ T Bs[32][TILE + PAD];  // C rows j
+  const int64_t nblk = gridDim.x;
+  const int64_t glin = blockIdx.x;
+  const int64_t logical = (glin % 8) * (nblk / 8) + glin / 8;  // XCD-aware
+  if (logical >= (int64_t)nprob * ntri) return;
+  const int prob = (int)(logical / ntri);
+  const SweepDesc d = desc[prob];
+  const int n = d.n, ld = d.ld;
+  const int sb = min(SLAB, d.p - j0);
+  if (sb <= 0) return;
+  const int lin = (int)(logical % ntri);
+  int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= lin) ++ti;
+  while (ti * (ti + 1) / 2 > lin) --ti;
+  const int tj = lin - ti * (ti + 1) / 2;
+  const int i0 = ti * TILE, c0 = tj * TILE;
+  if (i0 >= n || c0 >= n) return;
+  // tiles wholly inside the slab rows or columns take no update
+  if ((i0 >= j0 && i0 + TILE <= j0 + sb) || (c0 >= j0 && c0 + TILE <= j0 + sb)) return;
+  T* A = pool + d.off;
+  const T* CD = scratch + (int64_t)prob * scr_stride;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int kq = lane >> 4, rr = lane & 15;
+  const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  for (int k0 = 0; k0 < sb; k0 += 32) {
+    T av[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = tid + u * 256;
+      const int r = idx % TILE, q = idx / TILE;
+      const int i = i0 + r, j = c0 + r, kk = k0 + q;
+      av[u] = (i < n && kk < sb && !(i >= j0 && i < j0 + sb)) ? CD[i + (int64_t)n * kk] : (T)0;
+      bv[u] = (j < n && kk < sb && !(j >= j0 && j < j0 + sb)) ? slab_c(A, ld, j0, j, kk) : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = tid + u * 256;
+      As[idx / TILE][idx % TILE] = av[u];
+      Bs[idx / TILE][idx % TILE] = bv[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int kk = ks * 4 + kq;
+      T x[2], y[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) x[a] = As[kk][wi + a * 16 + rr];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) y[b] = Bs[kk][wj + b * 16 + rr];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(y[b], x[a], acc[a][b]);
+    }
+  }
+  T old[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = c0 + wj + b * 16 + Mfma<T>::row(kq, r);
+        const int i = i0 + wi + a * 16 + rr;
+        const bool on = i < n && j <= i && !(i >= j0 && i < j0 + sb) && !(j >= j0 && j < j0 + sb);
+        old[a][b][r] = on ? A[i + (int64_t)ld * j] : (T)0;
+      }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = c0 + wj + b * 16 + Mfma<T>::row(kq, r);
+        const int i = i0 + wi + a * 16 + rr;
+        if (i < n && j <= i && !(i >= j0 && i < j0 + sb) && !(j >= j0 && j < j0 + sb))
+          A[i + (int64_t)ld * j] = old[a][b][r] - acc[a][b][r];
+      }
+}
+
+// 4. The slab's rows and columns outside S become CD (lower triangle).
+template <typename T>
+__global__ void k_slab_writeback(const SweepDesc* __restrict__ desc, T* pool, int j0, const T* __restrict__ scratch,
+                                 int64_t scr_stride) {
+  const SweepDesc d = desc[blockIdx.y];
+  const int n = d.n, ld = d.ld;
+  const int sb = min(SLAB, d.p - j0);
+  if (sb <= 0) return;
+  T* A = pool + d.off;
+  const T* CD = scratch + (int64_t)blockIdx.y * scr_stride;
+  const int64_t tot = (int64_t)n * sb;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % n), q = (int)(idx / n);
+    if (i >= j0 && i < j0 + sb) continue;
+    const T v = CD[i + (int64_t)n * q];
+    if (i > j0) A[i + (int64_t)ld * (j0 + q)] = v;
+    else A[(j0 + q) + (int64_t)ld * i] = v;
   }
 }
 
@@ -2019,12 +2301,46 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
     // waves per workgroup: more waves for mid sizes, where the tiles per wave
     // and so the registers per lane stay low enough
     const int mt = (int)cdiv(maxn, 16);
-    if (mt <= 4) k_sweep_reg<T, 4, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code);
-    else if (mt <= 8) k_sweep_reg<T, 8, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code);
-    else if (mt <= 11) k_sweep_reg<T, 11, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code);
-    else if (mt <= 12) k_sweep_reg<T, 12, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code);
-    else k_sweep_reg<T, RS_MAX_TILES, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code);
+    if (mt <= 4) k_sweep_reg<T, 4, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
+    else if (mt <= 8) k_sweep_reg<T, 8, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
+    else if (mt <= 11) k_sweep_reg<T, 11, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
+    else if (mt <= 12) k_sweep_reg<T, 12, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
+    else k_sweep_reg<T, RS_MAX_TILES, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
     if (prof) prof->end(5, f, by, s);
+    return;
+  }
+  if (scr_stride >= (int64_t)maxn * SLAB) {
+    // slabs of SLAB pivots: register sweep of the diagonal block, CD, rank-SLAB update
+    static_assert(SLAB <= 16 * 12, "slab diagonal blocks use the 12-tile register sweep");
+    const int64_t tiles = cdiv(maxn, TILE);
+    const int64_t ntri = tiles * (tiles + 1) / 2;
+    for (int j0 = 0; j0 < maxp; j0 += SLAB) {
+      double cf = 0, cb = 0, uf = 0, ub = 0;
+      if (prof && h_desc)
+        for (int q = 0; q < nprob; ++q) {
+          const double n = h_desc[q].n, p = h_desc[q].p;
+          if (j0 >= p) continue;
+          const double sb = std::min<double>(SLAB, p - j0), m = n - sb;
+          const double low = m * (m + 1) / 2;
+          cf += 2.0 * m * sb * sb;
+          cb += sizeof(T) * (2.0 * m * sb + sb * sb);
+          uf += 2.0 * sb * low;
+          ub += sizeof(T) * (2.0 * low + 2.0 * m * sb);
+        }
+      if (prof) prof->begin(4, s);
+      k_sweep_reg<T, 12, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code, j0);
+      k_slab_cd<T><<<dim3(cdiv(maxn, TILE), cdiv(SLAB, TILE), nprob), 256, 0, s>>>(d_desc, pool, j0, scratch,
+                                                                                  scr_stride);
+      if (prof) prof->end(4, cf, cb, s);
+      if (prof) prof->begin(1, s);
+      k_slab_update<T><<<(unsigned)((ntri * nprob + 7) / 8 * 8), 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride,
+                                                                              (int)ntri, nprob);
+      if (prof) prof->end(1, uf, ub, s);
+      k_slab_writeback<T><<<dim3((unsigned)hmin(cdiv((int64_t)maxn * SLAB, 256), 2048), nprob), 256, 0, s>>>(
+          d_desc, pool, j0, scratch, scr_stride);
+    }
+    const int64_t st = cdiv(maxn, 32);
+    k_symmetrize<T><<<dim3((unsigned)hmin(st * (st + 1) / 2, 4096), nprob), 256, 0, s>>>(d_desc, pool, 0);
     return;
   }
   const int64_t tiles = cdiv(maxn, TILE);
