@@ -1809,6 +1809,123 @@ __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, Geo g, co
   }
 }
 
+// The same block-tridiagonal solve for many right-hand sides at once: one
+// workgroup per (subdomain, group of MR_COLS right-hand sides), so each G_k
+// is streamed from HBM once per group.  The products G_k C (C: the block's
+// right-hand sides, size x MR_COLS, staged in LDS) run on MFMA: a wave owns
+// 16 rows of the output and all MR_COLS columns, and each A-operand load of
+// G feeds MR_COLS / 16 MFMAs.
+constexpr int MR_COLS = 32;
+constexpr int MR_THREADS = 512;
+
+template <typename T>
+__device__ __forceinline__ void block_gemm_mr(const T* __restrict__ M, int s, int ncols, int nrows,
+                                              const T (*cl)[MR_COLS + 1], T* __restrict__ v, int64_t vstride,
+                                              int nr, bool accumulate, T sign, int wave, int lane) {
+  // v[r][i] (+)= sign * sum_{j < ncols} M[i + s j] cl[j][r],  i < nrows, r < nr
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int kq = lane >> 4, rr = lane & 15;
+  for (int rt = wave; rt * 16 < nrows; rt += MR_THREADS / 64) {
+    const int row = rt * 16 + rr;
+    const bool rok = row < nrows;
+    acc_t acc[MR_COLS / 16];
+#pragma unroll
+    for (int c = 0; c < MR_COLS / 16; ++c) acc[c] = acc_t{0, 0, 0, 0};
+    int k0 = 0;
+    for (; k0 + 16 <= ncols; k0 += 16) {
+      T a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = rok ? M[row + (int64_t)s * (k0 + 4 * u + kq)] : (T)0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < MR_COLS / 16; ++c)
+          acc[c] = Mfma<T>::mac(a[u], cl[k0 + 4 * u + kq][16 * c + rr], acc[c]);
+    }
+    for (; k0 < ncols; k0 += 4) {
+      const int kk = k0 + kq;
+      const T a = (rok && kk < ncols) ? M[row + (int64_t)s * kk] : (T)0;
+#pragma unroll
+      for (int c = 0; c < MR_COLS / 16; ++c)
+        acc[c] = Mfma<T>::mac(a, kk < ncols ? cl[kk][16 * c + rr] : (T)0, acc[c]);
+    }
+    // lane holds D[row(kq, e)][rr] of each 16 x 16 output block
+#pragma unroll
+    for (int c = 0; c < MR_COLS / 16; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = rt * 16 + Mfma<T>::row(kq, e), r = 16 * c + rr;
+        if (i < nrows && r < nr) {
+          T* dst = v + (int64_t)r * vstride + i;
+          *dst = accumulate ? *dst + sign * acc[c][e] : sign * acc[c][e];
+        }
+      }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(MR_THREADS) void k_block_solve_mr(PlanDev P, int setR, const T* __restrict__ G,
+                                                               T* __restrict__ vec, int nrhs) {
+  extern __shared__ char smem_raw[];
+  T(*cl)[MR_COLS + 1] = reinterpret_cast<T(*)[MR_COLS + 1]>(smem_raw);  // [max_block][cols]
+  const int sub = blockIdx.x, r0 = blockIdx.y * MR_COLS;
+  const int nr = min(MR_COLS, nrhs - r0);
+  const SubDev S = P.subs[sub];
+  const int nb = setR ? S.nbR : S.nbI;
+  const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
+  const int64_t vstride = setR ? P.tot_r : P.tot_I;
+  T* v = vec + (int64_t)r0 * vstride + (setR ? S.r_off : S.I_off);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int k = 0; k < nb; ++k) {
+    const BlockDev B = blk[k];
+    for (int idx = tid; idx < B.size * MR_COLS; idx += MR_THREADS) {
+      const int i = idx % B.size, r = idx / B.size;
+      T c = 0;
+      if (r < nr) {
+        const T* vr = v + (int64_t)r * vstride;
+        c = vr[B.start + i];
+        if (B.cf_off >= 0 && i < B.first_n) {
+          const int64_t row = B.cf_off + i;
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < 9; ++t) {
+            const int j = P.cpl_rank[row * 9 + t];
+            if (j >= 0) acc += P.cpl_coef[row * 9 + t] * (double)vr[j];
+          }
+          c -= (T)acc;
+        }
+      }
+      cl[i][r] = c;
+    }
+    __syncthreads();
+    block_gemm_mr(G + B.G_off, B.size, B.size, B.size, cl, v + B.start, vstride, nr, false, (T)-1, wave, lane);
+    __syncthreads();
+  }
+  for (int k = nb - 2; k >= 0; --k) {
+    const BlockDev B = blk[k];
+    if (B.cb_off < 0) continue;
+    const int base = B.size - B.last_n;
+    for (int idx = tid; idx < B.last_n * MR_COLS; idx += MR_THREADS) {
+      const int i = idx % B.last_n, r = idx / B.last_n;
+      double acc = 0.0;
+      if (r < nr) {
+        const T* vr = v + (int64_t)r * vstride;
+        const int64_t row = B.cb_off + i;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int j = P.cpl_rank[row * 9 + t];
+          if (j >= 0) acc += P.cpl_coef[row * 9 + t] * (double)vr[j];
+        }
+      }
+      cl[i][r] = (T)acc;
+    }
+    __syncthreads();
+    block_gemm_mr(G + B.G_off + (int64_t)B.size * base, B.size, B.last_n, B.size, cl, v + B.start, vstride, nr,
+                  true, (T)1, wave, lane);
+    __syncthreads();
+  }
+}
+
 // q[e] = (K_{Gamma I} y_I)[e] for the Gamma entries of each subdomain.
 template <typename T>
 __global__ void k_gamma_kgi(PlanDev P, Geo g, const double* __restrict__ rho, const T* __restrict__ vI,
@@ -2084,6 +2201,207 @@ __global__ __launch_bounds__(256) void k_front_bwd(PlanDev P, const int32_t* __r
     uc[rhs * P.n_coarse + P.front_idx[F.idx_off + k]] = xh[rhs * stride + F.voff + k] - acc;
 }
 
+// ---- products with many right-hand sides ----------------------------------
+// The per-iteration products with the coarse basis rows (Phi_Gamma, X_Gamma)
+// and with the coarse fronts, for groups of MR_COLS right-hand sides: one
+// workgroup takes 64 output rows (4 waves x 16) and the group's columns; the
+// right-hand sides are staged in LDS in chunks of MR_KC rows and each A
+// element read from HBM feeds MR_COLS / 16 MFMAs.
+constexpr int MR_KC = 128;
+
+// acc[c] += sum_{k < kn} a(k) * Bs[k][16 c + rr]   (one wave, 16 output rows)
+template <typename T, typename AF>
+__device__ __forceinline__ void mr_accum(AF a_of, bool rok, int kn, const T (*Bs)[MR_COLS + 1],
+                                         typename Mfma<T>::acc_t* acc, int kq, int rr) {
+#pragma unroll 8
+  for (int k4 = 0; k4 < MR_KC / 4; ++k4) {
+    if (4 * k4 >= kn) break;
+    const int k = 4 * k4 + kq;
+    const T a = (rok && k < kn) ? a_of(k) : (T)0;
+#pragma unroll
+    for (int c = 0; c < MR_COLS / 16; ++c) acc[c] = Mfma<T>::mac(a, Bs[k][16 * c + rr], acc[c]);
+  }
+}
+
+// Coarse right-hand side of each subdomain: bci[c] = sum_e PhiG[e][c] g[e].
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_rhs_local_mr(PlanDev P, const T* __restrict__ PhiG,
+                                                             const T* __restrict__ gv, T* __restrict__ bci,
+                                                             int nrhs) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T Bs[MR_KC][MR_COLS + 1];
+  const int sub = blockIdx.y, r0 = blockIdx.z * MR_COLS, nr = min(MR_COLS, nrhs - r0);
+  const SubDev S = P.subs[sub];
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= S.n_c) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kq = lane >> 4, rr = lane & 15;
+  const int c = c0 + wave * 16 + rr;
+  const bool rok = c < S.n_c;
+  const T* M = PhiG + S.PhiG_off + (int64_t)S.n_g * c;
+  acc_t acc[MR_COLS / 16];
+#pragma unroll
+  for (int q = 0; q < MR_COLS / 16; ++q) acc[q] = acc_t{0, 0, 0, 0};
+  for (int kb = 0; kb < S.n_g; kb += MR_KC) {
+    const int kn = min(MR_KC, S.n_g - kb);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MR_KC * MR_COLS / 256; ++u) {
+      const int idx = tid + u * 256, k = idx % MR_KC, r = idx / MR_KC;
+      Bs[k][r] = (k < kn && r < nr) ? gv[(int64_t)(r0 + r) * P.tot_g + S.g_off + kb + k] : (T)0;
+    }
+    __syncthreads();
+    mr_accum<T>([&](int k) { return M[kb + k]; }, rok, kn, Bs, acc, kq, rr);
+  }
+#pragma unroll
+  for (int q = 0; q < MR_COLS / 16; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int cc = c0 + wave * 16 + Mfma<T>::row(kq, e), r = 16 * q + rr;
+      if (cc < S.n_c && r < nr) bci[(int64_t)(r0 + r) * P.tot_c + S.c_off + cc] = acc[q][e];
+    }
+}
+
+// v2 on Gamma = u - X_Gamma mu + Phi_Gamma u_c, for 64 Gamma rows per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_v2_mr(PlanDev P, const T* __restrict__ vR, const T* __restrict__ XG,
+                                               const T* __restrict__ mu, const T* __restrict__ PhiG,
+                                               const double* __restrict__ uc, T* __restrict__ v2, int nrhs) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T Bs[MR_KC][MR_COLS + 1];
+  const int sub = blockIdx.y, r0 = blockIdx.z * MR_COLS, nr = min(MR_COLS, nrhs - r0);
+  const SubDev S = P.subs[sub];
+  const int e0 = blockIdx.x * 64;
+  if (e0 >= S.n_g) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kq = lane >> 4, rr = lane & 15;
+  const int e = e0 + wave * 16 + rr;
+  const bool rok = e < S.n_g;
+  acc_t acc[MR_COLS / 16];
+#pragma unroll
+  for (int q = 0; q < MR_COLS / 16; ++q) acc[q] = acc_t{0, 0, 0, 0};
+  for (int kb = 0; kb < S.n_c; kb += MR_KC) {   // + Phi_Gamma u_c
+    const int kn = min(MR_KC, S.n_c - kb);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MR_KC * MR_COLS / 256; ++u) {
+      const int idx = tid + u * 256, k = idx % MR_KC, r = idx / MR_KC;
+      Bs[k][r] = (k < kn && r < nr) ? (T)uc[(int64_t)(r0 + r) * P.n_coarse + P.c_glob[S.c_off + kb + k]] : (T)0;
+    }
+    __syncthreads();
+    const T* M = PhiG + S.PhiG_off + e + (int64_t)S.n_g * kb;
+    mr_accum<T>([&](int k) { return M[(int64_t)S.n_g * k]; }, rok, kn, Bs, acc, kq, rr);
+  }
+  for (int kb = 0; kb < S.n_a; kb += MR_KC) {   // - X_Gamma mu
+    const int kn = min(MR_KC, S.n_a - kb);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MR_KC * MR_COLS / 256; ++u) {
+      const int idx = tid + u * 256, k = idx % MR_KC, r = idx / MR_KC;
+      Bs[k][r] = (k < kn && r < nr) ? -mu[(int64_t)(r0 + r) * P.tot_a + S.am_off + kb + k] : (T)0;
+    }
+    __syncthreads();
+    const T* M = XG + S.XG_off + e + (int64_t)S.n_g * kb;
+    mr_accum<T>([&](int k) { return M[(int64_t)S.n_g * k]; }, rok, kn, Bs, acc, kq, rr);
+  }
+#pragma unroll
+  for (int q = 0; q < MR_COLS / 16; ++q)
+#pragma unroll
+    for (int ee = 0; ee < 4; ++ee) {
+      const int row = e0 + wave * 16 + Mfma<T>::row(kq, ee), r = 16 * q + rr;
+      if (row < S.n_g && r < nr) {
+        const int rx = P.g_r[S.g_off + row];
+        const T base = rx >= 0 ? vR[(int64_t)(r0 + r) * P.tot_r + S.r_off + rx] : (T)0;
+        v2[(int64_t)(r0 + r) * P.tot_g + S.g_off + row] = base + acc[q][ee];
+      }
+    }
+}
+
+// Front forward step for many right-hand sides: z = F[:, :p] y_P; rows < p
+// give xh_P = -z_P, rows >= p update y_B -= z_B.
+__global__ __launch_bounds__(256) void k_front_fwd_mr(PlanDev P, const int32_t* __restrict__ fr,
+                                                      const double* __restrict__ fpool, double* __restrict__ fvec,
+                                                      double* __restrict__ xh, int64_t stride, int nrhs) {
+  typedef Mfma<double>::acc_t acc_t;
+  __shared__ double Bs[MR_KC][MR_COLS + 1];
+  const FrontDev F = P.fronts[fr[blockIdx.y]];
+  const int r0 = blockIdx.z * MR_COLS, nr = min(MR_COLS, nrhs - r0);
+  const int i0 = blockIdx.x * 64;
+  if (i0 >= F.n || F.p == 0) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kq = lane >> 4, rr = lane & 15;
+  const int row = i0 + wave * 16 + rr;
+  const bool rok = row < F.n;
+  acc_t acc[MR_COLS / 16];
+#pragma unroll
+  for (int q = 0; q < MR_COLS / 16; ++q) acc[q] = acc_t{0, 0, 0, 0};
+  for (int kb = 0; kb < F.p; kb += MR_KC) {
+    const int kn = min(MR_KC, F.p - kb);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MR_KC * MR_COLS / 256; ++u) {
+      const int idx = tid + u * 256, k = idx % MR_KC, r = idx / MR_KC;
+      Bs[k][r] = (k < kn && r < nr) ? fvec[(int64_t)(r0 + r) * stride + F.voff + kb + k] : 0.0;
+    }
+    __syncthreads();
+    const double* M = fpool + F.off + row + (int64_t)F.n * kb;
+    mr_accum<double>([&](int k) { return M[(int64_t)F.n * k]; }, rok, kn, Bs, acc, kq, rr);
+  }
+  __syncthreads();  // every workgroup of this front reads rows < p only; rows >= p are written below
+#pragma unroll
+  for (int q = 0; q < MR_COLS / 16; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = i0 + wave * 16 + Mfma<double>::row(kq, e), r = 16 * q + rr;
+      if (i < F.n && r < nr) {
+        const int64_t at = (int64_t)(r0 + r) * stride + F.voff + i;
+        if (i < F.p) xh[at] = -acc[q][e];
+        else fvec[at] -= acc[q][e];
+      }
+    }
+}
+
+// Front backward step for many right-hand sides: x_P = xh_P - L~^T x_B with
+// x_B (the ancestors' coarse unknowns) gathered from u_c.
+__global__ __launch_bounds__(256) void k_front_bwd_mr(PlanDev P, const int32_t* __restrict__ fr,
+                                                      const double* __restrict__ fpool,
+                                                      const double* __restrict__ xh, int64_t stride,
+                                                      double* __restrict__ uc, int nrhs) {
+  typedef Mfma<double>::acc_t acc_t;
+  __shared__ double Bs[MR_KC][MR_COLS + 1];
+  const FrontDev F = P.fronts[fr[blockIdx.y]];
+  const int r0 = blockIdx.z * MR_COLS, nr = min(MR_COLS, nrhs - r0);
+  const int i0 = blockIdx.x * 64;
+  if (i0 >= F.p) return;
+  const int nb = F.n - F.p;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kq = lane >> 4, rr = lane & 15;
+  const int row = i0 + wave * 16 + rr;   // pivot index
+  const bool rok = row < F.p;
+  acc_t acc[MR_COLS / 16];
+#pragma unroll
+  for (int q = 0; q < MR_COLS / 16; ++q) acc[q] = acc_t{0, 0, 0, 0};
+  for (int kb = 0; kb < nb; kb += MR_KC) {
+    const int kn = min(MR_KC, nb - kb);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MR_KC * MR_COLS / 256; ++u) {
+      const int idx = tid + u * 256, k = idx % MR_KC, r = idx / MR_KC;
+      Bs[k][r] = (k < kn && r < nr)
+                     ? uc[(int64_t)(r0 + r) * P.n_coarse + P.front_idx[F.idx_off + F.p + kb + k]] : 0.0;
+    }
+    __syncthreads();
+    // L~^T[row][b] = F[p + b][row]
+    const double* M = fpool + F.off + F.p + kb + (int64_t)F.n * row;
+    mr_accum<double>([&](int k) { return M[k]; }, rok, kn, Bs, acc, kq, rr);
+  }
+#pragma unroll
+  for (int q = 0; q < MR_COLS / 16; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = i0 + wave * 16 + Mfma<double>::row(kq, e), r = 16 * q + rr;
+      if (i < F.p && r < nr)
+        uc[(int64_t)(r0 + r) * P.n_coarse + P.front_idx[F.idx_off + i]] =
+            xh[(int64_t)(r0 + r) * stride + F.voff + i] - acc[q][e];
+    }
+}
+
 // ---- PCG vectors ----------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ a,
@@ -2230,6 +2548,7 @@ int64_t max_lds_bytes(const PlanDev& P, int elt) {
   need = hmax(need, mp * (SC_COLS + 1) * elt);                                         // schur couple
   need = hmax(need, mp * (CPL_COLS + 1) * elt);                                        // couple multi
   need = hmax(need, (hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * elt);     // block solve
+  need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);               // many-rhs block solve
   need = hmax(need, (int64_t)(P.max_na + P.max_nc + 1) * elt);                         // v2
   need = hmax(need, (int64_t)hmax(P.max_ng, 1) * elt);                                 // coarse rhs
   need = hmax(need, (int64_t)SWEEP_ROWS * (SWEEP_NB + 1) * elt + 2 * 32 * 33 * 8);   // sweep panel
@@ -2472,9 +2791,14 @@ void Kern<T>::gather_I(const PlanDev& P, const Geo& g, const double* r, T* vI, i
 template <typename T>
 void Kern<T>::block_solve(const PlanDev& P, const Geo& g, const double* rho, int setR, const T* G,
                           T* v, int nrhs, hipStream_t s, Profiler* prof, double g_entries, double vec_entries) {
-  size_t sm = (size_t)(hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * sizeof(T);
   if (prof) prof->begin(2, s);
-  k_block_solve<T><<<dim3(P.n_sub, nrhs), BS_THREADS, sm, s>>>(P, g, rho, setR, G, v);
+  if (nrhs >= 4) {
+    const size_t smr = (size_t)hmax(P.max_block, 1) * (MR_COLS + 1) * sizeof(T);
+    k_block_solve_mr<T><<<dim3(P.n_sub, cdiv(nrhs, MR_COLS)), MR_THREADS, smr, s>>>(P, setR, G, v, nrhs);
+  } else {
+    size_t sm = (size_t)(hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * sizeof(T);
+    k_block_solve<T><<<dim3(P.n_sub, nrhs), BS_THREADS, sm, s>>>(P, g, rho, setR, G, v);
+  }
   // the method must stream each G entry once per launch (2 flops per rhs) and
   // read and write each vector once
   if (prof) prof->end(2, 2.0 * g_entries * nrhs, sizeof(T) * (g_entries + 2.0 * vec_entries * nrhs), s);
@@ -2509,6 +2833,11 @@ void Kern<T>::mu(const PlanDev& P, const T* vR, const T* Sc, T* mu_out, int nrhs
 template <typename T>
 void Kern<T>::coarse_rhs_local(const PlanDev& P, const T* PhiG, const T* gv, T* bci, int nrhs, hipStream_t s) {
   if (P.max_nc == 0) return;
+  if (nrhs >= 4) {
+    k_coarse_rhs_local_mr<T><<<dim3(cdiv(P.max_nc, 64), P.n_sub, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, PhiG, gv, bci,
+                                                                                                  nrhs);
+    return;
+  }
   k_coarse_rhs_local<T><<<dim3(cdiv(P.max_nc, CRL_COLS), P.n_sub, nrhs), 256, (size_t)hmax(P.max_ng, 1) * sizeof(T), s>>>(
       P, PhiG, gv, bci);
 }
@@ -2517,6 +2846,11 @@ template <typename T>
 void Kern<T>::v2(const PlanDev& P, const T* vR, const T* XG, const T* mu_in, const T* PhiG, const double* uc,
                  T* v2_out, int nrhs, hipStream_t s) {
   if (P.max_ng == 0) return;
+  if (nrhs >= 4) {
+    k_v2_mr<T><<<dim3(cdiv(P.max_ng, 64), P.n_sub, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, vR, XG, mu_in, PhiG, uc,
+                                                                                     v2_out, nrhs);
+    return;
+  }
   size_t sm = (size_t)(P.max_na + P.max_nc + 1) * sizeof(T);
   k_v2<T><<<dim3(cdiv(P.max_ng, 256), P.n_sub, nrhs), 256, sm, s>>>(P, vR, XG, mu_in, PhiG, uc, v2_out);
 }
@@ -2568,12 +2902,21 @@ void launch_front_vec_scatter(const PlanDev& P, const int32_t* children, int nch
 void launch_front_fwd(const PlanDev& P, const int32_t* fr, int nfr, int maxn, int maxp, const double* fpool,
                       double* fvec, double* xh, int64_t stride, int nrhs, hipStream_t s) {
   if (nfr == 0 || maxp == 0) return;
+  if (nrhs >= 4) {
+    k_front_fwd_mr<<<dim3(cdiv(maxn, 64), nfr, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, fr, fpool, fvec, xh, stride,
+                                                                                  nrhs);
+    return;
+  }
   k_front_fwd<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, fpool, fvec, xh, stride);
 }
 void launch_front_bwd(const PlanDev& P, const int32_t* fr, int nfr, int maxp, int maxb, const double* fpool,
                       const double* xh, int64_t stride, double* uc, int nrhs, hipStream_t s) {
   (void)maxb;
   if (nfr == 0 || maxp == 0) return;
+  if (nrhs >= 4) {
+    k_front_bwd_mr<<<dim3(cdiv(maxp, 64), nfr, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, fr, fpool, xh, stride, uc, nrhs);
+    return;
+  }
   k_front_bwd<<<dim3(cdiv(maxp, 4), nfr, nrhs), 256, 0, s>>>(P, fr, fpool, xh, stride, uc);
 }
 

@@ -156,3 +156,23 @@ def test_many_rhs_match_single_solves():
         pc1 = m.Preconditioner(prob, dev(p.rho), fixed_iters=st["iters"][k])
         x1, _ = pc1.solve(dev(F[k]))
         assert relerr(Xh[k], host(x1)) <= 1e-12
+
+
+def test_many_rhs_mixed_precision():
+    """Several right-hand sides with FP32 locals (the many-rhs MFMA block
+    solves in FP32): every column reaches the true residual 1e-8 and agrees
+    with the oracle's FP64 solve."""
+    p = W.config2_like(n=24, H=6, L=3, cfg=56)
+    F = W.rng(56, 0).uniform(-1, 1, (6, p.n_free))
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    pc = m.Preconditioner(prob, dev(p.rho), max_nrhs=6, precision=1)
+    X, st = pc.solve(dev(F))
+    Xh = host(X).reshape(6, -1)
+    A = q1.assemble(p.n_el, p.h, p.rho)
+    orc = bddc.from_problem(p)
+    for k in (0, 5):
+        assert np.linalg.norm(F[k] - A @ Xh[k]) <= 1.0001e-8 * np.linalg.norm(F[k])
+        ref = pcg.solve(orc, F[k], rtol=1e-8)
+        assert relerr(Xh[k], ref.x) <= 1e-6
+        assert st["iters"][k] <= ref.iters + 3
