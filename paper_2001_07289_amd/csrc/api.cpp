@@ -208,6 +208,7 @@ struct bddcso_precond {
   int32_t* vcode = nullptr;
   int max_nv = 0;
   double *fpool = nullptr, *fsw = nullptr, *bc = nullptr, *uc = nullptr, *fvec = nullptr, *xh = nullptr;
+  double* fpart = nullptr;  // partial products of the split forward front step (few right-hand sides)
   int64_t fsw_stride = 0;
   int32_t* status = nullptr;
   // batches
@@ -541,7 +542,7 @@ void coarse_solve(bddcso_precond* pc, int nrhs, hipStream_t s) {
       launch_front_vec_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fvec, stride,
                                nrhs, s);
     launch_front_fwd(P, pc->level_dev[L], pc->level_n[L], pc->level_maxn[L], pc->level_maxp[L], pc->fpool,
-                     pc->fvec, pc->xh, stride, nrhs, s);
+                     pc->fvec, pc->xh, stride, nrhs, s, nrhs < 4 ? pc->fpart : nullptr);
   }
   for (int L = nlev - 1; L >= 0; --L)
     launch_front_bwd(P, pc->level_dev[L], pc->level_n[L], pc->level_maxp[L], pc->level_maxb[L], pc->fpool, pc->xh,
@@ -825,6 +826,11 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     pc->uc = m.alloc<double>(pl.n_coarse * nr);
     pc->fvec = m.alloc<double>(pl.front_vec * nr);
     pc->xh = m.alloc<double>(pl.front_vec * nr);
+    {
+      int maxp = 1;
+      for (auto& F : pl.fronts) maxp = std::max(maxp, F.p);
+      pc->fpart = m.alloc<double>((int64_t)front_fwd_chunks(maxp) * std::min(nr, 3) * pl.front_vec);
+    }
     if (o.precision == 1) alloc_numeric<float>(pc, s);
     else alloc_numeric<double>(pc, s);
     build_batches(pc, s);

@@ -128,7 +128,8 @@ void launch_front_vec_scatter(const PlanDev& P, const int32_t* children, int nch
                               double* fvec, int64_t fvec_stride, int nrhs, hipStream_t s);
 void launch_front_fwd(const PlanDev& P, const int32_t* fr, int nfr, int maxn, int maxp,
                       const double* fpool, double* fvec, double* xh, int64_t fvec_stride,
-                      int nrhs, hipStream_t s);
+                      int nrhs, hipStream_t s,
+                      double* part = nullptr);
 void launch_front_bwd(const PlanDev& P, const int32_t* fr, int nfr, int maxp, int maxb,
                       const double* fpool, const double* xh, int64_t fvec_stride, double* uc,
                       int nrhs, hipStream_t s);
@@ -146,6 +147,8 @@ void launch_pcg_p_flex(double* p, const double* z, const double* zdr, const doub
 void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);
 void launch_copy16(const void* a, void* b, int64_t n16, hipStream_t s);
 int64_t max_lds_bytes(const PlanDev& P, int elt);
+// Chunks of pivot columns of the split forward front step (partial-sum rows).
+int front_fwd_chunks(int maxp);
 
 void launch_element_grad(const Geo& g, const double* khat, const double* rho, const double* u,
                          const double* lam, double* out, int nrhs, hipStream_t s);

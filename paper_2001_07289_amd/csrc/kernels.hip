@@ -1397,21 +1397,28 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
   store(0);
   __syncthreads();
   const int cur = 0;
+  // 16x16 sub-tiles of this wave that hold any output (the rest are padding)
+  const bool ra0 = m0 + wr < d.m, ra1 = m0 + wr + 16 < d.m;
+  const bool rb0 = n0 + wc < d.n, rb1 = n0 + wc + 16 < d.n;
   for (int k0 = 0; k0 < d.k; k0 += GBK) {
     const bool more = k0 + GBK < d.k;
     if (more) load(k0 + GBK);  // next chunk in flight while this one is multiplied
+    const int ksteps = min(GBK / 4, (d.k - k0 + 3) / 4);
+    if (ra0 && rb0) {
 #pragma unroll
-    for (int ks = 0; ks < GBK / 4; ++ks) {
-      const int kk = ks * 4 + kq;
-      T av[2], bv[2];
+      for (int ks = 0; ks < GBK / 4; ++ks) {
+        if (ks >= ksteps) break;
+        const int kk = ks * 4 + kq;
+        T av[2], bv[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[cur][kk][wr + a * 16 + rr];
+        for (int a = 0; a < 2; ++a) av[a] = As[cur][kk][wr + a * 16 + rr];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[cur][kk][wc + b * 16 + rr];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::mac(bv[b], av[a], acc[a][b]);
+        for (int b = 0; b < 2; ++b) bv[b] = Bs[cur][kk][wc + b * 16 + rr];
+        acc[0][0] = Mfma<T>::mac(bv[0], av[0], acc[0][0]);
+        if (rb1) acc[0][1] = Mfma<T>::mac(bv[1], av[0], acc[0][1]);
+        if (ra1) acc[1][0] = Mfma<T>::mac(bv[0], av[1], acc[1][0]);
+        if (ra1 && rb1) acc[1][1] = Mfma<T>::mac(bv[1], av[1], acc[1][1]);
+      }
     }
     __syncthreads();
     if (more) store(0);
@@ -2173,6 +2180,56 @@ __global__ __launch_bounds__(256) void k_front_fwd(PlanDev P, const int32_t* __r
   else y[i] -= acc;
 }
 
+// The same forward step split over chunks of FK pivot columns, for one or a
+// few right-hand sides: k_front_fwd_part writes the partial products of
+// each chunk (64 rows x 4 column groups per workgroup, the groups summed in
+// fixed order), k_front_fwd_fin sums the chunks in order and applies them.
+// part[kc][rhs][front row] (kc-major, stride nrhs * stride per chunk).
+constexpr int FK = 256;
+
+__global__ __launch_bounds__(256) void k_front_fwd_part(PlanDev P, const int32_t* __restrict__ fr,
+                                                        const double* __restrict__ fpool,
+                                                        const double* __restrict__ fvec, int64_t stride, int nrhs,
+                                                        double* __restrict__ part) {
+  __shared__ double yl[FK];
+  __shared__ double red[4][64];
+  const FrontDev F = P.fronts[fr[blockIdx.z / nrhs]];
+  const int rhs = blockIdx.z % nrhs;
+  const int i0 = blockIdx.x * 64, kc = blockIdx.y, k0 = kc * FK;
+  if (i0 >= F.n || k0 >= F.p) return;
+  const int kn = min(FK, F.p - k0);
+  const double* y = fvec + rhs * stride + F.voff;
+  for (int j = threadIdx.x; j < FK; j += blockDim.x) yl[j] = j < kn ? y[k0 + j] : 0.0;
+  __syncthreads();
+  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = i0 + r;
+  double acc = 0.0;
+  if (i < F.n) {
+    const double* M = fpool + F.off + i + (int64_t)F.n * k0;
+#pragma unroll 8
+    for (int j = g; j < kn; j += 4) acc += M[(int64_t)F.n * j] * yl[j];
+  }
+  red[g][r] = acc;
+  __syncthreads();
+  if (g == 0 && i < F.n)
+    part[(int64_t)kc * nrhs * stride + rhs * stride + F.voff + i] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+}
+
+__global__ __launch_bounds__(256) void k_front_fwd_fin(PlanDev P, const int32_t* __restrict__ fr,
+                                                       double* __restrict__ fvec, double* __restrict__ xh,
+                                                       int64_t stride, int nrhs, const double* __restrict__ part) {
+  const FrontDev F = P.fronts[fr[blockIdx.y]];
+  const int rhs = blockIdx.z;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= F.n || F.p == 0) return;
+  const int nkc = (F.p + FK - 1) / FK;
+  double z = 0.0;
+  for (int kc = 0; kc < nkc; ++kc) z += part[(int64_t)kc * nrhs * stride + rhs * stride + F.voff + i];
+  const int64_t at = rhs * stride + F.voff + i;
+  if (i < F.p) xh[at] = -z;
+  else fvec[at] -= z;
+}
+
 // x_P = xh_P - L~^T x_B, x_B from ancestors; one wave per pivot column.
 __global__ __launch_bounds__(256) void k_front_bwd(PlanDev P, const int32_t* __restrict__ fr,
                                                    const double* __restrict__ fpool,
@@ -2542,6 +2599,8 @@ void launch_kc_to_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
 }
 // Largest LDS footprint (static + dynamic, bytes) of any kernel launched for
 // a plan with these maxima and element size; LDS per workgroup is 160 KiB.
+int front_fwd_chunks(int maxp) { return (int)cdiv(maxp, FK); }
+
 int64_t max_lds_bytes(const PlanDev& P, int elt) {
   const int64_t mp = hmax(P.max_plane, 1);
   int64_t need = 0;
@@ -2900,11 +2959,17 @@ void launch_front_vec_scatter(const PlanDev& P, const int32_t* children, int nch
   k_front_vec_scatter<<<dim3(cdiv(maxn, 256), nchild, nrhs), 256, 0, s>>>(P, children, fvec, stride);
 }
 void launch_front_fwd(const PlanDev& P, const int32_t* fr, int nfr, int maxn, int maxp, const double* fpool,
-                      double* fvec, double* xh, int64_t stride, int nrhs, hipStream_t s) {
+                      double* fvec, double* xh, int64_t stride, int nrhs, hipStream_t s, double* part) {
   if (nfr == 0 || maxp == 0) return;
   if (nrhs >= 4) {
     k_front_fwd_mr<<<dim3(cdiv(maxn, 64), nfr, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, fr, fpool, fvec, xh, stride,
                                                                                   nrhs);
+    return;
+  }
+  if (part) {
+    k_front_fwd_part<<<dim3(cdiv(maxn, 64), cdiv(maxp, FK), nfr * nrhs), 256, 0, s>>>(P, fr, fpool, fvec, stride,
+                                                                                      nrhs, part);
+    k_front_fwd_fin<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, fvec, xh, stride, nrhs, part);
     return;
   }
   k_front_fwd<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, fpool, fvec, xh, stride);
