@@ -34,6 +34,12 @@ import numpy as np  # noqa: E402
 import workloads as W  # noqa: E402
 
 HBM_GBS = 8000.0                       # MI355X HBM3E peak, GB/s
+KERNELS_SRC = os.path.join(ROOT, "paper_2001_07289_amd", "csrc", "kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+# kernel-name prefixes of each profiled kernel class
+CLASS_KERNELS = {"sweep_update": ("k_sweep_update", "k_slab_update"), "block_solve": ("k_block_solve",),
+                 "gemm": ("k_gemm",), "sweep_panel": ("k_sweep_panel", "k_slab_cd"),
+                 "sweep_small": ("k_sweep_reg",)}
 MFMA_TFLOPS = {"f64": 78.6, "f32": 157.3}  # dense matrix peaks, TFLOP/s
 
 WORKLOADS = {
@@ -59,7 +65,91 @@ def parse():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the library's copy kernel over MIB MiB (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=5, metavar=("WORKLOAD", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                       "COPY_WRITE_DIR"),
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs (of this bench and of --copy-probe) "
+                         "into per-class HBM bytes per dispatch, printed as the profiles/ text")
     return ap.parse_args()
+
+
+def source_sha():
+    import hashlib
+
+    with open(KERNELS_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def kernel_class(name):
+    import re
+
+    m = re.search(r"\b(k_[A-Za-z0-9_]+)", name)
+    if not m:
+        return None
+    base = m.group(1)
+    for cls, prefixes in CLASS_KERNELS.items():
+        if any(base == p or base.startswith(p + "_") for p in prefixes):
+            return cls
+    return None
+
+
+def pmc_summary(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes):
+    """Per-class mean HBM bytes per dispatch from two counter runs, each counter
+    scaled by what it reads for the library's copy kernel of known size."""
+    import csv
+    import glob
+
+    def rows(d):
+        (path,) = glob.glob(os.path.join(d, "*counter_collection.csv"))
+        return list(csv.DictReader(open(path)))
+
+    def per_class(d):
+        agg = {}
+        for r in rows(d):
+            cls = kernel_class(r["Kernel_Name"])
+            if cls is None:
+                continue
+            a = agg.setdefault(cls, [0, 0.0])
+            a[0] += 1
+            a[1] += float(r["Counter_Value"])
+        return agg
+
+    def copy_kib(d):
+        vals = [float(r["Counter_Value"]) for r in rows(d) if "k_copy16" in r["Kernel_Name"]]
+        return sum(vals) / len(vals)
+
+    cf, cw = copy_kib(copy_fetch_dir), copy_kib(copy_write_dir)
+    ff, fw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    fe, wr = per_class(fetch_dir), per_class(write_dir)
+    lines = [f"source_sha256 {source_sha()}",
+             f"workload {workload}",
+             f"copy_bytes {copy_bytes} fetch_kib {cf:.1f} write_kib {cw:.1f} fetch_factor {ff:.4f} write_factor {fw:.4f}"]
+    for cls in CLASS_KERNELS:
+        if cls not in fe or cls not in wr:
+            continue
+        n = fe[cls][0]
+        fk, wk = fe[cls][1] / n, wr[cls][1] / wr[cls][0]
+        lines.append(f"class {cls} dispatches {n} fetch_kib {fk:.1f} write_kib {wk:.1f} "
+                     f"traffic_bytes {(fk * ff + wk * fw) * 1024.0:.0f}")
+    return "\n".join(lines)
+
+
+def measured_traffic(workload, cls):
+    """HBM bytes per dispatch of a kernel class from the committed counter
+    summary of this workload, or None when there is none or the kernels have
+    changed since the counters were taken."""
+    path = os.path.join(PROFILES, f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    sha, out = None, None
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "source_sha256":
+            sha = f[1]
+        elif f[0] == "class" and f[1] == cls:
+            out = float(f[f.index("traffic_bytes") + 1])
+    return out if sha == source_sha() else None
 
 
 def cpu_baseline():
@@ -80,7 +170,7 @@ def cpu_baseline():
                       f"setup {t1 - t0:.1f} s + PCG {t2 - t1:.1f} s, {r.iters} iterations"}
 
 
-def roofline(prof, dtype):
+def roofline(prof, dtype, workload):
     """Roofline of the dominant kernel class (largest event time in the
     warmup steps), from its events in the timed steps."""
     name = prof["dominant"]
@@ -100,7 +190,7 @@ def roofline(prof, dtype):
     else:
         ach = nbytes / avg_s / 1e9
         out = {"bound": "hbm", "achieved": ach, "peak": HBM_GBS, "unit": "GB/s", "frac": ach / HBM_GBS}
-    out.update({"traffic": None, "kernel": name, "launches": rec["launches"],
+    out.update({"traffic": measured_traffic(workload, name), "kernel": name, "launches": rec["launches"],
                 "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": nbytes,
                 "algorithmic_flops_per_launch": flops})
     return out
@@ -194,6 +284,9 @@ def main():
     if a.copy_probe:
         copy_probe(a.copy_probe)
         return
+    if a.pmc_summary:
+        print(pmc_summary(*a.pmc_summary, copy_bytes=1 << 30))
+        return
     import torch
 
     import paper_2001_07289_amd as pk
@@ -227,7 +320,7 @@ def main():
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     dtype = "f64" if a.precision == "fp64" else "f32"
-    rf = roofline(prof, "f64" if a.precision == "fp64" else "f32")
+    rf = roofline(prof, "f64" if a.precision == "fp64" else "f32", a.workload if a.precision == "fp64" else None)
     warm = prof["warmup"]
     tot = sum(r["total_ms"] for r in warm.values())
     if rf:

@@ -491,8 +491,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   Kern<T>::rhs_fill(P, g, rho, N.Z, s);
   const int nk = (int)pc->gfwd.size();
   for (int k = 0; k < nk; ++k) {
-    if (k > 0) Kern<T>::couple_multi(P, g, rho, k, 1, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
-    Kern<T>::copy_block_rows(P, k, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
+    Kern<T>::couple_multi(P, g, rho, k, 1, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
     const Batch& b = pc->gfwd[k];
     Kern<T>::gemm((GemmDesc*)b.desc, b.hg.data(), b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)-1, (T)0, s,
                   pc->P_());

@@ -85,8 +85,6 @@ struct Kern {
   static void rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, hipStream_t s);
   static void couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
                            int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s);
-  static void copy_block_rows(const PlanDev& P, int k, int ncols_max, const T* Z, T* tmp,
-                              int64_t tmp_stride, hipStream_t s);
   static void sc_assemble(const PlanDev& P, const T* Z, T* Sc, hipStream_t s);
   static void lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s);
   static void phi_r_init(const PlanDev& P, const T* Z, T* PhiR, hipStream_t s);

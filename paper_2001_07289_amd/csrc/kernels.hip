@@ -1440,6 +1440,111 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
       }
 }
 
+// Batched GEMM for problems with at most 176 output rows (non-transposed
+// operands): one workgroup of 16 waves per (problem, 128 output columns)
+// holds its output block in registers, so every A element is read from
+// memory once per 128 columns and every B element once.  The waves form a
+// 4 x 4 grid; wave (wr, wc) owns the row tiles wr + 4i and the column tiles
+// wc + 4j (16 x 16 each).  K goes in chunks of GF_KC through LDS with the
+// next chunk prefetched into registers.
+constexpr int GF_KC = 32;
+constexpr int GF_M = 176, GF_N = 128;
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_gemm_full(const GemmDesc* __restrict__ desc,
+                                                    const T* __restrict__ Ap, const T* __restrict__ Bp,
+                                                    T* __restrict__ Cp, T alpha, T beta) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T As[GF_KC][GF_M + 4];
+  __shared__ T Bs[GF_KC][GF_N + 4];
+  const GemmDesc d = desc[blockIdx.x];
+  const int n0 = blockIdx.y * GF_N;
+  if (d.m <= 0 || n0 >= d.n) return;
+  const int nn = min(GF_N, d.n - n0);
+  const T* A = Ap + d.a;
+  const T* B = Bp + d.b + (int64_t)d.ldb * n0;
+  T* C = Cp + d.c + (int64_t)d.ldc * n0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int kq = lane >> 4, rr = lane & 15;
+  const int wr = wave & 3, wc = wave >> 2;
+  constexpr int PA = (GF_M * GF_KC + 1023) / 1024, PB = GF_N * GF_KC / 1024;
+  T ra[PA], rb[PB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PA; ++u) {
+      const int idx = tid + 1024 * u, i = idx % GF_M, q = idx / GF_M;
+      ra[u] = (q < GF_KC && i < d.m && k0 + q < d.k) ? A[i + (int64_t)d.lda * (k0 + q)] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int idx = tid + 1024 * u, q = idx % GF_KC, j = idx / GF_KC;
+      rb[u] = (j < nn && k0 + q < d.k) ? B[(k0 + q) + (int64_t)d.ldb * j] : (T)0;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < PA; ++u) {
+      const int idx = tid + 1024 * u, i = idx % GF_M, q = idx / GF_M;
+      if (q < GF_KC) As[q][i] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int idx = tid + 1024 * u, q = idx % GF_KC, j = idx / GF_KC;
+      Bs[q][j] = rb[u];
+    }
+  };
+  acc_t acc[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  bool ra_on[3], rb_on[2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ra_on[a] = (wr + 4 * a) * 16 < d.m;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) rb_on[b] = (wc + 4 * b) * 16 < nn;
+  load(0);
+  for (int k0 = 0; k0 < d.k; k0 += GF_KC) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + GF_KC < d.k) load(k0 + GF_KC);
+    const int ksteps = min(GF_KC / 4, (d.k - k0 + 3) / 4);
+#pragma unroll
+    for (int ks = 0; ks < GF_KC / 4; ++ks) {
+      if (ks >= ksteps) break;
+      const int kk = ks * 4 + kq;
+      T av[3], bv[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) av[a] = ra_on[a] ? As[kk][(wr + 4 * a) * 16 + rr] : (T)0;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = rb_on[b] ? Bs[kk][(wc + 4 * b) * 16 + rr] : (T)0;
+      // transposed product (B as the A operand) so each lane's outputs run down a column
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          if (ra_on[a] && rb_on[b]) acc[a][b] = Mfma<T>::mac(bv[b], av[a], acc[a][b]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (!(ra_on[a] && rb_on[b])) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = (wr + 4 * a) * 16 + rr;
+        const int j = (wc + 4 * b) * 16 + Mfma<T>::row(kq, r);
+        if (i < d.m && j < nn) {
+          T* c = C + i + (int64_t)d.ldc * j;
+          const T v = alpha * acc[a][b][r];
+          *c = beta == (T)0 ? v : beta * *c + v;
+        }
+      }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // constrained Neumann setup: right-hand sides [C_r^T | -K_rv], couplings
 
@@ -1474,7 +1579,7 @@ __global__ void k_rhs_fill(PlanDev P, Geo g, const double* __restrict__ rho, T* 
   }
 }
 
-// fwd (fwd = 1): Z[first plane of block k, :] -= A_{k,k-1} Z[last plane of k-1, :]
+// fwd (fwd = 1): tmp = Z[block k, :] - A_{k,k-1} Z[last plane of k-1, :]
 // bwd (fwd = 0): tmp[0:last_n, :] = A_{k,k+1} Z[first plane of k+1, :]
 // One workgroup per (column chunk of CPL_COLS, subdomain): the source plane's
 // rows of the chunk are staged in LDS once, then every output row takes its
@@ -1490,58 +1595,51 @@ __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd,
   const SubDev S = P.subs[sub];
   const int nb = S.nbR;
   const int ncols = S.n_a + S.n_v;
-  if (fwd ? (k >= nb || k == 0) : (k + 1 >= nb)) return;
+  if (fwd ? k >= nb : k + 1 >= nb) return;
   const int c0 = blockIdx.x * CPL_COLS;
   if (c0 >= ncols) return;
   const int nc = min(CPL_COLS, ncols - c0);
   const BlockDev B = P.blocks[S.bR_off + k];
   const int64_t roff = fwd ? B.cf_off : B.cb_off;
-  if (roff < 0) return;
-  const BlockDev O = P.blocks[S.bR_off + (fwd ? k - 1 : k + 1)];
-  const int sbase = fwd ? O.start + O.size - O.last_n : O.start;  // first rank of the source plane
-  const int sn = fwd ? O.last_n : O.first_n;
-  T* z = Z + S.Z_off;
-  for (int idx = threadIdx.x; idx < sn * nc; idx += blockDim.x) {
-    const int r = idx % sn, c = idx / sn;
-    src[r][c] = z[sbase + r + (int64_t)S.n_r * (c0 + c)];
+  const bool couple = fwd ? (k > 0 && roff >= 0) : roff >= 0;
+  if (!fwd && !couple) return;
+  const T* z = Z + S.Z_off;
+  int sbase = 0;
+  if (couple) {
+    const BlockDev O = P.blocks[S.bR_off + (fwd ? k - 1 : k + 1)];
+    sbase = fwd ? O.start + O.size - O.last_n : O.start;  // first rank of the source plane
+    const int sn = fwd ? O.last_n : O.first_n;
+    for (int idx = threadIdx.x; idx < sn * nc; idx += blockDim.x) {
+      const int r = idx % sn, c = idx / sn;
+      src[r][c] = z[sbase + r + (int64_t)S.n_r * (c0 + c)];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  const int rows = fwd ? B.first_n : B.last_n;
-  const int rowbase = fwd ? B.start : B.start + B.size - B.last_n;
+  // forward: the whole block's right-hand side, coupled on its first plane;
+  // backward: the coupling of the last plane only
+  const int rows = fwd ? B.size : B.last_n;
+  const int crow = fwd ? B.first_n : B.last_n;   // rows that take a coupling
+  const int ld = fwd ? B.size : B.last_n;
   T* tp = tmp + sub * tmp_stride;
   for (int i = threadIdx.x; i < rows; i += blockDim.x) {
-    const int64_t row = roff + i;
     double a[9];
     int l[9];
+    const bool ci = couple && i < crow;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const int rk = P.cpl_rank[row * 9 + t];
-      a[t] = rk >= 0 ? P.cpl_coef[row * 9 + t] : 0.0;
+      const int rk = ci ? P.cpl_rank[(roff + i) * 9 + t] : -1;
+      a[t] = rk >= 0 ? P.cpl_coef[(roff + i) * 9 + t] : 0.0;
       l[t] = rk >= 0 ? rk - sbase : 0;
     }
     for (int c = 0; c < nc; ++c) {
       double acc = 0.0;
+      if (ci) {
 #pragma unroll
-      for (int t = 0; t < 9; ++t) acc += a[t] * (double)src[l[t]][c];
-      if (fwd) z[rowbase + i + (int64_t)S.n_r * (c0 + c)] -= (T)acc;
-      else tp[i + (int64_t)B.last_n * (c0 + c)] = (T)acc;
+        for (int t = 0; t < 9; ++t) acc += a[t] * (double)src[l[t]][c];
+      }
+      if (fwd) tp[i + (int64_t)ld * (c0 + c)] = z[B.start + i + (int64_t)S.n_r * (c0 + c)] - (T)acc;
+      else tp[i + (int64_t)ld * (c0 + c)] = (T)acc;
     }
-  }
-}
-
-template <typename T>
-__global__ void k_copy_block_rows(PlanDev P, int k, const T* __restrict__ Z, T* __restrict__ tmp,
-                                  int64_t tmp_stride) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  if (k >= S.nbR) return;
-  const BlockDev B = P.blocks[S.bR_off + k];
-  const int ncols = S.n_a + S.n_v;
-  const int64_t tot = (int64_t)B.size * ncols;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    int i = (int)(idx % B.size), c = (int)(idx / B.size);
-    tmp[sub * tmp_stride + idx] = Z[S.Z_off + B.start + i + (int64_t)S.n_r * c];
   }
 }
 
@@ -2693,20 +2791,24 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
     const int64_t tiles = cdiv(maxn, TILE);
     const int64_t ntri = tiles * (tiles + 1) / 2;
     for (int j0 = 0; j0 < maxp; j0 += SLAB) {
-      double cf = 0, cb = 0, uf = 0, ub = 0;
+      double df = 0, db = 0, cf = 0, cb = 0, uf = 0, ub = 0;
       if (prof && h_desc)
         for (int q = 0; q < nprob; ++q) {
           const double n = h_desc[q].n, p = h_desc[q].p;
           if (j0 >= p) continue;
           const double sb = std::min<double>(SLAB, p - j0), m = n - sb;
           const double low = m * (m + 1) / 2;
+          df += sb * sb * sb;
+          db += sizeof(T) * (sb * (sb + 1) / 2 + sb * sb);
           cf += 2.0 * m * sb * sb;
           cb += sizeof(T) * (2.0 * m * sb + sb * sb);
           uf += 2.0 * sb * low;
           ub += sizeof(T) * (2.0 * low + 2.0 * m * sb);
         }
-      if (prof) prof->begin(4, s);
+      if (prof) prof->begin(5, s);
       k_sweep_reg<T, 12, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code, j0);
+      if (prof) prof->end(5, df, db, s);
+      if (prof) prof->begin(4, s);
       k_slab_cd<T><<<dim3(cdiv(maxn, TILE), cdiv(SLAB, TILE), nprob), 256, 0, s>>>(d_desc, pool, j0, scratch,
                                                                                   scr_stride);
       if (prof) prof->end(4, cf, cb, s);
@@ -2767,6 +2869,11 @@ void Kern<T>::gemm(const GemmDesc* d_desc, const GemmDesc* h_desc, int nprob, in
     }
   const unsigned nb = (unsigned)(((int64_t)tm * tn * nprob + 7) / 8 * 8);
   if (prof) prof->begin(3, s);
+  if (!transA && !transB && maxm <= GF_M) {
+    k_gemm_full<T><<<dim3(nprob, cdiv(maxn, GF_N)), 1024, 0, s>>>(d_desc, A, B, C, alpha, beta);
+    if (prof) prof->end(3, f, by, s);
+    return;
+  }
   if (!transA && !transB) k_gemm<T, 0, 0><<<nb, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm, tn, nprob);
   else if (transA && !transB) k_gemm<T, 1, 0><<<nb, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm, tn, nprob);
   else if (!transA && transB) k_gemm<T, 0, 1><<<nb, 256, 0, s>>>(d_desc, A, B, C, alpha, beta, tm, tn, nprob);
@@ -2788,14 +2895,6 @@ void Kern<T>::couple_multi(const PlanDev& P, const Geo& g, const double* rho, in
   if (ncols_max == 0) return;
   const size_t sm = (size_t)hmax(P.max_plane, 1) * (CPL_COLS + 1) * sizeof(T);
   k_couple_multi<T><<<dim3(cdiv(ncols_max, CPL_COLS), P.n_sub), 256, sm, s>>>(P, k, fwd, Z, tmp, tmp_stride);
-}
-
-template <typename T>
-void Kern<T>::copy_block_rows(const PlanDev& P, int k, int ncols_max, const T* Z, T* tmp,
-                              int64_t tmp_stride, hipStream_t s) {
-  int64_t tot = (int64_t)P.max_block * ncols_max;
-  if (tot == 0) return;
-  k_copy_block_rows<T><<<dim3(hmin(cdiv(tot, 256), 1024), P.n_sub), 256, 0, s>>>(P, k, Z, tmp, tmp_stride);
 }
 
 template <typename T>
