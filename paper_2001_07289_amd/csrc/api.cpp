@@ -184,7 +184,7 @@ namespace {
 template <typename T>
 struct Numeric {
   T *G = nullptr, *Z = nullptr, *XG = nullptr, *Sc = nullptr, *Tm = nullptr, *Lam = nullptr,
-    *Phi = nullptr, *PhiG = nullptr, *Kc = nullptr;
+    *PhiG = nullptr, *Kc = nullptr;
   T *W = nullptr, *W2 = nullptr, *tmp = nullptr, *sw = nullptr, *sw2 = nullptr;
   int64_t wstride = 0, tmp_stride = 0, sw_stride = 0;
   // per-iteration
@@ -213,7 +213,7 @@ struct bddcso_precond {
   int32_t* status = nullptr;
   // batches
   std::vector<Batch> swI, swR, gfwd, gbwd;
-  Batch swSc, gLam, gPhiR;
+  Batch swSc, gLam, gSel;
   std::vector<Batch> swFront;                       // per level
   std::vector<int32_t*> color_dev;                  // per colour
   std::vector<int> color_n;
@@ -313,7 +313,6 @@ void alloc_numeric(bddcso_precond* pc, hipStream_t s) {
   N.Sc = m.alloc<T>(pl.pool_Sc);
   N.Tm = m.alloc<T>(pl.pool_T);
   N.Lam = m.alloc<T>(pl.pool_T);
-  N.Phi = m.alloc<T>(pl.pool_Phi);
   N.PhiG = m.alloc<T>(pl.pool_PhiG);
   N.Kc = m.alloc<T>(pl.pool_Kc);
   int max_plane = pc->P.max_plane;
@@ -387,16 +386,16 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
         d.push_back({S.Sc_off, S.n_a, S.n_a, S.n_a});
         if (S.n_c > 0) {
           lam.push_back({S.Sc_off, S.T_off, S.T_off, S.n_a, S.n_c, S.n_a, S.n_a, S.n_a, S.n_a});
-          phir.push_back({S.Z_off, S.T_off, S.Phi_off, S.n_r, S.n_c, S.n_a, S.n_r, S.n_a, S.n_r});
+          phir.push_back({S.XG_off, S.T_off, S.PhiG_off, S.n_s, S.n_c, S.n_a, S.n_s, S.n_a, S.n_s});
         }
       }
     }
     check_sweeps(d, pl.pool_Sc, ns, "S_c");
     check_gemms(lam, pl.pool_Sc, pl.pool_T, pl.pool_T, "Lambda GEMM");
-    check_gemms(phir, pl.pool_Z, pl.pool_T, pl.pool_Phi, "Phi GEMM");
+    check_gemms(phir, pl.pool_XG, pl.pool_T, pl.pool_PhiG, "Phi GEMM");
     pc->swSc = make_sweep_batch(m, d, s);
     pc->gLam = make_gemm_batch(m, lam, s);
-    pc->gPhiR = make_gemm_batch(m, phir, s);
+    pc->gSel = make_gemm_batch(m, phir, s);
   }
   // G entries streamed by one block solve of each set
   for (const SubDev& S : pl.subs)
@@ -484,6 +483,8 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
                      N.sw_stride, pc->status, setR ? 2 : 1, ss, pc->P_());
     }
   }
+  // the coarse front pool is zeroed on the second stream too (it is summed into later)
+  launch_fill_f64(pc->fpool, pl.front_pool, 0.0, pc->s2);
   HIPCHK(hipEventRecord(pc->ev_join, pc->s2));
   // [X | Y'] = K_rr^{-1} [C_r^T | -K_rv]
   if (sizeof(T) == 8) launch_fill_f64((double*)N.Z, pl.pool_Z, 0.0, s);
@@ -509,13 +510,13 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   Kern<T>::lambda_rhs(P, N.Z, N.Tm, s);
   Kern<T>::gemm((GemmDesc*)pc->gLam.desc, pc->gLam.hg.data(), pc->gLam.n, pc->gLam.maxm, pc->gLam.maxn, N.Sc, 0,
                 N.Tm, 0, N.Lam, (T)-1, (T)0, s, pc->P_());
-  Kern<T>::phi_r_init(P, N.Z, N.Phi, s);
-  Kern<T>::gemm((GemmDesc*)pc->gPhiR.desc, pc->gPhiR.hg.data(), pc->gPhiR.n, pc->gPhiR.maxm, pc->gPhiR.maxn,
-                N.Z, 0, N.Lam, 0, N.Phi, (T)-1, (T)1, s, pc->P_());
-  Kern<T>::kc_identity(P, g, rho, N.Phi, N.Lam, N.Kc, pc->vcoef, pc->vcode, pc->max_nv, s);
-  Kern<T>::extract_gamma(P, N.Phi, N.Z, N.PhiG, N.XG, s);
+  // Phi = Y' - X Lambda, only at the selected rows (Gamma and the vertices' stencils)
+  Kern<T>::sel_gather(P, N.Z, N.XG, N.PhiG, s);
+  Kern<T>::gemm((GemmDesc*)pc->gSel.desc, pc->gSel.hg.data(), pc->gSel.n, pc->gSel.maxm, pc->gSel.maxn, N.XG, 0,
+                N.Lam, 0, N.PhiG, (T)-1, (T)1, s, pc->P_());
+  Kern<T>::kc_identity(P, g, rho, N.PhiG, N.Lam, N.Kc, pc->vcoef, pc->vcode, pc->max_nv, s);
   // coarse: assemble into the fronts and factor level by level (FP64)
-  launch_fill_f64(pc->fpool, pl.front_pool, 0.0, s);
+  HIPCHK(hipStreamWaitEvent(s, pc->ev_join, 0));  // interior factors and the zeroed front pool
   for (size_t c = 0; c < pc->color_dev.size(); ++c)
     Kern<T>::kc_to_front(P, pc->color_dev[c], pc->color_n[c], N.Kc, pc->fpool, s);
   for (size_t L = 0; L < pc->swFront.size(); ++L) {
@@ -525,7 +526,6 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
     Kern<double>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, pc->fpool, pc->fsw, pc->fsw_stride,
                         pc->status, 4, s, pc->P_());
   }
-  HIPCHK(hipStreamWaitEvent(s, pc->ev_join, 0));
 }
 
 void coarse_solve(bddcso_precond* pc, int nrhs, hipStream_t s) {
@@ -755,6 +755,8 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     P.g_loc = m.upload(pl.g_loc, s);
     P.g_gam = m.upload(pl.g_gam, s);
     P.g_r = m.upload(pl.g_r, s);
+    P.loc_sel = m.upload(pl.loc_sel, s);
+    P.sel_r = m.upload(pl.sel_r, s);
     P.g_v = m.upload(pl.g_v, s);
     P.g_sub = m.upload(pl.g_sub, s);
     P.v_loc = m.upload(pl.v_loc, s);
@@ -801,6 +803,7 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     P.max_na = pl.max_na;
     P.max_nc = pl.max_nc;
     P.max_ng = pl.max_ng;
+    P.max_ns = pl.max_ns;
     P.max_nloc = pl.max_nloc;
     P.max_nr = pl.max_nr;
     int max_nI = 0, max_plane = 0;
@@ -1071,9 +1074,9 @@ bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bd
   const double ns = (double)pl.subs.size();
   int max_plane = 0;
   for (auto& B : pl.blocks) max_plane = std::max(max_plane, std::max(B.first_n, B.last_n));
-  double tpool = pl.pool_G + pl.pool_Z + pl.pool_XG + pl.pool_Sc + 2.0 * pl.pool_T + pl.pool_Phi + pl.pool_PhiG +
+  double tpool = pl.pool_G + pl.pool_Z + pl.pool_XG + pl.pool_Sc + 2.0 * pl.pool_T + pl.pool_PhiG +
                  pl.pool_Kc + ns * ((double)max_plane * max_plane + (double)pl.max_block * std::max(pl.max_zcols, 1) +
-                                    2.0 * ((double)std::max(pl.max_block, pl.max_na) * kSweepNB + kSweepNB * kSweepNB)) +
+                                    2.0 * std::max(2.0 * ((double)std::max(pl.max_block, pl.max_na) * kSweepNB + kSweepNB * kSweepNB), (double)std::max(pl.max_block, pl.max_na) * kSlab)) +
                  nr * (pl.tot_I + pl.tot_r + 3.0 * pl.tot_g + pl.tot_a + pl.tot_c);
   double dpool = (double)pl.front_pool + 2.0 * nr * pl.front_vec + 2.0 * nr * pl.n_coarse +
                  9.0 * pl.cpl_sub.size() + 6.0 * nr * p->c.n_free + p->c.n_elem + pl.tot_g;

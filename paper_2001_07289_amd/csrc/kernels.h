@@ -39,6 +39,7 @@ struct PlanDev {
   const int32_t *loc_I, *loc_r, *loc_g;
   const int32_t *I_loc, *r_loc;
   const int32_t *g_loc, *g_gam, *g_r, *g_v, *g_sub;
+  const int32_t *loc_sel, *sel_r;
   const int32_t *v_loc, *v_c;
   const int32_t *a_ptr, *a_r, *a_c;
   const int32_t *c_glob, *c_kind;
@@ -54,7 +55,7 @@ struct PlanDev {
   int64_t n_cpl;
   int n_sub;
   int64_t tot_I, tot_r, tot_g, tot_c, tot_a, n_gam, n_coarse;
-  int max_block, max_na, max_nc, max_ng, max_nloc, max_nr, max_nI, max_zcols, max_plane;
+  int max_block, max_na, max_nc, max_ng, max_ns, max_nloc, max_nr, max_nI, max_zcols, max_plane;
 };
 
 // ---- launchers (defined in kernels.hip) ---------------------------------
@@ -87,11 +88,10 @@ struct Kern {
                            int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s);
   static void sc_assemble(const PlanDev& P, const T* Z, T* Sc, hipStream_t s);
   static void lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s);
-  static void phi_r_init(const PlanDev& P, const T* Z, T* PhiR, hipStream_t s);
-  static void kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PhiR,
+  // rows of [X | Phi initialised to Y'] at the selected rows
+  static void sel_gather(const PlanDev& P, const T* Z, T* XS, T* PS, hipStream_t s);
+  static void kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PS,
                           const T* Lam, T* Kc, double* vcoef, int32_t* vcode, int max_nv, hipStream_t s);
-  static void extract_gamma(const PlanDev& P, const T* PhiR, const T* Z, T* PhiG, T* XG,
-                            hipStream_t s);
   static void kc_to_front(const PlanDev& P, const int32_t* subs_of_color, int ns, const T* Kc,
                           double* fpool, hipStream_t s);
   // per-iteration

@@ -1679,16 +1679,34 @@ __global__ void k_lambda_rhs(PlanDev P, const T* __restrict__ Z, T* __restrict__
   Tm[S.T_off + idx] = (T)v;
 }
 
+// Rows of X and of Phi's initial value [Y' by coarse kind | 0] at the
+// selected rows; at a Gamma entry that is a primal vertex, X is 0 and Phi is
+// the unit row of the vertex's coarse dof.  Phi = Y' - X Lambda then needs
+// the product only over these rows.
 template <typename T>
-__global__ void k_phi_r_init(PlanDev P, const T* __restrict__ Z, T* __restrict__ PhiR) {
+__global__ void k_sel_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__ XS, T* __restrict__ PS) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
-  const int64_t tot = (int64_t)S.n_r * S.n_c;
+  const int64_t totx = (int64_t)S.n_s * S.n_a, tot = totx + (int64_t)S.n_s * S.n_c;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    int i = (int)(idx % S.n_r), c = (int)(idx / S.n_r);
-    int kind = P.c_kind[S.c_off + c];
-    PhiR[S.Phi_off + idx] = kind >= 0 ? Z[S.Z_off + i + (int64_t)S.n_r * (S.n_a + kind)] : (T)0;
+    if (idx < totx) {
+      const int e = (int)(idx % S.n_s), a = (int)(idx / S.n_s);
+      const int r = P.sel_r[S.sel_off + e];
+      XS[S.XG_off + idx] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * a] : (T)0;
+    } else {
+      const int64_t j = idx - totx;
+      const int e = (int)(j % S.n_s), c = (int)(j / S.n_s);
+      const int r = P.sel_r[S.sel_off + e];
+      T v;
+      if (r >= 0) {
+        const int kind = P.c_kind[S.c_off + c];
+        v = kind >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * (S.n_a + kind)] : (T)0;
+      } else {
+        v = P.v_c[S.v_off + P.g_v[S.g_off + e]] == c ? (T)1 : (T)0;
+      }
+      PS[S.PhiG_off + j] = v;
+    }
   }
 }
 
@@ -1698,7 +1716,7 @@ __global__ void k_phi_r_init(PlanDev P, const T* __restrict__ Z, T* __restrict__
 // (K Phi)_v at vertex dofs and -Lambda at average dofs.  The two triangles
 // are averaged so the result is symmetric to the last bit.
 // Stencil rows of the primal vertices: for vertex v of a subdomain and its
-// 27 neighbour offsets, the coefficient K[v, j] and a code: the r rank of j,
+// 27 neighbour offsets, the coefficient K[v, j] and a code: the selected-row index of j,
 // or -(c+1) when j is the vertex of local coarse dof c, or INT32_MIN when j
 // is not a local node.  Filled once per setup.
 __global__ void k_vertex_stencil(PlanDev P, Geo g, const double* __restrict__ rho, int64_t* __restrict__ vcode_unused,
@@ -1722,7 +1740,7 @@ __global__ void k_vertex_stencil(PlanDev P, Geo g, const double* __restrict__ rh
     return;
   }
   const int r = P.loc_r[S.loc_off + ln];
-  vcode[out] = r >= 0 ? r : -(P.v_c[S.v_off + P.g_v[S.g_off + P.loc_g[S.loc_off + ln]]] + 1);
+  vcode[out] = r >= 0 ? P.loc_sel[S.loc_off + ln] : -(P.v_c[S.v_off + P.g_v[S.g_off + P.loc_g[S.loc_off + ln]]] + 1);
   vcoef[out] = kloc(S, g, rho, P.khat, cv, cn);
 }
 
@@ -1737,7 +1755,7 @@ __device__ __forceinline__ double kc_entry(const PlanDev& P, const SubDev& S, co
   for (int t = 0; t < 27; ++t) {
     const int code = vcode[base + t];
     if (code == INT32_MIN) continue;
-    const double phi = code >= 0 ? (double)PhiR[S.Phi_off + code + (int64_t)S.n_r * c2] : (-code - 1 == c2 ? 1.0 : 0.0);
+    const double phi = code >= 0 ? (double)PhiR[S.PhiG_off + code + (int64_t)S.n_s * c2] : (-code - 1 == c2 ? 1.0 : 0.0);
     acc += vcoef[base + t] * phi;
   }
   return acc;
@@ -1757,30 +1775,6 @@ __global__ void k_kc_identity(PlanDev P, const T* __restrict__ PhiR, const T* __
                           kc_entry(P, S, PhiR, Lam, vcoef, vcode, c2, c));
   Kc[S.Kc_off + c + (int64_t)S.n_c * c2] = (T)v;
   Kc[S.Kc_off + c2 + (int64_t)S.n_c * c] = (T)v;
-}
-
-template <typename T>
-__global__ void k_extract_gamma(PlanDev P, const T* __restrict__ PhiR, const T* __restrict__ Z,
-                                T* __restrict__ PhiG, T* __restrict__ XG) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  const int64_t totp = (int64_t)S.n_g * S.n_c, totx = (int64_t)S.n_g * S.n_a;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < totp + totx;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    if (idx < totp) {
-      const int e = (int)(idx % S.n_g), c = (int)(idx / S.n_g);
-      const int r = P.g_r[S.g_off + e];
-      T v;
-      if (r >= 0) v = PhiR[S.Phi_off + r + (int64_t)S.n_r * c];
-      else v = P.v_c[S.v_off + P.g_v[S.g_off + e]] == c ? (T)1 : (T)0;
-      PhiG[S.PhiG_off + idx] = v;
-    } else {
-      const int64_t j = idx - totp;
-      const int e = (int)(j % S.n_g), a = (int)(j / S.n_g);
-      const int r = P.g_r[S.g_off + e];
-      XG[S.XG_off + j] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * a] : (T)0;
-    }
-  }
 }
 
 template <typename T>
@@ -2134,7 +2128,7 @@ __global__ __launch_bounds__(256) void k_coarse_rhs_local(PlanDev P, const T* __
   const T* M = PhiG + S.PhiG_off;
   for (int c = cb + wave; c < min(S.n_c, cb + CRL_COLS); c += blockDim.x >> 6) {
     double acc = 0.0;
-    for (int e = lane; e < S.n_g; e += 64) acc += (double)(M[e + (int64_t)S.n_g * c] * gl[e]);
+    for (int e = lane; e < S.n_g; e += 64) acc += (double)(M[e + (int64_t)S.n_s * c] * gl[e]);
     acc = wave_sum(acc);
     if (lane == 0) bci[rhs * P.tot_c + S.c_off + c] = (T)acc;
   }
@@ -2164,8 +2158,8 @@ __global__ __launch_bounds__(256) void k_v2(PlanDev P, const T* __restrict__ vR,
   const T* F = PhiG + S.PhiG_off;
   const int r = P.g_r[S.g_off + e];
   T acc = r >= 0 ? u[r] : (T)0;
-  for (int a = 0; a < S.n_a; ++a) acc -= X[e + (int64_t)S.n_g * a] * mul[a];
-  for (int c = 0; c < S.n_c; ++c) acc += F[e + (int64_t)S.n_g * c] * ucl[c];
+  for (int a = 0; a < S.n_a; ++a) acc -= X[e + (int64_t)S.n_s * a] * mul[a];
+  for (int c = 0; c < S.n_c; ++c) acc += F[e + (int64_t)S.n_s * c] * ucl[c];
   v2[rhs * P.tot_g + S.g_off + e] = acc;
 }
 
@@ -2392,7 +2386,7 @@ __global__ __launch_bounds__(256) void k_coarse_rhs_local_mr(PlanDev P, const T*
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kq = lane >> 4, rr = lane & 15;
   const int c = c0 + wave * 16 + rr;
   const bool rok = c < S.n_c;
-  const T* M = PhiG + S.PhiG_off + (int64_t)S.n_g * c;
+  const T* M = PhiG + S.PhiG_off + (int64_t)S.n_s * c;
   acc_t acc[MR_COLS / 16];
 #pragma unroll
   for (int q = 0; q < MR_COLS / 16; ++q) acc[q] = acc_t{0, 0, 0, 0};
@@ -2442,8 +2436,8 @@ __global__ __launch_bounds__(256) void k_v2_mr(PlanDev P, const T* __restrict__ 
       Bs[k][r] = (k < kn && r < nr) ? (T)uc[(int64_t)(r0 + r) * P.n_coarse + P.c_glob[S.c_off + kb + k]] : (T)0;
     }
     __syncthreads();
-    const T* M = PhiG + S.PhiG_off + e + (int64_t)S.n_g * kb;
-    mr_accum<T>([&](int k) { return M[(int64_t)S.n_g * k]; }, rok, kn, Bs, acc, kq, rr);
+    const T* M = PhiG + S.PhiG_off + e + (int64_t)S.n_s * kb;
+    mr_accum<T>([&](int k) { return M[(int64_t)S.n_s * k]; }, rok, kn, Bs, acc, kq, rr);
   }
   for (int kb = 0; kb < S.n_a; kb += MR_KC) {   // - X_Gamma mu
     const int kn = min(MR_KC, S.n_a - kb);
@@ -2454,8 +2448,8 @@ __global__ __launch_bounds__(256) void k_v2_mr(PlanDev P, const T* __restrict__ 
       Bs[k][r] = (k < kn && r < nr) ? -mu[(int64_t)(r0 + r) * P.tot_a + S.am_off + kb + k] : (T)0;
     }
     __syncthreads();
-    const T* M = XG + S.XG_off + e + (int64_t)S.n_g * kb;
-    mr_accum<T>([&](int k) { return M[(int64_t)S.n_g * k]; }, rok, kn, Bs, acc, kq, rr);
+    const T* M = XG + S.XG_off + e + (int64_t)S.n_s * kb;
+    mr_accum<T>([&](int k) { return M[(int64_t)S.n_s * k]; }, rok, kn, Bs, acc, kq, rr);
   }
 #pragma unroll
   for (int q = 0; q < MR_COLS / 16; ++q)
@@ -2702,7 +2696,7 @@ int front_fwd_chunks(int maxp) { return (int)cdiv(maxp, FK); }
 int64_t max_lds_bytes(const PlanDev& P, int elt) {
   const int64_t mp = hmax(P.max_plane, 1);
   int64_t need = 0;
-  need = hmax(need, mp * (SC_COLS + 1) * elt);                                         // schur couple
+  need = hmax(need, mp * (SC_COLS + 1) * elt + 2048);                                  // schur couple
   need = hmax(need, mp * (CPL_COLS + 1) * elt);                                        // couple multi
   need = hmax(need, (hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * elt);     // block solve
   need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);               // many-rhs block solve
@@ -2910,10 +2904,10 @@ void Kern<T>::lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s) {
 }
 
 template <typename T>
-void Kern<T>::phi_r_init(const PlanDev& P, const T* Z, T* PhiR, hipStream_t s) {
-  int64_t tot = (int64_t)P.max_nr * P.max_nc;
+void Kern<T>::sel_gather(const PlanDev& P, const T* Z, T* XS, T* PS, hipStream_t s) {
+  const int64_t tot = (int64_t)P.max_ns * (P.max_na + P.max_nc);
   if (tot == 0) return;
-  k_phi_r_init<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, PhiR);
+  k_sel_gather<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, XS, PS);
 }
 
 template <typename T>
@@ -2924,13 +2918,6 @@ void Kern<T>::kc_identity(const PlanDev& P, const Geo& g, const double* rho, con
     k_vertex_stencil<<<dim3(cdiv((int64_t)max_nv * 27, 256), P.n_sub), 256, 0, s>>>(P, g, rho, nullptr, vcoef, vcode);
   k_kc_identity<T><<<dim3(cdiv((int64_t)P.max_nc * P.max_nc, 256), P.n_sub), 256, 0, s>>>(P, PhiR, Lam, vcoef,
                                                                                           vcode, Kc);
-}
-
-template <typename T>
-void Kern<T>::extract_gamma(const PlanDev& P, const T* PhiR, const T* Z, T* PhiG, T* XG, hipStream_t s) {
-  int64_t tot = (int64_t)P.max_ng * (P.max_nc + P.max_na);
-  if (tot == 0) return;
-  k_extract_gamma<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, PhiR, Z, PhiG, XG);
 }
 
 template <typename T>

@@ -355,9 +355,8 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
   plan.n_coarse = (int64_t)plan.coarse_obj.size();
 
   plan.subs.resize(c.n_sub);
-  int64_t loc_off = 0, I_off = 0, r_off = 0, g_off = 0, v_off = 0, a_off = 0, c_off = 0;
-  int64_t G_off = 0, Z_off = 0, XG_off = 0, Sc_off = 0, T_off = 0, Phi_off = 0, PhiG_off = 0,
-          Kc_off = 0;
+  int64_t loc_off = 0, I_off = 0, r_off = 0, g_off = 0, v_off = 0, a_off = 0, c_off = 0, sel_off = 0;
+  int64_t G_off = 0, Z_off = 0, XG_off = 0, Sc_off = 0, T_off = 0, PhiG_off = 0, Kc_off = 0;
   std::vector<std::vector<int32_t>> sub_dofs(c.n_sub);
   for (int s = 0; s < c.n_sub; ++s) {
     SubDev& S = plan.subs[s];
@@ -450,6 +449,34 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
         int l = plan.v_loc[k];
         plan.g_v[g_off + lg[l]] = vi;
       }
+    }
+    // selected rows: the Gamma entries, then the r-set nodes of the primal
+    // vertices' stencils that are not on Gamma (the rows of Phi that the
+    // local coarse matrix and the per-iteration products read)
+    {
+      S.sel_off = sel_off;
+      std::vector<int32_t> ls(lg);
+      for (int e = 0; e < ngl; ++e) plan.sel_r.push_back(plan.g_r[g_off + e]);
+      int ns = ngl;
+      for (int64_t k = v_off; k < v_off + nv; ++k) {
+        const int l = plan.v_loc[k];
+        const int cv[3] = {l % S.m[0], (l / S.m[0]) % S.m[1], l / (S.m[0] * S.m[1])};
+        for (int t = 0; t < 27; ++t) {
+          const int dz = dim == 3 ? t / 9 - 1 : 0, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+          if (dim == 2 && t >= 9) continue;
+          const int cn[3] = {cv[0] + dx, cv[1] + dy, cv[2] + dz};
+          bool in = true;
+          for (int a = 0; a < 3; ++a) in = in && cn[a] >= 0 && cn[a] < S.m[a];
+          if (!in) continue;
+          const int ln = cn[0] + S.m[0] * (cn[1] + S.m[1] * cn[2]);
+          if (lr[ln] < 0 || ls[ln] >= 0) continue;
+          ls[ln] = ns++;
+          plan.sel_r.push_back(lr[ln]);
+        }
+      }
+      S.n_s = ns;
+      sel_off += ns;
+      plan.loc_sel.insert(plan.loc_sel.end(), ls.begin(), ls.end());
     }
     // local coarse: vertices and averages, in coarse order
     std::vector<int32_t> v_c(nv, -1);
@@ -557,15 +584,13 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     S.Z_off = Z_off;
     Z_off += (int64_t)S.n_r * (S.n_a + S.n_v);
     S.XG_off = XG_off;
-    XG_off += (int64_t)S.n_g * S.n_a;
+    XG_off += (int64_t)S.n_s * S.n_a;
     S.Sc_off = Sc_off;
     Sc_off += (int64_t)S.n_a * S.n_a;
     S.T_off = T_off;
     T_off += (int64_t)S.n_a * S.n_c;
-    S.Phi_off = Phi_off;
-    Phi_off += (int64_t)S.n_r * S.n_c;
     S.PhiG_off = PhiG_off;
-    PhiG_off += (int64_t)S.n_g * S.n_c;
+    PhiG_off += (int64_t)S.n_s * S.n_c;
     S.Kc_off = Kc_off;
     Kc_off += (int64_t)S.n_c * S.n_c;
     loc_off += S.n_loc;
@@ -580,6 +605,7 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     plan.max_nr = std::max(plan.max_nr, S.n_r);
     plan.max_nloc = std::max(plan.max_nloc, S.n_loc);
     plan.max_ng = std::max(plan.max_ng, S.n_g);
+    plan.max_ns = std::max(plan.max_ns, S.n_s);
     plan.max_zcols = std::max(plan.max_zcols, S.n_a + S.n_v);
   }
   plan.tot_loc = loc_off;
@@ -594,7 +620,6 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
   plan.pool_XG = XG_off;
   plan.pool_Sc = Sc_off;
   plan.pool_T = T_off;
-  plan.pool_Phi = Phi_off;
   plan.pool_PhiG = PhiG_off;
   plan.pool_Kc = Kc_off;
 

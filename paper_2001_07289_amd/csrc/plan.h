@@ -64,6 +64,8 @@ struct Plan {
   std::vector<int32_t> loc_I, loc_r, loc_g;   // per local node: rank in I / r / Gamma entries, -1
   std::vector<int32_t> I_loc, r_loc;          // set order -> local node
   std::vector<int32_t> g_loc, g_gam, g_r, g_v, g_sub; // per Gamma entry
+  std::vector<int32_t> loc_sel;   // per local node: selected-row index or -1
+  std::vector<int32_t> sel_r;     // per selected row: r rank (-1 at primal vertices)
   std::vector<int32_t> v_loc, v_c;            // per vertex: local node, local coarse index
   std::vector<int32_t> a_ptr, a_r, a_c;       // averages: CSR of r ranks; local coarse index
   std::vector<int32_t> c_glob, c_kind;        // per local coarse: global id; vertex idx or -(a+1)
@@ -88,9 +90,8 @@ struct Plan {
 
   // totals
   int64_t tot_loc = 0, tot_I = 0, tot_r = 0, tot_g = 0, tot_v = 0, tot_a = 0, tot_c = 0;
-  int64_t pool_G = 0, pool_Z = 0, pool_XG = 0, pool_Sc = 0, pool_T = 0, pool_Phi = 0,
-          pool_PhiG = 0, pool_Kc = 0;
-  int max_block = 0, max_na = 0, max_nc = 0, max_nr = 0, max_nloc = 0, max_ng = 0;
+  int64_t pool_G = 0, pool_Z = 0, pool_XG = 0, pool_Sc = 0, pool_T = 0, pool_PhiG = 0, pool_Kc = 0;
+  int max_block = 0, max_na = 0, max_nc = 0, max_nr = 0, max_nloc = 0, max_ng = 0, max_ns = 0;
   int max_nbI = 0, max_nbR = 0;
   int max_zcols = 0;
 };

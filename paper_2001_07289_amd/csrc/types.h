@@ -14,6 +14,8 @@ struct SubDev {
   int elo[3];     // element box, inclusive lower corner
   int ehi[3];     // element box, exclusive upper corner
   int n_loc, n_I, n_r, n_g, n_v, n_a, n_c;
+  int n_s;        // selected rows: the Gamma entries, then the r-set stencil
+                  // neighbours of the primal vertices that are not on Gamma
   int nbI, nbR;   // diagonal blocks of the I and r factors
   int color;      // subdomains of one colour share no coarse dof
   int front;      // front the local coarse matrix is added to
@@ -27,11 +29,12 @@ struct SubDev {
   int64_t c_off;     // offset of local coarse tables / vectors
   int64_t bI_off, bR_off;  // offsets into the block table
   int64_t Z_off;     // n_r x (n_a + n_v): [X | Y'] (column-major, ld n_r)
-  int64_t XG_off;    // n_g x n_a: rows of X at Gamma entries (0 at vertices)
+  int64_t sel_off;   // offset of the selected-row table
+  int64_t XG_off;    // n_s x n_a (ld n_s): rows of X at the selected rows (0 at vertices)
   int64_t Sc_off;    // n_a x n_a: constraint Schur complement, swept
   int64_t T_off;     // n_a x n_c: C_r Y - [0 I], then Lambda
-  int64_t Phi_off;   // n_r x n_c: rows of the coarse basis on the r set
-  int64_t PhiG_off;  // n_g x n_c: rows of Phi at Gamma entries
+  int64_t PhiG_off;  // n_s x n_c (ld n_s): rows of Phi at the selected rows (the first
+                     // n_g are the Gamma entries)
   int64_t Kc_off;    // n_c x n_c local coarse matrix
 };
 
