@@ -173,3 +173,25 @@ def test_fixed_iters_equals_free_run_prefix():
     free = pcg.solve(o, p.f[0], rtol=1e-8)
     fixed = pcg.solve(o, p.f[0], fixed_iters=free.iters)
     assert np.array_equal(free.x, fixed.x)
+
+
+def _table1_iters():
+    from conftest import golden_path
+    out = {}
+    for line in open(golden_path("table1_iters.txt")):
+        f = line.split()
+        if f and not f[0].startswith("#"):
+            out[(f[0], int(f[1]))] = int(f[2])
+    return out
+
+
+def test_table1_bddc_so_k4_iterations():
+    """Table 1, k = 4: BDDC-SO(vef) with L = 4h takes the printed 4 PCG
+    iterations to a 10^6 reduction of the residual (f = 1, 10^3 subdomains).
+    At k = 4, L = H, so BDDC(vef) is the same preconditioner here; the paper
+    prints 5 for it, within the +-1 a tie at the threshold allows."""
+    printed = _table1_iters()
+    p = W.table1_problem(4)
+    r = pcg.solve(bddc.from_problem(p), p.f[0], rtol=1e-6)
+    assert r.iters == printed[("BDDC-SO(vef)", 4)]
+    assert abs(r.iters - printed[("BDDC(vef)", 4)]) <= 1
