@@ -812,7 +812,7 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     P.max_nI = max_nI;
     P.max_zcols = pl.max_zcols;
     P.max_plane = max_plane;
-    if (max_lds_bytes(P, o.precision == 1 ? 4 : 8) > 160 * 1024)
+    if (max_lds_bytes(P, o.precision == 1 ? 4 : 8, o.max_nrhs) > 160 * 1024)
       throw PlanFail{"a subdomain plane or block is too large for the LDS staging of the local kernels"};
 
     pc->rho = m.alloc<double>(c.n_elem);

@@ -144,7 +144,7 @@ void launch_pcg_p_flex(double* p, const double* z, const double* zdr, const doub
                        const int32_t* active, int64_t n, int nrhs, hipStream_t s);
 void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);
 void launch_copy16(const void* a, void* b, int64_t n16, hipStream_t s);
-int64_t max_lds_bytes(const PlanDev& P, int elt);
+int64_t max_lds_bytes(const PlanDev& P, int elt, int max_nrhs);
 // Chunks of pivot columns of the split forward front step (partial-sum rows).
 int front_fwd_chunks(int maxp);
 

@@ -2693,13 +2693,13 @@ void launch_kc_to_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
 // a plan with these maxima and element size; LDS per workgroup is 160 KiB.
 int front_fwd_chunks(int maxp) { return (int)cdiv(maxp, FK); }
 
-int64_t max_lds_bytes(const PlanDev& P, int elt) {
+int64_t max_lds_bytes(const PlanDev& P, int elt, int max_nrhs) {
   const int64_t mp = hmax(P.max_plane, 1);
   int64_t need = 0;
   need = hmax(need, mp * (SC_COLS + 1) * elt + 2048);                                  // schur couple
   need = hmax(need, mp * (CPL_COLS + 1) * elt);                                        // couple multi
   need = hmax(need, (hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * elt);     // block solve
-  need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);               // many-rhs block solve
+  if (max_nrhs >= 4) need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);  // many-rhs block solve
   need = hmax(need, (int64_t)(P.max_na + P.max_nc + 1) * elt);                         // v2
   need = hmax(need, (int64_t)hmax(P.max_ng, 1) * elt);                                 // coarse rhs
   need = hmax(need, (int64_t)SWEEP_ROWS * (SWEEP_NB + 1) * elt + 2 * 32 * 33 * 8);   // sweep panel

@@ -2,7 +2,9 @@
 reduction of the residual for the Poisson problem with f = 1 on (10k)^3
 hexahedra, 10^3 subdomains of k^3 cells, BDDC-SO(vef) with L/h = 4 and
 BDDC(vef) (L = H).  The printed counts are the reference (within +-1, a tie
-at the threshold); the coarse sizes must match exactly."""
+at the threshold); the coarse sizes must match exactly.  BDDC-SO at k = 24
+(354,159 coarse unknowns) needs more device memory than one GPU holds with
+this single-level coarse solver, so it is left out."""
 import numpy as np
 import pytest
 
@@ -44,7 +46,7 @@ def test_bddc_so_vef(k):
     assert abs(st["iters"][0] - iters[("BDDC-SO(vef)", k)]) <= 1
 
 
-@pytest.mark.parametrize("k", [8, 16])
+@pytest.mark.parametrize("k", [8, 16, 24])
 def test_bddc_vef(k):
     iters, sizes = _golden("table1_iters.txt"), _golden("table1.txt")
     p = W.table1_problem(k, L=k)
