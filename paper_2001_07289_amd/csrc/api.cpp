@@ -403,7 +403,9 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       const int nb = setR ? S.nbR : S.nbI;
       for (int k = 0; k < nb; ++k) {
         const BlockDev& B = pl.blocks[(setR ? S.bR_off : S.bI_off) + k];
-        double e = (double)B.size * B.size + (B.cb_off >= 0 ? (double)B.size * B.last_n : 0.0);
+        // lower triangle (forward) and the band of rows >= size - last_n (backward)
+        const double lb = B.last_n, base = B.size - B.last_n;
+        double e = (double)B.size * (B.size + 1) / 2 + (B.cb_off >= 0 ? lb * base + lb * (lb + 1) / 2 : 0.0);
         (setR ? pc->gR_entries : pc->gI_entries) += e;
       }
     }

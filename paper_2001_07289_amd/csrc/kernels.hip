@@ -1820,39 +1820,81 @@ __global__ void k_gather_I(PlanDev P, Geo g, const double* __restrict__ r, T* __
 //   forward  c_k = b_k - A_{k,k-1} xh_{k-1},  xh_k = G_k c_k
 //   backward x_k = xh_k - G_k A_{k,k+1} x_{k+1}
 // (G_k = -Gs_k, the swept block).  The couplings A_{k,k+-1} come from the
-// coupling table.  Each G_k is streamed once forward and its last-plane
-// columns once backward; a GEMV splits the columns over thread groups so all
-// 1024 threads keep loads in flight, then reduces the groups in fixed order.
+// coupling table.  G_k is symmetric, so only its lower triangle is read:
+// each 16x16 lower tile T(r, q) adds T c_q to rows r and T^T c_r to rows q.
+// The backward product G_k[:, base:] c (the last-plane columns) reads the
+// band of lower rows >= base the same way.  Waves take tiles round-robin,
+// keep partial sums per wave in LDS and the waves' sums are added in fixed
+// order, so the result is bitwise repeatable.
 constexpr int BS_THREADS = 1024;
+constexpr int BS_WAVES = BS_THREADS / 64;
 
+// out[i] (+)= sign * sum_{j >= base} G[i][j] x[j - base], i < s, from the lower
+// triangle of the symmetric s x s matrix M (column-major, ld s) restricted to
+// rows >= base.  yp: BS_WAVES x s doubles of LDS.  Every thread of the
+// workgroup calls it; it ends with a barrier.
 template <typename T>
-__device__ __forceinline__ void block_gemv(const T* __restrict__ M, int s, int ncols, const T* __restrict__ x,
-                                           T* __restrict__ part, int tid, T* __restrict__ out, bool accumulate,
-                                           T sign) {
-  // out[i] (+)= sign * sum_{j < ncols} M[i + s j] x[j], i < s
-  const int groups = s >= BS_THREADS ? 1 : min(BS_THREADS / s, max(ncols, 1));
-  const int chunk = (ncols + groups - 1) / groups;
-  if (groups == 1) {
-    for (int i = tid; i < s; i += BS_THREADS) {
-      T acc = 0;
-      for (int j = 0; j < ncols; ++j) acc += M[i + (int64_t)s * j] * x[j];
-      out[i] = accumulate ? out[i] + sign * acc : sign * acc;
+__device__ __forceinline__ void block_symv(const T* __restrict__ M, int s, int base, const T* __restrict__ x,
+                                           double* __restrict__ yp, T* __restrict__ out, bool accumulate, T sign,
+                                           int tid) {
+  const int wave = tid >> 6, lane = tid & 63, a = lane & 15, g = lane >> 4;
+  for (int i = tid; i < BS_WAVES * s; i += BS_THREADS) yp[i] = 0.0;
+  __syncthreads();
+  double* y = yp + wave * s;
+  const int nt = (s + 15) >> 4, t0 = base >> 4;
+  const int nrow = nt - t0;
+  const int ntiles = nrow * t0 + nrow * (nrow + 1) / 2;  // tile rows t0.., tile columns 0..row
+  for (int lin = wave; lin < ntiles; lin += BS_WAVES) {
+    int tr, tc;
+    if (lin < nrow * t0) {  // rectangle left of the band's first tile column
+      tr = t0 + lin / t0;
+      tc = lin % t0;
+    } else {
+      const int l2 = lin - nrow * t0;
+      int q = (int)((sqrt(8.0 * l2 + 1.0) - 1.0) * 0.5);
+      while ((q + 1) * (q + 2) / 2 <= l2) ++q;
+      while (q * (q + 1) / 2 > l2) --q;
+      tr = t0 + q;
+      tc = t0 + (l2 - q * (q + 1) / 2);
     }
-    return;
-  }
-  const int i = tid % s, g = tid / s;
-  if (g < groups) {
-    const int jlo = g * chunk, jhi = min(ncols, jlo + chunk);
-    T acc = 0;
-    for (int j = jlo; j < jhi; ++j) acc += M[i + (int64_t)s * j] * x[j];
-    part[g * s + i] = acc;
+    const int r = tr * 16 + a;
+    const bool rok = r < s && r >= base;
+    double L[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = tc * 16 + 4 * g + u;
+      L[u] = (rok && q <= r) ? (double)M[(int64_t)q * s + r] : 0.0;
+    }
+    // rows r: sum over the tile's columns q >= base
+    double t1 = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = tc * 16 + 4 * g + u;
+      if (q >= base && q < s) t1 += L[u] * (double)x[q - base];
+    }
+    t1 += __shfl_xor(t1, 16, 64);
+    t1 += __shfl_xor(t1, 32, 64);
+    if (g == 0 && rok) y[r] += t1;
+    // columns q < r: the transposed entries times x at the rows
+    const double xr = rok ? (double)x[r - base] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = tc * 16 + 4 * g + u;
+      double t2 = (q < r) ? L[u] * xr : 0.0;
+      t2 += __shfl_xor(t2, 8, 64);
+      t2 += __shfl_xor(t2, 4, 64);
+      t2 += __shfl_xor(t2, 2, 64);
+      t2 += __shfl_xor(t2, 1, 64);
+      if (a == 0 && q < s) y[q] += t2;
+    }
   }
   __syncthreads();
-  for (int r = tid; r < s; r += BS_THREADS) {
-    T acc = 0;
-    for (int q = 0; q < groups; ++q) acc += part[q * s + r];
-    out[r] = accumulate ? out[r] + sign * acc : sign * acc;
+  for (int i = tid; i < s; i += BS_THREADS) {
+    double acc = 0.0;
+    for (int w = 0; w < BS_WAVES; ++w) acc += yp[w * s + i];
+    out[i] = accumulate ? out[i] + sign * (T)acc : sign * (T)acc;
   }
+  __syncthreads();
 }
 
 template <typename T>
@@ -1860,8 +1902,8 @@ __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, Geo g, co
                                                             int setR, const T* __restrict__ G,
                                                             T* __restrict__ vec) {
   extern __shared__ char smem_raw[];
-  T* cl = reinterpret_cast<T*>(smem_raw);          // max_block
-  T* part = cl + P.max_block;                      // max(BS_THREADS, max_block)
+  double* yp = reinterpret_cast<double*>(smem_raw);                   // BS_WAVES x max_block
+  T* cl = reinterpret_cast<T*>(yp + (int64_t)BS_WAVES * P.max_block);  // max_block
   const int sub = blockIdx.x, rhs = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int nb = setR ? S.nbR : S.nbI;
@@ -1884,9 +1926,7 @@ __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, Geo g, co
       }
       cl[i] = c;
     }
-    __syncthreads();
-    block_gemv(G + B.G_off, B.size, B.size, cl, part, tid, v + B.start, false, (T)-1);
-    __syncthreads();
+    block_symv(G + B.G_off, B.size, 0, cl, yp, v + B.start, false, (T)-1, tid);
   }
   for (int k = nb - 2; k >= 0; --k) {
     const BlockDev B = blk[k];
@@ -1902,9 +1942,7 @@ __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, Geo g, co
       }
       cl[i] = (T)acc;
     }
-    __syncthreads();
-    block_gemv(G + B.G_off + (int64_t)B.size * base, B.size, B.last_n, cl, part, tid, v + B.start, true, (T)1);
-    __syncthreads();
+    block_symv(G + B.G_off, B.size, base, cl, yp, v + B.start, true, (T)1, tid);
   }
 }
 
@@ -2698,7 +2736,7 @@ int64_t max_lds_bytes(const PlanDev& P, int elt, int max_nrhs) {
   int64_t need = 0;
   need = hmax(need, mp * (SC_COLS + 1) * elt + 2048);                                  // schur couple
   need = hmax(need, mp * (CPL_COLS + 1) * elt);                                        // couple multi
-  need = hmax(need, (hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * elt);     // block solve
+  need = hmax(need, (int64_t)hmax(P.max_block, 1) * (BS_WAVES * 8 + elt));              // block solve
   if (max_nrhs >= 4) need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);  // many-rhs block solve
   need = hmax(need, (int64_t)(P.max_na + P.max_nc + 1) * elt);                         // v2
   need = hmax(need, (int64_t)hmax(P.max_ng, 1) * elt);                                 // coarse rhs
@@ -2941,12 +2979,12 @@ void Kern<T>::block_solve(const PlanDev& P, const Geo& g, const double* rho, int
     const size_t smr = (size_t)hmax(P.max_block, 1) * (MR_COLS + 1) * sizeof(T);
     k_block_solve_mr<T><<<dim3(P.n_sub, cdiv(nrhs, MR_COLS)), MR_THREADS, smr, s>>>(P, setR, G, v, nrhs);
   } else {
-    size_t sm = (size_t)(hmax(P.max_block, 1) + hmax(BS_THREADS, P.max_block)) * sizeof(T);
+    const size_t sm = (size_t)hmax(P.max_block, 1) * (BS_WAVES * sizeof(double) + sizeof(T));
     k_block_solve<T><<<dim3(P.n_sub, nrhs), BS_THREADS, sm, s>>>(P, g, rho, setR, G, v);
   }
-  // the method must stream each G entry once per launch (2 flops per rhs) and
-  // read and write each vector once
-  if (prof) prof->end(2, 2.0 * g_entries * nrhs, sizeof(T) * (g_entries + 2.0 * vec_entries * nrhs), s);
+  // the method must stream each lower-triangle G entry once per launch (4
+  // flops per rhs off the diagonal) and read and write each vector once
+  if (prof) prof->end(2, 4.0 * g_entries * nrhs, sizeof(T) * (g_entries + 2.0 * vec_entries * nrhs), s);
 }
 
 template <typename T>
