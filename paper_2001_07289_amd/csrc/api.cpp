@@ -233,6 +233,7 @@ struct bddcso_precond {
   EventProfiler prof;
   hipStream_t s2 = nullptr;                 // second stream of the setup
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_la = nullptr, ev_lb = nullptr;   // slab look-ahead of the coarse fronts
   double gI_entries = 0, gR_entries = 0;  // G entries streamed by one block solve
   Profiler* P_() { return prof.mask ? &prof : nullptr; }
 };
@@ -525,8 +526,9 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
     for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
       launch_front_child_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fpool, s);
     const Batch& b = pc->swFront[L];
+    const SweepAux aux{pc->s2, pc->ev_la, pc->ev_lb};
     Kern<double>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, pc->fpool, pc->fsw, pc->fsw_stride,
-                        pc->status, 4, s, pc->P_());
+                        pc->status, 4, s, pc->P_(), &aux);
   }
 }
 
@@ -671,6 +673,8 @@ void bddcso_precond_destroy(bddcso_precond* pc) {
   pc->mem.release();
   if (pc->ev_fork) (void)hipEventDestroy(pc->ev_fork);
   if (pc->ev_join) (void)hipEventDestroy(pc->ev_join);
+  if (pc->ev_la) (void)hipEventDestroy(pc->ev_la);
+  if (pc->ev_lb) (void)hipEventDestroy(pc->ev_lb);
   if (pc->s2) (void)hipStreamDestroy(pc->s2);
   if (pc->h_nactive) (void)hipHostFree(pc->h_nactive);
   delete pc;
@@ -858,6 +862,8 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     HIPCHK(hipStreamCreateWithFlags(&pc->s2, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_la, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_lb, hipEventDisableTiming));
   } catch (const PlanFail& f) {
     bddcso_precond_destroy(pc);
     return set_err(BDDCSO_EINVAL, "inconsistent plan: " + f.what);

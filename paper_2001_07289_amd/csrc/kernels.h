@@ -32,6 +32,13 @@ struct Profiler {
   virtual void end(int cls, double flops, double bytes, hipStream_t s) = 0;
 };
 
+// A second stream and two events for the slab sweep's look-ahead: the next
+// slab's pivot block is swept on s2 while the current trailing update runs.
+struct SweepAux {
+  hipStream_t s2;
+  hipEvent_t a, b;
+};
+
 // Device views of the plan tables.
 struct PlanDev {
   const SubDev* subs;
@@ -79,7 +86,7 @@ struct Kern {
                            T* G, T* W, int64_t wstride, hipStream_t s);
   static void sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int maxn, int maxp, T* pool,
                     T* scratch, int64_t scr_stride, int* status, int status_code, hipStream_t s,
-                    Profiler* prof);
+                    Profiler* prof, const SweepAux* aux = nullptr);
   static void gemm(const GemmDesc* d_desc, const GemmDesc* h_desc, int nprob, int maxm, int maxn,
                    const T* A, int transA, const T* B, int transB, T* C, T alpha, T beta, hipStream_t s,
                    Profiler* prof);

@@ -1178,10 +1178,12 @@ __global__ __launch_bounds__(256) void k_slab_cd(const SweepDesc* __restrict__ d
 }
 
 // 3. Lower-triangle tiles outside S: M_ij -= sum_q CD[i][q] C[j][q].
+// region: 0 every tile; 1 only the tiles of the next slab's pivot block;
+// 2 every tile but those (the two halves of the update, for the look-ahead).
 template <typename T>
 __global__ __launch_bounds__(256) void k_slab_update(const SweepDesc* __restrict__ desc, T* pool, int j0,
                                                      const T* __restrict__ scratch, int64_t scr_stride,
-                                                     int ntri, int nprob) {
+                                                     int ntri, int nprob, int region) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T As[32][TILE + PAD];  // CD rows i
   __shared__ T Bs[32][TILE + PAD];  // C rows j
@@ -1203,6 +1205,11 @@ __global__ __launch_bounds__(256) void k_slab_update(const SweepDesc* __restrict
   if (i0 >= n || c0 >= n) return;
   // tiles wholly inside the slab rows or columns take no update
   if ((i0 >= j0 && i0 + TILE <= j0 + sb) || (c0 >= j0 && c0 + TILE <= j0 + sb)) return;
+  if (region) {
+    const int j1 = j0 + sb, sbn = min(SLAB, d.p - j1);  // next slab's pivots
+    const bool nextd = sbn > 0 && i0 + TILE > j1 && i0 < j1 + sbn && c0 + TILE > j1 && c0 < j1 + sbn;
+    if ((region == 1) != nextd) return;
+  }
   T* A = pool + d.off;
   const T* CD = scratch + (int64_t)prob * scr_stride;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -2794,7 +2801,7 @@ void Kern<T>::schur_couple(const PlanDev& P, const Geo& g, const double* rho, in
 template <typename T>
 void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int maxn, int maxp, T* pool,
                     T* scratch, int64_t scr_stride, int* status, int status_code, hipStream_t s,
-                    Profiler* prof) {
+                    Profiler* prof, const SweepAux* aux) {
   if (nprob == 0 || maxp == 0) return;
   if (maxn <= 16 * RS_MAX_TILES) {
     // register-resident: one workgroup per matrix, read once, written once
@@ -2822,34 +2829,58 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
     static_assert(SLAB <= 16 * 12, "slab diagonal blocks use the 12-tile register sweep");
     const int64_t tiles = cdiv(maxn, TILE);
     const int64_t ntri = tiles * (tiles + 1) / 2;
+    // with a second stream: the next slab's pivot block is updated first and
+    // swept on s2 while the rest of the trailing update runs on s
+    auto reg = [&](int j0, hipStream_t ss) {
+      double df = 0, db = 0;
+      if (prof && h_desc)
+        for (int q = 0; q < nprob; ++q) {
+          const double p = h_desc[q].p;
+          if (j0 >= p) continue;
+          const double sb = std::min<double>(SLAB, p - j0);
+          df += sb * sb * sb;
+          db += sizeof(T) * (sb * (sb + 1) / 2 + sb * sb);
+        }
+      if (prof) prof->begin(5, ss);
+      k_sweep_reg<T, 12, 12><<<nprob, 12 * 64, 0, ss>>>(d_desc, pool, status, status_code, j0);
+      if (prof) prof->end(5, df, db, ss);
+    };
+    reg(0, s);
     for (int j0 = 0; j0 < maxp; j0 += SLAB) {
-      double df = 0, db = 0, cf = 0, cb = 0, uf = 0, ub = 0;
+      double cf = 0, cb = 0, uf = 0, ub = 0;
       if (prof && h_desc)
         for (int q = 0; q < nprob; ++q) {
           const double n = h_desc[q].n, p = h_desc[q].p;
           if (j0 >= p) continue;
           const double sb = std::min<double>(SLAB, p - j0), m = n - sb;
           const double low = m * (m + 1) / 2;
-          df += sb * sb * sb;
-          db += sizeof(T) * (sb * (sb + 1) / 2 + sb * sb);
           cf += 2.0 * m * sb * sb;
           cb += sizeof(T) * (2.0 * m * sb + sb * sb);
           uf += 2.0 * sb * low;
           ub += sizeof(T) * (2.0 * low + 2.0 * m * sb);
         }
-      if (prof) prof->begin(5, s);
-      k_sweep_reg<T, 12, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code, j0);
-      if (prof) prof->end(5, df, db, s);
+      if (aux && j0 > 0) (void)hipStreamWaitEvent(s, aux->b, 0);  // this slab's pivot block is swept
       if (prof) prof->begin(4, s);
       k_slab_cd<T><<<dim3(cdiv(maxn, TILE), cdiv(SLAB, TILE), nprob), 256, 0, s>>>(d_desc, pool, j0, scratch,
                                                                                   scr_stride);
       if (prof) prof->end(4, cf, cb, s);
+      const unsigned ublk = (unsigned)((ntri * nprob + 7) / 8 * 8);
+      const bool next = j0 + SLAB < maxp;
       if (prof) prof->begin(1, s);
-      k_slab_update<T><<<(unsigned)((ntri * nprob + 7) / 8 * 8), 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride,
-                                                                              (int)ntri, nprob);
+      if (next && aux) {
+        k_slab_update<T><<<ublk, 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, (int)ntri, nprob, 1);
+        (void)hipEventRecord(aux->a, s);
+        (void)hipStreamWaitEvent(aux->s2, aux->a, 0);
+        reg(j0 + SLAB, aux->s2);
+        (void)hipEventRecord(aux->b, aux->s2);
+        k_slab_update<T><<<ublk, 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, (int)ntri, nprob, 2);
+      } else {
+        k_slab_update<T><<<ublk, 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, (int)ntri, nprob, 0);
+      }
       if (prof) prof->end(1, uf, ub, s);
       k_slab_writeback<T><<<dim3((unsigned)hmin(cdiv((int64_t)maxn * SLAB, 256), 2048), nprob), 256, 0, s>>>(
           d_desc, pool, j0, scratch, scr_stride);
+      if (next && !aux) reg(j0 + SLAB, s);
     }
     const int64_t st = cdiv(maxn, 32);
     k_symmetrize<T><<<dim3((unsigned)hmin(st * (st + 1) / 2, 4096), nprob), 256, 0, s>>>(d_desc, pool, 0);
