@@ -232,7 +232,9 @@ struct bddcso_precond {
   int max_nrhs = 1;
   EventProfiler prof;
   hipStream_t s2 = nullptr;                 // second stream of the setup
+  hipStream_t s3 = nullptr;                 // third stream: the interior factors
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork_i = nullptr, ev_join_i = nullptr;
   hipEvent_t ev_la = nullptr, ev_lb = nullptr;   // slab look-ahead of the coarse fronts
   double gI_entries = 0, gR_entries = 0;  // G entries streamed by one block solve
   Profiler* P_() { return prof.mask ? &prof : nullptr; }
@@ -385,11 +387,12 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       const SubDev& S = pl.subs[sidx];
       if (S.n_a > 0) {
         d.push_back({S.Sc_off, S.n_a, S.n_a, S.n_a});
-        if (S.n_c > 0) {
-          lam.push_back({S.Sc_off, S.T_off, S.T_off, S.n_a, S.n_c, S.n_a, S.n_a, S.n_a, S.n_a});
-          phir.push_back({S.XG_off, S.T_off, S.PhiG_off, S.n_s, S.n_c, S.n_a, S.n_s, S.n_a, S.n_s});
-        }
+        if (S.n_c > 0) lam.push_back({S.Sc_off, S.T_off, S.T_off, S.n_a, S.n_c, S.n_a, S.n_a, S.n_a, S.n_a});
       }
+      // every subdomain with coarse dofs: the product writes all of Phi's
+      // selected rows (-X Lambda, 0 when there are no averages)
+      if (S.n_c > 0)
+        phir.push_back({S.XG_off, S.T_off, S.PhiG_off, S.n_s, S.n_c, S.n_a, S.n_s, std::max(S.n_a, 1), S.n_s});
     }
     check_sweeps(d, pl.pool_Sc, ns, "S_c");
     check_gemms(lam, pl.pool_Sc, pl.pool_T, pl.pool_T, "Lambda GEMM");
@@ -470,13 +473,12 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   else launch_fill_f32((float*)N.G, pl.pool_G, 0.0f, s);
   Kern<T>::block_assemble(P, g, rho, 0, N.G, s);
   Kern<T>::block_assemble(P, g, rho, 1, N.G, s);
-  // The interior (Dirichlet) factors are needed only when the preconditioner
-  // is applied, so they are built on a second stream, overlapping the rest
-  // of the setup; the caller's stream waits for them at the end.
+  // the coarse front pool is zeroed on a second stream (it is summed into later)
   HIPCHK(hipEventRecord(pc->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_fork, 0));
-  for (int setR = 1; setR >= 0; --setR) {
-    hipStream_t ss = setR ? s : pc->s2;
+  launch_fill_f64(pc->fpool, pl.front_pool, 0.0, pc->s2);
+  HIPCHK(hipEventRecord(pc->ev_join, pc->s2));
+  auto factor_chain = [&](int setR, hipStream_t ss) {
     T* W = setR ? N.W : N.W2;
     T* sws = setR ? N.sw : N.sw2;
     auto& sw = setR ? pc->swR : pc->swI;
@@ -485,10 +487,8 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
       Kern<T>::sweep((SweepDesc*)sw[k].desc, sw[k].hs.data(), sw[k].n, sw[k].maxn, sw[k].maxp, N.G, sws,
                      N.sw_stride, pc->status, setR ? 2 : 1, ss, pc->P_());
     }
-  }
-  // the coarse front pool is zeroed on the second stream too (it is summed into later)
-  launch_fill_f64(pc->fpool, pl.front_pool, 0.0, pc->s2);
-  HIPCHK(hipEventRecord(pc->ev_join, pc->s2));
+  };
+  factor_chain(1, s);
   // [X | Y'] = K_rr^{-1} [C_r^T | -K_rv]
   if (sizeof(T) == 8) launch_fill_f64((double*)N.Z, pl.pool_Z, 0.0, s);
   else launch_fill_f32((float*)N.Z, pl.pool_Z, 0.0f, s);
@@ -514,12 +514,21 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   Kern<T>::gemm((GemmDesc*)pc->gLam.desc, pc->gLam.hg.data(), pc->gLam.n, pc->gLam.maxm, pc->gLam.maxn, N.Sc, 0,
                 N.Tm, 0, N.Lam, (T)-1, (T)0, s, pc->P_());
   // Phi = Y' - X Lambda, only at the selected rows (Gamma and the vertices' stencils)
-  Kern<T>::sel_gather(P, N.Z, N.XG, N.PhiG, s);
+  Kern<T>::sel_gather(P, N.Z, N.XG, s);
   Kern<T>::gemm((GemmDesc*)pc->gSel.desc, pc->gSel.hg.data(), pc->gSel.n, pc->gSel.maxm, pc->gSel.maxn, N.XG, 0,
-                N.Lam, 0, N.PhiG, (T)-1, (T)1, s, pc->P_());
+                N.Lam, 0, N.PhiG, (T)-1, (T)0, s, pc->P_());
+  Kern<T>::phi_add(P, N.Z, N.PhiG, pc->max_nv, s);
   Kern<T>::kc_identity(P, g, rho, N.PhiG, N.Lam, N.Kc, pc->vcoef, pc->vcode, pc->max_nv, s);
+  // The interior (Dirichlet) factors are needed only when the preconditioner
+  // is applied, so they are built on a third stream while the coarse
+  // factorization runs (its upper levels occupy few compute units); the
+  // caller's stream waits for them at the end.
+  HIPCHK(hipEventRecord(pc->ev_fork_i, s));
+  HIPCHK(hipStreamWaitEvent(pc->s3, pc->ev_fork_i, 0));
+  factor_chain(0, pc->s3);
+  HIPCHK(hipEventRecord(pc->ev_join_i, pc->s3));
   // coarse: assemble into the fronts and factor level by level (FP64)
-  HIPCHK(hipStreamWaitEvent(s, pc->ev_join, 0));  // interior factors and the zeroed front pool
+  HIPCHK(hipStreamWaitEvent(s, pc->ev_join, 0));  // the zeroed front pool
   for (size_t c = 0; c < pc->color_dev.size(); ++c)
     Kern<T>::kc_to_front(P, pc->color_dev[c], pc->color_n[c], N.Kc, pc->fpool, s);
   for (size_t L = 0; L < pc->swFront.size(); ++L) {
@@ -530,6 +539,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
     Kern<double>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, pc->fpool, pc->fsw, pc->fsw_stride,
                         pc->status, 4, s, pc->P_(), &aux);
   }
+  HIPCHK(hipStreamWaitEvent(s, pc->ev_join_i, 0));  // the interior factors
 }
 
 void coarse_solve(bddcso_precond* pc, int nrhs, hipStream_t s) {
@@ -670,12 +680,16 @@ bddcso_status bddcso_problem_info(const bddcso_problem* p, int primal_mask, int6
 void bddcso_precond_destroy(bddcso_precond* pc) {
   if (!pc) return;
   if (pc->s2) (void)hipStreamSynchronize(pc->s2);
+  if (pc->s3) (void)hipStreamSynchronize(pc->s3);
   pc->mem.release();
   if (pc->ev_fork) (void)hipEventDestroy(pc->ev_fork);
   if (pc->ev_join) (void)hipEventDestroy(pc->ev_join);
   if (pc->ev_la) (void)hipEventDestroy(pc->ev_la);
   if (pc->ev_lb) (void)hipEventDestroy(pc->ev_lb);
+  if (pc->ev_fork_i) (void)hipEventDestroy(pc->ev_fork_i);
+  if (pc->ev_join_i) (void)hipEventDestroy(pc->ev_join_i);
   if (pc->s2) (void)hipStreamDestroy(pc->s2);
+  if (pc->s3) (void)hipStreamDestroy(pc->s3);
   if (pc->h_nactive) (void)hipHostFree(pc->h_nactive);
   delete pc;
 }
@@ -818,6 +832,8 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     P.max_nI = max_nI;
     P.max_zcols = pl.max_zcols;
     P.max_plane = max_plane;
+    P.max_nv = 0;
+    for (auto& S : pl.subs) P.max_nv = std::max(P.max_nv, S.n_v);
     if (max_lds_bytes(P, o.precision == 1 ? 4 : 8, o.max_nrhs) > 160 * 1024)
       throw PlanFail{"a subdomain plane or block is too large for the LDS staging of the local kernels"};
 
@@ -860,6 +876,9 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     pc->nactive = m.alloc<int32_t>(1);
     HIPCHK(hipHostMalloc((void**)&pc->h_nactive, sizeof(int32_t) * 4, hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&pc->s2, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&pc->s3, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_fork_i, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_join_i, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_la, hipEventDisableTiming));

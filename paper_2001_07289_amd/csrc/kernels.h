@@ -62,7 +62,7 @@ struct PlanDev {
   int64_t n_cpl;
   int n_sub;
   int64_t tot_I, tot_r, tot_g, tot_c, tot_a, n_gam, n_coarse;
-  int max_block, max_na, max_nc, max_ng, max_ns, max_nloc, max_nr, max_nI, max_zcols, max_plane;
+  int max_block, max_na, max_nc, max_ng, max_ns, max_nloc, max_nr, max_nI, max_zcols, max_plane, max_nv;
 };
 
 // ---- launchers (defined in kernels.hip) ---------------------------------
@@ -96,7 +96,8 @@ struct Kern {
   static void sc_assemble(const PlanDev& P, const T* Z, T* Sc, hipStream_t s);
   static void lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s);
   // rows of [X | Phi initialised to Y'] at the selected rows
-  static void sel_gather(const PlanDev& P, const T* Z, T* XS, T* PS, hipStream_t s);
+  static void sel_gather(const PlanDev& P, const T* Z, T* XS, hipStream_t s);
+  static void phi_add(const PlanDev& P, const T* Z, T* PS, int max_nv, hipStream_t s);
   static void kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PS,
                           const T* Lam, T* Kc, double* vcoef, int32_t* vcode, int max_nv, hipStream_t s);
   static void kc_to_front(const PlanDev& P, const int32_t* subs_of_color, int ns, const T* Kc,
@@ -151,6 +152,7 @@ void launch_pcg_p_flex(double* p, const double* z, const double* zdr, const doub
                        const int32_t* active, int64_t n, int nrhs, hipStream_t s);
 void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);
 void launch_copy16(const void* a, void* b, int64_t n16, hipStream_t s);
+int kc_cols(const PlanDev& P);
 int64_t max_lds_bytes(const PlanDev& P, int elt, int max_nrhs);
 // Chunks of pivot columns of the split forward front step (partial-sum rows).
 int front_fwd_chunks(int maxp);

@@ -242,21 +242,20 @@ __global__ void k_delta(PlanDev P, const double* __restrict__ alpha, double* __r
 // Plane-coupling coefficients A[i, j] between a block's boundary plane node i
 // and its neighbours j in the adjacent block, from rho (one thread per row).
 __global__ void k_coupling_coefs(PlanDev P, Geo g, const double* __restrict__ rho, double* __restrict__ coef) {
-  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (row >= P.n_cpl) return;
-  const SubDev S = P.subs[P.cpl_sub[row]];
-  int c[3];
-  loc_coords(S, P.cpl_loc[row], c);
-  const int dir = P.cpl_dir[row];
-  for (int t = 0; t < 9; ++t) {
-    double v = 0.0;
-    if (P.cpl_rank[row * 9 + t] >= 0) {
-      int cn[3];
-      plane_nbr(S, g.dim, c, dir, t, cn);
-      v = kloc(S, g, rho, P.khat, c, cn);
-    }
-    coef[row * 9 + t] = v;
+  // one thread per (row, neighbour): the stores are contiguous
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= P.n_cpl * 9) return;
+  const int64_t row = e / 9;
+  const int t = (int)(e - row * 9);
+  double v = 0.0;
+  if (P.cpl_rank[e] >= 0) {
+    const SubDev S = P.subs[P.cpl_sub[row]];
+    int c[3], cn[3];
+    loc_coords(S, P.cpl_loc[row], c);
+    plane_nbr(S, g.dim, c, P.cpl_dir[row], t, cn);
+    v = kloc(S, g, rho, P.khat, c, cn);
   }
+  coef[e] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1287,10 +1286,9 @@ __global__ void k_slab_writeback(const SweepDesc* __restrict__ desc, T* pool, in
   if (sb <= 0) return;
   T* A = pool + d.off;
   const T* CD = scratch + (int64_t)blockIdx.y * scr_stride;
-  const int64_t tot = (int64_t)n * sb;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(idx % n), q = (int)(idx / n);
+  const int tot = n * sb;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
+    const int i = idx % n, q = idx / n;
     if (i >= j0 && i < j0 + sb) continue;
     const T v = CD[i + (int64_t)n * q];
     if (i > j0) A[i + (int64_t)ld * (j0 + q)] = v;
@@ -1616,9 +1614,18 @@ __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd,
     const BlockDev O = P.blocks[S.bR_off + (fwd ? k - 1 : k + 1)];
     sbase = fwd ? O.start + O.size - O.last_n : O.start;  // first rank of the source plane
     const int sn = fwd ? O.last_n : O.first_n;
-    for (int idx = threadIdx.x; idx < sn * nc; idx += blockDim.x) {
-      const int r = idx % sn, c = idx / sn;
-      src[r][c] = z[sbase + r + (int64_t)S.n_r * (c0 + c)];
+    for (int b0 = 0; b0 < sn * nc; b0 += 8 * 256) {  // 8 loads in flight per thread
+      T vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = b0 + threadIdx.x + 256 * u, r = idx % sn, c = idx / sn;
+        vv[u] = idx < sn * nc ? z[sbase + r + (int64_t)S.n_r * (c0 + c)] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = b0 + threadIdx.x + 256 * u, r = idx % sn, c = idx / sn;
+        if (idx < sn * nc) src[r][c] = vv[u];
+      }
     }
     __syncthreads();
   }
@@ -1638,14 +1645,19 @@ __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd,
       a[t] = rk >= 0 ? P.cpl_coef[(roff + i) * 9 + t] : 0.0;
       l[t] = rk >= 0 ? rk - sbase : 0;
     }
-    for (int c = 0; c < nc; ++c) {
+    T zin[CPL_COLS];  // the block's right-hand side, all columns' loads in flight at once
+#pragma unroll
+    for (int c = 0; c < CPL_COLS; ++c)
+      zin[c] = (fwd && c < nc) ? z[B.start + i + (int64_t)S.n_r * (c0 + c)] : (T)0;
+#pragma unroll
+    for (int c = 0; c < CPL_COLS; ++c) {
+      if (c >= nc) break;
       double acc = 0.0;
       if (ci) {
 #pragma unroll
         for (int t = 0; t < 9; ++t) acc += a[t] * (double)src[l[t]][c];
       }
-      if (fwd) tp[i + (int64_t)ld * (c0 + c)] = z[B.start + i + (int64_t)S.n_r * (c0 + c)] - (T)acc;
-      else tp[i + (int64_t)ld * (c0 + c)] = (T)acc;
+      tp[i + (int64_t)ld * (c0 + c)] = fwd ? zin[c] - (T)acc : (T)acc;
     }
   }
 }
@@ -1686,34 +1698,35 @@ __global__ void k_lambda_rhs(PlanDev P, const T* __restrict__ Z, T* __restrict__
   Tm[S.T_off + idx] = (T)v;
 }
 
-// Rows of X and of Phi's initial value [Y' by coarse kind | 0] at the
-// selected rows; at a Gamma entry that is a primal vertex, X is 0 and Phi is
-// the unit row of the vertex's coarse dof.  Phi = Y' - X Lambda then needs
-// the product only over these rows.
+// Rows of X at the selected rows (0 at a Gamma entry that is a primal vertex).
 template <typename T>
-__global__ void k_sel_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__ XS, T* __restrict__ PS) {
+__global__ void k_sel_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__ XS) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
-  const int64_t totx = (int64_t)S.n_s * S.n_a, tot = totx + (int64_t)S.n_s * S.n_c;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    if (idx < totx) {
-      const int e = (int)(idx % S.n_s), a = (int)(idx / S.n_s);
-      const int r = P.sel_r[S.sel_off + e];
-      XS[S.XG_off + idx] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * a] : (T)0;
-    } else {
-      const int64_t j = idx - totx;
-      const int e = (int)(j % S.n_s), c = (int)(j / S.n_s);
-      const int r = P.sel_r[S.sel_off + e];
-      T v;
-      if (r >= 0) {
-        const int kind = P.c_kind[S.c_off + c];
-        v = kind >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * (S.n_a + kind)] : (T)0;
-      } else {
-        v = P.v_c[S.v_off + P.g_v[S.g_off + e]] == c ? (T)1 : (T)0;
-      }
-      PS[S.PhiG_off + j] = v;
-    }
+  const int tot = S.n_s * S.n_a;  // per subdomain: 32-bit index math
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
+    const int e = idx % S.n_s, a = idx / S.n_s;
+    const int r = P.sel_r[S.sel_off + e];
+    XS[S.XG_off + idx] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * a] : (T)0;
+  }
+}
+
+// Phi = Y' - X Lambda at the selected rows: after the product has written
+// -X Lambda, add Y' = -K_rr^{-1} K_rv (nonzero only in the vertex columns) and
+// put the unit entry of the vertex's coarse dof in the rows of Gamma entries
+// that are primal vertices (X is 0 there).
+template <typename T>
+__global__ void k_phi_add(PlanDev P, const T* __restrict__ Z, T* __restrict__ PS) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int tot = S.n_s * S.n_v;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
+    const int e = idx % S.n_s, v = idx / S.n_s;
+    const int r = P.sel_r[S.sel_off + e];
+    const int c = P.v_c[S.v_off + v];
+    T* dst = PS + S.PhiG_off + e + (int64_t)S.n_s * c;
+    if (r >= 0) *dst = Z[S.Z_off + r + (int64_t)S.n_r * (S.n_a + v)] + *dst;
+    else if (P.g_v[S.g_off + e] == v) *dst = (T)1;
   }
 }
 
@@ -1751,37 +1764,106 @@ __global__ void k_vertex_stencil(PlanDev P, Geo g, const double* __restrict__ rh
   vcoef[out] = kloc(S, g, rho, P.khat, cv, cn);
 }
 
+// Every entry (c, c2) of a chunk of columns from its row's equation.  The
+// chunk's columns of Phi (all selected rows) and the subdomain's vertex
+// stencils are staged in LDS with coalesced loads; a vertex row's entry is
+// then a 27-term sum over LDS, an average row's entry a copy of -Lambda.
 template <typename T>
-__device__ __forceinline__ double kc_entry(const PlanDev& P, const SubDev& S, const T* __restrict__ PhiR,
-                                           const T* __restrict__ Lam, const double* __restrict__ vcoef,
-                                           const int32_t* __restrict__ vcode, int c, int c2) {
-  const int kind = P.c_kind[S.c_off + c];
-  if (kind < 0) return -(double)Lam[S.T_off + (-kind - 1) + (int64_t)S.n_a * c2];
-  const int64_t base = (S.v_off + kind) * 27;
-  double acc = 0.0;
-  for (int t = 0; t < 27; ++t) {
-    const int code = vcode[base + t];
-    if (code == INT32_MIN) continue;
-    const double phi = code >= 0 ? (double)PhiR[S.PhiG_off + code + (int64_t)S.n_s * c2] : (-code - 1 == c2 ? 1.0 : 0.0);
-    acc += vcoef[base + t] * phi;
+__global__ __launch_bounds__(256) void k_kc_identity(PlanDev P, const T* __restrict__ PhiR, const T* __restrict__ Lam,
+                                                     const double* __restrict__ vcoef,
+                                                     const int32_t* __restrict__ vcode, T* __restrict__ Kc,
+                                                     int kc_cols) {
+  extern __shared__ double phs[];  // [kc_cols][n_s] Phi, then [n_v][27] coefficients, then [n_v][27] codes
+  const SubDev S = P.subs[blockIdx.y];
+  const int c0 = blockIdx.x * kc_cols;
+  if (c0 >= S.n_c) return;
+  const int nc = min(kc_cols, S.n_c - c0), ns = S.n_s, nv27 = S.n_v * 27;
+  double* scoef = phs + (int64_t)kc_cols * P.max_ns;
+  int32_t* scode = reinterpret_cast<int32_t*>(scoef + (int64_t)27 * P.max_nv);
+  // the chunk's columns are contiguous (ld n_s): a straight copy, 8 loads in flight per thread
+  const T* src = PhiR + S.PhiG_off + (int64_t)ns * c0;
+  const int tot = ns * nc;
+  for (int b0 = 0; b0 < tot; b0 += 8 * 256) {
+    T r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = b0 + threadIdx.x + 256 * u;
+      r[u] = i < tot ? src[i] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = b0 + threadIdx.x + 256 * u;
+      if (i < tot) phs[i] = (double)r[u];
+    }
   }
-  return acc;
+  for (int b0 = 0; b0 < nv27; b0 += 4 * 256) {
+    double cf[4];
+    int32_t cd[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = b0 + threadIdx.x + 256 * u;
+      cf[u] = i < nv27 ? vcoef[S.v_off * 27 + i] : 0.0;
+      cd[u] = i < nv27 ? vcode[S.v_off * 27 + i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = b0 + threadIdx.x + 256 * u;
+      if (i < nv27) {
+        scoef[i] = cf[u];
+        scode[i] = cd[u];
+      }
+    }
+  }
+  __syncthreads();
+  // vertex rows: thread (v, j)
+  for (int idx = threadIdx.x; idx < S.n_v * nc; idx += blockDim.x) {
+    const int v = idx % S.n_v, j = idx / S.n_v, c2 = c0 + j;
+    double acc = 0.0;
+    for (int t = 0; t < 27; ++t) {
+      const int code = scode[v * 27 + t];
+      if (code == INT32_MIN) continue;
+      const double phi = code >= 0 ? phs[j * ns + code] : (-code - 1 == c2 ? 1.0 : 0.0);
+      acc += scoef[v * 27 + t] * phi;
+    }
+    Kc[S.Kc_off + P.v_c[S.v_off + v] + (int64_t)S.n_c * c2] = (T)acc;
+  }
+  // average rows
+  for (int idx = threadIdx.x; idx < S.n_c * nc; idx += blockDim.x) {
+    const int c = idx % S.n_c, j = idx / S.n_c, c2 = c0 + j;
+    const int kind = P.c_kind[S.c_off + c];
+    if (kind < 0) Kc[S.Kc_off + c + (int64_t)S.n_c * c2] = (T)(-(double)Lam[S.T_off + (-kind - 1) + (int64_t)S.n_a * c2]);
+  }
 }
 
+// Kc <- (Kc + Kc^T) / 2 in place, by pairs of 32 x 32 tiles (ti >= tj)
+// staged in LDS, so reads and writes run along columns.
 template <typename T>
-__global__ void k_kc_identity(PlanDev P, const T* __restrict__ PhiR, const T* __restrict__ Lam,
-                              const double* __restrict__ vcoef, const int32_t* __restrict__ vcode,
-                              T* __restrict__ Kc) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= S.n_c * S.n_c) return;
-  const int c = idx % S.n_c, c2 = idx / S.n_c;
-  if (c2 < c) return;
-  const double v = 0.5 * (kc_entry(P, S, PhiR, Lam, vcoef, vcode, c, c2) +
-                          kc_entry(P, S, PhiR, Lam, vcoef, vcode, c2, c));
-  Kc[S.Kc_off + c + (int64_t)S.n_c * c2] = (T)v;
-  Kc[S.Kc_off + c2 + (int64_t)S.n_c * c] = (T)v;
+__global__ void k_kc_symmetrize(PlanDev P, T* __restrict__ Kc) {
+  __shared__ double ta[32][33], tb[32][33];
+  const SubDev S = P.subs[blockIdx.y];
+  const int n = S.n_c, nt = (n + 31) / 32;
+  int lin = blockIdx.x, ti = 0;
+  if (lin >= nt * (nt + 1) / 2) return;
+  while (lin > ti) lin -= ++ti;
+  const int tj = lin;
+  T* K = Kc + S.Kc_off;
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    const int r = e % 32, q = e / 32;
+    const int i = ti * 32 + r, j = tj * 32 + q;        // tile (ti, tj)
+    ta[r][q] = (i < n && j < n) ? (double)K[i + (int64_t)n * j] : 0.0;
+    const int i2 = tj * 32 + r, j2 = ti * 32 + q;      // tile (tj, ti)
+    tb[r][q] = (i2 < n && j2 < n) ? (double)K[i2 + (int64_t)n * j2] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    const int r = e % 32, q = e / 32;
+    const double v = 0.5 * (ta[r][q] + tb[q][r]);       // entry (ti*32 + r, tj*32 + q)
+    const int i = ti * 32 + r, j = tj * 32 + q;
+    if (i < n && j < n) K[i + (int64_t)n * j] = (T)v;
+    const double w = 0.5 * (tb[r][q] + ta[q][r]);       // entry (tj*32 + r, ti*32 + q)
+    const int i2 = tj * 32 + r, j2 = ti * 32 + q;
+    if (ti != tj && i2 < n && j2 < n) K[i2 + (int64_t)n * j2] = (T)w;
+  }
 }
 
 template <typename T>
@@ -1803,9 +1885,9 @@ __global__ void k_front_child_scatter(PlanDev P, const int32_t* __restrict__ chi
   const FrontDev C = P.fronts[ch];
   const FrontDev F = P.fronts[C.parent];
   const int nb = C.n - C.p;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)nb * nb) return;
-  const int a = (int)(idx % nb), b = (int)(idx / nb);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // fronts stay far below 46340 rows
+  if (idx >= nb * nb) return;
+  const int a = idx % nb, b = idx / nb;
   const int pa = P.front_pmap[C.pmap_off + a], pb = P.front_pmap[C.pmap_off + b];
   fpool[F.off + pa + (int64_t)F.n * pb] += fpool[C.off + (C.p + a) + (int64_t)C.n * (C.p + b)];
 }
@@ -1830,126 +1912,286 @@ __global__ void k_gather_I(PlanDev P, Geo g, const double* __restrict__ r, T* __
 // coupling table.  G_k is symmetric, so only its lower triangle is read:
 // each 16x16 lower tile T(r, q) adds T c_q to rows r and T^T c_r to rows q.
 // The backward product G_k[:, base:] c (the last-plane columns) reads the
-// band of lower rows >= base the same way.  Waves take tiles round-robin,
-// keep partial sums per wave in LDS and the waves' sums are added in fixed
-// order, so the result is bitwise repeatable.
-constexpr int BS_THREADS = 1024;
+// band of lower rows >= base the same way.
+//
+// The steps form one chain per workgroup, so the kernel is built to keep
+// HBM busy across it: the tiles of the next step's block (which do not
+// depend on the solution) are loaded into registers as soon as the current
+// step's tiles are consumed, and the next step's coupling terms and vector
+// entries are loaded before that.  The neighbour block's values that the
+// coupling reads stay in LDS from the step that produced them.  Waves take
+// tiles round-robin, keep partial sums per wave in LDS and the waves' sums
+// are added in fixed order, so the result is bitwise repeatable.
+constexpr int BS_THREADS = 512;
 constexpr int BS_WAVES = BS_THREADS / 64;
+constexpr int BS_PT = 10;  // tiles per wave held in registers: blocks up to 192 rows
+constexpr int BS_CP = 3;   // coupling terms per thread held in registers: 170 coupled rows
 
-// out[i] (+)= sign * sum_{j >= base} G[i][j] x[j - base], i < s, from the lower
-// triangle of the symmetric s x s matrix M (column-major, ld s) restricted to
-// rows >= base.  yp: BS_WAVES x s doubles of LDS.  Every thread of the
-// workgroup calls it; it ends with a barrier.
+// Tile lin of the lower triangle restricted to tile rows >= t0: first the
+// rectangle left of tile column t0, then the triangle of tile rows/columns >= t0.
+__device__ __forceinline__ void bs_tile_rc(int lin, int t0, int nrow, int& tr, int& tc) {
+  if (lin < nrow * t0) {
+    tr = t0 + lin / t0;
+    tc = lin % t0;
+  } else {
+    int l2 = lin - nrow * t0, q = 0;  // integer steps only, so wave-uniform inputs stay scalar
+    while (l2 > q) l2 -= ++q;
+    tr = t0 + q;
+    tc = t0 + l2;
+  }
+}
+
+// lane (a, g) loads the entries (16 tr + a, 16 tc + 4 g + u), u < 4, of the
+// lower triangle; outside it or above row s / below row base it loads the
+// block's first entry, which bs_tile_mul ignores.  The tile's
+// origin is wave-uniform, so each load is a scalar base plus a 32-bit lane
+// offset.
 template <typename T>
-__device__ __forceinline__ void block_symv(const T* __restrict__ M, int s, int base, const T* __restrict__ x,
-                                           double* __restrict__ yp, T* __restrict__ out, bool accumulate, T sign,
-                                           int tid) {
-  const int wave = tid >> 6, lane = tid & 63, a = lane & 15, g = lane >> 4;
-  for (int i = tid; i < BS_WAVES * s; i += BS_THREADS) yp[i] = 0.0;
-  __syncthreads();
-  double* y = yp + wave * s;
-  const int nt = (s + 15) >> 4, t0 = base >> 4;
-  const int nrow = nt - t0;
-  const int ntiles = nrow * t0 + nrow * (nrow + 1) / 2;  // tile rows t0.., tile columns 0..row
-  for (int lin = wave; lin < ntiles; lin += BS_WAVES) {
-    int tr, tc;
-    if (lin < nrow * t0) {  // rectangle left of the band's first tile column
-      tr = t0 + lin / t0;
-      tc = lin % t0;
-    } else {
-      const int l2 = lin - nrow * t0;
-      int q = (int)((sqrt(8.0 * l2 + 1.0) - 1.0) * 0.5);
-      while ((q + 1) * (q + 2) / 2 <= l2) ++q;
-      while (q * (q + 1) / 2 > l2) --q;
-      tr = t0 + q;
-      tc = t0 + (l2 - q * (q + 1) / 2);
-    }
-    const int r = tr * 16 + a;
-    const bool rok = r < s && r >= base;
-    double L[4];
+__device__ __forceinline__ void bs_tile_load(const T* __restrict__ M, int s, int base, int tr, int tc, int a, int g,
+                                             T (&L)[4]) {
+  const int r = tr * 16 + a;
+  const bool rok = r < s && r >= base;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = tc * 16 + 4 * g + u;
-      L[u] = (rok && q <= r) ? (double)M[(int64_t)q * s + r] : 0.0;
-    }
-    // rows r: sum over the tile's columns q >= base
-    double t1 = 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = tc * 16 + 4 * g + u;
-      if (q >= base && q < s) t1 += L[u] * (double)x[q - base];
-    }
-    t1 += __shfl_xor(t1, 16, 64);
-    t1 += __shfl_xor(t1, 32, 64);
-    if (g == 0 && rok) y[r] += t1;
-    // columns q < r: the transposed entries times x at the rows
-    const double xr = rok ? (double)x[r - base] : 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = tc * 16 + 4 * g + u;
-      double t2 = (q < r) ? L[u] * xr : 0.0;
-      t2 += __shfl_xor(t2, 8, 64);
-      t2 += __shfl_xor(t2, 4, 64);
-      t2 += __shfl_xor(t2, 2, 64);
-      t2 += __shfl_xor(t2, 1, 64);
-      if (a == 0 && q < s) y[q] += t2;
-    }
+  for (int u = 0; u < 4; ++u) {
+    const int q = tc * 16 + 4 * g + u;
+    const bool on = rok && q <= r;
+    // every lane loads (entry 0 when off: bs_tile_mul masks it), from the
+    // uniform block base plus a 32-bit byte offset; nothing touches the
+    // value until it is used, so the load stays in flight
+    const uint32_t byte = on ? (uint32_t)(q * s + r) * (uint32_t)sizeof(T) : 0u;
+    L[u] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(M) + byte);
   }
-  __syncthreads();
-  for (int i = tid; i < s; i += BS_THREADS) {
-    double acc = 0.0;
-    for (int w = 0; w < BS_WAVES; ++w) acc += yp[w * s + i];
-    out[i] = accumulate ? out[i] + sign * (T)acc : sign * (T)acc;
+}
+
+// y[r] += sum_{q >= base} T(r, q) x[q - base] (rows of the tile) and
+// y[q] += T(r, q) x[r - base] for q < r (the mirrored upper entries).
+template <typename T>
+__device__ __forceinline__ void bs_tile_mul(const T (&L)[4], int s, int base, int tr, int tc, int a, int g,
+                                            const T* __restrict__ x, double* __restrict__ y) {
+  const int r = tr * 16 + a;
+  const bool rok = r < s && r >= base;
+  double t1 = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int q = tc * 16 + 4 * g + u;
+    if (rok && q >= base && q <= r) t1 += (double)L[u] * (double)x[q - base];
   }
-  __syncthreads();
+  t1 += __shfl_xor(t1, 16, 64);
+  t1 += __shfl_xor(t1, 32, 64);
+  if (g == 0 && rok) y[r] += t1;
+  const double xr = rok ? (double)x[r - base] : 0.0;
+  double p[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) p[u] = (rok && tc * 16 + 4 * g + u < r) ? (double)L[u] * xr : 0.0;
+  // sum p[u] over the 16 lanes a by halving: after the exchange across
+  // lane bit 3 a lane keeps two columns, after bit 2 one column
+  // u = 2 (a>>3 & 1) + (a>>2 & 1), and bits 1 and 0 complete the sum
+  const bool h8 = (a & 8) != 0, h4 = (a & 4) != 0;
+  double k0 = h8 ? p[2] : p[0], k1 = h8 ? p[3] : p[1];
+  k0 += __shfl_xor(h8 ? p[0] : p[2], 8, 64);
+  k1 += __shfl_xor(h8 ? p[1] : p[3], 8, 64);
+  double k2 = h4 ? k1 : k0;
+  k2 += __shfl_xor(h4 ? k0 : k1, 4, 64);
+  k2 += __shfl_xor(k2, 2, 64);
+  k2 += __shfl_xor(k2, 1, 64);
+  const int q = tc * 16 + 4 * g + (h8 ? 2 : 0) + (h4 ? 1 : 0);
+  if ((a & 3) == 0 && q < s) y[q] += k2;
+}
+
+// A block descriptor read into scalar registers (the loads cannot be proven
+// unclobbered by the kernel's vector stores, so the fields are made uniform
+// explicitly and the tile addresses stay scalar).
+__device__ __forceinline__ int64_t rfl64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ BlockDev block_uniform(const BlockDev* __restrict__ p) {
+  BlockDev B = *p;
+  B.start = __builtin_amdgcn_readfirstlane(B.start);
+  B.size = __builtin_amdgcn_readfirstlane(B.size);
+  B.plane_lo = __builtin_amdgcn_readfirstlane(B.plane_lo);
+  B.plane_hi = __builtin_amdgcn_readfirstlane(B.plane_hi);
+  B.first_n = __builtin_amdgcn_readfirstlane(B.first_n);
+  B.last_n = __builtin_amdgcn_readfirstlane(B.last_n);
+  B.G_off = rfl64(B.G_off);
+  B.cf_off = rfl64(B.cf_off);
+  B.cb_off = rfl64(B.cb_off);
+  return B;
 }
 
 template <typename T>
-__global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, Geo g, const double* __restrict__ rho,
-                                                            int setR, const T* __restrict__ G,
+__global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, int setR, const T* __restrict__ G,
                                                             T* __restrict__ vec) {
   extern __shared__ char smem_raw[];
-  double* yp = reinterpret_cast<double*>(smem_raw);                   // BS_WAVES x max_block
-  T* cl = reinterpret_cast<T*>(yp + (int64_t)BS_WAVES * P.max_block);  // max_block
+  const int mb = P.max_block;
+  double* yp = reinterpret_cast<double*>(smem_raw);  // BS_WAVES x mb partial products
+  double* prod = yp + (int64_t)BS_WAVES * mb;        // 9 x mb coupling terms
+  T* cl = reinterpret_cast<T*>(prod + (int64_t)9 * mb);  // the step's right-hand side
+  T* xs = cl + mb;                                   // final values of the last block solved
   const int sub = blockIdx.x, rhs = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int nb = setR ? S.nbR : S.nbI;
   const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
   T* v = vec + rhs * (setR ? P.tot_r : P.tot_I) + (setR ? S.r_off : S.I_off);
-  const int tid = threadIdx.x;
-  for (int k = 0; k < nb; ++k) {
-    const BlockDev B = blk[k];
-    for (int i = tid; i < B.size; i += BS_THREADS) {
-      T c = v[B.start + i];
-      if (B.cf_off >= 0 && i < B.first_n) {
-        const int64_t row = B.cf_off + i;
-        double acc = 0.0;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          const int j = P.cpl_rank[row * 9 + t];
-          if (j >= 0) acc += P.cpl_coef[row * 9 + t] * (double)v[j];
-        }
-        c -= (T)acc;
-      }
-      cl[i] = c;
+  const int tid = threadIdx.x, lane = tid & 63, a = lane & 15, g = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int i = tid; i < BS_WAVES * mb; i += BS_THREADS) yp[i] = 0.0;
+  // steps 0..nb-1 forward over block t, then backward over block 2 nb - 2 - t
+  // (blocks without a coupling to the next one have no backward step)
+  const int nsteps = nb > 0 ? 2 * nb - 1 : 0;
+  auto next_step = [&](int t) {
+    ++t;
+    while (t < nsteps && t >= nb && blk[2 * nb - 2 - t].cb_off < 0) ++t;
+    return t;
+  };
+  auto step_block = [&](int t) { return t < nb ? t : 2 * nb - 2 - t; };
+  // coupled rows and their table offset, base of the product
+  auto step_shape = [&](int t, const BlockDev& B, int& nrows, int64_t& crow, int& base) {
+    if (t < nb) {
+      nrows = B.cf_off >= 0 ? B.first_n : 0;
+      crow = B.cf_off;
+      base = 0;
+    } else {
+      nrows = B.last_n;
+      crow = B.cb_off;
+      base = B.size - B.last_n;
     }
-    block_symv(G + B.G_off, B.size, 0, cl, yp, v + B.start, false, (T)-1, tid);
+  };
+  T L[BS_PT][4];
+  int rk[BS_CP];
+  double cf[BS_CP];
+  T vin_next = (T)0;
+  auto prefetch_small = [&](int t, const BlockDev& B) {  // coupling terms and v entries of step t
+    int nrows, base;
+    int64_t crow;
+    step_shape(t, B, nrows, crow, base);
+#pragma unroll
+    for (int m = 0; m < BS_CP; ++m) {
+      const int p = tid + BS_THREADS * m;
+      const bool on = p < 9 * nrows;
+      rk[m] = on ? P.cpl_rank[crow * 9 + p] : -1;
+      cf[m] = on ? P.cpl_coef[crow * 9 + p] : 0.0;
+    }
+    vin_next = tid < B.size ? v[B.start + tid] : (T)0;
+  };
+  auto prefetch_tiles = [&](int t, const BlockDev& B) {
+    int nrows, base;
+    int64_t crow;
+    step_shape(t, B, nrows, crow, base);
+    const int nt = (B.size + 15) >> 4, t0 = base >> 4, nrow = nt - t0;
+    const int ntiles = nrow * t0 + nrow * (nrow + 1) / 2;
+#pragma unroll
+    for (int u = 0; u < BS_PT; ++u) {
+      const int lin = wave + BS_WAVES * u;
+      int tr = nt, tc = 0;  // past the last row: loads nothing
+      if (lin < ntiles) bs_tile_rc(lin, t0, nrow, tr, tc);
+      bs_tile_load(G + B.G_off, B.size, base, tr, tc, a, g, L[u]);
+    }
+  };
+  if (nsteps > 0) {
+    const BlockDev B0 = block_uniform(blk);
+    prefetch_small(0, B0);
+    prefetch_tiles(0, B0);
   }
-  for (int k = nb - 2; k >= 0; --k) {
-    const BlockDev B = blk[k];
-    if (B.cb_off < 0) continue;
-    const int base = B.size - B.last_n;
-    for (int i = tid; i < B.last_n; i += BS_THREADS) {
-      const int64_t row = B.cb_off + i;
+  int xs_blk = -1, xs_start = 0;
+  __syncthreads();
+  for (int t = 0; t < nsteps;) {
+    const int tn = next_step(t);
+    const BlockDev Bn = block_uniform(blk + step_block(tn < nsteps ? tn : t));
+    const bool fwd = t < nb;
+    const int k = step_block(t);
+    const BlockDev B = block_uniform(blk + k);
+    const int s = B.size;
+    int nrows, base;
+    int64_t crow;
+    step_shape(t, B, nrows, crow, base);
+    const T vin = vin_next;  // vin_next is reloaded for the next step before C reads vin
+    // A. coupling terms from the neighbour block's final values
+    if (nrows > 0) {
+      const int nbr = fwd ? k - 1 : k + 1;
+      if (xs_blk != nbr) {  // its values are not in LDS (a skipped step before): read them
+        const BlockDev Bx = block_uniform(blk + nbr);
+        for (int i = tid; i < Bx.size; i += BS_THREADS) xs[i] = v[Bx.start + i];
+        xs_blk = nbr;
+        xs_start = Bx.start;
+        __syncthreads();
+      }
+#pragma unroll
+      for (int m = 0; m < BS_CP; ++m) {
+        const int p = tid + BS_THREADS * m;
+        if (p < 9 * nrows) prod[p] = rk[m] >= 0 ? cf[m] * (double)xs[rk[m] - xs_start] : 0.0;
+      }
+      for (int p = tid + BS_THREADS * BS_CP; p < 9 * nrows; p += BS_THREADS) {
+        const int j = P.cpl_rank[crow * 9 + p];
+        prod[p] = j >= 0 ? P.cpl_coef[crow * 9 + p] * (double)xs[j - xs_start] : 0.0;
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < (fwd ? s : nrows); i += BS_THREADS) {
+      double acc = 0.0;
+      if (i < nrows) {
+#pragma unroll
+        for (int u = 0; u < 9; ++u) acc += prod[9 * i + u];
+      }
+      if (fwd) {
+        const T b = i == tid ? vin : v[B.start + i];
+        cl[i] = b - (T)acc;
+      } else {
+        cl[i] = (T)acc;
+      }
+    }
+    __syncthreads();
+    // B. the block product, then the next step's loads
+    {
+      const int nt = (s + 15) >> 4, t0 = base >> 4, nrow = nt - t0;
+      const int ntiles = nrow * t0 + nrow * (nrow + 1) / 2;
+      double* y = yp + (int64_t)wave * mb;
+#pragma unroll
+      for (int u = 0; u < BS_PT; ++u) {
+        const int lin = wave + BS_WAVES * u;
+        if (lin < ntiles) {
+          int tr, tc;
+          bs_tile_rc(lin, t0, nrow, tr, tc);
+          bs_tile_mul(L[u], s, base, tr, tc, a, g, cl, y);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // one tile's temporaries at a time (register pressure)
+      }
+      for (int lin = wave + BS_WAVES * BS_PT; lin < ntiles; lin += BS_WAVES) {  // blocks above 192 rows
+        int tr, tc;
+        bs_tile_rc(lin, t0, nrow, tr, tc);
+        T Lx[4];
+        bs_tile_load(G + B.G_off, s, base, tr, tc, a, g, Lx);
+        bs_tile_mul(Lx, s, base, tr, tc, a, g, cl, y);
+      }
+    }
+    if (tn < nsteps) {  // the small loads first: A waits for them, not for the tiles
+      prefetch_small(tn, Bn);
+      prefetch_tiles(tn, Bn);
+    }
+    __syncthreads();
+    // C. sum the waves' partials in fixed order, clear them, store
+    for (int i = tid; i < s; i += BS_THREADS) {
       double acc = 0.0;
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int j = P.cpl_rank[row * 9 + t];
-        if (j >= 0) acc += P.cpl_coef[row * 9 + t] * (double)v[j];
+      for (int w = 0; w < BS_WAVES; ++w) {
+        acc += yp[(int64_t)w * mb + i];
+        yp[(int64_t)w * mb + i] = 0.0;
       }
-      cl[i] = (T)acc;
+      T o;
+      if (fwd) {
+        o = -(T)acc;
+      } else {
+        const T xh = i == tid ? vin : v[B.start + i];
+        o = xh + (T)acc;
+      }
+      v[B.start + i] = o;
+      xs[i] = o;
     }
-    block_symv(G + B.G_off, B.size, base, cl, yp, v + B.start, true, (T)1, tid);
+    xs_blk = k;
+    xs_start = B.start;
+    __syncthreads();
+    t = tn;
   }
 }
 
@@ -2738,15 +2980,25 @@ void launch_kc_to_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
 // a plan with these maxima and element size; LDS per workgroup is 160 KiB.
 int front_fwd_chunks(int maxp) { return (int)cdiv(maxp, FK); }
 
+// columns of Phi staged per workgroup of the local coarse matrices (<= 64 KB)
+int kc_cols(const PlanDev& P) {
+  const int64_t stencils = (int64_t)P.max_nv * 27 * 12;
+  return (int)hmax((int64_t)1, hmin((int64_t)8, (65536 - stencils) / ((int64_t)hmax(P.max_ns, 1) * 8)));
+}
+int64_t kc_lds_bytes(const PlanDev& P) {
+  return (int64_t)kc_cols(P) * hmax(P.max_ns, 1) * 8 + (int64_t)P.max_nv * 27 * 12;
+}
+
 int64_t max_lds_bytes(const PlanDev& P, int elt, int max_nrhs) {
   const int64_t mp = hmax(P.max_plane, 1);
   int64_t need = 0;
   need = hmax(need, mp * (SC_COLS + 1) * elt + 2048);                                  // schur couple
   need = hmax(need, mp * (CPL_COLS + 1) * elt);                                        // couple multi
-  need = hmax(need, (int64_t)hmax(P.max_block, 1) * (BS_WAVES * 8 + elt));              // block solve
+  need = hmax(need, (int64_t)hmax(P.max_block, 1) * ((BS_WAVES + 9) * 8 + 2 * elt));      // block solve
   if (max_nrhs >= 4) need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);  // many-rhs block solve
   need = hmax(need, (int64_t)(P.max_na + P.max_nc + 1) * elt);                         // v2
   need = hmax(need, (int64_t)hmax(P.max_ng, 1) * elt);                                 // coarse rhs
+  need = hmax(need, kc_lds_bytes(P));                                                  // local coarse matrices
   need = hmax(need, (int64_t)SWEEP_ROWS * (SWEEP_NB + 1) * elt + 2 * 32 * 33 * 8);   // sweep panel
   return need;
 }
@@ -2775,7 +3027,7 @@ void launch_delta(const PlanDev& P, const double* alpha, double* delta, hipStrea
 }
 void launch_coupling_coefs(const PlanDev& P, const Geo& g, const double* rho, double* coef, hipStream_t s) {
   if (P.n_cpl == 0) return;
-  k_coupling_coefs<<<cdiv(P.n_cpl, 256), 256, 0, s>>>(P, g, rho, coef);
+  k_coupling_coefs<<<cdiv(P.n_cpl * 9, 256), 256, 0, s>>>(P, g, rho, coef);
 }
 
 template <typename T>
@@ -2973,10 +3225,17 @@ void Kern<T>::lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s) {
 }
 
 template <typename T>
-void Kern<T>::sel_gather(const PlanDev& P, const T* Z, T* XS, T* PS, hipStream_t s) {
-  const int64_t tot = (int64_t)P.max_ns * (P.max_na + P.max_nc);
+void Kern<T>::sel_gather(const PlanDev& P, const T* Z, T* XS, hipStream_t s) {
+  const int64_t tot = (int64_t)P.max_ns * P.max_na;
   if (tot == 0) return;
-  k_sel_gather<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, XS, PS);
+  k_sel_gather<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, XS);
+}
+
+template <typename T>
+void Kern<T>::phi_add(const PlanDev& P, const T* Z, T* PS, int max_nv, hipStream_t s) {
+  const int64_t tot = (int64_t)P.max_ns * max_nv;
+  if (tot == 0) return;
+  k_phi_add<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, PS);
 }
 
 template <typename T>
@@ -2985,8 +3244,11 @@ void Kern<T>::kc_identity(const PlanDev& P, const Geo& g, const double* rho, con
   if (P.max_nc == 0) return;
   if (max_nv > 0)
     k_vertex_stencil<<<dim3(cdiv((int64_t)max_nv * 27, 256), P.n_sub), 256, 0, s>>>(P, g, rho, nullptr, vcoef, vcode);
-  k_kc_identity<T><<<dim3(cdiv((int64_t)P.max_nc * P.max_nc, 256), P.n_sub), 256, 0, s>>>(P, PhiR, Lam, vcoef,
-                                                                                          vcode, Kc);
+  const int cols = kc_cols(P);
+  k_kc_identity<T><<<dim3(cdiv(P.max_nc, cols), P.n_sub), 256, (size_t)kc_lds_bytes(P), s>>>(P, PhiR, Lam, vcoef,
+                                                                                          vcode, Kc, cols);
+  const int nt = cdiv(P.max_nc, 32);
+  k_kc_symmetrize<T><<<dim3(nt * (nt + 1) / 2, P.n_sub), 256, 0, s>>>(P, Kc);
 }
 
 template <typename T>
@@ -3010,8 +3272,8 @@ void Kern<T>::block_solve(const PlanDev& P, const Geo& g, const double* rho, int
     const size_t smr = (size_t)hmax(P.max_block, 1) * (MR_COLS + 1) * sizeof(T);
     k_block_solve_mr<T><<<dim3(P.n_sub, cdiv(nrhs, MR_COLS)), MR_THREADS, smr, s>>>(P, setR, G, v, nrhs);
   } else {
-    const size_t sm = (size_t)hmax(P.max_block, 1) * (BS_WAVES * sizeof(double) + sizeof(T));
-    k_block_solve<T><<<dim3(P.n_sub, nrhs), BS_THREADS, sm, s>>>(P, g, rho, setR, G, v);
+    const size_t sm = (size_t)hmax(P.max_block, 1) * ((BS_WAVES + 9) * sizeof(double) + 2 * sizeof(T));
+    k_block_solve<T><<<dim3(P.n_sub, nrhs), BS_THREADS, sm, s>>>(P, setR, G, v);
   }
   // the method must stream each lower-triangle G entry once per launch (4
   // flops per rhs off the diagonal) and read and write each vector once
