@@ -305,19 +305,25 @@ __global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rh
 constexpr int SC_COLS = 16;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_schur_couple(PlanDev P, int setR, int k, T* __restrict__ G) {
+__global__ __launch_bounds__(256) void k_schur_couple(PlanDev P, int setR, int k, T* __restrict__ G, int nch) {
   extern __shared__ char smem_raw[];
   T(*W)[SC_COLS + 1] = reinterpret_cast<T(*)[SC_COLS + 1]>(smem_raw);  // [last_n][cols]
   __shared__ int crk[SC_COLS][9];
   __shared__ double ccf[SC_COLS][9];
-  const int sub = blockIdx.y;
+  // XCD-aware order: workgroups go round-robin over the 8 XCDs, so the nch
+  // chunks of one subdomain (which gather the same G_{k-1}) are given
+  // consecutive logical indices on one XCD and share its L2
+  const int nblk = gridDim.x, lin = blockIdx.x;
+  const int logical = (lin % 8) * (nblk / 8) + lin / 8;
+  if (logical >= nch * P.n_sub) return;
+  const int sub = logical / nch, chunk = logical % nch;
   const SubDev S = P.subs[sub];
   const int nb = setR ? S.nbR : S.nbI;
   if (k >= nb || k == 0) return;
   const BlockDev* blk = P.blocks + (setR ? S.bR_off : S.bI_off);
   const BlockDev Bp = blk[k - 1], B = blk[k];
   if (B.cf_off < 0) return;
-  const int c0 = blockIdx.x * SC_COLS;
+  const int c0 = chunk * SC_COLS;
   if (c0 >= B.first_n) return;
   const int cols = min(SC_COLS, B.first_n - c0);
   // coupling rows of this chunk's columns (first-plane rows of block k)
@@ -1662,6 +1668,26 @@ __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd,
   }
 }
 
+// Mean of column col of Z over the r-set nodes a_r[pb..pe) of one object,
+// summed in order with eight gathers in flight at a time.
+template <typename T>
+__device__ __forceinline__ double object_mean(const PlanDev& P, const T* __restrict__ z, int64_t nr, int col,
+                                              int pb, int pe) {
+  double s = 0.0;
+  for (int t0 = pb; t0 < pe; t0 += 8) {
+    int rr[8];
+    T zv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) rr[u] = t0 + u < pe ? P.a_r[t0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) zv[u] = t0 + u < pe ? z[rr[u] + nr * col] : (T)0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (t0 + u < pe) s += (double)zv[u];
+  }
+  return s / (double)(pe - pb);
+}
+
 // S_c[a, b] = (C_r X)[a, b]: mean of X's column b over object a's nodes.
 template <typename T>
 __global__ void k_sc_assemble(PlanDev P, const T* __restrict__ Z, T* __restrict__ Sc) {
@@ -1671,9 +1697,7 @@ __global__ void k_sc_assemble(PlanDev P, const T* __restrict__ Z, T* __restrict_
   if (idx >= S.n_a * S.n_a) return;
   const int a = idx % S.n_a, b = idx / S.n_a;
   const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
-  double s = 0.0;
-  for (int t = pb; t < pe; ++t) s += (double)Z[S.Z_off + P.a_r[t] + (int64_t)S.n_r * b];
-  Sc[S.Sc_off + idx] = (T)(s / (double)(pe - pb));
+  Sc[S.Sc_off + idx] = (T)object_mean(P, Z + S.Z_off, S.n_r, b, pb, pe);
 }
 
 // T[a, c] = (C_r Y)[a, c] - [0 I][a, c]: Y is -K_rr^{-1} K_rv at vertex
@@ -1689,9 +1713,7 @@ __global__ void k_lambda_rhs(PlanDev P, const T* __restrict__ Z, T* __restrict__
   double v;
   if (kind >= 0) {
     const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
-    double s = 0.0;
-    for (int t = pb; t < pe; ++t) s += (double)Z[S.Z_off + P.a_r[t] + (int64_t)S.n_r * (S.n_a + kind)];
-    v = s / (double)(pe - pb);
+    v = object_mean(P, Z + S.Z_off, S.n_r, S.n_a + kind, pb, pe);
   } else {
     v = (-kind - 1 == a) ? -1.0 : 0.0;
   }
@@ -1703,11 +1725,17 @@ template <typename T>
 __global__ void k_sel_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__ XS) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
-  const int tot = S.n_s * S.n_a;  // per subdomain: 32-bit index math
+  // thread (row e, 8 columns): one index load, eight gathers in flight
+  const int na8 = (S.n_a + 7) / 8, tot = S.n_s * na8;  // per subdomain: 32-bit index math
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
-    const int e = idx % S.n_s, a = idx / S.n_s;
+    const int e = idx % S.n_s, a0 = (idx / S.n_s) * 8;
     const int r = P.sel_r[S.sel_off + e];
-    XS[S.XG_off + idx] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * a] : (T)0;
+    T xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = (r >= 0 && a0 + u < S.n_a) ? Z[S.Z_off + r + (int64_t)S.n_r * (a0 + u)] : (T)0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (a0 + u < S.n_a) XS[S.XG_off + e + (int64_t)S.n_s * (a0 + u)] = xv[u];
   }
 }
 
@@ -1816,6 +1844,7 @@ __global__ __launch_bounds__(256) void k_kc_identity(PlanDev P, const T* __restr
   }
   __syncthreads();
   // vertex rows: thread (v, j)
+  constexpr int KCM = 8;  // largest chunk
   for (int idx = threadIdx.x; idx < S.n_v * nc; idx += blockDim.x) {
     const int v = idx % S.n_v, j = idx / S.n_v, c2 = c0 + j;
     double acc = 0.0;
@@ -1827,11 +1856,16 @@ __global__ __launch_bounds__(256) void k_kc_identity(PlanDev P, const T* __restr
     }
     Kc[S.Kc_off + P.v_c[S.v_off + v] + (int64_t)S.n_c * c2] = (T)acc;
   }
-  // average rows
-  for (int idx = threadIdx.x; idx < S.n_c * nc; idx += blockDim.x) {
-    const int c = idx % S.n_c, j = idx / S.n_c, c2 = c0 + j;
+  // average rows: one thread per row, the chunk's Lambda loads in flight together
+  for (int c = threadIdx.x; c < S.n_c; c += blockDim.x) {
     const int kind = P.c_kind[S.c_off + c];
-    if (kind < 0) Kc[S.Kc_off + c + (int64_t)S.n_c * c2] = (T)(-(double)Lam[S.T_off + (-kind - 1) + (int64_t)S.n_a * c2]);
+    if (kind >= 0) continue;
+    T lv[KCM];
+#pragma unroll
+    for (int j = 0; j < KCM; ++j) lv[j] = j < nc ? Lam[S.T_off + (-kind - 1) + (int64_t)S.n_a * (c0 + j)] : (T)0;
+#pragma unroll
+    for (int j = 0; j < KCM; ++j)
+      if (j < nc) Kc[S.Kc_off + c + (int64_t)S.n_c * (c0 + j)] = (T)(-(double)lv[j]);
   }
 }
 
@@ -3047,7 +3081,9 @@ void Kern<T>::schur_couple(const PlanDev& P, const Geo& g, const double* rho, in
   (void)wstride;
   const int mp = P.max_plane;
   const size_t sm = (size_t)hmax(mp, 1) * (SC_COLS + 1) * sizeof(T);
-  k_schur_couple<T><<<dim3(cdiv(mp, SC_COLS), P.n_sub), 256, sm, s>>>(P, setR, k, G);
+  const int nch = (int)cdiv(mp, SC_COLS);
+  const unsigned nblk = (unsigned)(((int64_t)nch * P.n_sub + 7) / 8 * 8);
+  k_schur_couple<T><<<nblk, 256, sm, s>>>(P, setR, k, G, nch);
 }
 
 template <typename T>
@@ -3226,7 +3262,7 @@ void Kern<T>::lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s) {
 
 template <typename T>
 void Kern<T>::sel_gather(const PlanDev& P, const T* Z, T* XS, hipStream_t s) {
-  const int64_t tot = (int64_t)P.max_ns * P.max_na;
+  const int64_t tot = (int64_t)P.max_ns * cdiv(P.max_na, 8);
   if (tot == 0) return;
   k_sel_gather<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, XS);
 }
