@@ -235,6 +235,7 @@ struct bddcso_precond {
   hipStream_t s3 = nullptr;                 // third stream: the interior factors
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_fork_i = nullptr, ev_join_i = nullptr;
+  hipEvent_t ev_cfork = nullptr, ev_cjoin = nullptr;  // coarse solve beside the Neumann solves
   hipEvent_t ev_la = nullptr, ev_lb = nullptr;   // slab look-ahead of the coarse fronts
   double gI_entries = 0, gR_entries = 0;  // G entries streamed by one block solve
   Profiler* P_() { return prof.mask ? &prof : nullptr; }
@@ -575,17 +576,23 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   Kern<T>::gamma_kgi(P, g, rho, N.vI, N.q, nrhs, s);
   // 3: E^T
   Kern<T>::gamma_t(P, g, r, N.q, pc->delta, N.gv, nrhs, s);
+  // 5-6: coarse problem.  It needs only E^T's output, so it runs on a second
+  // stream beside the constrained Neumann solves (bandwidth-bound, while the
+  // coarse solve is a chain of small latency-bound kernels).
+  HIPCHK(hipEventRecord(pc->ev_cfork, s));
+  HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_cfork, 0));
+  Kern<T>::coarse_rhs_local(P, N.PhiG, N.gv, N.bci, nrhs, pc->s2);
+  if (sizeof(T) == 8) launch_coarse_rhs_gather(P, (const double*)N.bci, nullptr, pc->bc, nrhs, pc->s2);
+  else launch_coarse_rhs_gather(P, nullptr, (const float*)N.bci, pc->bc, nrhs, pc->s2);
+  coarse_solve(pc, nrhs, pc->s2);
+  HIPCHK(hipEventRecord(pc->ev_cjoin, pc->s2));
   // 4: constrained Neumann solves
   if (sizeof(T) == 8) launch_fill_f64((double*)N.vR, pl.tot_r * nrhs, 0.0, s);
   else launch_fill_f32((float*)N.vR, pl.tot_r * nrhs, 0.0f, s);
   Kern<T>::neumann_rhs(P, N.gv, N.vR, nrhs, s);
   Kern<T>::block_solve(P, g, rho, 1, N.G, N.vR, nrhs, s, pc->P_(), pc->gR_entries, (double)pl.tot_r);
   Kern<T>::mu(P, N.vR, N.Sc, N.mu, nrhs, s);
-  // 5-6: coarse problem
-  Kern<T>::coarse_rhs_local(P, N.PhiG, N.gv, N.bci, nrhs, s);
-  if (sizeof(T) == 8) launch_coarse_rhs_gather(P, (const double*)N.bci, nullptr, pc->bc, nrhs, s);
-  else launch_coarse_rhs_gather(P, nullptr, (const float*)N.bci, pc->bc, nrhs, s);
-  coarse_solve(pc, nrhs, s);
+  HIPCHK(hipStreamWaitEvent(s, pc->ev_cjoin, 0));
   // 7-8: v2 on Gamma and E
   Kern<T>::v2(P, N.vR, N.XG, N.mu, N.PhiG, pc->uc, N.v2, nrhs, s);
   if (sizeof(T) == 8) launch_gamma_w(P, g, (const double*)N.v2, nullptr, pc->delta, z, nrhs, s);
@@ -686,6 +693,8 @@ void bddcso_precond_destroy(bddcso_precond* pc) {
   if (pc->ev_join) (void)hipEventDestroy(pc->ev_join);
   if (pc->ev_la) (void)hipEventDestroy(pc->ev_la);
   if (pc->ev_lb) (void)hipEventDestroy(pc->ev_lb);
+  if (pc->ev_cfork) (void)hipEventDestroy(pc->ev_cfork);
+  if (pc->ev_cjoin) (void)hipEventDestroy(pc->ev_cjoin);
   if (pc->ev_fork_i) (void)hipEventDestroy(pc->ev_fork_i);
   if (pc->ev_join_i) (void)hipEventDestroy(pc->ev_join_i);
   if (pc->s2) (void)hipStreamDestroy(pc->s2);
@@ -878,6 +887,8 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     HIPCHK(hipStreamCreateWithFlags(&pc->s2, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&pc->s3, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_fork_i, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_cfork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_cjoin, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_join_i, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
@@ -916,7 +927,11 @@ bddcso_status bddcso_apply(bddcso_precond* pc, const double* r, double* z, int n
   if (!pc || !r || !z) return set_err(BDDCSO_EINVAL, "null argument");
   if (nrhs < 1 || nrhs > pc->max_nrhs) return set_err(BDDCSO_EINVAL, "nrhs must be in 1..max_nrhs");
   if (r == z) return set_err(BDDCSO_EINVAL, "r and z must be distinct");
-  apply_B_any(pc, r, z, nrhs, as_stream(stream));
+  try {
+    apply_B_any(pc, r, z, nrhs, as_stream(stream));
+  } catch (const HipFail& f) {
+    return set_err(BDDCSO_EHIP, "HIP error in apply: " + f.where);
+  }
   if (hipGetLastError() != hipSuccess) return set_err(BDDCSO_EHIP, "kernel launch failed in apply");
   return BDDCSO_OK;
 }
