@@ -221,6 +221,8 @@ struct bddcso_precond {
   std::vector<std::vector<int>> slot_n, slot_maxn;
   std::vector<int32_t*> level_dev;
   std::vector<int> level_n, level_maxn, level_maxp, level_maxb;
+  int32_t* all_fronts = nullptr;  // every front, all levels (one launch initialises their vectors)
+  int all_n = 0, all_maxn = 0;
   // PCG
   double *r = nullptr, *p = nullptr, *qv = nullptr, *z = nullptr, *rold = nullptr, *dtmp = nullptr;
   double* partial = nullptr;
@@ -451,6 +453,13 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       pc->slot_maxn[L].push_back(cm);
     }
   }
+  {
+    std::vector<int32_t> all;
+    for (int L = 0; L < nlev; ++L) all.insert(all.end(), pl.level_fronts[L].begin(), pl.level_fronts[L].end());
+    pc->all_n = (int)all.size();
+    pc->all_maxn = maxfn;
+    if (!all.empty()) pc->all_fronts = m.upload(all, s);
+  }
   int maxlev = 1;
   for (int L = 0; L < nlev; ++L) maxlev = std::max(maxlev, pc->level_n[L]);
   pc->fsw_stride = std::max<int64_t>(2 * ((int64_t)std::max(maxfn, 1) * kSweepNB + kSweepNB * kSweepNB),
@@ -548,9 +557,7 @@ void coarse_solve(bddcso_precond* pc, int nrhs, hipStream_t s) {
   const Plan& pl = *pc->plan;
   const int nlev = (int)pc->level_dev.size();
   const int64_t stride = pl.front_vec;
-  for (int L = 0; L < nlev; ++L)
-    launch_front_vec_init(P, pc->level_dev[L], pc->level_n[L], pc->level_maxn[L], pc->bc, pc->fvec, stride, nrhs,
-                          s);
+  launch_front_vec_init(P, pc->all_fronts, pc->all_n, pc->all_maxn, pc->bc, pc->fvec, stride, nrhs, s);
   for (int L = 0; L < nlev; ++L) {
     for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
       launch_front_vec_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fvec, stride,

@@ -996,19 +996,26 @@ __global__ __launch_bounds__(RS_WAVES * 64) void k_sweep_reg(const SweepDesc* __
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * sti[sl] + Mfma<T>::row(kq, r), j = 16 * stj[sl] + rr;
       const int hi = min(max(i, j), n - 1), lo = min(min(i, j), n - 1);
-      const T v = A[(int64_t)lo * ld + hi];
+      // uniform base + 32-bit byte offset: no 64-bit address registers
+      const T v = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(A) +
+                                              (uint32_t)(lo * ld + hi) * (uint32_t)sizeof(T));
       acc[sl][r] = (i < n && j < n) ? v : (T)0;
     }
   }
   bool bad = false;
   const int npan = (p + 15) >> 4;
   for (int tq = 0; tq < npan; ++tq) {
+    // an opaque scalar zero added to the slots' tile coordinates: the LDS
+    // addresses derived from them are recomputed each panel instead of being
+    // hoisted out of the loop and held in registers for every slot
+    int oz;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(oz));
     const int j0 = 16 * tq, jb = min(16, p - j0);
     __syncthreads();  // the previous panel's readers of Cs / CDs / Dw are done
     // 1. stage C and D from the tiles of tile row / column tq
 #pragma unroll
     for (int sl = 0; sl < TPW; ++sl) {
-      const int ti = sti[sl], tj = stj[sl];
+      const int ti = sti[sl] + oz, tj = stj[sl] + oz;
       if (ti < 0) continue;
       if (ti == tq && tj == tq) {  // pivot rows carry no C
 #pragma unroll
@@ -1056,7 +1063,7 @@ __global__ __launch_bounds__(RS_WAVES * 64) void k_sweep_reg(const SweepDesc* __
     // 4. rank-16 update and the panel's new entries
 #pragma unroll
     for (int sl = 0; sl < TPW; ++sl) {
-      const int ti = sti[sl], tj = stj[sl];
+      const int ti = sti[sl] + oz, tj = stj[sl] + oz;
       if (ti < 0) continue;
       acc_t c = acc[sl];
 #pragma unroll
@@ -1087,8 +1094,9 @@ __global__ __launch_bounds__(RS_WAVES * 64) void k_sweep_reg(const SweepDesc* __
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * ti + Mfma<T>::row(kq, r), j = 16 * tj + rr;
       if (i < n && j < n) {
-        A[(int64_t)i * ld + j] = acc[sl][r];
-        if (ti != tj) A[(int64_t)j * ld + i] = acc[sl][r];
+        char* base = reinterpret_cast<char*>(A);
+        *reinterpret_cast<T*>(base + (uint32_t)(i * ld + j) * (uint32_t)sizeof(T)) = acc[sl][r];
+        if (ti != tj) *reinterpret_cast<T*>(base + (uint32_t)(j * ld + i) * (uint32_t)sizeof(T)) = acc[sl][r];
       }
     }
   }
@@ -3106,7 +3114,7 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
     const int mt = (int)cdiv(maxn, 16);
     if (mt <= 4) k_sweep_reg<T, 4, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
     else if (mt <= 8) k_sweep_reg<T, 8, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
-    else if (mt <= 11) k_sweep_reg<T, 11, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
+    else if (mt <= 11) k_sweep_reg<T, 11, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
     else if (mt <= 12) k_sweep_reg<T, 12, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
     else k_sweep_reg<T, RS_MAX_TILES, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
     if (prof) prof->end(5, f, by, s);
