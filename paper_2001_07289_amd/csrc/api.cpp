@@ -583,22 +583,23 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   Kern<T>::gamma_kgi(P, g, rho, N.vI, N.q, nrhs, s);
   // 3: E^T
   Kern<T>::gamma_t(P, g, r, N.q, pc->delta, N.gv, nrhs, s);
-  // 5-6: coarse problem.  It needs only E^T's output, so it runs on a second
-  // stream beside the constrained Neumann solves (bandwidth-bound, while the
-  // coarse solve is a chain of small latency-bound kernels).
+  // 4: constrained Neumann solves, and 5-6: the coarse problem, which needs
+  // only E^T's output and runs on a second stream beside them (the Neumann
+  // solves are bandwidth-bound, the coarse solve a chain of small
+  // latency-bound kernels).  The Neumann solves are enqueued first so the
+  // GPU starts them while the host is still launching the coarse chain.
   HIPCHK(hipEventRecord(pc->ev_cfork, s));
+  if (sizeof(T) == 8) launch_fill_f64((double*)N.vR, pl.tot_r * nrhs, 0.0, s);
+  else launch_fill_f32((float*)N.vR, pl.tot_r * nrhs, 0.0f, s);
+  Kern<T>::neumann_rhs(P, N.gv, N.vR, nrhs, s);
+  Kern<T>::block_solve(P, g, rho, 1, N.G, N.vR, nrhs, s, pc->P_(), pc->gR_entries, (double)pl.tot_r);
+  Kern<T>::mu(P, N.vR, N.Sc, N.mu, nrhs, s);
   HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_cfork, 0));
   Kern<T>::coarse_rhs_local(P, N.PhiG, N.gv, N.bci, nrhs, pc->s2);
   if (sizeof(T) == 8) launch_coarse_rhs_gather(P, (const double*)N.bci, nullptr, pc->bc, nrhs, pc->s2);
   else launch_coarse_rhs_gather(P, nullptr, (const float*)N.bci, pc->bc, nrhs, pc->s2);
   coarse_solve(pc, nrhs, pc->s2);
   HIPCHK(hipEventRecord(pc->ev_cjoin, pc->s2));
-  // 4: constrained Neumann solves
-  if (sizeof(T) == 8) launch_fill_f64((double*)N.vR, pl.tot_r * nrhs, 0.0, s);
-  else launch_fill_f32((float*)N.vR, pl.tot_r * nrhs, 0.0f, s);
-  Kern<T>::neumann_rhs(P, N.gv, N.vR, nrhs, s);
-  Kern<T>::block_solve(P, g, rho, 1, N.G, N.vR, nrhs, s, pc->P_(), pc->gR_entries, (double)pl.tot_r);
-  Kern<T>::mu(P, N.vR, N.Sc, N.mu, nrhs, s);
   HIPCHK(hipStreamWaitEvent(s, pc->ev_cjoin, 0));
   // 7-8: v2 on Gamma and E
   Kern<T>::v2(P, N.vR, N.XG, N.mu, N.PhiG, pc->uc, N.v2, nrhs, s);

@@ -1964,10 +1964,10 @@ __global__ void k_gather_I(PlanDev P, Geo g, const double* __restrict__ r, T* __
 // coupling reads stay in LDS from the step that produced them.  Waves take
 // tiles round-robin, keep partial sums per wave in LDS and the waves' sums
 // are added in fixed order, so the result is bitwise repeatable.
-constexpr int BS_THREADS = 512;
+constexpr int BS_THREADS = 1024;
 constexpr int BS_WAVES = BS_THREADS / 64;
-constexpr int BS_PT = 10;  // tiles per wave held in registers: blocks up to 192 rows
-constexpr int BS_CP = 3;   // coupling terms per thread held in registers: 170 coupled rows
+constexpr int BS_PT = 5;   // tiles per wave held in registers: blocks up to 192 rows
+constexpr int BS_CP = 2;   // coupling terms per thread held in registers: 227 coupled rows
 
 // Tile lin of the lower triangle restricted to tile rows >= t0: first the
 // rectangle left of tile column t0, then the triangle of tile rows/columns >= t0.
