@@ -3138,7 +3138,7 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
           db += sizeof(T) * (sb * (sb + 1) / 2 + sb * sb);
         }
       if (prof) prof->begin(5, ss);
-      k_sweep_reg<T, 12, 12><<<nprob, 12 * 64, 0, ss>>>(d_desc, pool, status, status_code, j0);
+      k_sweep_reg<T, 12, 16><<<nprob, 16 * 64, 0, ss>>>(d_desc, pool, status, status_code, j0);
       if (prof) prof->end(5, df, db, ss);
     };
     reg(0, s);
