@@ -1808,14 +1808,16 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_kc_identity(PlanDev P, const T* __restrict__ PhiR, const T* __restrict__ Lam,
                                                      const double* __restrict__ vcoef,
                                                      const int32_t* __restrict__ vcode, T* __restrict__ Kc,
-                                                     int kc_cols) {
+                                                     int kc_cols, int stage_stencils) {
   extern __shared__ double phs[];  // [kc_cols][n_s] Phi, then [n_v][27] coefficients, then [n_v][27] codes
   const SubDev S = P.subs[blockIdx.y];
   const int c0 = blockIdx.x * kc_cols;
   if (c0 >= S.n_c) return;
-  const int nc = min(kc_cols, S.n_c - c0), ns = S.n_s, nv27 = S.n_v * 27;
-  double* scoef = phs + (int64_t)kc_cols * P.max_ns;
-  int32_t* scode = reinterpret_cast<int32_t*>(scoef + (int64_t)27 * P.max_nv);
+  const int nc = min(kc_cols, S.n_c - c0), ns = S.n_s, nv27 = stage_stencils ? S.n_v * 27 : 0;
+  double* lcoef = phs + (int64_t)kc_cols * P.max_ns;
+  int32_t* lcode = reinterpret_cast<int32_t*>(lcoef + (int64_t)27 * P.max_nv);
+  const double* scoef = stage_stencils ? lcoef : vcoef + S.v_off * 27;
+  const int32_t* scode = stage_stencils ? lcode : vcode + S.v_off * 27;
   // the chunk's columns are contiguous (ld n_s): a straight copy, 8 loads in flight per thread
   const T* src = PhiR + S.PhiG_off + (int64_t)ns * c0;
   const int tot = ns * nc;
@@ -1845,8 +1847,8 @@ __global__ __launch_bounds__(256) void k_kc_identity(PlanDev P, const T* __restr
     for (int u = 0; u < 4; ++u) {
       const int i = b0 + threadIdx.x + 256 * u;
       if (i < nv27) {
-        scoef[i] = cf[u];
-        scode[i] = cd[u];
+        lcoef[i] = cf[u];
+        lcode[i] = cd[u];
       }
     }
   }
@@ -3023,12 +3025,15 @@ void launch_kc_to_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
 int front_fwd_chunks(int maxp) { return (int)cdiv(maxp, FK); }
 
 // columns of Phi staged per workgroup of the local coarse matrices (<= 64 KB)
+// The vertex stencils go to LDS too when they are small (up to 24 KB); with
+// many vertices (every interface node primal) they are read from memory.
+bool kc_stage_stencils(const PlanDev& P) { return (int64_t)P.max_nv * 27 * 12 <= 24576; }
 int kc_cols(const PlanDev& P) {
-  const int64_t stencils = (int64_t)P.max_nv * 27 * 12;
+  const int64_t stencils = kc_stage_stencils(P) ? (int64_t)P.max_nv * 27 * 12 : 0;
   return (int)hmax((int64_t)1, hmin((int64_t)8, (65536 - stencils) / ((int64_t)hmax(P.max_ns, 1) * 8)));
 }
 int64_t kc_lds_bytes(const PlanDev& P) {
-  return (int64_t)kc_cols(P) * hmax(P.max_ns, 1) * 8 + (int64_t)P.max_nv * 27 * 12;
+  return (int64_t)kc_cols(P) * hmax(P.max_ns, 1) * 8 + (kc_stage_stencils(P) ? (int64_t)P.max_nv * 27 * 12 : 0);
 }
 
 int64_t max_lds_bytes(const PlanDev& P, int elt, int max_nrhs) {
@@ -3289,8 +3294,8 @@ void Kern<T>::kc_identity(const PlanDev& P, const Geo& g, const double* rho, con
   if (max_nv > 0)
     k_vertex_stencil<<<dim3(cdiv((int64_t)max_nv * 27, 256), P.n_sub), 256, 0, s>>>(P, g, rho, nullptr, vcoef, vcode);
   const int cols = kc_cols(P);
-  k_kc_identity<T><<<dim3(cdiv(P.max_nc, cols), P.n_sub), 256, (size_t)kc_lds_bytes(P), s>>>(P, PhiR, Lam, vcoef,
-                                                                                          vcode, Kc, cols);
+  k_kc_identity<T><<<dim3(cdiv(P.max_nc, cols), P.n_sub), 256, (size_t)kc_lds_bytes(P), s>>>(
+      P, PhiR, Lam, vcoef, vcode, Kc, cols, kc_stage_stencils(P) ? 1 : 0);
   const int nt = cdiv(P.max_nc, 32);
   k_kc_symmetrize<T><<<dim3(nt * (nt + 1) / 2, P.n_sub), 256, 0, s>>>(P, Kc);
 }

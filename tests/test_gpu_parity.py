@@ -47,6 +47,9 @@ def cases():
         "cfg1": W.config1(),
         "3d_L3": W.config2_like(n=12, H=6, L=3, cfg=13),
         "3d_L2_exact": W.config2_like(n=8, H=4, L=2, cfg=12),
+        # every interface node primal on 8^3 subdomains: more vertex stencils
+        # than the local coarse kernel stages in LDS
+        "3d_L2_many_vertices": W.config2_like(n=16, H=8, L=2, cfg=14),
         "uneven3d": uneven_3d(),
     }
 
@@ -94,7 +97,7 @@ def test_preconditioner_apply(name, coarse_solver):
         assert relerr(z, zo) <= 1e-11, (name, weighting, relerr(z, zo))
 
 
-@pytest.mark.parametrize("name", ["cfg1", "3d_L3", "uneven3d"])
+@pytest.mark.parametrize("name", ["cfg1", "3d_L3", "uneven3d", "3d_L2_many_vertices"])
 def test_local_coarse_matrices(name):
     p = CASES[name]
     _, pc, orc = setup_both(p)
