@@ -238,6 +238,7 @@ struct bddcso_precond {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_fork_i = nullptr, ev_join_i = nullptr;
   hipEvent_t ev_cfork = nullptr, ev_cjoin = nullptr;  // coarse solve beside the Neumann solves
+  hipEvent_t ev_cpl = nullptr;                         // plane-coupling coefficients ready
   hipEvent_t ev_la = nullptr, ev_lb = nullptr;   // slab look-ahead of the coarse fronts
   double gI_entries = 0, gR_entries = 0;  // G entries streamed by one block solve
   Profiler* P_() { return prof.mask ? &prof : nullptr; }
@@ -475,30 +476,30 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   const Geo& g = pc->geo;
   const double* rho = pc->rho;
   launch_fill_i32(pc->status, 1, 0, s);
-  launch_alpha(P, pc->prob->c.n_ss, rho, pc->opt.weighting, pc->alpha, s);
-  launch_delta(P, pc->alpha, pc->delta, s);
-  launch_coupling_coefs(P, g, rho, pc->cpl_coef, s);
-  // local block-tridiagonal factors of K_II and K_rr
-  if (sizeof(T) == 8) launch_fill_f64((double*)N.G, pl.pool_G, 0.0, s);
-  else launch_fill_f32((float*)N.G, pl.pool_G, 0.0f, s);
-  Kern<T>::block_assemble(P, g, rho, 0, N.G, s);
-  Kern<T>::block_assemble(P, g, rho, 1, N.G, s);
-  // the coarse front pool is zeroed on a second stream (it is summed into later)
+  // on a second stream: the plane-coupling coefficients (first needed by the
+  // second plane's Schur update)
   HIPCHK(hipEventRecord(pc->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_fork, 0));
-  launch_fill_f64(pc->fpool, pl.front_pool, 0.0, pc->s2);
-  HIPCHK(hipEventRecord(pc->ev_join, pc->s2));
+  launch_coupling_coefs(P, g, rho, pc->cpl_coef, pc->s2);
+  HIPCHK(hipEventRecord(pc->ev_cpl, pc->s2));
+  launch_alpha(P, pc->prob->c.n_ss, rho, pc->opt.weighting, pc->alpha, s);
+  launch_delta(P, pc->alpha, pc->delta, s);
+  // local block-tridiagonal factors of K_II and K_rr (lower triangles written whole)
+  Kern<T>::block_assemble(P, g, rho, 0, N.G, pl.max_nbI, s);
+  Kern<T>::block_assemble(P, g, rho, 1, N.G, pl.max_nbR, s);
   auto factor_chain = [&](int setR, hipStream_t ss) {
     T* W = setR ? N.W : N.W2;
     T* sws = setR ? N.sw : N.sw2;
     auto& sw = setR ? pc->swR : pc->swI;
     for (int k = 0; k < (int)sw.size(); ++k) {
+      if (k == 1 && setR) HIPCHK(hipStreamWaitEvent(ss, pc->ev_cpl, 0));  // the coupling coefficients
       if (k > 0) Kern<T>::schur_couple(P, g, rho, setR, k, N.G, W, N.wstride, ss);
       Kern<T>::sweep((SweepDesc*)sw[k].desc, sw[k].hs.data(), sw[k].n, sw[k].maxn, sw[k].maxp, N.G, sws,
                      N.sw_stride, pc->status, setR ? 2 : 1, ss, pc->P_());
     }
   };
   factor_chain(1, s);
+  HIPCHK(hipStreamWaitEvent(s, pc->ev_cpl, 0));  // also when K_rr has a single block
   // [X | Y'] = K_rr^{-1} [C_r^T | -K_rv]
   if (sizeof(T) == 8) launch_fill_f64((double*)N.Z, pl.pool_Z, 0.0, s);
   else launch_fill_f32((float*)N.Z, pl.pool_Z, 0.0f, s);
@@ -533,12 +534,15 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   // is applied, so they are built on a third stream while the coarse
   // factorization runs (its upper levels occupy few compute units); the
   // caller's stream waits for them at the end.
+  // The fronts' lower triangles are zeroed first (they are summed into);
+  // alone on the GPU this streaming pass is short, while beside the factor
+  // chains it slows their latency-bound sweeps.
+  launch_front_zero_lower(P, pc->all_fronts, pc->all_n, pc->all_maxn, pc->fpool, s);
   HIPCHK(hipEventRecord(pc->ev_fork_i, s));
   HIPCHK(hipStreamWaitEvent(pc->s3, pc->ev_fork_i, 0));
   factor_chain(0, pc->s3);
   HIPCHK(hipEventRecord(pc->ev_join_i, pc->s3));
   // coarse: assemble into the fronts and factor level by level (FP64)
-  HIPCHK(hipStreamWaitEvent(s, pc->ev_join, 0));  // the zeroed front pool
   for (size_t c = 0; c < pc->color_dev.size(); ++c)
     Kern<T>::kc_to_front(P, pc->color_dev[c], pc->color_n[c], N.Kc, pc->fpool, s);
   for (size_t L = 0; L < pc->swFront.size(); ++L) {
@@ -701,6 +705,7 @@ void bddcso_precond_destroy(bddcso_precond* pc) {
   if (pc->ev_join) (void)hipEventDestroy(pc->ev_join);
   if (pc->ev_la) (void)hipEventDestroy(pc->ev_la);
   if (pc->ev_lb) (void)hipEventDestroy(pc->ev_lb);
+  if (pc->ev_cpl) (void)hipEventDestroy(pc->ev_cpl);
   if (pc->ev_cfork) (void)hipEventDestroy(pc->ev_cfork);
   if (pc->ev_cjoin) (void)hipEventDestroy(pc->ev_cjoin);
   if (pc->ev_fork_i) (void)hipEventDestroy(pc->ev_fork_i);
@@ -895,6 +900,7 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     HIPCHK(hipStreamCreateWithFlags(&pc->s2, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&pc->s3, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_fork_i, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_cpl, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_cfork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_cjoin, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_join_i, hipEventDisableTiming));

@@ -66,7 +66,7 @@ struct PlanDev {
 };
 
 // ---- launchers (defined in kernels.hip) ---------------------------------
-void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s, int max_blocks = 65536);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
@@ -80,7 +80,7 @@ void launch_coupling_coefs(const PlanDev& P, const Geo& g, const double* rho, do
 template <typename T>
 struct Kern {
   // setup
-  static void block_assemble(const PlanDev& P, const Geo& g, const double* rho, int setR, T* G,
+  static void block_assemble(const PlanDev& P, const Geo& g, const double* rho, int setR, T* G, int max_nb,
                              hipStream_t s);
   static void schur_couple(const PlanDev& P, const Geo& g, const double* rho, int setR, int k,
                            T* G, T* W, int64_t wstride, hipStream_t s);
@@ -126,6 +126,8 @@ void launch_coarse_rhs_gather(const PlanDev& P, const double* bci_d, const float
                               double* bc, int nrhs, hipStream_t s);
 void launch_gamma_w(const PlanDev& P, const Geo& g, const double* v2_d, const float* v2_f,
                     const double* delta, double* z, int nrhs, hipStream_t s);
+void launch_front_zero_lower(const PlanDev& P, const int32_t* fronts, int nfr, int maxn, double* fpool,
+                             hipStream_t s);
 void launch_front_child_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
                                 double* fpool, hipStream_t s);
 void launch_front_vec_init(const PlanDev& P, const int32_t* fr, int nfr, int maxn, const double* bc,

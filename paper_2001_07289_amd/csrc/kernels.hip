@@ -260,6 +260,25 @@ __global__ void k_coupling_coefs(PlanDev P, Geo g, const double* __restrict__ rh
 
 // ---------------------------------------------------------------------------
 // local matrices: dense diagonal blocks of K_II / K_rr (entries within a block)
+//
+// Only the lower triangles are formed: k_block_zero_lower clears them (one
+// thread per entry, lanes along i), then k_block_assemble writes the stencil
+// entries with j <= i.  The upper triangles are left as they are: the sweeps
+// read only the lower triangle and write both, and the Schur coupling's
+// updates of the upper entries are overwritten by the sweep.
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_zero_lower(PlanDev P, int setR, T* __restrict__ G) {
+  // one workgroup per block, running through the square (stores contiguous)
+  const int sub = blockIdx.y, k = blockIdx.x;
+  const SubDev S = P.subs[sub];
+  if (k >= (setR ? S.nbR : S.nbI)) return;
+  const BlockDev B = P.blocks[(setR ? S.bR_off : S.bI_off) + k];
+  T* Gb = G + B.G_off;
+  const int n2 = B.size * B.size;
+  for (int idx = threadIdx.x; idx < n2; idx += 256)
+    if (idx / B.size <= idx % B.size) Gb[idx] = (T)0;
+}
 
 template <typename T>
 __global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rho, int setR,
@@ -289,7 +308,7 @@ __global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rh
         if (ln < 0) continue;
         int j = ls[ln];
         if (j < 0) continue;
-        if (cn[pa] < B.plane_lo || cn[pa] >= B.plane_hi) continue;
+        if (cn[pa] < B.plane_lo || cn[pa] >= B.plane_hi || j > i) continue;
         G[B.G_off + (int64_t)(i - B.start) + (int64_t)B.size * (j - B.start)] =
             (T)kloc(S, g, rho, P.khat, c, cn);
       }
@@ -1920,7 +1939,22 @@ __global__ void k_kc_to_front(PlanDev P, const int32_t* __restrict__ subs_c, con
   const int a = idx % S.n_c, b = idx / S.n_c;
   const FrontDev F = P.fronts[S.front];
   const int pa = P.sub_fmap[S.c_off + a], pb = P.sub_fmap[S.c_off + b];
+  // the fronts' lower triangles only (the sweeps read nothing else); K_c,i is
+  // symmetric, so each lower entry takes (a, b) or its mirror exactly once
+  if (pa < pb) return;
   fpool[F.off + pa + (int64_t)F.n * pb] += (double)Kc[S.Kc_off + idx];
+}
+
+// Zero the lower triangle of every front (all that is summed into and read
+// by the sweeps): one workgroup per (front, 32 columns).
+__global__ __launch_bounds__(256) void k_front_zero_lower(PlanDev P, const int32_t* __restrict__ fr,
+                                                          double* __restrict__ fpool) {
+  const FrontDev F = P.fronts[fr[blockIdx.y]];
+  const int j0 = blockIdx.x * 32;
+  if (j0 >= F.n) return;
+  double* M = fpool + F.off;
+  for (int j = j0; j < min(j0 + 32, F.n); ++j)
+    for (int i = j + threadIdx.x; i < F.n; i += 256) M[i + (int64_t)F.n * j] = 0.0;
 }
 
 __global__ void k_front_child_scatter(PlanDev P, const int32_t* __restrict__ children,
@@ -1933,6 +1967,7 @@ __global__ void k_front_child_scatter(PlanDev P, const int32_t* __restrict__ chi
   if (idx >= nb * nb) return;
   const int a = idx % nb, b = idx / nb;
   const int pa = P.front_pmap[C.pmap_off + a], pb = P.front_pmap[C.pmap_off + b];
+  if (pa < pb) return;  // lower triangle of the parent; the child's update block is symmetric
   fpool[F.off + pa + (int64_t)F.n * pb] += fpool[C.off + (C.p + a) + (int64_t)C.n * (C.p + b)];
 }
 
@@ -3004,9 +3039,9 @@ __global__ void k_box_filter(Geo g, const double* __restrict__ in, double* __res
 
 #define LAUNCH_CHECK() (void)hipGetLastError()
 
-void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s, int max_blocks) {
   if (n <= 0) return;
-  k_fill<double><<<hmin(cdiv(n, 256), 65536), 256, 0, s>>>(p, n, v);
+  k_fill<double><<<hmin(cdiv(n, 256), (int64_t)max_blocks), 256, 0, s>>>(p, n, v);
 }
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   if (n <= 0) return;
@@ -3078,10 +3113,11 @@ void launch_coupling_coefs(const PlanDev& P, const Geo& g, const double* rho, do
 }
 
 template <typename T>
-void Kern<T>::block_assemble(const PlanDev& P, const Geo& g, const double* rho, int setR, T* G,
+void Kern<T>::block_assemble(const PlanDev& P, const Geo& g, const double* rho, int setR, T* G, int max_nb,
                              hipStream_t s) {
-  int mx = setR ? P.max_nr : P.max_nI;
-  if (mx == 0) return;
+  if (max_nb == 0 || P.max_block == 0) return;
+  k_block_zero_lower<T><<<dim3(max_nb, P.n_sub), 256, 0, s>>>(P, setR, G);
+  const int mx = setR ? P.max_nr : P.max_nI;
   k_block_assemble<T><<<dim3(cdiv(mx, 128), P.n_sub), 128, 0, s>>>(P, g, rho, setR, G);
 }
 
@@ -3409,6 +3445,11 @@ void launch_coarse_rhs_gather(const PlanDev& P, const double* bci_d, const float
   else k_coarse_rhs_gather<float><<<grid, 256, 0, s>>>(P, bci_f, bc);
 }
 
+void launch_front_zero_lower(const PlanDev& P, const int32_t* fronts, int nfr, int maxn, double* fpool,
+                             hipStream_t s) {
+  if (nfr == 0 || maxn == 0) return;
+  k_front_zero_lower<<<dim3(cdiv(maxn, 32), nfr), 256, 0, s>>>(P, fronts, fpool);
+}
 void launch_front_child_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
                                 double* fpool, hipStream_t s) {
   if (nchild == 0 || maxn == 0) return;
