@@ -1484,34 +1484,28 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
 // memory once per 128 columns and every B element once.  The waves form a
 // 4 x 4 grid; wave (wr, wc) owns the row tiles wr + 4i and the column tiles
 // wc + 4j (16 x 16 each).  K goes in chunks of GF_KC through LDS with the
-// next chunk prefetched into registers.
+// next chunk prefetched into registers.  The LDS tiles are zero-padded to
+// 192 rows and to whole chunks, so every wave runs the same branch-free
+// k-steps (three row tiles, one or two column tiles by a wave-uniform
+// choice made once) and the products of padding are never stored.
 constexpr int GF_KC = 32;
-constexpr int GF_M = 176, GF_N = 128;
+constexpr int GF_M = 176, GF_N = 128, GF_MP = 192;
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_gemm_full(const GemmDesc* __restrict__ desc,
-                                                    const T* __restrict__ Ap, const T* __restrict__ Bp,
-                                                    T* __restrict__ Cp, T alpha, T beta) {
+template <typename T, int NB>
+__device__ __forceinline__ void gf_main(const GemmDesc& d, const T* __restrict__ A, const T* __restrict__ B,
+                                        T* __restrict__ C, int nn, T alpha, T beta, T (*As)[GF_MP + 4],
+                                        T (*Bs)[GF_N + 4]) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[GF_KC][GF_M + 4];
-  __shared__ T Bs[GF_KC][GF_N + 4];
-  const GemmDesc d = desc[blockIdx.x];
-  const int n0 = blockIdx.y * GF_N;
-  if (d.m <= 0 || n0 >= d.n) return;
-  const int nn = min(GF_N, d.n - n0);
-  const T* A = Ap + d.a;
-  const T* B = Bp + d.b + (int64_t)d.ldb * n0;
-  T* C = Cp + d.c + (int64_t)d.ldc * n0;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int kq = lane >> 4, rr = lane & 15;
   const int wr = wave & 3, wc = wave >> 2;
-  constexpr int PA = (GF_M * GF_KC + 1023) / 1024, PB = GF_N * GF_KC / 1024;
+  constexpr int PA = (GF_MP * GF_KC) / 1024, PB = GF_N * GF_KC / 1024;
   T ra[PA], rb[PB];
   auto load = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < PA; ++u) {
-      const int idx = tid + 1024 * u, i = idx % GF_M, q = idx / GF_M;
-      ra[u] = (q < GF_KC && i < d.m && k0 + q < d.k) ? A[i + (int64_t)d.lda * (k0 + q)] : (T)0;
+      const int idx = tid + 1024 * u, i = idx % GF_MP, q = idx / GF_MP;
+      ra[u] = (i < d.m && k0 + q < d.k) ? A[i + (int64_t)d.lda * (k0 + q)] : (T)0;
     }
 #pragma unroll
     for (int u = 0; u < PB; ++u) {
@@ -1522,8 +1516,8 @@ __global__ __launch_bounds__(1024) void k_gemm_full(const GemmDesc* __restrict__
   auto store = [&]() {
 #pragma unroll
     for (int u = 0; u < PA; ++u) {
-      const int idx = tid + 1024 * u, i = idx % GF_M, q = idx / GF_M;
-      if (q < GF_KC) As[q][i] = ra[u];
+      const int idx = tid + 1024 * u, i = idx % GF_MP, q = idx / GF_MP;
+      As[q][i] = ra[u];
     }
 #pragma unroll
     for (int u = 0; u < PB; ++u) {
@@ -1531,45 +1525,38 @@ __global__ __launch_bounds__(1024) void k_gemm_full(const GemmDesc* __restrict__
       Bs[q][j] = rb[u];
     }
   };
-  acc_t acc[3][2];
+  acc_t acc[3][NB > 0 ? NB : 1];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-  bool ra_on[3], rb_on[2];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) ra_on[a] = (wr + 4 * a) * 16 < d.m;
-#pragma unroll
-  for (int b = 0; b < 2; ++b) rb_on[b] = (wc + 4 * b) * 16 < nn;
+    for (int b = 0; b < (NB > 0 ? NB : 1); ++b) acc[a][b] = acc_t{0, 0, 0, 0};
   load(0);
   for (int k0 = 0; k0 < d.k; k0 += GF_KC) {
     __syncthreads();
     store();
     __syncthreads();
     if (k0 + GF_KC < d.k) load(k0 + GF_KC);
-    const int ksteps = min(GF_KC / 4, (d.k - k0 + 3) / 4);
+    if (NB > 0) {
 #pragma unroll
-    for (int ks = 0; ks < GF_KC / 4; ++ks) {
-      if (ks >= ksteps) break;
-      const int kk = ks * 4 + kq;
-      T av[3], bv[2];
+      for (int ks = 0; ks < GF_KC / 4; ++ks) {
+        const int kk = ks * 4 + kq;
+        T av[3], bv[NB > 0 ? NB : 1];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) av[a] = ra_on[a] ? As[kk][(wr + 4 * a) * 16 + rr] : (T)0;
+        for (int a = 0; a < 3; ++a) av[a] = As[kk][(wr + 4 * a) * 16 + rr];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = rb_on[b] ? Bs[kk][(wc + 4 * b) * 16 + rr] : (T)0;
-      // transposed product (B as the A operand) so each lane's outputs run down a column
+        for (int b = 0; b < NB; ++b) bv[b] = Bs[kk][(wc + 4 * b) * 16 + rr];
+        // transposed product (B as the A operand) so each lane's outputs run down a column
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-          if (ra_on[a] && rb_on[b]) acc[a][b] = Mfma<T>::mac(bv[b], av[a], acc[a][b]);
+          for (int b = 0; b < NB; ++b) acc[a][b] = Mfma<T>::mac(bv[b], av[a], acc[a][b]);
+      }
     }
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      if (!(ra_on[a] && rb_on[b])) continue;
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = (wr + 4 * a) * 16 + rr;
@@ -1580,7 +1567,28 @@ __global__ __launch_bounds__(1024) void k_gemm_full(const GemmDesc* __restrict__
           *c = beta == (T)0 ? v : beta * *c + v;
         }
       }
-    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_gemm_full(const GemmDesc* __restrict__ desc,
+                                                    const T* __restrict__ Ap, const T* __restrict__ Bp,
+                                                    T* __restrict__ Cp, T alpha, T beta) {
+  __shared__ T As[GF_KC][GF_MP + 4];
+  __shared__ T Bs[GF_KC][GF_N + 4];
+  const GemmDesc d = desc[blockIdx.x];
+  const int n0 = blockIdx.y * GF_N;
+  if (d.m <= 0 || n0 >= d.n) return;
+  const int nn = min(GF_N, d.n - n0);
+  const T* A = Ap + d.a;
+  const T* B = Bp + d.b + (int64_t)d.ldb * n0;
+  T* C = Cp + d.c + (int64_t)d.ldc * n0;
+  // column tiles wc, wc + 4 of this wave that hold output (wave-uniform);
+  // every wave runs the same chunk loop and barriers
+  const int wc = (threadIdx.x >> 6) >> 2;
+  const int nb = __builtin_amdgcn_readfirstlane((wc + 4) * 16 < nn ? 2 : wc * 16 < nn ? 1 : 0);
+  if (nb == 2) gf_main<T, 2>(d, A, B, C, nn, alpha, beta, As, Bs);
+  else if (nb == 1) gf_main<T, 1>(d, A, B, C, nn, alpha, beta, As, Bs);
+  else gf_main<T, 0>(d, A, B, C, nn, alpha, beta, As, Bs);
 }
 
 // ---------------------------------------------------------------------------
@@ -3178,9 +3186,11 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
           df += sb * sb * sb;
           db += sizeof(T) * (sb * (sb + 1) / 2 + sb * sb);
         }
-      if (prof) prof->begin(5, ss);
+      // booked with the panel work (class 4): one workgroup per front sweeps
+      // the slab's pivot block, a latency chain rather than a batch
+      if (prof) prof->begin(4, ss);
       k_sweep_reg<T, 12, 16><<<nprob, 16 * 64, 0, ss>>>(d_desc, pool, status, status_code, j0);
-      if (prof) prof->end(5, df, db, ss);
+      if (prof) prof->end(4, df, db, ss);
     };
     reg(0, s);
     for (int j0 = 0; j0 < maxp; j0 += SLAB) {
