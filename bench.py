@@ -86,6 +86,9 @@ def kernel_class(name):
     if not m:
         return None
     base = m.group(1)
+    # the 16-wave register sweep instance is the slab pivot-block sweep (class 4)
+    if base == "k_sweep_reg" and re.search(r"k_sweep_reg<[^,>]+,\s*12,\s*16>|k_sweep_regI[df]Li12ELi16E", name):
+        return "sweep_panel"
     for cls, prefixes in CLASS_KERNELS.items():
         if any(base == p or base.startswith(p + "_") for p in prefixes):
             return cls

@@ -204,8 +204,9 @@ bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bd
  * selects class c (0 switches it off and clears the record).  Classes: 1 the
  * trailing updates of the sweeps (rank-32 panels, rank-192 slabs; MFMA),
  * 2 the block-tridiagonal solves (HBM), 3 the batched GEMMs (MFMA), 4 the
- * sweep panels and slab CD products, 5 the register-resident sweeps of
- * matrices up to 272 rows and of slab pivot blocks (MFMA).
+ * pivot-block work of the large sweeps: 32-pivot panels, slab pivot blocks
+ * (one workgroup each) and slab CD products, 5 the batched register-resident
+ * sweeps of matrices up to 272 rows (MFMA).
  * bddcso_profile_read waits for
  * the recorded events, then returns for one class the launches seen, their
  * summed duration and their summed algorithmic flops and bytes (the minimum
