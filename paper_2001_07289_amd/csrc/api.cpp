@@ -358,7 +358,7 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
         int nb = setR ? S.nbR : S.nbI;
         if (k >= nb) continue;
         const BlockDev& B = pl.blocks[(setR ? S.bR_off : S.bI_off) + k];
-        d.push_back({B.G_off, B.size, B.size, B.size});
+        d.push_back({B.G_off, B.size, B.size, B.ld});
       }
       check_sweeps(d, pl.pool_G, ns, setR ? "K_rr blocks" : "K_II blocks");
       vec.push_back(make_sweep_batch(m, d, s));
@@ -371,12 +371,12 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       int ncols = S.n_a + S.n_v;
       if (k >= S.nbR || ncols == 0) continue;
       const BlockDev& B = pl.blocks[S.bR_off + k];
-      f.push_back({B.G_off, sidx * tmp_stride, S.Z_off + B.start, B.size, ncols, B.size, B.size, B.size, S.n_r});
+      f.push_back({B.G_off, sidx * tmp_stride, S.Z_off + B.start, B.size, ncols, B.size, B.ld, B.size, S.n_r});
       if (k + 1 < S.nbR) {
         const BlockDev& N = pl.blocks[S.bR_off + k + 1];
         if (B.plane_hi == N.plane_lo)
-          b.push_back({B.G_off + (int64_t)B.size * (B.size - B.last_n), sidx * tmp_stride, S.Z_off + B.start,
-                       B.size, ncols, B.last_n, B.size, B.last_n, S.n_r});
+          b.push_back({B.G_off + (int64_t)B.ld * (B.size - B.last_n), sidx * tmp_stride, S.Z_off + B.start,
+                       B.size, ncols, B.last_n, B.ld, B.last_n, S.n_r});
       }
     }
     check_gemms(f, pl.pool_G, tmp_stride * ns, pl.pool_Z, "forward block GEMM");

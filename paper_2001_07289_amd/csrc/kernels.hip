@@ -276,8 +276,10 @@ __global__ __launch_bounds__(256) void k_block_zero_lower(PlanDev P, int setR, T
   const BlockDev B = P.blocks[(setR ? S.bR_off : S.bI_off) + k];
   T* Gb = G + B.G_off;
   const int n2 = B.size * B.size;
-  for (int idx = threadIdx.x; idx < n2; idx += 256)
-    if (idx / B.size <= idx % B.size) Gb[idx] = (T)0;
+  for (int idx = threadIdx.x; idx < n2; idx += 256) {
+    const int i = idx % B.size, j = idx / B.size;
+    if (j <= i) Gb[i + (int64_t)B.ld * j] = (T)0;
+  }
 }
 
 template <typename T>
@@ -309,7 +311,7 @@ __global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rh
         int j = ls[ln];
         if (j < 0) continue;
         if (cn[pa] < B.plane_lo || cn[pa] >= B.plane_hi || j > i) continue;
-        G[B.G_off + (int64_t)(i - B.start) + (int64_t)B.size * (j - B.start)] =
+        G[B.G_off + (int64_t)(i - B.start) + (int64_t)B.ld * (j - B.start)] =
             (T)kloc(S, g, rho, P.khat, c, cn);
       }
 }
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(256) void k_schur_couple(PlanDev P, int setR, int k
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
           const int m = crk[cb + cc][t];
-          gv[cc][t] = m >= 0 ? Gr[lp + (int64_t)Bp.size * m] : (T)0;
+          gv[cc][t] = m >= 0 ? Gr[lp + (int64_t)Bp.ld * m] : (T)0;
         }
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc) {
@@ -378,7 +380,7 @@ __global__ __launch_bounds__(256) void k_schur_couple(PlanDev P, int setR, int k
   __syncthreads();
   // S_k[i'][c] += sum_t A[i', l_t] W[l_t][c], all of the row's columns at once
   const int base = Bp.start + Bp.size - Bp.last_n;
-  T* Gk = G + B.G_off + (int64_t)B.size * c0;
+  T* Gk = G + B.G_off + (int64_t)B.ld * c0;
   for (int ip = threadIdx.x; ip < B.first_n; ip += blockDim.x) {
     const int64_t row = B.cf_off + ip;
     double a[9];
@@ -391,13 +393,13 @@ __global__ __launch_bounds__(256) void k_schur_couple(PlanDev P, int setR, int k
     }
     T old[SC_COLS];
 #pragma unroll
-    for (int c = 0; c < SC_COLS; ++c) old[c] = c < cols ? Gk[ip + (int64_t)B.size * c] : (T)0;
+    for (int c = 0; c < SC_COLS; ++c) old[c] = c < cols ? Gk[ip + (int64_t)B.ld * c] : (T)0;
 #pragma unroll
     for (int c = 0; c < SC_COLS; ++c) {
       double acc = 0.0;
 #pragma unroll
       for (int t = 0; t < 9; ++t) acc += a[t] * (double)W[l[t]][c];
-      if (c < cols) Gk[ip + (int64_t)B.size * c] = old[c] + (T)acc;
+      if (c < cols) Gk[ip + (int64_t)B.ld * c] = old[c] + (T)acc;
     }
   }
 }
@@ -2034,8 +2036,8 @@ __device__ __forceinline__ void bs_tile_rc(int lin, int t0, int nrow, int& tr, i
 // origin is wave-uniform, so each load is a scalar base plus a 32-bit lane
 // offset.
 template <typename T>
-__device__ __forceinline__ void bs_tile_load(const T* __restrict__ M, int s, int base, int tr, int tc, int a, int g,
-                                             T (&L)[4]) {
+__device__ __forceinline__ void bs_tile_load(const T* __restrict__ M, int s, int ld, int base, int tr, int tc, int a,
+                                             int g, T (&L)[4]) {
   const int r = tr * 16 + a;
   const bool rok = r < s && r >= base;
 #pragma unroll
@@ -2045,7 +2047,7 @@ __device__ __forceinline__ void bs_tile_load(const T* __restrict__ M, int s, int
     // every lane loads (entry 0 when off: bs_tile_mul masks it), from the
     // uniform block base plus a 32-bit byte offset; nothing touches the
     // value until it is used, so the load stays in flight
-    const uint32_t byte = on ? (uint32_t)(q * s + r) * (uint32_t)sizeof(T) : 0u;
+    const uint32_t byte = on ? (uint32_t)(q * ld + r) * (uint32_t)sizeof(T) : 0u;
     L[u] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(M) + byte);
   }
 }
@@ -2101,6 +2103,7 @@ __device__ __forceinline__ BlockDev block_uniform(const BlockDev* __restrict__ p
   B.plane_hi = __builtin_amdgcn_readfirstlane(B.plane_hi);
   B.first_n = __builtin_amdgcn_readfirstlane(B.first_n);
   B.last_n = __builtin_amdgcn_readfirstlane(B.last_n);
+  B.ld = __builtin_amdgcn_readfirstlane(B.ld);
   B.G_off = rfl64(B.G_off);
   B.cf_off = rfl64(B.cf_off);
   B.cb_off = rfl64(B.cb_off);
@@ -2173,7 +2176,7 @@ __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, int setR,
       const int lin = wave + BS_WAVES * u;
       int tr = nt, tc = 0;  // past the last row: loads nothing
       if (lin < ntiles) bs_tile_rc(lin, t0, nrow, tr, tc);
-      bs_tile_load(G + B.G_off, B.size, base, tr, tc, a, g, L[u]);
+      bs_tile_load(G + B.G_off, B.size, B.ld, base, tr, tc, a, g, L[u]);
     }
   };
   if (nsteps > 0) {
@@ -2248,7 +2251,7 @@ __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, int setR,
         int tr, tc;
         bs_tile_rc(lin, t0, nrow, tr, tc);
         T Lx[4];
-        bs_tile_load(G + B.G_off, s, base, tr, tc, a, g, Lx);
+        bs_tile_load(G + B.G_off, s, B.ld, base, tr, tc, a, g, Lx);
         bs_tile_mul(Lx, s, base, tr, tc, a, g, cl, y);
       }
     }
@@ -2371,7 +2374,7 @@ __global__ __launch_bounds__(MR_THREADS) void k_block_solve_mr(PlanDev P, int se
       cl[i][r] = c;
     }
     __syncthreads();
-    block_gemm_mr(G + B.G_off, B.size, B.size, B.size, cl, v + B.start, vstride, nr, false, (T)-1, wave, lane);
+    block_gemm_mr(G + B.G_off, B.ld, B.size, B.size, cl, v + B.start, vstride, nr, false, (T)-1, wave, lane);
     __syncthreads();
   }
   for (int k = nb - 2; k >= 0; --k) {
@@ -2393,7 +2396,7 @@ __global__ __launch_bounds__(MR_THREADS) void k_block_solve_mr(PlanDev P, int se
       cl[i][r] = (T)acc;
     }
     __syncthreads();
-    block_gemm_mr(G + B.G_off + (int64_t)B.size * base, B.size, B.last_n, B.size, cl, v + B.start, vstride, nr,
+    block_gemm_mr(G + B.G_off + (int64_t)B.ld * base, B.ld, B.last_n, B.size, cl, v + B.start, vstride, nr,
                   true, (T)1, wave, lane);
     __syncthreads();
   }

@@ -574,8 +574,12 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     }
     for (int64_t k = S.bI_off; k < (int64_t)plan.blocks.size(); ++k) {
       BlockDev& B = plan.blocks[k];
+      // columns start on 16-element (128-byte in FP64) boundaries, so the
+      // 16-row tiles of the solves and sweeps are whole cache lines
+      B.ld = (B.size + 15) / 16 * 16;
+      G_off = (G_off + 15) / 16 * 16;
       B.G_off = G_off;
-      G_off += (int64_t)B.size * B.size;
+      G_off += (int64_t)B.ld * B.size;
       plan.max_block = std::max(plan.max_block, B.size);
     }
     plan.max_nbI = std::max(plan.max_nbI, S.nbI);

@@ -44,7 +44,8 @@ struct BlockDev {
   int start, size;          // first rank in set order, number of nodes
   int plane_lo, plane_hi;   // local plane range
   int first_n, last_n;      // nodes in the first / last plane of the block
-  int64_t G_off;            // offset of its size x size matrix in the pool
+  int ld;                   // leading dimension of its matrix: size rounded up to 16
+  int64_t G_off;            // offset of its size x size matrix (ld x size storage, 16-aligned)
   int64_t cf_off;           // coupling rows of the first plane to block k-1 (-1: none)
   int64_t cb_off;           // coupling rows of the last plane to block k+1 (-1: none)
 };
