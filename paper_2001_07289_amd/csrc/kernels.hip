@@ -1140,10 +1140,22 @@ __device__ __forceinline__ T slab_c(const T* A, int ld, int j0, int i, int t) {
   return i >= j0 ? A[i + (int64_t)ld * (j0 + t)] : A[(j0 + t) + (int64_t)ld * i];
 }
 
+// Element e of an array with a wave-uniform base, addressed by a 32-bit byte
+// offset (matrices here stay far below 4 GB): no 64-bit address registers.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t e) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + e * (uint32_t)sizeof(T));
+}
+// slab_c through 32-bit offsets
+template <typename T>
+__device__ __forceinline__ T slab_c32(const T* A, int ld, int j0, int i, int t) {
+  return ld32(A, i >= j0 ? (uint32_t)(i + ld * (j0 + t)) : (uint32_t)((j0 + t) + ld * i));
+}
+
 // 2. CD[i][q] = -sum_t C[i][t] W[t][q], W = M_SS after step 1 (= -M_SS^{-1}).
 // One workgroup per (64-row tile, 64-column tile of the slab, matrix).
 template <typename T>
-__global__ __launch_bounds__(256) void k_slab_cd(const SweepDesc* __restrict__ desc, const T* __restrict__ pool,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_slab_cd(const SweepDesc* __restrict__ desc, const T* __restrict__ pool,
                                                  int j0, T* __restrict__ scratch, int64_t scr_stride) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T As[32][TILE + PAD];  // C rows i, K chunk
@@ -1164,18 +1176,22 @@ __global__ __launch_bounds__(256) void k_slab_cd(const SweepDesc* __restrict__ d
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-  for (int k0 = 0; k0 < sb; k0 += 32) {
-    T av[8], bv[8];
+  // the next K chunk is loaded into registers while this one is multiplied
+  T av[8], bv[8];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = tid + u * 256;
       const int r = idx % TILE, t = idx / TILE;   // 64 rows x 32 K
       const int i = i0 + r, kk = k0 + t;
       const bool ok = i < n && kk < sb && !(i >= j0 && i < j0 + sb);
-      av[u] = ok ? slab_c(A, ld, j0, i, kk) : (T)0;
+      av[u] = ok ? slab_c32(A, ld, j0, i, kk) : (T)0;
       const int q = q0 + r;                        // W[kk][q] = M[j0+q][j0+kk] (both triangles valid)
-      bv[u] = (q < sb && kk < sb) ? A[(j0 + q) + (int64_t)ld * (j0 + kk)] : (T)0;
+      bv[u] = (q < sb && kk < sb) ? ld32(A, (uint32_t)((j0 + q) + ld * (j0 + kk))) : (T)0;
     }
+  };
+  load(0);
+  for (int k0 = 0; k0 < sb; k0 += 32) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -1184,6 +1200,7 @@ __global__ __launch_bounds__(256) void k_slab_cd(const SweepDesc* __restrict__ d
       Bs[idx / TILE][idx % TILE] = bv[u];
     }
     __syncthreads();
+    if (k0 + 32 < sb) load(k0 + 32);
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const int kk = ks * 4 + kq;
@@ -1215,7 +1232,7 @@ __global__ __launch_bounds__(256) void k_slab_cd(const SweepDesc* __restrict__ d
 // region: 0 every tile; 1 only the tiles of the next slab's pivot block;
 // 2 every tile but those (the two halves of the update, for the look-ahead).
 template <typename T>
-__global__ __launch_bounds__(256) void k_slab_update(const SweepDesc* __restrict__ desc, T* pool, int j0,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_slab_update(const SweepDesc* __restrict__ desc, T* pool, int j0,
                                                      const T* __restrict__ scratch, int64_t scr_stride,
                                                      int ntri, int nprob, int region) {
   typedef typename Mfma<T>::acc_t acc_t;
@@ -1254,16 +1271,20 @@ __global__ __launch_bounds__(256) void k_slab_update(const SweepDesc* __restrict
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-  for (int k0 = 0; k0 < sb; k0 += 32) {
-    T av[8], bv[8];
+  // the next K chunk is loaded into registers while this one is multiplied
+  T av[8], bv[8];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = tid + u * 256;
       const int r = idx % TILE, q = idx / TILE;
       const int i = i0 + r, j = c0 + r, kk = k0 + q;
-      av[u] = (i < n && kk < sb && !(i >= j0 && i < j0 + sb)) ? CD[i + (int64_t)n * kk] : (T)0;
-      bv[u] = (j < n && kk < sb && !(j >= j0 && j < j0 + sb)) ? slab_c(A, ld, j0, j, kk) : (T)0;
+      av[u] = (i < n && kk < sb && !(i >= j0 && i < j0 + sb)) ? ld32(CD, (uint32_t)(i + n * kk)) : (T)0;
+      bv[u] = (j < n && kk < sb && !(j >= j0 && j < j0 + sb)) ? slab_c32(A, ld, j0, j, kk) : (T)0;
     }
+  };
+  load(0);
+  for (int k0 = 0; k0 < sb; k0 += 32) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -1272,6 +1293,7 @@ __global__ __launch_bounds__(256) void k_slab_update(const SweepDesc* __restrict
       Bs[idx / TILE][idx % TILE] = bv[u];
     }
     __syncthreads();
+    if (k0 + 32 < sb) load(k0 + 32);
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const int kk = ks * 4 + kq;
@@ -1459,8 +1481,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
         if (ra1) acc[1][0] = Mfma<T>::mac(bv[0], av[1], acc[1][0]);
         if (ra1 && rb1) acc[1][1] = Mfma<T>::mac(bv[1], av[1], acc[1][1]);
       }
-    }
-    __syncthreads();
+    }    __syncthreads();
     if (more) store(0);
     __syncthreads();
   }
