@@ -3213,7 +3213,7 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
       // booked with the panel work (class 4): one workgroup per front sweeps
       // the slab's pivot block, a latency chain rather than a batch
       if (prof) prof->begin(4, ss);
-      k_sweep_reg<T, 12, 16><<<nprob, 16 * 64, 0, ss>>>(d_desc, pool, status, status_code, j0);
+      k_sweep_reg<T, SLAB / 16, 16><<<nprob, 16 * 64, 0, ss>>>(d_desc, pool, status, status_code, j0);
       if (prof) prof->end(4, df, db, ss);
     };
     reg(0, s);
