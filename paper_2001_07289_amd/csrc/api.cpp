@@ -241,6 +241,7 @@ struct bddcso_precond {
   hipEvent_t ev_cpl = nullptr;                         // plane-coupling coefficients ready
   hipEvent_t ev_la = nullptr, ev_lb = nullptr;   // slab look-ahead of the coarse fronts
   double gI_entries = 0, gR_entries = 0;  // G entries streamed by one block solve
+  int max_block_I = 0, max_block_R = 0;   // largest diagonal block of each set
   Profiler* P_() { return prof.mask ? &prof : nullptr; }
 };
 
@@ -411,6 +412,8 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       const int nb = setR ? S.nbR : S.nbI;
       for (int k = 0; k < nb; ++k) {
         const BlockDev& B = pl.blocks[(setR ? S.bR_off : S.bI_off) + k];
+        int& mbs = setR ? pc->max_block_R : pc->max_block_I;
+        mbs = std::max(mbs, B.size);
         // lower triangle (forward) and the band of rows >= size - last_n (backward)
         const double lb = B.last_n, base = B.size - B.last_n;
         double e = (double)B.size * (B.size + 1) / 2 + (B.cb_off >= 0 ? lb * base + lb * (lb + 1) / 2 : 0.0);
@@ -583,7 +586,8 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   const double* rho = pc->rho;
   // 1-2: Dirichlet solves and (I - P)^T on Gamma
   Kern<T>::gather_I(P, g, r, N.vI, nrhs, s);
-  Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s, pc->P_(), pc->gI_entries, (double)pl.tot_I);
+  Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s, pc->P_(), pc->gI_entries, (double)pl.tot_I,
+                       pc->max_block_I);
   Kern<T>::gamma_kgi(P, g, rho, N.vI, N.q, nrhs, s);
   // 3: E^T
   Kern<T>::gamma_t(P, g, r, N.q, pc->delta, N.gv, nrhs, s);
@@ -596,7 +600,8 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   if (sizeof(T) == 8) launch_fill_f64((double*)N.vR, pl.tot_r * nrhs, 0.0, s);
   else launch_fill_f32((float*)N.vR, pl.tot_r * nrhs, 0.0f, s);
   Kern<T>::neumann_rhs(P, N.gv, N.vR, nrhs, s);
-  Kern<T>::block_solve(P, g, rho, 1, N.G, N.vR, nrhs, s, pc->P_(), pc->gR_entries, (double)pl.tot_r);
+  Kern<T>::block_solve(P, g, rho, 1, N.G, N.vR, nrhs, s, pc->P_(), pc->gR_entries, (double)pl.tot_r,
+                       pc->max_block_R);
   Kern<T>::mu(P, N.vR, N.Sc, N.mu, nrhs, s);
   HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_cfork, 0));
   Kern<T>::coarse_rhs_local(P, N.PhiG, N.gv, N.bci, nrhs, pc->s2);
@@ -611,7 +616,8 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   else launch_gamma_w(P, g, nullptr, (const float*)N.v2, pc->delta, z, nrhs, s);
   // 9-10: harmonic extension into the interiors
   Kern<T>::interior_rhs(P, g, rho, r, z, N.vI, nrhs, s);
-  Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s, pc->P_(), pc->gI_entries, (double)pl.tot_I);
+  Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s, pc->P_(), pc->gI_entries, (double)pl.tot_I,
+                       pc->max_block_I);
   Kern<T>::scatter_I(P, g, N.vI, z, nrhs, s);
 }
 

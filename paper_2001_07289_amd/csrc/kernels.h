@@ -106,7 +106,7 @@ struct Kern {
   static void gather_I(const PlanDev& P, const Geo& g, const double* r, T* vI, int nrhs, hipStream_t s);
   static void block_solve(const PlanDev& P, const Geo& g, const double* rho, int setR, const T* G,
                           T* v, int nrhs, hipStream_t s, Profiler* prof, double g_entries,
-                          double vec_entries);
+                          double vec_entries, int set_max_block);
   static void gamma_kgi(const PlanDev& P, const Geo& g, const double* rho, const T* vI, T* q,
                         int nrhs, hipStream_t s);
   static void gamma_t(const PlanDev& P, const Geo& g, const double* r, const T* q, const double* delta,

@@ -2032,10 +2032,11 @@ __global__ void k_gather_I(PlanDev P, Geo g, const double* __restrict__ r, T* __
 // coupling reads stay in LDS from the step that produced them.  Waves take
 // tiles round-robin, keep partial sums per wave in LDS and the waves' sums
 // are added in fixed order, so the result is bitwise repeatable.
-constexpr int BS_THREADS = 1024;
-constexpr int BS_WAVES = BS_THREADS / 64;
-constexpr int BS_PT = 5;   // tiles per wave held in registers: blocks up to 192 rows
-constexpr int BS_CP = 2;   // coupling terms per thread held in registers: 227 coupled rows
+// Two shapes: 16 waves with 5 register-held tiles each (blocks up to 192
+// rows, one workgroup per CU), and 8 waves with 5 tiles each for sets whose
+// blocks have at most 40 tiles (up to 144 rows), which keeps the registers at
+// two workgroups per CU.
+constexpr int BS_WAVES_MAX = 16;
 
 // Tile lin of the lower triangle restricted to tile rows >= t0: first the
 // rectangle left of tile column t0, then the triangle of tile rows/columns >= t0.
@@ -2131,9 +2132,10 @@ __device__ __forceinline__ BlockDev block_uniform(const BlockDev* __restrict__ p
   return B;
 }
 
-template <typename T>
+template <typename T, int BS_THREADS, int BS_PT, int BS_CP>
 __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, int setR, const T* __restrict__ G,
                                                             T* __restrict__ vec) {
+  constexpr int BS_WAVES = BS_THREADS / 64;
   extern __shared__ char smem_raw[];
   const int mb = P.max_block;
   double* yp = reinterpret_cast<double*>(smem_raw);  // BS_WAVES x mb partial products
@@ -3108,7 +3110,7 @@ int64_t max_lds_bytes(const PlanDev& P, int elt, int max_nrhs) {
   int64_t need = 0;
   need = hmax(need, mp * (SC_COLS + 1) * elt + 2048);                                  // schur couple
   need = hmax(need, mp * (CPL_COLS + 1) * elt);                                        // couple multi
-  need = hmax(need, (int64_t)hmax(P.max_block, 1) * ((BS_WAVES + 9) * 8 + 2 * elt));      // block solve
+  need = hmax(need, (int64_t)hmax(P.max_block, 1) * ((BS_WAVES_MAX + 9) * 8 + 2 * elt));  // block solve
   if (max_nrhs >= 4) need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);  // many-rhs block solve
   need = hmax(need, (int64_t)(P.max_na + P.max_nc + 1) * elt);                         // v2
   need = hmax(need, (int64_t)hmax(P.max_ng, 1) * elt);                                 // coarse rhs
@@ -3385,14 +3387,21 @@ void Kern<T>::gather_I(const PlanDev& P, const Geo& g, const double* r, T* vI, i
 
 template <typename T>
 void Kern<T>::block_solve(const PlanDev& P, const Geo& g, const double* rho, int setR, const T* G,
-                          T* v, int nrhs, hipStream_t s, Profiler* prof, double g_entries, double vec_entries) {
+                          T* v, int nrhs, hipStream_t s, Profiler* prof, double g_entries, double vec_entries,
+                          int set_max_block) {
   if (prof) prof->begin(2, s);
   if (nrhs >= 4) {
     const size_t smr = (size_t)hmax(P.max_block, 1) * (MR_COLS + 1) * sizeof(T);
     k_block_solve_mr<T><<<dim3(P.n_sub, cdiv(nrhs, MR_COLS)), MR_THREADS, smr, s>>>(P, setR, G, v, nrhs);
   } else {
-    const size_t sm = (size_t)hmax(P.max_block, 1) * ((BS_WAVES + 9) * sizeof(double) + 2 * sizeof(T));
-    k_block_solve<T><<<dim3(P.n_sub, nrhs), BS_THREADS, sm, s>>>(P, setR, G, v);
+    const int nt = (int)cdiv(set_max_block, 16), tiles = nt * (nt + 1) / 2;
+    if (tiles <= 8 * 5) {
+      const size_t sm = (size_t)hmax(P.max_block, 1) * ((8 + 9) * sizeof(double) + 2 * sizeof(T));
+      k_block_solve<T, 512, 5, 3><<<dim3(P.n_sub, nrhs), 512, sm, s>>>(P, setR, G, v);
+    } else {
+      const size_t sm = (size_t)hmax(P.max_block, 1) * ((16 + 9) * sizeof(double) + 2 * sizeof(T));
+      k_block_solve<T, 1024, 5, 2><<<dim3(P.n_sub, nrhs), 1024, sm, s>>>(P, setR, G, v);
+    }
   }
   // the method must stream each lower-triangle G entry once per launch (4
   // flops per rhs off the diagonal) and read and write each vector once
