@@ -3399,8 +3399,8 @@ void Kern<T>::block_solve(const PlanDev& P, const Geo& g, const double* rho, int
       const size_t sm = (size_t)hmax(P.max_block, 1) * ((8 + 9) * sizeof(double) + 2 * sizeof(T));
       k_block_solve<T, 512, 5, 3><<<dim3(P.n_sub, nrhs), 512, sm, s>>>(P, setR, G, v);
     } else {
-      const size_t sm = (size_t)hmax(P.max_block, 1) * ((16 + 9) * sizeof(double) + 2 * sizeof(T));
-      k_block_solve<T, 1024, 5, 2><<<dim3(P.n_sub, nrhs), 1024, sm, s>>>(P, setR, G, v);
+      const size_t sm = (size_t)hmax(P.max_block, 1) * ((8 + 9) * sizeof(double) + 2 * sizeof(T));
+      k_block_solve<T, 512, 9, 3><<<dim3(P.n_sub, nrhs), 512, sm, s>>>(P, setR, G, v);
     }
   }
   // the method must stream each lower-triangle G entry once per launch (4
