@@ -239,7 +239,7 @@ struct bddcso_precond {
   hipEvent_t ev_fork_i = nullptr, ev_join_i = nullptr;
   hipEvent_t ev_cfork = nullptr, ev_cjoin = nullptr;  // coarse solve beside the Neumann solves
   hipEvent_t ev_cpl = nullptr;                         // plane-coupling coefficients ready
-  hipEvent_t ev_la = nullptr, ev_lb = nullptr;   // slab look-ahead of the coarse fronts
+  hipEvent_t ev_la = nullptr, ev_lb = nullptr, ev_lc = nullptr;  // slab look-ahead of the coarse fronts
   double gI_entries = 0, gR_entries = 0;  // G entries streamed by one block solve
   int max_block_I = 0, max_block_R = 0;   // largest diagonal block of each set
   Profiler* P_() { return prof.mask ? &prof : nullptr; }
@@ -552,7 +552,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
     for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
       launch_front_child_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fpool, s);
     const Batch& b = pc->swFront[L];
-    const SweepAux aux{pc->s2, pc->ev_la, pc->ev_lb};
+    const SweepAux aux{pc->s2, pc->ev_la, pc->ev_lb, pc->ev_lc};
     Kern<double>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, pc->fpool, pc->fsw, pc->fsw_stride,
                         pc->status, 4, s, pc->P_(), &aux);
   }
@@ -711,6 +711,7 @@ void bddcso_precond_destroy(bddcso_precond* pc) {
   if (pc->ev_join) (void)hipEventDestroy(pc->ev_join);
   if (pc->ev_la) (void)hipEventDestroy(pc->ev_la);
   if (pc->ev_lb) (void)hipEventDestroy(pc->ev_lb);
+  if (pc->ev_lc) (void)hipEventDestroy(pc->ev_lc);
   if (pc->ev_cpl) (void)hipEventDestroy(pc->ev_cpl);
   if (pc->ev_cfork) (void)hipEventDestroy(pc->ev_cfork);
   if (pc->ev_cjoin) (void)hipEventDestroy(pc->ev_cjoin);
@@ -914,6 +915,7 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     HIPCHK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_la, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_lb, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_lc, hipEventDisableTiming));
   } catch (const PlanFail& f) {
     bddcso_precond_destroy(pc);
     return set_err(BDDCSO_EINVAL, "inconsistent plan: " + f.what);

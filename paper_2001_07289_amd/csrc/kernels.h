@@ -36,7 +36,7 @@ struct Profiler {
 // slab's pivot block is swept on s2 while the current trailing update runs.
 struct SweepAux {
   hipStream_t s2;
-  hipEvent_t a, b;
+  hipEvent_t a, b, c;
 };
 
 // Device views of the plan tables.

@@ -967,6 +967,10 @@ __global__ void k_symmetrize(const SweepDesc* __restrict__ desc, T* pool, int nt
 // Only the lower triangle is read; both triangles are written.
 constexpr int RS_MAX_TILES = 17;  // largest matrix: 272 rows
 constexpr int SLAB = kSlab;       // pivots per slab of the large-matrix sweep
+// Flops of a slab's trailing update below which its pivot-block sweep of the
+// next slab stays on the main stream (about 250 us of update at the 35-37
+// TFLOP/s these updates reach; the sweep takes about 100 us).
+constexpr double kSlabInlineFlops = 9e9;
 
 template <typename T, int MT, int RS_WAVES>
 __global__ __launch_bounds__(RS_WAVES * 64) void k_sweep_reg(const SweepDesc* __restrict__ desc, T* pool,
@@ -3218,42 +3222,63 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
       k_sweep_reg<T, SLAB / 16, 16><<<nprob, 16 * 64, 0, ss>>>(d_desc, pool, status, status_code, j0);
       if (prof) prof->end(4, df, db, ss);
     };
+    // Two orders for a slab with a look-ahead (u1: the next pivot block's
+    // update, u2: the rest of the trailing update, wb: the writeback):
+    //   s: cd u1 u2 wb | s2: reg(next)  when the rest is the longer branch;
+    //   s: cd u1 reg(next) | s2: u2 wb  when the sweep is, so the chain of
+    //   pivot-block sweeps and CD products runs on one stream without
+    //   cross-stream hand-offs, and the sweep is dispatched before u2 fills
+    //   the compute units.
+    // The next slab's CD product waits for the branch on s2.
     reg(0, s);
+    bool prev_inl = false;
     for (int j0 = 0; j0 < maxp; j0 += SLAB) {
       double cf = 0, cb = 0, uf = 0, ub = 0;
-      if (prof && h_desc)
-        for (int q = 0; q < nprob; ++q) {
-          const double n = h_desc[q].n, p = h_desc[q].p;
-          if (j0 >= p) continue;
-          const double sb = std::min<double>(SLAB, p - j0), m = n - sb;
-          const double low = m * (m + 1) / 2;
-          cf += 2.0 * m * sb * sb;
-          cb += sizeof(T) * (2.0 * m * sb + sb * sb);
-          uf += 2.0 * sb * low;
-          ub += sizeof(T) * (2.0 * low + 2.0 * m * sb);
-        }
-      if (aux && j0 > 0) (void)hipStreamWaitEvent(s, aux->b, 0);  // this slab's pivot block is swept
+      for (int q = 0; h_desc && q < nprob; ++q) {
+        const double n = h_desc[q].n, p = h_desc[q].p;
+        if (j0 >= p) continue;
+        const double sb = std::min<double>(SLAB, p - j0), m = n - sb;
+        const double low = m * (m + 1) / 2;
+        cf += 2.0 * m * sb * sb;
+        cb += sizeof(T) * (2.0 * m * sb + sb * sb);
+        uf += 2.0 * sb * low;
+        ub += sizeof(T) * (2.0 * low + 2.0 * m * sb);
+      }
+      if (aux && j0 > 0) (void)hipStreamWaitEvent(s, prev_inl ? aux->c : aux->b, 0);
       if (prof) prof->begin(4, s);
       k_slab_cd<T><<<dim3(cdiv(maxn, TILE), cdiv(SLAB, TILE), nprob), 256, 0, s>>>(d_desc, pool, j0, scratch,
                                                                                   scr_stride);
       if (prof) prof->end(4, cf, cb, s);
       const unsigned ublk = (unsigned)((ntri * nprob + 7) / 8 * 8);
+      const unsigned wgrid = (unsigned)hmin(cdiv((int64_t)maxn * SLAB, 256), 2048);
       const bool next = j0 + SLAB < maxp;
-      if (prof) prof->begin(1, s);
+      prev_inl = false;
       if (next && aux) {
+        const bool inl = h_desc && uf < kSlabInlineFlops;
+        if (prof) prof->begin(1, s);
         k_slab_update<T><<<ublk, 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, (int)ntri, nprob, 1);
+        if (prof) prof->end(1, 0.0, 0.0, s);
         (void)hipEventRecord(aux->a, s);
         (void)hipStreamWaitEvent(aux->s2, aux->a, 0);
-        reg(j0 + SLAB, aux->s2);
-        (void)hipEventRecord(aux->b, aux->s2);
-        k_slab_update<T><<<ublk, 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, (int)ntri, nprob, 2);
+        hipStream_t su = inl ? aux->s2 : s;
+        if (inl) reg(j0 + SLAB, s);
+        else {
+          reg(j0 + SLAB, aux->s2);
+          (void)hipEventRecord(aux->b, aux->s2);
+        }
+        if (prof) prof->begin(1, su);
+        k_slab_update<T><<<ublk, 256, 0, su>>>(d_desc, pool, j0, scratch, scr_stride, (int)ntri, nprob, 2);
+        if (prof) prof->end(1, uf, ub, su);
+        k_slab_writeback<T><<<dim3(wgrid, nprob), 256, 0, su>>>(d_desc, pool, j0, scratch, scr_stride);
+        if (inl) (void)hipEventRecord(aux->c, aux->s2);
+        prev_inl = inl;
       } else {
+        if (prof) prof->begin(1, s);
         k_slab_update<T><<<ublk, 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, (int)ntri, nprob, 0);
+        if (prof) prof->end(1, uf, ub, s);
+        k_slab_writeback<T><<<dim3(wgrid, nprob), 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride);
+        if (next) reg(j0 + SLAB, s);
       }
-      if (prof) prof->end(1, uf, ub, s);
-      k_slab_writeback<T><<<dim3((unsigned)hmin(cdiv((int64_t)maxn * SLAB, 256), 2048), nprob), 256, 0, s>>>(
-          d_desc, pool, j0, scratch, scr_stride);
-      if (next && !aux) reg(j0 + SLAB, s);
     }
     const int64_t st = cdiv(maxn, 32);
     k_symmetrize<T><<<dim3((unsigned)hmin(st * (st + 1) / 2, 4096), nprob), 256, 0, s>>>(d_desc, pool, 0);
