@@ -921,14 +921,17 @@ __global__ __launch_bounds__(256) void k_sweep_update(const SweepDesc* __restric
       }
 }
 
-// Mirrors the lower triangle into the upper one after a sweep, by 32x32
-// tiles through LDS so both the read and the write run along columns.
+// Mirrors the lower triangle of the pivot block (the leading p x p) into its
+// upper one after a sweep, by 32x32 tiles through LDS so both the read and
+// the write run along columns.  Outside the pivot block only the lower
+// triangle is kept: a front's border rows and update block are read there
+// (the products with -F_PP^{-1} read whole pivot columns).
 template <typename T>
 __global__ void k_symmetrize(const SweepDesc* __restrict__ desc, T* pool, int ntri) {
   __shared__ T tile[32][33];
   const SweepDesc d = desc[blockIdx.y];
   T* A = pool + d.off;
-  const int nt = (d.n + 31) / 32;
+  const int nt = (d.p + 31) / 32;
   for (int lin = blockIdx.x; lin < nt * (nt + 1) / 2; lin += gridDim.x) {
     int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= lin) ++ti;
@@ -938,13 +941,13 @@ __global__ void k_symmetrize(const SweepDesc* __restrict__ desc, T* pool, int nt
     for (int idx = threadIdx.x; idx < 32 * 32; idx += blockDim.x) {
       const int r = idx % 32, c = idx / 32;
       const int i = ti * 32 + r, j = tj * 32 + c;
-      tile[c][r] = (i < d.n && j < d.n) ? A[i + (int64_t)d.ld * j] : (T)0;
+      tile[c][r] = (i < d.p && j < d.p) ? A[i + (int64_t)d.ld * j] : (T)0;
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < 32 * 32; idx += blockDim.x) {
       const int r = idx % 32, c = idx / 32;   // upper entry (tj*32 + r, ti*32 + c) = lower (ti*32 + c, tj*32 + r)
       const int i = tj * 32 + r, j = ti * 32 + c;
-      if (i < d.n && j < d.n && i < j) A[i + (int64_t)d.ld * j] = tile[r][c];
+      if (i < d.p && j < d.p && i < j) A[i + (int64_t)d.ld * j] = tile[r][c];
     }
   }
   (void)ntri;
@@ -2001,9 +2004,12 @@ __global__ void k_front_child_scatter(PlanDev P, const int32_t* __restrict__ chi
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // fronts stay far below 46340 rows
   if (idx >= nb * nb) return;
   const int a = idx % nb, b = idx / nb;
+  // the child's update block is symmetric and only its lower triangle is
+  // kept; each of its lower entries goes to the parent's lower triangle
+  // (the position map is one-to-one, so every parent entry is hit once)
+  if (a < b) return;
   const int pa = P.front_pmap[C.pmap_off + a], pb = P.front_pmap[C.pmap_off + b];
-  if (pa < pb) return;  // lower triangle of the parent; the child's update block is symmetric
-  fpool[F.off + pa + (int64_t)F.n * pb] += fpool[C.off + (C.p + a) + (int64_t)C.n * (C.p + b)];
+  fpool[F.off + max(pa, pb) + (int64_t)F.n * min(pa, pb)] += fpool[C.off + (C.p + a) + (int64_t)C.n * (C.p + b)];
 }
 
 // ---------------------------------------------------------------------------
@@ -3280,7 +3286,7 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
         if (next) reg(j0 + SLAB, s);
       }
     }
-    const int64_t st = cdiv(maxn, 32);
+    const int64_t st = cdiv(maxp, 32);
     k_symmetrize<T><<<dim3((unsigned)hmin(st * (st + 1) / 2, 4096), nprob), 256, 0, s>>>(d_desc, pool, 0);
     return;
   }
@@ -3312,7 +3318,7 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
     prev = j0;
   }
   k_sweep_panel<T><<<pgrid, 256, psm, s>>>(d_desc, pool, -1, prev, scratch, scr_stride, status, status_code);
-  const int64_t st = cdiv(maxn, 32);
+  const int64_t st = cdiv(maxp, 32);
   k_symmetrize<T><<<dim3((unsigned)hmin(st * (st + 1) / 2, 4096), nprob), 256, 0, s>>>(d_desc, pool, 0);
 }
 
