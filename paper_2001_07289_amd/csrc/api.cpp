@@ -212,7 +212,9 @@ struct bddcso_precond {
   int64_t fsw_stride = 0;
   int32_t* status = nullptr;
   // batches
-  std::vector<Batch> swI, swR, gfwd, gbwd;
+  std::vector<Batch> swI, swR;
+  std::vector<Batch> gfwd[2], gbwd[2];  // block GEMMs of the basis solves, per half of the subdomains
+  int zsplit = 0;                       // first subdomain of the second half
   Batch swSc, gLam, gSel;
   std::vector<Batch> swFront;                       // per level
   std::vector<int32_t*> color_dev;                  // per colour
@@ -240,6 +242,7 @@ struct bddcso_precond {
   hipEvent_t ev_cfork = nullptr, ev_cjoin = nullptr;  // coarse solve beside the Neumann solves
   hipEvent_t ev_cpl = nullptr;                         // plane-coupling coefficients ready
   hipEvent_t ev_la = nullptr, ev_lb = nullptr, ev_lc = nullptr;  // slab look-ahead of the coarse fronts
+  hipEvent_t ev_zf = nullptr, ev_zj = nullptr;  // fork and join of the two halves of the basis solves
   double gI_entries = 0, gR_entries = 0;  // G entries streamed by one block solve
   int max_block_I = 0, max_block_R = 0;   // largest diagonal block of each set
   Profiler* P_() { return prof.mask ? &prof : nullptr; }
@@ -365,9 +368,10 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       vec.push_back(make_sweep_batch(m, d, s));
     }
   }
-  for (int k = 0; k < pl.max_nbR; ++k) {
+  pc->zsplit = ns / 2;
+  for (int k = 0; k < pl.max_nbR; ++k) for (int h = 0; h < 2; ++h) {
     std::vector<GemmDesc> f, b;
-    for (int sidx = 0; sidx < ns; ++sidx) {
+    for (int sidx = h ? pc->zsplit : 0; sidx < (h ? ns : pc->zsplit); ++sidx) {
       const SubDev& S = pl.subs[sidx];
       int ncols = S.n_a + S.n_v;
       if (k >= S.nbR || ncols == 0) continue;
@@ -382,8 +386,8 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
     }
     check_gemms(f, pl.pool_G, tmp_stride * ns, pl.pool_Z, "forward block GEMM");
     check_gemms(b, pl.pool_G, tmp_stride * ns, pl.pool_Z, "backward block GEMM");
-    pc->gfwd.push_back(make_gemm_batch(m, f, s));
-    pc->gbwd.push_back(make_gemm_batch(m, b, s));
+    pc->gfwd[h].push_back(make_gemm_batch(m, f, s));
+    pc->gbwd[h].push_back(make_gemm_batch(m, b, s));
   }
   {
     std::vector<SweepDesc> d;
@@ -507,19 +511,38 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   if (sizeof(T) == 8) launch_fill_f64((double*)N.Z, pl.pool_Z, 0.0, s);
   else launch_fill_f32((float*)N.Z, pl.pool_Z, 0.0f, s);
   Kern<T>::rhs_fill(P, g, rho, N.Z, s);
-  const int nk = (int)pc->gfwd.size();
-  for (int k = 0; k < nk; ++k) {
-    Kern<T>::couple_multi(P, g, rho, k, 1, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
-    const Batch& b = pc->gfwd[k];
-    Kern<T>::gemm((GemmDesc*)b.desc, b.hg.data(), b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)-1, (T)0, s,
-                  pc->P_());
+  // Two halves of the subdomains, each a chain of coupling products (HBM)
+  // and block GEMMs (MFMA) on its own stream.  The second half starts one
+  // coupling product later, so one half's GEMMs run beside the other's
+  // coupling products.
+  const int nk = (int)pc->gfwd[0].size();
+  auto zchain = [&](int h, hipStream_t ss) {
+    const int sub0 = h ? pc->zsplit : 0, nsub = h ? (int)pl.subs.size() - pc->zsplit : pc->zsplit;
+    for (int k = 0; k < nk; ++k) {
+      Kern<T>::couple_multi(P, g, rho, k, 1, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, ss, sub0, nsub);
+      if (k == 0 && h == 0) {
+        HIPCHK(hipEventRecord(pc->ev_zf, ss));
+        HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_zf, 0));
+      }
+      const Batch& b = pc->gfwd[h][k];
+      Kern<T>::gemm((GemmDesc*)b.desc, b.hg.data(), b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)-1, (T)0, ss,
+                    pc->P_());
+    }
+    for (int k = nk - 2; k >= 0; --k) {
+      Kern<T>::couple_multi(P, g, rho, k, 0, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, ss, sub0, nsub);
+      const Batch& b = pc->gbwd[h][k];
+      Kern<T>::gemm((GemmDesc*)b.desc, b.hg.data(), b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)1, (T)1, ss,
+                    pc->P_());
+    }
+  };
+  zchain(0, s);
+  if (nk == 0) {
+    HIPCHK(hipEventRecord(pc->ev_zf, s));
+    HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_zf, 0));
   }
-  for (int k = nk - 2; k >= 0; --k) {
-    Kern<T>::couple_multi(P, g, rho, k, 0, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, s);
-    const Batch& b = pc->gbwd[k];
-    Kern<T>::gemm((GemmDesc*)b.desc, b.hg.data(), b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)1, (T)1, s,
-                  pc->P_());
-  }
+  zchain(1, pc->s2);
+  HIPCHK(hipEventRecord(pc->ev_zj, pc->s2));
+  HIPCHK(hipStreamWaitEvent(s, pc->ev_zj, 0));
   // constraint Schur complement and the coarse basis
   Kern<T>::sc_assemble(P, N.Z, N.Sc, s);
   Kern<T>::sweep((SweepDesc*)pc->swSc.desc, pc->swSc.hs.data(), pc->swSc.n, pc->swSc.maxn, pc->swSc.maxp, N.Sc,
@@ -712,6 +735,8 @@ void bddcso_precond_destroy(bddcso_precond* pc) {
   if (pc->ev_la) (void)hipEventDestroy(pc->ev_la);
   if (pc->ev_lb) (void)hipEventDestroy(pc->ev_lb);
   if (pc->ev_lc) (void)hipEventDestroy(pc->ev_lc);
+  if (pc->ev_zf) (void)hipEventDestroy(pc->ev_zf);
+  if (pc->ev_zj) (void)hipEventDestroy(pc->ev_zj);
   if (pc->ev_cpl) (void)hipEventDestroy(pc->ev_cpl);
   if (pc->ev_cfork) (void)hipEventDestroy(pc->ev_cfork);
   if (pc->ev_cjoin) (void)hipEventDestroy(pc->ev_cjoin);
@@ -916,6 +941,8 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     HIPCHK(hipEventCreateWithFlags(&pc->ev_la, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_lb, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&pc->ev_lc, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_zf, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pc->ev_zj, hipEventDisableTiming));
   } catch (const PlanFail& f) {
     bddcso_precond_destroy(pc);
     return set_err(BDDCSO_EINVAL, "inconsistent plan: " + f.what);

@@ -92,7 +92,7 @@ struct Kern {
                    Profiler* prof);
   static void rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, hipStream_t s);
   static void couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
-                           int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s);
+                           int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s, int sub0, int nsub);
   static void sc_assemble(const PlanDev& P, const T* Z, T* Sc, hipStream_t s);
   static void lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s);
   // rows of [X | Phi initialised to Y'] at the selected rows

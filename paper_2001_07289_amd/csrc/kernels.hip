@@ -1657,17 +1657,17 @@ __global__ void k_rhs_fill(PlanDev P, Geo g, const double* __restrict__ rho, T* 
 
 // fwd (fwd = 1): tmp = Z[block k, :] - A_{k,k-1} Z[last plane of k-1, :]
 // bwd (fwd = 0): tmp[0:last_n, :] = A_{k,k+1} Z[first plane of k+1, :]
-// One workgroup per (column chunk of CPL_COLS, subdomain): the source plane's
+// One workgroup per (column chunk of CPL_COLS, subdomain sub0 + blockIdx.y): the source plane's
 // rows of the chunk are staged in LDS once, then every output row takes its
 // (up to) 9 neighbours from LDS.
 constexpr int CPL_COLS = 16;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd, T* __restrict__ Z,
-                                                      T* __restrict__ tmp, int64_t tmp_stride) {
+                                                      T* __restrict__ tmp, int64_t tmp_stride, int sub0) {
   extern __shared__ char smem_raw[];
   T(*src)[CPL_COLS + 1] = reinterpret_cast<T(*)[CPL_COLS + 1]>(smem_raw);
-  const int sub = blockIdx.y;
+  const int sub = sub0 + blockIdx.y;
   const SubDev S = P.subs[sub];
   const int nb = S.nbR;
   const int ncols = S.n_a + S.n_v;
@@ -3356,12 +3356,12 @@ void Kern<T>::rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, 
 
 template <typename T>
 void Kern<T>::couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
-                           int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s) {
+                           int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s, int sub0, int nsub) {
   (void)g;
   (void)rho;
-  if (ncols_max == 0) return;
+  if (ncols_max == 0 || nsub <= 0) return;
   const size_t sm = (size_t)hmax(P.max_plane, 1) * (CPL_COLS + 1) * sizeof(T);
-  k_couple_multi<T><<<dim3(cdiv(ncols_max, CPL_COLS), P.n_sub), 256, sm, s>>>(P, k, fwd, Z, tmp, tmp_stride);
+  k_couple_multi<T><<<dim3(cdiv(ncols_max, CPL_COLS), nsub), 256, sm, s>>>(P, k, fwd, Z, tmp, tmp_stride, sub0);
 }
 
 template <typename T>
