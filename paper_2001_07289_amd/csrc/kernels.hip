@@ -1995,21 +1995,37 @@ __global__ __launch_bounds__(256) void k_front_zero_lower(PlanDev P, const int32
     for (int i = j + threadIdx.x; i < F.n; i += 256) M[i + (int64_t)F.n * j] = 0.0;
 }
 
-__global__ void k_front_child_scatter(PlanDev P, const int32_t* __restrict__ children,
-                                      double* __restrict__ fpool) {
+// Extend-add of a child's update block into its parent: one wave per column
+// b of the child's border, lanes down the rows a >= b (the lower triangle,
+// read along columns).  Each lower entry goes once to the parent's lower
+// triangle; the plan orders a child's border as its parent does, so rows
+// stay in increasing order there too.  Four entries are read before any is
+// added (child and parent fronts never overlap).
+__global__ __launch_bounds__(256) void k_front_child_scatter(PlanDev P, const int32_t* __restrict__ children,
+                                                             double* __restrict__ fpool) {
   const int ch = children[blockIdx.y];
   const FrontDev C = P.fronts[ch];
   const FrontDev F = P.fronts[C.parent];
   const int nb = C.n - C.p;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // fronts stay far below 46340 rows
-  if (idx >= nb * nb) return;
-  const int a = idx % nb, b = idx / nb;
-  // the child's update block is symmetric and only its lower triangle is
-  // kept; each of its lower entries goes to the parent's lower triangle
-  // (the position map is one-to-one, so every parent entry is hit once)
-  if (a < b) return;
-  const int pa = P.front_pmap[C.pmap_off + a], pb = P.front_pmap[C.pmap_off + b];
-  fpool[F.off + max(pa, pb) + (int64_t)F.n * min(pa, pb)] += fpool[C.off + (C.p + a) + (int64_t)C.n * (C.p + b)];
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (b >= nb) return;
+  const int32_t* __restrict__ pm = P.front_pmap + C.pmap_off;
+  const int pb = pm[b];
+  const double* __restrict__ src = fpool + C.off + (int64_t)C.n * (C.p + b) + C.p;
+  double* __restrict__ dst = fpool + F.off;
+  for (int a0 = b; a0 < nb; a0 += 256) {
+    double v[4];
+    int pa[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = a0 + 64 * u + lane;
+      pa[u] = a < nb ? pm[a] : -1;
+      v[u] = a < nb ? src[a] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (pa[u] >= 0) dst[max(pa[u], pb) + (int64_t)F.n * min(pa[u], pb)] += v[u];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -3527,7 +3543,7 @@ void launch_front_zero_lower(const PlanDev& P, const int32_t* fronts, int nfr, i
 void launch_front_child_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
                                 double* fpool, hipStream_t s) {
   if (nchild == 0 || maxn == 0) return;
-  k_front_child_scatter<<<dim3(cdiv((int64_t)maxn * maxn, 256), nchild), 256, 0, s>>>(P, children, fpool);
+  k_front_child_scatter<<<dim3(cdiv(maxn, 4), nchild), 256, 0, s>>>(P, children, fpool);
 }
 void launch_front_vec_init(const PlanDev& P, const int32_t* fr, int nfr, int maxn, const double* bc,
                            double* fvec, int64_t stride, int nrhs, hipStream_t s) {

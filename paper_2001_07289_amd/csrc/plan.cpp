@@ -714,6 +714,17 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     off += (int64_t)F.n * F.n;
     voff += F.n;
     ioff += F.n;
+    if (N.parent >= 0) {
+      // the border in the parent's order (parents precede their children
+      // here): the extend-add then takes the child's update block lower
+      // triangle to the parent's lower triangle, rows in increasing order
+      const auto& pp = pos_of[N.parent];
+      auto key = [&](int32_t d) {
+        auto it = pp.find(d);
+        return it == pp.end() ? INT32_MAX : it->second;  // not nested: reported below
+      };
+      std::stable_sort(N.B.begin(), N.B.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
+    }
     for (int32_t d : N.P) plan.front_idx.push_back(d);
     for (int32_t d : N.B) plan.front_idx.push_back(d);
     for (int k = 0; k < F.n; ++k) pos_of[t][plan.front_idx[F.idx_off + k]] = k;
