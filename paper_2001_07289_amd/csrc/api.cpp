@@ -560,20 +560,27 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   // is applied, so they are built on a third stream while the coarse
   // factorization runs (its upper levels occupy few compute units); the
   // caller's stream waits for them at the end.
-  // The fronts' lower triangles are zeroed first (they are summed into);
-  // alone on the GPU this streaming pass is short, while beside the factor
-  // chains it slows their latency-bound sweeps.
-  launch_front_zero_lower(P, pc->all_fronts, pc->all_n, pc->all_maxn, pc->fpool, s);
+  // Scatter plans: the fronts' lower triangles are zeroed first (they are
+  // summed into); alone on the GPU this streaming pass is short, while
+  // beside the factor chains it slows their latency-bound sweeps.
+  if (!pl.front_gather) launch_front_zero_lower(P, pc->all_fronts, pc->all_n, pc->all_maxn, pc->fpool, s);
   HIPCHK(hipEventRecord(pc->ev_fork_i, s));
   HIPCHK(hipStreamWaitEvent(pc->s3, pc->ev_fork_i, 0));
   factor_chain(0, pc->s3);
   HIPCHK(hipEventRecord(pc->ev_join_i, pc->s3));
-  // coarse: assemble into the fronts and factor level by level (FP64)
-  for (size_t c = 0; c < pc->color_dev.size(); ++c)
-    Kern<T>::kc_to_front(P, pc->color_dev[c], pc->color_n[c], N.Kc, pc->fpool, s);
+  // coarse: assemble into the fronts and factor level by level (FP64).
+  // Fronts with at most two sources gather them (each entry written once);
+  // otherwise the local coarse matrices are added by colour classes and the
+  // children's update blocks in slot order.
+  if (!pl.front_gather)
+    for (size_t c = 0; c < pc->color_dev.size(); ++c)
+      Kern<T>::kc_to_front(P, pc->color_dev[c], pc->color_n[c], N.Kc, pc->fpool, s);
   for (size_t L = 0; L < pc->swFront.size(); ++L) {
-    for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
-      launch_front_child_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fpool, s);
+    if (pl.front_gather)
+      Kern<T>::front_gather(P, pc->level_dev[L], pc->level_n[L], pc->level_maxn[L], N.Kc, pc->fpool, s);
+    else
+      for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
+        launch_front_child_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fpool, s);
     const Batch& b = pc->swFront[L];
     const SweepAux aux{pc->s2, pc->ev_la, pc->ev_lb, pc->ev_lc};
     Kern<double>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, pc->fpool, pc->fsw, pc->fsw_stride,
@@ -853,6 +860,7 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     P.fronts = m.upload(pl.fronts, s);
     P.front_idx = m.upload(pl.front_idx, s);
     P.front_pmap = m.upload(pl.front_pmap, s);
+    P.front_imap = pl.front_imap.empty() ? nullptr : m.upload(pl.front_imap, s);
     P.sub_fmap = m.upload(pl.sub_fmap, s);
     P.cpl_rank = m.upload(pl.cpl_rank, s);
     P.cpl_sub = m.upload(pl.cpl_sub, s);

@@ -55,7 +55,7 @@ struct PlanDev {
   const int32_t *gam_kptr, *gam_key, *ss_parent, *ss_eptr, *ss_elem;
   const int32_t *crs_eptr, *crs_ent;
   const FrontDev* fronts;
-  const int32_t *front_idx, *front_pmap, *sub_fmap;
+  const int32_t *front_idx, *front_pmap, *sub_fmap, *front_imap;
   const double* khat;  // 8x8 unit-coefficient element matrix (2D replicated over the z bit)
   const int32_t *cpl_rank, *cpl_sub, *cpl_loc, *cpl_dir;
   const double* cpl_coef;  // 9 coefficients per coupling row (filled at setup)
@@ -102,6 +102,9 @@ struct Kern {
                           const T* Lam, T* Kc, double* vcoef, int32_t* vcode, int max_nv, hipStream_t s);
   static void kc_to_front(const PlanDev& P, const int32_t* subs_of_color, int ns, const T* Kc,
                           double* fpool, hipStream_t s);
+  // every front of a level assembled from its sources (gather plans only)
+  static void front_gather(const PlanDev& P, const int32_t* fr, int nfr, int maxn, const T* Kc, double* fpool,
+                           hipStream_t s);
   // per-iteration
   static void gather_I(const PlanDev& P, const Geo& g, const double* r, T* vI, int nrhs, hipStream_t s);
   static void block_solve(const PlanDev& P, const Geo& g, const double* rho, int setR, const T* G,

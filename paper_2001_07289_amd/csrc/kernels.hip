@@ -1995,6 +1995,69 @@ __global__ __launch_bounds__(256) void k_front_zero_lower(PlanDev P, const int32
     for (int i = j + threadIdx.x; i < F.n; i += 256) M[i + (int64_t)F.n * j] = 0.0;
 }
 
+// Assembly of a front's lower triangle from its sources, each entry written
+// once (no zeroing pass, no read-modify-write, no atomics): the update
+// blocks of its children (swept at the level below) and the local coarse
+// matrices of the subdomains it splits off, summed in source order.  One
+// wave per column j, lanes down the rows i >= j, four rows in flight.
+template <typename T>
+__global__ __launch_bounds__(256) void k_front_gather(PlanDev P, const int32_t* __restrict__ fr,
+                                                      const T* __restrict__ Kc, double* __restrict__ fpool) {
+  const FrontDev F = P.fronts[fr[blockIdx.y]];
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= F.n) return;
+  const int ns = F.nsrc;
+  const int32_t* mp[2];
+  const double* cb[2];  // a child's update block (lower triangle, leading dimension ld)
+  const T* kb[2];       // a subdomain's local coarse matrix (full, symmetric)
+  int mj[2], ld[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    mp[q] = nullptr;
+    cb[q] = nullptr;
+    kb[q] = nullptr;
+    mj[q] = -1;
+    ld[q] = 0;
+    if (q >= ns) continue;
+    mp[q] = P.front_imap + F.src_map[q];
+    mj[q] = mp[q][j];
+    if (F.src[q] >= 0) {
+      const FrontDev C = P.fronts[F.src[q]];
+      cb[q] = fpool + C.off + C.p + (int64_t)C.n * C.p;
+      ld[q] = C.n;
+    } else {
+      const SubDev& S = P.subs[-F.src[q] - 1];
+      kb[q] = Kc + S.Kc_off;
+      ld[q] = S.n_c;
+    }
+  }
+  double* __restrict__ dst = fpool + F.off + (int64_t)F.n * j;
+  for (int i0 = j; i0 < F.n; i0 += 256) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u + lane;
+      double acc = 0.0;
+      if (i < F.n) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (mj[q] < 0) continue;
+          const int mi = mp[q][i];
+          if (mi < 0) continue;
+          const int hi = max(mi, mj[q]), lo = min(mi, mj[q]);
+          acc += cb[q] ? cb[q][hi + (int64_t)ld[q] * lo] : (double)kb[q][hi + (int64_t)ld[q] * lo];
+        }
+      }
+      v[u] = acc;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u + lane;
+      if (i < F.n) dst[i] = v[u];
+    }
+  }
+}
+
 // Extend-add of a child's update block into its parent: one wave per column
 // b of the child's border, lanes down the rows a >= b (the lower triangle,
 // read along columns).  Each lower entry goes once to the parent's lower
@@ -3424,6 +3487,13 @@ void Kern<T>::kc_to_front(const PlanDev& P, const int32_t* subs_c, int ns, const
                           hipStream_t s) {
   if (ns == 0 || P.max_nc == 0) return;
   k_kc_to_front<T><<<dim3(cdiv((int64_t)P.max_nc * P.max_nc, 256), ns), 256, 0, s>>>(P, subs_c, Kc, fpool);
+}
+
+template <typename T>
+void Kern<T>::front_gather(const PlanDev& P, const int32_t* fr, int nfr, int maxn, const T* Kc, double* fpool,
+                           hipStream_t s) {
+  if (nfr == 0 || maxn == 0) return;
+  k_front_gather<T><<<dim3(cdiv(maxn, 4), nfr), 256, 0, s>>>(P, fr, Kc, fpool);
 }
 
 template <typename T>

@@ -754,6 +754,44 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
       plan.sub_fmap[S.c_off + k] = it->second;
     }
   }
+  // gather assembly: a front's sources are its children and the subdomains
+  // it splits off, each with a map from the front's positions to the
+  // source's (child border position, or local coarse index; -1: none)
+  plan.front_gather = true;
+  for (int t = 0; t < nfr; ++t) {
+    FrontDev& F = plan.fronts[t];
+    const auto& N = nd.nodes[t];
+    std::vector<int> src(N.kids.begin(), N.kids.end());
+    for (int s : N.leaves) src.push_back(-(s + 1));
+    F.nsrc = (int)src.size();
+    F.src[0] = F.src[1] = 0;
+    F.src_map[0] = F.src_map[1] = 0;
+    if (src.size() > 2) {
+      plan.front_gather = false;
+      continue;
+    }
+    for (size_t q = 0; q < src.size(); ++q) {
+      F.src[q] = src[q];
+      F.src_map[q] = (int64_t)plan.front_imap.size();
+      if (src[q] >= 0) {
+        const FrontDev& C = plan.fronts[src[q]];
+        for (int i = 0; i < F.n; ++i) {
+          auto it = pos_of[src[q]].find(plan.front_idx[F.idx_off + i]);
+          plan.front_imap.push_back(it != pos_of[src[q]].end() && it->second >= C.p ? it->second - C.p : -1);
+        }
+      } else {
+        const SubDev& S = plan.subs[-src[q] - 1];
+        std::unordered_map<int32_t, int32_t> loc;
+        for (int k = 0; k < S.n_c; ++k) loc[plan.c_glob[S.c_off + k]] = k;
+        for (int i = 0; i < F.n; ++i) {
+          auto it = loc.find(plan.front_idx[F.idx_off + i]);
+          plan.front_imap.push_back(it != loc.end() ? it->second : -1);
+        }
+      }
+    }
+  }
+  if (!plan.front_gather)
+    for (auto& F : plan.fronts) F.nsrc = -1;
   plan.front_pool = off;
   plan.front_vec = voff;
   plan.front_idx_total = ioff;

@@ -83,6 +83,8 @@ struct Plan {
   std::vector<FrontDev> fronts;
   std::vector<int32_t> front_idx;             // coarse ids of front positions
   std::vector<int32_t> front_pmap;            // positions p..n-1 -> parent positions
+  std::vector<int32_t> front_imap;            // gather maps (FrontDev::src_map)
+  bool front_gather = true;                   // every front has at most 2 sources
   std::vector<int32_t> sub_fmap;              // local coarse entry -> position in its front
   std::vector<std::vector<int32_t>> level_fronts;       // fronts per level (bottom-up)
   std::vector<std::vector<std::vector<int32_t>>> level_slot_children; // [level][slot] children

@@ -61,6 +61,9 @@ struct FrontDev {
   int n, p;
   int parent;         // -1 at a root
   int level;
+  int nsrc;           // sources of the gather assembly (at most 2; -1: assembled by scatter)
+  int src[2];         // a child front, or -(s + 1) for the local coarse matrix of subdomain s
+  int64_t src_map[2]; // offset in front_imap: per position of this front, the source's index, -1 if none
 };
 
 // Batched dense sweep descriptor.
