@@ -184,11 +184,12 @@ namespace {
 template <typename T>
 struct Numeric {
   T *G = nullptr, *Z = nullptr, *XG = nullptr, *Sc = nullptr, *Tm = nullptr, *Lam = nullptr,
-    *PhiG = nullptr, *Kc = nullptr;
+    *PhiG = nullptr, *YG = nullptr, *Kc = nullptr;
   T *W = nullptr, *W2 = nullptr, *tmp = nullptr, *sw = nullptr, *sw2 = nullptr;
   int64_t wstride = 0, tmp_stride = 0, sw_stride = 0;
   // per-iteration
   T *vI = nullptr, *vR = nullptr, *q = nullptr, *gv = nullptr, *v2 = nullptr, *mu = nullptr, *bci = nullptr;
+  T* lu = nullptr;  // Lambda u_c per subdomain (averages), from the coarse solve
 };
 
 }  // namespace
@@ -325,6 +326,7 @@ void alloc_numeric(bddcso_precond* pc, hipStream_t s) {
   N.Tm = m.alloc<T>(pl.pool_T);
   N.Lam = m.alloc<T>(pl.pool_T);
   N.PhiG = m.alloc<T>(pl.pool_PhiG);
+  N.YG = m.alloc<T>(pl.pool_YG);
   N.Kc = m.alloc<T>(pl.pool_Kc);
   int max_plane = pc->P.max_plane;
   N.wstride = (int64_t)max_plane * max_plane;
@@ -342,6 +344,7 @@ void alloc_numeric(bddcso_precond* pc, hipStream_t s) {
   N.gv = m.alloc<T>(pl.tot_g * nr);
   N.v2 = m.alloc<T>(pl.tot_g * nr);
   N.mu = m.alloc<T>(pl.tot_a * nr);
+  N.lu = m.alloc<T>(pl.tot_a * nr);
   N.bci = m.alloc<T>(pl.tot_c * nr);
   (void)s;
 }
@@ -555,6 +558,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   Kern<T>::gemm((GemmDesc*)pc->gSel.desc, pc->gSel.hg.data(), pc->gSel.n, pc->gSel.maxm, pc->gSel.maxn, N.XG, 0,
                 N.Lam, 0, N.PhiG, (T)-1, (T)0, s, pc->P_());
   Kern<T>::phi_add(P, N.Z, N.PhiG, pc->max_nv, s);
+  Kern<T>::yg_gather(P, N.Z, N.YG, pc->max_nv, s);
   Kern<T>::kc_identity(P, g, rho, N.PhiG, N.Lam, N.Kc, pc->vcoef, pc->vcode, pc->max_nv, s);
   // The interior (Dirichlet) factors are needed only when the preconditioner
   // is applied, so they are built on a third stream while the coarse
@@ -638,10 +642,11 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   if (sizeof(T) == 8) launch_coarse_rhs_gather(P, (const double*)N.bci, nullptr, pc->bc, nrhs, pc->s2);
   else launch_coarse_rhs_gather(P, nullptr, (const float*)N.bci, pc->bc, nrhs, pc->s2);
   coarse_solve(pc, nrhs, pc->s2);
+  Kern<T>::lam_uc(P, N.Lam, pc->uc, N.lu, nrhs, pc->s2);
   HIPCHK(hipEventRecord(pc->ev_cjoin, pc->s2));
   HIPCHK(hipStreamWaitEvent(s, pc->ev_cjoin, 0));
   // 7-8: v2 on Gamma and E
-  Kern<T>::v2(P, N.vR, N.XG, N.mu, N.PhiG, pc->uc, N.v2, nrhs, s);
+  Kern<T>::v2(P, N.vR, N.XG, N.mu, N.lu, N.YG, pc->uc, N.v2, nrhs, s);
   if (sizeof(T) == 8) launch_gamma_w(P, g, (const double*)N.v2, nullptr, pc->delta, z, nrhs, s);
   else launch_gamma_w(P, g, nullptr, (const float*)N.v2, pc->delta, z, nrhs, s);
   // 9-10: harmonic extension into the interiors
@@ -1173,10 +1178,10 @@ bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bd
   const double ns = (double)pl.subs.size();
   int max_plane = 0;
   for (auto& B : pl.blocks) max_plane = std::max(max_plane, std::max(B.first_n, B.last_n));
-  double tpool = pl.pool_G + pl.pool_Z + pl.pool_XG + pl.pool_Sc + 2.0 * pl.pool_T + pl.pool_PhiG +
+  double tpool = pl.pool_G + pl.pool_Z + pl.pool_XG + pl.pool_Sc + 2.0 * pl.pool_T + pl.pool_PhiG + pl.pool_YG +
                  pl.pool_Kc + ns * ((double)max_plane * max_plane + (double)pl.max_block * std::max(pl.max_zcols, 1) +
                                     2.0 * std::max(2.0 * ((double)std::max(pl.max_block, pl.max_na) * kSweepNB + kSweepNB * kSweepNB), (double)std::max(pl.max_block, pl.max_na) * kSlab)) +
-                 nr * (pl.tot_I + pl.tot_r + 3.0 * pl.tot_g + pl.tot_a + pl.tot_c);
+                 nr * (pl.tot_I + pl.tot_r + 3.0 * pl.tot_g + 2.0 * pl.tot_a + pl.tot_c);
   double dpool = (double)pl.front_pool + 2.0 * nr * pl.front_vec + 2.0 * nr * pl.n_coarse +
                  9.0 * pl.cpl_sub.size() + 6.0 * nr * p->c.n_free + p->c.n_elem + pl.tot_g;
   out->device_bytes = ts * tpool + 8.0 * dpool;

@@ -118,8 +118,14 @@ struct Kern {
   static void mu(const PlanDev& P, const T* vR, const T* Sc, T* mu_out, int nrhs, hipStream_t s);
   static void coarse_rhs_local(const PlanDev& P, const T* PhiG, const T* gv, T* bci, int nrhs,
                                hipStream_t s);
-  static void v2(const PlanDev& P, const T* vR, const T* XG, const T* mu_in, const T* PhiG,
+  // v2 on Gamma = u - X_Gamma (mu + Lambda u_c) + Y'_Gamma u_c (equal to
+  // u - X_Gamma mu + Phi_Gamma u_c, as Phi = Y' - X Lambda)
+  static void v2(const PlanDev& P, const T* vR, const T* XG, const T* mu_in, const T* lu, const T* YG,
                  const double* uc, T* v2_out, int nrhs, hipStream_t s);
+  // lu = Lambda u_c per subdomain (the local coarse values of u_c)
+  static void lam_uc(const PlanDev& P, const T* Lam, const double* uc, T* lu, int nrhs, hipStream_t s);
+  // Y' at the Gamma entries, from [X | Y']
+  static void yg_gather(const PlanDev& P, const T* Z, T* YG, int max_nv, hipStream_t s);
   static void interior_rhs(const PlanDev& P, const Geo& g, const double* rho, const double* r,
                            const double* w, T* vI, int nrhs, hipStream_t s);
   static void scatter_I(const PlanDev& P, const Geo& g, const T* vI, double* z, int nrhs, hipStream_t s);

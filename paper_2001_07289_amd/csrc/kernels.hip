@@ -2623,12 +2623,16 @@ __global__ __launch_bounds__(256) void k_coarse_rhs_local(PlanDev P, const T* __
   }
 }
 
-// v2 on Gamma = u - X mu + Phi_Gamma u_c (v_Delta plus the coarse
-// correction): one workgroup per (chunk of 256 Gamma rows, subdomain, rhs).
+// v2 on Gamma = v_Delta plus the coarse correction, u - X mu + Phi_Gamma u_c.
+// With Phi = Y' - X Lambda this is u - X (mu + Lambda u_c) + Y' u_c, where
+// Y' is nonzero only in the vertex columns: the rows of X and of Y' at the
+// Gamma entries are read (n_a + n_v columns instead of n_a + n_c).  One
+// workgroup per (chunk of 256 Gamma rows, subdomain, rhs).
 template <typename T>
 __global__ __launch_bounds__(256) void k_v2(PlanDev P, const T* __restrict__ vR, const T* __restrict__ XG,
-                                            const T* __restrict__ mu, const T* __restrict__ PhiG,
-                                            const double* __restrict__ uc, T* __restrict__ v2) {
+                                            const T* __restrict__ mu, const T* __restrict__ lu,
+                                            const T* __restrict__ YG, const double* __restrict__ uc,
+                                            T* __restrict__ v2) {
   extern __shared__ char smem_raw[];
   T* sh = reinterpret_cast<T*>(smem_raw);
   const int sub = blockIdx.y, rhs = blockIdx.z;
@@ -2636,20 +2640,57 @@ __global__ __launch_bounds__(256) void k_v2(PlanDev P, const T* __restrict__ vR,
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if ((int)(blockIdx.x * blockDim.x) >= S.n_g) return;
   T* mul = sh;
-  T* ucl = sh + S.n_a;
-  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x) mul[a] = mu[rhs * P.tot_a + S.am_off + a];
-  for (int c = threadIdx.x; c < S.n_c; c += blockDim.x)
-    ucl[c] = (T)uc[rhs * P.n_coarse + P.c_glob[S.c_off + c]];
+  T* ucv = sh + S.n_a;
+  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x)
+    mul[a] = mu[rhs * P.tot_a + S.am_off + a] + lu[rhs * P.tot_a + S.am_off + a];
+  for (int v = threadIdx.x; v < S.n_v; v += blockDim.x)
+    ucv[v] = (T)uc[rhs * P.n_coarse + P.c_glob[S.c_off + P.v_c[S.v_off + v]]];
   __syncthreads();
   if (e >= S.n_g) return;
   const T* u = vR + rhs * P.tot_r + S.r_off;
   const T* X = XG + S.XG_off;
-  const T* F = PhiG + S.PhiG_off;
+  const T* Y = YG + S.YG_off;
   const int r = P.g_r[S.g_off + e];
   T acc = r >= 0 ? u[r] : (T)0;
   for (int a = 0; a < S.n_a; ++a) acc -= X[e + (int64_t)S.n_s * a] * mul[a];
-  for (int c = 0; c < S.n_c; ++c) acc += F[e + (int64_t)S.n_s * c] * ucl[c];
+  for (int v = 0; v < S.n_v; ++v) acc += Y[e + (int64_t)S.n_g * v] * ucv[v];
   v2[rhs * P.tot_g + S.g_off + e] = acc;
+}
+
+// lu = Lambda u_c per subdomain and right-hand side: one workgroup per
+// (subdomain, rhs), the local coarse values staged in LDS, one thread per
+// average row (Lambda read along its columns).
+template <typename T>
+__global__ __launch_bounds__(256) void k_lam_uc(PlanDev P, const T* __restrict__ Lam,
+                                                const double* __restrict__ uc, T* __restrict__ lu) {
+  extern __shared__ char smem_raw[];
+  double* ucl = reinterpret_cast<double*>(smem_raw);
+  const int sub = blockIdx.x, rhs = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  for (int c = threadIdx.x; c < S.n_c; c += blockDim.x) ucl[c] = uc[rhs * P.n_coarse + P.c_glob[S.c_off + c]];
+  __syncthreads();
+  const T* L = Lam + S.T_off;
+  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < S.n_c; ++c) acc += (double)L[a + (int64_t)S.n_a * c] * ucl[c];
+    lu[rhs * P.tot_a + S.am_off + a] = (T)acc;
+  }
+}
+
+// Y' at the Gamma entries: the vertex columns of [X | Y'] gathered by the
+// Gamma entries' r-rows; a Gamma entry that is a primal vertex has no r-row
+// and takes the unit value of its own coarse dof.
+template <typename T>
+__global__ void k_yg_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__ YG) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  const int tot = S.n_g * S.n_v;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
+    const int e = idx % S.n_g, v = idx / S.n_g;
+    const int r = P.g_r[S.g_off + e];
+    YG[S.YG_off + idx] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * (S.n_a + v)]
+                                : (P.g_v[S.g_off + e] == v ? (T)1 : (T)0);
+  }
 }
 
 // Interior right-hand side of the second Dirichlet solve: r_I - K_{I Gamma} w.
@@ -2667,6 +2708,14 @@ __global__ void k_interior_rhs(PlanDev P, Geo g, const double* __restrict__ rho,
   const int32_t* lg = P.loc_g + S.loc_off;
   double acc = r[rhs * g.n_free + free_of_local(S, g, l)];
   const int zr = g.dim == 3 ? 1 : 0;
+  // Gamma lies on the faces of the subdomain's box: a node two or more
+  // layers inside has no Gamma neighbour
+  bool deep = c[0] >= 2 && c[0] <= S.m[0] - 3 && c[1] >= 2 && c[1] <= S.m[1] - 3;
+  if (zr) deep = deep && c[2] >= 2 && c[2] <= S.m[2] - 3;
+  if (deep) {
+    vI[rhs * P.tot_I + S.I_off + i] = (T)acc;
+    return;
+  }
   for (int dz = -zr; dz <= zr; ++dz)
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
@@ -2899,11 +2948,13 @@ __global__ __launch_bounds__(256) void k_coarse_rhs_local_mr(PlanDev P, const T*
     }
 }
 
-// v2 on Gamma = u - X_Gamma mu + Phi_Gamma u_c, for 64 Gamma rows per workgroup.
+// v2 on Gamma = u - X_Gamma (mu + Lambda u_c) + Y'_Gamma u_c (as in k_v2),
+// for 64 Gamma rows per workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void k_v2_mr(PlanDev P, const T* __restrict__ vR, const T* __restrict__ XG,
-                                               const T* __restrict__ mu, const T* __restrict__ PhiG,
-                                               const double* __restrict__ uc, T* __restrict__ v2, int nrhs) {
+                                               const T* __restrict__ mu, const T* __restrict__ lu,
+                                               const T* __restrict__ YG, const double* __restrict__ uc,
+                                               T* __restrict__ v2, int nrhs) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T Bs[MR_KC][MR_COLS + 1];
   const int sub = blockIdx.y, r0 = blockIdx.z * MR_COLS, nr = min(MR_COLS, nrhs - r0);
@@ -2916,25 +2967,28 @@ __global__ __launch_bounds__(256) void k_v2_mr(PlanDev P, const T* __restrict__ 
   acc_t acc[MR_COLS / 16];
 #pragma unroll
   for (int q = 0; q < MR_COLS / 16; ++q) acc[q] = acc_t{0, 0, 0, 0};
-  for (int kb = 0; kb < S.n_c; kb += MR_KC) {   // + Phi_Gamma u_c
-    const int kn = min(MR_KC, S.n_c - kb);
+  for (int kb = 0; kb < S.n_v; kb += MR_KC) {   // + Y'_Gamma u_c (vertex columns)
+    const int kn = min(MR_KC, S.n_v - kb);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < MR_KC * MR_COLS / 256; ++u) {
       const int idx = tid + u * 256, k = idx % MR_KC, r = idx / MR_KC;
-      Bs[k][r] = (k < kn && r < nr) ? (T)uc[(int64_t)(r0 + r) * P.n_coarse + P.c_glob[S.c_off + kb + k]] : (T)0;
+      Bs[k][r] = (k < kn && r < nr)
+                     ? (T)uc[(int64_t)(r0 + r) * P.n_coarse + P.c_glob[S.c_off + P.v_c[S.v_off + kb + k]]]
+                     : (T)0;
     }
     __syncthreads();
-    const T* M = PhiG + S.PhiG_off + e + (int64_t)S.n_s * kb;
-    mr_accum<T>([&](int k) { return M[(int64_t)S.n_s * k]; }, rok, kn, Bs, acc, kq, rr);
+    const T* M = YG + S.YG_off + e + (int64_t)S.n_g * kb;
+    mr_accum<T>([&](int k) { return M[(int64_t)S.n_g * k]; }, rok, kn, Bs, acc, kq, rr);
   }
-  for (int kb = 0; kb < S.n_a; kb += MR_KC) {   // - X_Gamma mu
+  for (int kb = 0; kb < S.n_a; kb += MR_KC) {   // - X_Gamma (mu + Lambda u_c)
     const int kn = min(MR_KC, S.n_a - kb);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < MR_KC * MR_COLS / 256; ++u) {
       const int idx = tid + u * 256, k = idx % MR_KC, r = idx / MR_KC;
-      Bs[k][r] = (k < kn && r < nr) ? -mu[(int64_t)(r0 + r) * P.tot_a + S.am_off + kb + k] : (T)0;
+      const int64_t at = (int64_t)(r0 + r) * P.tot_a + S.am_off + kb + k;
+      Bs[k][r] = (k < kn && r < nr) ? -(mu[at] + lu[at]) : (T)0;
     }
     __syncthreads();
     const T* M = XG + S.XG_off + e + (int64_t)S.n_s * kb;
@@ -3564,16 +3618,29 @@ void Kern<T>::coarse_rhs_local(const PlanDev& P, const T* PhiG, const T* gv, T* 
 }
 
 template <typename T>
-void Kern<T>::v2(const PlanDev& P, const T* vR, const T* XG, const T* mu_in, const T* PhiG, const double* uc,
-                 T* v2_out, int nrhs, hipStream_t s) {
+void Kern<T>::v2(const PlanDev& P, const T* vR, const T* XG, const T* mu_in, const T* lu, const T* YG,
+                 const double* uc, T* v2_out, int nrhs, hipStream_t s) {
   if (P.max_ng == 0) return;
   if (nrhs >= 4) {
-    k_v2_mr<T><<<dim3(cdiv(P.max_ng, 64), P.n_sub, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, vR, XG, mu_in, PhiG, uc,
-                                                                                     v2_out, nrhs);
+    k_v2_mr<T><<<dim3(cdiv(P.max_ng, 64), P.n_sub, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, vR, XG, mu_in, lu, YG,
+                                                                                     uc, v2_out, nrhs);
     return;
   }
-  size_t sm = (size_t)(P.max_na + P.max_nc + 1) * sizeof(T);
-  k_v2<T><<<dim3(cdiv(P.max_ng, 256), P.n_sub, nrhs), 256, sm, s>>>(P, vR, XG, mu_in, PhiG, uc, v2_out);
+  size_t sm = (size_t)(P.max_na + P.max_nv + 1) * sizeof(T);
+  k_v2<T><<<dim3(cdiv(P.max_ng, 256), P.n_sub, nrhs), 256, sm, s>>>(P, vR, XG, mu_in, lu, YG, uc, v2_out);
+}
+
+template <typename T>
+void Kern<T>::lam_uc(const PlanDev& P, const T* Lam, const double* uc, T* lu, int nrhs, hipStream_t s) {
+  if (P.max_na == 0) return;
+  k_lam_uc<T><<<dim3(P.n_sub, nrhs), 256, (size_t)hmax(P.max_nc, 1) * sizeof(double), s>>>(P, Lam, uc, lu);
+}
+
+template <typename T>
+void Kern<T>::yg_gather(const PlanDev& P, const T* Z, T* YG, int max_nv, hipStream_t s) {
+  const int64_t tot = (int64_t)P.max_ng * max_nv;
+  if (tot == 0) return;
+  k_yg_gather<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, YG);
 }
 
 template <typename T>

@@ -356,7 +356,7 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
 
   plan.subs.resize(c.n_sub);
   int64_t loc_off = 0, I_off = 0, r_off = 0, g_off = 0, v_off = 0, a_off = 0, c_off = 0, sel_off = 0;
-  int64_t G_off = 0, Z_off = 0, XG_off = 0, Sc_off = 0, T_off = 0, PhiG_off = 0, Kc_off = 0;
+  int64_t G_off = 0, Z_off = 0, XG_off = 0, Sc_off = 0, T_off = 0, PhiG_off = 0, YG_off = 0, Kc_off = 0;
   std::vector<std::vector<int32_t>> sub_dofs(c.n_sub);
   for (int s = 0; s < c.n_sub; ++s) {
     SubDev& S = plan.subs[s];
@@ -595,6 +595,8 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     T_off += (int64_t)S.n_a * S.n_c;
     S.PhiG_off = PhiG_off;
     PhiG_off += (int64_t)S.n_s * S.n_c;
+    S.YG_off = YG_off;
+    YG_off += (int64_t)S.n_g * S.n_v;
     S.Kc_off = Kc_off;
     Kc_off += (int64_t)S.n_c * S.n_c;
     loc_off += S.n_loc;
@@ -625,6 +627,7 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
   plan.pool_Sc = Sc_off;
   plan.pool_T = T_off;
   plan.pool_PhiG = PhiG_off;
+  plan.pool_YG = YG_off;
   plan.pool_Kc = Kc_off;
 
   // Gamma index -> entries; coarse id -> local coarse entries

@@ -92,7 +92,7 @@ struct Plan {
 
   // totals
   int64_t tot_loc = 0, tot_I = 0, tot_r = 0, tot_g = 0, tot_v = 0, tot_a = 0, tot_c = 0;
-  int64_t pool_G = 0, pool_Z = 0, pool_XG = 0, pool_Sc = 0, pool_T = 0, pool_PhiG = 0, pool_Kc = 0;
+  int64_t pool_G = 0, pool_Z = 0, pool_XG = 0, pool_Sc = 0, pool_T = 0, pool_PhiG = 0, pool_YG = 0, pool_Kc = 0;
   int max_block = 0, max_na = 0, max_nc = 0, max_nr = 0, max_nloc = 0, max_ng = 0, max_ns = 0;
   int max_nbI = 0, max_nbR = 0;
   int max_zcols = 0;

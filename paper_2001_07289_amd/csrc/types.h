@@ -35,6 +35,8 @@ struct SubDev {
   int64_t T_off;     // n_a x n_c: C_r Y - [0 I], then Lambda
   int64_t PhiG_off;  // n_s x n_c (ld n_s): rows of Phi at the selected rows (the first
                      // n_g are the Gamma entries)
+  int64_t YG_off;    // n_g x n_v (ld n_g): Y' at the Gamma entries (the unit entry of
+                     // its coarse dof at a Gamma entry that is a primal vertex)
   int64_t Kc_off;    // n_c x n_c local coarse matrix
 };
 
