@@ -493,6 +493,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   launch_coupling_coefs(P, g, rho, pc->cpl_coef, pc->s2);
   HIPCHK(hipEventRecord(pc->ev_cpl, pc->s2));
   launch_alpha(P, pc->prob->c.n_ss, rho, pc->opt.weighting, pc->alpha, s);
+  launch_kig_fill(P, g, rho, s);
   launch_delta(P, pc->alpha, pc->delta, s);
   // local block-tridiagonal factors of K_II and K_rr (lower triangles written whole)
   Kern<T>::block_assemble(P, g, rho, 0, N.G, pl.max_nbI, s);
@@ -837,6 +838,14 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     P.loc_r = m.upload(pl.loc_r, s);
     P.loc_g = m.upload(pl.loc_g, s);
     P.I_loc = m.upload(pl.I_loc, s);
+    P.kig_ptr = m.upload(pl.kig_ptr, s);
+    P.kig_t = m.upload(pl.kig_t, s);
+    P.kig_col = m.alloc<int32_t>((int64_t)pl.kig_t.size());
+    P.kig_val = m.alloc<double>((int64_t)pl.kig_t.size());
+    P.kgi_ptr = m.upload(pl.kgi_ptr, s);
+    P.kgi_t = m.upload(pl.kgi_t, s);
+    P.kgi_col = m.alloc<int32_t>((int64_t)pl.kgi_t.size());
+    P.kgi_val = m.alloc<double>((int64_t)pl.kgi_t.size());
     P.r_loc = m.upload(pl.r_loc, s);
     P.g_loc = m.upload(pl.g_loc, s);
     P.g_gam = m.upload(pl.g_gam, s);

@@ -45,6 +45,14 @@ struct PlanDev {
   const BlockDev* blocks;
   const int32_t *loc_I, *loc_r, *loc_g;
   const int32_t *I_loc, *r_loc;
+  const int32_t* kig_ptr;   // per interior node (global I order) into the K_{I Gamma} entries
+  const int8_t* kig_t;      // neighbour code of each entry
+  int32_t* kig_col;         // free index of the neighbour (filled by the setup)
+  double* kig_val;          // K_{I Gamma} entry (filled by the setup from rho)
+  const int32_t* kgi_ptr;   // per Gamma entry (global order) into the K_{Gamma I} entries
+  const int8_t* kgi_t;      // neighbour code of each entry
+  int32_t* kgi_col;         // interior index of the neighbour in its subdomain (filled by the setup)
+  double* kgi_val;          // K_{Gamma I} entry (filled by the setup from rho)
   const int32_t *g_loc, *g_gam, *g_r, *g_v, *g_sub;
   const int32_t *loc_sel, *sel_r;
   const int32_t *v_loc, *v_c;
@@ -68,6 +76,10 @@ struct PlanDev {
 // ---- launchers (defined in kernels.hip) ---------------------------------
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s, int max_blocks = 65536);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+// the K_{I Gamma} entries of every interior node (free index of the Gamma
+// neighbour and the stiffness entry from rho) and the K_{Gamma I} entries of
+// every Gamma entry (interior index of the neighbour and the entry)
+void launch_kig_fill(const PlanDev& P, const Geo& g, const double* rho, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
 void launch_q1_apply(const Geo& g, const double* khat, const double* rho, const double* x,

@@ -2514,31 +2514,38 @@ __global__ __launch_bounds__(MR_THREADS) void k_block_solve_mr(PlanDev P, int se
   }
 }
 
-// q[e] = (K_{Gamma I} y_I)[e] for the Gamma entries of each subdomain.
-template <typename T>
-__global__ void k_gamma_kgi(PlanDev P, Geo g, const double* __restrict__ rho, const T* __restrict__ vI,
-                            T* __restrict__ q) {
-  const int sub = blockIdx.y, rhs = blockIdx.z;
+// The K_{Gamma I} entries of each Gamma entry: for each interior neighbour
+// listed by the plan, its interior index and the stiffness entry (from rho).
+__global__ void k_kgi_fill(PlanDev P, Geo g, const double* __restrict__ rho) {
+  const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= S.n_g) return;
   int c[3];
   loc_coords(S, P.g_loc[S.g_off + e], c);
   const int32_t* li = P.loc_I + S.loc_off;
+  const int64_t ge = S.g_off + e;
+  for (int k = P.kgi_ptr[ge]; k < P.kgi_ptr[ge + 1]; ++k) {
+    const int t = P.kgi_t[k];
+    const int cn[3] = {c[0] + t % 3 - 1, c[1] + (t / 3) % 3 - 1, c[2] + t / 9 - 1};
+    P.kgi_col[k] = li[loc_index(S, cn)];
+    P.kgi_val[k] = kloc(S, g, rho, P.khat, c, cn);
+  }
+}
+
+// q[e] = (K_{Gamma I} y_I)[e] for the Gamma entries of each subdomain, from
+// the entries the setup stored.
+template <typename T>
+__global__ void k_gamma_kgi(PlanDev P, const T* __restrict__ vI, T* __restrict__ q) {
+  const int sub = blockIdx.y, rhs = blockIdx.z;
+  const SubDev S = P.subs[sub];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S.n_g) return;
   const T* y = vI + rhs * P.tot_I + S.I_off;
+  const int64_t ge = S.g_off + e;
   double acc = 0.0;
-  const int zr = g.dim == 3 ? 1 : 0;
-  for (int dz = -zr; dz <= zr; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        int cn[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
-        int ln = loc_index(S, cn);
-        if (ln < 0) continue;
-        int j = li[ln];
-        if (j < 0) continue;
-        acc += kloc(S, g, rho, P.khat, c, cn) * (double)y[j];
-      }
-  q[rhs * P.tot_g + S.g_off + e] = (T)acc;
+  for (int k = P.kgi_ptr[ge]; k < P.kgi_ptr[ge + 1]; ++k) acc += P.kgi_val[k] * (double)y[P.kgi_col[k]];
+  q[rhs * P.tot_g + ge] = (T)acc;
 }
 
 // t = r_Gamma - sum_i q_i (I - P)^T, then g_e = delta_e t (E^T).
@@ -2693,38 +2700,39 @@ __global__ void k_yg_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__ 
   }
 }
 
-// Interior right-hand side of the second Dirichlet solve: r_I - K_{I Gamma} w.
-template <typename T>
-__global__ void k_interior_rhs(PlanDev P, Geo g, const double* __restrict__ rho,
-                               const double* __restrict__ r, const double* __restrict__ w,
-                               T* __restrict__ vI) {
-  const int sub = blockIdx.y, rhs = blockIdx.z;
+// The K_{I Gamma} entries of each interior node: for each Gamma neighbour
+// listed by the plan, its free index and the stiffness entry (from rho).
+__global__ void k_kig_fill(PlanDev P, Geo g, const double* __restrict__ rho) {
+  const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.n_I) return;
   const int l = P.I_loc[S.I_off + i];
   int c[3];
   loc_coords(S, l, c);
-  const int32_t* lg = P.loc_g + S.loc_off;
-  double acc = r[rhs * g.n_free + free_of_local(S, g, l)];
-  const int zr = g.dim == 3 ? 1 : 0;
-  // Gamma lies on the faces of the subdomain's box: a node two or more
-  // layers inside has no Gamma neighbour
-  bool deep = c[0] >= 2 && c[0] <= S.m[0] - 3 && c[1] >= 2 && c[1] <= S.m[1] - 3;
-  if (zr) deep = deep && c[2] >= 2 && c[2] <= S.m[2] - 3;
-  if (deep) {
-    vI[rhs * P.tot_I + S.I_off + i] = (T)acc;
-    return;
+  const int64_t gi = S.I_off + i;
+  for (int e = P.kig_ptr[gi]; e < P.kig_ptr[gi + 1]; ++e) {
+    const int t = P.kig_t[e];
+    const int cn[3] = {c[0] + t % 3 - 1, c[1] + (t / 3) % 3 - 1, c[2] + t / 9 - 1};
+    P.kig_col[e] = (int32_t)free_of_local(S, g, loc_index(S, cn));
+    P.kig_val[e] = kloc(S, g, rho, P.khat, c, cn);
   }
-  for (int dz = -zr; dz <= zr; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        int cn[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
-        int ln = loc_index(S, cn);
-        if (ln < 0 || lg[ln] < 0) continue;
-        acc -= kloc(S, g, rho, P.khat, c, cn) * w[rhs * g.n_free + free_of_local(S, g, ln)];
-      }
-  vI[rhs * P.tot_I + S.I_off + i] = (T)acc;
+}
+
+// Interior right-hand side of the second Dirichlet solve: r_I - K_{I Gamma} w,
+// from the entries the setup stored.
+template <typename T>
+__global__ void k_interior_rhs(PlanDev P, Geo g, const double* __restrict__ r, const double* __restrict__ w,
+                               T* __restrict__ vI) {
+  const int sub = blockIdx.y, rhs = blockIdx.z;
+  const SubDev S = P.subs[sub];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n_I) return;
+  const int64_t gi = S.I_off + i;
+  const double* wr = w + rhs * g.n_free;
+  double acc = r[rhs * g.n_free + free_of_local(S, g, P.I_loc[gi])];
+  for (int e = P.kig_ptr[gi]; e < P.kig_ptr[gi + 1]; ++e) acc -= P.kig_val[e] * wr[P.kig_col[e]];
+  vI[rhs * P.tot_I + gi] = (T)acc;
 }
 
 template <typename T>
@@ -3583,7 +3591,9 @@ template <typename T>
 void Kern<T>::gamma_kgi(const PlanDev& P, const Geo& g, const double* rho, const T* vI, T* q, int nrhs,
                         hipStream_t s) {
   if (P.max_ng == 0) return;
-  k_gamma_kgi<T><<<dim3(cdiv(P.max_ng, 128), P.n_sub, nrhs), 128, 0, s>>>(P, g, rho, vI, q);
+  (void)g;
+  (void)rho;
+  k_gamma_kgi<T><<<dim3(cdiv(P.max_ng, 128), P.n_sub, nrhs), 128, 0, s>>>(P, vI, q);
 }
 
 template <typename T>
@@ -3647,7 +3657,8 @@ template <typename T>
 void Kern<T>::interior_rhs(const PlanDev& P, const Geo& g, const double* rho, const double* r, const double* w,
                            T* vI, int nrhs, hipStream_t s) {
   if (P.max_nI == 0) return;
-  k_interior_rhs<T><<<dim3(cdiv(P.max_nI, 128), P.n_sub, nrhs), 128, 0, s>>>(P, g, rho, r, w, vI);
+  (void)rho;
+  k_interior_rhs<T><<<dim3(cdiv(P.max_nI, 128), P.n_sub, nrhs), 128, 0, s>>>(P, g, r, w, vI);
 }
 
 template <typename T>
@@ -3676,6 +3687,10 @@ void launch_front_zero_lower(const PlanDev& P, const int32_t* fronts, int nfr, i
                              hipStream_t s) {
   if (nfr == 0 || maxn == 0) return;
   k_front_zero_lower<<<dim3(cdiv(maxn, 32), nfr), 256, 0, s>>>(P, fronts, fpool);
+}
+void launch_kig_fill(const PlanDev& P, const Geo& g, const double* rho, hipStream_t s) {
+  if (P.max_nI > 0) k_kig_fill<<<dim3(cdiv(P.max_nI, 128), P.n_sub), 128, 0, s>>>(P, g, rho);
+  if (P.max_ng > 0) k_kgi_fill<<<dim3(cdiv(P.max_ng, 128), P.n_sub), 128, 0, s>>>(P, g, rho);
 }
 void launch_front_child_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
                                 double* fpool, hipStream_t s) {

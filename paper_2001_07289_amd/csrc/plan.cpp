@@ -431,6 +431,22 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
       if (lI[l] >= 0) plan.I_loc.push_back(l);
       if (lr[l] >= 0) plan.r_loc.push_back(l);
     }
+    // the Gamma neighbours of each interior node (the nonzeros of K_{I Gamma}),
+    // by neighbour code t = 9 (dz + 1) + 3 (dy + 1) + (dx + 1), in I order
+    if (plan.kig_ptr.empty()) plan.kig_ptr.push_back(0);
+    for (int l = 0; l < S.n_loc; ++l) {
+      if (lI[l] < 0) continue;
+      const int cl[3] = {l % S.m[0], (l / S.m[0]) % S.m[1], l / (S.m[0] * S.m[1])};
+      for (int t = 0; t < 27; ++t) {
+        const int cn[3] = {cl[0] + t % 3 - 1, cl[1] + (t / 3) % 3 - 1, cl[2] + t / 9 - 1};
+        bool in = true;
+        for (int a = 0; a < 3; ++a) in = in && cn[a] >= 0 && cn[a] < S.m[a];
+        if (!in) continue;
+        const int ln = cn[0] + S.m[0] * (cn[1] + S.m[1] * cn[2]);
+        if (lg[ln] >= 0) plan.kig_t.push_back((int8_t)t);
+      }
+      plan.kig_ptr.push_back((int32_t)plan.kig_t.size());
+    }
     // Gamma entries
     for (int l = 0; l < S.n_loc; ++l) {
       if (lg[l] < 0) continue;
@@ -441,6 +457,21 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
       plan.g_r.push_back(lr[l]);
       plan.g_sub.push_back(s);
       plan.g_v.push_back(-1);
+    }
+    // the interior neighbours of each Gamma entry (the nonzeros of K_{Gamma I})
+    if (plan.kgi_ptr.empty()) plan.kgi_ptr.push_back(0);
+    for (int l = 0; l < S.n_loc; ++l) {
+      if (lg[l] < 0) continue;
+      const int cl[3] = {l % S.m[0], (l / S.m[0]) % S.m[1], l / (S.m[0] * S.m[1])};
+      for (int t = 0; t < 27; ++t) {
+        const int cn[3] = {cl[0] + t % 3 - 1, cl[1] + (t / 3) % 3 - 1, cl[2] + t / 9 - 1};
+        bool in = true;
+        for (int a = 0; a < 3; ++a) in = in && cn[a] >= 0 && cn[a] < S.m[a];
+        if (!in) continue;
+        const int ln = cn[0] + S.m[0] * (cn[1] + S.m[1] * cn[2]);
+        if (lI[ln] >= 0) plan.kgi_t.push_back((int8_t)t);
+      }
+      plan.kgi_ptr.push_back((int32_t)plan.kgi_t.size());
     }
     // vertex index of each Gamma entry
     {

@@ -63,6 +63,10 @@ struct Plan {
   std::vector<SubDev> subs;
   std::vector<int32_t> loc_I, loc_r, loc_g;   // per local node: rank in I / r / Gamma entries, -1
   std::vector<int32_t> I_loc, r_loc;          // set order -> local node
+  std::vector<int32_t> kig_ptr;               // per interior node (all subdomains): its Gamma neighbours
+  std::vector<int8_t> kig_t;                  //   as 27-point neighbour codes
+  std::vector<int32_t> kgi_ptr;               // per Gamma entry (all subdomains): its interior neighbours
+  std::vector<int8_t> kgi_t;                  //   as 27-point neighbour codes
   std::vector<int32_t> g_loc, g_gam, g_r, g_v, g_sub; // per Gamma entry
   std::vector<int32_t> loc_sel;   // per local node: selected-row index or -1
   std::vector<int32_t> sel_r;     // per selected row: r rank (-1 at primal vertices)
