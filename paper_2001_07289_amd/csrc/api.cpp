@@ -379,7 +379,13 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       int ncols = S.n_a + S.n_v;
       if (k >= S.nbR || ncols == 0) continue;
       const BlockDev& B = pl.blocks[S.bR_off + k];
-      f.push_back({B.G_off, sidx * tmp_stride, S.Z_off + B.start, B.size, ncols, B.size, B.ld, B.size, S.n_r});
+      // forward: only the columns the right-hand sides have reached (the
+      // others are still zero): the first za averages and zv vertices
+      if (B.za > 0)
+        f.push_back({B.G_off, sidx * tmp_stride, S.Z_off + B.start, B.size, B.za, B.size, B.ld, B.size, S.n_r});
+      if (B.zv > 0)
+        f.push_back({B.G_off, sidx * tmp_stride + (int64_t)B.size * S.n_a, S.Z_off + B.start + (int64_t)S.n_r * S.n_a,
+                     B.size, B.zv, B.size, B.ld, B.size, S.n_r});
       if (k + 1 < S.nbR) {
         const BlockDev& N = pl.blocks[S.bR_off + k + 1];
         if (B.plane_hi == N.plane_lo)

@@ -1676,6 +1676,8 @@ __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd,
   if (c0 >= ncols) return;
   const int nc = min(CPL_COLS, ncols - c0);
   const BlockDev B = P.blocks[S.bR_off + k];
+  // forward: columns the right-hand sides have not reached yet stay zero
+  if (fwd && !(c0 < B.za || (c0 + nc > S.n_a && c0 < S.n_a + B.zv))) return;
   const int64_t roff = fwd ? B.cf_off : B.cb_off;
   const bool couple = fwd ? (k > 0 && roff >= 0) : roff >= 0;
   if (!fwd && !couple) return;

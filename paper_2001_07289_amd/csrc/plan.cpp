@@ -509,10 +509,31 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
       sel_off += ns;
       plan.loc_sel.insert(plan.loc_sel.end(), ls.begin(), ls.end());
     }
-    // local coarse: vertices and averages, in coarse order
+    // local coarse: vertices and averages, in coarse order.  The averages
+    // are numbered by the first plane of their object, so that at each
+    // block of the forward basis solve the columns already reached form a
+    // prefix (the vertices are numbered by local node, so by plane, already).
+    auto node_plane = [&](int32_t q) {
+      int gcoord[3];
+      c.node_coords(c.gam_node[q], gcoord);
+      return pa == 2 ? gcoord[2] - S.lo[2] : gcoord[1] - S.lo[1];
+    };
+    std::vector<int> avg_key, avg_k;
+    for (int k = 0; k < S.n_c; ++k) {
+      int32_t o = plan.coarse_obj[local_coarse[k]];
+      if (c.obj_ptr[o + 1] - c.obj_ptr[o] == 1) continue;
+      int key = INT32_MAX;
+      for (int t = c.obj_ptr[o]; t < c.obj_ptr[o + 1]; ++t) key = std::min(key, node_plane(c.obj_gam[t]));
+      avg_key.push_back(key);
+      avg_k.push_back(k);
+    }
+    std::vector<int> avg_order(avg_k.size());
+    std::iota(avg_order.begin(), avg_order.end(), 0);
+    std::stable_sort(avg_order.begin(), avg_order.end(), [&](int x, int y) { return avg_key[x] < avg_key[y]; });
+    std::vector<int> avg_of_k(S.n_c, -1);
+    for (size_t j = 0; j < avg_order.size(); ++j) avg_of_k[avg_k[avg_order[j]]] = (int)j;
     std::vector<int32_t> v_c(nv, -1);
-    int na = 0;
-    plan.a_ptr.push_back((int32_t)plan.a_r.size());
+    const int na = (int)avg_k.size();
     for (int k = 0; k < S.n_c; ++k) {
       int32_t cid = local_coarse[k];
       int32_t o = plan.coarse_obj[cid];
@@ -528,18 +549,22 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
         plan.c_kind.push_back(vi);
         v_c[vi] = k;
       } else {
-        plan.c_kind.push_back(-(na + 1));
-        for (int t = c.obj_ptr[o]; t < c.obj_ptr[o + 1]; ++t) {
-          int32_t q = c.obj_gam[t];
-          int gcoord[3];
-          c.node_coords(c.gam_node[q], gcoord);
-          int l = (gcoord[0] - S.lo[0]) + S.m[0] * ((gcoord[1] - S.lo[1]) + S.m[1] * (gcoord[2] - S.lo[2]));
-          plan.a_r.push_back(lr[l]);
-        }
-        plan.a_c.push_back(k);
-        plan.a_ptr.push_back((int32_t)plan.a_r.size());
-        na++;
+        plan.c_kind.push_back(-(avg_of_k[k] + 1));
       }
+    }
+    plan.a_ptr.push_back((int32_t)plan.a_r.size());
+    for (int j = 0; j < na; ++j) {
+      const int k = avg_k[avg_order[j]];
+      const int32_t o = plan.coarse_obj[local_coarse[k]];
+      for (int t = c.obj_ptr[o]; t < c.obj_ptr[o + 1]; ++t) {
+        int32_t q = c.obj_gam[t];
+        int gcoord[3];
+        c.node_coords(c.gam_node[q], gcoord);
+        int l = (gcoord[0] - S.lo[0]) + S.m[0] * ((gcoord[1] - S.lo[1]) + S.m[1] * (gcoord[2] - S.lo[2]));
+        plan.a_r.push_back(lr[l]);
+      }
+      plan.a_c.push_back(k);
+      plan.a_ptr.push_back((int32_t)plan.a_r.size());
     }
     for (int vi = 0; vi < nv; ++vi) {
       if (v_c[vi] < 0) return fail(err, -6, "internal: vertex without coarse dof");
@@ -553,6 +578,26 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     S.bR_off = (int64_t)plan.blocks.size();
     make_blocks(cntR, plan.block_target, 0, plan.blocks);
     S.nbR = (int)(plan.blocks.size() - S.bR_off);
+    // the basis columns reached at each r block of the forward solve: an
+    // average from its first plane on, a vertex from the plane below its own
+    // (its stiffness column touches the planes next to it)
+    for (int64_t b = S.bR_off; b < S.bR_off + S.nbR; ++b) {
+      BlockDev& B = plan.blocks[b];
+      const int last = B.plane_hi - 1;
+      B.za = 0;
+      while (B.za < na && avg_key[avg_order[B.za]] <= last) ++B.za;
+      B.zv = 0;
+      while (B.zv < nv) {
+        const int l = plan.v_loc[v_off + B.zv];
+        const int vp = pa == 2 ? l / (S.m[0] * S.m[1]) : (l / S.m[0]) % S.m[1];
+        if (std::max(vp - 1, 0) > last) break;
+        ++B.zv;
+      }
+    }
+    if (S.nbR > 0) {  // every column is reached by the last block
+      plan.blocks[S.bR_off + S.nbR - 1].za = na;
+      plan.blocks[S.bR_off + S.nbR - 1].zv = nv;
+    }
     // coupling rows between consecutive blocks of each set
     for (int setR = 0; setR < 2; ++setR) {
       const int64_t b0 = setR ? S.bR_off : S.bI_off;
