@@ -2123,10 +2123,12 @@ __global__ void k_gather_I(PlanDev P, Geo g, const double* __restrict__ r, T* __
 // coupling reads stay in LDS from the step that produced them.  Waves take
 // tiles round-robin, keep partial sums per wave in LDS and the waves' sums
 // are added in fixed order, so the result is bitwise repeatable.
-// Two shapes: 16 waves with 5 register-held tiles each (blocks up to 192
-// rows, one workgroup per CU), and 8 waves with 5 tiles each for sets whose
-// blocks have at most 40 tiles (up to 144 rows), which keeps the registers at
-// two workgroups per CU.
+// Two shapes, both of 8 waves so that two workgroups share a CU: 5
+// register-held tiles per wave for sets whose blocks have at most 40 tiles
+// (up to 144 rows), 9 tiles for larger blocks.  Sixteen waves (one workgroup
+// per CU) make the constrained Neumann solve faster alone but take compute
+// units from the coarse solve that runs beside it.  The LDS size allows up
+// to 16 waves.
 constexpr int BS_WAVES_MAX = 16;
 
 // Tile lin of the lower triangle restricted to tile rows >= t0: first the
