@@ -261,24 +261,25 @@ __global__ void k_coupling_coefs(PlanDev P, Geo g, const double* __restrict__ rh
 // ---------------------------------------------------------------------------
 // local matrices: dense diagonal blocks of K_II / K_rr (entries within a block)
 //
-// Only the lower triangles are formed: k_block_zero_lower clears them (one
-// thread per entry, lanes along i), then k_block_assemble writes the stencil
+// Only the lower triangles are formed: k_block_zero_lower clears them (a
+// wave per column, lanes along i), then k_block_assemble writes the stencil
 // entries with j <= i.  The upper triangles are left as they are: the sweeps
 // read only the lower triangle and write both, and the Schur coupling's
 // updates of the upper entries are overwritten by the sweep.
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_block_zero_lower(PlanDev P, int setR, T* __restrict__ G) {
-  // one workgroup per block, running through the square (stores contiguous)
+  // one workgroup per block
   const int sub = blockIdx.y, k = blockIdx.x;
   const SubDev S = P.subs[sub];
   if (k >= (setR ? S.nbR : S.nbI)) return;
   const BlockDev B = P.blocks[(setR ? S.bR_off : S.bI_off) + k];
   T* Gb = G + B.G_off;
-  const int n2 = B.size * B.size;
-  for (int idx = threadIdx.x; idx < n2; idx += 256) {
-    const int i = idx % B.size, j = idx / B.size;
-    if (j <= i) Gb[i + (int64_t)B.ld * j] = (T)0;
+  // wave w clears the columns j = w, w + 4, ..., lanes down rows i >= j
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int j = wave; j < B.size; j += 4) {
+    T* col = Gb + (int64_t)B.ld * j;
+    for (int i = j + lane; i < B.size; i += 64) col[i] = (T)0;
   }
 }
 
