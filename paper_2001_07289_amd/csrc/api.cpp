@@ -1197,8 +1197,12 @@ bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bd
                  pl.pool_Kc + ns * ((double)max_plane * max_plane + (double)pl.max_block * std::max(pl.max_zcols, 1) +
                                     2.0 * std::max(2.0 * ((double)std::max(pl.max_block, pl.max_na) * kSweepNB + kSweepNB * kSweepNB), (double)std::max(pl.max_block, pl.max_na) * kSlab)) +
                  nr * (pl.tot_I + pl.tot_r + 3.0 * pl.tot_g + 2.0 * pl.tot_a + pl.tot_c);
+  // interior-Gamma couplings: a code, a column and a value per entry; the
+  // fronts' gather maps (int32)
+  const double kig = (double)(pl.kig_t.size() + pl.kgi_t.size()) * 13.0 +
+                     4.0 * (double)(pl.kig_ptr.size() + pl.kgi_ptr.size() + pl.front_imap.size());
   double dpool = (double)pl.front_pool + 2.0 * nr * pl.front_vec + 2.0 * nr * pl.n_coarse +
-                 9.0 * pl.cpl_sub.size() + 6.0 * nr * p->c.n_free + p->c.n_elem + pl.tot_g;
+                 9.0 * pl.cpl_sub.size() + 6.0 * nr * p->c.n_free + p->c.n_elem + pl.tot_g + kig / 8.0;
   out->device_bytes = ts * tpool + 8.0 * dpool;
   return BDDCSO_OK;
 }
