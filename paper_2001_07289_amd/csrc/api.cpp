@@ -380,12 +380,9 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       if (k >= S.nbR || ncols == 0) continue;
       const BlockDev& B = pl.blocks[S.bR_off + k];
       // forward: only the columns the right-hand sides have reached (the
-      // others are still zero): the first za averages and zv vertices
+      // others are still zero), a prefix in the stored column order
       if (B.za > 0)
         f.push_back({B.G_off, sidx * tmp_stride, S.Z_off + B.start, B.size, B.za, B.size, B.ld, B.size, S.n_r});
-      if (B.zv > 0)
-        f.push_back({B.G_off, sidx * tmp_stride + (int64_t)B.size * S.n_a, S.Z_off + B.start + (int64_t)S.n_r * S.n_a,
-                     B.size, B.zv, B.size, B.ld, B.size, S.n_r});
       if (k + 1 < S.nbR) {
         const BlockDev& N = pl.blocks[S.bR_off + k + 1];
         if (B.plane_hi == N.plane_lo)
@@ -844,6 +841,7 @@ bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcs
     P.loc_r = m.upload(pl.loc_r, s);
     P.loc_g = m.upload(pl.loc_g, s);
     P.I_loc = m.upload(pl.I_loc, s);
+    P.z_col = m.upload(pl.z_col, s);
     P.kig_ptr = m.upload(pl.kig_ptr, s);
     P.kig_t = m.upload(pl.kig_t, s);
     P.kig_col = m.alloc<int32_t>((int64_t)pl.kig_t.size());

@@ -45,6 +45,7 @@ struct PlanDev {
   const BlockDev* blocks;
   const int32_t *loc_I, *loc_r, *loc_g;
   const int32_t *I_loc, *r_loc;
+  const int32_t* z_col;     // per local coarse entry (c_off order: averages, then vertices): its column of [X | Y']
   const int32_t* kig_ptr;   // per interior node (global I order) into the K_{I Gamma} entries
   const int8_t* kig_t;      // neighbour code of each entry
   int32_t* kig_col;         // free index of the neighbour (filled by the setup)

@@ -1631,7 +1631,7 @@ __global__ void k_rhs_fill(PlanDev P, Geo g, const double* __restrict__ rho, T* 
   const SubDev S = P.subs[sub];
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= S.n_a + S.n_v) return;
-  T* z = Z + S.Z_off + (int64_t)S.n_r * col;
+  T* z = Z + S.Z_off + (int64_t)S.n_r * P.z_col[S.c_off + col];  // stored in the order the forward solve reaches
   if (col < S.n_a) {
     const int b = P.a_ptr[S.a_off + col], e = P.a_ptr[S.a_off + col + 1];
     const T w = (T)(1.0 / (double)(e - b));
@@ -1678,7 +1678,7 @@ __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd,
   const int nc = min(CPL_COLS, ncols - c0);
   const BlockDev B = P.blocks[S.bR_off + k];
   // forward: columns the right-hand sides have not reached yet stay zero
-  if (fwd && !(c0 < B.za || (c0 + nc > S.n_a && c0 < S.n_a + B.zv))) return;
+  if (fwd && c0 >= B.za) return;
   const int64_t roff = fwd ? B.cf_off : B.cb_off;
   const bool couple = fwd ? (k > 0 && roff >= 0) : roff >= 0;
   if (!fwd && !couple) return;
@@ -1765,7 +1765,7 @@ __global__ void k_sc_assemble(PlanDev P, const T* __restrict__ Z, T* __restrict_
   if (idx >= S.n_a * S.n_a) return;
   const int a = idx % S.n_a, b = idx / S.n_a;
   const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
-  Sc[S.Sc_off + idx] = (T)object_mean(P, Z + S.Z_off, S.n_r, b, pb, pe);
+  Sc[S.Sc_off + idx] = (T)object_mean(P, Z + S.Z_off, S.n_r, P.z_col[S.c_off + b], pb, pe);
 }
 
 // T[a, c] = (C_r Y)[a, c] - [0 I][a, c]: Y is -K_rr^{-1} K_rv at vertex
@@ -1781,7 +1781,7 @@ __global__ void k_lambda_rhs(PlanDev P, const T* __restrict__ Z, T* __restrict__
   double v;
   if (kind >= 0) {
     const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
-    v = object_mean(P, Z + S.Z_off, S.n_r, S.n_a + kind, pb, pe);
+    v = object_mean(P, Z + S.Z_off, S.n_r, P.z_col[S.c_off + S.n_a + kind], pb, pe);
   } else {
     v = (-kind - 1 == a) ? -1.0 : 0.0;
   }
@@ -1800,7 +1800,8 @@ __global__ void k_sel_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__
     const int r = P.sel_r[S.sel_off + e];
     T xv[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) xv[u] = (r >= 0 && a0 + u < S.n_a) ? Z[S.Z_off + r + (int64_t)S.n_r * (a0 + u)] : (T)0;
+    for (int u = 0; u < 8; ++u)
+      xv[u] = (r >= 0 && a0 + u < S.n_a) ? Z[S.Z_off + r + (int64_t)S.n_r * P.z_col[S.c_off + a0 + u]] : (T)0;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (a0 + u < S.n_a) XS[S.XG_off + e + (int64_t)S.n_s * (a0 + u)] = xv[u];
@@ -1821,7 +1822,7 @@ __global__ void k_phi_add(PlanDev P, const T* __restrict__ Z, T* __restrict__ PS
     const int r = P.sel_r[S.sel_off + e];
     const int c = P.v_c[S.v_off + v];
     T* dst = PS + S.PhiG_off + e + (int64_t)S.n_s * c;
-    if (r >= 0) *dst = Z[S.Z_off + r + (int64_t)S.n_r * (S.n_a + v)] + *dst;
+    if (r >= 0) *dst = Z[S.Z_off + r + (int64_t)S.n_r * P.z_col[S.c_off + S.n_a + v]] + *dst;
     else if (P.g_v[S.g_off + e] == v) *dst = (T)1;
   }
 }
@@ -2700,7 +2701,7 @@ __global__ void k_yg_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__ 
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
     const int e = idx % S.n_g, v = idx / S.n_g;
     const int r = P.g_r[S.g_off + e];
-    YG[S.YG_off + idx] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * (S.n_a + v)]
+    YG[S.YG_off + idx] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * P.z_col[S.c_off + S.n_a + v]]
                                 : (P.g_v[S.g_off + e] == v ? (T)1 : (T)0);
   }
 }

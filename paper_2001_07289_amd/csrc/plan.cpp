@@ -578,25 +578,31 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     S.bR_off = (int64_t)plan.blocks.size();
     make_blocks(cntR, plan.block_target, 0, plan.blocks);
     S.nbR = (int)(plan.blocks.size() - S.bR_off);
-    // the basis columns reached at each r block of the forward solve: an
+    // The columns of [X | Y'] in the order the forward solve reaches them: an
     // average from its first plane on, a vertex from the plane below its own
-    // (its stiffness column touches the planes next to it)
-    for (int64_t b = S.bR_off; b < S.bR_off + S.nbR; ++b) {
-      BlockDev& B = plan.blocks[b];
-      const int last = B.plane_hi - 1;
-      B.za = 0;
-      while (B.za < na && avg_key[avg_order[B.za]] <= last) ++B.za;
-      B.zv = 0;
-      while (B.zv < nv) {
-        const int l = plan.v_loc[v_off + B.zv];
+    // (its stiffness column touches the planes next to it).  Column j of the
+    // right-hand side (an average for j < na, else vertex j - na) is stored
+    // at z_col[j]; at each r block the reached columns are a prefix.
+    {
+      std::vector<int> key(na + nv), ord(na + nv);
+      for (int a = 0; a < na; ++a) key[a] = avg_key[avg_order[a]];
+      for (int v = 0; v < nv; ++v) {
+        const int l = plan.v_loc[v_off + v];
         const int vp = pa == 2 ? l / (S.m[0] * S.m[1]) : (l / S.m[0]) % S.m[1];
-        if (std::max(vp - 1, 0) > last) break;
-        ++B.zv;
+        key[na + v] = std::max(vp - 1, 0);
       }
-    }
-    if (S.nbR > 0) {  // every column is reached by the last block
-      plan.blocks[S.bR_off + S.nbR - 1].za = na;
-      plan.blocks[S.bR_off + S.nbR - 1].zv = nv;
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key[x] < key[y]; });
+      std::vector<int32_t> zc(na + nv);
+      for (int q = 0; q < na + nv; ++q) zc[ord[q]] = q;
+      plan.z_col.insert(plan.z_col.end(), zc.begin(), zc.end());
+      for (int64_t b = S.bR_off; b < S.bR_off + S.nbR; ++b) {
+        BlockDev& B = plan.blocks[b];
+        const int last = B.plane_hi - 1;
+        B.za = 0;
+        while (B.za < na + nv && key[ord[B.za]] <= last) ++B.za;
+      }
+      if (S.nbR > 0) plan.blocks[S.bR_off + S.nbR - 1].za = na + nv;  // every column by the last block
     }
     // coupling rows between consecutive blocks of each set
     for (int setR = 0; setR < 2; ++setR) {

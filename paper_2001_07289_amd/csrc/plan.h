@@ -63,6 +63,8 @@ struct Plan {
   std::vector<SubDev> subs;
   std::vector<int32_t> loc_I, loc_r, loc_g;   // per local node: rank in I / r / Gamma entries, -1
   std::vector<int32_t> I_loc, r_loc;          // set order -> local node
+  std::vector<int32_t> z_col;                 // per local coarse entry j (average j < n_a, else
+                                              // vertex j - n_a): its column of [X | Y']
   std::vector<int32_t> kig_ptr;               // per interior node (all subdomains): its Gamma neighbours
   std::vector<int8_t> kig_t;                  //   as 27-point neighbour codes
   std::vector<int32_t> kgi_ptr;               // per Gamma entry (all subdomains): its interior neighbours

@@ -50,8 +50,8 @@ struct BlockDev {
   int64_t G_off;            // offset of its size x size matrix (ld x size storage, 16-aligned)
   int64_t cf_off;           // coupling rows of the first plane to block k-1 (-1: none)
   int64_t cb_off;           // coupling rows of the last plane to block k+1 (-1: none)
-  int za, zv;               // r blocks: the averages 0..za-1 and vertices 0..zv-1 whose basis
-                            // right-hand sides reach this block or an earlier one
+  int za;                   // r blocks: the columns 0..za-1 of [X | Y'] (in their stored
+                            // order) whose right-hand sides reach this block or an earlier one
 };
 
 // One front of the multifrontal coarse factorization.  Positions 0..p-1 are
