@@ -1757,6 +1757,8 @@ __device__ __forceinline__ double object_mean(const PlanDev& P, const T* __restr
 }
 
 // S_c[a, b] = (C_r X)[a, b]: mean of X's column b over object a's nodes.
+// S_c = C_r K_rr^{-1} C_r^T is symmetric and its sweep reads only the lower
+// triangle, so only a >= b is formed.
 template <typename T>
 __global__ void k_sc_assemble(PlanDev P, const T* __restrict__ Z, T* __restrict__ Sc) {
   const int sub = blockIdx.y;
@@ -1764,6 +1766,7 @@ __global__ void k_sc_assemble(PlanDev P, const T* __restrict__ Z, T* __restrict_
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= S.n_a * S.n_a) return;
   const int a = idx % S.n_a, b = idx / S.n_a;
+  if (a < b) return;
   const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
   Sc[S.Sc_off + idx] = (T)object_mean(P, Z + S.Z_off, S.n_r, P.z_col[S.c_off + b], pb, pe);
 }
