@@ -300,7 +300,7 @@ def main():
     dev = torch.device("cuda:0")
     nrhs = p.f.shape[0]
     if a.workload == "cfg5":
-        rho = torch.exp(prob.box_filter(torch.as_tensor(p.extra["theta"], device=dev)))
+        rho = prob.coef_from_log(torch.as_tensor(p.extra["theta"], device=dev))
     else:
         rho = torch.as_tensor(p.rho, device=dev)
     b = torch.as_tensor(np.ascontiguousarray(p.f.reshape(-1)), device=dev)

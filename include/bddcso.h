@@ -119,25 +119,44 @@ bddcso_status bddcso_problem_info(const bddcso_problem* p, int primal_mask, int6
                                   int64_t counts[3]);
 
 /*
+ * Device workspace that bddcso_setup needs for these options: every factor,
+ * basis, coarse front, plan table and per-application vector of one
+ * preconditioner, each piece 256-byte aligned.  Host only (plans the
+ * problem, no device work); the same sizes bddcso_setup lays out.
+ * Errors: EINVAL (options or plan, e.g. a coarse front above 4 GiB).
+ */
+bddcso_status bddcso_setup_workspace_size(bddcso_problem* p, const bddcso_options* opts, size_t* bytes);
+
+/*
  * Builds the preconditioner for coefficient rho (Remark 4), on the device:
  * local matrices, block factorizations of K_II and K_rr (primal vertices
  * eliminated), the constraint Schur complement, the coarse basis Phi_i, the
  * local coarse matrices Phi_i^T K_i Phi_i and the factorization of the
- * assembled coarse matrix (Section 3 with Definition 1).  Allocates the
- * device memory it needs (freed by bddcso_precond_destroy) and synchronises
- * the stream before returning.
- *   rho_dev  [n_elements] FP64 device array, > 0
- * Errors: EINVAL, ENOMEM, ESINGULAR (a pivot <= 0, e.g. a floating
- * subdomain left without enough primal constraints), EHIP.
+ * assembled coarse matrix (Section 3 with Definition 1).  Synchronises the
+ * stream before returning.
+ *   rho_dev       [n_elements] FP64 device array, > 0
+ *   workspace_dev caller-owned device memory of at least ws_bytes =
+ *                 bddcso_setup_workspace_size(...) bytes, 256-byte aligned;
+ *                 it must outlive the preconditioner and is never freed by
+ *                 the library.  NULL: the library allocates the same amount
+ *                 itself (freed by bddcso_precond_destroy).
+ * Errors: EINVAL (also: workspace too small or misaligned), ENOMEM,
+ * ESINGULAR (a pivot <= 0, e.g. a floating subdomain left without enough
+ * primal constraints), EHIP.
  */
 bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcso_options* opts,
-                           void* stream, bddcso_precond** out);
+                           void* workspace_dev, size_t ws_bytes, void* stream, bddcso_precond** out);
 
 /* Recomputes every numeric factor of an existing preconditioner for a new
  * coefficient field, reusing its plan and device memory: no allocation.
  * Enqueued on stream; pivot failures are reported by the next
- * bddcso_check_pivots or bddcso_solve. */
+ * bddcso_check_pivots or bddcso_solve.  Increments the generation. */
 bddcso_status bddcso_refactor(bddcso_precond* pc, const double* rho_dev, void* stream);
+
+/* Number of numeric setups (bddcso_setup's included) this preconditioner
+ * has gone through: a caller that keeps results tied to one set of factors
+ * (an adjoint solve after a forward solve) checks that it has not changed. */
+bddcso_status bddcso_precond_generation(const bddcso_precond* pc, int64_t* generation);
 
 /* Synchronises stream and returns ESINGULAR if the last setup/refactor met a
  * non-positive pivot. */
@@ -180,6 +199,13 @@ bddcso_status bddcso_element_grad(const bddcso_precond* pc, const double* u_dev,
 bddcso_status bddcso_box_filter(const bddcso_problem* p, const double* in_dev, double* out_dev,
                                 int transpose, void* stream);
 
+/* The coefficient of a log-coefficient field: rho_e = exp((F theta)_e), with
+ * F the 3^dim box mean of bddcso_box_filter (the smoothed log-coefficient of
+ * the adjoint workload; not in the paper).  theta_dev, rho_dev:
+ * [n_elements] FP64, distinct. */
+bddcso_status bddcso_coef_from_log(const bddcso_problem* p, const double* theta_dev, double* rho_dev,
+                                   void* stream);
+
 /* Sizes and algorithmic work of the plan for these options (host only; no
  * device work).  Flop counts are those of the symmetric sweeps (n^2 p per
  * matrix of size n with p pivots, lower triangle). */
@@ -194,7 +220,7 @@ typedef struct {
   double coarse_factor_entries;/* sum over fronts of n * p                      */
   double coarse_sweep_flops;   /* sum over fronts of n^2 p                      */
   double local_sweep_flops;    /* sum over local blocks of size^3               */
-  double device_bytes;         /* device memory a setup with these options holds */
+  double device_bytes;         /* = bddcso_setup_workspace_size                 */
 } bddcso_plan_stats;
 
 bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bddcso_plan_stats* out);

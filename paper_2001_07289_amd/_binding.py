@@ -22,6 +22,7 @@ EXPORTED = [
     "bddcso_element_grad", "bddcso_box_filter", "bddcso_precond_info", "bddcso_local_coarse",
     "bddcso_precond_destroy", "bddcso_problem_destroy", "bddcso_last_error",
     "bddcso_plan_info", "bddcso_profile", "bddcso_profile_read", "bddcso_copy_probe",
+    "bddcso_setup_workspace_size", "bddcso_precond_generation", "bddcso_coef_from_log",
 ]
 
 
@@ -71,7 +72,10 @@ def load() -> C.CDLL:
         "bddcso_default_options": (None, [C.POINTER(Options)]),
         "bddcso_problem_create": (C.c_int, [C.c_int, i64p, dp, i32p, i32p, C.POINTER(vp)]),
         "bddcso_problem_info": (C.c_int, [vp, C.c_int, i64p, i64p, i64p, C.POINTER(C.c_int), i64p]),
-        "bddcso_setup": (C.c_int, [vp, vp, C.POINTER(Options), vp, C.POINTER(vp)]),
+        "bddcso_setup_workspace_size": (C.c_int, [vp, C.POINTER(Options), C.POINTER(C.c_size_t)]),
+        "bddcso_setup": (C.c_int, [vp, vp, C.POINTER(Options), vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "bddcso_precond_generation": (C.c_int, [vp, i64p]),
+        "bddcso_coef_from_log": (C.c_int, [vp, vp, vp, vp]),
         "bddcso_refactor": (C.c_int, [vp, vp, vp]),
         "bddcso_check_pivots": (C.c_int, [vp, vp]),
         "bddcso_operator_apply": (C.c_int, [vp, vp, vp, C.c_int, vp]),

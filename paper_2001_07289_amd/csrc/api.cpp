@@ -96,23 +96,46 @@ void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e
   hi = kth(n - 1);
 }
 
+// Device memory of one preconditioner.  Three modes share one allocation
+// sequence: MALLOC (the library allocates each buffer), COUNT (host only:
+// sums the aligned sizes, returns placeholder addresses that are never
+// dereferenced, copies nothing) and CARVE (buffers are cut, in the same
+// order, from a caller-owned workspace).
+struct WorkspaceShort {
+  size_t need, have;
+};
+
 struct DevMem {
+  enum Mode { MALLOC, COUNT, CARVE } mode = MALLOC;
+  static constexpr size_t kAlign = 256;
+  char* base = nullptr;  // CARVE: the workspace
+  size_t cap = 0;        // CARVE: its size
+  size_t used = 0;       // COUNT / CARVE: bytes laid out so far
   std::vector<void*> ptrs;
   int64_t bytes = 0;
   template <typename T>
   T* alloc(int64_t n) {
     if (n <= 0) n = 1;
-    void* p = nullptr;
-    size_t b = (size_t)n * sizeof(T);
-    HIPCHK(hipMalloc(&p, b));
-    ptrs.push_back(p);
-    bytes += (int64_t)b;
-    return (T*)p;
+    const size_t b = (size_t)n * sizeof(T);
+    if (mode == MALLOC) {
+      void* p = nullptr;
+      HIPCHK(hipMalloc(&p, b));
+      ptrs.push_back(p);
+      bytes += (int64_t)b;
+      return (T*)p;
+    }
+    const size_t off = (used + kAlign - 1) / kAlign * kAlign;
+    used = off + b;
+    bytes = (int64_t)used;
+    if (mode == COUNT) return (T*)(uintptr_t)(kAlign + off);
+    if (used > cap) throw WorkspaceShort{used, cap};
+    return (T*)(base + off);
   }
   template <typename T>
   T* upload(const std::vector<T>& v, hipStream_t s) {
     T* p = alloc<T>((int64_t)v.size());
-    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    if (mode != COUNT && !v.empty())
+      HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
     return p;
   }
   void release() {
@@ -235,6 +258,7 @@ struct bddcso_precond {
   int32_t *active = nullptr, *iters = nullptr, *flags = nullptr, *nactive = nullptr;
   int32_t* h_nactive = nullptr;  // pinned
   int max_nrhs = 1;
+  int64_t generation = 0;  // numeric setups done (bddcso_refactor calls)
   EventProfiler prof;
   hipStream_t s2 = nullptr;                 // second stream of the setup
   hipStream_t s3 = nullptr;                 // third stream: the interior factors
@@ -276,9 +300,13 @@ int64_t extent(int64_t off, int rows, int cols, int ld) {
 void check_sweeps(const std::vector<SweepDesc>& v, int64_t pool, int64_t scratch_slots, const char* name) {
   if ((int64_t)v.size() > scratch_slots)
     throw PlanFail{std::string(name) + ": more problems than sweep scratch slots"};
-  for (const SweepDesc& d : v)
+  for (const SweepDesc& d : v) {
     if (d.off < 0 || d.p < 0 || d.p > d.n || d.ld < d.n || extent(d.off, d.n, d.n, d.ld) > pool)
       throw PlanFail{std::string(name) + ": sweep descriptor outside its pool"};
+    // the sweep kernels address a matrix's entries by 32-bit byte offsets
+    if ((int64_t)d.n * d.ld * (int64_t)sizeof(double) >= ((int64_t)1 << 32))
+      throw PlanFail{std::string(name) + ": a matrix of " + std::to_string(d.n) + " rows exceeds 4 GiB"};
+  }
 }
 
 // Non-transposed operands: A is m x k, B is k x n, C is m x n (column-major).
@@ -680,6 +708,231 @@ hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 }  // namespace
 
+extern "C" void bddcso_precond_destroy(bddcso_precond* pc);
+
+namespace {
+
+// Lays out (allocates, carves or counts, by pc->mem.mode) every device
+// buffer of the preconditioner and uploads the plan's tables.
+void layout(bddcso_precond* pc, hipStream_t s) {
+  const bddcso_problem* p = pc->prob;
+  const bddcso_options& o = pc->opt;
+  const Classification& c = p->c;
+  const Plan& pl = *pc->plan;
+  DevMem& m = pc->mem;
+  PlanDev& P = pc->P;
+  P.subs = m.upload(pl.subs, s);
+  P.blocks = m.upload(pl.blocks, s);
+  P.loc_I = m.upload(pl.loc_I, s);
+  P.loc_r = m.upload(pl.loc_r, s);
+  P.loc_g = m.upload(pl.loc_g, s);
+  P.I_loc = m.upload(pl.I_loc, s);
+  P.z_col = m.upload(pl.z_col, s);
+  P.kig_ptr = m.upload(pl.kig_ptr, s);
+  P.kig_t = m.upload(pl.kig_t, s);
+  P.kig_col = m.alloc<int32_t>((int64_t)pl.kig_t.size());
+  P.kig_val = m.alloc<double>((int64_t)pl.kig_t.size());
+  P.kgi_ptr = m.upload(pl.kgi_ptr, s);
+  P.kgi_t = m.upload(pl.kgi_t, s);
+  P.kgi_col = m.alloc<int32_t>((int64_t)pl.kgi_t.size());
+  P.kgi_val = m.alloc<double>((int64_t)pl.kgi_t.size());
+  P.r_loc = m.upload(pl.r_loc, s);
+  P.g_loc = m.upload(pl.g_loc, s);
+  P.g_gam = m.upload(pl.g_gam, s);
+  P.g_r = m.upload(pl.g_r, s);
+  P.loc_sel = m.upload(pl.loc_sel, s);
+  P.sel_r = m.upload(pl.sel_r, s);
+  P.g_v = m.upload(pl.g_v, s);
+  P.g_sub = m.upload(pl.g_sub, s);
+  P.v_loc = m.upload(pl.v_loc, s);
+  P.v_c = m.upload(pl.v_c, s);
+  P.a_ptr = m.upload(pl.a_ptr, s);
+  P.a_r = m.upload(pl.a_r, s);
+  P.a_c = m.upload(pl.a_c, s);
+  P.c_glob = m.upload(pl.c_glob, s);
+  P.c_kind = m.upload(pl.c_kind, s);
+  P.gam_eptr = m.upload(pl.gam_eptr, s);
+  P.gam_ent = m.upload(pl.gam_ent, s);
+  P.gam_node = m.upload(c.gam_node, s);
+  P.gam_kptr = m.upload(c.gam_kptr, s);
+  P.gam_key = m.upload(c.gam_key, s);
+  P.ss_parent = m.upload(c.ss_parent, s);
+  P.ss_eptr = m.upload(c.ss_eptr, s);
+  P.ss_elem = m.upload(c.ss_elem, s);
+  P.crs_eptr = m.upload(pl.crs_eptr, s);
+  P.crs_ent = m.upload(pl.crs_ent, s);
+  P.fronts = m.upload(pl.fronts, s);
+  P.front_idx = m.upload(pl.front_idx, s);
+  P.front_pmap = m.upload(pl.front_pmap, s);
+  P.front_imap = pl.front_imap.empty() ? nullptr : m.upload(pl.front_imap, s);
+  P.sub_fmap = m.upload(pl.sub_fmap, s);
+  P.cpl_rank = m.upload(pl.cpl_rank, s);
+  P.cpl_sub = m.upload(pl.cpl_sub, s);
+  P.cpl_loc = m.upload(pl.cpl_loc, s);
+  P.cpl_dir = m.upload(pl.cpl_dir, s);
+  P.n_cpl = (int64_t)pl.cpl_sub.size();
+  pc->cpl_coef = m.alloc<double>(P.n_cpl * 9);
+  P.cpl_coef = pc->cpl_coef;
+  std::vector<double> kh(p->khat, p->khat + 64);
+  pc->khat = m.upload(kh, s);
+  P.khat = pc->khat;
+  if (m.mode != DevMem::COUNT) HIPCHK(hipStreamSynchronize(s));
+  P.n_sub = c.n_sub;
+  P.tot_I = pl.tot_I;
+  P.tot_r = pl.tot_r;
+  P.tot_g = pl.tot_g;
+  P.tot_c = pl.tot_c;
+  P.tot_a = pl.tot_a;
+  P.n_gam = (int64_t)c.gam_node.size();
+  P.n_coarse = pl.n_coarse;
+  P.max_block = pl.max_block;
+  P.max_na = pl.max_na;
+  P.max_nc = pl.max_nc;
+  P.max_ng = pl.max_ng;
+  P.max_ns = pl.max_ns;
+  P.max_nloc = pl.max_nloc;
+  P.max_nr = pl.max_nr;
+  int max_nI = 0, max_plane = 0;
+  for (auto& S : pl.subs) max_nI = std::max(max_nI, S.n_I);
+  for (auto& B : pl.blocks) max_plane = std::max(max_plane, std::max(B.first_n, B.last_n));
+  P.max_nI = max_nI;
+  P.max_zcols = pl.max_zcols;
+  P.max_plane = max_plane;
+  P.max_nv = 0;
+  for (auto& S : pl.subs) P.max_nv = std::max(P.max_nv, S.n_v);
+  if (max_lds_bytes(P, o.precision == 1 ? 4 : 8, o.max_nrhs) > 160 * 1024)
+    throw PlanFail{"a subdomain plane or block is too large for the LDS staging of the local kernels"};
+
+  pc->rho = m.alloc<double>(c.n_elem);
+  for (auto& S : pl.subs) pc->max_nv = std::max(pc->max_nv, S.n_v);
+  pc->vcoef = m.alloc<double>(pl.tot_v * 27);
+  pc->vcode = m.alloc<int32_t>(pl.tot_v * 27);
+  pc->alpha = m.alloc<double>(c.n_ss);
+  pc->delta = m.alloc<double>(pl.tot_g);
+  pc->status = m.alloc<int32_t>(1);
+  pc->fpool = m.alloc<double>(pl.front_pool);
+  const int nr = pc->max_nrhs;
+  pc->bc = m.alloc<double>(pl.n_coarse * nr);
+  pc->uc = m.alloc<double>(pl.n_coarse * nr);
+  pc->fvec = m.alloc<double>(pl.front_vec * nr);
+  pc->xh = m.alloc<double>(pl.front_vec * nr);
+  {
+    int maxp = 1;
+    for (auto& F : pl.fronts) maxp = std::max(maxp, F.p);
+    pc->fpart = m.alloc<double>((int64_t)front_fwd_chunks(maxp) * std::min(nr, 3) * pl.front_vec);
+  }
+  if (o.precision == 1) alloc_numeric<float>(pc, s);
+  else alloc_numeric<double>(pc, s);
+  build_batches(pc, s);
+  const int64_t n = c.n_free;
+  pc->r = m.alloc<double>(n * nr);
+  pc->p = m.alloc<double>(n * nr);
+  pc->qv = m.alloc<double>(n * nr);
+  pc->z = m.alloc<double>(n * nr);
+  pc->rold = m.alloc<double>(n * nr);
+  pc->dtmp = m.alloc<double>(n * nr);
+  pc->partial = m.alloc<double>((int64_t)pc->dot_blocks * nr);
+  pc->sc = m.alloc<double>(8 * BDDCSO_MAX_RHS);
+  int maxit = std::max(o.maxit, o.fixed_iters) + 1;
+  pc->hist_a = m.alloc<double>((int64_t)maxit * nr);
+  pc->hist_b = m.alloc<double>((int64_t)maxit * nr);
+  pc->active = m.alloc<int32_t>(nr);
+  pc->iters = m.alloc<int32_t>(nr);
+  pc->flags = m.alloc<int32_t>(nr);
+  pc->nactive = m.alloc<int32_t>(1);
+}
+
+// Streams, events and the pinned flag of the convergence test (no device
+// memory of the preconditioner's own).
+void make_streams(bddcso_precond* pc) {
+  HIPCHK(hipHostMalloc((void**)&pc->h_nactive, sizeof(int32_t) * 4, hipHostMallocDefault));
+  HIPCHK(hipStreamCreateWithFlags(&pc->s2, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&pc->s3, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_fork_i, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_cpl, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_cfork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_cjoin, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_join_i, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_la, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_lb, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_lc, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_zf, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_zj, hipEventDisableTiming));
+}
+
+// Validates the options, plans, and builds a preconditioner object whose
+// device memory is laid out in the given mode.  COUNT: host only, *need gets
+// the workspace size and nothing is kept.
+bddcso_status create_precond(bddcso_problem* p, const bddcso_options* opts, DevMem::Mode mode, void* ws,
+                             size_t ws_bytes, hipStream_t s, bddcso_precond** out, size_t* need) {
+  *out = nullptr;
+  bddcso_options o;
+  if (opts) o = *opts;
+  else bddcso_default_options(&o);
+  if (o.max_nrhs < 1 || o.max_nrhs > BDDCSO_MAX_RHS) return set_err(BDDCSO_EINVAL, "max_nrhs out of range");
+  if (o.precision != 0 && o.precision != 1) return set_err(BDDCSO_EINVAL, "precision must be 0 or 1");
+  if (o.primal_mask <= 0 || o.primal_mask > 7) return set_err(BDDCSO_EINVAL, "primal_mask must be in 1..7");
+  if (o.coarse_solver != 0 && o.coarse_solver != 1) return set_err(BDDCSO_EINVAL, "coarse_solver must be 0 or 1");
+  if (o.maxit < 0 || o.fixed_iters < 0) return set_err(BDDCSO_EINVAL, "maxit and fixed_iters must be >= 0");
+  Error err;
+  std::shared_ptr<Plan> plan;
+  try {
+    plan = get_plan(p, o, err);
+  } catch (const std::bad_alloc&) {
+    return set_err(BDDCSO_ENOMEM, "host allocation failed while planning");
+  }
+  if (!plan) return set_err(BDDCSO_EINVAL, err.msg);
+  auto* pc = new (std::nothrow) bddcso_precond();
+  if (!pc) return set_err(BDDCSO_ENOMEM, "host allocation failed");
+  pc->prob = p;
+  pc->plan = plan;
+  pc->opt = o;
+  pc->precision = o.precision;
+  pc->max_nrhs = o.max_nrhs;
+  pc->mem.mode = mode;
+  pc->mem.base = (char*)ws;
+  pc->mem.cap = ws_bytes;
+  const Classification& c = p->c;
+  Geo& g = pc->geo;
+  g.dim = c.dim;
+  for (int a = 0; a < 3; ++a) {
+    g.ne[a] = (int)c.ne[a];
+    g.nf[a] = (int)c.nf[a];
+  }
+  g.n_free = c.n_free;
+  g.n_elem = c.n_elem;
+  try {
+    layout(pc, s);
+    if (mode == DevMem::COUNT) {
+      if (need) *need = pc->mem.used;
+      bddcso_precond_destroy(pc);
+      return BDDCSO_OK;
+    }
+    make_streams(pc);
+  } catch (const PlanFail& f) {
+    bddcso_precond_destroy(pc);
+    return set_err(BDDCSO_EINVAL, "inconsistent plan: " + f.what);
+  } catch (const WorkspaceShort& w) {
+    bddcso_precond_destroy(pc);
+    return set_err(BDDCSO_EINVAL, "workspace too small: " + std::to_string(w.have) + " bytes given, at least " +
+                                      std::to_string(w.need) + " needed (bddcso_setup_workspace_size)");
+  } catch (const HipFail& f) {
+    bddcso_precond_destroy(pc);
+    if (f.e == hipErrorOutOfMemory)
+      return set_err(BDDCSO_ENOMEM, "device allocation failed: " + f.where);
+    return set_err(BDDCSO_EHIP, f.where + ": " + hipGetErrorString(f.e));
+  } catch (const std::bad_alloc&) {
+    bddcso_precond_destroy(pc);
+    return set_err(BDDCSO_ENOMEM, "host allocation failed");
+  }
+  *out = pc;
+  return BDDCSO_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void bddcso_default_options(bddcso_options* o) {
@@ -771,6 +1024,7 @@ bddcso_status bddcso_refactor(bddcso_precond* pc, const double* rho_dev, void* s
   hipStream_t s = as_stream(stream);
   try {
     HIPCHK(hipMemcpyAsync(pc->rho, rho_dev, pc->geo.n_elem * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ++pc->generation;
     if (pc->precision == 1) numeric_setup<float>(pc, s);
     else numeric_setup<double>(pc, s);
     HIPCHK(hipGetLastError());
@@ -795,190 +1049,27 @@ bddcso_status bddcso_check_pivots(bddcso_precond* pc, void* stream) {
   return BDDCSO_OK;
 }
 
-bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcso_options* opts, void* stream,
-                           bddcso_precond** out) {
+bddcso_status bddcso_setup_workspace_size(bddcso_problem* p, const bddcso_options* opts, size_t* bytes) {
+  if (!p || !bytes) return set_err(BDDCSO_EINVAL, "null argument");
+  bddcso_precond* pc = nullptr;
+  size_t need = 0;
+  bddcso_status st = create_precond(p, opts, DevMem::COUNT, nullptr, 0, nullptr, &pc, &need);
+  if (st != BDDCSO_OK) return st;
+  *bytes = need;
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_setup(bddcso_problem* p, const double* rho_dev, const bddcso_options* opts,
+                           void* workspace_dev, size_t ws_bytes, void* stream, bddcso_precond** out) {
   if (!p || !rho_dev || !out) return set_err(BDDCSO_EINVAL, "null argument");
   *out = nullptr;
-  bddcso_options o;
-  if (opts) o = *opts;
-  else bddcso_default_options(&o);
-  if (o.max_nrhs < 1 || o.max_nrhs > BDDCSO_MAX_RHS) return set_err(BDDCSO_EINVAL, "max_nrhs out of range");
-  if (o.precision != 0 && o.precision != 1) return set_err(BDDCSO_EINVAL, "precision must be 0 or 1");
-  if (o.primal_mask <= 0 || o.primal_mask > 7) return set_err(BDDCSO_EINVAL, "primal_mask must be in 1..7");
-  if (o.coarse_solver != 0 && o.coarse_solver != 1) return set_err(BDDCSO_EINVAL, "coarse_solver must be 0 or 1");
-  hipStream_t s = as_stream(stream);
-  Error err;
-  std::shared_ptr<Plan> plan;
-  try {
-    plan = get_plan(p, o, err);
-  } catch (const std::bad_alloc&) {
-    return set_err(BDDCSO_ENOMEM, "host allocation failed while planning");
-  }
-  if (!plan) return set_err(BDDCSO_EINVAL, err.msg);
-  auto* pc = new (std::nothrow) bddcso_precond();
-  if (!pc) return set_err(BDDCSO_ENOMEM, "host allocation failed");
-  pc->prob = p;
-  pc->plan = plan;
-  pc->opt = o;
-  pc->precision = o.precision;
-  pc->max_nrhs = o.max_nrhs;
-  const Classification& c = p->c;
-  const Plan& pl = *plan;
-  Geo& g = pc->geo;
-  g.dim = c.dim;
-  for (int a = 0; a < 3; ++a) {
-    g.ne[a] = (int)c.ne[a];
-    g.nf[a] = (int)c.nf[a];
-  }
-  g.n_free = c.n_free;
-  g.n_elem = c.n_elem;
-  try {
-    DevMem& m = pc->mem;
-    PlanDev& P = pc->P;
-    P.subs = m.upload(pl.subs, s);
-    P.blocks = m.upload(pl.blocks, s);
-    P.loc_I = m.upload(pl.loc_I, s);
-    P.loc_r = m.upload(pl.loc_r, s);
-    P.loc_g = m.upload(pl.loc_g, s);
-    P.I_loc = m.upload(pl.I_loc, s);
-    P.z_col = m.upload(pl.z_col, s);
-    P.kig_ptr = m.upload(pl.kig_ptr, s);
-    P.kig_t = m.upload(pl.kig_t, s);
-    P.kig_col = m.alloc<int32_t>((int64_t)pl.kig_t.size());
-    P.kig_val = m.alloc<double>((int64_t)pl.kig_t.size());
-    P.kgi_ptr = m.upload(pl.kgi_ptr, s);
-    P.kgi_t = m.upload(pl.kgi_t, s);
-    P.kgi_col = m.alloc<int32_t>((int64_t)pl.kgi_t.size());
-    P.kgi_val = m.alloc<double>((int64_t)pl.kgi_t.size());
-    P.r_loc = m.upload(pl.r_loc, s);
-    P.g_loc = m.upload(pl.g_loc, s);
-    P.g_gam = m.upload(pl.g_gam, s);
-    P.g_r = m.upload(pl.g_r, s);
-    P.loc_sel = m.upload(pl.loc_sel, s);
-    P.sel_r = m.upload(pl.sel_r, s);
-    P.g_v = m.upload(pl.g_v, s);
-    P.g_sub = m.upload(pl.g_sub, s);
-    P.v_loc = m.upload(pl.v_loc, s);
-    P.v_c = m.upload(pl.v_c, s);
-    P.a_ptr = m.upload(pl.a_ptr, s);
-    P.a_r = m.upload(pl.a_r, s);
-    P.a_c = m.upload(pl.a_c, s);
-    P.c_glob = m.upload(pl.c_glob, s);
-    P.c_kind = m.upload(pl.c_kind, s);
-    P.gam_eptr = m.upload(pl.gam_eptr, s);
-    P.gam_ent = m.upload(pl.gam_ent, s);
-    P.gam_node = m.upload(c.gam_node, s);
-    P.gam_kptr = m.upload(c.gam_kptr, s);
-    P.gam_key = m.upload(c.gam_key, s);
-    P.ss_parent = m.upload(c.ss_parent, s);
-    P.ss_eptr = m.upload(c.ss_eptr, s);
-    P.ss_elem = m.upload(c.ss_elem, s);
-    P.crs_eptr = m.upload(pl.crs_eptr, s);
-    P.crs_ent = m.upload(pl.crs_ent, s);
-    P.fronts = m.upload(pl.fronts, s);
-    P.front_idx = m.upload(pl.front_idx, s);
-    P.front_pmap = m.upload(pl.front_pmap, s);
-    P.front_imap = pl.front_imap.empty() ? nullptr : m.upload(pl.front_imap, s);
-    P.sub_fmap = m.upload(pl.sub_fmap, s);
-    P.cpl_rank = m.upload(pl.cpl_rank, s);
-    P.cpl_sub = m.upload(pl.cpl_sub, s);
-    P.cpl_loc = m.upload(pl.cpl_loc, s);
-    P.cpl_dir = m.upload(pl.cpl_dir, s);
-    P.n_cpl = (int64_t)pl.cpl_sub.size();
-    pc->cpl_coef = m.alloc<double>(P.n_cpl * 9);
-    P.cpl_coef = pc->cpl_coef;
-    std::vector<double> kh(p->khat, p->khat + 64);
-    pc->khat = m.upload(kh, s);
-    P.khat = pc->khat;
-    HIPCHK(hipStreamSynchronize(s));
-    P.n_sub = c.n_sub;
-    P.tot_I = pl.tot_I;
-    P.tot_r = pl.tot_r;
-    P.tot_g = pl.tot_g;
-    P.tot_c = pl.tot_c;
-    P.tot_a = pl.tot_a;
-    P.n_gam = (int64_t)c.gam_node.size();
-    P.n_coarse = pl.n_coarse;
-    P.max_block = pl.max_block;
-    P.max_na = pl.max_na;
-    P.max_nc = pl.max_nc;
-    P.max_ng = pl.max_ng;
-    P.max_ns = pl.max_ns;
-    P.max_nloc = pl.max_nloc;
-    P.max_nr = pl.max_nr;
-    int max_nI = 0, max_plane = 0;
-    for (auto& S : pl.subs) max_nI = std::max(max_nI, S.n_I);
-    for (auto& B : pl.blocks) max_plane = std::max(max_plane, std::max(B.first_n, B.last_n));
-    P.max_nI = max_nI;
-    P.max_zcols = pl.max_zcols;
-    P.max_plane = max_plane;
-    P.max_nv = 0;
-    for (auto& S : pl.subs) P.max_nv = std::max(P.max_nv, S.n_v);
-    if (max_lds_bytes(P, o.precision == 1 ? 4 : 8, o.max_nrhs) > 160 * 1024)
-      throw PlanFail{"a subdomain plane or block is too large for the LDS staging of the local kernels"};
-
-    pc->rho = m.alloc<double>(c.n_elem);
-    for (auto& S : pl.subs) pc->max_nv = std::max(pc->max_nv, S.n_v);
-    pc->vcoef = m.alloc<double>(pl.tot_v * 27);
-    pc->vcode = m.alloc<int32_t>(pl.tot_v * 27);
-    pc->alpha = m.alloc<double>(c.n_ss);
-    pc->delta = m.alloc<double>(pl.tot_g);
-    pc->status = m.alloc<int32_t>(1);
-    pc->fpool = m.alloc<double>(pl.front_pool);
-    const int nr = pc->max_nrhs;
-    pc->bc = m.alloc<double>(pl.n_coarse * nr);
-    pc->uc = m.alloc<double>(pl.n_coarse * nr);
-    pc->fvec = m.alloc<double>(pl.front_vec * nr);
-    pc->xh = m.alloc<double>(pl.front_vec * nr);
-    {
-      int maxp = 1;
-      for (auto& F : pl.fronts) maxp = std::max(maxp, F.p);
-      pc->fpart = m.alloc<double>((int64_t)front_fwd_chunks(maxp) * std::min(nr, 3) * pl.front_vec);
-    }
-    if (o.precision == 1) alloc_numeric<float>(pc, s);
-    else alloc_numeric<double>(pc, s);
-    build_batches(pc, s);
-    const int64_t n = c.n_free;
-    pc->r = m.alloc<double>(n * nr);
-    pc->p = m.alloc<double>(n * nr);
-    pc->qv = m.alloc<double>(n * nr);
-    pc->z = m.alloc<double>(n * nr);
-    pc->rold = m.alloc<double>(n * nr);
-    pc->dtmp = m.alloc<double>(n * nr);
-    pc->partial = m.alloc<double>((int64_t)pc->dot_blocks * nr);
-    pc->sc = m.alloc<double>(8 * BDDCSO_MAX_RHS);
-    int maxit = std::max(o.maxit, o.fixed_iters) + 1;
-    pc->hist_a = m.alloc<double>((int64_t)maxit * nr);
-    pc->hist_b = m.alloc<double>((int64_t)maxit * nr);
-    pc->active = m.alloc<int32_t>(nr);
-    pc->iters = m.alloc<int32_t>(nr);
-    pc->flags = m.alloc<int32_t>(nr);
-    pc->nactive = m.alloc<int32_t>(1);
-    HIPCHK(hipHostMalloc((void**)&pc->h_nactive, sizeof(int32_t) * 4, hipHostMallocDefault));
-    HIPCHK(hipStreamCreateWithFlags(&pc->s2, hipStreamNonBlocking));
-    HIPCHK(hipStreamCreateWithFlags(&pc->s3, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_fork_i, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_cpl, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_cfork, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_cjoin, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_join_i, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_fork, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_join, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_la, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_lb, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_lc, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_zf, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&pc->ev_zj, hipEventDisableTiming));
-  } catch (const PlanFail& f) {
-    bddcso_precond_destroy(pc);
-    return set_err(BDDCSO_EINVAL, "inconsistent plan: " + f.what);
-  } catch (const HipFail& f) {
-    bddcso_precond_destroy(pc);
-    if (f.e == hipErrorOutOfMemory)
-      return set_err(BDDCSO_ENOMEM, "device allocation failed: " + f.where);
-    return set_err(BDDCSO_EHIP, f.where + ": " + hipGetErrorString(f.e));
-  }
-  bddcso_status st = bddcso_refactor(pc, rho_dev, stream);
+  if (workspace_dev && ((uintptr_t)workspace_dev % DevMem::kAlign))
+    return set_err(BDDCSO_EINVAL, "workspace must be 256-byte aligned");
+  bddcso_precond* pc = nullptr;
+  bddcso_status st = create_precond(p, opts, workspace_dev ? DevMem::CARVE : DevMem::MALLOC, workspace_dev,
+                                    ws_bytes, as_stream(stream), &pc, nullptr);
+  if (st != BDDCSO_OK) return st;
+  st = bddcso_refactor(pc, rho_dev, stream);
   if (st == BDDCSO_OK) st = bddcso_check_pivots(pc, stream);
   if (st != BDDCSO_OK) {
     std::string msg = g_last_error;
@@ -1153,8 +1244,30 @@ bddcso_status bddcso_box_filter(const bddcso_problem* p, const double* in, doubl
   }
   g.n_free = p->c.n_free;
   g.n_elem = p->c.n_elem;
-  launch_box_filter(g, in, out, transpose, as_stream(stream));
+  launch_box_filter(g, in, out, transpose ? 1 : 0, as_stream(stream));
   if (hipGetLastError() != hipSuccess) return set_err(BDDCSO_EHIP, "box filter launch failed");
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_coef_from_log(const bddcso_problem* p, const double* theta, double* rho, void* stream) {
+  if (!p || !theta || !rho) return set_err(BDDCSO_EINVAL, "null argument");
+  if (theta == rho) return set_err(BDDCSO_EINVAL, "theta and rho must be distinct");
+  Geo g{};
+  g.dim = p->c.dim;
+  for (int a = 0; a < 3; ++a) {
+    g.ne[a] = (int)p->c.ne[a];
+    g.nf[a] = (int)p->c.nf[a];
+  }
+  g.n_free = p->c.n_free;
+  g.n_elem = p->c.n_elem;
+  launch_box_filter(g, theta, rho, 2, as_stream(stream));
+  if (hipGetLastError() != hipSuccess) return set_err(BDDCSO_EHIP, "box filter launch failed");
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_precond_generation(const bddcso_precond* pc, int64_t* generation) {
+  if (!pc || !generation) return set_err(BDDCSO_EINVAL, "null argument");
+  *generation = pc->generation;
   return BDDCSO_OK;
 }
 
@@ -1186,22 +1299,11 @@ bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bd
   out->max_block = pl.max_block;
   for (const BlockDev& B : pl.blocks) out->local_sweep_flops += (double)B.size * B.size * B.size;
   for (const SubDev& S : pl.subs) out->local_sweep_flops += (double)S.n_a * S.n_a * S.n_a;
-  const double ts = o.precision == 1 ? 4.0 : 8.0;
-  const double nr = std::max(o.max_nrhs, 1);
-  const double ns = (double)pl.subs.size();
-  int max_plane = 0;
-  for (auto& B : pl.blocks) max_plane = std::max(max_plane, std::max(B.first_n, B.last_n));
-  double tpool = pl.pool_G + pl.pool_Z + pl.pool_XG + pl.pool_Sc + 2.0 * pl.pool_T + pl.pool_PhiG + pl.pool_YG +
-                 pl.pool_Kc + ns * ((double)max_plane * max_plane + (double)pl.max_block * std::max(pl.max_zcols, 1) +
-                                    2.0 * std::max(2.0 * ((double)std::max(pl.max_block, pl.max_na) * kSweepNB + kSweepNB * kSweepNB), (double)std::max(pl.max_block, pl.max_na) * kSlab)) +
-                 nr * (pl.tot_I + pl.tot_r + 3.0 * pl.tot_g + 2.0 * pl.tot_a + pl.tot_c);
-  // interior-Gamma couplings: a code, a column and a value per entry; the
-  // fronts' gather maps (int32)
-  const double kig = (double)(pl.kig_t.size() + pl.kgi_t.size()) * 13.0 +
-                     4.0 * (double)(pl.kig_ptr.size() + pl.kgi_ptr.size() + pl.front_imap.size());
-  double dpool = (double)pl.front_pool + 2.0 * nr * pl.front_vec + 2.0 * nr * pl.n_coarse +
-                 9.0 * pl.cpl_sub.size() + 6.0 * nr * p->c.n_free + p->c.n_elem + pl.tot_g + kig / 8.0;
-  out->device_bytes = ts * tpool + 8.0 * dpool;
+  bddcso_precond* tmp = nullptr;
+  size_t need = 0;
+  bddcso_status st = create_precond(p, &o, DevMem::COUNT, nullptr, 0, nullptr, &tmp, &need);
+  if (st != BDDCSO_OK) return st;
+  out->device_bytes = (double)need;
   return BDDCSO_OK;
 }
 

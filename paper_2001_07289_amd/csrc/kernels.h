@@ -183,7 +183,8 @@ int front_fwd_chunks(int maxp);
 
 void launch_element_grad(const Geo& g, const double* khat, const double* rho, const double* u,
                          const double* lam, double* out, int nrhs, hipStream_t s);
-void launch_box_filter(const Geo& g, const double* in, double* out, int transpose, hipStream_t s);
+// mode 0: box mean F; 1: its transpose; 2: exp of the box mean
+void launch_box_filter(const Geo& g, const double* in, double* out, int mode, hipStream_t s);
 
 }  // namespace bddcso
 

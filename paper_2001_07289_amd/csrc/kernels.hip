@@ -3207,7 +3207,11 @@ __device__ __forceinline__ int filter_count(const Geo& g, int ex, int ey, int ez
   return cx * cy * cz;
 }
 
-__global__ void k_box_filter(Geo g, const double* __restrict__ in, double* __restrict__ out, int transpose) {
+// mode 0: out = F in (the 3^dim box mean over in-domain neighbours);
+// mode 1: out = F^T in; mode 2: out = exp(F in), the coefficient of a
+// log-coefficient field.
+__global__ void k_box_filter(Geo g, const double* __restrict__ in, double* __restrict__ out, int mode) {
+  const bool transpose = mode == 1;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= g.n_elem) return;
   const int ex = (int)(e % g.ne[0]);
@@ -3223,7 +3227,11 @@ __global__ void k_box_filter(Geo g, const double* __restrict__ in, double* __res
         int64_t e2 = x + (int64_t)g.ne[0] * (y + (int64_t)g.ne[1] * z);
         s += transpose ? in[e2] / (double)filter_count(g, x, y, z) : in[e2];
       }
-  out[e] = transpose ? s : s / (double)filter_count(g, ex, ey, ez);
+  if (transpose) out[e] = s;
+  else {
+    const double m = s / (double)filter_count(g, ex, ey, ez);
+    out[e] = mode == 2 ? exp(m) : m;
+  }
 }
 
 }  // namespace
@@ -3765,8 +3773,8 @@ void launch_element_grad(const Geo& g, const double* khat, const double* rho, co
                          const double* lam, double* out, int nrhs, hipStream_t s) {
   k_element_grad<<<cdiv(g.n_elem, 256), 256, 0, s>>>(g, khat, rho, u, lam, out, nrhs);
 }
-void launch_box_filter(const Geo& g, const double* in, double* out, int transpose, hipStream_t s) {
-  k_box_filter<<<cdiv(g.n_elem, 256), 256, 0, s>>>(g, in, out, transpose);
+void launch_box_filter(const Geo& g, const double* in, double* out, int mode, hipStream_t s) {
+  k_box_filter<<<cdiv(g.n_elem, 256), 256, 0, s>>>(g, in, out, mode);
 }
 
 template struct Kern<double>;

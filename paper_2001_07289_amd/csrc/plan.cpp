@@ -416,6 +416,17 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
         cntR[plane]++;
       }
     }
+    // The local Neumann matrices are made definite by eliminating the
+    // primal point constraints: a subdomain away from the Dirichlet boundary
+    // (its local matrix holds the constants in its kernel) needs one.
+    bool floating = true;
+    for (int a = 0; a < dim; ++a)
+      if (b[a] == 0 || b[3 + a] == (int)c.ne[a]) floating = false;
+    if (floating && nv == 0)
+      return fail(err, -1, "subdomain " + std::to_string(s) +
+                               " does not touch the Dirichlet boundary and has no primal point constraint "
+                               "(a selected vertex or single-node object): its constrained Neumann problem "
+                               "needs one here (choose a primal_mask with vertices)");
     std::sort(local_coarse.begin(), local_coarse.end());
     local_coarse.erase(std::unique(local_coarse.begin(), local_coarse.end()), local_coarse.end());
     S.n_I = nI;
@@ -877,6 +888,17 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
   }
   if (!plan.front_gather)
     for (auto& F : plan.fronts) F.nsrc = -1;
+  // The front kernels address one front's FP64 entries with 32-bit byte
+  // offsets (the front's base pointer is 64-bit): every front must stay
+  // below 4 GiB, i.e. fewer than 23,170 rows.
+  for (int t = 0; t < nfr; ++t) {
+    const FrontDev& F = plan.fronts[t];
+    if ((int64_t)F.n * F.n * (int64_t)sizeof(double) >= ((int64_t)1 << 32))
+      return fail(err, -1, "coarse front " + std::to_string(t) + " has " + std::to_string(F.n) +
+                               " rows: its " + std::to_string((int64_t)F.n * F.n * 8) +
+                               " bytes exceed the 4 GiB a front may hold (choose the nested-dissection "
+                               "coarse solver, or fewer coarse dofs)");
+  }
   plan.front_pool = off;
   plan.front_vec = voff;
   plan.front_idx_total = ioff;

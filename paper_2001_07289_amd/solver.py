@@ -91,6 +91,20 @@ class Problem:
         B.check(B.load().bddcso_plan_info(self._h, C.byref(o), C.byref(st)))
         return {name: getattr(st, name) for name, _ in B.PlanStats._fields_}
 
+    def workspace_size(self, options: Optional[B.Options] = None, **kw) -> int:
+        """Device bytes a setup with these options needs (bddcso_setup_workspace_size)."""
+        o = options if options is not None else default_options(**kw)
+        n = C.c_size_t()
+        B.check(B.load().bddcso_setup_workspace_size(self._h, C.byref(o), C.byref(n)))
+        return n.value
+
+    def coef_from_log(self, theta: torch.Tensor, stream=None) -> torch.Tensor:
+        """rho = exp(F theta), F the 3^dim box mean (bddcso_coef_from_log)."""
+        _f64_cuda(theta, "theta")
+        out = torch.empty_like(theta)
+        B.check(B.load().bddcso_coef_from_log(self._h, _ptr(theta), _ptr(out), _stream(stream)))
+        return out
+
     def box_filter(self, x: torch.Tensor, transpose: bool = False, stream=None) -> torch.Tensor:
         _f64_cuda(x, "x")
         out = torch.empty_like(x)
@@ -105,18 +119,37 @@ class Problem:
 
 
 class Preconditioner:
-    """Device factors of one setup (bddcso_setup / bddcso_refactor)."""
+    """Device factors of one setup (bddcso_setup / bddcso_refactor).
+
+    The device memory is a PyTorch-owned workspace of
+    ``bddcso_setup_workspace_size`` bytes on rho's device, kept alive with
+    the preconditioner (``workspace=False`` lets the library allocate it).
+    """
 
     def __init__(self, problem: Problem, rho: torch.Tensor, options: Optional[B.Options] = None,
-                 stream=None, **kw):
+                 stream=None, workspace: bool = True, **kw):
         self.problem = problem
         self.options = options if options is not None else default_options(**kw)
         _f64_cuda(rho, "rho")
+        self._ws = None
+        ws_ptr, ws_bytes = None, 0
+        if workspace:
+            ws_bytes = problem.workspace_size(self.options)
+            # the caching allocator returns blocks aligned to at least 512 bytes
+            self._ws = torch.empty(ws_bytes, dtype=torch.uint8, device=rho.device)
+            ws_ptr = C.c_void_p(self._ws.data_ptr())
         out = C.c_void_p()
-        B.check(B.load().bddcso_setup(problem._h, _ptr(rho), C.byref(self.options), _stream(stream),
-                                      C.byref(out)))
+        B.check(B.load().bddcso_setup(problem._h, _ptr(rho), C.byref(self.options), ws_ptr, ws_bytes,
+                                      _stream(stream), C.byref(out)))
         self._h = out
         self.n_free = problem.n_free
+
+    @property
+    def generation(self) -> int:
+        """Numeric setups done so far (bddcso_precond_generation)."""
+        g = C.c_int64()
+        B.check(B.load().bddcso_precond_generation(self._h, C.byref(g)))
+        return g.value
 
     def refactor(self, rho: torch.Tensor, stream=None) -> None:
         _f64_cuda(rho, "rho")
@@ -205,6 +238,7 @@ class Preconditioner:
         if h is not None and h.value:
             B.load().bddcso_precond_destroy(h)
             self._h = None
+        self._ws = None  # released only after the library has let go of it
 
 
 class BDDCSOSolve(torch.autograd.Function):
@@ -212,24 +246,30 @@ class BDDCSOSolve(torch.autograd.Function):
 
     Backward: the adjoint solve A lambda = dL/du with the same BDDC-SO
     preconditioner (A is symmetric), then dL/dtheta = F^T (rho * g) with
-    g_e = -lambda_e^T K^_e u_e from the element kernel.
+    g_e = -lambda_e^T K^_e u_e from the element kernel.  The forward's rho
+    is kept: when the preconditioner has been refactored since (another
+    forward on it), the backward refactors it from that rho first, so the
+    gradient always belongs to its own forward.
     """
 
     @staticmethod
     def forward(ctx, theta, f, pc: Preconditioner):
-        prob = pc.problem
-        rho = torch.exp(prob.box_filter(theta.contiguous()))
+        rho = pc.problem.coef_from_log(theta.detach().contiguous())
         pc.refactor(rho)
         u, st = pc.solve(f.contiguous())
         ctx.pc = pc
         ctx.stats = st
-        ctx.save_for_backward(u)
+        ctx.generation = pc.generation
+        ctx.save_for_backward(u, rho)
         return u
 
     @staticmethod
     def backward(ctx, grad_u):
-        (u,) = ctx.saved_tensors
+        u, rho = ctx.saved_tensors
         pc = ctx.pc
+        if pc.generation != ctx.generation:
+            pc.refactor(rho)
+            ctx.generation = pc.generation
         lam, _ = pc.solve(grad_u.contiguous())
         g = pc.element_grad(u, lam)           # -rho_e lam_e^T K^_e u_e = dL/dtheta~_e
         return pc.problem.box_filter(g, transpose=True), None, None

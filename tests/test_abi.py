@@ -84,3 +84,48 @@ def test_default_options():
     o = pk.default_options()
     assert (o.primal_mask, o.weighting, o.precision, o.coarse_solver, o.max_nrhs) == (7, 1, 0, 0, 1)
     assert o.rtol == 1e-8 and o.maxit == 1000
+
+
+def test_workspace_size_matches_plan_info():
+    """bddcso_setup_workspace_size is host-only and equals the device bytes
+    the plan reports; more right-hand sides need more workspace."""
+    p = W.config1()
+    prob = pk.Problem.from_workload(p)
+    n1 = prob.workspace_size()
+    assert n1 > 0 and n1 % 1 == 0
+    assert prob.plan_stats()["device_bytes"] == n1
+    assert prob.workspace_size(max_nrhs=4) > n1
+
+
+def test_front_above_4gib_is_refused():
+    """The front kernels address a front's entries with 32-bit byte offsets:
+    one dense front of the 96^3 problem's 39,823 coarse dofs (12.7 GB) is
+    refused by the planner, while its nested-dissection fronts are accepted
+    and stay below 23,170 rows."""
+    p = W.config2()
+    prob = pk.Problem.from_workload(p)
+    with pytest.raises(pk.BDDCSOError) as e:
+        prob.plan_stats(coarse_solver=1)
+    assert e.value.name == "EINVAL" and "4 GiB" in str(e.value)
+    with pytest.raises(pk.BDDCSOError):
+        prob.workspace_size(coarse_solver=1)
+    st = prob.plan_stats(coarse_solver=0)
+    assert st["n_coarse"] == 39823 and st["max_front"] < 23170
+
+
+def test_vertex_free_floating_subdomain_is_refused():
+    """A primal set without point constraints leaves a subdomain that does
+    not touch the Dirichlet boundary with a singular local Neumann matrix in
+    this build (it eliminates primal vertices): the planner refuses it,
+    while a partition whose subdomains all touch the boundary is accepted."""
+    p = W.config2_like(n=18, H=6, L=3, log_range=None)   # 3^3 subdomains: the centre one floats
+    prob = pk.Problem.from_workload(p)
+    for mask in (2, 4, 6):
+        with pytest.raises(pk.BDDCSOError) as e:
+            prob.plan_stats(primal_mask=mask)
+        assert e.value.name == "EINVAL" and "Dirichlet" in str(e.value)
+    for mask in (1, 3, 5, 7):
+        assert prob.plan_stats(primal_mask=mask)["n_coarse"] > 0
+    q = pk.Problem.from_workload(W.config2_like(n=12, H=6, L=3, log_range=None))
+    for mask in range(1, 8):
+        assert q.plan_stats(primal_mask=mask)["n_coarse"] > 0

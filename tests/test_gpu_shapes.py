@@ -1,0 +1,216 @@
+"""GPU parity against the oracle at the headline workload's subdomain shapes,
+for the many-right-hand-side kernels, and for partial primal sets.
+
+* The 48^3 sample has exactly the 96^3 workload's subdomains: 4^3
+  subdomains of 12^3 elements, subobjects of 4h, log10(rho) ~ U[-3, 3] per
+  subdomain.  That means 169-node plane blocks, 162 averages and 218 local
+  coarse dofs in an interior subdomain, and coarse fronts large enough for
+  the slab path of the front sweeps.
+* Six and 34 right-hand sides run the many-RHS block solves, front solves
+  and coarse right-hand sides (32-column chunks: 34 leaves a ragged chunk).
+* Primal sets other than "vef" (Remark 5), on partitions where every
+  subdomain has a point constraint or touches the Dirichlet boundary.
+
+Tolerances as in test_gpu_parity: apply 1e-11, iterates at equal counts
+1e-10, iterations within 1, kappa within 1%; FP32 locals with flexible FP64
+CG reach the oracle's solution to 1e-6.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bddc, pcg, q1
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def pk():
+    import paper_2001_07289_amd as m
+    return m
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def sample():
+    p = W.config2_like(48, 12, 4, cfg=2, name="cfg2_sample")
+    orc = bddc.from_problem(p)
+    ref = pcg.solve(orc, p.f[0], rtol=1e-8)
+    prob = pk().Problem.from_workload(p)
+    print(f"\n[sample] 48^3, {p.n_free} dofs, oracle {ref.iters} iterations, kappa {ref.kappa:.4f}", flush=True)
+    return p, orc, ref, prob
+
+
+def test_sample_shapes(sample):
+    p, orc, ref, prob = sample
+    st = prob.plan_stats()
+    assert st["max_block"] == 169
+    assert max(len(L.coarse) for L in orc.locals) == 218
+    assert st["max_front"] > 272          # the slab path of the front sweeps runs
+    assert st["n_coarse"] == orc.cls.n_coarse
+
+
+def test_sample_pcg_fixed_iters(sample):
+    p, orc, ref, prob = sample
+    pcf = pk().Preconditioner(prob, dev(p.rho), fixed_iters=ref.iters)
+    x, _ = pcf.solve(dev(p.f[0]))
+    e = relerr(host(x), ref.x)
+    print(f"[sample] fixed {ref.iters} iterations: rel err {e:.2e}", flush=True)
+    assert e <= 1e-10
+
+
+def test_sample_pcg_free_run(sample):
+    p, orc, ref, prob = sample
+    pc = pk().Preconditioner(prob, dev(p.rho))
+    x, st = pc.solve(dev(p.f[0]))
+    print(f"[sample] free run: {st['iters'][0]} iterations, kappa {st['kappa'][0]:.5f} "
+          f"(oracle {ref.iters}, {ref.kappa:.5f})", flush=True)
+    assert abs(st["iters"][0] - ref.iters) <= 1
+    assert abs(st["kappa"][0] - ref.kappa) <= 0.01 * ref.kappa
+    A = q1.assemble(p.n_el, p.h, p.rho)
+    assert np.linalg.norm(p.f[0] - A @ host(x)) <= 1.0001e-8 * np.linalg.norm(p.f[0])
+
+
+def test_sample_mixed(sample):
+    p, orc, ref, prob = sample
+    pc = pk().Preconditioner(prob, dev(p.rho), precision=1)
+    x, st = pc.solve(dev(p.f[0]))
+    A = q1.assemble(p.n_el, p.h, p.rho)
+    xr = host(x)
+    e = relerr(xr, ref.x)
+    print(f"[sample] mixed: {st['iters'][0]} iterations, rel err vs oracle {e:.2e}", flush=True)
+    assert np.linalg.norm(p.f[0] - A @ xr) <= 1.0001e-8 * np.linalg.norm(p.f[0])
+    assert st["iters"][0] <= ref.iters + 3
+    assert e <= 1e-6
+
+
+@pytest.mark.parametrize("coarse_solver", [0, 1], ids=["nd", "dense"])
+def test_sample_apply(sample, coarse_solver):
+    p, orc, ref, prob = sample
+    pc = pk().Preconditioner(prob, dev(p.rho), coarse_solver=coarse_solver)
+    r = W.rng(96, 0).standard_normal((2, p.n_free))
+    pc2 = pk().Preconditioner(prob, dev(p.rho), coarse_solver=coarse_solver, max_nrhs=2)
+    z1 = host(pc.apply(dev(r[0])))
+    z2 = host(pc2.apply(dev(r))).reshape(2, -1)
+    for k, z in ((0, z1), (0, z2[0]), (1, z2[1])):
+        assert relerr(z, orc.apply(r[k])) <= 1e-11
+
+
+def test_sample_apply_counting_weights(sample):
+    p, orc, ref, prob = sample
+    orc0 = bddc.from_problem(p, weighting=0)
+    pc = pk().Preconditioner(prob, dev(p.rho), weighting=0)
+    r = W.rng(95, 0).standard_normal(p.n_free)
+    assert relerr(host(pc.apply(dev(r))), orc0.apply(r)) <= 1e-11
+
+
+def test_sample_local_coarse_interior(sample):
+    p, orc, ref, prob = sample
+    pc = pk().Preconditioner(prob, dev(p.rho))
+    interior = 1 + 4 + 16  # subdomain (1, 1, 1): no Dirichlet face
+    for sub in (0, interior, 63):
+        kc, ids = pc.local_coarse(sub, cap=512)
+        L = orc.locals[sub]
+        assert np.array_equal(ids, L.coarse)
+        assert np.abs(kc - L.Kc).max() <= 1e-11 * np.abs(L.Kc).max(), sub
+
+
+@pytest.mark.parametrize("nrhs,n,H,L,cfg", [(6, 24, 6, 3, 57), (34, 12, 6, 3, 59)], ids=["6rhs_24", "34rhs_12"])
+def test_many_rhs_fp64_match_oracle(nrhs, n, H, L, cfg):
+    """Every column of an FP64 many-RHS solve (the MFMA block, front and
+    coarse-RHS kernels) against the oracle at an equal iteration count, and
+    the free-running lockstep solve column by column."""
+    p = W.config2_like(n=n, H=H, L=L, cfg=cfg)
+    F = W.rng(cfg, 0).uniform(-1, 1, (nrhs, p.n_free))
+    F[1] *= 1e-3
+    orc = bddc.from_problem(p)
+    refs = [pcg.solve(orc, F[k], rtol=1e-8) for k in range(nrhs)]
+    kfix = max(r.iters for r in refs)
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    pcf = m.Preconditioner(prob, dev(p.rho), max_nrhs=nrhs, fixed_iters=kfix)
+    X, _ = pcf.solve(dev(F))
+    Xh = host(X).reshape(nrhs, -1)
+    for k in range(nrhs):
+        rk = pcg.solve(orc, F[k], fixed_iters=kfix)
+        assert relerr(Xh[k], rk.x) <= 1e-10, k
+    pc = m.Preconditioner(prob, dev(p.rho), max_nrhs=nrhs)
+    X, st = pc.solve(dev(F))
+    Xh = host(X).reshape(nrhs, -1)
+    for k in range(nrhs):
+        assert abs(st["iters"][k] - refs[k].iters) <= 1, k
+        rk = refs[k] if st["iters"][k] == refs[k].iters else pcg.solve(orc, F[k], fixed_iters=st["iters"][k])
+        assert relerr(Xh[k], rk.x) <= 1e-10, k
+
+
+def test_many_rhs_apply_match_oracle():
+    p = W.config2_like(n=24, H=6, L=3, cfg=60)
+    R = W.rng(60, 0).standard_normal((6, p.n_free))
+    orc = bddc.from_problem(p)
+    m = pk()
+    pc = m.Preconditioner(m.Problem.from_workload(p), dev(p.rho), max_nrhs=6)
+    Z = host(pc.apply(dev(R))).reshape(6, -1)
+    for k in range(6):
+        assert relerr(Z[k], orc.apply(R[k])) <= 1e-11, k
+
+
+def _mask_cases():
+    out = []
+    # 2^3 subdomains: every subdomain touches the Dirichlet boundary
+    for mask in range(1, 7):
+        out.append((f"2x2x2_m{mask}", 12, mask))
+    # 3^3 subdomains: the floating centre needs a vertex
+    for mask in (1, 3, 5):
+        out.append((f"3x3x3_m{mask}", 18, mask))
+    return out
+
+
+@pytest.mark.parametrize("name,n,mask", _mask_cases(), ids=[c[0] for c in _mask_cases()])
+def test_apply_partial_primal_sets(name, n, mask):
+    p = W.config2_like(n=n, H=6, L=3, cfg=58)
+    orc = bddc.from_problem(p, primal_mask=mask)
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    r = W.rng(58, 0).standard_normal(p.n_free)
+    zo = orc.apply(r)
+    for cs in (0, 1):
+        pc = m.Preconditioner(prob, dev(p.rho), primal_mask=mask, coarse_solver=cs)
+        assert relerr(host(pc.apply(dev(r))), zo) <= 1e-11, (name, cs)
+
+
+def test_pcg_partial_primal_set():
+    """Vertices and faces only (mask 5): iterates at the oracle's count."""
+    p = W.config2_like(n=18, H=6, L=3, cfg=61)
+    orc = bddc.from_problem(p, primal_mask=5)
+    ref = pcg.solve(orc, p.f[0], rtol=1e-8)
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    pcf = m.Preconditioner(prob, dev(p.rho), primal_mask=5, fixed_iters=ref.iters)
+    x, _ = pcf.solve(dev(p.f[0]))
+    assert relerr(host(x), ref.x) <= 1e-10
+    pc = m.Preconditioner(prob, dev(p.rho), primal_mask=5)
+    _, st = pc.solve(dev(p.f[0]))
+    assert abs(st["iters"][0] - ref.iters) <= 1
+
+
+def test_fig1_coefficient_weights():
+    """Figure 1's asymmetric split with a coefficient 2^j on subsubdomain j:
+    the coefficient weights of Remark 4 on unequal keys."""
+    p = W.fig1_problem()
+    p.rho = 2.0 ** p.elem_subsub
+    orc = bddc.from_problem(p, weighting=1)
+    m = pk()
+    pc = m.Preconditioner(m.Problem.from_workload(p), dev(p.rho), weighting=1)
+    r = W.rng(62, 0).standard_normal(p.n_free)
+    assert relerr(host(pc.apply(dev(r))), orc.apply(r)) <= 1e-11

@@ -32,7 +32,7 @@ def test_algorithmic_equals_definitional(name, p):
 def test_partial_primal_sets():
     # Edges-only and faces-only selections (Remark on acceptable paths) still match Definition 1.
     p = W.config2_like(n=12, H=6, L=3, cfg=14, log_range=None)
-    for mask in (2, 3, 4, 5):
+    for mask in (1, 2, 3, 4, 5, 6):
         alg = bddc.from_problem(p, primal_mask=mask).dense()
         ref = definitional.bddc_dense(p.n_el, p.h, p.elem_sub, p.elem_subsub, p.rho, primal_mask=mask)
         assert np.linalg.norm(alg - ref) <= 1e-11 * np.linalg.norm(ref), mask
@@ -123,16 +123,30 @@ def test_kappa_bounded_at_fixed_L_over_h():
 
 
 def test_contrast_robustness_aligned():
-    """Remark 4: rho constant per subdomain (so per subsubdomain) with the
-    coefficient weights; iterations do not grow with the contrast."""
-    its = []
-    for hi in (0.0, 2.0, 4.0, 6.0):
+    """Remark 4: a coefficient constant on each subdomain (so on each
+    subsubdomain), contrasts 10^0, 10^3, 10^6 on a 24^3 mesh with 3^3
+    subdomains of 8^3 and subobjects of 4h (not every interface dof is
+    primal).  With the coefficient weights the iteration count stays within
+    1 of itself; with the counting weights of eq. (W) it is strictly worse
+    at the large contrasts (the weights are on the wrong side)."""
+    rho_its, count_its = [], []
+    for hi in (0.0, 3.0, 6.0):
+        p = W.config2_like(n=24, H=8, L=4, cfg=19, log_range=(-hi / 2, hi / 2))
+        for w, its in ((1, rho_its), (0, count_its)):
+            r = pcg.solve(bddc.from_problem(p, weighting=w), p.f[0], rtol=1e-8, maxit=30)
+            its.append(r.iters if r.converged else 10 ** 6)
+    assert max(rho_its) - min(rho_its) <= 1 and max(rho_its) < 10
+    assert count_its[0] == rho_its[0]          # equal weights at rho = const
+    assert count_its[1] > 3 * rho_its[1] and count_its[2] > 3 * rho_its[2]
+
+
+def test_every_interface_dof_primal_is_exact_at_any_contrast():
+    """Exactness pin (L = 2h, every interface node its own primal object):
+    W~ = U, so one iteration at any contrast and with either weights."""
+    for hi in (0.0, 6.0):
         p = W.config2_like(n=16, H=4, L=2, cfg=19, log_range=(-hi / 2, hi / 2))
-        p2 = W.tensor_problem(p.n_el, [W.uniform_cuts(16, 4)] * 3, [W.uniform_cuts(16, 2)] * 3, cfg=19)
-        p2.rho = p.rho
-        o = bddc.from_problem(p2, weighting=1)
-        its.append(pcg.solve(o, p2.f[0], rtol=1e-8).iters)
-    assert max(its) - min(its) <= 1
+        for w in (0, 1):
+            assert pcg.solve(bddc.from_problem(p, weighting=w), p.f[0], rtol=1e-8).iters == 1
 
 
 def test_local_invariants():

@@ -43,6 +43,34 @@ def test_fig1_subobjects_and_weights():
             assert classify.weight(c, alpha, xi, int(row[4])) == pytest.approx(float(Fraction(row[5])))
 
 
+def _remark4_problem(case):
+    if case in ("two", "twomean"):
+        n_el = (8, 4)
+        ex = np.tile(np.arange(8), 4)
+        ey = np.repeat(np.arange(4), 8)
+        sub = (ex >= 4).astype(np.int32)
+        rho = np.where(sub == 0, 1.0, 9.0)
+        if case == "twomean":
+            rho = np.where(sub == 0, 1.0, np.where(ey < 2, 6.0, 12.0))
+        return n_el, sub, sub.copy(), rho
+    p = W.fig1_problem()
+    return p.n_el, p.elem_sub, p.elem_subsub, 2.0 ** p.elem_subsub
+
+
+def test_remark4_weights_golden():
+    """Remark 4's coefficient weights against values worked by hand, with
+    asymmetric keys (Figure 1's split) and a coefficient that varies inside
+    a subsubdomain (its mean is alpha_j); each subdomain's weights at a node
+    sum to 1."""
+    for row in _read_golden("remark4_weights.txt"):
+        n_el, sub, ss, rho = _remark4_problem(row[1])
+        c = classify.classify(n_el, sub, ss)
+        alpha = classify.subsub_alpha(ss, rho, 1)
+        xi = q1.Grid(n_el).free_index(np.array([int(row[2]), int(row[3])]))
+        assert classify.weight(c, alpha, xi, int(row[5])) == pytest.approx(float(Fraction(row[6])), rel=1e-14), row
+        assert sum(classify.weight(c, alpha, xi, int(i)) for i in c.node_subs[xi]) == pytest.approx(1.0)
+
+
 def test_fig1_multiplicity_differs():
     # The paper contrasts delta_1(xi) = 2/3 with the multiplicity weight 1/2 at xi = (10, 5).
     p = W.fig1_problem()
