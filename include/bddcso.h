@@ -185,6 +185,23 @@ bddcso_status bddcso_apply(bddcso_precond* pc, const double* r_dev, double* z_de
 bddcso_status bddcso_solve(bddcso_precond* pc, const double* b_dev, double* x_dev, int nrhs,
                            bddcso_stats* stats, void* stream);
 
+/*
+ * bddcso_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as bddcso_solve, but the solve state
+ * (the six PCG vectors, dot partials, scalars, history and flags) lives in a
+ * static 64 MiB device array of the library instead of the preconditioner's
+ * memory; it needs about 48 * n_free * nrhs + 16 * (maxit + 1) * nrhs bytes,
+ * i.e. n_free * nrhs up to about 1.39e6.  Larger solves return EINVAL and
+ * run nothing.  The call allocates no device or pinned memory (the
+ * preconditioner must already exist).  Every call on one device shares that
+ * device's array, which keeps the last call's contents: calls that overlap
+ * on one device (other streams or threads) race and must be serialised by
+ * the caller.
+ */
+bddcso_status bddcso_solve_noalloc(bddcso_precond* pc, const double* b_dev, double* x_dev, int nrhs,
+                                   bddcso_stats* stats, void* stream);
+
 /* Element gradient of a loss through the solve:
  *   g_e = -rho_e * sum_k lam_k,e^T K^_e u_k,e
  * with K^_e the unit-coefficient Q1 element matrix and u_e, lam_e the

@@ -23,6 +23,7 @@ EXPORTED = [
     "bddcso_precond_destroy", "bddcso_problem_destroy", "bddcso_last_error",
     "bddcso_plan_info", "bddcso_profile", "bddcso_profile_read", "bddcso_copy_probe",
     "bddcso_setup_workspace_size", "bddcso_precond_generation", "bddcso_coef_from_log",
+    "bddcso_solve_noalloc",
 ]
 
 
@@ -81,6 +82,7 @@ def load() -> C.CDLL:
         "bddcso_operator_apply": (C.c_int, [vp, vp, vp, C.c_int, vp]),
         "bddcso_apply": (C.c_int, [vp, vp, vp, C.c_int, vp]),
         "bddcso_solve": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(Stats), vp]),
+        "bddcso_solve_noalloc": (C.c_int, [vp, vp, vp, C.c_int, C.POINTER(Stats), vp]),
         "bddcso_element_grad": (C.c_int, [vp, vp, vp, vp, C.c_int, vp]),
         "bddcso_box_filter": (C.c_int, [vp, vp, vp, C.c_int, vp]),
         "bddcso_precond_info": (C.c_int, [vp, i64p, i64p, i64p, i64p]),

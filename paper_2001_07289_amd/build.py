@@ -25,7 +25,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 
 SOURCES = [
     ("kernels.hip", DEVICE),
-    ("api.cpp", [f"--offload-arch={ARCH}"]),
+    ("api.cpp", DEVICE),
     ("plan.cpp", []),
 ]
 

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1102,11 +1103,54 @@ bddcso_status bddcso_apply(bddcso_precond* pc, const double* r, double* z, int n
   return BDDCSO_OK;
 }
 
-bddcso_status bddcso_solve(bddcso_precond* pc, const double* b, double* x, int nrhs, bddcso_stats* stats,
-                           void* stream) {
-  if (!pc || !b || !x) return set_err(BDDCSO_EINVAL, "null argument");
-  if (nrhs < 1 || nrhs > pc->max_nrhs) return set_err(BDDCSO_EINVAL, "nrhs must be in 1..max_nrhs");
-  if (b == x) return set_err(BDDCSO_EINVAL, "b and x must be distinct");
+}  // extern "C"
+
+namespace {
+
+// Device state of one PCG solve: the vectors ([nrhs][n_free] each), the dot
+// partials, the scalar slots (8 x BDDCSO_MAX_RHS), the per-iteration
+// (alpha, beta) history and the per-column flags.
+struct Krylov {
+  double *r, *p, *qv, *z, *rold, *dtmp, *partial, *sc, *hist_a, *hist_b;
+  int32_t *active, *iters, *flags, *nactive;
+};
+
+Krylov precond_krylov(bddcso_precond* pc) {
+  return {pc->r, pc->p, pc->qv, pc->z, pc->rold, pc->dtmp, pc->partial, pc->sc, pc->hist_a, pc->hist_b,
+          pc->active, pc->iters, pc->flags, pc->nactive};
+}
+
+// Cuts a Krylov state for nrhs columns, in a fixed order with 256-byte
+// aligned pieces, from base (nullptr: only counts).  Returns the bytes used.
+size_t carve_krylov(char* base, int64_t n, int nr, int dot_blocks, int maxit, Krylov* k) {
+  size_t used = 0;
+  auto take = [&](size_t bytes) {
+    const size_t off = (used + 255) / 256 * 256;
+    used = off + std::max<size_t>(bytes, 1);
+    return base ? (void*)(base + off) : nullptr;
+  };
+  const size_t vec = (size_t)n * nr * sizeof(double);
+  Krylov t;
+  t.r = (double*)take(vec);
+  t.p = (double*)take(vec);
+  t.qv = (double*)take(vec);
+  t.z = (double*)take(vec);
+  t.rold = (double*)take(vec);
+  t.dtmp = (double*)take(vec);
+  t.partial = (double*)take((size_t)dot_blocks * nr * sizeof(double));
+  t.sc = (double*)take(8 * BDDCSO_MAX_RHS * sizeof(double));
+  t.hist_a = (double*)take((size_t)(maxit + 1) * nr * sizeof(double));
+  t.hist_b = (double*)take((size_t)(maxit + 1) * nr * sizeof(double));
+  t.active = (int32_t*)take(nr * sizeof(int32_t));
+  t.iters = (int32_t*)take(nr * sizeof(int32_t));
+  t.flags = (int32_t*)take(nr * sizeof(int32_t));
+  t.nactive = (int32_t*)take(sizeof(int32_t));
+  if (k) *k = t;
+  return used;
+}
+
+bddcso_status solve_impl(bddcso_precond* pc, const Krylov& K, const double* b, double* x, int nrhs,
+                         bddcso_stats* stats, void* stream) {
   hipStream_t s = as_stream(stream);
   auto t0 = std::chrono::steady_clock::now();
   const int64_t n = pc->geo.n_free;
@@ -1114,7 +1158,7 @@ bddcso_status bddcso_solve(bddcso_precond* pc, const double* b, double* x, int n
   const bddcso_options& o = pc->opt;
   const bool flex = o.flexible || pc->precision == 1;
   const int limit = o.fixed_iters > 0 ? o.fixed_iters : o.maxit;
-  double* SC = pc->sc;
+  double* SC = K.sc;
   double *s_bb = SC, *s_rz = SC + 64, *s_pq = SC + 128, *s_rr = SC + 192, *s_rzn = SC + 256, *s_num = SC + 320,
          *s_tol = SC + 384;
   std::vector<double> hbb(nr), htol(nr);
@@ -1124,8 +1168,8 @@ bddcso_status bddcso_solve(bddcso_precond* pc, const double* b, double* x, int n
     bddcso_status pst = bddcso_check_pivots(pc, stream);
     if (pst != BDDCSO_OK) return pst;
     launch_fill_f64(x, n * nr, 0.0, s);
-    HIPCHK(hipMemcpyAsync(pc->r, b, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
-    launch_dot(b, b, n, nr, pc->partial, pc->dot_blocks, s_bb, s);
+    HIPCHK(hipMemcpyAsync(K.r, b, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_dot(b, b, n, nr, K.partial, pc->dot_blocks, s_bb, s);
     HIPCHK(hipMemcpyAsync(hbb.data(), s_bb, nr * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int j = 0; j < nr; ++j) {
@@ -1134,50 +1178,50 @@ bddcso_status bddcso_solve(bddcso_precond* pc, const double* b, double* x, int n
       hact[j] = hbb[j] > 0.0 ? 1 : 0;
     }
     HIPCHK(hipMemcpyAsync(s_tol, htol.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(pc->active, hact.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    launch_fill_i32(pc->iters, nr, 0, s);
-    launch_fill_i32(pc->flags, nr, 0, s);
-    apply_B_any(pc, pc->r, pc->z, nr, s);
-    HIPCHK(hipMemcpyAsync(pc->p, pc->z, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
-    launch_dot(pc->r, pc->z, n, nr, pc->partial, pc->dot_blocks, s_rz, s);
+    HIPCHK(hipMemcpyAsync(K.active, hact.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    launch_fill_i32(K.iters, nr, 0, s);
+    launch_fill_i32(K.flags, nr, 0, s);
+    apply_B_any(pc, K.r, K.z, nr, s);
+    HIPCHK(hipMemcpyAsync(K.p, K.z, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_dot(K.r, K.z, n, nr, K.partial, pc->dot_blocks, s_rz, s);
     int any = 0;
     for (int j = 0; j < nr; ++j) any |= hact[j];
     for (int k = 0; any && k < limit; ++k) {
-      launch_q1_apply(pc->geo, pc->khat, pc->rho, pc->p, pc->qv, nr, s);
-      launch_dot(pc->p, pc->qv, n, nr, pc->partial, pc->dot_blocks, s_pq, s);
-      if (flex) HIPCHK(hipMemcpyAsync(pc->rold, pc->r, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
-      launch_pcg_xr(x, pc->r, pc->p, pc->qv, s_rz, s_pq, pc->active, n, nr, s);
-      launch_dot(pc->r, pc->r, n, nr, pc->partial, pc->dot_blocks, s_rr, s);
-      launch_pcg_book1(nr, k, s_rz, s_pq, s_rr, s_tol, pc->active, pc->iters, pc->flags, pc->hist_a, pc->nactive, s);
+      launch_q1_apply(pc->geo, pc->khat, pc->rho, K.p, K.qv, nr, s);
+      launch_dot(K.p, K.qv, n, nr, K.partial, pc->dot_blocks, s_pq, s);
+      if (flex) HIPCHK(hipMemcpyAsync(K.rold, K.r, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_pcg_xr(x, K.r, K.p, K.qv, s_rz, s_pq, K.active, n, nr, s);
+      launch_dot(K.r, K.r, n, nr, K.partial, pc->dot_blocks, s_rr, s);
+      launch_pcg_book1(nr, k, s_rz, s_pq, s_rr, s_tol, K.active, K.iters, K.flags, K.hist_a, K.nactive, s);
       k_done = k + 1;
       if (o.fixed_iters <= 0) {
-        HIPCHK(hipMemcpyAsync(pc->h_nactive, pc->nactive, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(pc->h_nactive, K.nactive, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (*pc->h_nactive == 0) break;
       }
       if (k + 1 == limit) break;
-      apply_B_any(pc, pc->r, pc->z, nr, s);
-      launch_dot(pc->r, pc->z, n, nr, pc->partial, pc->dot_blocks, s_rzn, s);
+      apply_B_any(pc, K.r, K.z, nr, s);
+      launch_dot(K.r, K.z, n, nr, K.partial, pc->dot_blocks, s_rzn, s);
       if (flex) {
-        launch_sub(pc->r, pc->rold, pc->dtmp, n * nr, s);
-        launch_dot(pc->z, pc->dtmp, n, nr, pc->partial, pc->dot_blocks, s_num, s);
-        launch_pcg_p(pc->p, pc->z, s_num, s_rz, pc->active, n, nr, s);
-        launch_pcg_book2(nr, k, s_rz, s_num, s_rzn, pc->active, pc->hist_b, s);
+        launch_sub(K.r, K.rold, K.dtmp, n * nr, s);
+        launch_dot(K.z, K.dtmp, n, nr, K.partial, pc->dot_blocks, s_num, s);
+        launch_pcg_p(K.p, K.z, s_num, s_rz, K.active, n, nr, s);
+        launch_pcg_book2(nr, k, s_rz, s_num, s_rzn, K.active, K.hist_b, s);
       } else {
-        launch_pcg_p(pc->p, pc->z, s_rzn, s_rz, pc->active, n, nr, s);
-        launch_pcg_book2(nr, k, s_rz, s_rzn, s_rzn, pc->active, pc->hist_b, s);
+        launch_pcg_p(K.p, K.z, s_rzn, s_rz, K.active, n, nr, s);
+        launch_pcg_book2(nr, k, s_rz, s_rzn, s_rzn, K.active, K.hist_b, s);
       }
     }
     HIPCHK(hipGetLastError());
     // results
     std::vector<int32_t> it(nr), fl(nr);
     std::vector<double> rr(nr), ha((size_t)std::max(k_done, 1) * nr), hb((size_t)std::max(k_done, 1) * nr);
-    HIPCHK(hipMemcpyAsync(it.data(), pc->iters, nr * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(fl.data(), pc->flags, nr * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(it.data(), K.iters, nr * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(fl.data(), K.flags, nr * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(rr.data(), s_rr, nr * sizeof(double), hipMemcpyDeviceToHost, s));
     if (k_done > 0) {
-      HIPCHK(hipMemcpyAsync(ha.data(), pc->hist_a, (size_t)k_done * nr * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hb.data(), pc->hist_b, (size_t)k_done * nr * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(ha.data(), K.hist_a, (size_t)k_done * nr * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hb.data(), K.hist_b, (size_t)k_done * nr * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
@@ -1221,6 +1265,64 @@ bddcso_status bddcso_solve(bddcso_precond* pc, const double* b, double* x, int n
     return set_err(BDDCSO_EHIP, f.where + ": " + hipGetErrorString(f.e));
   }
   return BDDCSO_OK;
+}
+
+// The static scratch of the allocation-free solve (each device holds its own
+// copy from module load until the process ends).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's scratch, looked up once per device (the
+// array's host-side name is not a device address).
+bddcso_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return set_err(BDDCSO_EHIP, "hipGetDevice failed or device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_err(BDDCSO_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return BDDCSO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bddcso_status bddcso_solve(bddcso_precond* pc, const double* b, double* x, int nrhs, bddcso_stats* stats,
+                           void* stream) {
+  if (!pc || !b || !x) return set_err(BDDCSO_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > pc->max_nrhs) return set_err(BDDCSO_EINVAL, "nrhs must be in 1..max_nrhs");
+  if (b == x) return set_err(BDDCSO_EINVAL, "b and x must be distinct");
+  return solve_impl(pc, precond_krylov(pc), b, x, nrhs, stats, stream);
+}
+
+bddcso_status bddcso_solve_noalloc(bddcso_precond* pc, const double* b, double* x, int nrhs, bddcso_stats* stats,
+                                   void* stream) {
+  if (!pc || !b || !x) return set_err(BDDCSO_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > pc->max_nrhs) return set_err(BDDCSO_EINVAL, "nrhs must be in 1..max_nrhs");
+  if (b == x) return set_err(BDDCSO_EINVAL, "b and x must be distinct");
+  const int maxit = std::max(pc->opt.maxit, pc->opt.fixed_iters);
+  const size_t need = carve_krylov(nullptr, pc->geo.n_free, nrhs, pc->dot_blocks, maxit, nullptr);
+  if (need > kNoAllocScratchBytes)
+    return set_err(BDDCSO_EINVAL, "solve state of " + std::to_string(need) + " bytes exceeds the " +
+                                      std::to_string(kNoAllocScratchBytes) +
+                                      "-byte static scratch (about n_free * nrhs <= 1.39e6)");
+  void* base = nullptr;
+  bddcso_status st = scratch_address(&base);
+  if (st != BDDCSO_OK) return st;
+  Krylov K;
+  carve_krylov((char*)base, pc->geo.n_free, nrhs, pc->dot_blocks, maxit, &K);
+  return solve_impl(pc, K, b, x, nrhs, stats, stream);
 }
 
 bddcso_status bddcso_element_grad(const bddcso_precond* pc, const double* u, const double* lam, double* g,

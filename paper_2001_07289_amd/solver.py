@@ -191,6 +191,21 @@ class Preconditioner:
         }
         return x, stats
 
+    def solve_noalloc(self, b: torch.Tensor, x: torch.Tensor, stream=None, raise_on_noconv: bool = True):
+        """bddcso_solve_noalloc into the caller's x (same shape as b); allocates nothing."""
+        _f64_cuda(b, "b")
+        _f64_cuda(x, "x")
+        if x.shape != b.shape:
+            raise ValueError("x must have the shape of b")
+        st = B.Stats()
+        status = B.load().bddcso_solve_noalloc(self._h, _ptr(b), _ptr(x), self._nrhs(b), C.byref(st),
+                                               _stream(stream))
+        if status != 0 and (raise_on_noconv or status != -5):
+            B.check(status)
+        n = st.nrhs
+        return {"iters": list(st.iters[:n]), "converged": list(st.converged[:n]), "relres": list(st.relres[:n]),
+                "kappa": list(st.kappa[:n]), "status": B.STATUS.get(status, status)}
+
     def element_grad(self, u: torch.Tensor, lam: torch.Tensor, stream=None) -> torch.Tensor:
         _f64_cuda(u, "u")
         _f64_cuda(lam, "lam")
