@@ -39,7 +39,10 @@ PROFILES = os.path.join(ROOT, "profiles")
 # kernel-name prefixes of each profiled kernel class
 CLASS_KERNELS = {"sweep_update": ("k_sweep_update", "k_slab_update"), "block_solve": ("k_block_solve",),
                  "gemm": ("k_gemm",), "sweep_panel": ("k_sweep_panel", "k_slab_cd"),
-                 "sweep_small": ("k_sweep_reg",)}
+                 "sweep_small": ("k_sweep_reg",), "schur_couple": ("k_schur_couple",),
+                 "couple_multi": ("k_couple_multi",), "q1_apply": ("k_q1_apply",)}
+MFMA_CLASSES = ("sweep_update", "gemm", "sweep_panel", "sweep_small")
+METRIC = "BDDC-SO PCG DoF/s to rel.res 1e-8: FP64 plain vs mixed batched; grads/s"
 MFMA_TFLOPS = {"f64": 78.6, "f32": 157.3}  # dense matrix peaks, TFLOP/s
 
 WORKLOADS = {
@@ -61,6 +64,10 @@ def parse():
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--coarse", default="nd", choices=["nd", "dense"])
+    ap.add_argument("--graph", type=int, default=0, choices=[0, 1],
+                    help="1: numeric setup and PCG iterations replayed from HIP graphs")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shapes with bddcso_autotune (untimed) before the timed steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -69,6 +76,9 @@ def parse():
                                                        "COPY_WRITE_DIR"),
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs (of this bench and of --copy-probe) "
                          "into per-class HBM bytes per dispatch, printed as the profiles/ text")
+    ap.add_argument("--pmc-mfma", nargs=2, metavar=("MFMA_DIR", "TRACE_DIR"),
+                    help="with --pmc-summary: also summarise an MFMA counter run (SQ_INSTS_VALU_MFMA_MOPS_F64, "
+                         "SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE) against a kernel-trace run's durations")
     return ap.parse_args()
 
 
@@ -136,6 +146,43 @@ def pmc_summary(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, 
     return "\n".join(lines)
 
 
+def mfma_summary(mfma_dir, trace_dir):
+    """Per kernel class: MFMA flops per dispatch from the counters (one MOPS
+    unit is 512 flops), the MFMA-busy share of the active cycles summed over
+    the 256 compute units, and the rate over the traced mean duration."""
+    import csv
+    import glob
+
+    (path,) = glob.glob(os.path.join(mfma_dir, "*counter_collection.csv"))
+    agg = {}
+    for r in csv.DictReader(open(path)):
+        cls = kernel_class(r["Kernel_Name"])
+        if cls is None:
+            continue
+        a = agg.setdefault(cls, {})
+        a.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    (tpath,) = glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))
+    dur = {}
+    for r in csv.DictReader(open(tpath)):
+        cls = kernel_class(r["Kernel_Name"])
+        if cls is not None:
+            dur.setdefault(cls, []).append((float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9)
+    lines = []
+    for cls in CLASS_KERNELS:
+        a = agg.get(cls)
+        if not a or "SQ_INSTS_VALU_MFMA_MOPS_F64" not in a:
+            continue
+        n = len(a["SQ_INSTS_VALU_MFMA_MOPS_F64"])
+        fl = 512.0 * sum(a["SQ_INSTS_VALU_MFMA_MOPS_F64"]) / n
+        fl32 = 512.0 * sum(a.get("SQ_INSTS_VALU_MFMA_MOPS_F32", [0.0])) / n
+        busy = sum(a.get("SQ_VALU_MFMA_BUSY_CYCLES", [0.0])) / max(sum(a.get("GRBM_GUI_ACTIVE", [1.0])) * 256, 1.0)
+        t = sum(dur.get(cls, [0.0])) / max(len(dur.get(cls, [])), 1)
+        rate = fl / t / 1e12 if t > 0 else 0.0
+        lines.append(f"mfma {cls} dispatches {n} mfma_f64_flops {fl:.4g} mfma_f32_flops {fl32:.4g} "
+                     f"mfma_busy_share {busy:.3f} traced_mean_us {t * 1e6:.1f} mfma_tflops {rate:.2f}")
+    return "\n".join(lines)
+
+
 def measured_traffic(workload, cls):
     """HBM bytes per dispatch of a kernel class from the committed counter
     summary of this workload, or None when there is none or the kernels have
@@ -155,10 +202,12 @@ def measured_traffic(workload, cls):
     return out if sha == source_sha() else None
 
 
-def cpu_baseline():
+def cpu_baseline(gpu_check=True):
     """The oracle, untuned, on a bounded sample: cfg2's subdomain and
     subobject shapes (12^3 elements, L = 4h, same rho law) on a 48^3 mesh,
-    64 subdomains, 103,823 dofs; end-to-end setup + PCG to 1e-8."""
+    64 subdomains, 103,823 dofs; end-to-end setup + PCG to 1e-8.  The same
+    sample is then solved on the GPU (FP64 at the oracle's iteration count,
+    FP64 and mixed free-running) and compared with the oracle's solution."""
     from oracle import bddc, pcg
 
     p = W.config2_like(48, 12, 4, cfg=2, name="cfg2_sample")
@@ -168,34 +217,79 @@ def cpu_baseline():
     r = pcg.solve(o, p.f[0], rtol=1e-8)
     t2 = time.perf_counter()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": p.n_free / (t2 - t0), "unit": "DoF/s", "cores": threads, "kind": "oracle",
-            "sample": f"cfg2 shapes on a 48^3 mesh ({p.n_free} dofs, 64 subdomains of 12^3, L=4h): "
-                      f"setup {t1 - t0:.1f} s + PCG {t2 - t1:.1f} s, {r.iters} iterations"}
+    out = {"value": p.n_free / (t2 - t0), "unit": "DoF/s", "cores": threads, "kind": "oracle",
+           "sample": f"cfg2 shapes on a 48^3 mesh ({p.n_free} dofs, 64 subdomains of 12^3, L=4h): "
+                     f"setup {t1 - t0:.1f} s + PCG {t2 - t1:.1f} s, {r.iters} iterations"}
+    if gpu_check:
+        import torch
+
+        import paper_2001_07289_amd as pk
+
+        prob = pk.Problem.from_workload(p)
+        rho = torch.as_tensor(p.rho, device="cuda:0")
+        b = torch.as_tensor(p.f[0], device="cuda:0")
+        xo = np.asarray(r.x)
+
+        def err(x):
+            return float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+
+        x_fix, _ = pk.Preconditioner(prob, rho, fixed_iters=r.iters).solve(b)
+        x64, st64 = pk.Preconditioner(prob, rho, rtol=1e-8).solve(b)
+        xm, stm = pk.Preconditioner(prob, rho, precision=1, rtol=1e-8).solve(b)
+        out["gpu_vs_oracle"] = {
+            "oracle_iters": r.iters, "oracle_kappa": r.kappa,
+            "fp64_rel_err_at_oracle_iters": err(x_fix),
+            "fp64_iters": st64["iters"][0], "fp64_kappa": st64["kappa"][0], "fp64_rel_err": err(x64),
+            "mixed_iters": stm["iters"][0], "mixed_rel_err": err(xm)}
+    return out
 
 
 def roofline(prof, dtype, workload):
     """Roofline of the dominant kernel class (largest event time in the
-    warmup steps), from its events in the timed steps."""
+    warmup steps), from its events in the timed steps.  `achieved` uses the
+    reference count of the class's work (banded factors and solves,
+    Cholesky-equivalent sweeps); the count the kernels execute is given
+    beside it."""
     name = prof["dominant"]
     rec = prof["timed"][name]
     if rec["launches"] == 0 or rec["total_ms"] <= 0:
         return None
-    avg_s = rec["total_ms"] / rec["launches"] * 1e-3
-    flops = rec["flops"] / rec["launches"]
-    nbytes = rec["bytes"] / rec["launches"]
+    n = rec["launches"]
+    avg_s = rec["total_ms"] / n * 1e-3
+    flops, nbytes = rec["flops"] / n, rec["bytes"] / n
+    rflops, rbytes = rec["ref_flops"] / n, rec["ref_bytes"] / n
     peak_f = MFMA_TFLOPS[dtype] * 1e12
     ai = flops / max(nbytes, 1.0)
-    mfma_bound = name in ("sweep_update", "gemm", "sweep_panel", "sweep_small") and ai * HBM_GBS * 1e9 >= peak_f
-    if mfma_bound:
-        ach = flops / avg_s / 1e12
+    if name in MFMA_CLASSES and ai * HBM_GBS * 1e9 >= peak_f:
+        ach, ex = rflops / avg_s / 1e12, flops / avg_s / 1e12
         out = {"bound": "mfma", "achieved": ach, "peak": MFMA_TFLOPS[dtype], "unit": "TFLOP/s",
-               "frac": ach / MFMA_TFLOPS[dtype]}
+               "frac": ach / MFMA_TFLOPS[dtype],
+               "executed": {"achieved": ex, "frac": ex / MFMA_TFLOPS[dtype], "flops_per_launch": flops}}
     else:
-        ach = nbytes / avg_s / 1e9
-        out = {"bound": "hbm", "achieved": ach, "peak": HBM_GBS, "unit": "GB/s", "frac": ach / HBM_GBS}
-    out.update({"traffic": measured_traffic(workload, name), "kernel": name, "launches": rec["launches"],
-                "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": nbytes,
-                "algorithmic_flops_per_launch": flops})
+        ach, ex = rbytes / avg_s / 1e9, nbytes / avg_s / 1e9
+        out = {"bound": "hbm", "achieved": ach, "peak": HBM_GBS, "unit": "GB/s", "frac": ach / HBM_GBS,
+               "executed": {"achieved": ex, "frac": ex / HBM_GBS, "bytes_per_launch": nbytes}}
+    out.update({"traffic": measured_traffic(workload, name), "kernel": name, "launches": n,
+                "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": rbytes,
+                "algorithmic_flops_per_launch": rflops})
+    return out
+
+
+def class_rooflines(warm, steps, dtype):
+    """Per kernel class over the warm-up steps: ms per step and the achieved
+    rate by the reference count (TFLOP/s for the MFMA classes, GB/s else)."""
+    out = {}
+    for k, v in warm.items():
+        if v["launches"] == 0 or v["total_ms"] <= 0:
+            continue
+        s = v["total_ms"] * 1e-3
+        if k in MFMA_CLASSES:
+            out[k] = {"ms_per_step": v["total_ms"] / steps, "tflops": v["ref_flops"] / s / 1e12,
+                      "frac": v["ref_flops"] / s / 1e12 / MFMA_TFLOPS[dtype],
+                      "executed_tflops": v["flops"] / s / 1e12}
+        else:
+            out[k] = {"ms_per_step": v["total_ms"] / steps, "gbs": v["ref_bytes"] / s / 1e9,
+                      "frac": v["ref_bytes"] / s / 1e9 / HBM_GBS, "executed_gbs": v["bytes"] / s / 1e9}
     return out
 
 
@@ -264,6 +358,60 @@ def grads_rate(steps=3):
             "grad_norm": float(torch.linalg.norm(g))}
 
 
+def cfg4_plain_vs_mixed(steps=2):
+    """cfg2's mesh, partition and rho with subobjects of 2h (every interface
+    dof primal, 175,903 coarse dofs): plain FP64 against FP32 local factors
+    with flexible FP64 CG, same rtol.  The mixed solution's difference is
+    stated against the FP64 GPU solution (the oracle does not run at this
+    size; the FP64 path is checked against it at the 48^3 sample)."""
+    import torch
+
+    import paper_2001_07289_amd as pk
+
+    p = W.config4()
+    prob = pk.Problem.from_workload(p)
+    rho = torch.as_tensor(p.rho, device="cuda:0")
+    b = torch.as_tensor(p.f[0], device="cuda:0")
+    res = {}
+    xs = {}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        pc = pk.Preconditioner(prob, rho, precision=prec, rtol=1e-8, maxit=500)
+        dt, x, st, _ = run_steps(pc, rho, b, steps, 1)
+        xs[name] = x
+        res[name] = {"value": p.n_free / dt, "unit": "DoF/s", "ms_per_step": dt * 1e3, "iters": st["iters"][0],
+                     "true_relres": float(torch.linalg.norm(b - pc.operator(x)) / torch.linalg.norm(b))}
+        del pc
+        torch.cuda.empty_cache()
+    res["mixed"]["rel_diff_vs_fp64_solution"] = float(torch.linalg.norm(xs["mixed"] - xs["fp64"]) /
+                                                      torch.linalg.norm(xs["fp64"]))
+    res["workload"] = "cfg4: 96^3, 512 subdomains of 12^3, subobjects 2h, log10 rho ~ U[-3,3]"
+    return res
+
+
+def cfg3_rate(steps=2):
+    """The batched uneven workload (128^3, 1000 boxes of 8^3..16^3, subobject
+    lengths 2h/4h/8h, 1e6 channels, 32 right-hand sides in lockstep), FP64,
+    default launch shapes."""
+    import torch
+
+    import paper_2001_07289_amd as pk
+
+    p = W.config3(nrhs=32)
+    prob = pk.Problem.from_workload(p)
+    rho = torch.as_tensor(p.rho, device="cuda:0")
+    b = torch.as_tensor(np.ascontiguousarray(p.f.reshape(-1)), device="cuda:0")
+    pc = pk.Preconditioner(prob, rho, rtol=1e-8, maxit=500, max_nrhs=32)
+    dt, x, st, _ = run_steps(pc, rho, b, steps, 1)
+    n = p.n_free * 32
+    res = float(torch.linalg.norm(b - pc.operator(x)) / torch.linalg.norm(b))
+    out = {"value": n / dt, "unit": "DoF/s", "ms_per_step": dt * 1e3, "iters": [min(st["iters"]), max(st["iters"])],
+           "true_relres": res, "n_coarse": pc.info()["n_coarse"],
+           "workload": "cfg3: 128^3 (2,048,383 dofs x 32 rhs), 1000 uneven boxes, L in {2,4,8}h, 1e6 channels"}
+    del pc
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_probe(mib):
     import torch
 
@@ -289,6 +437,8 @@ def main():
         return
     if a.pmc_summary:
         print(pmc_summary(*a.pmc_summary, copy_bytes=1 << 30))
+        if a.pmc_mfma:
+            print(mfma_summary(*a.pmc_mfma))
         return
     import torch
 
@@ -305,12 +455,23 @@ def main():
         rho = torch.as_tensor(p.rho, device=dev)
     b = torch.as_tensor(np.ascontiguousarray(p.f.reshape(-1)), device=dev)
     opts = dict(precision=1 if a.precision == "mixed" else 0, coarse_solver=1 if a.coarse == "dense" else 0,
-                rtol=1e-8, maxit=500, max_nrhs=nrhs)
+                rtol=1e-8, maxit=500, max_nrhs=nrhs, graph=a.graph)
+    tune = None
+    if a.autotune:
+        t0 = time.perf_counter()
+        best, rep = prob.autotune(rho, b, **opts)
+        knobs = ("update_tile", "slab_lookahead", "sweep_reg_rows", "block_target", "mr_min_rhs", "graph")
+        tune = {"seconds": time.perf_counter() - t0, "chosen": {k: getattr(best, k) for k in knobs},
+                "trials": [{"knobs": kn, "ms": ms, "status": stt} for kn, ms, stt in rep["trials"]]}
+        opts.update(tune["chosen"])
+        a.graph = opts["graph"]
     t0 = time.perf_counter()
     pc = pk.Preconditioner(prob, rho, **opts)
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
-    dt, x, st, prof = run_steps(pc, rho, b, a.steps, a.warmup, profile=True)
+    # graph-mode runs are timed without the event profiler (events are not
+    # recorded inside replayed graphs), so they carry no roofline
+    dt, x, st, prof = run_steps(pc, rho, b, a.steps, a.warmup, profile=not a.graph)
     n = p.n_free * nrhs
     res = float(torch.linalg.norm(b - pc.operator(x)) / torch.linalg.norm(b))
     # phase split (outside the timed region)
@@ -323,13 +484,17 @@ def main():
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     dtype = "f64" if a.precision == "fp64" else "f32"
-    rf = roofline(prof, "f64" if a.precision == "fp64" else "f32", a.workload if a.precision == "fp64" else None)
-    warm = prof["warmup"]
+    rf, classes, warm = None, {}, {}
+    if prof:
+        rf = roofline(prof, "f64" if a.precision == "fp64" else "f32",
+                      a.workload if a.precision == "fp64" else None)
+        warm = prof["warmup"]
+        classes = class_rooflines(warm, max(a.warmup, 1), "f64" if a.precision == "fp64" else "f32")
     tot = sum(r["total_ms"] for r in warm.values())
     if rf:
         rf["share_of_profiled_kernel_time"] = warm[rf["kernel"]]["total_ms"] / max(tot, 1e-12)
     out = {
-        "metric": "BDDC-SO PCG DoF/s to rel.res 1e-8",
+        "metric": METRIC,
         "value": n / dt,
         "unit": "DoF/s",
         "n_gpus": 1,
@@ -343,14 +508,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "description": desc, "n_free": p.n_free, "nrhs": nrhs,
                    "n_sub": prob.info()["n_sub"], "n_coarse": pc.info()["n_coarse"], "precision": a.precision,
-                   "coarse": a.coarse, "rtol": 1e-8},
+                   "coarse": a.coarse, "rtol": 1e-8, "graph": a.graph},
         "roofline": rf,
         "iters": st["iters"][:4], "kappa": st["kappa"][:4], "true_relres": res,
         "setup_ms": (t1 - t0) * 1e3, "solve_ms": (t2 - t1) * 1e3,
         "first_setup_s": t_first, "device_bytes": pc.info()["device_bytes"],
-        "kernel_classes_ms_per_warmup_step": {k: v["total_ms"] / max(a.warmup, 1) for k, v in warm.items()},
+        "kernel_classes": classes,
         "dtype_kernels": dtype,
     }
+    if tune:
+        out["autotune"] = tune
     if not a.no_extras and a.workload == "cfg2" and a.precision == "fp64":
         # same workload, FP32 local factors with flexible FP64 CG
         pcm = pk.Preconditioner(prob, rho, precision=1, rtol=1e-8, maxit=500)
@@ -360,8 +527,10 @@ def main():
                         "rel_diff_vs_fp64_solution": float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))}
         del pcm
         out["grads"] = grads_rate()
+        out["cfg4"] = cfg4_plain_vs_mixed()
+        out["cfg3"] = cfg3_rate()
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(gpu_check=True)
     print(json.dumps(out))
 
 

@@ -53,13 +53,25 @@ typedef enum {
 typedef struct bddcso_problem bddcso_problem; /* host descriptors + classification */
 typedef struct bddcso_precond bddcso_precond; /* device factors of one setup      */
 
-/* Primal object kinds (Section 3; Remark 5 on acceptable paths). */
+/* Primal object kinds (Section 3; Remark 5 on acceptable paths).
+ * BDDCSO_PRIMAL_HALF keeps only half of the codimension-one objects (faces
+ * in 3D, edges in 2D) of the selected kinds: the "half of the face
+ * constraints" of Section 5.1's vf-min, which does not say which half.  The
+ * rule is a checkerboard over the fine partition: each subsubdomain gets,
+ * per axis, the rank of its lowest element coordinate among all
+ * subsubdomains' lowest coordinates; a face between subsubdomains j1 < j2
+ * is kept when the sum of j1's ranks over the axes other than its normal
+ * (the axis along which the two ranks differ most) is even.
+ * BDDCSO_PRIMAL_VF_MIN = V | F | HALF. */
 #define BDDCSO_PRIMAL_V 1
 #define BDDCSO_PRIMAL_E 2
 #define BDDCSO_PRIMAL_F 4
+#define BDDCSO_PRIMAL_HALF 8
+#define BDDCSO_PRIMAL_VF_MIN 13
 
 typedef struct {
-  int primal_mask;   /* OR of BDDCSO_PRIMAL_*; 7 = every subobject ("vef")   */
+  int primal_mask;   /* OR of BDDCSO_PRIMAL_*; 7 = every subobject ("vef"),
+                        13 = vertices and half of the faces ("vf-min")     */
   int weighting;     /* 0: eq. (W) counting weights; 1: Remark 4, weights by
                         the coefficient averaged over each subsubdomain       */
   int precision;     /* 0: FP64 throughout; 1: local factors, local solves
@@ -74,6 +86,21 @@ typedef struct {
                         used automatically when precision = 1               */
   int block_target;  /* target size of the dense diagonal blocks of the local
                         block-tridiagonal factors; 0 = default (192)          */
+  int graph;         /* 1: the numeric setup and the two halves of a PCG
+                        iteration are captured once (per right-hand-side
+                        count) into HIP graphs and replayed on the caller's
+                        stream; 0: ordinary launches.  bddcso_solve_noalloc
+                        and profiled runs always launch directly.           */
+  /* Launch shapes (results agree to rounding; chosen by bddcso_autotune).  */
+  int sweep_reg_rows;/* largest matrix swept by the register-resident kernel
+                        (<= 304; 0 = 304); larger ones take the slab path    */
+  int slab_lookahead;/* slab sweeps: 0 = by the trailing update's size,
+                        1 = none (each pivot block swept after the whole
+                        update), 2 = always beside the rest of the update   */
+  int mr_min_rhs;    /* right-hand sides from which the many-RHS kernels
+                        are used (0 = 4)                                     */
+  int update_tile;   /* tile rows of the slab sweeps' trailing update: 64 or
+                        128 (0 = 64)                                         */
 } bddcso_options;
 
 /* Fills the defaults: vef, coefficient weights, FP64, multifrontal coarse,
@@ -223,6 +250,31 @@ bddcso_status bddcso_box_filter(const bddcso_problem* p, const double* in_dev, d
 bddcso_status bddcso_coef_from_log(const bddcso_problem* p, const double* theta_dev, double* rho_dev,
                                    void* stream);
 
+/*
+ * Autotuner: times one step (numeric setup and the PCG solve of b_dev) of
+ * the problem for launch-shape variants of base and returns the fastest in
+ * best.  The variants go knob by knob (coordinate descent): update_tile,
+ * slab_lookahead, sweep_reg_rows, block_target, mr_min_rhs (nrhs > 1),
+ * graph; each trial
+ * builds a preconditioner in library-allocated memory, runs one untimed and
+ * one timed step on the stream (HIP events) and frees it.  Every trial uses
+ * base's method options (primal_mask, weighting, precision, coarse_solver,
+ * rtol, maxit), so the variants compute the same preconditioner.
+ *   rho_dev: [n_elements]; b_dev: [nrhs][n_free]; report may be NULL.
+ */
+#define BDDCSO_TUNE_MAX 32
+typedef struct {
+  int n_trials;
+  int best;                              /* index into the arrays below      */
+  bddcso_options tried[BDDCSO_TUNE_MAX];
+  double step_ms[BDDCSO_TUNE_MAX];       /* setup + solve, HIP events        */
+  int status[BDDCSO_TUNE_MAX];           /* bddcso_status of the trial       */
+} bddcso_tune_report;
+
+bddcso_status bddcso_autotune(bddcso_problem* p, const double* rho_dev, const bddcso_options* base,
+                              const double* b_dev, int nrhs, void* stream, bddcso_options* best,
+                              bddcso_tune_report* report);
+
 /* Sizes and algorithmic work of the plan for these options (host only; no
  * device work).  Flop counts are those of the symmetric sweeps (n^2 p per
  * matrix of size n with p pivots, lower triangle). */
@@ -249,7 +301,9 @@ bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bd
  * 2 the block-tridiagonal solves (HBM), 3 the batched GEMMs (MFMA), 4 the
  * pivot-block work of the large sweeps: 32-pivot panels, slab pivot blocks
  * (one workgroup each) and slab CD products, 5 the batched register-resident
- * sweeps of matrices up to 272 rows (MFMA).
+ * sweeps of matrices up to 272 rows (MFMA), 6 the block Schur updates of the
+ * local factor chains, 7 the plane-coupling products of the basis solves,
+ * 8 the Q1 operator inside bddcso_solve (the last three HBM).
  * bddcso_profile_read waits for
  * the recorded events, then returns for one class the launches seen, their
  * summed duration and their summed algorithmic flops and bytes (the minimum
@@ -257,6 +311,15 @@ bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bd
 bddcso_status bddcso_profile(bddcso_precond* pc, int class_mask);
 bddcso_status bddcso_profile_read(bddcso_precond* pc, int kernel_class, int64_t* launches, double* total_ms,
                                   double* flops, double* bytes);
+
+/* The same launches' work by the reference count of a banded
+ * representation: local factors as lexicographic band Cholesky factors
+ * (bandwidth m_x m_y + m_x + 1 in 3D, m_x + 1 in 2D; n b^2 flops to factor,
+ * 2 nnz reads per triangular solve, 4 nnz flops per column of [X | Y']),
+ * dense sweeps as Cholesky (p^3/3 + (n-p) p^2 + (n-p)^2 p for n rows and p
+ * pivots); other classes as executed.  Host only; any pointer may be NULL. */
+bddcso_status bddcso_profile_reference(const bddcso_precond* pc, int kernel_class, double* flops,
+                                       double* bytes);
 
 /* Plain device copy of `bytes` (a multiple of 16) from src_dev to dst_dev by
  * a streaming kernel: a known traffic against which hardware byte counters

@@ -18,6 +18,16 @@ list of subsubdomains that contain it.  This module does exactly that:
 * the selected (primal) objects are those whose type is in ``primal_mask``
   (1 = v, 2 = e, 4 = f; 7 = "vef", every object); they are numbered by their
   smallest global free-node index, which is the coarse numbering.
+* bit 8 of ``primal_mask`` keeps only half of the codimension-one objects
+  (faces in 3D, edges in 2D: the keys of two subsubdomains), the "half of
+  the face constraints" of Section 5.1's vf-min selection (mask 1 | 4 | 8).
+  The paper does not say which half; here it is a checkerboard over the
+  fine partition: index each subsubdomain along each axis by the rank of its
+  lowest element coordinate among all subsubdomains' lowest coordinates
+  along that axis; a face between j1 < j2 is kept when the sum of j1's
+  indices along the axes other than the face normal (the axis along which
+  j1 and j2 differ most) is even.  On a tensor fine partition neighbouring
+  faces of one interface plane then alternate.
 
 Weights, eq. (W) and Remark 4: for a Gamma node xi and a subdomain i that
 contains it, delta_i(xi) = sum of alpha_j over the subsubdomains j of key(xi)
@@ -38,6 +48,7 @@ from scipy.sparse.csgraph import connected_components
 from .q1 import Grid
 
 TYPE_V, TYPE_E, TYPE_F = 1, 2, 4
+HALF_CODIM1 = 8
 
 
 @dataclasses.dataclass
@@ -147,7 +158,13 @@ def classify(n_el, elem_sub, elem_subsub, primal_mask: int = 7) -> Classificatio
         obj_key.append(k)
         obj_subs.append(np.unique(parent[list(k)]))
         obj_type[o] = object_type(g.dim, len(k))
-    selected = np.array([o for o in range(n_obj) if obj_type[o] & primal_mask], dtype=np.int64)
+    keep = np.array([bool(obj_type[o] & primal_mask) for o in range(n_obj)], dtype=bool)
+    if primal_mask & HALF_CODIM1:
+        idx = subsub_grid_index(g, elem_subsub, n_ss)
+        for o in range(n_obj):
+            if keep[o] and len(obj_key[o]) == 2:
+                keep[o] = checkerboard_even(idx, obj_key[o])
+    selected = np.nonzero(keep)[0].astype(np.int64)
     # objects are already numbered by smallest node id, so selection keeps that order
     # closure of each subdomain: free nodes having subdomain i in their list
     flat_nodes = np.repeat(np.arange(g.n_free), subs.shape[1])
@@ -162,6 +179,28 @@ def classify(n_el, elem_sub, elem_subsub, primal_mask: int = 7) -> Classificatio
     return Classification(g.n_free, n_sub, node_subs, is_gamma, obj_nodes, obj_key,
                           obj_subs, obj_type, node_obj, selected, sub_nodes, node_keys,
                           parent)
+
+
+def subsub_grid_index(g: Grid, elem_subsub: np.ndarray, n_ss: int) -> np.ndarray:
+    """[n_ss, dim]: per axis, the rank of each subsubdomain's lowest element
+    coordinate among the distinct lowest coordinates of all subsubdomains."""
+    ec = g.element_coords()
+    idx = np.empty((n_ss, g.dim), dtype=np.int64)
+    for a in range(g.dim):
+        lo = np.full(n_ss, np.iinfo(np.int64).max, dtype=np.int64)
+        np.minimum.at(lo, elem_subsub, ec[:, a])
+        _, idx[:, a] = np.unique(lo, return_inverse=True)
+    return idx
+
+
+def checkerboard_even(idx: np.ndarray, key: tuple) -> bool:
+    """The half-selection rule for a codimension-one object between the two
+    subsubdomains of key (see the module docstring)."""
+    j1, j2 = key
+    diff = np.abs(idx[j1] - idx[j2])
+    normal = int(np.argmax(diff))
+    s = int(np.sum(idx[j1])) - int(idx[j1][normal])
+    return s % 2 == 0
 
 
 def subsub_alpha(elem_subsub, rho, weighting: int) -> np.ndarray:

@@ -23,7 +23,7 @@ EXPORTED = [
     "bddcso_precond_destroy", "bddcso_problem_destroy", "bddcso_last_error",
     "bddcso_plan_info", "bddcso_profile", "bddcso_profile_read", "bddcso_copy_probe",
     "bddcso_setup_workspace_size", "bddcso_precond_generation", "bddcso_coef_from_log",
-    "bddcso_solve_noalloc",
+    "bddcso_solve_noalloc", "bddcso_profile_reference", "bddcso_autotune",
 ]
 
 
@@ -31,7 +31,16 @@ class Options(C.Structure):
     _fields_ = [("primal_mask", C.c_int), ("weighting", C.c_int), ("precision", C.c_int),
                 ("coarse_solver", C.c_int), ("max_nrhs", C.c_int), ("maxit", C.c_int),
                 ("rtol", C.c_double), ("fixed_iters", C.c_int), ("flexible", C.c_int),
-                ("block_target", C.c_int)]
+                ("block_target", C.c_int), ("graph", C.c_int), ("sweep_reg_rows", C.c_int),
+                ("slab_lookahead", C.c_int), ("mr_min_rhs", C.c_int), ("update_tile", C.c_int)]
+
+
+TUNE_MAX = 32
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("n_trials", C.c_int), ("best", C.c_int), ("tried", Options * TUNE_MAX),
+                ("step_ms", C.c_double * TUNE_MAX), ("status", C.c_int * TUNE_MAX)]
 
 
 class Stats(C.Structure):
@@ -94,6 +103,9 @@ def load() -> C.CDLL:
         "bddcso_profile": (C.c_int, [vp, C.c_int]),
         "bddcso_copy_probe": (C.c_int, [vp, vp, C.c_int64, vp]),
         "bddcso_profile_read": (C.c_int, [vp, C.c_int, i64p, dp, dp, dp]),
+        "bddcso_profile_reference": (C.c_int, [vp, C.c_int, dp, dp]),
+        "bddcso_autotune": (C.c_int, [vp, vp, C.POINTER(Options), vp, C.c_int, vp, C.POINTER(Options),
+                                      C.POINTER(TuneReport)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

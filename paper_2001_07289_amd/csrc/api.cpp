@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -145,6 +146,10 @@ struct DevMem {
   }
 };
 
+struct GraphPair {
+  hipGraphExec_t g1 = nullptr, g2 = nullptr;
+};
+
 struct Batch {
   void* desc = nullptr;  // device descriptor array
   int n = 0, maxm = 0, maxn = 0, maxp = 0;
@@ -152,14 +157,21 @@ struct Batch {
   std::vector<SweepDesc> hs;
 };
 
+// Kernel classes timed by the profiler (bit c of the mask records class c):
+// 1 sweep_update, 2 block_solve, 3 gemm, 4 sweep_panel, 5 sweep_small,
+// 6 schur_couple, 7 couple_multi, 8 q1_apply.
+constexpr int kNumClasses = 8;
+
 struct EventProfiler : Profiler {
   int mask = 0;  // bit c: record class c
   struct Rec {
     std::vector<hipEvent_t> ev;  // begin/end pairs
     size_t used = 0;
-    double flops = 0, bytes = 0;
+    double flops = 0, bytes = 0;          // as executed by the kernels
+    double ref_flops = 0, ref_bytes = 0;  // the reference count of the same work
     int64_t launches = 0;
-  } rec[6];
+  } rec[kNumClasses + 1];
+  bool on(int c) const { return c >= 1 && c <= kNumClasses && (mask & (1 << c)); }
   hipEvent_t next(Rec& r) {
     if (r.used == r.ev.size()) {
       hipEvent_t e;
@@ -169,23 +181,30 @@ struct EventProfiler : Profiler {
     return r.ev[r.used++];
   }
   void begin(int c, hipStream_t s) override {
-    if (c < 1 || c > 5 || !(mask & (1 << c))) return;
+    if (!on(c)) return;
     hipEvent_t e = next(rec[c]);
     if (e) (void)hipEventRecord(e, s);
   }
   void end(int c, double f, double b, hipStream_t s) override {
-    if (c < 1 || c > 5 || !(mask & (1 << c))) return;
+    if (!on(c)) return;
     hipEvent_t e = next(rec[c]);
     if (e) (void)hipEventRecord(e, s);
     rec[c].flops += f;
     rec[c].bytes += b;
     ++rec[c].launches;
   }
+  // work of launches booked under class c by the reference count (banded
+  // Cholesky factors and triangular solves), added beside the executed count
+  void ref(int c, double f, double b) {
+    if (!on(c)) return;
+    rec[c].ref_flops += f;
+    rec[c].ref_bytes += b;
+  }
   void reset(int m) {
     mask = m;
     for (auto& r : rec) {
       r.used = 0;
-      r.flops = r.bytes = 0;
+      r.flops = r.bytes = r.ref_flops = r.ref_bytes = 0;
       r.launches = 0;
     }
   }
@@ -237,11 +256,12 @@ struct bddcso_precond {
   int64_t fsw_stride = 0;
   int32_t* status = nullptr;
   // batches
-  std::vector<Batch> swI, swR;
+  std::vector<std::vector<Batch>> swI, swR;  // per block index k: size buckets
   std::vector<Batch> gfwd[2], gbwd[2];  // block GEMMs of the basis solves, per half of the subdomains
   int zsplit = 0;                       // first subdomain of the second half
-  Batch swSc, gLam, gSel;
-  std::vector<Batch> swFront;                       // per level
+  std::vector<Batch> swSc;                          // size buckets
+  Batch gLam, gSel;
+  std::vector<std::vector<Batch>> swFront;          // per level: size buckets
   std::vector<int32_t*> color_dev;                  // per colour
   std::vector<int> color_n;
   std::vector<std::vector<int32_t*>> slot_dev;      // [level][slot]
@@ -260,6 +280,16 @@ struct bddcso_precond {
   int32_t* h_nactive = nullptr;  // pinned
   int max_nrhs = 1;
   int64_t generation = 0;  // numeric setups done (bddcso_refactor calls)
+  // graph mode (options.graph): capture stream, the numeric setup's graph,
+  // and per right-hand-side count the two halves of a PCG iteration
+  hipStream_t sg = nullptr;
+  hipGraphExec_t g_setup = nullptr;
+  std::map<int, GraphPair> iter_graphs;
+  double* xk = nullptr;      // x of graph-mode solves [max_nrhs][n_free]
+  // pinned subdomains: e / delta per average, delta per subdomain, and the
+  // constant c of the last Neumann solves per (rhs, subdomain)
+  double *feps = nullptr, *fdelta = nullptr, *fc = nullptr;
+  int32_t* kdev = nullptr;   // iteration index of graph-mode solves
   EventProfiler prof;
   hipStream_t s2 = nullptr;                 // second stream of the setup
   hipStream_t s3 = nullptr;                 // third stream: the interior factors
@@ -270,6 +300,15 @@ struct bddcso_precond {
   hipEvent_t ev_la = nullptr, ev_lb = nullptr, ev_lc = nullptr;  // slab look-ahead of the coarse fronts
   hipEvent_t ev_zf = nullptr, ev_zj = nullptr;  // fork and join of the two halves of the basis solves
   double gI_entries = 0, gR_entries = 0;  // G entries streamed by one block solve
+  // Reference counts (lexicographic band factors of each subdomain, bandwidth
+  // b = m_x m_y + m_x + 1 in 3D, m_x + 1 in 2D): band entries of L_I and L_r,
+  // banded Cholesky flops n b^2 per diagonal block of the two chains, and
+  // the banded forward and backward solves of [X | Y'] (4 nnz(L_r) flops
+  // per column).  Executed counts of the coupling kernels per launch.
+  double refI_nnz = 0, refR_nnz = 0, ref_basis_flops = 0;
+  std::vector<double> refI_potrf, refR_potrf;           // per block index k
+  std::vector<double> sc_flops[2], sc_bytes[2];         // schur_couple, per set and k
+  std::vector<double> cm_flops[2][2], cm_bytes[2][2];   // couple_multi, [half][fwd], per k
   int max_block_I = 0, max_block_R = 0;   // largest diagonal block of each set
   Profiler* P_() { return prof.mask ? &prof : nullptr; }
 };
@@ -342,6 +381,26 @@ Batch make_sweep_batch(DevMem& mem, const std::vector<SweepDesc>& v, hipStream_t
   return b;
 }
 
+// Splits a batch of sweeps into buckets by the register-sweep instance
+// their sizes need (the instance of a launch follows its largest matrix),
+// so that small matrices of an uneven batch run at their own instance's
+// occupancy; matrices above the register sweep form the last bucket.
+std::vector<Batch> make_sweep_buckets(DevMem& mem, const std::vector<SweepDesc>& v, hipStream_t s, int reg_max) {
+  const int lim[] = {64, 128, 176, 192, 272, kRegSweepMaxRows, INT32_MAX};
+  std::vector<std::vector<SweepDesc>> g(7);
+  for (const SweepDesc& d : v) {
+    int c = 0;
+    if (d.n > reg_max) c = 6;
+    else
+      while (d.n > lim[c]) ++c;
+    g[c].push_back(d);
+  }
+  std::vector<Batch> out;
+  for (auto& b : g)
+    if (!b.empty()) out.push_back(make_sweep_batch(mem, b, s));
+  return out;
+}
+
 template <typename T>
 void alloc_numeric(bddcso_precond* pc, hipStream_t s) {
   const Plan& pl = *pc->plan;
@@ -397,7 +456,7 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
         d.push_back({B.G_off, B.size, B.size, B.ld});
       }
       check_sweeps(d, pl.pool_G, ns, setR ? "K_rr blocks" : "K_II blocks");
-      vec.push_back(make_sweep_batch(m, d, s));
+      vec.push_back(make_sweep_buckets(m, d, s, pc->opt.sweep_reg_rows));
     }
   }
   pc->zsplit = ns / 2;
@@ -441,7 +500,7 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
     check_sweeps(d, pl.pool_Sc, ns, "S_c");
     check_gemms(lam, pl.pool_Sc, pl.pool_T, pl.pool_T, "Lambda GEMM");
     check_gemms(phir, pl.pool_XG, pl.pool_T, pl.pool_PhiG, "Phi GEMM");
-    pc->swSc = make_sweep_batch(m, d, s);
+    pc->swSc = make_sweep_buckets(m, d, s, pc->opt.sweep_reg_rows);
     pc->gLam = make_gemm_batch(m, lam, s);
     pc->gSel = make_gemm_batch(m, phir, s);
   }
@@ -482,7 +541,7 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       maxfn = std::max(maxfn, F.n);
     }
     check_sweeps(d, pl.front_pool, (int64_t)d.size(), "coarse fronts");
-    pc->swFront.push_back(make_sweep_batch(m, d, s));
+    pc->swFront.push_back(make_sweep_buckets(m, d, s, pc->opt.sweep_reg_rows));
     pc->level_dev.push_back(m.upload(pl.level_fronts[L], s));
     pc->level_n.push_back((int)pl.level_fronts[L].size());
     pc->level_maxn.push_back(mn);
@@ -508,6 +567,95 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
   pc->fsw_stride = std::max<int64_t>(2 * ((int64_t)std::max(maxfn, 1) * kSweepNB + kSweepNB * kSweepNB),
                                      (int64_t)std::max(maxfn, 1) * kSlab);
   pc->fsw = m.alloc<double>(pc->fsw_stride * maxlev);
+}
+
+// Reference and executed work of the profiled kernel classes (host only,
+// from the plan): see the bddcso_precond fields.
+double band_width(int dim, int mx, int my) { return dim == 3 ? (double)mx * my + mx + 1 : (double)mx + 1; }
+double band_nnz(double n, double b) { return n > b ? n * (b + 1) - b * (b + 1) / 2 : n * (n + 1) / 2; }
+
+void precompute_refs(bddcso_precond* pc) {
+  const Plan& pl = *pc->plan;
+  const Classification& c = pc->prob->c;
+  const double es = pc->precision == 1 ? 4.0 : 8.0;
+  const int ns = (int)pl.subs.size();
+  pc->refI_potrf.assign(pl.max_nbI, 0.0);
+  pc->refR_potrf.assign(pl.max_nbR, 0.0);
+  for (int st = 0; st < 2; ++st) {
+    const int nb = st ? pl.max_nbR : pl.max_nbI;
+    pc->sc_flops[st].assign(nb, 0.0);
+    pc->sc_bytes[st].assign(nb, 0.0);
+  }
+  for (int h = 0; h < 2; ++h)
+    for (int f = 0; f < 2; ++f) {
+      pc->cm_flops[h][f].assign(pl.max_nbR, 0.0);
+      pc->cm_bytes[h][f].assign(pl.max_nbR, 0.0);
+    }
+  for (int sidx = 0; sidx < ns; ++sidx) {
+    const SubDev& S = pl.subs[sidx];
+    int mI[2];
+    for (int a = 0; a < 2; ++a) mI[a] = S.m[a] - (S.elo[a] > 0 ? 1 : 0) - (S.ehi[a] < (int)c.ne[a] ? 1 : 0);
+    const double bI = band_width(c.dim, mI[0], mI[1]), bR = band_width(c.dim, S.m[0], S.m[1]);
+    pc->refI_nnz += band_nnz(S.n_I, bI);
+    pc->refR_nnz += band_nnz(S.n_r, bR);
+    const int ncols = S.n_a + S.n_v;
+    pc->ref_basis_flops += 4.0 * band_nnz(S.n_r, bR) * ncols;
+    for (int st = 0; st < 2; ++st) {
+      const int nb = st ? S.nbR : S.nbI;
+      const BlockDev* blk = pl.blocks.data() + (st ? S.bR_off : S.bI_off);
+      const double bw = st ? bR : bI;
+      for (int k = 0; k < nb; ++k) {
+        const BlockDev& B = blk[k];
+        (st ? pc->refR_potrf : pc->refI_potrf)[k] += (double)B.size * bw * bw;
+        if (k > 0 && B.cf_off >= 0) {
+          const double lp = blk[k - 1].last_n, fn = B.first_n;
+          pc->sc_bytes[st][k] += es * (lp * lp + 2.0 * fn * fn) + 12.0 * 9.0 * fn;
+          pc->sc_flops[st][k] += 18.0 * (lp * fn + fn * fn);
+        }
+        if (!st || ncols == 0) continue;
+        const int h = sidx < pc->zsplit ? 0 : 1;
+        if (B.za > 0) {  // forward coupling product over the reached columns
+          const bool cpl = k > 0 && B.cf_off >= 0;
+          pc->cm_bytes[h][1][k] += es * 2.0 * B.size * B.za +
+                                   (cpl ? es * blk[k - 1].last_n * B.za + 12.0 * 9.0 * B.first_n : 0.0);
+          pc->cm_flops[h][1][k] += cpl ? 18.0 * B.first_n * B.za : 0.0;
+        }
+        if (k + 1 < nb && B.cb_off >= 0) {  // backward coupling product
+          pc->cm_bytes[h][0][k] += es * ((double)blk[k + 1].first_n * ncols + (double)B.last_n * ncols) +
+                                   12.0 * 9.0 * B.last_n;
+          pc->cm_flops[h][0][k] += 18.0 * B.last_n * ncols;
+        }
+      }
+    }
+  }
+}
+
+// Reference (Cholesky-equivalent) flops of the sweeps of one batch, booked
+// under the class its launches time: the register path (class 5) or the
+// slab path (pivot blocks and panels class 4, trailing updates class 1).
+// A matrix of n rows with p pivots: p^3/3 to factor the pivots,
+// (n - p) p^2 for the border, (n - p)^2 p for the Schur update.
+void ref_sweep_batch(bddcso_precond* pc, const Batch& b) {
+  if (!pc->P_()) return;
+  double fac = 0, upd = 0;
+  for (const SweepDesc& d : b.hs) {
+    const double n = d.n, p = d.p, m = n - p;
+    fac += p * p * p / 3.0 + m * p * p;
+    upd += m * m * p;
+  }
+  if (b.maxn <= pc->opt.sweep_reg_rows) pc->prof.ref(5, fac + upd, 0.0);
+  else {
+    pc->prof.ref(4, fac, 0.0);
+    pc->prof.ref(1, upd, 0.0);
+  }
+}
+
+// executed = reference flops of a batch of GEMM products (2 m n k each)
+void ref_gemm_batch(bddcso_precond* pc, const Batch& b) {
+  if (!pc->P_()) return;
+  double f = 0;
+  for (const GemmDesc& d : b.hg) f += 2.0 * d.m * d.n * d.k;
+  pc->prof.ref(3, f, 0.0);
 }
 
 template <typename T>
@@ -536,9 +684,26 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
     auto& sw = setR ? pc->swR : pc->swI;
     for (int k = 0; k < (int)sw.size(); ++k) {
       if (k == 1 && setR) HIPCHK(hipStreamWaitEvent(ss, pc->ev_cpl, 0));  // the coupling coefficients
-      if (k > 0) Kern<T>::schur_couple(P, g, rho, setR, k, N.G, W, N.wstride, ss);
-      Kern<T>::sweep((SweepDesc*)sw[k].desc, sw[k].hs.data(), sw[k].n, sw[k].maxn, sw[k].maxp, N.G, sws,
-                     N.sw_stride, pc->status, setR ? 2 : 1, ss, pc->P_());
+      if (k > 0) {
+        if (pc->P_()) pc->prof.begin(6, ss);
+        Kern<T>::schur_couple(P, g, rho, setR, k, N.G, W, N.wstride, ss);
+        if (pc->P_()) {
+          pc->prof.end(6, pc->sc_flops[setR][k], pc->sc_bytes[setR][k], ss);
+          pc->prof.ref(6, pc->sc_flops[setR][k], pc->sc_bytes[setR][k]);
+        }
+      }
+      int maxn = 0;
+      for (const Batch& b : sw[k]) {
+        Kern<T>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, N.G, sws, N.sw_stride, pc->status,
+                       setR ? 2 : 1, ss, pc->P_(), nullptr, pc->opt.sweep_reg_rows, pc->opt.slab_lookahead,
+                       pc->opt.update_tile);
+        maxn = std::max(maxn, b.maxn);
+      }
+      if (pc->P_()) {  // banded Cholesky of block k of every subdomain
+        const double f = (setR ? pc->refR_potrf : pc->refI_potrf)[k];
+        if (maxn <= pc->opt.sweep_reg_rows) pc->prof.ref(5, f, 0.0);
+        else pc->prof.ref(4, f, 0.0);
+      }
     }
   };
   factor_chain(1, s);
@@ -554,8 +719,16 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   const int nk = (int)pc->gfwd[0].size();
   auto zchain = [&](int h, hipStream_t ss) {
     const int sub0 = h ? pc->zsplit : 0, nsub = h ? (int)pl.subs.size() - pc->zsplit : pc->zsplit;
+    auto couple = [&](int k, int fwd) {
+      if (pc->P_()) pc->prof.begin(7, ss);
+      Kern<T>::couple_multi(P, g, rho, k, fwd, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, ss, sub0, nsub);
+      if (pc->P_()) {
+        pc->prof.end(7, pc->cm_flops[h][fwd][k], pc->cm_bytes[h][fwd][k], ss);
+        pc->prof.ref(7, pc->cm_flops[h][fwd][k], pc->cm_bytes[h][fwd][k]);
+      }
+    };
     for (int k = 0; k < nk; ++k) {
-      Kern<T>::couple_multi(P, g, rho, k, 1, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, ss, sub0, nsub);
+      couple(k, 1);
       if (k == 0 && h == 0) {
         HIPCHK(hipEventRecord(pc->ev_zf, ss));
         HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_zf, 0));
@@ -565,7 +738,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
                     pc->P_());
     }
     for (int k = nk - 2; k >= 0; --k) {
-      Kern<T>::couple_multi(P, g, rho, k, 0, pl.max_zcols, N.Z, N.tmp, N.tmp_stride, ss, sub0, nsub);
+      couple(k, 0);
       const Batch& b = pc->gbwd[h][k];
       Kern<T>::gemm((GemmDesc*)b.desc, b.hg.data(), b.n, b.maxm, b.maxn, N.G, 0, N.tmp, 0, N.Z, (T)1, (T)1, ss,
                     pc->P_());
@@ -579,18 +752,27 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   zchain(1, pc->s2);
   HIPCHK(hipEventRecord(pc->ev_zj, pc->s2));
   HIPCHK(hipStreamWaitEvent(s, pc->ev_zj, 0));
+  // the banded forward and backward solves the block GEMMs stand for
+  if (pc->P_()) pc->prof.ref(3, pc->ref_basis_flops, 0.0);
   // constraint Schur complement and the coarse basis
   Kern<T>::sc_assemble(P, N.Z, N.Sc, s);
-  Kern<T>::sweep((SweepDesc*)pc->swSc.desc, pc->swSc.hs.data(), pc->swSc.n, pc->swSc.maxn, pc->swSc.maxp, N.Sc,
-                 N.sw, N.sw_stride, pc->status, 3, s, pc->P_());
+  for (const Batch& b : pc->swSc) {
+    Kern<T>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, N.Sc, N.sw, N.sw_stride, pc->status, 3, s,
+                   pc->P_(), nullptr, pc->opt.sweep_reg_rows, pc->opt.slab_lookahead, pc->opt.update_tile);
+    ref_sweep_batch(pc, b);
+  }
   Kern<T>::lambda_rhs(P, N.Z, N.Tm, s);
   Kern<T>::gemm((GemmDesc*)pc->gLam.desc, pc->gLam.hg.data(), pc->gLam.n, pc->gLam.maxm, pc->gLam.maxn, N.Sc, 0,
                 N.Tm, 0, N.Lam, (T)-1, (T)0, s, pc->P_());
+  ref_gemm_batch(pc, pc->gLam);
+  Kern<T>::float_setup(P, N.Sc, N.Lam, pc->feps, pc->fdelta, s);
   // Phi = Y' - X Lambda, only at the selected rows (Gamma and the vertices' stencils)
   Kern<T>::sel_gather(P, N.Z, N.XG, s);
   Kern<T>::gemm((GemmDesc*)pc->gSel.desc, pc->gSel.hg.data(), pc->gSel.n, pc->gSel.maxm, pc->gSel.maxn, N.XG, 0,
                 N.Lam, 0, N.PhiG, (T)-1, (T)0, s, pc->P_());
+  ref_gemm_batch(pc, pc->gSel);
   Kern<T>::phi_add(P, N.Z, N.PhiG, pc->max_nv, s);
+  Kern<T>::float_phi(P, pc->feps, N.PhiG, s);
   Kern<T>::yg_gather(P, N.Z, N.YG, pc->max_nv, s);
   Kern<T>::kc_identity(P, g, rho, N.PhiG, N.Lam, N.Kc, pc->vcoef, pc->vcode, pc->max_nv, s);
   // The interior (Dirichlet) factors are needed only when the preconditioner
@@ -618,10 +800,13 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
     else
       for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
         launch_front_child_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fpool, s);
-    const Batch& b = pc->swFront[L];
     const SweepAux aux{pc->s2, pc->ev_la, pc->ev_lb, pc->ev_lc};
-    Kern<double>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, pc->fpool, pc->fsw, pc->fsw_stride,
-                        pc->status, 4, s, pc->P_(), &aux);
+    for (const Batch& b : pc->swFront[L]) {
+      Kern<double>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, pc->fpool, pc->fsw,
+                          pc->fsw_stride, pc->status, 4, s, pc->P_(), &aux, pc->opt.sweep_reg_rows,
+                          pc->opt.slab_lookahead, pc->opt.update_tile);
+      ref_sweep_batch(pc, b);
+    }
   }
   HIPCHK(hipStreamWaitEvent(s, pc->ev_join_i, 0));  // the interior factors
 }
@@ -637,7 +822,7 @@ void coarse_solve(bddcso_precond* pc, int nrhs, hipStream_t s) {
       launch_front_vec_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fvec, stride,
                                nrhs, s);
     launch_front_fwd(P, pc->level_dev[L], pc->level_n[L], pc->level_maxn[L], pc->level_maxp[L], pc->fpool,
-                     pc->fvec, pc->xh, stride, nrhs, s, nrhs < 4 ? pc->fpart : nullptr);
+                     pc->fvec, pc->xh, stride, nrhs, s, nrhs < pc->P.mr_min ? pc->fpart : nullptr);
   }
   for (int L = nlev - 1; L >= 0; --L)
     launch_front_bwd(P, pc->level_dev[L], pc->level_n[L], pc->level_maxp[L], pc->level_maxb[L], pc->fpool, pc->xh,
@@ -655,6 +840,7 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   Kern<T>::gather_I(P, g, r, N.vI, nrhs, s);
   Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s, pc->P_(), pc->gI_entries, (double)pl.tot_I,
                        pc->max_block_I);
+  if (pc->P_()) pc->prof.ref(2, 4.0 * pc->refI_nnz * nrhs, sizeof(T) * (2.0 * pc->refI_nnz + 2.0 * pl.tot_I * nrhs));
   Kern<T>::gamma_kgi(P, g, rho, N.vI, N.q, nrhs, s);
   // 3: E^T
   Kern<T>::gamma_t(P, g, r, N.q, pc->delta, N.gv, nrhs, s);
@@ -669,7 +855,9 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   Kern<T>::neumann_rhs(P, N.gv, N.vR, nrhs, s);
   Kern<T>::block_solve(P, g, rho, 1, N.G, N.vR, nrhs, s, pc->P_(), pc->gR_entries, (double)pl.tot_r,
                        pc->max_block_R);
+  if (pc->P_()) pc->prof.ref(2, 4.0 * pc->refR_nnz * nrhs, sizeof(T) * (2.0 * pc->refR_nnz + 2.0 * pl.tot_r * nrhs));
   Kern<T>::mu(P, N.vR, N.Sc, N.mu, nrhs, s);
+  Kern<T>::float_mu(P, N.gv, N.mu, pc->feps, pc->fdelta, pc->fc, nrhs, s);
   HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_cfork, 0));
   Kern<T>::coarse_rhs_local(P, N.PhiG, N.gv, N.bci, nrhs, pc->s2);
   if (sizeof(T) == 8) launch_coarse_rhs_gather(P, (const double*)N.bci, nullptr, pc->bc, nrhs, pc->s2);
@@ -680,13 +868,35 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   HIPCHK(hipStreamWaitEvent(s, pc->ev_cjoin, 0));
   // 7-8: v2 on Gamma and E
   Kern<T>::v2(P, N.vR, N.XG, N.mu, N.lu, N.YG, pc->uc, N.v2, nrhs, s);
+  Kern<T>::float_v2(P, pc->uc, pc->feps, pc->fc, N.v2, nrhs, s);
   if (sizeof(T) == 8) launch_gamma_w(P, g, (const double*)N.v2, nullptr, pc->delta, z, nrhs, s);
   else launch_gamma_w(P, g, nullptr, (const float*)N.v2, pc->delta, z, nrhs, s);
   // 9-10: harmonic extension into the interiors
   Kern<T>::interior_rhs(P, g, rho, r, z, N.vI, nrhs, s);
   Kern<T>::block_solve(P, g, rho, 0, N.G, N.vI, nrhs, s, pc->P_(), pc->gI_entries, (double)pl.tot_I,
                        pc->max_block_I);
+  if (pc->P_()) pc->prof.ref(2, 4.0 * pc->refI_nnz * nrhs, sizeof(T) * (2.0 * pc->refI_nnz + 2.0 * pl.tot_I * nrhs));
   Kern<T>::scatter_I(P, g, N.vI, z, nrhs, s);
+}
+
+// Captures the work body enqueues on the preconditioner's capture stream
+// (and on the streams it forks to) into an instantiated graph.
+template <typename F>
+hipGraphExec_t capture_graph(bddcso_precond* pc, F&& body) {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  HIPCHK(hipStreamBeginCapture(pc->sg, hipStreamCaptureModeThreadLocal));
+  try {
+    body(pc->sg);
+  } catch (...) {
+    if (hipStreamEndCapture(pc->sg, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(pc->sg, &g));
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) throw HipFail{e, "hipGraphInstantiate"};
+  return ex;
 }
 
 void apply_B_any(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream_t s) {
@@ -800,7 +1010,12 @@ void layout(bddcso_precond* pc, hipStream_t s) {
   P.max_zcols = pl.max_zcols;
   P.max_plane = max_plane;
   P.max_nv = 0;
-  for (auto& S : pl.subs) P.max_nv = std::max(P.max_nv, S.n_v);
+  P.n_pinned = 0;
+  for (auto& S : pl.subs) {
+    P.max_nv = std::max(P.max_nv, S.n_v);
+    if (S.pin >= 0) ++P.n_pinned;
+  }
+  P.mr_min = o.mr_min_rhs;
   if (max_lds_bytes(P, o.precision == 1 ? 4 : 8, o.max_nrhs) > 160 * 1024)
     throw PlanFail{"a subdomain plane or block is too large for the LDS staging of the local kernels"};
 
@@ -820,11 +1035,13 @@ void layout(bddcso_precond* pc, hipStream_t s) {
   {
     int maxp = 1;
     for (auto& F : pl.fronts) maxp = std::max(maxp, F.p);
-    pc->fpart = m.alloc<double>((int64_t)front_fwd_chunks(maxp) * std::min(nr, 3) * pl.front_vec);
+    pc->fpart = m.alloc<double>((int64_t)front_fwd_chunks(maxp) * std::max(1, std::min(nr, o.mr_min_rhs - 1)) *
+                                pl.front_vec);
   }
   if (o.precision == 1) alloc_numeric<float>(pc, s);
   else alloc_numeric<double>(pc, s);
   build_batches(pc, s);
+  precompute_refs(pc);
   const int64_t n = c.n_free;
   pc->r = m.alloc<double>(n * nr);
   pc->p = m.alloc<double>(n * nr);
@@ -841,6 +1058,11 @@ void layout(bddcso_precond* pc, hipStream_t s) {
   pc->iters = m.alloc<int32_t>(nr);
   pc->flags = m.alloc<int32_t>(nr);
   pc->nactive = m.alloc<int32_t>(1);
+  pc->xk = m.alloc<double>(n * nr);
+  pc->kdev = m.alloc<int32_t>(1);
+  pc->feps = m.alloc<double>(pl.tot_a);
+  pc->fdelta = m.alloc<double>(c.n_sub);
+  pc->fc = m.alloc<double>((int64_t)c.n_sub * nr);
 }
 
 // Streams, events and the pinned flag of the convergence test (no device
@@ -849,6 +1071,7 @@ void make_streams(bddcso_precond* pc) {
   HIPCHK(hipHostMalloc((void**)&pc->h_nactive, sizeof(int32_t) * 4, hipHostMallocDefault));
   HIPCHK(hipStreamCreateWithFlags(&pc->s2, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&pc->s3, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&pc->sg, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&pc->ev_fork_i, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&pc->ev_cpl, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&pc->ev_cfork, hipEventDisableTiming));
@@ -874,9 +1097,19 @@ bddcso_status create_precond(bddcso_problem* p, const bddcso_options* opts, DevM
   else bddcso_default_options(&o);
   if (o.max_nrhs < 1 || o.max_nrhs > BDDCSO_MAX_RHS) return set_err(BDDCSO_EINVAL, "max_nrhs out of range");
   if (o.precision != 0 && o.precision != 1) return set_err(BDDCSO_EINVAL, "precision must be 0 or 1");
-  if (o.primal_mask <= 0 || o.primal_mask > 7) return set_err(BDDCSO_EINVAL, "primal_mask must be in 1..7");
+  if ((o.primal_mask & 7) == 0 || o.primal_mask > 15)
+    return set_err(BDDCSO_EINVAL, "primal_mask must select v, e or f (bits 1, 2, 4; bit 8 halves the faces)");
   if (o.coarse_solver != 0 && o.coarse_solver != 1) return set_err(BDDCSO_EINVAL, "coarse_solver must be 0 or 1");
   if (o.maxit < 0 || o.fixed_iters < 0) return set_err(BDDCSO_EINVAL, "maxit and fixed_iters must be >= 0");
+  if (o.graph != 0 && o.graph != 1) return set_err(BDDCSO_EINVAL, "graph must be 0 or 1");
+  if (o.sweep_reg_rows == 0) o.sweep_reg_rows = kRegSweepMaxRows;
+  if (o.sweep_reg_rows < 16 || o.sweep_reg_rows > kRegSweepMaxRows)
+    return set_err(BDDCSO_EINVAL, "sweep_reg_rows must be 0 or in 16..304");
+  if (o.slab_lookahead < 0 || o.slab_lookahead > 2) return set_err(BDDCSO_EINVAL, "slab_lookahead must be 0, 1 or 2");
+  if (o.mr_min_rhs == 0) o.mr_min_rhs = 4;
+  if (o.mr_min_rhs < 1) return set_err(BDDCSO_EINVAL, "mr_min_rhs must be >= 0");
+  if (o.update_tile == 0) o.update_tile = 64;
+  if (o.update_tile != 64 && o.update_tile != 128) return set_err(BDDCSO_EINVAL, "update_tile must be 0, 64 or 128");
   Error err;
   std::shared_ptr<Plan> plan;
   try {
@@ -949,6 +1182,11 @@ void bddcso_default_options(bddcso_options* o) {
   o->fixed_iters = 0;
   o->flexible = 0;
   o->block_target = 0;
+  o->graph = 0;
+  o->sweep_reg_rows = 0;
+  o->slab_lookahead = 0;
+  o->mr_min_rhs = 0;
+  o->update_tile = 0;
 }
 
 const char* bddcso_last_error(void) { return g_last_error.c_str(); }
@@ -982,7 +1220,7 @@ bddcso_status bddcso_problem_info(const bddcso_problem* p, int primal_mask, int6
   if (n_sub) *n_sub = p->c.n_sub;
   int64_t cnt[3] = {0, 0, 0};
   for (int o = 0; o < p->c.n_obj(); ++o)
-    if (p->c.obj_type[o] & primal_mask) {
+    if ((p->c.obj_type[o] & primal_mask) && (!(primal_mask & kHalfCodim1) || half_keep(p->c, o))) {
       int t = p->c.obj_type[o];
       cnt[t == 1 ? 0 : (t == 2 ? 1 : 2)]++;
     }
@@ -999,6 +1237,12 @@ void bddcso_precond_destroy(bddcso_precond* pc) {
   if (!pc) return;
   if (pc->s2) (void)hipStreamSynchronize(pc->s2);
   if (pc->s3) (void)hipStreamSynchronize(pc->s3);
+  if (pc->sg) (void)hipStreamSynchronize(pc->sg);
+  if (pc->g_setup) (void)hipGraphExecDestroy(pc->g_setup);
+  for (auto& kv : pc->iter_graphs) {
+    if (kv.second.g1) (void)hipGraphExecDestroy(kv.second.g1);
+    if (kv.second.g2) (void)hipGraphExecDestroy(kv.second.g2);
+  }
   pc->mem.release();
   if (pc->ev_fork) (void)hipEventDestroy(pc->ev_fork);
   if (pc->ev_join) (void)hipEventDestroy(pc->ev_join);
@@ -1014,6 +1258,7 @@ void bddcso_precond_destroy(bddcso_precond* pc) {
   if (pc->ev_join_i) (void)hipEventDestroy(pc->ev_join_i);
   if (pc->s2) (void)hipStreamDestroy(pc->s2);
   if (pc->s3) (void)hipStreamDestroy(pc->s3);
+  if (pc->sg) (void)hipStreamDestroy(pc->sg);
   if (pc->h_nactive) (void)hipHostFree(pc->h_nactive);
   delete pc;
 }
@@ -1026,8 +1271,18 @@ bddcso_status bddcso_refactor(bddcso_precond* pc, const double* rho_dev, void* s
   try {
     HIPCHK(hipMemcpyAsync(pc->rho, rho_dev, pc->geo.n_elem * sizeof(double), hipMemcpyDeviceToDevice, s));
     ++pc->generation;
-    if (pc->precision == 1) numeric_setup<float>(pc, s);
-    else numeric_setup<double>(pc, s);
+    if (pc->opt.graph && !pc->P_()) {
+      if (!pc->g_setup)
+        pc->g_setup = capture_graph(pc, [&](hipStream_t ss) {
+          if (pc->precision == 1) numeric_setup<float>(pc, ss);
+          else numeric_setup<double>(pc, ss);
+        });
+      HIPCHK(hipGraphLaunch(pc->g_setup, s));
+    } else if (pc->precision == 1) {
+      numeric_setup<float>(pc, s);
+    } else {
+      numeric_setup<double>(pc, s);
+    }
     HIPCHK(hipGetLastError());
   } catch (const HipFail& f) {
     return set_err(BDDCSO_EHIP, f.where + ": " + hipGetErrorString(f.e));
@@ -1186,13 +1441,51 @@ bddcso_status solve_impl(bddcso_precond* pc, const Krylov& K, const double* b, d
     launch_dot(K.r, K.z, n, nr, K.partial, pc->dot_blocks, s_rz, s);
     int any = 0;
     for (int j = 0; j < nr; ++j) any |= hact[j];
+    // One iteration in two halves: the operator and the x, r update up to
+    // the convergence test, then the preconditioner and the p update.
+    // kd: device iteration counter of replayed graphs (nullptr: k).
+    auto half1 = [&](hipStream_t ss, int k, const int32_t* kd, double* xw) {
+      if (pc->P_()) pc->prof.begin(8, ss);
+      launch_q1_apply(pc->geo, pc->khat, pc->rho, K.p, K.qv, nr, ss);
+      if (pc->P_()) {  // x read and y written per column, rho once
+        const double f = 2.0 * (pc->geo.dim == 3 ? 27 : 9) * (double)n * nr;
+        const double b = 8.0 * (2.0 * (double)n * nr + (double)pc->geo.n_elem);
+        pc->prof.end(8, f, b, ss);
+        pc->prof.ref(8, f, b);
+      }
+      launch_dot(K.p, K.qv, n, nr, K.partial, pc->dot_blocks, s_pq, ss);
+      if (flex) launch_copy_f64(K.r, K.rold, n * nr, ss);
+      launch_pcg_xr(xw, K.r, K.p, K.qv, s_rz, s_pq, K.active, n, nr, ss);
+      launch_dot(K.r, K.r, n, nr, K.partial, pc->dot_blocks, s_rr, ss);
+      launch_pcg_book1(nr, k, kd, s_rz, s_pq, s_rr, s_tol, K.active, K.iters, K.flags, K.hist_a, K.nactive, ss);
+    };
+    auto half2 = [&](hipStream_t ss, int k, int32_t* kd) {
+      apply_B_any(pc, K.r, K.z, nr, ss);
+      launch_dot(K.r, K.z, n, nr, K.partial, pc->dot_blocks, s_rzn, ss);
+      if (flex) {
+        launch_sub(K.r, K.rold, K.dtmp, n * nr, ss);
+        launch_dot(K.z, K.dtmp, n, nr, K.partial, pc->dot_blocks, s_num, ss);
+        launch_pcg_p(K.p, K.z, s_num, s_rz, K.active, n, nr, ss);
+        launch_pcg_book2(nr, k, kd, s_rz, s_num, s_rzn, K.active, K.hist_b, ss);
+      } else {
+        launch_pcg_p(K.p, K.z, s_rzn, s_rz, K.active, n, nr, ss);
+        launch_pcg_book2(nr, k, kd, s_rz, s_rzn, s_rzn, K.active, K.hist_b, ss);
+      }
+    };
+    // Graph mode: the two halves are captured once per right-hand-side
+    // count and replayed; x accumulates in the preconditioner's own buffer.
+    const bool graph = o.graph && !pc->P_() && K.r == pc->r;
+    GraphPair* gp = nullptr;
+    if (graph) {
+      gp = &pc->iter_graphs[nr];
+      if (!gp->g1) gp->g1 = capture_graph(pc, [&](hipStream_t ss) { half1(ss, 0, pc->kdev, pc->xk); });
+      if (!gp->g2) gp->g2 = capture_graph(pc, [&](hipStream_t ss) { half2(ss, 0, pc->kdev); });
+      launch_fill_f64(pc->xk, n * nr, 0.0, s);
+      launch_fill_i32(pc->kdev, 1, 0, s);
+    }
     for (int k = 0; any && k < limit; ++k) {
-      launch_q1_apply(pc->geo, pc->khat, pc->rho, K.p, K.qv, nr, s);
-      launch_dot(K.p, K.qv, n, nr, K.partial, pc->dot_blocks, s_pq, s);
-      if (flex) HIPCHK(hipMemcpyAsync(K.rold, K.r, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
-      launch_pcg_xr(x, K.r, K.p, K.qv, s_rz, s_pq, K.active, n, nr, s);
-      launch_dot(K.r, K.r, n, nr, K.partial, pc->dot_blocks, s_rr, s);
-      launch_pcg_book1(nr, k, s_rz, s_pq, s_rr, s_tol, K.active, K.iters, K.flags, K.hist_a, K.nactive, s);
+      if (graph) HIPCHK(hipGraphLaunch(gp->g1, s));
+      else half1(s, k, nullptr, x);
       k_done = k + 1;
       if (o.fixed_iters <= 0) {
         HIPCHK(hipMemcpyAsync(pc->h_nactive, K.nactive, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1200,18 +1493,10 @@ bddcso_status solve_impl(bddcso_precond* pc, const Krylov& K, const double* b, d
         if (*pc->h_nactive == 0) break;
       }
       if (k + 1 == limit) break;
-      apply_B_any(pc, K.r, K.z, nr, s);
-      launch_dot(K.r, K.z, n, nr, K.partial, pc->dot_blocks, s_rzn, s);
-      if (flex) {
-        launch_sub(K.r, K.rold, K.dtmp, n * nr, s);
-        launch_dot(K.z, K.dtmp, n, nr, K.partial, pc->dot_blocks, s_num, s);
-        launch_pcg_p(K.p, K.z, s_num, s_rz, K.active, n, nr, s);
-        launch_pcg_book2(nr, k, s_rz, s_num, s_rzn, K.active, K.hist_b, s);
-      } else {
-        launch_pcg_p(K.p, K.z, s_rzn, s_rz, K.active, n, nr, s);
-        launch_pcg_book2(nr, k, s_rz, s_rzn, s_rzn, K.active, K.hist_b, s);
-      }
+      if (graph) HIPCHK(hipGraphLaunch(gp->g2, s));
+      else half2(s, k, nullptr);
     }
+    if (graph) launch_copy_f64(pc->xk, x, n * nr, s);
     HIPCHK(hipGetLastError());
     // results
     std::vector<int32_t> it(nr), fl(nr);
@@ -1373,6 +1658,94 @@ bddcso_status bddcso_precond_generation(const bddcso_precond* pc, int64_t* gener
   return BDDCSO_OK;
 }
 
+bddcso_status bddcso_autotune(bddcso_problem* p, const double* rho_dev, const bddcso_options* base,
+                              const double* b_dev, int nrhs, void* stream, bddcso_options* best,
+                              bddcso_tune_report* report) {
+  if (!p || !rho_dev || !b_dev || !best) return set_err(BDDCSO_EINVAL, "null argument");
+  bddcso_options o0;
+  if (base) o0 = *base;
+  else bddcso_default_options(&o0);
+  if (nrhs < 1 || nrhs > BDDCSO_MAX_RHS) return set_err(BDDCSO_EINVAL, "nrhs must be in 1..64");
+  o0.max_nrhs = std::max(o0.max_nrhs, nrhs);
+  // the knobs' defaults made explicit, so no variant repeats the base
+  if (o0.sweep_reg_rows == 0) o0.sweep_reg_rows = kRegSweepMaxRows;
+  if (o0.mr_min_rhs == 0) o0.mr_min_rhs = 4;
+  if (o0.block_target == 0) o0.block_target = 192;
+  if (o0.update_tile == 0) o0.update_tile = 64;
+  hipStream_t s = as_stream(stream);
+  bddcso_tune_report R;
+  std::memset(&R, 0, sizeof(R));
+  double* x = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMalloc((void**)&x, sizeof(double) * (size_t)p->c.n_free * nrhs) != hipSuccess)
+    return set_err(BDDCSO_ENOMEM, "autotune: device allocation failed");
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipFree(x);
+    return set_err(BDDCSO_EHIP, "autotune: event creation failed");
+  }
+  const double inf = std::numeric_limits<double>::infinity();
+  // one trial: a preconditioner for these options, an untimed step, then a
+  // step (numeric setup + solve) timed with events on the stream
+  auto trial = [&](const bddcso_options& o) -> double {
+    if (R.n_trials >= BDDCSO_TUNE_MAX) return inf;
+    const int t = R.n_trials++;
+    R.tried[t] = o;
+    R.step_ms[t] = inf;
+    bddcso_precond* pc = nullptr;
+    bddcso_status st = bddcso_setup(p, rho_dev, &o, nullptr, 0, stream, &pc);
+    if (st == BDDCSO_OK) st = bddcso_solve(pc, b_dev, x, nrhs, nullptr, stream);
+    if (st == BDDCSO_OK || st == BDDCSO_ENOCONV) {
+      st = BDDCSO_OK;
+      bool ok = hipEventRecord(e0, s) == hipSuccess;
+      bddcso_status s1 = bddcso_refactor(pc, rho_dev, stream);
+      bddcso_status s2 = s1 == BDDCSO_OK ? bddcso_solve(pc, b_dev, x, nrhs, nullptr, stream) : s1;
+      ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+      float ms = 0.f;
+      if (ok && (s2 == BDDCSO_OK || s2 == BDDCSO_ENOCONV) && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+        R.step_ms[t] = ms;
+      else
+        st = s2 != BDDCSO_OK ? s2 : BDDCSO_EHIP;
+    }
+    if (pc) bddcso_precond_destroy(pc);
+    R.status[t] = st;
+    return R.step_ms[t];
+  };
+  bddcso_options cur = o0;
+  double best_ms = trial(cur);
+  R.best = 0;
+  // a variant replaces the current choice only when it is more than 1% faster
+  auto knob = [&](int bddcso_options::*field, std::initializer_list<int> values) {
+    for (int v : values) {
+      if (cur.*field == v) continue;
+      bddcso_options cand = cur;
+      cand.*field = v;
+      const double ms = trial(cand);
+      if (ms < 0.99 * best_ms) {
+        best_ms = ms;
+        cur = cand;
+        R.best = R.n_trials - 1;
+      }
+    }
+  };
+  knob(&bddcso_options::update_tile, {64, 128});
+  knob(&bddcso_options::slab_lookahead, {0, 1, 2});
+  knob(&bddcso_options::sweep_reg_rows, {kRegSweepMaxRows, 272});
+  knob(&bddcso_options::block_target, {192, 128, 256});
+  if (nrhs > 1) knob(&bddcso_options::mr_min_rhs, {4, 2, 8, BDDCSO_MAX_RHS + 1});
+  knob(&bddcso_options::graph, {0, 1});
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(x);
+  if (!(best_ms < inf)) {
+    if (report) *report = R;
+    return set_err(R.status[0] != BDDCSO_OK ? (bddcso_status)R.status[0] : BDDCSO_EHIP,
+                   "autotune: no variant completed a step");
+  }
+  *best = cur;
+  if (report) *report = R;
+  return BDDCSO_OK;
+}
+
 bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bddcso_plan_stats* out) {
   if (!p || !out) return set_err(BDDCSO_EINVAL, "null argument");
   bddcso_options o;
@@ -1411,7 +1784,8 @@ bddcso_status bddcso_plan_info(bddcso_problem* p, const bddcso_options* opts, bd
 
 bddcso_status bddcso_profile(bddcso_precond* pc, int class_mask) {
   if (!pc) return set_err(BDDCSO_EINVAL, "null precond");
-  if (class_mask < 0 || class_mask > 0x3e) return set_err(BDDCSO_EINVAL, "class mask must use bits 1..5");
+  if (class_mask < 0 || class_mask > (1 << (kNumClasses + 1)) - 2)
+    return set_err(BDDCSO_EINVAL, "class mask must use bits 1..8");
   pc->prof.reset(class_mask);
   return BDDCSO_OK;
 }
@@ -1419,7 +1793,7 @@ bddcso_status bddcso_profile(bddcso_precond* pc, int class_mask) {
 bddcso_status bddcso_profile_read(bddcso_precond* pc, int kernel_class, int64_t* launches, double* total_ms,
                                   double* flops, double* bytes) {
   if (!pc) return set_err(BDDCSO_EINVAL, "null precond");
-  if (kernel_class < 1 || kernel_class > 5) return set_err(BDDCSO_EINVAL, "kernel class must be in 1..5");
+  if (kernel_class < 1 || kernel_class > kNumClasses) return set_err(BDDCSO_EINVAL, "kernel class must be in 1..8");
   auto& R = pc->prof.rec[kernel_class];
   double ms = 0.0;
   for (size_t i = 0; i + 1 < R.used; i += 2) {
@@ -1433,6 +1807,15 @@ bddcso_status bddcso_profile_read(bddcso_precond* pc, int kernel_class, int64_t*
   if (total_ms) *total_ms = ms;
   if (flops) *flops = R.flops;
   if (bytes) *bytes = R.bytes;
+  return BDDCSO_OK;
+}
+
+bddcso_status bddcso_profile_reference(const bddcso_precond* pc, int kernel_class, double* flops, double* bytes) {
+  if (!pc) return set_err(BDDCSO_EINVAL, "null precond");
+  if (kernel_class < 1 || kernel_class > kNumClasses) return set_err(BDDCSO_EINVAL, "kernel class must be in 1..8");
+  const auto& R = pc->prof.rec[kernel_class];
+  if (flops) *flops = R.ref_flops;
+  if (bytes) *bytes = R.ref_bytes;
   return BDDCSO_OK;
 }
 

@@ -14,6 +14,9 @@ constexpr int kSweepNB = 32;
 // Pivots per slab when sweeping matrices above 272 rows; their scratch needs
 // n x kSlab entries per matrix.
 constexpr int kSlab = 192;
+// Largest matrix swept by the register-resident kernel (one workgroup per
+// matrix); larger ones take the slab path.
+constexpr int kRegSweepMaxRows = 304;
 
 // Geometry passed by value to kernels.
 struct Geo {
@@ -72,6 +75,8 @@ struct PlanDev {
   int n_sub;
   int64_t tot_I, tot_r, tot_g, tot_c, tot_a, n_gam, n_coarse;
   int max_block, max_na, max_nc, max_ng, max_ns, max_nloc, max_nr, max_nI, max_zcols, max_plane, max_nv;
+  int n_pinned;  // subdomains with a pin (SubDev::pin >= 0)
+  int mr_min;    // right-hand sides from which the many-RHS kernels run
 };
 
 // ---- launchers (defined in kernels.hip) ---------------------------------
@@ -97,9 +102,13 @@ struct Kern {
                              hipStream_t s);
   static void schur_couple(const PlanDev& P, const Geo& g, const double* rho, int setR, int k,
                            T* G, T* W, int64_t wstride, hipStream_t s);
+  // reg_max: largest matrix of the register-resident sweep; lookahead: slab
+  // look-ahead mode (0 by the update's size, 1 none, 2 always beside);
+  // utile: tile rows of the slab trailing update (64 or 128)
   static void sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int maxn, int maxp, T* pool,
                     T* scratch, int64_t scr_stride, int* status, int status_code, hipStream_t s,
-                    Profiler* prof, const SweepAux* aux = nullptr);
+                    Profiler* prof, const SweepAux* aux = nullptr, int reg_max = kRegSweepMaxRows,
+                    int lookahead = 0, int utile = 64);
   static void gemm(const GemmDesc* d_desc, const GemmDesc* h_desc, int nprob, int maxm, int maxn,
                    const T* A, int transA, const T* B, int transB, T* C, T alpha, T beta, hipStream_t s,
                    Profiler* prof);
@@ -137,6 +146,13 @@ struct Kern {
                  const double* uc, T* v2_out, int nrhs, hipStream_t s);
   // lu = Lambda u_c per subdomain (the local coarse values of u_c)
   static void lam_uc(const PlanDev& P, const T* Lam, const double* uc, T* lu, int nrhs, hipStream_t s);
+  // pinned subdomains (SubDev::pin): the constant of the local kernel
+  static void float_setup(const PlanDev& P, const T* Sc, T* Lam, double* eps, double* fdelta, hipStream_t s);
+  static void float_phi(const PlanDev& P, const double* eps, T* PhiG, hipStream_t s);
+  static void float_mu(const PlanDev& P, const T* gv, T* mu_io, const double* eps, const double* fdelta,
+                       double* fc, int nrhs, hipStream_t s);
+  static void float_v2(const PlanDev& P, const double* uc, const double* eps, const double* fc, T* v2, int nrhs,
+                       hipStream_t s);
   // Y' at the Gamma entries, from [X | Y']
   static void yg_gather(const PlanDev& P, const T* Z, T* YG, int max_nv, hipStream_t s);
   static void interior_rhs(const PlanDev& P, const Geo& g, const double* rho, const double* r,
@@ -189,9 +205,12 @@ void launch_box_filter(const Geo& g, const double* in, double* out, int mode, hi
 }  // namespace bddcso
 
 namespace bddcso {
-void launch_pcg_book1(int nrhs, int k, const double* rz, const double* pq, const double* rr, const double* tol2,
-                      int32_t* active, int32_t* iters, int32_t* flags, double* hist_alpha, int32_t* nactive,
-                      hipStream_t s);
-void launch_pcg_book2(int nrhs, int k, double* rz, const double* num, const double* rz_new,
+// PCG bookkeeping; kd: the iteration index in device memory (advanced by
+// book2), or nullptr to use k.
+void launch_pcg_book1(int nrhs, int k, const int32_t* kd, const double* rz, const double* pq, const double* rr,
+                      const double* tol2, int32_t* active, int32_t* iters, int32_t* flags, double* hist_alpha,
+                      int32_t* nactive, hipStream_t s);
+void launch_pcg_book2(int nrhs, int k, int32_t* kd, double* rz, const double* num, const double* rz_new,
                       const int32_t* active, double* hist_beta, hipStream_t s);
+void launch_copy_f64(const double* a, double* b, int64_t n, hipStream_t s);
 }  // namespace bddcso

@@ -207,6 +207,72 @@ __global__ __launch_bounds__(256) void k_q1_apply(Geo g, const double* __restric
   y[rhs * g.n_free + f] = acc;
 }
 
+// 3D operator by tiles of QX x QY x QZ nodes: the tile's x values with a
+// one-node halo and its elements' rho are staged in LDS once (coalesced rows
+// along x), then each thread sums the 8 elements around each of its QZ nodes
+// from LDS.  Tiles are dealt so that consecutive tiles (which share halo
+// planes) run on one XCD and its L2.  Nodes outside the free range read 0.
+constexpr int QX = 32, QY = 8, QZ = 4;
+
+__global__ __launch_bounds__(256) void k_q1_apply3(Geo g, const double* __restrict__ khat,
+                                                   const double* __restrict__ rho,
+                                                   const double* __restrict__ x, double* __restrict__ y,
+                                                   int tx_n, int ty_n, int ntile) {
+  __shared__ double kh[64];
+  __shared__ double xs[QZ + 2][QY + 2][QX + 2];
+  __shared__ double rs[QZ + 1][QY + 1][QX + 1];
+  // gridDim.x is a multiple of 8: XCD k (blocks k, k + 8, ...) takes the
+  // logical tiles k * per .. (k + 1) * per - 1
+  const int per = gridDim.x / 8;
+  const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (logical >= ntile) return;
+  const int tid = threadIdx.x;
+  if (tid < 64) kh[tid] = khat[tid];
+  const int tx = logical % tx_n, ty = (logical / tx_n) % ty_n, tz = logical / (tx_n * ty_n);
+  const int X0 = 1 + tx * QX, Y0 = 1 + ty * QY, Z0 = 1 + tz * QZ;  // first node (free coordinates)
+  const int nfx = g.nf[0], nfy = g.nf[1], nfz = g.nf[2];
+  const double* xr = x + (int64_t)blockIdx.y * g.n_free;
+  // x at nodes X0-1 .. X0+QX (0 outside 1..nf)
+  for (int i = tid; i < (QZ + 2) * (QY + 2) * (QX + 2); i += 256) {
+    const int ix = i % (QX + 2), iy = (i / (QX + 2)) % (QY + 2), iz = i / ((QX + 2) * (QY + 2));
+    const int gx = X0 - 1 + ix, gy = Y0 - 1 + iy, gz = Z0 - 1 + iz;
+    double v = 0.0;
+    if (gx >= 1 && gx <= nfx && gy >= 1 && gy <= nfy && gz >= 1 && gz <= nfz)
+      v = xr[(gx - 1) + nfx * ((gy - 1) + nfy * (gz - 1))];
+    xs[iz][iy][ix] = v;
+  }
+  // rho at elements X0-1 .. X0+QX-1 (0 outside the mesh)
+  for (int i = tid; i < (QZ + 1) * (QY + 1) * (QX + 1); i += 256) {
+    const int ix = i % (QX + 1), iy = (i / (QX + 1)) % (QY + 1), iz = i / ((QX + 1) * (QY + 1));
+    const int ex = X0 - 1 + ix, ey = Y0 - 1 + iy, ez = Z0 - 1 + iz;
+    double v = 0.0;
+    if (ex < g.ne[0] && ey < g.ne[1] && ez < g.ne[2]) v = rho[ex + g.ne[0] * (ey + g.ne[1] * ez)];
+    rs[iz][iy][ix] = v;
+  }
+  __syncthreads();
+  const int lx = tid % QX, ly = tid / QX;
+  const int gx = X0 + lx, gy = Y0 + ly;
+  if (gx > nfx || gy > nfy) return;
+  double* yr = y + (int64_t)blockIdx.y * g.n_free;
+#pragma unroll
+  for (int lz = 0; lz < QZ; ++lz) {
+    const int gz = Z0 + lz;
+    if (gz > nfz) break;
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+      const int a = (1 - cx) + 2 * (1 - cy) + 4 * (1 - cz);  // this node's corner of the element
+      double sum = 0.0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        sum += kh[a * 8 + b] * xs[lz + cz + (b >> 2)][ly + cy + ((b >> 1) & 1)][lx + cx + (b & 1)];
+      acc += rs[lz + cz][ly + cy][lx + cx] * sum;
+    }
+    yr[(gx - 1) + nfx * ((gy - 1) + nfy * (gz - 1))] = acc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // weights (eq. W / Remark 4)
 
@@ -969,7 +1035,7 @@ __global__ void k_symmetrize(const SweepDesc* __restrict__ desc, T* pool, int nt
 //      panel's own entries become CD (rows or columns in the panel) or
 //      -D^{-1} (the pivot block).
 // Only the lower triangle is read; both triangles are written.
-constexpr int RS_MAX_TILES = 17;  // largest matrix: 272 rows
+constexpr int RS_MAX_TILES = kRegSweepMaxRows / 16;  // largest matrix: 304 rows
 constexpr int SLAB = kSlab;       // pivots per slab of the large-matrix sweep
 // Flops of a slab's trailing update below which its pivot-block sweep of the
 // next slab stays on the main stream (about 250 us of update at the 35-37
@@ -1339,6 +1405,111 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (i < n && j <= i && !(i >= j0 && i < j0 + sb) && !(j >= j0 && j < j0 + sb))
           A[i + (int64_t)ld * j] = old[a][b][r] - acc[a][b][r];
       }
+}
+
+// 3'. The same trailing update by 128 x 128 tiles: each of the four waves
+// owns a 64 x 64 quarter (4 x 4 MFMA tiles), so every operand element staged
+// in LDS feeds four MFMAs per wave and a tile moves half the operand bytes
+// per flop of the 64 x 64 form (about 10 flop/B from L2 instead of 6).
+constexpr int UT = 128, UK = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_slab_update128(
+    const SweepDesc* __restrict__ desc, T* pool, int j0, const T* __restrict__ scratch, int64_t scr_stride,
+    int ntri, int nprob, int region) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T As[UK][UT + PAD];  // CD rows i
+  __shared__ T Bs[UK][UT + PAD];  // slab columns of rows j
+  const int64_t nblk = gridDim.x;
+  const int64_t glin = blockIdx.x;
+  const int64_t logical = (glin % 8) * (nblk / 8) + glin / 8;  // XCD-aware
+  if (logical >= (int64_t)nprob * ntri) return;
+  const int prob = (int)(logical / ntri);
+  const SweepDesc d = desc[prob];
+  const int n = d.n, ld = d.ld;
+  const int sb = min(SLAB, d.p - j0);
+  if (sb <= 0) return;
+  const int lin = (int)(logical % ntri);
+  int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= lin) ++ti;
+  while (ti * (ti + 1) / 2 > lin) --ti;
+  const int tj = lin - ti * (ti + 1) / 2;
+  const int i0 = ti * UT, c0 = tj * UT;
+  if (i0 >= n || c0 >= n) return;
+  if ((i0 >= j0 && i0 + UT <= j0 + sb) || (c0 >= j0 && c0 + UT <= j0 + sb)) return;
+  if (region) {
+    const int j1 = j0 + sb, sbn = min(SLAB, d.p - j1);  // next slab's pivots
+    const bool nextd = sbn > 0 && i0 + UT > j1 && i0 < j1 + sbn && c0 + UT > j1 && c0 < j1 + sbn;
+    if ((region == 1) != nextd) return;
+  }
+  T* A = pool + d.off;
+  const T* CD = scratch + (int64_t)prob * scr_stride;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int kq = lane >> 4, rr = lane & 15;
+  const int wi = (wave & 1) * 64, wj = (wave >> 1) * 64;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  T av[8], bv[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = tid + u * 256;
+      const int r = idx % UT, q = idx / UT;
+      const int i = i0 + r, j = c0 + r, kk = k0 + q;
+      av[u] = (i < n && kk < sb && !(i >= j0 && i < j0 + sb)) ? ld32(CD, (uint32_t)(i + n * kk)) : (T)0;
+      bv[u] = (j < n && kk < sb && !(j >= j0 && j < j0 + sb)) ? slab_c32(A, ld, j0, j, kk) : (T)0;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < sb; k0 += UK) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = tid + u * 256;
+      As[idx / UT][idx % UT] = av[u];
+      Bs[idx / UT][idx % UT] = bv[u];
+    }
+    __syncthreads();
+    if (k0 + UK < sb) load(k0 + UK);
+#pragma unroll
+    for (int ks = 0; ks < UK / 4; ++ks) {
+      const int kk = ks * 4 + kq;
+      T x[4], y[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) x[a] = As[kk][wi + a * 16 + rr];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) y[b] = Bs[kk][wj + b * 16 + rr];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::mac(y[b], x[a], acc[a][b]);
+    }
+  }
+  // per tile row: read the old values of its four MFMA tiles, then write
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    T old[4][4];
+    const int i = i0 + wi + a * 16 + rr;
+    const bool irow = i < n && !(i >= j0 && i < j0 + sb);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = c0 + wj + b * 16 + Mfma<T>::row(kq, r);
+        const bool on = irow && j <= i && !(j >= j0 && j < j0 + sb);
+        old[b][r] = on ? A[i + (int64_t)ld * j] : (T)0;
+      }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = c0 + wj + b * 16 + Mfma<T>::row(kq, r);
+        if (irow && j <= i && !(j >= j0 && j < j0 + sb)) A[i + (int64_t)ld * j] = old[b][r] - acc[a][b][r];
+      }
+  }
 }
 
 // 4. The slab's rows and columns outside S become CD (lower triangle).
@@ -2693,6 +2864,116 @@ __global__ __launch_bounds__(256) void k_lam_uc(PlanDev P, const T* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pinned subdomains (floating, no primal point constraints; SubDev::pin).
+// Their r-set leaves out one interior node, so K_rr is definite, and the
+// local functions are w + c 1 with w = 0 at the pin: the constant c is one
+// more unknown.  With d = C 1 (all ones: each average of the constant is 1),
+// S = C_r K_rr^{-1} C_r^T, e = S^{-1} d and delta = d^T e, the constrained
+// Neumann problem [K C^T; C 0] [v; mu] = [g; 0] has
+//   mu = S^{-1} q + c e,  q = C_r K_rr^{-1} g_r,  c = (1^T g - d^T S^{-1} q) / delta,
+//   v = K_rr^{-1} (g_r - C_r^T mu) + c 1,
+// and the coarse basis (C Phi = I, minimal energy) has
+//   Lambda = e e^T / delta - S^{-1},  Phi_r = -X Lambda + 1 e^T / delta,
+// so K_c = Phi^T K Phi = -Lambda as with eliminated vertices.
+
+// Setup, after Lambda = -S^{-1}: eps = e / delta, delta, Lambda += e e^T / delta.
+template <typename T>
+__global__ __launch_bounds__(256) void k_float_setup(PlanDev P, const T* __restrict__ Sc, T* __restrict__ Lam,
+                                                     double* __restrict__ eps, double* __restrict__ fdelta) {
+  extern __shared__ char smem_raw[];
+  double* e = reinterpret_cast<double*>(smem_raw);
+  __shared__ double red[256];
+  const int sub = blockIdx.x;
+  const SubDev S = P.subs[sub];
+  if (S.pin < 0 || S.n_a == 0) return;
+  const int na = S.n_a;
+  // Sc holds -S^{-1} (both triangles) after its sweep
+  double part = 0.0;
+  for (int a = threadIdx.x; a < na; a += blockDim.x) {
+    double acc = 0.0;
+    for (int b = 0; b < na; ++b) acc -= (double)Sc[S.Sc_off + a + (int64_t)na * b];
+    e[a] = acc;
+    part += acc;
+  }
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double delta = red[0];
+  for (int a = threadIdx.x; a < na; a += blockDim.x) eps[S.am_off + a] = e[a] / delta;
+  if (threadIdx.x == 0) fdelta[sub] = delta;
+  T* L = Lam + S.T_off;
+  for (int idx = threadIdx.x; idx < na * na; idx += blockDim.x) {
+    const int a = idx % na, c = idx / na;
+    L[idx] = (T)((double)L[idx] + e[a] * e[c] / delta);
+  }
+}
+
+// Setup, after Phi = -X Lambda at the selected rows: add 1 e^T / delta.
+template <typename T>
+__global__ void k_float_phi(PlanDev P, const double* __restrict__ eps, T* __restrict__ PhiG) {
+  const int sub = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  if (S.pin < 0) return;
+  const int tot = S.n_s * S.n_c;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
+    const int c = idx / S.n_s;
+    PhiG[S.PhiG_off + idx] = (T)((double)PhiG[S.PhiG_off + idx] + eps[S.am_off + c]);
+  }
+}
+
+// Apply, after mu = S^{-1} q: c = (1^T g - sum mu) / delta, mu += c e.
+template <typename T>
+__global__ __launch_bounds__(256) void k_float_mu(PlanDev P, const T* __restrict__ gv, T* __restrict__ mu,
+                                                  const double* __restrict__ eps,
+                                                  const double* __restrict__ fdelta, double* __restrict__ fc) {
+  __shared__ double red[256];
+  const int sub = blockIdx.x, rhs = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  if (S.pin < 0) return;
+  double part = 0.0;
+  for (int e = threadIdx.x; e < S.n_g; e += blockDim.x) part += (double)gv[rhs * P.tot_g + S.g_off + e];
+  T* m = mu + rhs * P.tot_a + S.am_off;
+  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x) part -= (double)m[a];
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double delta = fdelta[sub], c = red[0] / delta;
+  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x)
+    m[a] = (T)((double)m[a] + c * delta * eps[S.am_off + a]);
+  if (threadIdx.x == 0) fc[rhs * P.n_sub + sub] = c;
+}
+
+// Apply, after v2 on Gamma: add c + e^T u_c / delta (the constant of the
+// Neumann solution and of Phi u_c).
+template <typename T>
+__global__ __launch_bounds__(256) void k_float_v2(PlanDev P, const double* __restrict__ uc,
+                                                  const double* __restrict__ eps, const double* __restrict__ fc,
+                                                  T* __restrict__ v2) {
+  __shared__ double red[256];
+  const int sub = blockIdx.x, rhs = blockIdx.y;
+  const SubDev S = P.subs[sub];
+  if (S.pin < 0) return;
+  double part = 0.0;
+  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x)
+    part += eps[S.am_off + a] * uc[rhs * P.n_coarse + P.c_glob[S.c_off + a]];
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double add = fc[rhs * P.n_sub + sub] + red[0];
+  T* v = v2 + rhs * P.tot_g + S.g_off;
+  for (int e = threadIdx.x; e < S.n_g; e += blockDim.x) v[e] = (T)((double)v[e] + add);
+}
+
 // Y' at the Gamma entries: the vertex columns of [X | Y'] gathered by the
 // Gamma entries' r-rows; a Gamma entry that is a primal vertex has no r-row
 // and takes the unit value of its own coarse dof.
@@ -3279,7 +3560,7 @@ int64_t max_lds_bytes(const PlanDev& P, int elt, int max_nrhs) {
   need = hmax(need, mp * (SC_COLS + 1) * elt + 2048);                                  // schur couple
   need = hmax(need, mp * (CPL_COLS + 1) * elt);                                        // couple multi
   need = hmax(need, (int64_t)hmax(P.max_block, 1) * ((BS_WAVES_MAX + 9) * 8 + 2 * elt));  // block solve
-  if (max_nrhs >= 4) need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);  // many-rhs block solve
+  if (max_nrhs >= P.mr_min) need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);  // many-rhs block solve
   need = hmax(need, (int64_t)(P.max_na + P.max_nc + 1) * elt);                         // v2
   need = hmax(need, (int64_t)hmax(P.max_ng, 1) * elt);                                 // coarse rhs
   need = hmax(need, kc_lds_bytes(P));                                                  // local coarse matrices
@@ -3298,6 +3579,13 @@ void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStr
 
 void launch_q1_apply(const Geo& g, const double* khat, const double* rho, const double* x,
                      double* y, int nrhs, hipStream_t s) {
+  if (g.dim == 3) {
+    const int txn = (int)cdiv(g.nf[0], QX), tyn = (int)cdiv(g.nf[1], QY), tzn = (int)cdiv(g.nf[2], QZ);
+    const int ntile = txn * tyn * tzn;
+    const unsigned nblk = (unsigned)((ntile + 7) / 8 * 8);
+    k_q1_apply3<<<dim3(nblk, nrhs), 256, 0, s>>>(g, khat, rho, x, y, txn, tyn, ntile);
+    return;
+  }
   k_q1_apply<<<dim3(cdiv(g.n_free, 256), nrhs), 256, 0, s>>>(g, khat, rho, x, y);
 }
 
@@ -3340,9 +3628,9 @@ void Kern<T>::schur_couple(const PlanDev& P, const Geo& g, const double* rho, in
 template <typename T>
 void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int maxn, int maxp, T* pool,
                     T* scratch, int64_t scr_stride, int* status, int status_code, hipStream_t s,
-                    Profiler* prof, const SweepAux* aux) {
+                    Profiler* prof, const SweepAux* aux, int reg_max, int lookahead, int utile) {
   if (nprob == 0 || maxp == 0) return;
-  if (maxn <= 16 * RS_MAX_TILES) {
+  if (maxn <= hmin(reg_max, 16 * RS_MAX_TILES)) {
     // register-resident: one workgroup per matrix, read once, written once
     double f = 0, by = 0;
     if (prof && h_desc)
@@ -3359,6 +3647,7 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
     else if (mt <= 8) k_sweep_reg<T, 8, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
     else if (mt <= 11) k_sweep_reg<T, 11, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
     else if (mt <= 12) k_sweep_reg<T, 12, 12><<<nprob, 12 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
+    else if (mt <= 17) k_sweep_reg<T, 17, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
     else k_sweep_reg<T, RS_MAX_TILES, 8><<<nprob, 8 * 64, 0, s>>>(d_desc, pool, status, status_code, -1);
     if (prof) prof->end(5, f, by, s);
     return;
@@ -3413,14 +3702,22 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
       k_slab_cd<T><<<dim3(cdiv(maxn, TILE), cdiv(SLAB, TILE), nprob), 256, 0, s>>>(d_desc, pool, j0, scratch,
                                                                                   scr_stride);
       if (prof) prof->end(4, cf, cb, s);
-      const unsigned ublk = (unsigned)((ntri * nprob + 7) / 8 * 8);
+      // trailing update by 64- or 128-row tiles of the lower triangle
+      const int64_t utiles = cdiv(maxn, utile == 128 ? UT : TILE), untri = utiles * (utiles + 1) / 2;
+      const unsigned ublk = (unsigned)((untri * nprob + 7) / 8 * 8);
+      auto upd = [&](int region, hipStream_t ss) {
+        if (utile == 128)
+          k_slab_update128<T><<<ublk, 256, 0, ss>>>(d_desc, pool, j0, scratch, scr_stride, (int)untri, nprob, region);
+        else
+          k_slab_update<T><<<ublk, 256, 0, ss>>>(d_desc, pool, j0, scratch, scr_stride, (int)untri, nprob, region);
+      };
       const unsigned wgrid = (unsigned)hmin(cdiv((int64_t)maxn * SLAB, 256), 2048);
       const bool next = j0 + SLAB < maxp;
       prev_inl = false;
-      if (next && aux) {
-        const bool inl = h_desc && uf < kSlabInlineFlops;
+      if (next && aux && lookahead != 1) {
+        const bool inl = lookahead == 2 || (h_desc && uf < kSlabInlineFlops);
         if (prof) prof->begin(1, s);
-        k_slab_update<T><<<ublk, 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, (int)ntri, nprob, 1);
+        upd(1, s);
         if (prof) prof->end(1, 0.0, 0.0, s);
         (void)hipEventRecord(aux->a, s);
         (void)hipStreamWaitEvent(aux->s2, aux->a, 0);
@@ -3431,14 +3728,14 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
           (void)hipEventRecord(aux->b, aux->s2);
         }
         if (prof) prof->begin(1, su);
-        k_slab_update<T><<<ublk, 256, 0, su>>>(d_desc, pool, j0, scratch, scr_stride, (int)ntri, nprob, 2);
+        upd(2, su);
         if (prof) prof->end(1, uf, ub, su);
         k_slab_writeback<T><<<dim3(wgrid, nprob), 256, 0, su>>>(d_desc, pool, j0, scratch, scr_stride);
         if (inl) (void)hipEventRecord(aux->c, aux->s2);
         prev_inl = inl;
       } else {
         if (prof) prof->begin(1, s);
-        k_slab_update<T><<<ublk, 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, (int)ntri, nprob, 0);
+        upd(0, s);
         if (prof) prof->end(1, uf, ub, s);
         k_slab_writeback<T><<<dim3(wgrid, nprob), 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride);
         if (next) reg(j0 + SLAB, s);
@@ -3586,7 +3883,7 @@ void Kern<T>::block_solve(const PlanDev& P, const Geo& g, const double* rho, int
                           T* v, int nrhs, hipStream_t s, Profiler* prof, double g_entries, double vec_entries,
                           int set_max_block) {
   if (prof) prof->begin(2, s);
-  if (nrhs >= 4) {
+  if (nrhs >= P.mr_min) {
     const size_t smr = (size_t)hmax(P.max_block, 1) * (MR_COLS + 1) * sizeof(T);
     k_block_solve_mr<T><<<dim3(P.n_sub, cdiv(nrhs, MR_COLS)), MR_THREADS, smr, s>>>(P, setR, G, v, nrhs);
   } else {
@@ -3635,7 +3932,7 @@ void Kern<T>::mu(const PlanDev& P, const T* vR, const T* Sc, T* mu_out, int nrhs
 template <typename T>
 void Kern<T>::coarse_rhs_local(const PlanDev& P, const T* PhiG, const T* gv, T* bci, int nrhs, hipStream_t s) {
   if (P.max_nc == 0) return;
-  if (nrhs >= 4) {
+  if (nrhs >= P.mr_min) {
     k_coarse_rhs_local_mr<T><<<dim3(cdiv(P.max_nc, 64), P.n_sub, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, PhiG, gv, bci,
                                                                                                   nrhs);
     return;
@@ -3648,13 +3945,36 @@ template <typename T>
 void Kern<T>::v2(const PlanDev& P, const T* vR, const T* XG, const T* mu_in, const T* lu, const T* YG,
                  const double* uc, T* v2_out, int nrhs, hipStream_t s) {
   if (P.max_ng == 0) return;
-  if (nrhs >= 4) {
+  if (nrhs >= P.mr_min) {
     k_v2_mr<T><<<dim3(cdiv(P.max_ng, 64), P.n_sub, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, vR, XG, mu_in, lu, YG,
                                                                                      uc, v2_out, nrhs);
     return;
   }
   size_t sm = (size_t)(P.max_na + P.max_nv + 1) * sizeof(T);
   k_v2<T><<<dim3(cdiv(P.max_ng, 256), P.n_sub, nrhs), 256, sm, s>>>(P, vR, XG, mu_in, lu, YG, uc, v2_out);
+}
+
+template <typename T>
+void Kern<T>::float_setup(const PlanDev& P, const T* Sc, T* Lam, double* eps, double* fdelta, hipStream_t s) {
+  if (P.n_pinned == 0) return;
+  k_float_setup<T><<<P.n_sub, 256, (size_t)hmax(P.max_na, 1) * sizeof(double), s>>>(P, Sc, Lam, eps, fdelta);
+}
+template <typename T>
+void Kern<T>::float_phi(const PlanDev& P, const double* eps, T* PhiG, hipStream_t s) {
+  if (P.n_pinned == 0 || P.max_nc == 0) return;
+  k_float_phi<T><<<dim3(cdiv((int64_t)P.max_ns * P.max_nc, 256), P.n_sub), 256, 0, s>>>(P, eps, PhiG);
+}
+template <typename T>
+void Kern<T>::float_mu(const PlanDev& P, const T* gv, T* mu_io, const double* eps, const double* fdelta,
+                       double* fc, int nrhs, hipStream_t s) {
+  if (P.n_pinned == 0) return;
+  k_float_mu<T><<<dim3(P.n_sub, nrhs), 256, 0, s>>>(P, gv, mu_io, eps, fdelta, fc);
+}
+template <typename T>
+void Kern<T>::float_v2(const PlanDev& P, const double* uc, const double* eps, const double* fc, T* v2,
+                       int nrhs, hipStream_t s) {
+  if (P.n_pinned == 0) return;
+  k_float_v2<T><<<dim3(P.n_sub, nrhs), 256, 0, s>>>(P, uc, eps, fc, v2);
 }
 
 template <typename T>
@@ -3727,7 +4047,7 @@ void launch_front_vec_scatter(const PlanDev& P, const int32_t* children, int nch
 void launch_front_fwd(const PlanDev& P, const int32_t* fr, int nfr, int maxn, int maxp, const double* fpool,
                       double* fvec, double* xh, int64_t stride, int nrhs, hipStream_t s, double* part) {
   if (nfr == 0 || maxp == 0) return;
-  if (nrhs >= 4) {
+  if (nrhs >= P.mr_min) {
     k_front_fwd_mr<<<dim3(cdiv(maxn, 64), nfr, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, fr, fpool, fvec, xh, stride,
                                                                                   nrhs);
     return;
@@ -3744,7 +4064,7 @@ void launch_front_bwd(const PlanDev& P, const int32_t* fr, int nfr, int maxp, in
                       const double* xh, int64_t stride, double* uc, int nrhs, hipStream_t s) {
   (void)maxb;
   if (nfr == 0 || maxp == 0) return;
-  if (nrhs >= 4) {
+  if (nrhs >= P.mr_min) {
     k_front_bwd_mr<<<dim3(cdiv(maxp, 64), nfr, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, fr, fpool, xh, stride, uc, nrhs);
     return;
   }
@@ -3787,20 +4107,22 @@ namespace {
 // PCG bookkeeping on the device, one thread per right-hand side.
 // After r is updated and rr = r.r: count the iteration, record alpha, test
 // convergence (rr <= tol2), flag breakdown (p.q <= 0 or r.z <= 0).
-__global__ void k_pcg_book1(int nrhs, int k, const double* __restrict__ rz, const double* __restrict__ pq,
-                            const double* __restrict__ rr, const double* __restrict__ tol2,
-                            int32_t* __restrict__ active, int32_t* __restrict__ iters,
-                            int32_t* __restrict__ flags, double* __restrict__ hist_alpha,
-                            int32_t* __restrict__ nactive) {
+__global__ void k_pcg_book1(int nrhs, int k, const int32_t* __restrict__ kd, const double* __restrict__ rz,
+                            const double* __restrict__ pq, const double* __restrict__ rr,
+                            const double* __restrict__ tol2, int32_t* __restrict__ active,
+                            int32_t* __restrict__ iters, int32_t* __restrict__ flags,
+                            double* __restrict__ hist_alpha, int32_t* __restrict__ nactive) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
+  // the iteration index: an argument, or (replayed launches) a device counter
+  const int kk = kd ? *kd : k;
   const int j = threadIdx.x;
   if (j < nrhs) {
     if (active[j]) {
-      iters[j] = k + 1;
+      iters[j] = kk + 1;
       const double a = rz[j] / pq[j];
-      hist_alpha[k * nrhs + j] = a;
+      hist_alpha[kk * nrhs + j] = a;
       if (!(pq[j] > 0.0) || !(rz[j] > 0.0) || !isfinite(a)) {
         flags[j] |= 2;  // breakdown
         active[j] = 0;
@@ -3815,24 +4137,40 @@ __global__ void k_pcg_book1(int nrhs, int k, const double* __restrict__ rz, cons
   if (threadIdx.x == 0) *nactive = cnt;
 }
 
-// After p = z + beta p: record beta = num/rz and move rz <- rz_new.
-__global__ void k_pcg_book2(int nrhs, int k, double* __restrict__ rz, const double* __restrict__ num,
-                            const double* __restrict__ rz_new, const int32_t* __restrict__ active,
-                            double* __restrict__ hist_beta) {
+// After p = z + beta p: record beta = num/rz and move rz <- rz_new; with a
+// device counter, advance it to the next iteration.
+__global__ void k_pcg_book2(int nrhs, int k, int32_t* __restrict__ kd, double* __restrict__ rz,
+                            const double* __restrict__ num, const double* __restrict__ rz_new,
+                            const int32_t* __restrict__ active, double* __restrict__ hist_beta) {
   const int j = threadIdx.x;
-  if (j >= nrhs || !active[j]) return;
-  hist_beta[k * nrhs + j] = num[j] / rz[j];
-  rz[j] = rz_new[j];
+  const int kk = kd ? *kd : k;
+  if (j < nrhs && active[j]) {
+    hist_beta[kk * nrhs + j] = num[j] / rz[j];
+    rz[j] = rz_new[j];
+  }
+  if (kd) {
+    __syncthreads();
+    if (threadIdx.x == 0) *kd = kk + 1;
+  }
+}
+
+__global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
 }
 }  // namespace
 
-void launch_pcg_book1(int nrhs, int k, const double* rz, const double* pq, const double* rr, const double* tol2,
-                      int32_t* active, int32_t* iters, int32_t* flags, double* hist_alpha, int32_t* nactive,
-                      hipStream_t s) {
-  k_pcg_book1<<<1, 64, 0, s>>>(nrhs, k, rz, pq, rr, tol2, active, iters, flags, hist_alpha, nactive);
+void launch_pcg_book1(int nrhs, int k, const int32_t* kd, const double* rz, const double* pq, const double* rr,
+                      const double* tol2, int32_t* active, int32_t* iters, int32_t* flags, double* hist_alpha,
+                      int32_t* nactive, hipStream_t s) {
+  k_pcg_book1<<<1, 64, 0, s>>>(nrhs, k, kd, rz, pq, rr, tol2, active, iters, flags, hist_alpha, nactive);
 }
-void launch_pcg_book2(int nrhs, int k, double* rz, const double* num, const double* rz_new,
+void launch_pcg_book2(int nrhs, int k, int32_t* kd, double* rz, const double* num, const double* rz_new,
                       const int32_t* active, double* hist_beta, hipStream_t s) {
-  k_pcg_book2<<<1, 64, 0, s>>>(nrhs, k, rz, num, rz_new, active, hist_beta);
+  k_pcg_book2<<<1, 64, 0, s>>>(nrhs, k, kd, rz, num, rz_new, active, hist_beta);
+}
+void launch_copy_f64(const double* a, double* b, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_copy_f64<<<hmin(cdiv(n, 256), 65536), 256, 0, s>>>(a, b, n);
 }
 }  // namespace bddcso

@@ -4,6 +4,8 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <climits>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -122,6 +124,24 @@ bool classify(int dim, const int64_t n_el[3], const double h[3], const int32_t* 
   {
     std::vector<int32_t> pos(c.ss_eptr.begin(), c.ss_eptr.end() - 1);
     for (int64_t e = 0; e < c.n_elem; ++e) c.ss_elem[pos[c.elem_subsub[e]]++] = (int32_t)e;
+  }
+
+  // grid index of each subsubdomain along each axis
+  c.ss_idx.assign(c.n_ss, {0, 0, 0});
+  for (int a = 0; a < dim; ++a) {
+    std::vector<int> lo(c.n_ss, INT32_MAX);
+    for (int j = 0; j < c.n_ss; ++j)
+      for (int t = c.ss_eptr[j]; t < c.ss_eptr[j + 1]; ++t) {
+        const int64_t e = c.ss_elem[t];
+        const int ec = a == 0 ? (int)(e % c.ne[0]) : a == 1 ? (int)((e / c.ne[0]) % c.ne[1])
+                                                           : (int)(e / (c.ne[0] * c.ne[1]));
+        lo[j] = std::min(lo[j], ec);
+      }
+    std::vector<int> d(lo);
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    for (int j = 0; j < c.n_ss; ++j)
+      c.ss_idx[j][a] = (int)(std::lower_bound(d.begin(), d.end(), lo[j]) - d.begin());
   }
 
   // Gamma nodes and their keys
@@ -337,6 +357,23 @@ struct NDBuilder {
 
 }  // namespace
 
+bool half_keep(const Classification& c, int obj) {
+  const int32_t q = c.obj_gam[c.obj_ptr[obj]];
+  if (c.gam_kptr[q + 1] - c.gam_kptr[q] != 2) return true;
+  const auto& i1 = c.ss_idx[c.gam_key[c.gam_kptr[q]]];
+  const auto& i2 = c.ss_idx[c.gam_key[c.gam_kptr[q] + 1]];
+  int normal = 0, best = -1, sum = 0;
+  for (int a = 0; a < c.dim; ++a) {
+    const int d = std::abs(i1[a] - i2[a]);
+    if (d > best) {
+      best = d;
+      normal = a;
+    }
+    sum += i1[a];
+  }
+  return (sum - i1[normal]) % 2 == 0;
+}
+
 bool build_plan(const Classification& c, int primal_mask, int block_target, int coarse_solver,
                 Plan& plan, Error& err) {
   plan = Plan();
@@ -348,7 +385,7 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
   // coarse numbering: selected objects in object order (smallest free index)
   plan.obj_coarse.assign(c.n_obj(), -1);
   for (int o = 0; o < c.n_obj(); ++o)
-    if (c.obj_type[o] & primal_mask) {
+    if ((c.obj_type[o] & primal_mask) && (!(primal_mask & kHalfCodim1) || half_keep(c, o))) {
       plan.obj_coarse[o] = (int32_t)plan.coarse_obj.size();
       plan.coarse_obj.push_back(o);
     }
@@ -384,6 +421,36 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     S.a_off = a_off;
     S.am_off = a_off - s;
     S.c_off = c_off;
+    // A subdomain away from the Dirichlet boundary has the constants in the
+    // kernel of its local matrix.  Primal point constraints (eliminated)
+    // remove them; without any, one interior node is left out of the r-set
+    // (the pin) and the constant is carried as one extra unknown of the
+    // constrained Neumann problem.
+    bool floating = true;
+    for (int a = 0; a < dim; ++a)
+      if (b[a] == 0 || b[3 + a] == (int)c.ne[a]) floating = false;
+    int pin_l = -1;
+    if (floating) {
+      int npt = 0, first_interior = -1;
+      for (int l = 0; l < S.n_loc; ++l) {
+        int x = l % S.m[0], y = (l / S.m[0]) % S.m[1], z = l / (S.m[0] * S.m[1]);
+        int gcoord[3] = {S.lo[0] + x, S.lo[1] + y, S.lo[2] + z};
+        int32_t q = c.node_gam[c.free_index(gcoord)];
+        if (q < 0) {
+          if (first_interior < 0) first_interior = l;
+          continue;
+        }
+        int32_t o = c.gam_obj[q];
+        if (plan.obj_coarse[o] >= 0 && c.obj_ptr[o + 1] - c.obj_ptr[o] == 1) ++npt;
+      }
+      if (npt == 0) {
+        if (first_interior < 0)
+          return fail(err, -1, "floating subdomain " + std::to_string(s) +
+                                   " has neither a primal point constraint nor an interior node");
+        pin_l = first_interior;
+      }
+    }
+    S.pin = pin_l;
     // classify local nodes
     std::vector<int32_t> lI(S.n_loc, -1), lr(S.n_loc, -1), lg(S.n_loc, -1);
     std::vector<int> cntI(S.m[pa], 0), cntR(S.m[pa], 0);
@@ -411,22 +478,12 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
       if (vert) {
         plan.v_loc.push_back(l);
         nv++;
-      } else {
+      } else if (l != pin_l) {
         lr[l] = nr++;
         cntR[plane]++;
       }
     }
-    // The local Neumann matrices are made definite by eliminating the
-    // primal point constraints: a subdomain away from the Dirichlet boundary
-    // (its local matrix holds the constants in its kernel) needs one.
-    bool floating = true;
-    for (int a = 0; a < dim; ++a)
-      if (b[a] == 0 || b[3 + a] == (int)c.ne[a]) floating = false;
-    if (floating && nv == 0)
-      return fail(err, -1, "subdomain " + std::to_string(s) +
-                               " does not touch the Dirichlet boundary and has no primal point constraint "
-                               "(a selected vertex or single-node object): its constrained Neumann problem "
-                               "needs one here (choose a primal_mask with vertices)");
+    if (pin_l >= 0 && nv != 0) return fail(err, -1, "internal: pinned subdomain with primal points");
     std::sort(local_coarse.begin(), local_coarse.end());
     local_coarse.erase(std::unique(local_coarse.begin(), local_coarse.end()), local_coarse.end());
     S.n_I = nI;

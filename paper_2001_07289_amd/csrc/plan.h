@@ -27,6 +27,10 @@ struct Classification {
   std::vector<int32_t> elem_sub, elem_subsub, ss_parent;
   std::vector<std::array<int, 6>> ebox;   // per subdomain: elo[3], ehi[3]
   std::vector<int32_t> ss_eptr, ss_elem;  // elements of each subsubdomain
+  // per subsubdomain and axis: rank of its lowest element coordinate among
+  // the distinct lowest coordinates of all subsubdomains (the fine
+  // partition's grid index for tensor partitions)
+  std::vector<std::array<int, 3>> ss_idx;
   // Gamma nodes (free nodes shared by >= 2 subdomains), ascending free index
   std::vector<int64_t> gam_node;
   std::vector<int32_t> node_gam;          // free index -> Gamma index or -1
@@ -110,6 +114,16 @@ bool classify(int dim, const int64_t n_el[3], const double h[3], const int32_t* 
 
 bool build_plan(const Classification& c, int primal_mask, int block_target, int coarse_solver,
                 Plan& plan, Error& err);
+
+// Primal selection bit 8: keep half of the codimension-one objects (faces in
+// 3D, edges in 2D), by the checkerboard rule of half_keep.
+constexpr int kHalfCodim1 = 8;
+
+// True when the object (key of two subsubdomains j1 < j2) is kept by the
+// half selection: the sum of j1's grid indices over the axes other than the
+// normal (the axis along which j1 and j2 differ most, the first on ties) is
+// even.
+bool half_keep(const Classification& c, int obj);
 
 int object_type(int dim, int key_size);
 

@@ -18,6 +18,9 @@ struct SubDev {
                   // neighbours of the primal vertices that are not on Gamma
   int nbI, nbR;   // diagonal blocks of the I and r factors
   int color;      // subdomains of one colour share no coarse dof
+  int pin;        // floating subdomain without primal point constraints: the
+                  // interior local node left out of the r-set (the constant
+                  // of its kernel is carried separately), else -1
   int front;      // front the local coarse matrix is added to
   int64_t loc_off;   // offset of per-local-node tables
   int64_t I_off;     // offset of I-order tables / vectors

@@ -98,6 +98,23 @@ class Problem:
         B.check(B.load().bddcso_setup_workspace_size(self._h, C.byref(o), C.byref(n)))
         return n.value
 
+    def autotune(self, rho: torch.Tensor, b: torch.Tensor, options: Optional[B.Options] = None, stream=None,
+                 **kw):
+        """bddcso_autotune: the fastest launch-shape variant of the options for
+        one step (numeric setup + solve of b) of this problem.  Returns the
+        tuned options and the trials as a list of (knobs, ms, status)."""
+        _f64_cuda(rho, "rho")
+        _f64_cuda(b, "b")
+        o = options if options is not None else default_options(**kw)
+        nrhs = b.numel() // self.n_free
+        best, rep = B.Options(), B.TuneReport()
+        B.check(B.load().bddcso_autotune(self._h, _ptr(rho), C.byref(o), _ptr(b), nrhs, _stream(stream),
+                                         C.byref(best), C.byref(rep)))
+        knobs = ("update_tile", "slab_lookahead", "sweep_reg_rows", "block_target", "mr_min_rhs", "graph")
+        trials = [({k: getattr(rep.tried[t], k) for k in knobs}, rep.step_ms[t], B.STATUS.get(rep.status[t]))
+                  for t in range(rep.n_trials)]
+        return best, {"trials": trials, "best": rep.best}
+
     def coef_from_log(self, theta: torch.Tensor, stream=None) -> torch.Tensor:
         """rho = exp(F theta), F the 3^dim box mean (bddcso_coef_from_log)."""
         _f64_cuda(theta, "theta")
@@ -114,7 +131,10 @@ class Problem:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            B.load().bddcso_problem_destroy(h)
+            try:
+                B.load().bddcso_problem_destroy(h)
+            except (TypeError, AttributeError):  # interpreter shutdown: the module is gone
+                pass
             self._h = None
 
 
@@ -220,7 +240,8 @@ class Preconditioner:
         return {"n_coarse": nc.value, "n_fronts": nf.value, "device_bytes": nb.value,
                 "coarse_factor_entries": ce.value}
 
-    KERNEL_CLASSES = {"sweep_update": 1, "block_solve": 2, "gemm": 3, "sweep_panel": 4, "sweep_small": 5}
+    KERNEL_CLASSES = {"sweep_update": 1, "block_solve": 2, "gemm": 3, "sweep_panel": 4, "sweep_small": 5,
+                      "schur_couple": 6, "couple_multi": 7, "q1_apply": 8}
 
     def profile(self, classes=None) -> None:
         """Start event timing of the named kernel classes (all when None); [] stops it."""
@@ -235,7 +256,10 @@ class Preconditioner:
         for name, c in self.KERNEL_CLASSES.items():
             n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
             B.check(B.load().bddcso_profile_read(self._h, c, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)))
-            out[name] = {"launches": n.value, "total_ms": ms.value, "flops": fl.value, "bytes": by.value}
+            rf, rb = C.c_double(), C.c_double()
+            B.check(B.load().bddcso_profile_reference(self._h, c, C.byref(rf), C.byref(rb)))
+            out[name] = {"launches": n.value, "total_ms": ms.value, "flops": fl.value, "bytes": by.value,
+                         "ref_flops": rf.value, "ref_bytes": rb.value}
         return out
 
     def local_coarse(self, sub: int, cap: int = 4096, stream=None):
@@ -251,7 +275,10 @@ class Preconditioner:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            B.load().bddcso_precond_destroy(h)
+            try:
+                B.load().bddcso_precond_destroy(h)
+            except (TypeError, AttributeError):  # interpreter shutdown: the module is gone
+                pass
             self._h = None
         self._ws = None  # released only after the library has let go of it
 

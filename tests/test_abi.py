@@ -40,9 +40,10 @@ def test_classification_matches_oracle(make):
     p = make()
     prob = pk.Problem.from_workload(p)
     c = classify.classify(p.n_el, p.elem_sub, p.elem_subsub)
-    for mask in (7, 1, 2, 4, 6):
+    for mask in (7, 1, 2, 4, 6, 13, 15):
         info = prob.info(mask)
-        sel = [o for o in range(len(c.obj_nodes)) if c.obj_type[o] & mask]
+        sel = c.coarse_objects if mask == 7 else classify.classify(p.n_el, p.elem_sub, p.elem_subsub,
+                                                                    primal_mask=mask).coarse_objects
         t = c.obj_type[sel]
         assert info["n_coarse"] == len(sel)
         assert info["counts"] == {"v": int(np.sum(t == 1)), "e": int(np.sum(t == 2)),
@@ -113,19 +114,14 @@ def test_front_above_4gib_is_refused():
     assert st["n_coarse"] == 39823 and st["max_front"] < 23170
 
 
-def test_vertex_free_floating_subdomain_is_refused():
-    """A primal set without point constraints leaves a subdomain that does
-    not touch the Dirichlet boundary with a singular local Neumann matrix in
-    this build (it eliminates primal vertices): the planner refuses it,
-    while a partition whose subdomains all touch the boundary is accepted."""
+def test_vertex_free_floating_subdomain_is_planned():
+    """A primal set without point constraints leaves the subdomains that do
+    not touch the Dirichlet boundary with constants in the kernel of their
+    local matrices: the planner pins one interior node of each (and carries
+    the constant separately) instead of refusing the set."""
     p = W.config2_like(n=18, H=6, L=3, log_range=None)   # 3^3 subdomains: the centre one floats
     prob = pk.Problem.from_workload(p)
-    for mask in (2, 4, 6):
-        with pytest.raises(pk.BDDCSOError) as e:
-            prob.plan_stats(primal_mask=mask)
-        assert e.value.name == "EINVAL" and "Dirichlet" in str(e.value)
-    for mask in (1, 3, 5, 7):
-        assert prob.plan_stats(primal_mask=mask)["n_coarse"] > 0
-    q = pk.Problem.from_workload(W.config2_like(n=12, H=6, L=3, log_range=None))
     for mask in range(1, 8):
-        assert q.plan_stats(primal_mask=mask)["n_coarse"] > 0
+        assert prob.plan_stats(primal_mask=mask)["n_coarse"] > 0
+    c = W.channels_problem(n=24, subs=3, ell=6, per_axis=1)
+    assert pk.Problem.from_workload(c).plan_stats(primal_mask=4)["n_coarse"] == 60

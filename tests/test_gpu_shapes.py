@@ -171,8 +171,10 @@ def _mask_cases():
     for mask in range(1, 7):
         out.append((f"2x2x2_m{mask}", 12, mask))
     # 3^3 subdomains: the floating centre needs a vertex
-    for mask in (1, 3, 5):
+    for mask in (1, 3, 5, 13):
         out.append((f"3x3x3_m{mask}", 18, mask))
+    # vf-min (vertices and half of the faces) on subdomains of 2 x 2 subfaces
+    out.append(("2x2x2_m13", 12, 13))
     return out
 
 
@@ -202,6 +204,23 @@ def test_pcg_partial_primal_set():
     pc = m.Preconditioner(prob, dev(p.rho), primal_mask=5)
     _, st = pc.solve(dev(p.f[0]))
     assert abs(st["iters"][0] - ref.iters) <= 1
+
+
+def test_pcg_vf_min():
+    """vf-min (mask 13: vertices and half of the faces) with a coefficient
+    contrast: iterates at the oracle's count, iterations and kappa free-running."""
+    p = W.config2_like(n=24, H=8, L=4, cfg=63)
+    orc = bddc.from_problem(p, primal_mask=13)
+    ref = pcg.solve(orc, p.f[0], rtol=1e-8)
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    pcf = m.Preconditioner(prob, dev(p.rho), primal_mask=13, fixed_iters=ref.iters)
+    x, _ = pcf.solve(dev(p.f[0]))
+    assert relerr(host(x), ref.x) <= 1e-10
+    pc = m.Preconditioner(prob, dev(p.rho), primal_mask=13)
+    _, st = pc.solve(dev(p.f[0]))
+    assert abs(st["iters"][0] - ref.iters) <= 1
+    assert abs(st["kappa"][0] - ref.kappa) <= 0.01 * ref.kappa
 
 
 def test_fig1_coefficient_weights():

@@ -32,7 +32,7 @@ def test_algorithmic_equals_definitional(name, p):
 def test_partial_primal_sets():
     # Edges-only and faces-only selections (Remark on acceptable paths) still match Definition 1.
     p = W.config2_like(n=12, H=6, L=3, cfg=14, log_range=None)
-    for mask in (1, 2, 3, 4, 5, 6):
+    for mask in (1, 2, 3, 4, 5, 6, 13):
         alg = bddc.from_problem(p, primal_mask=mask).dense()
         ref = definitional.bddc_dense(p.n_el, p.h, p.elem_sub, p.elem_subsub, p.rho, primal_mask=mask)
         assert np.linalg.norm(alg - ref) <= 1e-11 * np.linalg.norm(ref), mask
@@ -209,3 +209,28 @@ def test_table1_bddc_so_k4_iterations():
     r = pcg.solve(bddc.from_problem(p), p.f[0], rtol=1e-6)
     assert r.iters == printed[("BDDC-SO(vef)", 4)]
     assert abs(r.iters - printed[("BDDC(vef)", 4)]) <= 1
+
+
+def test_channels_physics_subobjects_definitional():
+    """Section 5.2's physics-based subobjects (each subdomain split into its
+    background and channel parts, face constraints only, a floating centre
+    subdomain without primal points): the step-by-step B equals Definition 1."""
+    p = W.channels_problem(n=12, subs=3, ell=4, width=2, per_axis=1, f_one=False)
+    alg = bddc.from_problem(p).dense()
+    ref = definitional.bddc_dense(p.n_el, p.h, p.elem_sub, p.elem_subsub, p.rho, primal_mask=4)
+    assert np.linalg.norm(alg - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_channels_contrast_robustness():
+    """Section 5.2: with the subsubdomains following the coefficient (Remark
+    4) and face constraints only, BDDC-SO(f) takes the same iterations
+    (within one) for channel coefficients 10^2 .. 10^8, while standard
+    BDDC(vef) degrades with the contrast."""
+    so, std = [], []
+    for ell in (2, 4, 6, 8):
+        p = W.channels_problem(n=24, subs=3, ell=ell, per_axis=1)
+        so.append(pcg.solve(bddc.from_problem(p), p.f[0], rtol=1e-6).iters)
+        q = W.channels_problem(n=24, subs=3, ell=ell, per_axis=1, physics=False)
+        std.append(pcg.solve(bddc.from_problem(q), q.f[0], rtol=1e-6).iters)
+    assert max(so) - min(so) <= 1, so
+    assert std[-1] >= 2 * std[0] and std[-1] >= 2 * so[-1], (so, std)

@@ -110,6 +110,77 @@ def test_table1_closed_form_matches_printed():
         assert closed_form_vef(10, k, k)[0] == golden[("BDDC(vef)", k)]
 
 
+def closed_form_vfmin(N, k, L):
+    """Every fine vertex and half of the fine faces (no edges)."""
+    _, (verts, _, faces) = closed_form_vef(N, k, L)
+    return verts + faces // 2, (verts, 0, faces // 2)
+
+
+def test_table1_vfmin_closed_form_matches_printed():
+    """Table 1, BDDC-SO(vf-min): vertices plus half of the faces is the
+    printed coarse size at k = 16 and 32 (Section 5.1)."""
+    golden = {(r[0], int(r[1])): int(r[2]) for r in _read_golden("table1.txt")}
+    for k in (16, 32):
+        assert closed_form_vfmin(10, k, 4)[0] == golden[("BDDC-SO(vf-min)", k)]
+
+
+@pytest.mark.parametrize("k", [4, 8])
+def test_table1_vfmin_brute_force(k):
+    """The half-face selection (mask 1|4|8) keeps exactly half of the faces
+    of the Table 1 meshes and every vertex."""
+    p = W.table1_problem(k)
+    c = classify.classify(p.n_el, p.elem_sub, p.elem_subsub, primal_mask=13)
+    total, (v, e, f) = closed_form_vfmin(10, k, 4)
+    assert c.n_coarse == total
+    assert c.counts_by_type() == {"v": v, "e": e, "f": f}
+
+
+def _face_boxes(c, n_el):
+    """Per face object: normal axis, plane coordinate, and its in-plane node
+    ranges (grid coordinates)."""
+    from oracle.q1 import Grid
+    fc = Grid(n_el).free_coords()
+    out = {}
+    for o in range(len(c.obj_nodes)):
+        if c.obj_type[o] != classify.TYPE_F:
+            continue
+        xyz = fc[c.obj_nodes[o]]
+        lo, hi = xyz.min(axis=0), xyz.max(axis=0)
+        (normal,) = np.nonzero(lo == hi)[0][:1]
+        out[o] = (int(normal), int(lo[normal]), lo, hi)
+    return out
+
+
+@pytest.mark.parametrize("sizes", [(24, 8, 4), (24, 12, 4), (20, 10, 5)])
+def test_half_faces_alternate_in_each_plane(sizes):
+    """Two faces of one interface plane separated by a single fine edge line
+    (in-plane neighbours) are never both kept or both dropped, and each
+    interface plane keeps half of its faces (even counts) -- a checkerboard."""
+    n, H, L = sizes
+    p = W.config2_like(n=n, H=H, L=L, cfg=15, log_range=None)
+    all_f = classify.classify(p.n_el, p.elem_sub, p.elem_subsub, primal_mask=4)
+    half = classify.classify(p.n_el, p.elem_sub, p.elem_subsub, primal_mask=4 | 8)
+    kept = set(int(o) for o in half.coarse_objects)
+    boxes = _face_boxes(all_f, p.n_el)
+    planes = {}
+    for o, (a, t, lo, hi) in boxes.items():
+        planes.setdefault((a, t), []).append(o)
+    pairs = 0
+    for (a, t), objs in planes.items():
+        assert 2 * sum(o in kept for o in objs) == len(objs)
+        ax = [b for b in range(3) if b != a]
+        for i, o1 in enumerate(objs):
+            for o2 in objs[i + 1:]:
+                lo1, hi1, lo2, hi2 = boxes[o1][2], boxes[o1][3], boxes[o2][2], boxes[o2][3]
+                for u, w in ((ax[0], ax[1]), (ax[1], ax[0])):
+                    touch = hi1[u] + 2 == lo2[u] or hi2[u] + 2 == lo1[u]
+                    same = lo1[w] == lo2[w] and hi1[w] == hi2[w]
+                    if touch and same:
+                        pairs += 1
+                        assert (o1 in kept) != (o2 in kept), (o1, o2)
+    assert pairs > 0
+
+
 def test_standard_bddc_is_L_equals_H():
     p = W.table1_problem(4, L=4, subs_per_axis=3)
     q = W.tensor_problem(p.n_el, p.extra["sub_cuts"], p.extra["sub_cuts"])

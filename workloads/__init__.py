@@ -302,3 +302,49 @@ def config1_like(n: int = 64, H: int = 16, L: int = 4, cfg: int = 1, rho=None,
     sc = uniform_cuts(n, H)
     fc = uniform_cuts(n, L)
     return tensor_problem((n, n), [sc, sc], [fc, fc], cfg=cfg, rho=rho, name=name, nrhs=nrhs)
+
+
+def channels_problem(n: int = 40, subs: int = 4, ell: float = 6.0, width: int = 3, per_axis: int = 2,
+                     cfg: int = 20, physics: bool = True, f_one: bool = True) -> Problem:
+    """Section 5.2's channels problem: an n^3 mesh in subs^3 box subdomains,
+    with straight channels of coefficient 10^ell in a background of 1.  Per
+    axis direction, ``per_axis`` channels of ``width`` x ``width`` elements
+    run through the whole domain at positions drawn from stream 4 of ``cfg``
+    (the paper's figure of the geometry is not in the text), centred in
+    a row of subdomains drawn from stream 4 of ``cfg``, so that no channel
+    runs along an interface plane.
+
+    ``physics=True``: every subdomain is split into its background part and
+    its channel part (which may be several disconnected pieces), and these
+    are the subsubdomains (BDDC-SO with physics-based subobjects).
+    ``physics=False``: the subsubdomains are the subdomains (standard BDDC).
+    f = 1 at every free node (the paper's load) unless ``f_one`` is False."""
+    n_el = (n, n, n)
+    cuts = uniform_cuts(n, n // subs)
+    elem_sub = _tensor_ids(n_el, [cuts] * 3)
+    e = np.arange(n ** 3)
+    ec = np.stack([e % n, (e // n) % n, e // (n * n)], axis=1)
+    r = rng(cfg, 4)
+    chan = np.zeros(n ** 3, dtype=bool)
+    lines = []
+    H = n // subs
+    off = (H - width) // 2
+    for a in range(3):
+        b, c = [x for x in range(3) if x != a]
+        for _ in range(per_axis):
+            p, q = (int(v) * H + off for v in r.integers(0, subs, size=2))
+            lines.append((a, p, q))
+            chan |= (ec[:, b] >= p) & (ec[:, b] < p + width) & (ec[:, c] >= q) & (ec[:, c] < q + width)
+    rho = np.where(chan, 10.0 ** ell, 1.0)
+    if physics:
+        raw = 2 * elem_sub.astype(np.int64) + chan.astype(np.int64)
+        _, elem_subsub = np.unique(raw, return_inverse=True)
+        elem_subsub = elem_subsub.reshape(-1).astype(np.int32)
+    else:
+        elem_subsub = elem_sub.copy()
+    nf = n_free_of(n_el)
+    f = np.ones((1, nf)) if f_one else rng(cfg, 0).uniform(-1.0, 1.0, size=(1, nf))
+    return Problem(3, n_el, (1.0 / n,) * 3, elem_sub, elem_subsub, rho, f,
+                   name=f"channels_n{n}_l{ell:g}_{'so' if physics else 'std'}",
+                   primal_mask=4 if physics else 7, weighting=1,
+                   extra={"channels": lines, "width": width})
