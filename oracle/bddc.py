@@ -114,13 +114,24 @@ class BDDCSO:
         self.locals: List[Local] = []
         if local_only:
             return
-        Kc = np.zeros((cls.n_coarse, cls.n_coarse))
+        # K_c = sum_i R_ci^T K_c,i R_ci, assembled sparse (each coarse dof
+        # couples only to those of its subdomains) and factored exactly
+        rows, cols, vals = [], [], []
         for i in range(cls.n_sub):
             L = self.local(i)
-            Kc[np.ix_(L.coarse, L.coarse)] += L.Kc
+            r, c = np.meshgrid(L.coarse, L.coarse, indexing="ij")
+            rows.append(r.reshape(-1))
+            cols.append(c.reshape(-1))
+            vals.append(L.Kc.reshape(-1))
             self.locals.append(L)
-        self.Kc = Kc
-        self.Kc_factor = sla.cho_factor(Kc, lower=True) if cls.n_coarse else None
+        nc = cls.n_coarse
+        if nc:
+            self.Kc = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                    shape=(nc, nc)).tocsc()
+            self.Kc_solve = spla.factorized(self.Kc)
+        else:
+            self.Kc = sp.csc_matrix((0, 0))
+            self.Kc_solve = None
 
     def local(self, i: int) -> Local:
         """Setup of subdomain i alone: K_i, K_II factor, constrained Neumann
@@ -184,7 +195,7 @@ class BDDCSO:
             vdelta.append(sol[:n])
             bc[L.coarse] += L.Phi.T @ g
         # step 6
-        uc = sla.cho_solve(self.Kc_factor, bc) if cls.n_coarse else bc
+        uc = self.Kc_solve(bc) if cls.n_coarse else bc
         # steps 7-8
         w = np.zeros(N)
         for L, vd in zip(self.locals, vdelta):
