@@ -460,7 +460,8 @@ def main():
     if a.autotune:
         t0 = time.perf_counter()
         best, rep = prob.autotune(rho, b, **opts)
-        knobs = ("update_tile", "slab_lookahead", "sweep_reg_rows", "block_target", "mr_min_rhs", "graph")
+        knobs = ("update_tile", "slab_width", "slab_lookahead", "sweep_reg_rows", "block_target", "mr_min_rhs",
+                 "graph")
         tune = {"seconds": time.perf_counter() - t0, "chosen": {k: getattr(best, k) for k in knobs},
                 "trials": [{"knobs": kn, "ms": ms, "status": stt} for kn, ms, stt in rep["trials"]]}
         opts.update(tune["chosen"])

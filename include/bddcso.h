@@ -101,6 +101,9 @@ typedef struct {
                         are used (0 = 4)                                     */
   int update_tile;   /* tile rows of the slab sweeps' trailing update: 64 or
                         128 (0 = 64)                                         */
+  int slab_width;    /* pivots per slab of the large sweeps: 96 or 192, or 0
+                        (96 for a few matrices with short trailing updates,
+                        else 192)                                            */
 } bddcso_options;
 
 /* Fills the defaults: vef, coefficient weights, FP64, multifrontal coarse,

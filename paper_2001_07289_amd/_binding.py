@@ -32,7 +32,8 @@ class Options(C.Structure):
                 ("coarse_solver", C.c_int), ("max_nrhs", C.c_int), ("maxit", C.c_int),
                 ("rtol", C.c_double), ("fixed_iters", C.c_int), ("flexible", C.c_int),
                 ("block_target", C.c_int), ("graph", C.c_int), ("sweep_reg_rows", C.c_int),
-                ("slab_lookahead", C.c_int), ("mr_min_rhs", C.c_int), ("update_tile", C.c_int)]
+                ("slab_lookahead", C.c_int), ("mr_min_rhs", C.c_int), ("update_tile", C.c_int),
+                ("slab_width", C.c_int)]
 
 
 TUNE_MAX = 32

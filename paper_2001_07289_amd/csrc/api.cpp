@@ -283,6 +283,13 @@ struct bddcso_precond {
   // graph mode (options.graph): capture stream, the numeric setup's graph,
   // and per right-hand-side count the two halves of a PCG iteration
   hipStream_t sg = nullptr;
+  // coarse factorization stream: in ordinary (non-graph) mode the setup
+  // leaves it running and the next preconditioner application's coarse
+  // solve waits for it, so that application's local solves overlap the
+  // latency-bound upper levels of the factorization
+  hipStream_t s4 = nullptr;
+  hipEvent_t ev_kc = nullptr, ev_coarse = nullptr;
+  bool coarse_pending = false;
   hipGraphExec_t g_setup = nullptr;
   std::map<int, GraphPair> iter_graphs;
   double* xk = nullptr;      // x of graph-mode solves [max_nrhs][n_free]
@@ -659,7 +666,10 @@ void ref_gemm_batch(bddcso_precond* pc, const Batch& b) {
 }
 
 template <typename T>
-void numeric_setup(bddcso_precond* pc, hipStream_t s) {
+void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
+  // a previous setup's coarse factorization may still read the local coarse
+  // matrices this one rewrites
+  if (pc->coarse_pending) HIPCHK(hipStreamWaitEvent(s, pc->ev_coarse, 0));
   const Plan& pl = *pc->plan;
   Numeric<T>& N = num<T>(pc);
   const PlanDev& P = pc->P;
@@ -696,7 +706,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
       for (const Batch& b : sw[k]) {
         Kern<T>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, N.G, sws, N.sw_stride, pc->status,
                        setR ? 2 : 1, ss, pc->P_(), nullptr, pc->opt.sweep_reg_rows, pc->opt.slab_lookahead,
-                       pc->opt.update_tile);
+                       pc->opt.update_tile, pc->opt.slab_width);
         maxn = std::max(maxn, b.maxn);
       }
       if (pc->P_()) {  // banded Cholesky of block k of every subdomain
@@ -758,7 +768,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   Kern<T>::sc_assemble(P, N.Z, N.Sc, s);
   for (const Batch& b : pc->swSc) {
     Kern<T>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, N.Sc, N.sw, N.sw_stride, pc->status, 3, s,
-                   pc->P_(), nullptr, pc->opt.sweep_reg_rows, pc->opt.slab_lookahead, pc->opt.update_tile);
+                   pc->P_(), nullptr, pc->opt.sweep_reg_rows, pc->opt.slab_lookahead, pc->opt.update_tile, pc->opt.slab_width);
     ref_sweep_batch(pc, b);
   }
   Kern<T>::lambda_rhs(P, N.Z, N.Tm, s);
@@ -787,28 +797,37 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s) {
   HIPCHK(hipStreamWaitEvent(pc->s3, pc->ev_fork_i, 0));
   factor_chain(0, pc->s3);
   HIPCHK(hipEventRecord(pc->ev_join_i, pc->s3));
-  // coarse: assemble into the fronts and factor level by level (FP64).
-  // Fronts with at most two sources gather them (each entry written once);
-  // otherwise the local coarse matrices are added by colour classes and the
-  // children's update blocks in slot order.
+  // coarse: assemble into the fronts and factor level by level (FP64), on
+  // the fourth stream.  Fronts with at most two sources gather them (each
+  // entry written once); otherwise the local coarse matrices are added by
+  // colour classes and the children's update blocks in slot order.
+  // (on the caller's stream itself when the setup must end with it, as in a
+  // captured graph)
+  hipStream_t sc = leave_coarse ? pc->s4 : s;
+  if (leave_coarse) {
+    HIPCHK(hipEventRecord(pc->ev_kc, s));
+    HIPCHK(hipStreamWaitEvent(sc, pc->ev_kc, 0));
+  }
   if (!pl.front_gather)
     for (size_t c = 0; c < pc->color_dev.size(); ++c)
-      Kern<T>::kc_to_front(P, pc->color_dev[c], pc->color_n[c], N.Kc, pc->fpool, s);
+      Kern<T>::kc_to_front(P, pc->color_dev[c], pc->color_n[c], N.Kc, pc->fpool, sc);
   for (size_t L = 0; L < pc->swFront.size(); ++L) {
     if (pl.front_gather)
-      Kern<T>::front_gather(P, pc->level_dev[L], pc->level_n[L], pc->level_maxn[L], N.Kc, pc->fpool, s);
+      Kern<T>::front_gather(P, pc->level_dev[L], pc->level_n[L], pc->level_maxn[L], N.Kc, pc->fpool, sc);
     else
       for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
-        launch_front_child_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fpool, s);
+        launch_front_child_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fpool, sc);
     const SweepAux aux{pc->s2, pc->ev_la, pc->ev_lb, pc->ev_lc};
     for (const Batch& b : pc->swFront[L]) {
       Kern<double>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, pc->fpool, pc->fsw,
-                          pc->fsw_stride, pc->status, 4, s, pc->P_(), &aux, pc->opt.sweep_reg_rows,
-                          pc->opt.slab_lookahead, pc->opt.update_tile);
+                          pc->fsw_stride, pc->status, 4, sc, pc->P_(), &aux, pc->opt.sweep_reg_rows,
+                          pc->opt.slab_lookahead, pc->opt.update_tile, pc->opt.slab_width);
       ref_sweep_batch(pc, b);
     }
   }
+  if (leave_coarse) HIPCHK(hipEventRecord(pc->ev_coarse, sc));
   HIPCHK(hipStreamWaitEvent(s, pc->ev_join_i, 0));  // the interior factors
+  pc->coarse_pending = leave_coarse;
 }
 
 void coarse_solve(bddcso_precond* pc, int nrhs, hipStream_t s) {
@@ -862,6 +881,7 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   Kern<T>::coarse_rhs_local(P, N.PhiG, N.gv, N.bci, nrhs, pc->s2);
   if (sizeof(T) == 8) launch_coarse_rhs_gather(P, (const double*)N.bci, nullptr, pc->bc, nrhs, pc->s2);
   else launch_coarse_rhs_gather(P, nullptr, (const float*)N.bci, pc->bc, nrhs, pc->s2);
+  if (pc->coarse_pending) HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_coarse, 0));
   coarse_solve(pc, nrhs, pc->s2);
   Kern<T>::lam_uc(P, N.Lam, pc->uc, N.lu, nrhs, pc->s2);
   HIPCHK(hipEventRecord(pc->ev_cjoin, pc->s2));
@@ -1072,6 +1092,9 @@ void make_streams(bddcso_precond* pc) {
   HIPCHK(hipStreamCreateWithFlags(&pc->s2, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&pc->s3, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&pc->sg, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&pc->s4, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_kc, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pc->ev_coarse, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&pc->ev_fork_i, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&pc->ev_cpl, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&pc->ev_cfork, hipEventDisableTiming));
@@ -1110,6 +1133,8 @@ bddcso_status create_precond(bddcso_problem* p, const bddcso_options* opts, DevM
   if (o.mr_min_rhs < 1) return set_err(BDDCSO_EINVAL, "mr_min_rhs must be >= 0");
   if (o.update_tile == 0) o.update_tile = 64;
   if (o.update_tile != 64 && o.update_tile != 128) return set_err(BDDCSO_EINVAL, "update_tile must be 0, 64 or 128");
+  if (o.slab_width != 0 && o.slab_width != 96 && o.slab_width != 192)
+    return set_err(BDDCSO_EINVAL, "slab_width must be 0, 96 or 192");
   Error err;
   std::shared_ptr<Plan> plan;
   try {
@@ -1187,6 +1212,7 @@ void bddcso_default_options(bddcso_options* o) {
   o->slab_lookahead = 0;
   o->mr_min_rhs = 0;
   o->update_tile = 0;
+  o->slab_width = 0;
 }
 
 const char* bddcso_last_error(void) { return g_last_error.c_str(); }
@@ -1238,6 +1264,7 @@ void bddcso_precond_destroy(bddcso_precond* pc) {
   if (pc->s2) (void)hipStreamSynchronize(pc->s2);
   if (pc->s3) (void)hipStreamSynchronize(pc->s3);
   if (pc->sg) (void)hipStreamSynchronize(pc->sg);
+  if (pc->s4) (void)hipStreamSynchronize(pc->s4);
   if (pc->g_setup) (void)hipGraphExecDestroy(pc->g_setup);
   for (auto& kv : pc->iter_graphs) {
     if (kv.second.g1) (void)hipGraphExecDestroy(kv.second.g1);
@@ -1259,6 +1286,9 @@ void bddcso_precond_destroy(bddcso_precond* pc) {
   if (pc->s2) (void)hipStreamDestroy(pc->s2);
   if (pc->s3) (void)hipStreamDestroy(pc->s3);
   if (pc->sg) (void)hipStreamDestroy(pc->sg);
+  if (pc->s4) (void)hipStreamDestroy(pc->s4);
+  if (pc->ev_kc) (void)hipEventDestroy(pc->ev_kc);
+  if (pc->ev_coarse) (void)hipEventDestroy(pc->ev_coarse);
   if (pc->h_nactive) (void)hipHostFree(pc->h_nactive);
   delete pc;
 }
@@ -1274,14 +1304,15 @@ bddcso_status bddcso_refactor(bddcso_precond* pc, const double* rho_dev, void* s
     if (pc->opt.graph && !pc->P_()) {
       if (!pc->g_setup)
         pc->g_setup = capture_graph(pc, [&](hipStream_t ss) {
-          if (pc->precision == 1) numeric_setup<float>(pc, ss);
-          else numeric_setup<double>(pc, ss);
+          if (pc->precision == 1) numeric_setup<float>(pc, ss, false);
+          else numeric_setup<double>(pc, ss, false);
         });
       HIPCHK(hipGraphLaunch(pc->g_setup, s));
+      pc->coarse_pending = false;
     } else if (pc->precision == 1) {
-      numeric_setup<float>(pc, s);
+      numeric_setup<float>(pc, s, !pc->opt.graph);
     } else {
-      numeric_setup<double>(pc, s);
+      numeric_setup<double>(pc, s, !pc->opt.graph);
     }
     HIPCHK(hipGetLastError());
   } catch (const HipFail& f) {
@@ -1294,6 +1325,8 @@ bddcso_status bddcso_check_pivots(bddcso_precond* pc, void* stream) {
   if (!pc) return set_err(BDDCSO_EINVAL, "null precond");
   int st = 0;
   hipStream_t s = as_stream(stream);
+  if (pc->coarse_pending && hipStreamWaitEvent(s, pc->ev_coarse, 0) != hipSuccess)
+    return set_err(BDDCSO_EHIP, "wait for the coarse factorization failed");
   if (hipMemcpyAsync(&st, pc->status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return set_err(BDDCSO_EHIP, "status copy failed");
@@ -1420,8 +1453,15 @@ bddcso_status solve_impl(bddcso_precond* pc, const Krylov& K, const double* b, d
   std::vector<int32_t> hact(nr);
   int k_done = 0;
   try {
-    bddcso_status pst = bddcso_check_pivots(pc, stream);
-    if (pst != BDDCSO_OK) return pst;
+    // With the coarse factorization still running (ordinary mode), its
+    // pivots are checked after the solve instead, so the first application's
+    // local solves overlap it; a non-positive pivot then still returns
+    // ESINGULAR.
+    const bool defer_pivots = pc->coarse_pending;
+    if (!defer_pivots) {
+      bddcso_status pst = bddcso_check_pivots(pc, stream);
+      if (pst != BDDCSO_OK) return pst;
+    }
     launch_fill_f64(x, n * nr, 0.0, s);
     HIPCHK(hipMemcpyAsync(K.r, b, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_dot(b, b, n, nr, K.partial, pc->dot_blocks, s_bb, s);
@@ -1509,6 +1549,10 @@ bddcso_status solve_impl(bddcso_precond* pc, const Krylov& K, const double* b, d
       HIPCHK(hipMemcpyAsync(hb.data(), K.hist_b, (size_t)k_done * nr * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
+    if (defer_pivots) {
+      bddcso_status pst = bddcso_check_pivots(pc, stream);
+      if (pst != BDDCSO_OK) return pst;
+    }
     auto t1 = std::chrono::steady_clock::now();
     bool breakdown = false, noconv = false;
     if (stats) {
@@ -1728,6 +1772,7 @@ bddcso_status bddcso_autotune(bddcso_problem* p, const double* rho_dev, const bd
     }
   };
   knob(&bddcso_options::update_tile, {64, 128});
+  knob(&bddcso_options::slab_width, {0, 192, 96});
   knob(&bddcso_options::slab_lookahead, {0, 1, 2});
   knob(&bddcso_options::sweep_reg_rows, {kRegSweepMaxRows, 272});
   knob(&bddcso_options::block_target, {192, 128, 256});

@@ -104,11 +104,12 @@ struct Kern {
                            T* G, T* W, int64_t wstride, hipStream_t s);
   // reg_max: largest matrix of the register-resident sweep; lookahead: slab
   // look-ahead mode (0 by the update's size, 1 none, 2 always beside);
-  // utile: tile rows of the slab trailing update (64 or 128)
+  // utile: tile rows of the slab trailing update (64 or 128); slab_w: slab
+  // width (0 by the batch, 96 or 192)
   static void sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int maxn, int maxp, T* pool,
                     T* scratch, int64_t scr_stride, int* status, int status_code, hipStream_t s,
                     Profiler* prof, const SweepAux* aux = nullptr, int reg_max = kRegSweepMaxRows,
-                    int lookahead = 0, int utile = 64);
+                    int lookahead = 0, int utile = 64, int slab_w = 0);
   static void gemm(const GemmDesc* d_desc, const GemmDesc* h_desc, int nprob, int maxm, int maxn,
                    const T* A, int transA, const T* B, int transB, T* C, T alpha, T beta, hipStream_t s,
                    Profiler* prof);

@@ -1044,7 +1044,8 @@ constexpr double kSlabInlineFlops = 9e9;
 
 template <typename T, int MT, int RS_WAVES>
 __global__ __launch_bounds__(RS_WAVES * 64) void k_sweep_reg(const SweepDesc* __restrict__ desc, T* pool,
-                                                             int* status, int status_code, int slab_j0) {
+                                                             int* status, int status_code, int slab_j0,
+                                                             int sl = SLAB) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int NTILE = MT * (MT + 1) / 2;
   constexpr int TPW = (NTILE + RS_WAVES - 1) / RS_WAVES;
@@ -1055,9 +1056,9 @@ __global__ __launch_bounds__(RS_WAVES * 64) void k_sweep_reg(const SweepDesc* __
   __shared__ int tab[NTILE];
   const SweepDesc d = desc[blockIdx.x];
   // slab mode (slab_j0 >= 0): the diagonal block of pivots slab_j0 ..
-  // slab_j0 + SLAB - 1 of the matrix, swept completely
+  // slab_j0 + sl - 1 of the matrix (sl <= 16 MT), swept completely
   const int ld = d.ld;
-  const int n = slab_j0 < 0 ? d.n : min(SLAB, d.p - slab_j0);
+  const int n = slab_j0 < 0 ? d.n : min(sl, d.p - slab_j0);
   const int p = slab_j0 < 0 ? d.p : n;
   if (slab_j0 >= 0 && n <= 0) return;
   T* A = pool + d.off + (slab_j0 < 0 ? 0 : (int64_t)slab_j0 * (ld + 1));
@@ -1230,13 +1231,13 @@ __device__ __forceinline__ T slab_c32(const T* A, int ld, int j0, int i, int t) 
 // One workgroup per (64-row tile, 64-column tile of the slab, matrix).
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_slab_cd(const SweepDesc* __restrict__ desc, const T* __restrict__ pool,
-                                                 int j0, T* __restrict__ scratch, int64_t scr_stride) {
+                                                 int j0, T* __restrict__ scratch, int64_t scr_stride, int sl) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T As[32][TILE + PAD];  // C rows i, K chunk
   __shared__ T Bs[32][TILE + PAD];  // W columns q, K chunk
   const SweepDesc d = desc[blockIdx.z];
   const int n = d.n, ld = d.ld;
-  const int sb = min(SLAB, d.p - j0);
+  const int sb = min(sl, d.p - j0);
   if (sb <= 0) return;
   const int i0 = blockIdx.x * TILE, q0 = blockIdx.y * TILE;
   if (i0 >= n || q0 >= sb) return;
@@ -1308,7 +1309,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_slab_update(const SweepDesc* __restrict__ desc, T* pool, int j0,
                                                      const T* __restrict__ scratch, int64_t scr_stride,
-                                                     int ntri, int nprob, int region) {
+                                                     int ntri, int nprob, int region, int sl) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T As[32][TILE + PAD];  // CD rows i
   __shared__ T Bs[32][TILE + PAD];  // C rows j
@@ -1319,7 +1320,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int prob = (int)(logical / ntri);
   const SweepDesc d = desc[prob];
   const int n = d.n, ld = d.ld;
-  const int sb = min(SLAB, d.p - j0);
+  const int sb = min(sl, d.p - j0);
   if (sb <= 0) return;
   const int lin = (int)(logical % ntri);
   int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
@@ -1331,7 +1332,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   // tiles wholly inside the slab rows or columns take no update
   if ((i0 >= j0 && i0 + TILE <= j0 + sb) || (c0 >= j0 && c0 + TILE <= j0 + sb)) return;
   if (region) {
-    const int j1 = j0 + sb, sbn = min(SLAB, d.p - j1);  // next slab's pivots
+    const int j1 = j0 + sb, sbn = min(sl, d.p - j1);  // next slab's pivots
     const bool nextd = sbn > 0 && i0 + TILE > j1 && i0 < j1 + sbn && c0 + TILE > j1 && c0 < j1 + sbn;
     if ((region == 1) != nextd) return;
   }
@@ -1416,7 +1417,7 @@ constexpr int UT = 128, UK = 16;
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_slab_update128(
     const SweepDesc* __restrict__ desc, T* pool, int j0, const T* __restrict__ scratch, int64_t scr_stride,
-    int ntri, int nprob, int region) {
+    int ntri, int nprob, int region, int sl) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T As[UK][UT + PAD];  // CD rows i
   __shared__ T Bs[UK][UT + PAD];  // slab columns of rows j
@@ -1427,7 +1428,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int prob = (int)(logical / ntri);
   const SweepDesc d = desc[prob];
   const int n = d.n, ld = d.ld;
-  const int sb = min(SLAB, d.p - j0);
+  const int sb = min(sl, d.p - j0);
   if (sb <= 0) return;
   const int lin = (int)(logical % ntri);
   int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
@@ -1438,7 +1439,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (i0 >= n || c0 >= n) return;
   if ((i0 >= j0 && i0 + UT <= j0 + sb) || (c0 >= j0 && c0 + UT <= j0 + sb)) return;
   if (region) {
-    const int j1 = j0 + sb, sbn = min(SLAB, d.p - j1);  // next slab's pivots
+    const int j1 = j0 + sb, sbn = min(sl, d.p - j1);  // next slab's pivots
     const bool nextd = sbn > 0 && i0 + UT > j1 && i0 < j1 + sbn && c0 + UT > j1 && c0 < j1 + sbn;
     if ((region == 1) != nextd) return;
   }
@@ -1515,10 +1516,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // 4. The slab's rows and columns outside S become CD (lower triangle).
 template <typename T>
 __global__ void k_slab_writeback(const SweepDesc* __restrict__ desc, T* pool, int j0, const T* __restrict__ scratch,
-                                 int64_t scr_stride) {
+                                 int64_t scr_stride, int sl) {
   const SweepDesc d = desc[blockIdx.y];
   const int n = d.n, ld = d.ld;
-  const int sb = min(SLAB, d.p - j0);
+  const int sb = min(sl, d.p - j0);
   if (sb <= 0) return;
   T* A = pool + d.off;
   const T* CD = scratch + (int64_t)blockIdx.y * scr_stride;
@@ -1732,15 +1733,22 @@ __device__ __forceinline__ void gf_main(const GemmDesc& d, const T* __restrict__
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < (NB > 0 ? NB : 1); ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  // row tiles of this wave that hold output rows (wave-uniform): a 169-row
+  // block needs 11 of the 12 row tiles
+  const int na = __builtin_amdgcn_readfirstlane((wr + 8) * 16 < d.m ? 3 : (wr + 4) * 16 < d.m ? 2 : 1);
   load(0);
   for (int k0 = 0; k0 < d.k; k0 += GF_KC) {
     __syncthreads();
     store();
     __syncthreads();
     if (k0 + GF_KC < d.k) load(k0 + GF_KC);
+    // K steps of 4 that reach a valid index of this chunk (the tail chunk of
+    // a 169-deep product has 9 of 32)
+    const int kv = min(GF_KC, d.k - k0);
     if (NB > 0) {
 #pragma unroll
       for (int ks = 0; ks < GF_KC / 4; ++ks) {
+        if (ks * 4 >= kv) break;
         const int kk = ks * 4 + kq;
         T av[3], bv[NB > 0 ? NB : 1];
 #pragma unroll
@@ -1749,9 +1757,11 @@ __device__ __forceinline__ void gf_main(const GemmDesc& d, const T* __restrict__
         for (int b = 0; b < NB; ++b) bv[b] = Bs[kk][(wc + 4 * b) * 16 + rr];
         // transposed product (B as the A operand) so each lane's outputs run down a column
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
+          if (a >= na) break;
 #pragma unroll
           for (int b = 0; b < NB; ++b) acc[a][b] = Mfma<T>::mac(bv[b], av[a], acc[a][b]);
+        }
       }
     }
   }
@@ -3628,7 +3638,7 @@ void Kern<T>::schur_couple(const PlanDev& P, const Geo& g, const double* rho, in
 template <typename T>
 void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int maxn, int maxp, T* pool,
                     T* scratch, int64_t scr_stride, int* status, int status_code, hipStream_t s,
-                    Profiler* prof, const SweepAux* aux, int reg_max, int lookahead, int utile) {
+                    Profiler* prof, const SweepAux* aux, int reg_max, int lookahead, int utile, int slab_w) {
   if (nprob == 0 || maxp == 0) return;
   if (maxn <= hmin(reg_max, 16 * RS_MAX_TILES)) {
     // register-resident: one workgroup per matrix, read once, written once
@@ -3653,8 +3663,22 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
     return;
   }
   if (scr_stride >= (int64_t)maxn * SLAB) {
-    // slabs of SLAB pivots: register sweep of the diagonal block, CD, rank-SLAB update
+    // slabs of sl pivots: register sweep of the diagonal block, CD, rank-sl update
     static_assert(SLAB <= 16 * 12, "slab diagonal blocks use the 12-tile register sweep");
+    // Slab width: 192 pivots, or 96 for a few matrices whose first trailing
+    // update is short (a chain where the one-workgroup pivot-block sweeps
+    // dominate: a 96-pivot block sweeps in about a fifth of the time of a
+    // 192-pivot one, for twice the slabs)
+    int sl = SLAB;
+    if (slab_w == 96) sl = 96;
+    else if (slab_w == 0 && nprob <= 4 && h_desc) {
+      double uf0 = 0;
+      for (int q = 0; q < nprob; ++q) {
+        const double m = h_desc[q].n - std::min<double>(SLAB, h_desc[q].p);
+        uf0 += 2.0 * SLAB * m * (m + 1) / 2;
+      }
+      if (uf0 < kSlabInlineFlops) sl = 96;
+    }
     const int64_t tiles = cdiv(maxn, TILE);
     const int64_t ntri = tiles * (tiles + 1) / 2;
     // with a second stream: the next slab's pivot block is updated first and
@@ -3665,14 +3689,15 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
         for (int q = 0; q < nprob; ++q) {
           const double p = h_desc[q].p;
           if (j0 >= p) continue;
-          const double sb = std::min<double>(SLAB, p - j0);
+          const double sb = std::min<double>(sl, p - j0);
           df += sb * sb * sb;
           db += sizeof(T) * (sb * (sb + 1) / 2 + sb * sb);
         }
       // booked with the panel work (class 4): one workgroup per front sweeps
       // the slab's pivot block, a latency chain rather than a batch
       if (prof) prof->begin(4, ss);
-      k_sweep_reg<T, SLAB / 16, 16><<<nprob, 16 * 64, 0, ss>>>(d_desc, pool, status, status_code, j0);
+      if (sl == 96) k_sweep_reg<T, 6, 8><<<nprob, 8 * 64, 0, ss>>>(d_desc, pool, status, status_code, j0, 96);
+      else k_sweep_reg<T, SLAB / 16, 16><<<nprob, 16 * 64, 0, ss>>>(d_desc, pool, status, status_code, j0, SLAB);
       if (prof) prof->end(4, df, db, ss);
     };
     // Two orders for a slab with a look-ahead (u1: the next pivot block's
@@ -3685,12 +3710,12 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
     // The next slab's CD product waits for the branch on s2.
     reg(0, s);
     bool prev_inl = false;
-    for (int j0 = 0; j0 < maxp; j0 += SLAB) {
+    for (int j0 = 0; j0 < maxp; j0 += sl) {
       double cf = 0, cb = 0, uf = 0, ub = 0;
       for (int q = 0; h_desc && q < nprob; ++q) {
         const double n = h_desc[q].n, p = h_desc[q].p;
         if (j0 >= p) continue;
-        const double sb = std::min<double>(SLAB, p - j0), m = n - sb;
+        const double sb = std::min<double>(sl, p - j0), m = n - sb;
         const double low = m * (m + 1) / 2;
         cf += 2.0 * m * sb * sb;
         cb += sizeof(T) * (2.0 * m * sb + sb * sb);
@@ -3699,20 +3724,22 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
       }
       if (aux && j0 > 0) (void)hipStreamWaitEvent(s, prev_inl ? aux->c : aux->b, 0);
       if (prof) prof->begin(4, s);
-      k_slab_cd<T><<<dim3(cdiv(maxn, TILE), cdiv(SLAB, TILE), nprob), 256, 0, s>>>(d_desc, pool, j0, scratch,
-                                                                                  scr_stride);
+      k_slab_cd<T><<<dim3(cdiv(maxn, TILE), cdiv(sl, TILE), nprob), 256, 0, s>>>(d_desc, pool, j0, scratch,
+                                                                                scr_stride, sl);
       if (prof) prof->end(4, cf, cb, s);
       // trailing update by 64- or 128-row tiles of the lower triangle
       const int64_t utiles = cdiv(maxn, utile == 128 ? UT : TILE), untri = utiles * (utiles + 1) / 2;
       const unsigned ublk = (unsigned)((untri * nprob + 7) / 8 * 8);
       auto upd = [&](int region, hipStream_t ss) {
         if (utile == 128)
-          k_slab_update128<T><<<ublk, 256, 0, ss>>>(d_desc, pool, j0, scratch, scr_stride, (int)untri, nprob, region);
+          k_slab_update128<T><<<ublk, 256, 0, ss>>>(d_desc, pool, j0, scratch, scr_stride, (int)untri, nprob, region,
+                                                    sl);
         else
-          k_slab_update<T><<<ublk, 256, 0, ss>>>(d_desc, pool, j0, scratch, scr_stride, (int)untri, nprob, region);
+          k_slab_update<T><<<ublk, 256, 0, ss>>>(d_desc, pool, j0, scratch, scr_stride, (int)untri, nprob, region,
+                                                 sl);
       };
-      const unsigned wgrid = (unsigned)hmin(cdiv((int64_t)maxn * SLAB, 256), 2048);
-      const bool next = j0 + SLAB < maxp;
+      const unsigned wgrid = (unsigned)hmin(cdiv((int64_t)maxn * sl, 256), 2048);
+      const bool next = j0 + sl < maxp;
       prev_inl = false;
       if (next && aux && lookahead != 1) {
         const bool inl = lookahead == 2 || (h_desc && uf < kSlabInlineFlops);
@@ -3722,23 +3749,23 @@ void Kern<T>::sweep(SweepDesc* d_desc, const SweepDesc* h_desc, int nprob, int m
         (void)hipEventRecord(aux->a, s);
         (void)hipStreamWaitEvent(aux->s2, aux->a, 0);
         hipStream_t su = inl ? aux->s2 : s;
-        if (inl) reg(j0 + SLAB, s);
+        if (inl) reg(j0 + sl, s);
         else {
-          reg(j0 + SLAB, aux->s2);
+          reg(j0 + sl, aux->s2);
           (void)hipEventRecord(aux->b, aux->s2);
         }
         if (prof) prof->begin(1, su);
         upd(2, su);
         if (prof) prof->end(1, uf, ub, su);
-        k_slab_writeback<T><<<dim3(wgrid, nprob), 256, 0, su>>>(d_desc, pool, j0, scratch, scr_stride);
+        k_slab_writeback<T><<<dim3(wgrid, nprob), 256, 0, su>>>(d_desc, pool, j0, scratch, scr_stride, sl);
         if (inl) (void)hipEventRecord(aux->c, aux->s2);
         prev_inl = inl;
       } else {
         if (prof) prof->begin(1, s);
         upd(0, s);
         if (prof) prof->end(1, uf, ub, s);
-        k_slab_writeback<T><<<dim3(wgrid, nprob), 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride);
-        if (next) reg(j0 + SLAB, s);
+        k_slab_writeback<T><<<dim3(wgrid, nprob), 256, 0, s>>>(d_desc, pool, j0, scratch, scr_stride, sl);
+        if (next) reg(j0 + sl, s);
       }
     }
     const int64_t st = cdiv(maxp, 32);

@@ -110,7 +110,8 @@ class Problem:
         best, rep = B.Options(), B.TuneReport()
         B.check(B.load().bddcso_autotune(self._h, _ptr(rho), C.byref(o), _ptr(b), nrhs, _stream(stream),
                                          C.byref(best), C.byref(rep)))
-        knobs = ("update_tile", "slab_lookahead", "sweep_reg_rows", "block_target", "mr_min_rhs", "graph")
+        knobs = ("update_tile", "slab_width", "slab_lookahead", "sweep_reg_rows", "block_target", "mr_min_rhs",
+                 "graph")
         trials = [({k: getattr(rep.tried[t], k) for k in knobs}, rep.step_ms[t], B.STATUS.get(rep.status[t]))
                   for t in range(rep.n_trials)]
         return best, {"trials": trials, "best": rep.best}

@@ -63,3 +63,26 @@ def test_graph_fixed_iterations_match_oracle():
         x, _ = pc.solve(dev(p.f[0]))
         err = float(np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x))
         assert err <= 1e-10, err
+
+
+def test_coarse_factorization_overlap_orders_setups():
+    """The coarse factorization runs on its own stream and the next
+    application waits for it: back-to-back refactors, then a solve, equal a
+    fresh setup with the last coefficient (bitwise), in ordinary mode."""
+    p = W.config2_like(n=24, H=6, L=3, cfg=73)
+    m = pk()
+    prob = m.Problem.from_workload(p)
+    rho0 = dev(p.rho)
+    a = m.Preconditioner(prob, rho0 * 3.0)
+    a.refactor(rho0 * 0.5)
+    a.refactor(rho0)
+    b = dev(p.f[0])
+    xa, sa = a.solve(b)
+    fresh = m.Preconditioner(prob, rho0)
+    xf, sf = fresh.solve(b)
+    torch.cuda.synchronize()
+    assert sa["iters"] == sf["iters"]
+    assert torch.equal(xa, xf)
+    z1 = a.apply(b)
+    a.refactor(rho0)
+    assert torch.equal(a.apply(b), z1)
