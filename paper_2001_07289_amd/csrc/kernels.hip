@@ -504,31 +504,51 @@ __device__ __forceinline__ double recip_f64(double x) {
   return r;
 }
 
-// Lane l of a wave reads lane Q of its own row of 16 lanes (DPP row share).
+// Lane l of a wave reads lane 16 G + (l mod 16): row G of 16 lanes copied to
+// all four (two register swaps of gfx950: v_permlane16_swap exchanges the odd
+// rows of its first operand with the even rows of its second, and
+// v_permlane32_swap the upper half of the first with the lower half of the
+// second).  No LDS traffic.
+template <int G>
+__device__ __forceinline__ int rowgroup_bcast_i32(int x) {
+  const auto a = __builtin_amdgcn_permlane16_swap(x, x, false, false);  // rows (x0 x0 x2 x2), (x1 x1 x3 x3)
+  const int h = (G & 1) ? (int)a[1] : (int)a[0];
+  const auto b = __builtin_amdgcn_permlane32_swap(h, h, false, false);  // rows (h0 h1 h0 h1), (h2 h3 h2 h3)
+  return (G & 2) ? (int)b[1] : (int)b[0];
+}
+
+template <int G>
+__device__ __forceinline__ double rowgroup_bcast_f64(double x) {
+  return __hiloint2double(rowgroup_bcast_i32<G>(__double2hiint(x)), rowgroup_bcast_i32<G>(__double2loint(x)));
+}
+
+// Lane l of a wave reads lane Q of its own row of 16 lanes (DPP row
+// broadcast; every lane is written, so the destination needs no fill)
 template <int Q>
-__device__ __forceinline__ double row_share_f64(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x150 + Q, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x150 + Q, 0xf, 0xf, false);
+__device__ __forceinline__ double row_bcast_f64(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x150 + Q, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x150 + Q, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
 
-// One pivot step of the 16x16 sweep below.
+// One pivot step of the 16x16 sweep below, as the rank-1 form
+// X <- X0 - u v^T  (X0: X with row and column q zeroed; u = column q with -1
+// at q; v = row q / d with -1/d at q).
 template <int Q>
 __device__ __forceinline__ void sweep16_step(double m[4], int jb, int kq, int rr, bool& bad) {
-  double dq = readlane_f64(m[Q & 3], (Q >> 2) * 16 + Q);        // X[Q][Q]
-  if (!(dq > 0.0)) {
-    if (Q < jb) bad = true;
-    dq = 1.0;
-  }
-  const double inv = recip_f64(dq);
-  const double rowq = __shfl(m[Q & 3], (Q >> 2) * 16 + rr, 64);  // X[Q][rr]
-  const double rs = rowq * inv;
-  const bool qcol = rr == Q, qrow = kq == (Q >> 2);
+  const double dq = readlane_f64(m[Q & 3], (Q >> 2) * 16 + Q);     // X[Q][Q]
+  const double rowq = rowgroup_bcast_f64<(Q >> 2)>(m[Q & 3]);     // X[Q][rr]
+  bad |= (Q < jb) & !(dq > 0.0);
+  const double inv = recip_f64(dq > 0.0 ? dq : 1.0);
+  const bool qcol = rr == Q;
+  const double v = qcol ? -inv : rowq * inv;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const double colq = row_share_f64<Q>(m[t]);                   // X[4kq+t][Q]
-    const double upd = qcol ? colq * inv : m[t] - colq * rs;
-    m[t] = (t == (Q & 3) && qrow) ? (qcol ? -inv : rs) : upd;
+    const double colq = row_bcast_f64<Q>(m[t]);                   // X[4kq+t][Q]
+    const bool qrow = t == (Q & 3) && kq == (Q >> 2);
+    const double u = qrow ? -1.0 : colq;
+    const double mz = (qrow || qcol) ? 0.0 : m[t];
+    m[t] = fma(-u, v, mz);
   }
 }
 
@@ -542,9 +562,9 @@ __device__ __forceinline__ void sweep16_all(double m[4], int jb, int kq, int rr,
 // (kq = lane/16, rr = lane%16).  Sweeps pivots 0..15 (pivots >= jb are
 // identity padding).  Per pivot q: X[q][q] comes by a wave-uniform
 // broadcast, the pivot column X[4 kq + t][q] from lane q of the lane's own
-// row of 16 (DPP), the pivot row X[q][rr] by one cross-lane permute.  On
-// return m holds the swept block (-X^{-1} on the pivots).  Returns true on a
-// pivot <= 0.
+// row of 16 (DPP), the pivot row X[q][rr] from row q / 4 of the wave by two
+// register swaps (no LDS traffic).  On return m holds the swept block
+// (-X^{-1} on the pivots).  Returns true on a pivot <= 0.
 __device__ __forceinline__ bool quad_sweep16(double m[4], int jb, int lane) {
   bool bad = false;
   sweep16_all(m, jb, lane >> 4, lane & 15, bad, std::make_integer_sequence<int, 16>{});
