@@ -531,6 +531,36 @@ __device__ __forceinline__ double row_bcast_f64(double x) {
   return __hiloint2double(hi, lo);
 }
 
+// Lane l of a wave reads lane l ^ M (M = 1, 2, 4, 8, 16 or 32), the value
+// __shfl_xor returns, without LDS traffic: DPP within rows of 16 lanes (xor 1
+// and 2 by quad permutes, 4 by the half-row mirror followed by a quad
+// reversal, 8 by a row rotation), register swaps across rows (xor 16 and 32).
+template <int M>
+__device__ __forceinline__ int xor_lane_i32(int x) {
+  static_assert(M == 1 || M == 2 || M == 4 || M == 8 || M == 16 || M == 32, "lane xor mask");
+  if constexpr (M == 1) {
+    return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (M == 2) {
+    return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (M == 4) {
+    const int h = __builtin_amdgcn_mov_dpp(x, 0x141, 0xf, 0xf, false);  // i -> 7 - i in each 8
+    return __builtin_amdgcn_mov_dpp(h, 0x1B, 0xf, 0xf, false);           // quad_perm [3,2,1,0]
+  } else if constexpr (M == 8) {
+    return __builtin_amdgcn_mov_dpp(x, 0x128, 0xf, 0xf, false);  // row_ror:8
+  } else if constexpr (M == 16) {
+    const auto a = __builtin_amdgcn_permlane16_swap(x, x, false, false);  // rows (x0 x0 x2 x2), (x1 x1 x3 x3)
+    return (threadIdx.x & 16) ? (int)a[0] : (int)a[1];
+  } else {
+    const auto a = __builtin_amdgcn_permlane32_swap(x, x, false, false);  // rows (x0 x1 x0 x1), (x2 x3 x2 x3)
+    return (threadIdx.x & 32) ? (int)a[0] : (int)a[1];
+  }
+}
+
+template <int M>
+__device__ __forceinline__ double xor_lane_f64(double x) {
+  return __hiloint2double(xor_lane_i32<M>(__double2hiint(x)), xor_lane_i32<M>(__double2loint(x)));
+}
+
 // One pivot step of the 16x16 sweep below, as the rank-1 form
 // X <- X0 - u v^T  (X0: X with row and column q zeroed; u = column q with -1
 // at q; v = row q / d with -1/d at q).
@@ -2386,8 +2416,8 @@ __device__ __forceinline__ void bs_tile_mul(const T (&L)[4], int s, int base, in
     const int q = tc * 16 + 4 * g + u;
     if (rok && q >= base && q <= r) t1 += (double)L[u] * (double)x[q - base];
   }
-  t1 += __shfl_xor(t1, 16, 64);
-  t1 += __shfl_xor(t1, 32, 64);
+  t1 += xor_lane_f64<16>(t1);
+  t1 += xor_lane_f64<32>(t1);
   if (g == 0 && rok) y[r] += t1;
   const double xr = rok ? (double)x[r - base] : 0.0;
   double p[4];
@@ -2398,12 +2428,12 @@ __device__ __forceinline__ void bs_tile_mul(const T (&L)[4], int s, int base, in
   // u = 2 (a>>3 & 1) + (a>>2 & 1), and bits 1 and 0 complete the sum
   const bool h8 = (a & 8) != 0, h4 = (a & 4) != 0;
   double k0 = h8 ? p[2] : p[0], k1 = h8 ? p[3] : p[1];
-  k0 += __shfl_xor(h8 ? p[0] : p[2], 8, 64);
-  k1 += __shfl_xor(h8 ? p[1] : p[3], 8, 64);
+  k0 += xor_lane_f64<8>(h8 ? p[0] : p[2]);
+  k1 += xor_lane_f64<8>(h8 ? p[1] : p[3]);
   double k2 = h4 ? k1 : k0;
-  k2 += __shfl_xor(h4 ? k0 : k1, 4, 64);
-  k2 += __shfl_xor(k2, 2, 64);
-  k2 += __shfl_xor(k2, 1, 64);
+  k2 += xor_lane_f64<4>(h4 ? k0 : k1);
+  k2 += xor_lane_f64<2>(k2);
+  k2 += xor_lane_f64<1>(k2);
   const int q = tc * 16 + 4 * g + (h8 ? 2 : 0) + (h4 ? 1 : 0);
   if ((a & 3) == 0 && q < s) y[q] += k2;
 }
