@@ -2517,19 +2517,21 @@ __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, int setR,
     }
     vin_next = tid < B.size ? v[B.start + tid] : (T)0;
   };
-  auto prefetch_tiles = [&](int t, const BlockDev& B) {
+  // tile u of step t into L[u]
+  auto prefetch_tile = [&](int t, const BlockDev& B, int u) {
     int nrows, base;
     int64_t crow;
     step_shape(t, B, nrows, crow, base);
     const int nt = (B.size + 15) >> 4, t0 = base >> 4, nrow = nt - t0;
     const int ntiles = nrow * t0 + nrow * (nrow + 1) / 2;
+    const int lin = wave + BS_WAVES * u;
+    int tr = nt, tc = 0;  // past the last row: loads nothing
+    if (lin < ntiles) bs_tile_rc(lin, t0, nrow, tr, tc);
+    bs_tile_load(G + B.G_off, B.size, B.ld, base, tr, tc, a, g, L[u]);
+  };
+  auto prefetch_tiles = [&](int t, const BlockDev& B) {
 #pragma unroll
-    for (int u = 0; u < BS_PT; ++u) {
-      const int lin = wave + BS_WAVES * u;
-      int tr = nt, tc = 0;  // past the last row: loads nothing
-      if (lin < ntiles) bs_tile_rc(lin, t0, nrow, tr, tc);
-      bs_tile_load(G + B.G_off, B.size, B.ld, base, tr, tc, a, g, L[u]);
-    }
+    for (int u = 0; u < BS_PT; ++u) prefetch_tile(t, B, u);
   };
   if (nsteps > 0) {
     const BlockDev B0 = block_uniform(blk);
@@ -2584,7 +2586,11 @@ __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, int setR,
       }
     }
     __syncthreads();
-    // B. the block product, then the next step's loads
+    // B. the block product.  The next step's loads are issued as the
+    // registers free up: the small ones first (A waits for them), then each
+    // tile's right after its product, so the step's HBM traffic runs beside
+    // its arithmetic instead of after it.
+    if (tn < nsteps) prefetch_small(tn, Bn);
     {
       const int nt = (s + 15) >> 4, t0 = base >> 4, nrow = nt - t0;
       const int ntiles = nrow * t0 + nrow * (nrow + 1) / 2;
@@ -2597,6 +2603,7 @@ __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, int setR,
           bs_tile_rc(lin, t0, nrow, tr, tc);
           bs_tile_mul(L[u], s, base, tr, tc, a, g, cl, y);
         }
+        if (tn < nsteps) prefetch_tile(tn, Bn, u);
         __builtin_amdgcn_sched_barrier(0);  // one tile's temporaries at a time (register pressure)
       }
       for (int lin = wave + BS_WAVES * BS_PT; lin < ntiles; lin += BS_WAVES) {  // blocks above 192 rows
@@ -2606,10 +2613,6 @@ __global__ __launch_bounds__(BS_THREADS) void k_block_solve(PlanDev P, int setR,
         bs_tile_load(G + B.G_off, s, B.ld, base, tr, tc, a, g, Lx);
         bs_tile_mul(Lx, s, base, tr, tc, a, g, cl, y);
       }
-    }
-    if (tn < nsteps) {  // the small loads first: A waits for them, not for the tiles
-      prefetch_small(tn, Bn);
-      prefetch_tiles(tn, Bn);
     }
     __syncthreads();
     // C. sum the waves' partials in fixed order, clear them, store
