@@ -2819,6 +2819,33 @@ __global__ void k_neumann_rhs(PlanDev P, const T* __restrict__ gv, T* __restrict
 
 // mu = S_c^{-1} C_r u, one workgroup per (subdomain, rhs).  Sc holds the
 // swept matrix -S_c^{-1}.
+// Partial sums of y = M x (M: nrow x ncol, column-major with leading
+// dimension ld; x in LDS), accumulated in A, by a 256-thread workgroup: lane
+// l of wave w sums rows 64 k + l over the columns j = w mod 4 with four loads
+// in flight, into part[w * stride + row] (LDS, stride >= nrow).  Ends with a
+// barrier.
+template <typename A, typename T, typename X>
+__device__ __forceinline__ void gemv_split4(const T* __restrict__ M, int ld, int nrow, int ncol, const X* x,
+                                            A* part, int stride) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r0 = 0; r0 < nrow; r0 += 64) {
+    const int r = r0 + lane;
+    if (r < nrow) {
+      A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      int j = w;
+      for (; j + 12 < ncol; j += 16) {
+        a0 += (A)M[r + (int64_t)ld * j] * (A)x[j];
+        a1 += (A)M[r + (int64_t)ld * (j + 4)] * (A)x[j + 4];
+        a2 += (A)M[r + (int64_t)ld * (j + 8)] * (A)x[j + 8];
+        a3 += (A)M[r + (int64_t)ld * (j + 12)] * (A)x[j + 12];
+      }
+      for (; j < ncol; j += 4) a0 += (A)M[r + (int64_t)ld * j] * (A)x[j];
+      part[w * stride + r] = (a0 + a1) + (a2 + a3);
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_mu(PlanDev P, const T* __restrict__ vR, const T* __restrict__ Sc,
                                             T* __restrict__ mu) {
@@ -2834,16 +2861,24 @@ __global__ __launch_bounds__(256) void k_mu(PlanDev P, const T* __restrict__ vR,
     av[a] = (T)(s / (double)(pe - pb));
   }
   __syncthreads();
+  // the product with S_c: 64 rows per pass, the columns in four groups (one
+  // per wave), partial sums combined in a fixed order
   const T* M = Sc + S.Sc_off;
-  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x) {
-    T acc = 0;
-    for (int b = 0; b < S.n_a; ++b) acc += M[a + (int64_t)S.n_a * b] * av[b];
-    mu[rhs * P.tot_a + S.am_off + a] = -acc;
-  }
+  T* part = av + P.max_na;
+  gemv_split4<T>(M, S.n_a, S.n_a, S.n_a, av, part, P.max_na);
+  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x)
+    mu[rhs * P.tot_a + S.am_off + a] = -((part[a] + part[P.max_na + a]) + (part[2 * P.max_na + a] + part[3 * P.max_na + a]));
 }
 
+// Sum over the wave (every lane gets it; lane 0's pairing is that of the
+// shift-down tree), by register swaps and DPP: no LDS traffic.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  v += xor_lane_f64<32>(v);
+  v += xor_lane_f64<16>(v);
+  v += xor_lane_f64<8>(v);
+  v += xor_lane_f64<4>(v);
+  v += xor_lane_f64<2>(v);
+  v += xor_lane_f64<1>(v);
   return v;
 }
 
@@ -2866,9 +2901,17 @@ __global__ __launch_bounds__(256) void k_coarse_rhs_local(PlanDev P, const T* __
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const T* M = PhiG + S.PhiG_off;
   for (int c = cb + wave; c < min(S.n_c, cb + CRL_COLS); c += blockDim.x >> 6) {
-    double acc = 0.0;
-    for (int e = lane; e < S.n_g; e += 64) acc += (double)(M[e + (int64_t)S.n_s * c] * gl[e]);
-    acc = wave_sum(acc);
+    const T* col = M + (int64_t)S.n_s * c;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int e = lane;
+    for (; e + 192 < S.n_g; e += 256) {  // four loads in flight per lane
+      a0 += (double)(col[e] * gl[e]);
+      a1 += (double)(col[e + 64] * gl[e + 64]);
+      a2 += (double)(col[e + 128] * gl[e + 128]);
+      a3 += (double)(col[e + 192] * gl[e + 192]);
+    }
+    for (; e < S.n_g; e += 64) a0 += (double)(col[e] * gl[e]);
+    const double acc = wave_sum((a0 + a1) + (a2 + a3));
     if (lane == 0) bci[rhs * P.tot_c + S.c_off + c] = (T)acc;
   }
 }
@@ -2877,7 +2920,9 @@ __global__ __launch_bounds__(256) void k_coarse_rhs_local(PlanDev P, const T* __
 // With Phi = Y' - X Lambda this is u - X (mu + Lambda u_c) + Y' u_c, where
 // Y' is nonzero only in the vertex columns: the rows of X and of Y' at the
 // Gamma entries are read (n_a + n_v columns instead of n_a + n_c).  One
-// workgroup per (chunk of 256 Gamma rows, subdomain, rhs).
+// workgroup per (chunk of 64 Gamma rows, subdomain, rhs): lane l of wave w
+// takes row 64 chunk + l and the columns j = w mod 4, four loads in flight;
+// wave 0 adds the four partial sums in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_v2(PlanDev P, const T* __restrict__ vR, const T* __restrict__ XG,
                                             const T* __restrict__ mu, const T* __restrict__ lu,
@@ -2887,24 +2932,41 @@ __global__ __launch_bounds__(256) void k_v2(PlanDev P, const T* __restrict__ vR,
   T* sh = reinterpret_cast<T*>(smem_raw);
   const int sub = blockIdx.y, rhs = blockIdx.z;
   const SubDev S = P.subs[sub];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if ((int)(blockIdx.x * blockDim.x) >= S.n_g) return;
+  const int e0 = blockIdx.x * 64;
+  if (e0 >= S.n_g) return;
   T* mul = sh;
-  T* ucv = sh + S.n_a;
+  T* ucv = sh + P.max_na;
+  T* part = ucv + P.max_nv + 1;  // [4][64]
   for (int a = threadIdx.x; a < S.n_a; a += blockDim.x)
     mul[a] = mu[rhs * P.tot_a + S.am_off + a] + lu[rhs * P.tot_a + S.am_off + a];
   for (int v = threadIdx.x; v < S.n_v; v += blockDim.x)
     ucv[v] = (T)uc[rhs * P.n_coarse + P.c_glob[S.c_off + P.v_c[S.v_off + v]]];
   __syncthreads();
-  if (e >= S.n_g) return;
-  const T* u = vR + rhs * P.tot_r + S.r_off;
-  const T* X = XG + S.XG_off;
-  const T* Y = YG + S.YG_off;
-  const int r = P.g_r[S.g_off + e];
-  T acc = r >= 0 ? u[r] : (T)0;
-  for (int a = 0; a < S.n_a; ++a) acc -= X[e + (int64_t)S.n_s * a] * mul[a];
-  for (int v = 0; v < S.n_v; ++v) acc += Y[e + (int64_t)S.n_g * v] * ucv[v];
-  v2[rhs * P.tot_g + S.g_off + e] = acc;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, e = e0 + lane;
+  T acc = 0;
+  if (e < S.n_g) {
+    const T* X = XG + S.XG_off;
+    const T* Y = YG + S.YG_off;
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int a = w;
+    for (; a + 12 < S.n_a; a += 16) {
+      a0 -= X[e + (int64_t)S.n_s * a] * mul[a];
+      a1 -= X[e + (int64_t)S.n_s * (a + 4)] * mul[a + 4];
+      a2 -= X[e + (int64_t)S.n_s * (a + 8)] * mul[a + 8];
+      a3 -= X[e + (int64_t)S.n_s * (a + 12)] * mul[a + 12];
+    }
+    for (; a < S.n_a; a += 4) a0 -= X[e + (int64_t)S.n_s * a] * mul[a];
+    for (int v = w; v < S.n_v; v += 4) a1 += Y[e + (int64_t)S.n_g * v] * ucv[v];
+    acc = (a0 + a1) + (a2 + a3);
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (w == 0 && e < S.n_g) {
+    const T* u = vR + rhs * P.tot_r + S.r_off;
+    const int r = P.g_r[S.g_off + e];
+    const T base = r >= 0 ? u[r] : (T)0;
+    v2[rhs * P.tot_g + S.g_off + e] = base + ((part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]));
+  }
 }
 
 // lu = Lambda u_c per subdomain and right-hand side: one workgroup per
@@ -2920,11 +2982,11 @@ __global__ __launch_bounds__(256) void k_lam_uc(PlanDev P, const T* __restrict__
   for (int c = threadIdx.x; c < S.n_c; c += blockDim.x) ucl[c] = uc[rhs * P.n_coarse + P.c_glob[S.c_off + c]];
   __syncthreads();
   const T* L = Lam + S.T_off;
-  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x) {
-    double acc = 0.0;
-    for (int c = 0; c < S.n_c; ++c) acc += (double)L[a + (int64_t)S.n_a * c] * ucl[c];
-    lu[rhs * P.tot_a + S.am_off + a] = (T)acc;
-  }
+  double* part = ucl + P.max_nc;
+  gemv_split4<double>(L, S.n_a, S.n_a, S.n_c, ucl, part, P.max_na);
+  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x)
+    lu[rhs * P.tot_a + S.am_off + a] =
+        (T)((part[a] + part[P.max_na + a]) + (part[2 * P.max_na + a] + part[3 * P.max_na + a]));
 }
 
 // ---------------------------------------------------------------------------
@@ -4006,7 +4068,7 @@ void Kern<T>::neumann_rhs(const PlanDev& P, const T* gv, T* vR, int nrhs, hipStr
 template <typename T>
 void Kern<T>::mu(const PlanDev& P, const T* vR, const T* Sc, T* mu_out, int nrhs, hipStream_t s) {
   if (P.max_na == 0) return;
-  k_mu<T><<<dim3(P.n_sub, nrhs), 256, (size_t)P.max_na * sizeof(T), s>>>(P, vR, Sc, mu_out);
+  k_mu<T><<<dim3(P.n_sub, nrhs), 256, (size_t)5 * P.max_na * sizeof(T), s>>>(P, vR, Sc, mu_out);
 }
 
 template <typename T>
@@ -4030,8 +4092,8 @@ void Kern<T>::v2(const PlanDev& P, const T* vR, const T* XG, const T* mu_in, con
                                                                                      uc, v2_out, nrhs);
     return;
   }
-  size_t sm = (size_t)(P.max_na + P.max_nv + 1) * sizeof(T);
-  k_v2<T><<<dim3(cdiv(P.max_ng, 256), P.n_sub, nrhs), 256, sm, s>>>(P, vR, XG, mu_in, lu, YG, uc, v2_out);
+  size_t sm = (size_t)(P.max_na + P.max_nv + 1 + 256) * sizeof(T);
+  k_v2<T><<<dim3(cdiv(P.max_ng, 64), P.n_sub, nrhs), 256, sm, s>>>(P, vR, XG, mu_in, lu, YG, uc, v2_out);
 }
 
 template <typename T>
@@ -4060,7 +4122,8 @@ void Kern<T>::float_v2(const PlanDev& P, const double* uc, const double* eps, co
 template <typename T>
 void Kern<T>::lam_uc(const PlanDev& P, const T* Lam, const double* uc, T* lu, int nrhs, hipStream_t s) {
   if (P.max_na == 0) return;
-  k_lam_uc<T><<<dim3(P.n_sub, nrhs), 256, (size_t)hmax(P.max_nc, 1) * sizeof(double), s>>>(P, Lam, uc, lu);
+  k_lam_uc<T><<<dim3(P.n_sub, nrhs), 256, (size_t)(hmax(P.max_nc, 1) + 4 * (size_t)P.max_na) * sizeof(double), s>>>(
+      P, Lam, uc, lu);
 }
 
 template <typename T>
