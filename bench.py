@@ -40,7 +40,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 CLASS_KERNELS = {"sweep_update": ("k_sweep_update", "k_slab_update"), "block_solve": ("k_block_solve",),
                  "gemm": ("k_gemm",), "sweep_panel": ("k_sweep_panel", "k_slab_cd"),
                  "sweep_small": ("k_sweep_reg",), "schur_couple": ("k_schur_couple",),
-                 "couple_multi": ("k_couple_multi",), "q1_apply": ("k_q1_apply",)}
+                 "couple_multi": ("k_couple_multi",), "q1_apply": ("k_q1_apply", "k_q1_apply3")}
 MFMA_CLASSES = ("sweep_update", "gemm", "sweep_panel", "sweep_small")
 METRIC = "BDDC-SO PCG DoF/s to rel.res 1e-8: FP64 plain vs mixed batched; grads/s"
 MFMA_TFLOPS = {"f64": 78.6, "f32": 157.3}  # dense matrix peaks, TFLOP/s
