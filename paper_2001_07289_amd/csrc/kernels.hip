@@ -1739,20 +1739,24 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ desc,
 // wc + 4j (16 x 16 each).  K goes in chunks of GF_KC through LDS with the
 // next chunk prefetched into registers.  The LDS tiles are zero-padded to
 // 192 rows and to whole chunks, so every wave runs the same branch-free
-// k-steps (three row tiles, one or two column tiles by a wave-uniform
-// choice made once) and the products of padding are never stored.
+// k-steps (three row tiles, one to three column tiles by a wave-uniform
+// choice made once) and the products of padding are never stored.  Two
+// shapes: 128 columns per workgroup with K chunks of 32, and for 129 to 192
+// columns one workgroup per problem (the 128-column form would need a second
+// round of workgroups for the last columns) with K chunks of 16, which keeps
+// the nine accumulator tiles per wave within 128 VGPRs.
 constexpr int GF_KC = 32;
-constexpr int GF_M = 176, GF_N = 128, GF_MP = 192;
+constexpr int GF_M = 176, GF_N = 128, GF_MP = 192, GF_N3 = 192, GF_KC3 = 16;
 
-template <typename T, int NB>
+template <typename T, int NB, int KC, int GN>
 __device__ __forceinline__ void gf_main(const GemmDesc& d, const T* __restrict__ A, const T* __restrict__ B,
                                         T* __restrict__ C, int nn, T alpha, T beta, T (*As)[GF_MP + 4],
-                                        T (*Bs)[GF_N + 4]) {
+                                        T (*Bs)[GN + 4]) {
   typedef typename Mfma<T>::acc_t acc_t;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int kq = lane >> 4, rr = lane & 15;
   const int wr = wave & 3, wc = wave >> 2;
-  constexpr int PA = (GF_MP * GF_KC) / 1024, PB = GF_N * GF_KC / 1024;
+  constexpr int PA = (GF_MP * KC) / 1024, PB = GN * KC / 1024;
   T ra[PA], rb[PB];
   auto load = [&](int k0) {
 #pragma unroll
@@ -1762,7 +1766,7 @@ __device__ __forceinline__ void gf_main(const GemmDesc& d, const T* __restrict__
     }
 #pragma unroll
     for (int u = 0; u < PB; ++u) {
-      const int idx = tid + 1024 * u, q = idx % GF_KC, j = idx / GF_KC;
+      const int idx = tid + 1024 * u, q = idx % KC, j = idx / KC;
       rb[u] = (j < nn && k0 + q < d.k) ? B[(k0 + q) + (int64_t)d.ldb * j] : (T)0;
     }
   };
@@ -1774,7 +1778,7 @@ __device__ __forceinline__ void gf_main(const GemmDesc& d, const T* __restrict__
     }
 #pragma unroll
     for (int u = 0; u < PB; ++u) {
-      const int idx = tid + 1024 * u, q = idx % GF_KC, j = idx / GF_KC;
+      const int idx = tid + 1024 * u, q = idx % KC, j = idx / KC;
       Bs[q][j] = rb[u];
     }
   };
@@ -1787,17 +1791,17 @@ __device__ __forceinline__ void gf_main(const GemmDesc& d, const T* __restrict__
   // block needs 11 of the 12 row tiles
   const int na = __builtin_amdgcn_readfirstlane((wr + 8) * 16 < d.m ? 3 : (wr + 4) * 16 < d.m ? 2 : 1);
   load(0);
-  for (int k0 = 0; k0 < d.k; k0 += GF_KC) {
+  for (int k0 = 0; k0 < d.k; k0 += KC) {
     __syncthreads();
     store();
     __syncthreads();
-    if (k0 + GF_KC < d.k) load(k0 + GF_KC);
+    if (k0 + KC < d.k) load(k0 + KC);
     // K steps of 4 that reach a valid index of this chunk (the tail chunk of
     // a 169-deep product has 9 of 32)
-    const int kv = min(GF_KC, d.k - k0);
+    const int kv = min(KC, d.k - k0);
     if (NB > 0) {
 #pragma unroll
-      for (int ks = 0; ks < GF_KC / 4; ++ks) {
+      for (int ks = 0; ks < KC / 4; ++ks) {
         if (ks * 4 >= kv) break;
         const int kk = ks * 4 + kq;
         T av[3], bv[NB > 0 ? NB : 1];
@@ -1831,26 +1835,30 @@ __device__ __forceinline__ void gf_main(const GemmDesc& d, const T* __restrict__
       }
 }
 
-template <typename T>
+template <typename T, int KC, int GN>
 __global__ __launch_bounds__(1024) void k_gemm_full(const GemmDesc* __restrict__ desc,
                                                     const T* __restrict__ Ap, const T* __restrict__ Bp,
                                                     T* __restrict__ Cp, T alpha, T beta) {
-  __shared__ T As[GF_KC][GF_MP + 4];
-  __shared__ T Bs[GF_KC][GF_N + 4];
+  __shared__ T As[KC][GF_MP + 4];
+  __shared__ T Bs[KC][GN + 4];
   const GemmDesc d = desc[blockIdx.x];
-  const int n0 = blockIdx.y * GF_N;
+  const int n0 = blockIdx.y * GN;
   if (d.m <= 0 || n0 >= d.n) return;
-  const int nn = min(GF_N, d.n - n0);
+  const int nn = min(GN, d.n - n0);
   const T* A = Ap + d.a;
   const T* B = Bp + d.b + (int64_t)d.ldb * n0;
   T* C = Cp + d.c + (int64_t)d.ldc * n0;
   // column tiles wc, wc + 4 of this wave that hold output (wave-uniform);
   // every wave runs the same chunk loop and barriers
   const int wc = (threadIdx.x >> 6) >> 2;
-  const int nb = __builtin_amdgcn_readfirstlane((wc + 4) * 16 < nn ? 2 : wc * 16 < nn ? 1 : 0);
-  if (nb == 2) gf_main<T, 2>(d, A, B, C, nn, alpha, beta, As, Bs);
-  else if (nb == 1) gf_main<T, 1>(d, A, B, C, nn, alpha, beta, As, Bs);
-  else gf_main<T, 0>(d, A, B, C, nn, alpha, beta, As, Bs);
+  const int nb = __builtin_amdgcn_readfirstlane((wc + 8) * 16 < nn && GN > 128 ? 3
+                                                 : (wc + 4) * 16 < nn                ? 2
+                                                 : wc * 16 < nn                      ? 1
+                                                                                     : 0);
+  if (nb == 3) gf_main<T, (GN > 128 ? 3 : 2), KC, GN>(d, A, B, C, nn, alpha, beta, As, Bs);
+  else if (nb == 2) gf_main<T, 2, KC, GN>(d, A, B, C, nn, alpha, beta, As, Bs);
+  else if (nb == 1) gf_main<T, 1, KC, GN>(d, A, B, C, nn, alpha, beta, As, Bs);
+  else gf_main<T, 0, KC, GN>(d, A, B, C, nn, alpha, beta, As, Bs);
 }
 
 // ---------------------------------------------------------------------------
@@ -3934,7 +3942,10 @@ void Kern<T>::gemm(const GemmDesc* d_desc, const GemmDesc* h_desc, int nprob, in
   const unsigned nb = (unsigned)(((int64_t)tm * tn * nprob + 7) / 8 * 8);
   if (prof) prof->begin(3, s);
   if (!transA && !transB && maxm <= GF_M) {
-    k_gemm_full<T><<<dim3(nprob, cdiv(maxn, GF_N)), 1024, 0, s>>>(d_desc, A, B, C, alpha, beta);
+    if (maxn > GF_N && maxn <= GF_N3)
+      k_gemm_full<T, GF_KC3, GF_N3><<<dim3(nprob, 1), 1024, 0, s>>>(d_desc, A, B, C, alpha, beta);
+    else
+      k_gemm_full<T, GF_KC, GF_N><<<dim3(nprob, cdiv(maxn, GF_N)), 1024, 0, s>>>(d_desc, A, B, C, alpha, beta);
     if (prof) prof->end(3, f, by, s);
     return;
   }
