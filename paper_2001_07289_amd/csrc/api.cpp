@@ -836,12 +836,15 @@ void coarse_solve(bddcso_precond* pc, int nrhs, hipStream_t s) {
   const int nlev = (int)pc->level_dev.size();
   const int64_t stride = pl.front_vec;
   launch_front_vec_init(P, pc->all_fronts, pc->all_n, pc->all_maxn, pc->bc, pc->fvec, stride, nrhs, s);
+  double* part = nrhs < pc->P.mr_min ? pc->fpart : nullptr;
+  const bool pull = part && P.front_pull;  // the chunked forward step gathers the children's values itself
   for (int L = 0; L < nlev; ++L) {
-    for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
-      launch_front_vec_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fvec, stride,
-                               nrhs, s);
+    if (!pull)
+      for (size_t j = 0; j < pc->slot_dev[L].size(); ++j)
+        launch_front_vec_scatter(P, pc->slot_dev[L][j], pc->slot_n[L][j], pc->slot_maxn[L][j], pc->fvec, stride,
+                                 nrhs, s);
     launch_front_fwd(P, pc->level_dev[L], pc->level_n[L], pc->level_maxn[L], pc->level_maxp[L], pc->fpool,
-                     pc->fvec, pc->xh, stride, nrhs, s, nrhs < pc->P.mr_min ? pc->fpart : nullptr);
+                     pc->fvec, pc->xh, stride, nrhs, s, part, pull);
   }
   for (int L = nlev - 1; L >= 0; --L)
     launch_front_bwd(P, pc->level_dev[L], pc->level_n[L], pc->level_maxp[L], pc->level_maxb[L], pc->fpool, pc->xh,
@@ -995,6 +998,28 @@ void layout(bddcso_precond* pc, hipStream_t s) {
   P.fronts = m.upload(pl.fronts, s);
   P.front_idx = m.upload(pl.front_idx, s);
   P.front_pmap = m.upload(pl.front_pmap, s);
+  {
+    // per front vector entry and scatter slot, the child border value the
+    // entry receives (the single-RHS coarse forward step pulls them in slot
+    // order instead of running the scatter launches), -1 for none
+    int ns = 0;
+    for (const auto& lv : pl.level_slot_children) ns = std::max(ns, (int)lv.size());
+    std::vector<int32_t> pull;
+    if (ns > 0 && pl.front_vec > 0) {
+      if (pl.front_vec > INT32_MAX) throw PlanFail{"coarse front vectors above 2^31 entries"};
+      pull.assign((size_t)pl.front_vec * ns, -1);
+      for (const auto& lv : pl.level_slot_children)
+        for (size_t j = 0; j < lv.size(); ++j)
+          for (int c : lv[j]) {
+            const FrontDev& C = pl.fronts[c];
+            const FrontDev& F = pl.fronts[C.parent];
+            for (int k = 0; k < C.n - C.p; ++k)
+              pull[(size_t)(F.voff + pl.front_pmap[C.pmap_off + k]) * ns + j] = (int32_t)(C.voff + C.p + k);
+          }
+    }
+    P.n_slot = pull.empty() ? 0 : ns;
+    P.front_pull = pull.empty() ? nullptr : m.upload(pull, s);
+  }
   P.front_imap = pl.front_imap.empty() ? nullptr : m.upload(pl.front_imap, s);
   P.sub_fmap = m.upload(pl.sub_fmap, s);
   P.cpl_rank = m.upload(pl.cpl_rank, s);

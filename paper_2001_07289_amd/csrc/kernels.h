@@ -68,6 +68,10 @@ struct PlanDev {
   const int32_t *crs_eptr, *crs_ent;
   const FrontDev* fronts;
   const int32_t *front_idx, *front_pmap, *sub_fmap, *front_imap;
+  // per front vector entry and scatter slot: the vector index of the child
+  // border value the entry receives, -1 for none ([entry][n_slot])
+  const int32_t* front_pull;
+  int n_slot;
   const double* khat;  // 8x8 unit-coefficient element matrix (2D replicated over the z bit)
   const int32_t *cpl_rank, *cpl_sub, *cpl_loc, *cpl_dir;
   const double* cpl_coef;  // 9 coefficients per coupling row (filled at setup)
@@ -173,10 +177,13 @@ void launch_front_vec_init(const PlanDev& P, const int32_t* fr, int nfr, int max
                            double* fvec, int64_t fvec_stride, int nrhs, hipStream_t s);
 void launch_front_vec_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
                               double* fvec, int64_t fvec_stride, int nrhs, hipStream_t s);
+// pull: with part (the chunked single-RHS form), the entries take their
+// children's border values themselves (P.front_pull, in slot order) instead
+// of a preceding launch_front_vec_scatter
 void launch_front_fwd(const PlanDev& P, const int32_t* fr, int nfr, int maxn, int maxp,
                       const double* fpool, double* fvec, double* xh, int64_t fvec_stride,
                       int nrhs, hipStream_t s,
-                      double* part = nullptr);
+                      double* part = nullptr, bool pull = false);
 void launch_front_bwd(const PlanDev& P, const int32_t* fr, int nfr, int maxp, int maxb,
                       const double* fpool, const double* xh, int64_t fvec_stride, double* uc,
                       int nrhs, hipStream_t s);

@@ -3241,6 +3241,18 @@ __global__ __launch_bounds__(256) void k_front_fwd(PlanDev P, const int32_t* __r
   else y[i] -= acc;
 }
 
+// Vector entry idx of one right-hand side (fv: its part of fvec) plus the
+// children's border values it receives, added in slot order (the order of
+// the scatter launches it replaces).
+__device__ __forceinline__ double front_pulled(const PlanDev& P, const double* __restrict__ fv, int64_t idx) {
+  double v = fv[idx];
+  for (int j = 0; j < P.n_slot; ++j) {
+    const int32_t src = P.front_pull[idx * P.n_slot + j];
+    if (src >= 0) v += fv[src];
+  }
+  return v;
+}
+
 // The same forward step split over chunks of FK pivot columns, for one or a
 // few right-hand sides: k_front_fwd_part writes the partial products of
 // each chunk (64 rows x 4 column groups per workgroup, the groups summed in
@@ -3251,7 +3263,7 @@ constexpr int FK = 256;
 __global__ __launch_bounds__(256) void k_front_fwd_part(PlanDev P, const int32_t* __restrict__ fr,
                                                         const double* __restrict__ fpool,
                                                         const double* __restrict__ fvec, int64_t stride, int nrhs,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, int pull) {
   __shared__ double yl[FK];
   __shared__ double red[4][64];
   const FrontDev F = P.fronts[fr[blockIdx.z / nrhs]];
@@ -3259,8 +3271,9 @@ __global__ __launch_bounds__(256) void k_front_fwd_part(PlanDev P, const int32_t
   const int i0 = blockIdx.x * 64, kc = blockIdx.y, k0 = kc * FK;
   if (i0 >= F.n || k0 >= F.p) return;
   const int kn = min(FK, F.p - k0);
-  const double* y = fvec + rhs * stride + F.voff;
-  for (int j = threadIdx.x; j < FK; j += blockDim.x) yl[j] = j < kn ? y[k0 + j] : 0.0;
+  const double* fv = fvec + rhs * stride;
+  for (int j = threadIdx.x; j < FK; j += blockDim.x)
+    yl[j] = j >= kn ? 0.0 : pull ? front_pulled(P, fv, F.voff + k0 + j) : fv[F.voff + k0 + j];
   __syncthreads();
   const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int i = i0 + r;
@@ -3278,7 +3291,8 @@ __global__ __launch_bounds__(256) void k_front_fwd_part(PlanDev P, const int32_t
 
 __global__ __launch_bounds__(256) void k_front_fwd_fin(PlanDev P, const int32_t* __restrict__ fr,
                                                        double* __restrict__ fvec, double* __restrict__ xh,
-                                                       int64_t stride, int nrhs, const double* __restrict__ part) {
+                                                       int64_t stride, int nrhs, const double* __restrict__ part,
+                                                       int pull) {
   const FrontDev F = P.fronts[fr[blockIdx.y]];
   const int rhs = blockIdx.z;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -3288,7 +3302,7 @@ __global__ __launch_bounds__(256) void k_front_fwd_fin(PlanDev P, const int32_t*
   for (int kc = 0; kc < nkc; ++kc) z += part[(int64_t)kc * nrhs * stride + rhs * stride + F.voff + i];
   const int64_t at = rhs * stride + F.voff + i;
   if (i < F.p) xh[at] = -z;
-  else fvec[at] -= z;
+  else fvec[at] = (pull ? front_pulled(P, fvec + rhs * stride, F.voff + i) : fvec[at]) - z;
 }
 
 // x_P = xh_P - L~^T x_B, x_B from ancestors; one wave per pivot column.
@@ -4199,7 +4213,7 @@ void launch_front_vec_scatter(const PlanDev& P, const int32_t* children, int nch
   k_front_vec_scatter<<<dim3(cdiv(maxn, 256), nchild, nrhs), 256, 0, s>>>(P, children, fvec, stride);
 }
 void launch_front_fwd(const PlanDev& P, const int32_t* fr, int nfr, int maxn, int maxp, const double* fpool,
-                      double* fvec, double* xh, int64_t stride, int nrhs, hipStream_t s, double* part) {
+                      double* fvec, double* xh, int64_t stride, int nrhs, hipStream_t s, double* part, bool pull) {
   if (nfr == 0 || maxp == 0) return;
   if (nrhs >= P.mr_min) {
     k_front_fwd_mr<<<dim3(cdiv(maxn, 64), nfr, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, fr, fpool, fvec, xh, stride,
@@ -4207,9 +4221,10 @@ void launch_front_fwd(const PlanDev& P, const int32_t* fr, int nfr, int maxn, in
     return;
   }
   if (part) {
+    const int pl = pull && P.front_pull ? 1 : 0;
     k_front_fwd_part<<<dim3(cdiv(maxn, 64), cdiv(maxp, FK), nfr * nrhs), 256, 0, s>>>(P, fr, fpool, fvec, stride,
-                                                                                      nrhs, part);
-    k_front_fwd_fin<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, fvec, xh, stride, nrhs, part);
+                                                                                      nrhs, part, pl);
+    k_front_fwd_fin<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, fvec, xh, stride, nrhs, part, pl);
     return;
   }
   k_front_fwd<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, fpool, fvec, xh, stride);
