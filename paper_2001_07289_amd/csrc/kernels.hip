@@ -3260,10 +3260,13 @@ __device__ __forceinline__ double front_pulled(const PlanDev& P, const double* _
 // part[kc][rhs][front row] (kc-major, stride nrhs * stride per chunk).
 constexpr int FK = 256;
 
+// direct: every front of the launch has at most FK pivots (one chunk), and
+// the chunk's sums are applied here as k_front_fwd_fin would (no part).
 __global__ __launch_bounds__(256) void k_front_fwd_part(PlanDev P, const int32_t* __restrict__ fr,
                                                         const double* __restrict__ fpool,
-                                                        const double* __restrict__ fvec, int64_t stride, int nrhs,
-                                                        double* __restrict__ part, int pull) {
+                                                        double* __restrict__ fvec, int64_t stride, int nrhs,
+                                                        double* __restrict__ part, int pull, int direct,
+                                                        double* __restrict__ xh) {
   __shared__ double yl[FK];
   __shared__ double red[4][64];
   const FrontDev F = P.fronts[fr[blockIdx.z / nrhs]];
@@ -3285,8 +3288,16 @@ __global__ __launch_bounds__(256) void k_front_fwd_part(PlanDev P, const int32_t
   }
   red[g][r] = acc;
   __syncthreads();
-  if (g == 0 && i < F.n)
-    part[(int64_t)kc * nrhs * stride + rhs * stride + F.voff + i] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+  if (g == 0 && i < F.n) {
+    const double z = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+    if (direct) {
+      const int64_t at = rhs * stride + F.voff + i;
+      if (i < F.p) xh[at] = -z;
+      else fvec[at] = (pull ? front_pulled(P, fvec + rhs * stride, F.voff + i) : fvec[at]) - z;
+    } else {
+      part[(int64_t)kc * nrhs * stride + rhs * stride + F.voff + i] = z;
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_front_fwd_fin(PlanDev P, const int32_t* __restrict__ fr,
@@ -4222,9 +4233,11 @@ void launch_front_fwd(const PlanDev& P, const int32_t* fr, int nfr, int maxn, in
   }
   if (part) {
     const int pl = pull && P.front_pull ? 1 : 0;
+    const int direct = maxp <= FK ? 1 : 0;  // one chunk: no separate sum of the chunks
     k_front_fwd_part<<<dim3(cdiv(maxn, 64), cdiv(maxp, FK), nfr * nrhs), 256, 0, s>>>(P, fr, fpool, fvec, stride,
-                                                                                      nrhs, part, pl);
-    k_front_fwd_fin<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, fvec, xh, stride, nrhs, part, pl);
+                                                                                      nrhs, part, pl, direct, xh);
+    if (!direct)
+      k_front_fwd_fin<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, fvec, xh, stride, nrhs, part, pl);
     return;
   }
   k_front_fwd<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, fpool, fvec, xh, stride);
