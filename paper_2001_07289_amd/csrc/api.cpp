@@ -228,8 +228,8 @@ template <typename T>
 struct Numeric {
   T *G = nullptr, *Z = nullptr, *XG = nullptr, *Sc = nullptr, *Tm = nullptr, *Lam = nullptr,
     *PhiG = nullptr, *YG = nullptr, *Kc = nullptr;
-  T *W = nullptr, *W2 = nullptr, *tmp = nullptr, *sw = nullptr, *sw2 = nullptr;
-  int64_t wstride = 0, tmp_stride = 0, sw_stride = 0;
+  T *tmp = nullptr, *sw = nullptr, *sw2 = nullptr;
+  int64_t tmp_stride = 0, sw_stride = 0;
   // per-iteration
   T *vI = nullptr, *vR = nullptr, *q = nullptr, *gv = nullptr, *v2 = nullptr, *mu = nullptr, *bci = nullptr;
   T* lu = nullptr;  // Lambda u_c per subdomain (averages), from the coarse solve
@@ -423,10 +423,6 @@ void alloc_numeric(bddcso_precond* pc, hipStream_t s) {
   N.PhiG = m.alloc<T>(pl.pool_PhiG);
   N.YG = m.alloc<T>(pl.pool_YG);
   N.Kc = m.alloc<T>(pl.pool_Kc);
-  int max_plane = pc->P.max_plane;
-  N.wstride = (int64_t)max_plane * max_plane;
-  N.W = m.alloc<T>(N.wstride * pl.subs.size());
-  N.W2 = m.alloc<T>(N.wstride * pl.subs.size());
   N.tmp_stride = (int64_t)pl.max_block * std::max(pl.max_zcols, 1);
   N.tmp = m.alloc<T>(N.tmp_stride * pl.subs.size());
   int maxsw = std::max(pl.max_block, pl.max_na);
@@ -616,8 +612,9 @@ void precompute_refs(bddcso_precond* pc) {
         (st ? pc->refR_potrf : pc->refI_potrf)[k] += (double)B.size * bw * bw;
         if (k > 0 && B.cf_off >= 0) {
           const double lp = blk[k - 1].last_n, fn = B.first_n;
-          pc->sc_bytes[st][k] += es * (lp * lp + 2.0 * fn * fn) + 12.0 * 9.0 * fn;
-          pc->sc_flops[st][k] += 18.0 * (lp * fn + fn * fn);
+          // G_{k-1}'s last-plane block read, S_k's lower triangle read and written
+          pc->sc_bytes[st][k] += es * (lp * lp + fn * (fn + 1)) + 12.0 * 9.0 * fn;
+          pc->sc_flops[st][k] += 18.0 * (lp * fn + fn * (fn + 1) / 2);
         }
         if (!st || ncols == 0) continue;
         const int h = sidx < pc->zsplit ? 0 : 1;
@@ -677,7 +674,10 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   const double* rho = pc->rho;
   launch_fill_i32(pc->status, 1, 0, s);
   // on a second stream: the plane-coupling coefficients (first needed by the
-  // second plane's Schur update)
+  // second plane's Schur update).  Nothing else runs beside the K_rr chain:
+  // its sweeps are latency-bound but fill every compute unit and its Schur
+  // updates are bandwidth-bound, so streaming work beside it (or beside the
+  // coarse factorization later) slows it about as much as it takes alone.
   HIPCHK(hipEventRecord(pc->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_fork, 0));
   launch_coupling_coefs(P, g, rho, pc->cpl_coef, pc->s2);
@@ -689,14 +689,13 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   Kern<T>::block_assemble(P, g, rho, 0, N.G, pl.max_nbI, s);
   Kern<T>::block_assemble(P, g, rho, 1, N.G, pl.max_nbR, s);
   auto factor_chain = [&](int setR, hipStream_t ss) {
-    T* W = setR ? N.W : N.W2;
     T* sws = setR ? N.sw : N.sw2;
     auto& sw = setR ? pc->swR : pc->swI;
     for (int k = 0; k < (int)sw.size(); ++k) {
       if (k == 1 && setR) HIPCHK(hipStreamWaitEvent(ss, pc->ev_cpl, 0));  // the coupling coefficients
       if (k > 0) {
         if (pc->P_()) pc->prof.begin(6, ss);
-        Kern<T>::schur_couple(P, g, rho, setR, k, N.G, W, N.wstride, ss);
+        Kern<T>::schur_couple(P, setR, k, N.G, ss);
         if (pc->P_()) {
           pc->prof.end(6, pc->sc_flops[setR][k], pc->sc_bytes[setR][k], ss);
           pc->prof.ref(6, pc->sc_flops[setR][k], pc->sc_bytes[setR][k]);

@@ -104,8 +104,7 @@ struct Kern {
   // setup
   static void block_assemble(const PlanDev& P, const Geo& g, const double* rho, int setR, T* G, int max_nb,
                              hipStream_t s);
-  static void schur_couple(const PlanDev& P, const Geo& g, const double* rho, int setR, int k,
-                           T* G, T* W, int64_t wstride, hipStream_t s);
+  static void schur_couple(const PlanDev& P, int setR, int k, T* G, hipStream_t s);
   // reg_max: largest matrix of the register-resident sweep; lookahead: slab
   // look-ahead mode (0 by the update's size, 1 none, 2 always beside);
   // utile: tile rows of the slab trailing update (64 or 128); slab_w: slab

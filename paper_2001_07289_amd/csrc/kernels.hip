@@ -305,23 +305,38 @@ __global__ void k_delta(PlanDev P, const double* __restrict__ alpha, double* __r
   delta[e] = num / den;
 }
 
-// Plane-coupling coefficients A[i, j] between a block's boundary plane node i
-// and its neighbours j in the adjacent block, from rho (one thread per row).
-__global__ void k_coupling_coefs(PlanDev P, Geo g, const double* __restrict__ rho, double* __restrict__ coef) {
-  // one thread per (row, neighbour): the stores are contiguous
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= P.n_cpl * 9) return;
-  const int64_t row = e / 9;
-  const int t = (int)(e - row * 9);
-  double v = 0.0;
-  if (P.cpl_rank[e] >= 0) {
+// Plane-coupling coefficients A[i, j] between a block's boundary-plane node i
+// and its (up to 9) neighbours j in the adjacent plane, from rho.  One thread
+// per row decodes the node once; the rank table is read and the coefficients
+// are written through LDS, so that both move as contiguous runs.
+constexpr int CPL_ROWS = 256;
+
+__global__ __launch_bounds__(CPL_ROWS) void k_coupling_coefs(PlanDev P, Geo g, const double* __restrict__ rho,
+                                                             double* __restrict__ coef) {
+  __shared__ double cf[CPL_ROWS * 9];
+  __shared__ int rk[CPL_ROWS * 9];
+  const int64_t row0 = (int64_t)blockIdx.x * CPL_ROWS;
+  const int nr = (int)min((int64_t)CPL_ROWS, P.n_cpl - row0);
+  const int64_t e0 = row0 * 9;
+  for (int e = threadIdx.x; e < nr * 9; e += CPL_ROWS) rk[e] = P.cpl_rank[e0 + e];
+  __syncthreads();
+  if ((int)threadIdx.x < nr) {
+    const int64_t row = row0 + threadIdx.x;
     const SubDev S = P.subs[P.cpl_sub[row]];
+    const int dir = P.cpl_dir[row];
     int c[3], cn[3];
     loc_coords(S, P.cpl_loc[row], c);
-    plane_nbr(S, g.dim, c, P.cpl_dir[row], t, cn);
-    v = kloc(S, g, rho, P.khat, c, cn);
+    for (int t = 0; t < 9; ++t) {
+      double v = 0.0;
+      if (rk[threadIdx.x * 9 + t] >= 0) {
+        plane_nbr(S, g.dim, c, dir, t, cn);
+        v = kloc(S, g, rho, P.khat, c, cn);
+      }
+      cf[threadIdx.x * 9 + t] = v;
+    }
   }
-  coef[e] = v;
+  __syncthreads();
+  for (int e = threadIdx.x; e < nr * 9; e += CPL_ROWS) coef[e0 + e] = cf[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -333,6 +348,8 @@ __global__ void k_coupling_coefs(PlanDev P, Geo g, const double* __restrict__ rh
 // read only the lower triangle and write both, and the Schur coupling's
 // updates of the upper entries are overwritten by the sweep.
 
+typedef int i4v __attribute__((ext_vector_type(4)));
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_block_zero_lower(PlanDev P, int setR, T* __restrict__ G) {
   // one workgroup per block
@@ -341,11 +358,19 @@ __global__ __launch_bounds__(256) void k_block_zero_lower(PlanDev P, int setR, T
   if (k >= (setR ? S.nbR : S.nbI)) return;
   const BlockDev B = P.blocks[(setR ? S.bR_off : S.bI_off) + k];
   T* Gb = G + B.G_off;
-  // wave w clears the columns j = w, w + 4, ..., lanes down rows i >= j
+  // wave w clears the columns j = w, w + 4, ...: from the start of the
+  // 16-row group holding row j to the end of the column, in 16-byte stores
+  // of whole 64/128-byte lines.  Columns start on 16-entry boundaries and
+  // ld is a multiple of 16, so the stores stay inside the column; the
+  // entries above row j they also clear are upper-triangle entries or
+  // padding, which nothing reads before the sweep writes them.
+  constexpr int per = 16 / (int)sizeof(T);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int j = wave; j < B.size; j += 4) {
-    T* col = Gb + (int64_t)B.ld * j;
-    for (int i = j + lane; i < B.size; i += 64) col[i] = (T)0;
+    const int i0 = j & ~15;
+    i4v* col = reinterpret_cast<i4v*>(Gb + (int64_t)B.ld * j + i0);
+    const int nv = (B.size - i0 + per - 1) / per;
+    for (int q = lane; q < nv; q += 64) col[q] = i4v{0, 0, 0, 0};
   }
 }
 
@@ -385,8 +410,9 @@ __global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rh
 
 // Block Schur update S_k = A_kk - A_{k,k-1} G_{k-1} A_{k-1,k} of the
 // block-tridiagonal factorization, restricted to the first-plane rows and
-// columns of block k (the only ones the plane coupling reaches).  One
-// workgroup per (subdomain, chunk of SC_COLS columns j'):
+// columns of block k (the only ones the plane coupling reaches), on and
+// below the diagonal.  One workgroup per (subdomain, chunk of SC_COLS
+// columns j'):
 //   W[l', j'] = sum_m Gs[l', m] A[m, j']  over the last plane of block k-1,
 //   S_k[i', j'] += sum_l A[i', l] W[l, j'],
 // with Gs = -G_{k-1} the swept block, so the sum adds -A G A.  W stays in LDS.
@@ -414,41 +440,103 @@ __global__ __launch_bounds__(256) void k_schur_couple(PlanDev P, int setR, int k
   const int c0 = chunk * SC_COLS;
   if (c0 >= B.first_n) return;
   const int cols = min(SC_COLS, B.first_n - c0);
-  // coupling rows of this chunk's columns (first-plane rows of block k)
+  __shared__ int mlo, mhi;
+  if constexpr (sizeof(T) == 4) {
+    if (threadIdx.x == 0) {
+      mlo = INT32_MAX;
+      mhi = -1;
+    }
+    __syncthreads();
+  }
+  // coupling rows of this chunk's columns (first-plane rows of block k), and
+  // (FP32) the range of G_{k-1} columns their taps reach
   for (int e = threadIdx.x; e < SC_COLS * 9; e += blockDim.x) {
     const int c = e / 9, t = e % 9;
     const int64_t row = B.cf_off + c0 + c;
     const int m = c < cols ? P.cpl_rank[row * 9 + t] : -1;
     crk[c][t] = m >= 0 ? m - Bp.start : -1;
     ccf[c][t] = m >= 0 ? P.cpl_coef[row * 9 + t] : 0.0;
+    if (sizeof(T) == 4 && m >= 0) {
+      atomicMin(&mlo, m - Bp.start);
+      atomicMax(&mhi, m - Bp.start);
+    }
   }
   __syncthreads();
-  // W[l'][c] = sum_t Gs[l', m_t] a_t, four columns' gathers in flight at a time
   const T* Gr = G + Bp.G_off + (Bp.size - Bp.last_n);
-  for (int lp = threadIdx.x; lp < Bp.last_n; lp += blockDim.x) {
-    for (int cb = 0; cb < SC_COLS; cb += 4) {
-      T gv[4][9];
+  if constexpr (sizeof(T) == 4) {
+    // FP32 blocks: W = Gs[:, lo..hi] A_c on MFMA, A_c the chunk's coupling
+    // columns over the taps' range (nine nonzeros per column, formed in the
+    // B operand from the tap table), so each element of Gs in the range is
+    // loaded once, 16 consecutive rows per load (measured: the gathers
+    // below are the slower form in FP32, the faster one in FP64)
+    typedef typename Mfma<T>::acc_t acc_t;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4, rr = lane & 15;
+    const int lo = mlo, hi = mhi;
+    const int ks = hi >= lo ? (hi - lo + 4) >> 2 : 0;
+    int tm[9];
+    T tc[9];
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc)
+    for (int t = 0; t < 9; ++t) {
+      tm[t] = crk[rr][t];
+      tc[t] = (T)ccf[rr][t];
+    }
+    const int nrt = (Bp.last_n + 15) >> 4;
+    for (int rt = wave; rt < nrt; rt += 4) {
+      const int row = rt * 16 + rr;
+      acc_t acc = acc_t{0, 0, 0, 0};
+      for (int s0 = 0; s0 < ks; s0 += 8) {
+        T av[8];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          const int m = crk[cb + cc][t];
-          gv[cc][t] = m >= 0 ? Gr[lp + (int64_t)Bp.ld * m] : (T)0;
+        for (int u = 0; u < 8; ++u) {
+          const int m = lo + 4 * (s0 + u) + kq;
+          av[u] = (s0 + u < ks && row < Bp.last_n && m <= hi) ? Gr[row + (int64_t)Bp.ld * m] : (T)0;
         }
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        double acc = 0.0;
+        for (int u = 0; u < 8; ++u) {
+          if (s0 + u >= ks) break;
+          const int m = lo + 4 * (s0 + u) + kq;
+          T b = (T)0;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc += (double)gv[cc][t] * ccf[cb + cc][t];
-        W[lp][cb + cc] = (T)acc;
+          for (int t = 0; t < 9; ++t) b = tm[t] == m ? tc[t] : b;
+          acc = Mfma<T>::mac(av[u], b, acc);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int lr = rt * 16 + Mfma<T>::row(kq, r);
+        if (lr < Bp.last_n) W[lr][rr] = acc[r];
+      }
+    }
+  } else {
+    // FP64 blocks: W[l'][c] = sum_t Gs[l', m_t] a_t, four columns' gathers
+    // in flight at a time
+    for (int lp = threadIdx.x; lp < Bp.last_n; lp += blockDim.x) {
+      for (int cb = 0; cb < SC_COLS; cb += 4) {
+        T gv[4][9];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+          for (int t = 0; t < 9; ++t) {
+            const int m = crk[cb + cc][t];
+            gv[cc][t] = m >= 0 ? Gr[lp + (int64_t)Bp.ld * m] : (T)0;
+          }
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < 9; ++t) acc += (double)gv[cc][t] * ccf[cb + cc][t];
+          W[lp][cb + cc] = (T)acc;
+        }
       }
     }
   }
   __syncthreads();
-  // S_k[i'][c] += sum_t A[i', l_t] W[l_t][c], all of the row's columns at once
+  // S_k[i'][c] += sum_t A[i', l_t] W[l_t][c], all of the row's columns at
+  // once, on and below the diagonal only (the sweep of block k reads only
+  // its lower triangle): rows i' >= c0 + c
   const int base = Bp.start + Bp.size - Bp.last_n;
   T* Gk = G + B.G_off + (int64_t)B.ld * c0;
-  for (int ip = threadIdx.x; ip < B.first_n; ip += blockDim.x) {
+  for (int ip = c0 + threadIdx.x; ip < B.first_n; ip += blockDim.x) {
     const int64_t row = B.cf_off + ip;
     double a[9];
     int l[9];
@@ -458,15 +546,16 @@ __global__ __launch_bounds__(256) void k_schur_couple(PlanDev P, int setR, int k
       a[t] = r >= 0 ? P.cpl_coef[row * 9 + t] : 0.0;
       l[t] = r >= 0 ? r - base : 0;
     }
+    const int cl = min(cols, ip - c0 + 1);  // columns c < cl lie on or below the diagonal
     T old[SC_COLS];
 #pragma unroll
-    for (int c = 0; c < SC_COLS; ++c) old[c] = c < cols ? Gk[ip + (int64_t)B.ld * c] : (T)0;
+    for (int c = 0; c < SC_COLS; ++c) old[c] = c < cl ? Gk[ip + (int64_t)B.ld * c] : (T)0;
 #pragma unroll
     for (int c = 0; c < SC_COLS; ++c) {
       double acc = 0.0;
 #pragma unroll
       for (int t = 0; t < 9; ++t) acc += a[t] * (double)W[l[t]][c];
-      if (c < cols) Gk[ip + (int64_t)B.ld * c] = old[c] + (T)acc;
+      if (c < cl) Gk[ip + (int64_t)B.ld * c] = old[c] + (T)acc;
     }
   }
 }
@@ -3757,7 +3846,7 @@ void launch_delta(const PlanDev& P, const double* alpha, double* delta, hipStrea
 }
 void launch_coupling_coefs(const PlanDev& P, const Geo& g, const double* rho, double* coef, hipStream_t s) {
   if (P.n_cpl == 0) return;
-  k_coupling_coefs<<<cdiv(P.n_cpl * 9, 256), 256, 0, s>>>(P, g, rho, coef);
+  k_coupling_coefs<<<cdiv(P.n_cpl, CPL_ROWS), CPL_ROWS, 0, s>>>(P, g, rho, coef);
 }
 
 template <typename T>
@@ -3770,14 +3859,10 @@ void Kern<T>::block_assemble(const PlanDev& P, const Geo& g, const double* rho, 
 }
 
 template <typename T>
-void Kern<T>::schur_couple(const PlanDev& P, const Geo& g, const double* rho, int setR, int k, T* G,
-                           T* W, int64_t wstride, hipStream_t s) {
-  (void)g;
-  (void)rho;
-  (void)W;
-  (void)wstride;
+void Kern<T>::schur_couple(const PlanDev& P, int setR, int k, T* G, hipStream_t s) {
   const int mp = P.max_plane;
-  const size_t sm = (size_t)hmax(mp, 1) * (SC_COLS + 1) * sizeof(T);
+  if (P.n_sub <= 0 || mp <= 0) return;
+  const size_t sm = (size_t)mp * (SC_COLS + 1) * sizeof(T);
   const int nch = (int)cdiv(mp, SC_COLS);
   const unsigned nblk = (unsigned)(((int64_t)nch * P.n_sub + 7) / 8 * 8);
   k_schur_couple<T><<<nblk, 256, sm, s>>>(P, setR, k, G, nch);
