@@ -248,6 +248,7 @@ struct bddcso_precond {
   Numeric<double> nd;
   Numeric<float> nf;
   double *rho = nullptr, *alpha = nullptr, *delta = nullptr, *khat = nullptr, *cpl_coef = nullptr;
+  double* ipl_coef = nullptr;  // in-plane A_kk entries of the first-plane coupling rows
   double* vcoef = nullptr;    // stencil rows of the primal vertices (27 per vertex)
   int32_t* vcode = nullptr;
   int max_nv = 0;
@@ -680,7 +681,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   // coarse factorization later) slows it about as much as it takes alone.
   HIPCHK(hipEventRecord(pc->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_fork, 0));
-  launch_coupling_coefs(P, g, rho, pc->cpl_coef, pc->s2);
+  launch_coupling_coefs(P, g, rho, pc->cpl_coef, pc->ipl_coef, pc->s2);
   HIPCHK(hipEventRecord(pc->ev_cpl, pc->s2));
   launch_alpha(P, pc->prob->c.n_ss, rho, pc->opt.weighting, pc->alpha, s);
   launch_kig_fill(P, g, rho, s);
@@ -1028,6 +1029,9 @@ void layout(bddcso_precond* pc, hipStream_t s) {
   P.n_cpl = (int64_t)pl.cpl_sub.size();
   pc->cpl_coef = m.alloc<double>(P.n_cpl * 9);
   P.cpl_coef = pc->cpl_coef;
+  P.ipl_rank = m.upload(pl.ipl_rank, s);
+  pc->ipl_coef = m.alloc<double>(P.n_cpl * 5);
+  P.ipl_coef = pc->ipl_coef;
   std::vector<double> kh(p->khat, p->khat + 64);
   pc->khat = m.upload(kh, s);
   P.khat = pc->khat;

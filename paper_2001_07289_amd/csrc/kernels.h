@@ -75,6 +75,8 @@ struct PlanDev {
   const double* khat;  // 8x8 unit-coefficient element matrix (2D replicated over the z bit)
   const int32_t *cpl_rank, *cpl_sub, *cpl_loc, *cpl_dir;
   const double* cpl_coef;  // 9 coefficients per coupling row (filled at setup)
+  const int32_t* ipl_rank;  // 5 in-plane lower stencil ranks per coupling row (block-local, -1: none)
+  const double* ipl_coef;   // their A_kk entries (filled at setup)
   int64_t n_cpl;
   int n_sub;
   int64_t tot_I, tot_r, tot_g, tot_c, tot_a, n_gam, n_coarse;
@@ -97,7 +99,8 @@ void launch_q1_apply(const Geo& g, const double* khat, const double* rho, const 
 void launch_alpha(const PlanDev& P, int n_ss, const double* rho, int weighting, double* alpha,
                   hipStream_t s);
 void launch_delta(const PlanDev& P, const double* alpha, double* delta, hipStream_t s);
-void launch_coupling_coefs(const PlanDev& P, const Geo& g, const double* rho, double* coef, hipStream_t s);
+void launch_coupling_coefs(const PlanDev& P, const Geo& g, const double* rho, double* coef, double* icoef,
+                           hipStream_t s);
 
 template <typename T>
 struct Kern {

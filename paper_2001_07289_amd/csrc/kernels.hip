@@ -306,13 +306,15 @@ __global__ void k_delta(PlanDev P, const double* __restrict__ alpha, double* __r
 }
 
 // Plane-coupling coefficients A[i, j] between a block's boundary-plane node i
-// and its (up to 9) neighbours j in the adjacent plane, from rho.  One thread
-// per row decodes the node once; the rank table is read and the coefficients
-// are written through LDS, so that both move as contiguous runs.
+// and its (up to 9) neighbours j in the adjacent plane, from rho, and for a
+// first-plane row also the entries A[i, j] of its in-plane neighbours of
+// rank at most its own (the part of A_kk the Schur coupling adds).  One
+// thread per row decodes the node once; the rank tables are read and the
+// coefficients written through LDS, so that they move as contiguous runs.
 constexpr int CPL_ROWS = 256;
 
 __global__ __launch_bounds__(CPL_ROWS) void k_coupling_coefs(PlanDev P, Geo g, const double* __restrict__ rho,
-                                                             double* __restrict__ coef) {
+                                                             double* __restrict__ coef, double* __restrict__ icoef) {
   __shared__ double cf[CPL_ROWS * 9];
   __shared__ int rk[CPL_ROWS * 9];
   const int64_t row0 = (int64_t)blockIdx.x * CPL_ROWS;
@@ -337,6 +339,29 @@ __global__ __launch_bounds__(CPL_ROWS) void k_coupling_coefs(PlanDev P, Geo g, c
   }
   __syncthreads();
   for (int e = threadIdx.x; e < nr * 9; e += CPL_ROWS) coef[e0 + e] = cf[e];
+  // the in-plane entries, through the same LDS
+  const int64_t f0 = row0 * 5;
+  __syncthreads();
+  for (int e = threadIdx.x; e < nr * 5; e += CPL_ROWS) rk[e] = P.ipl_rank[f0 + e];
+  __syncthreads();
+  if ((int)threadIdx.x < nr) {
+    const int64_t row = row0 + threadIdx.x;
+    const SubDev S = P.subs[P.cpl_sub[row]];
+    int c[3], cn[3];
+    loc_coords(S, P.cpl_loc[row], c);
+    for (int t = 0; t < 5; ++t) {
+      double v = 0.0;
+      if (rk[threadIdx.x * 5 + t] >= 0) {
+        cn[0] = c[0] + kInPlaneLower[t][0];
+        cn[1] = c[1] + (g.dim == 3 ? kInPlaneLower[t][1] : 0);
+        cn[2] = c[2];
+        v = kloc(S, g, rho, P.khat, c, cn);
+      }
+      cf[threadIdx.x * 5 + t] = v;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nr * 5; e += CPL_ROWS) icoef[f0 + e] = cf[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -345,8 +370,9 @@ __global__ __launch_bounds__(CPL_ROWS) void k_coupling_coefs(PlanDev P, Geo g, c
 // Only the lower triangles are formed: k_block_zero_lower clears them (a
 // wave per column, lanes along i), then k_block_assemble writes the stencil
 // entries with j <= i.  The upper triangles are left as they are: the sweeps
-// read only the lower triangle and write both, and the Schur coupling's
-// updates of the upper entries are overwritten by the sweep.
+// read only the lower triangle and write both.  The first-plane corner of a
+// block coupled to the previous one is left out of both: the Schur coupling
+// writes its whole lower triangle, stencil entries included.
 
 typedef int i4v __attribute__((ext_vector_type(4)));
 
@@ -364,10 +390,15 @@ __global__ __launch_bounds__(256) void k_block_zero_lower(PlanDev P, int setR, T
   // ld is a multiple of 16, so the stores stay inside the column; the
   // entries above row j they also clear are upper-triangle entries or
   // padding, which nothing reads before the sweep writes them.
+  // The first-plane corner of a block coupled to the previous one is written
+  // whole (lower triangle) by the Schur coupling, A_kk included: skipped.
   constexpr int per = 16 / (int)sizeof(T);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int fc = B.cf_off >= 0 ? B.first_n : 0;
   for (int j = wave; j < B.size; j += 4) {
-    const int i0 = j & ~15;
+    const int start = j < fc ? fc : j;
+    if (start >= B.size) continue;
+    const int i0 = start & ~15;
     i4v* col = reinterpret_cast<i4v*>(Gb + (int64_t)B.ld * j + i0);
     const int nv = (B.size - i0 + per - 1) / per;
     for (int q = lane; q < nv; q += 64) col[q] = i4v{0, 0, 0, 0};
@@ -393,6 +424,9 @@ __global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rh
   while (k < nb && !(c[pa] >= blk[k].plane_lo && c[pa] < blk[k].plane_hi)) ++k;
   if (k == nb) return;
   const BlockDev B = blk[k];
+  // a first-plane node of a coupled block: its neighbours of lower rank in
+  // the block lie in the same plane, the corner the Schur coupling writes
+  if (B.cf_off >= 0 && i - B.start < B.first_n) return;
   const int zr = g.dim == 3 ? 1 : 0;
   for (int dz = -zr; dz <= zr; ++dz)
     for (int dy = -1; dy <= 1; ++dy)
@@ -403,6 +437,8 @@ __global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rh
         int j = ls[ln];
         if (j < 0) continue;
         if (cn[pa] < B.plane_lo || cn[pa] >= B.plane_hi || j > i) continue;
+        // the first-plane corner of a coupled block: the Schur coupling's
+        if (B.cf_off >= 0 && i - B.start < B.first_n && j - B.start < B.first_n) continue;
         G[B.G_off + (int64_t)(i - B.start) + (int64_t)B.ld * (j - B.start)] =
             (T)kloc(S, g, rho, P.khat, c, cn);
       }
@@ -411,7 +447,8 @@ __global__ void k_block_assemble(PlanDev P, Geo g, const double* __restrict__ rh
 // Block Schur update S_k = A_kk - A_{k,k-1} G_{k-1} A_{k-1,k} of the
 // block-tridiagonal factorization, restricted to the first-plane rows and
 // columns of block k (the only ones the plane coupling reaches), on and
-// below the diagonal.  One workgroup per (subdomain, chunk of SC_COLS
+// below the diagonal.  This corner is not assembled in the matrix: A_kk's
+// entries there (the in-plane stencil) come from the coupling table.  One workgroup per (subdomain, chunk of SC_COLS
 // columns j'):
 //   W[l', j'] = sum_m Gs[l', m] A[m, j']  over the last plane of block k-1,
 //   S_k[i', j'] += sum_l A[i', l] W[l, j'],
@@ -547,9 +584,23 @@ __global__ __launch_bounds__(256) void k_schur_couple(PlanDev P, int setR, int k
       l[t] = r >= 0 ? r - base : 0;
     }
     const int cl = min(cols, ip - c0 + 1);  // columns c < cl lie on or below the diagonal
+    // A_kk on this row within the chunk: its in-plane stencil entries of
+    // rank at most its own (the corner is not assembled in the matrix)
+    int jr[5];
+    T jv[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      jr[q] = P.ipl_rank[row * 5 + q];
+      jv[q] = (T)P.ipl_coef[row * 5 + q];
+    }
     T old[SC_COLS];
 #pragma unroll
-    for (int c = 0; c < SC_COLS; ++c) old[c] = c < cl ? Gk[ip + (int64_t)B.ld * c] : (T)0;
+    for (int c = 0; c < SC_COLS; ++c) {
+      T v = (T)0;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) v = jr[q] == c0 + c ? jv[q] : v;
+      old[c] = v;
+    }
 #pragma unroll
     for (int c = 0; c < SC_COLS; ++c) {
       double acc = 0.0;
@@ -3844,9 +3895,10 @@ void launch_delta(const PlanDev& P, const double* alpha, double* delta, hipStrea
   if (P.tot_g == 0) return;
   k_delta<<<cdiv(P.tot_g, 256), 256, 0, s>>>(P, alpha, delta);
 }
-void launch_coupling_coefs(const PlanDev& P, const Geo& g, const double* rho, double* coef, hipStream_t s) {
+void launch_coupling_coefs(const PlanDev& P, const Geo& g, const double* rho, double* coef, double* icoef,
+                           hipStream_t s) {
   if (P.n_cpl == 0) return;
-  k_coupling_coefs<<<cdiv(P.n_cpl, CPL_ROWS), CPL_ROWS, 0, s>>>(P, g, rho, coef);
+  k_coupling_coefs<<<cdiv(P.n_cpl, CPL_ROWS), CPL_ROWS, 0, s>>>(P, g, rho, coef, icoef);
 }
 
 template <typename T>

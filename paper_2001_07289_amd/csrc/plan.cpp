@@ -690,6 +690,19 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
           plan.cpl_sub.push_back(s);
           plan.cpl_loc.push_back(l);
           plan.cpl_dir.push_back(dir);
+          for (int t = 0; t < 5; ++t) {
+            int32_t jl = -1;
+            if (first && (dim == 3 || t < 2)) {
+              int cn[3] = {c[0] + kInPlaneLower[t][0], c[1] + (dim == 3 ? kInPlaneLower[t][1] : 0), c[2]};
+              bool ok = true;
+              for (int a = 0; a < 3; ++a) ok = ok && cn[a] >= 0 && cn[a] < S.m[a];
+              if (ok) {
+                const int32_t rk = ls[cn[0] + S.m[0] * (cn[1] + S.m[1] * cn[2])];
+                if (rk >= 0) jl = rk - B.start;
+              }
+            }
+            plan.ipl_rank.push_back(jl);
+          }
           for (int t = 0; t < 9; ++t) {
             int cn[3] = {c[0], c[1], c[2]};
             bool ok = t < nt;

@@ -84,6 +84,11 @@ struct Plan {
   // first or last plane) the set ranks of its 9 (3 in 2D) neighbours in the
   // adjacent plane, -1 where absent
   std::vector<int32_t> cpl_rank, cpl_sub, cpl_loc, cpl_dir;
+  // per coupling row of a first plane (dir -1), the block-local ranks of its
+  // in-plane stencil neighbours of rank at most its own (itself, then x-1;
+  // in 3D also (x-1, y-1), (x, y-1), (x+1, y-1)), -1 where absent or on a
+  // last-plane row: the entries of A_kk that the Schur coupling adds itself
+  std::vector<int32_t> ipl_rank;
 
   std::vector<int32_t> gam_eptr, gam_ent;     // Gamma index -> Gamma entries
   std::vector<int32_t> crs_eptr, crs_ent;     // coarse id -> local coarse entries

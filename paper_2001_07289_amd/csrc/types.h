@@ -4,6 +4,11 @@
 
 namespace bddcso {
 
+// In-plane offsets (x, y) of a node's stencil neighbours of rank at most its
+// own within a block's plane (ranks run x fastest, then y): itself, x-1, and
+// the three of row y-1.  In 2D (planes are lines in x) only the first two.
+constexpr int kInPlaneLower[5][2] = {{0, 0}, {-1, 0}, {-1, -1}, {0, -1}, {1, -1}};
+
 // One subdomain: an axis-aligned box of elements.  Local nodes are the free
 // grid nodes of the closed box, numbered x fastest.  Sets: I (interior, not
 // on Gamma), r (every local node except the primal vertices, Section 3's
