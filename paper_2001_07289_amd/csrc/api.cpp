@@ -613,8 +613,9 @@ void precompute_refs(bddcso_precond* pc) {
         (st ? pc->refR_potrf : pc->refI_potrf)[k] += (double)B.size * bw * bw;
         if (k > 0 && B.cf_off >= 0) {
           const double lp = blk[k - 1].last_n, fn = B.first_n;
-          // G_{k-1}'s last-plane block read, S_k's lower triangle read and written
-          pc->sc_bytes[st][k] += es * (lp * lp + fn * (fn + 1)) + 12.0 * 9.0 * fn;
+          // G_{k-1}'s last-plane block read, S_k's lower triangle written; the
+          // coupling and in-plane stencil tables (9 and 5 ranks and coefficients per row)
+          pc->sc_bytes[st][k] += es * (lp * lp + fn * (fn + 1) / 2) + 12.0 * 14.0 * fn;
           pc->sc_flops[st][k] += 18.0 * (lp * fn + fn * (fn + 1) / 2);
         }
         if (!st || ncols == 0) continue;
