@@ -2243,33 +2243,38 @@ __global__ void k_vertex_stencil(PlanDev P, Geo g, const double* __restrict__ rh
   vcoef[out] = kloc(S, g, rho, P.khat, cv, cn);
 }
 
-// Every entry (c, c2) of a chunk of columns from its row's equation.  The
-// chunk's columns of Phi (all selected rows) and the subdomain's vertex
-// stencils are staged in LDS with coalesced loads; a vertex row's entry is
-// then a 27-term sum over LDS, an average row's entry a copy of -Lambda.
+// K_c's vertex rows in its vertex columns, from the rows' equations: one
+// workgroup per (chunk of vertex columns, subdomain).  The chunk's columns
+// of Phi (all selected rows) and the subdomain's vertex stencils are staged
+// in LDS with coalesced loads; an entry is then a 27-term sum over LDS.  The
+// entries in an average row or column are -Lambda (taken by
+// k_kc_symmetrize), so only the vertex columns of Phi are staged.
 template <typename T>
-__global__ __launch_bounds__(256) void k_kc_identity(PlanDev P, const T* __restrict__ PhiR, const T* __restrict__ Lam,
+__global__ __launch_bounds__(256) void k_kc_identity(PlanDev P, const T* __restrict__ PhiR,
                                                      const double* __restrict__ vcoef,
                                                      const int32_t* __restrict__ vcode, T* __restrict__ Kc,
                                                      int kc_cols, int stage_stencils) {
   extern __shared__ double phs[];  // [kc_cols][n_s] Phi, then [n_v][27] coefficients, then [n_v][27] codes
+  __shared__ int vcol[8];          // the chunk's columns (local coarse indices of its vertices)
   const SubDev S = P.subs[blockIdx.y];
-  const int c0 = blockIdx.x * kc_cols;
-  if (c0 >= S.n_c) return;
-  const int nc = min(kc_cols, S.n_c - c0), ns = S.n_s, nv27 = stage_stencils ? S.n_v * 27 : 0;
+  const int v0 = blockIdx.x * kc_cols;
+  if (v0 >= S.n_v) return;
+  const int nc = min(kc_cols, S.n_v - v0), ns = S.n_s, nv27 = stage_stencils ? S.n_v * 27 : 0;
   double* lcoef = phs + (int64_t)kc_cols * P.max_ns;
   int32_t* lcode = reinterpret_cast<int32_t*>(lcoef + (int64_t)27 * P.max_nv);
   const double* scoef = stage_stencils ? lcoef : vcoef + S.v_off * 27;
   const int32_t* scode = stage_stencils ? lcode : vcode + S.v_off * 27;
-  // the chunk's columns are contiguous (ld n_s): a straight copy, 8 loads in flight per thread
-  const T* src = PhiR + S.PhiG_off + (int64_t)ns * c0;
+  if ((int)threadIdx.x < nc) vcol[threadIdx.x] = P.v_c[S.v_off + v0 + threadIdx.x];
+  __syncthreads();
+  // each column is contiguous (ld n_s): 8 loads in flight per thread
+  const T* src = PhiR + S.PhiG_off;
   const int tot = ns * nc;
   for (int b0 = 0; b0 < tot; b0 += 8 * 256) {
     T r[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int i = b0 + threadIdx.x + 256 * u;
-      r[u] = i < tot ? src[i] : (T)0;
+      r[u] = i < tot ? src[(int64_t)ns * vcol[i / ns] + i % ns] : (T)0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -2296,10 +2301,9 @@ __global__ __launch_bounds__(256) void k_kc_identity(PlanDev P, const T* __restr
     }
   }
   __syncthreads();
-  // vertex rows: thread (v, j)
-  constexpr int KCM = 8;  // largest chunk
+  // thread (v, j): row v_c[v], column vcol[j]
   for (int idx = threadIdx.x; idx < S.n_v * nc; idx += blockDim.x) {
-    const int v = idx % S.n_v, j = idx / S.n_v, c2 = c0 + j;
+    const int v = idx % S.n_v, j = idx / S.n_v, c2 = vcol[j];
     double acc = 0.0;
     for (int t = 0; t < 27; ++t) {
       const int code = scode[v * 27 + t];
@@ -2309,24 +2313,18 @@ __global__ __launch_bounds__(256) void k_kc_identity(PlanDev P, const T* __restr
     }
     Kc[S.Kc_off + P.v_c[S.v_off + v] + (int64_t)S.n_c * c2] = (T)acc;
   }
-  // average rows: one thread per row, the chunk's Lambda loads in flight together
-  for (int c = threadIdx.x; c < S.n_c; c += blockDim.x) {
-    const int kind = P.c_kind[S.c_off + c];
-    if (kind >= 0) continue;
-    T lv[KCM];
-#pragma unroll
-    for (int j = 0; j < KCM; ++j) lv[j] = j < nc ? Lam[S.T_off + (-kind - 1) + (int64_t)S.n_a * (c0 + j)] : (T)0;
-#pragma unroll
-    for (int j = 0; j < KCM; ++j)
-      if (j < nc) Kc[S.Kc_off + c + (int64_t)S.n_c * (c0 + j)] = (T)(-(double)lv[j]);
-  }
 }
 
-// Kc <- (Kc + Kc^T) / 2 in place, by pairs of 32 x 32 tiles (ti >= tj)
-// staged in LDS, so reads and writes run along columns.
+// K_c <- its symmetric part, by pairs of 32 x 32 tiles (ti >= tj) staged in
+// LDS, so reads and writes run along columns.  Each one-sided entry (i, j)
+// (row i's equation) comes from where it was formed: -Lambda on an average
+// row (K_c = -Lambda there); on a vertex row, the transposed entry in an
+// average column (K_c is symmetric) and the stencil sum of k_kc_identity in
+// a vertex column.
 template <typename T>
-__global__ void k_kc_symmetrize(PlanDev P, T* __restrict__ Kc) {
+__global__ void k_kc_symmetrize(PlanDev P, const T* __restrict__ Lam, T* __restrict__ Kc) {
   __shared__ double ta[32][33], tb[32][33];
+  __shared__ int ki[32], kj[32];
   const SubDev S = P.subs[blockIdx.y];
   const int n = S.n_c, nt = (n + 31) / 32;
   int lin = blockIdx.x, ti = 0;
@@ -2334,12 +2332,25 @@ __global__ void k_kc_symmetrize(PlanDev P, T* __restrict__ Kc) {
   while (lin > ti) lin -= ++ti;
   const int tj = lin;
   T* K = Kc + S.Kc_off;
+  const T* L = Lam + S.T_off;
+  if (threadIdx.x < 32) {
+    const int i = ti * 32 + threadIdx.x, j = tj * 32 + threadIdx.x;
+    ki[threadIdx.x] = i < n ? P.c_kind[S.c_off + i] : 0;
+    kj[threadIdx.x] = j < n ? P.c_kind[S.c_off + j] : 0;
+  }
+  __syncthreads();
+  // one-sided entry (i, j) with kinds a (row) and b (column)
+  auto side = [&](int i, int j, int a, int b) -> double {
+    if (a < 0) return -(double)L[(-a - 1) + (int64_t)S.n_a * j];
+    if (b < 0) return -(double)L[(-b - 1) + (int64_t)S.n_a * i];
+    return (double)K[i + (int64_t)n * j];
+  };
   for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
     const int r = e % 32, q = e / 32;
     const int i = ti * 32 + r, j = tj * 32 + q;        // tile (ti, tj)
-    ta[r][q] = (i < n && j < n) ? (double)K[i + (int64_t)n * j] : 0.0;
+    ta[r][q] = (i < n && j < n) ? side(i, j, ki[r], kj[q]) : 0.0;
     const int i2 = tj * 32 + r, j2 = ti * 32 + q;      // tile (tj, ti)
-    tb[r][q] = (i2 < n && j2 < n) ? (double)K[i2 + (int64_t)n * j2] : 0.0;
+    tb[r][q] = (i2 < n && j2 < n) ? side(i2, j2, kj[r], ki[q]) : 0.0;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
@@ -4167,10 +4178,11 @@ void Kern<T>::kc_identity(const PlanDev& P, const Geo& g, const double* rho, con
   if (max_nv > 0)
     k_vertex_stencil<<<dim3(cdiv((int64_t)max_nv * 27, 256), P.n_sub), 256, 0, s>>>(P, g, rho, nullptr, vcoef, vcode);
   const int cols = kc_cols(P);
-  k_kc_identity<T><<<dim3(cdiv(P.max_nc, cols), P.n_sub), 256, (size_t)kc_lds_bytes(P), s>>>(
-      P, PhiR, Lam, vcoef, vcode, Kc, cols, kc_stage_stencils(P) ? 1 : 0);
+  if (max_nv > 0)
+    k_kc_identity<T><<<dim3(cdiv(max_nv, cols), P.n_sub), 256, (size_t)kc_lds_bytes(P), s>>>(
+        P, PhiR, vcoef, vcode, Kc, cols, kc_stage_stencils(P) ? 1 : 0);
   const int nt = cdiv(P.max_nc, 32);
-  k_kc_symmetrize<T><<<dim3(nt * (nt + 1) / 2, P.n_sub), 256, 0, s>>>(P, Kc);
+  k_kc_symmetrize<T><<<dim3(nt * (nt + 1) / 2, P.n_sub), 256, 0, s>>>(P, Lam, Kc);
 }
 
 template <typename T>
