@@ -965,10 +965,15 @@ void layout(bddcso_precond* pc, hipStream_t s) {
   P.z_col = m.upload(pl.z_col, s);
   P.kig_ptr = m.upload(pl.kig_ptr, s);
   P.kig_t = m.upload(pl.kig_t, s);
+  P.kig_own = m.upload(pl.kig_own, s);
+  P.kig_sub = m.upload(pl.kig_sub, s);
+  P.n_kig = (int64_t)pl.kig_t.size();
   P.kig_col = m.alloc<int32_t>((int64_t)pl.kig_t.size());
   P.kig_val = m.alloc<double>((int64_t)pl.kig_t.size());
   P.kgi_ptr = m.upload(pl.kgi_ptr, s);
   P.kgi_t = m.upload(pl.kgi_t, s);
+  P.kgi_own = m.upload(pl.kgi_own, s);
+  P.n_kgi = (int64_t)pl.kgi_t.size();
   P.kgi_col = m.alloc<int32_t>((int64_t)pl.kgi_t.size());
   P.kgi_val = m.alloc<double>((int64_t)pl.kgi_t.size());
   P.r_loc = m.upload(pl.r_loc, s);

@@ -51,10 +51,14 @@ struct PlanDev {
   const int32_t* z_col;     // per local coarse entry (c_off order: averages, then vertices): its column of [X | Y']
   const int32_t* kig_ptr;   // per interior node (global I order) into the K_{I Gamma} entries
   const int8_t* kig_t;      // neighbour code of each entry
+  const int32_t *kig_own, *kig_sub;  // interior node (global I order) and subdomain of each entry
+  int64_t n_kig;
   int32_t* kig_col;         // free index of the neighbour (filled by the setup)
   double* kig_val;          // K_{I Gamma} entry (filled by the setup from rho)
   const int32_t* kgi_ptr;   // per Gamma entry (global order) into the K_{Gamma I} entries
   const int8_t* kgi_t;      // neighbour code of each entry
+  const int32_t* kgi_own;   // Gamma entry (global order) of each entry
+  int64_t n_kgi;
   int32_t* kgi_col;         // interior index of the neighbour in its subdomain (filled by the setup)
   double* kgi_val;          // K_{Gamma I} entry (filled by the setup from rho)
   const int32_t *g_loc, *g_gam, *g_r, *g_v, *g_sub;

@@ -2916,23 +2916,20 @@ __global__ __launch_bounds__(MR_THREADS) void k_block_solve_mr(PlanDev P, int se
   }
 }
 
-// The K_{Gamma I} entries of each Gamma entry: for each interior neighbour
-// listed by the plan, its interior index and the stiffness entry (from rho).
+// The K_{Gamma I} entries (the interior neighbours the plan lists for each
+// Gamma entry): the neighbour's interior index and the stiffness entry (from
+// rho).  One thread per entry.
 __global__ void k_kgi_fill(PlanDev P, Geo g, const double* __restrict__ rho) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= S.n_g) return;
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= P.n_kgi) return;
+  const int64_t ge = P.kgi_own[k];
+  const SubDev S = P.subs[P.g_sub[ge]];
   int c[3];
-  loc_coords(S, P.g_loc[S.g_off + e], c);
-  const int32_t* li = P.loc_I + S.loc_off;
-  const int64_t ge = S.g_off + e;
-  for (int k = P.kgi_ptr[ge]; k < P.kgi_ptr[ge + 1]; ++k) {
-    const int t = P.kgi_t[k];
-    const int cn[3] = {c[0] + t % 3 - 1, c[1] + (t / 3) % 3 - 1, c[2] + t / 9 - 1};
-    P.kgi_col[k] = li[loc_index(S, cn)];
-    P.kgi_val[k] = kloc(S, g, rho, P.khat, c, cn);
-  }
+  loc_coords(S, P.g_loc[ge], c);
+  const int t = P.kgi_t[k];
+  const int cn[3] = {c[0] + t % 3 - 1, c[1] + (t / 3) % 3 - 1, c[2] + t / 9 - 1};
+  P.kgi_col[k] = P.loc_I[S.loc_off + loc_index(S, cn)];
+  P.kgi_val[k] = kloc(S, g, rho, P.khat, c, cn);
 }
 
 // q[e] = (K_{Gamma I} y_I)[e] for the Gamma entries of each subdomain, from
@@ -3274,23 +3271,19 @@ __global__ void k_yg_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__ 
   }
 }
 
-// The K_{I Gamma} entries of each interior node: for each Gamma neighbour
-// listed by the plan, its free index and the stiffness entry (from rho).
+// The K_{I Gamma} entries (the Gamma neighbours the plan lists for each
+// interior node): the neighbour's free index and the stiffness entry (from
+// rho).  One thread per entry, so no thread walks a node's list.
 __global__ void k_kig_fill(PlanDev P, Geo g, const double* __restrict__ rho) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= S.n_I) return;
-  const int l = P.I_loc[S.I_off + i];
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= P.n_kig) return;
+  const SubDev S = P.subs[P.kig_sub[e]];
   int c[3];
-  loc_coords(S, l, c);
-  const int64_t gi = S.I_off + i;
-  for (int e = P.kig_ptr[gi]; e < P.kig_ptr[gi + 1]; ++e) {
-    const int t = P.kig_t[e];
-    const int cn[3] = {c[0] + t % 3 - 1, c[1] + (t / 3) % 3 - 1, c[2] + t / 9 - 1};
-    P.kig_col[e] = (int32_t)free_of_local(S, g, loc_index(S, cn));
-    P.kig_val[e] = kloc(S, g, rho, P.khat, c, cn);
-  }
+  loc_coords(S, P.I_loc[P.kig_own[e]], c);
+  const int t = P.kig_t[e];
+  const int cn[3] = {c[0] + t % 3 - 1, c[1] + (t / 3) % 3 - 1, c[2] + t / 9 - 1};
+  P.kig_col[e] = (int32_t)free_of_local(S, g, loc_index(S, cn));
+  P.kig_val[e] = kloc(S, g, rho, P.khat, c, cn);
 }
 
 // Interior right-hand side of the second Dirichlet solve: r_I - K_{I Gamma} w,
@@ -4354,8 +4347,8 @@ void launch_front_zero_lower(const PlanDev& P, const int32_t* fronts, int nfr, i
   k_front_zero_lower<<<dim3(cdiv(maxn, 32), nfr), 256, 0, s>>>(P, fronts, fpool);
 }
 void launch_kig_fill(const PlanDev& P, const Geo& g, const double* rho, hipStream_t s) {
-  if (P.max_nI > 0) k_kig_fill<<<dim3(cdiv(P.max_nI, 128), P.n_sub), 128, 0, s>>>(P, g, rho);
-  if (P.max_ng > 0) k_kgi_fill<<<dim3(cdiv(P.max_ng, 128), P.n_sub), 128, 0, s>>>(P, g, rho);
+  if (P.n_kig > 0) k_kig_fill<<<cdiv(P.n_kig, 256), 256, 0, s>>>(P, g, rho);
+  if (P.n_kgi > 0) k_kgi_fill<<<cdiv(P.n_kgi, 256), 256, 0, s>>>(P, g, rho);
 }
 void launch_front_child_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
                                 double* fpool, hipStream_t s) {

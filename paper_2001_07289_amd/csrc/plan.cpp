@@ -511,7 +511,11 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
         for (int a = 0; a < 3; ++a) in = in && cn[a] >= 0 && cn[a] < S.m[a];
         if (!in) continue;
         const int ln = cn[0] + S.m[0] * (cn[1] + S.m[1] * cn[2]);
-        if (lg[ln] >= 0) plan.kig_t.push_back((int8_t)t);
+        if (lg[ln] >= 0) {
+          plan.kig_t.push_back((int8_t)t);
+          plan.kig_own.push_back((int32_t)plan.kig_ptr.size() - 1);
+          plan.kig_sub.push_back(s);
+        }
       }
       plan.kig_ptr.push_back((int32_t)plan.kig_t.size());
     }
@@ -537,7 +541,10 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
         for (int a = 0; a < 3; ++a) in = in && cn[a] >= 0 && cn[a] < S.m[a];
         if (!in) continue;
         const int ln = cn[0] + S.m[0] * (cn[1] + S.m[1] * cn[2]);
-        if (lI[ln] >= 0) plan.kgi_t.push_back((int8_t)t);
+        if (lI[ln] >= 0) {
+          plan.kgi_t.push_back((int8_t)t);
+          plan.kgi_own.push_back((int32_t)plan.kgi_ptr.size() - 1);
+        }
       }
       plan.kgi_ptr.push_back((int32_t)plan.kgi_t.size());
     }

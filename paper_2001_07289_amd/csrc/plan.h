@@ -71,8 +71,10 @@ struct Plan {
                                               // vertex j - n_a): its column of [X | Y']
   std::vector<int32_t> kig_ptr;               // per interior node (all subdomains): its Gamma neighbours
   std::vector<int8_t> kig_t;                  //   as 27-point neighbour codes
+  std::vector<int32_t> kig_own, kig_sub;      //   per entry: its interior node (global I order), subdomain
   std::vector<int32_t> kgi_ptr;               // per Gamma entry (all subdomains): its interior neighbours
   std::vector<int8_t> kgi_t;                  //   as 27-point neighbour codes
+  std::vector<int32_t> kgi_own;               //   per entry: its Gamma entry (global order)
   std::vector<int32_t> g_loc, g_gam, g_r, g_v, g_sub; // per Gamma entry
   std::vector<int32_t> loc_sel;   // per local node: selected-row index or -1
   std::vector<int32_t> sel_r;     // per selected row: r rank (-1 at primal vertices)
