@@ -782,9 +782,8 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   Kern<T>::gemm((GemmDesc*)pc->gSel.desc, pc->gSel.hg.data(), pc->gSel.n, pc->gSel.maxm, pc->gSel.maxn, N.XG, 0,
                 N.Lam, 0, N.PhiG, (T)-1, (T)0, s, pc->P_());
   ref_gemm_batch(pc, pc->gSel);
-  Kern<T>::phi_add(P, N.Z, N.PhiG, pc->max_nv, s);
+  Kern<T>::phi_add(P, N.Z, N.PhiG, N.YG, pc->max_nv, s);  // and Y' at the Gamma entries
   Kern<T>::float_phi(P, pc->feps, N.PhiG, s);
-  Kern<T>::yg_gather(P, N.Z, N.YG, pc->max_nv, s);
   Kern<T>::kc_identity(P, g, rho, N.PhiG, N.Lam, N.Kc, pc->vcoef, pc->vcode, pc->max_nv, s);
   // The interior (Dirichlet) factors are needed only when the preconditioner
   // is applied, so they are built on a third stream while the coarse

@@ -130,7 +130,8 @@ struct Kern {
   static void lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s);
   // rows of [X | Phi initialised to Y'] at the selected rows
   static void sel_gather(const PlanDev& P, const T* Z, T* XS, hipStream_t s);
-  static void phi_add(const PlanDev& P, const T* Z, T* PS, int max_nv, hipStream_t s);
+  // also writes Y' at the Gamma entries (YG)
+  static void phi_add(const PlanDev& P, const T* Z, T* PS, T* YG, int max_nv, hipStream_t s);
   static void kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PS,
                           const T* Lam, T* Kc, double* vcoef, int32_t* vcode, int max_nv, hipStream_t s);
   static void kc_to_front(const PlanDev& P, const int32_t* subs_of_color, int ns, const T* Kc,
@@ -165,7 +166,6 @@ struct Kern {
   static void float_v2(const PlanDev& P, const double* uc, const double* eps, const double* fc, T* v2, int nrhs,
                        hipStream_t s);
   // Y' at the Gamma entries, from [X | Y']
-  static void yg_gather(const PlanDev& P, const T* Z, T* YG, int max_nv, hipStream_t s);
   static void interior_rhs(const PlanDev& P, const Geo& g, const double* rho, const double* r,
                            const double* w, T* vI, int nrhs, hipStream_t s);
   static void scatter_I(const PlanDev& P, const Geo& g, const T* vI, double* z, int nrhs, hipStream_t s);

@@ -2193,9 +2193,11 @@ __global__ void k_sel_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__
 // Phi = Y' - X Lambda at the selected rows: after the product has written
 // -X Lambda, add Y' = -K_rr^{-1} K_rv (nonzero only in the vertex columns) and
 // put the unit entry of the vertex's coarse dof in the rows of Gamma entries
-// that are primal vertices (X is 0 there).
+// that are primal vertices (X is 0 there).  The Gamma entries are the first
+// n_g selected rows, so the same pass also stores Y' there (YG, with the
+// same unit entries) for the preconditioner's application.
 template <typename T>
-__global__ void k_phi_add(PlanDev P, const T* __restrict__ Z, T* __restrict__ PS) {
+__global__ void k_phi_add(PlanDev P, const T* __restrict__ Z, T* __restrict__ PS, T* __restrict__ YG) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int tot = S.n_s * S.n_v;
@@ -2204,8 +2206,15 @@ __global__ void k_phi_add(PlanDev P, const T* __restrict__ Z, T* __restrict__ PS
     const int r = P.sel_r[S.sel_off + e];
     const int c = P.v_c[S.v_off + v];
     T* dst = PS + S.PhiG_off + e + (int64_t)S.n_s * c;
-    if (r >= 0) *dst = Z[S.Z_off + r + (int64_t)S.n_r * P.z_col[S.c_off + S.n_a + v]] + *dst;
-    else if (P.g_v[S.g_off + e] == v) *dst = (T)1;
+    T y;
+    if (r >= 0) {
+      y = Z[S.Z_off + r + (int64_t)S.n_r * P.z_col[S.c_off + S.n_a + v]];
+      *dst = y + *dst;
+    } else {
+      y = P.g_v[S.g_off + e] == v ? (T)1 : (T)0;
+      if (y != (T)0) *dst = y;
+    }
+    if (e < S.n_g) YG[S.YG_off + e + (int64_t)S.n_g * v] = y;
   }
 }
 
@@ -3255,22 +3264,6 @@ __global__ __launch_bounds__(256) void k_float_v2(PlanDev P, const double* __res
   for (int e = threadIdx.x; e < S.n_g; e += blockDim.x) v[e] = (T)((double)v[e] + add);
 }
 
-// Y' at the Gamma entries: the vertex columns of [X | Y'] gathered by the
-// Gamma entries' r-rows; a Gamma entry that is a primal vertex has no r-row
-// and takes the unit value of its own coarse dof.
-template <typename T>
-__global__ void k_yg_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__ YG) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  const int tot = S.n_g * S.n_v;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
-    const int e = idx % S.n_g, v = idx / S.n_g;
-    const int r = P.g_r[S.g_off + e];
-    YG[S.YG_off + idx] = r >= 0 ? Z[S.Z_off + r + (int64_t)S.n_r * P.z_col[S.c_off + S.n_a + v]]
-                                : (P.g_v[S.g_off + e] == v ? (T)1 : (T)0);
-  }
-}
-
 // The K_{I Gamma} entries (the Gamma neighbours the plan lists for each
 // interior node): the neighbour's free index and the stiffness entry (from
 // rho).  One thread per entry, so no thread walks a node's list.
@@ -4158,10 +4151,10 @@ void Kern<T>::sel_gather(const PlanDev& P, const T* Z, T* XS, hipStream_t s) {
 }
 
 template <typename T>
-void Kern<T>::phi_add(const PlanDev& P, const T* Z, T* PS, int max_nv, hipStream_t s) {
+void Kern<T>::phi_add(const PlanDev& P, const T* Z, T* PS, T* YG, int max_nv, hipStream_t s) {
   const int64_t tot = (int64_t)P.max_ns * max_nv;
   if (tot == 0) return;
-  k_phi_add<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, PS);
+  k_phi_add<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, PS, YG);
 }
 
 template <typename T>
@@ -4302,13 +4295,6 @@ void Kern<T>::lam_uc(const PlanDev& P, const T* Lam, const double* uc, T* lu, in
   if (P.max_na == 0) return;
   k_lam_uc<T><<<dim3(P.n_sub, nrhs), 256, (size_t)(hmax(P.max_nc, 1) + 4 * (size_t)P.max_na) * sizeof(double), s>>>(
       P, Lam, uc, lu);
-}
-
-template <typename T>
-void Kern<T>::yg_gather(const PlanDev& P, const T* Z, T* YG, int max_nv, hipStream_t s) {
-  const int64_t tot = (int64_t)P.max_ng * max_nv;
-  if (tot == 0) return;
-  k_yg_gather<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, YG);
 }
 
 template <typename T>
