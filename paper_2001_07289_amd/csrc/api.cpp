@@ -766,13 +766,12 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   // the banded forward and backward solves the block GEMMs stand for
   if (pc->P_()) pc->prof.ref(3, pc->ref_basis_flops, 0.0);
   // constraint Schur complement and the coarse basis
-  Kern<T>::sc_assemble(P, N.Z, N.Sc, s);
+  Kern<T>::object_means(P, N.Z, N.Sc, N.Tm, s);  // S_c and the right-hand sides of Lambda
   for (const Batch& b : pc->swSc) {
     Kern<T>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, N.Sc, N.sw, N.sw_stride, pc->status, 3, s,
                    pc->P_(), nullptr, pc->opt.sweep_reg_rows, pc->opt.slab_lookahead, pc->opt.update_tile, pc->opt.slab_width);
     ref_sweep_batch(pc, b);
   }
-  Kern<T>::lambda_rhs(P, N.Z, N.Tm, s);
   Kern<T>::gemm((GemmDesc*)pc->gLam.desc, pc->gLam.hg.data(), pc->gLam.n, pc->gLam.maxm, pc->gLam.maxn, N.Sc, 0,
                 N.Tm, 0, N.Lam, (T)-1, (T)0, s, pc->P_());
   ref_gemm_batch(pc, pc->gLam);
@@ -1063,9 +1062,11 @@ void layout(bddcso_precond* pc, hipStream_t s) {
   P.max_zcols = pl.max_zcols;
   P.max_plane = max_plane;
   P.max_nv = 0;
+  P.max_nar = 0;
   P.n_pinned = 0;
   for (auto& S : pl.subs) {
     P.max_nv = std::max(P.max_nv, S.n_v);
+    P.max_nar = std::max(P.max_nar, pl.a_ptr[S.a_off + S.n_a] - pl.a_ptr[S.a_off]);
     if (S.pin >= 0) ++P.n_pinned;
   }
   P.mr_min = o.mr_min_rhs;

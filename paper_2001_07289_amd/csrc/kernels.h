@@ -85,6 +85,7 @@ struct PlanDev {
   int n_sub;
   int64_t tot_I, tot_r, tot_g, tot_c, tot_a, n_gam, n_coarse;
   int max_block, max_na, max_nc, max_ng, max_ns, max_nloc, max_nr, max_nI, max_zcols, max_plane, max_nv;
+  int max_nar;    // r-set nodes of one subdomain's averages
   int n_pinned;  // subdomains with a pin (SubDev::pin >= 0)
   int mr_min;    // right-hand sides from which the many-RHS kernels run
 };
@@ -126,8 +127,7 @@ struct Kern {
   static void rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, hipStream_t s);
   static void couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
                            int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s, int sub0, int nsub);
-  static void sc_assemble(const PlanDev& P, const T* Z, T* Sc, hipStream_t s);
-  static void lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s);
+  static void object_means(const PlanDev& P, const T* Z, T* Sc, T* Tm, hipStream_t s);
   // rows of [X | Phi initialised to Y'] at the selected rows
   static void sel_gather(const PlanDev& P, const T* Z, T* XS, hipStream_t s);
   // also writes Y' at the Gamma entries (YG)

@@ -2115,59 +2115,77 @@ __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd,
   }
 }
 
-// Mean of column col of Z over the r-set nodes a_r[pb..pe) of one object,
-// summed in order with eight gathers in flight at a time.
-template <typename T>
-__device__ __forceinline__ double object_mean(const PlanDev& P, const T* __restrict__ z, int64_t nr, int col,
-                                              int pb, int pe) {
-  double s = 0.0;
-  for (int t0 = pb; t0 < pe; t0 += 8) {
-    int rr[8];
-    T zv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) rr[u] = t0 + u < pe ? P.a_r[t0 + u] : 0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) zv[u] = t0 + u < pe ? z[rr[u] + nr * col] : (T)0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (t0 + u < pe) s += (double)zv[u];
-  }
-  return s / (double)(pe - pb);
-}
-
-// S_c[a, b] = (C_r X)[a, b]: mean of X's column b over object a's nodes.
-// S_c = C_r K_rr^{-1} C_r^T is symmetric and its sweep reads only the lower
-// triangle, so only a >= b is formed.
-template <typename T>
-__global__ void k_sc_assemble(PlanDev P, const T* __restrict__ Z, T* __restrict__ Sc) {
+// S_c = C_r X (lower triangle) and T = C_r Y - [0 I] in one pass.  C_r takes
+// the mean of a column over each average's r-set nodes (the objects own
+// disjoint node ranges a_r[a_ptr[a]..a_ptr[a+1])).  The column space is S_c's
+// n_a columns followed by T's n_c columns; a workgroup takes C of them,
+// stages their values at the objects' nodes in LDS (Z column b of X for S_c
+// column b, the vertex's column of Y' for a vertex column of T; an average
+// column of T is -e_a and reads nothing), then forms every mean of those
+// columns from LDS, summed in node order.  S_c = C_r K_rr^{-1} C_r^T is
+// symmetric and its sweep reads only the lower triangle, so only a >= b is
+// formed there.
+template <typename T, int C>
+__global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __restrict__ Z, T* __restrict__ Sc,
+                                                      T* __restrict__ Tm, int ld) {
+  extern __shared__ unsigned char om_smem[];
+  T* zs = (T*)om_smem;  // [C][ld]
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= S.n_a * S.n_a) return;
-  const int a = idx % S.n_a, b = idx / S.n_a;
-  if (a < b) return;
-  const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
-  Sc[S.Sc_off + idx] = (T)object_mean(P, Z + S.Z_off, S.n_r, P.z_col[S.c_off + b], pb, pe);
-}
-
-// T[a, c] = (C_r Y)[a, c] - [0 I][a, c]: Y is -K_rr^{-1} K_rv at vertex
-// columns and 0 at average columns.
-template <typename T>
-__global__ void k_lambda_rhs(PlanDev P, const T* __restrict__ Z, T* __restrict__ Tm) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= S.n_a * S.n_c) return;
-  const int a = idx % S.n_a, c = idx / S.n_a;
-  const int kind = P.c_kind[S.c_off + c];
-  double v;
-  if (kind >= 0) {
-    const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
-    v = object_mean(P, Z + S.Z_off, S.n_r, P.z_col[S.c_off + S.n_a + kind], pb, pe);
-  } else {
-    v = (-kind - 1 == a) ? -1.0 : 0.0;
+  const int na = S.n_a, ncol = na + S.n_c;
+  const int j0 = blockIdx.x * C;
+  if (j0 >= ncol) return;
+  const int a0 = P.a_ptr[S.a_off], nar = P.a_ptr[S.a_off + na] - a0;
+  int zc[C];  // Z column staged for each local column, -1: none
+  int tb[C];  // first staged node: S_c column b needs only the objects a >= b
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int jj = j0 + j;
+    zc[j] = -1;
+    tb[j] = 0;
+    if (jj < na) {
+      zc[j] = P.z_col[S.c_off + jj];
+      tb[j] = P.a_ptr[S.a_off + jj] - a0;
+    } else if (jj < ncol) {
+      const int kind = P.c_kind[S.c_off + jj - na];
+      if (kind >= 0) zc[j] = P.z_col[S.c_off + na + kind];
+    }
   }
-  Tm[S.T_off + idx] = (T)v;
+  int tmin = nar;
+#pragma unroll
+  for (int j = 0; j < C; ++j)
+    if (zc[j] >= 0) tmin = min(tmin, tb[j]);
+  const T* z = Z + S.Z_off;
+  for (int t = tmin + threadIdx.x; t < nar; t += blockDim.x) {
+    const int64_t r = P.a_r[a0 + t];
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      if (zc[j] >= 0 && t >= tb[j]) zs[j * ld + t] = z[r + S.n_r * (int64_t)zc[j]];
+  }
+  __syncthreads();
+  const int nj = min(C, ncol - j0);
+  for (int e = threadIdx.x; e < nj * na; e += blockDim.x) {
+    const int j = e / na, a = e - j * na, jj = j0 + j;
+    if (jj < na && a < jj) continue;  // S_c: lower triangle only
+    int zcj = -1;
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+      if (q == j) zcj = zc[q];
+    double v;
+    if (zcj >= 0) {
+      const int pb = P.a_ptr[S.a_off + a] - a0, pe = P.a_ptr[S.a_off + a + 1] - a0;
+      const T* col = zs + j * ld;
+      double acc = 0.0;
+      for (int t = pb; t < pe; ++t) acc += (double)col[t];
+      v = acc / (double)(pe - pb);
+    } else {
+      v = (-P.c_kind[S.c_off + jj - na] - 1 == a) ? -1.0 : 0.0;
+    }
+    if (jj < na)
+      Sc[S.Sc_off + a + (int64_t)na * jj] = (T)v;
+    else
+      Tm[S.T_off + a + (int64_t)na * (jj - na)] = (T)v;
+  }
 }
 
 // Rows of X at the selected rows (0 at a Gamma entry that is a primal vertex).
@@ -3858,6 +3876,7 @@ int64_t max_lds_bytes(const PlanDev& P, int elt, int max_nrhs) {
   if (max_nrhs >= P.mr_min) need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);  // many-rhs block solve
   need = hmax(need, (int64_t)(P.max_na + P.max_nc + 1) * elt);                         // v2
   need = hmax(need, (int64_t)hmax(P.max_ng, 1) * elt);                                 // coarse rhs
+  need = hmax(need, (int64_t)hmax(P.max_nar, 1) * elt);                                // object means
   need = hmax(need, kc_lds_bytes(P));                                                  // local coarse matrices
   need = hmax(need, (int64_t)SWEEP_ROWS * (SWEEP_NB + 1) * elt + 2 * 32 * 33 * 8);   // sweep panel
   return need;
@@ -4132,15 +4151,17 @@ void Kern<T>::couple_multi(const PlanDev& P, const Geo& g, const double* rho, in
 }
 
 template <typename T>
-void Kern<T>::sc_assemble(const PlanDev& P, const T* Z, T* Sc, hipStream_t s) {
-  if (P.max_na == 0) return;
-  k_sc_assemble<T><<<dim3(cdiv((int64_t)P.max_na * P.max_na, 256), P.n_sub), 256, 0, s>>>(P, Z, Sc);
-}
-
-template <typename T>
-void Kern<T>::lambda_rhs(const PlanDev& P, const T* Z, T* Tm, hipStream_t s) {
-  if (P.max_na == 0 || P.max_nc == 0) return;
-  k_lambda_rhs<T><<<dim3(cdiv((int64_t)P.max_na * P.max_nc, 256), P.n_sub), 256, 0, s>>>(P, Z, Tm);
+void Kern<T>::object_means(const PlanDev& P, const T* Z, T* Sc, T* Tm, hipStream_t s) {
+  if (P.n_sub == 0 || P.max_na == 0) return;
+  const int ld = hmax(P.max_nar, 1);
+  const int64_t col = (int64_t)ld * sizeof(T);
+  const int ncol = P.max_na + P.max_nc;
+  if (8 * col <= 32 * 1024)
+    k_object_means<T, 8><<<dim3(cdiv(ncol, 8), P.n_sub), 256, 8 * col, s>>>(P, Z, Sc, Tm, ld);
+  else if (4 * col <= 32 * 1024)
+    k_object_means<T, 4><<<dim3(cdiv(ncol, 4), P.n_sub), 256, 4 * col, s>>>(P, Z, Sc, Tm, ld);
+  else
+    k_object_means<T, 1><<<dim3(ncol, P.n_sub), 256, col, s>>>(P, Z, Sc, Tm, ld);
 }
 
 template <typename T>
