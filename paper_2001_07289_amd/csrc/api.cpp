@@ -496,10 +496,11 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
         d.push_back({S.Sc_off, S.n_a, S.n_a, S.n_a});
         if (S.n_c > 0) lam.push_back({S.Sc_off, S.T_off, S.T_off, S.n_a, S.n_c, S.n_a, S.n_a, S.n_a, S.n_a});
       }
-      // every subdomain with coarse dofs: the product writes all of Phi's
-      // selected rows (-X Lambda, 0 when there are no averages)
-      if (S.n_c > 0)
-        phir.push_back({S.XG_off, S.T_off, S.PhiG_off, S.n_s, S.n_c, S.n_a, S.n_s, std::max(S.n_a, 1), S.n_s});
+      // every subdomain with vertices: the product writes Phi's vertex
+      // columns at all selected rows (-X Lambda_v, 0 when there are no
+      // averages); Lambda_v is packed in the right-hand side buffer
+      if (S.n_v > 0)
+        phir.push_back({S.XG_off, S.T_off, S.PhiG_off, S.n_s, S.n_v, S.n_a, S.n_s, std::max(S.n_a, 1), S.n_s});
     }
     check_sweeps(d, pl.pool_Sc, ns, "S_c");
     check_gemms(lam, pl.pool_Sc, pl.pool_T, pl.pool_T, "Lambda GEMM");
@@ -776,13 +777,13 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
                 N.Tm, 0, N.Lam, (T)-1, (T)0, s, pc->P_());
   ref_gemm_batch(pc, pc->gLam);
   Kern<T>::float_setup(P, N.Sc, N.Lam, pc->feps, pc->fdelta, s);
-  // Phi = Y' - X Lambda, only at the selected rows (Gamma and the vertices' stencils)
-  Kern<T>::sel_gather(P, N.Z, N.XG, s);
+  // Phi = Y' - X Lambda, only at the selected rows (Gamma and the vertices'
+  // stencils) and only in the vertex columns
+  Kern<T>::sel_gather(P, N.Z, N.Lam, N.XG, N.Tm, s);
   Kern<T>::gemm((GemmDesc*)pc->gSel.desc, pc->gSel.hg.data(), pc->gSel.n, pc->gSel.maxm, pc->gSel.maxn, N.XG, 0,
-                N.Lam, 0, N.PhiG, (T)-1, (T)0, s, pc->P_());
+                N.Tm, 0, N.PhiG, (T)-1, (T)0, s, pc->P_());
   ref_gemm_batch(pc, pc->gSel);
   Kern<T>::phi_add(P, N.Z, N.PhiG, N.YG, pc->max_nv, s);  // and Y' at the Gamma entries
-  Kern<T>::float_phi(P, pc->feps, N.PhiG, s);
   Kern<T>::kc_identity(P, g, rho, N.PhiG, N.Lam, N.Kc, pc->vcoef, pc->vcode, pc->max_nv, s);
   // The interior (Dirichlet) factors are needed only when the preconditioner
   // is applied, so they are built on a third stream while the coarse
@@ -880,7 +881,9 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   Kern<T>::mu(P, N.vR, N.Sc, N.mu, nrhs, s);
   Kern<T>::float_mu(P, N.gv, N.mu, pc->feps, pc->fdelta, pc->fc, nrhs, s);
   HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_cfork, 0));
-  Kern<T>::coarse_rhs_local(P, N.PhiG, N.gv, N.bci, nrhs, pc->s2);
+  // X_Gamma^T g per average goes through lu, which lam_uc below refills
+  // and only v2 (after the join) reads
+  Kern<T>::coarse_rhs_local(P, N.XG, N.PhiG, N.Lam, pc->feps, N.gv, N.lu, N.bci, nrhs, pc->s2);
   if (sizeof(T) == 8) launch_coarse_rhs_gather(P, (const double*)N.bci, nullptr, pc->bc, nrhs, pc->s2);
   else launch_coarse_rhs_gather(P, nullptr, (const float*)N.bci, pc->bc, nrhs, pc->s2);
   if (pc->coarse_pending) HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_coarse, 0));

@@ -129,7 +129,7 @@ struct Kern {
                            int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s, int sub0, int nsub);
   static void object_means(const PlanDev& P, const T* Z, T* Sc, T* Tm, hipStream_t s);
   // rows of [X | Phi initialised to Y'] at the selected rows
-  static void sel_gather(const PlanDev& P, const T* Z, T* XS, hipStream_t s);
+  static void sel_gather(const PlanDev& P, const T* Z, const T* Lam, T* XS, T* LV, hipStream_t s);
   // also writes Y' at the Gamma entries (YG)
   static void phi_add(const PlanDev& P, const T* Z, T* PS, T* YG, int max_nv, hipStream_t s);
   static void kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PS,
@@ -150,7 +150,8 @@ struct Kern {
                       T* gv, int nrhs, hipStream_t s);
   static void neumann_rhs(const PlanDev& P, const T* gv, T* vR, int nrhs, hipStream_t s);
   static void mu(const PlanDev& P, const T* vR, const T* Sc, T* mu_out, int nrhs, hipStream_t s);
-  static void coarse_rhs_local(const PlanDev& P, const T* PhiG, const T* gv, T* bci, int nrhs,
+  static void coarse_rhs_local(const PlanDev& P, const T* XG, const T* PhiG, const T* Lam, const double* eps,
+                               const T* gv, T* wv, T* bci, int nrhs,
                                hipStream_t s);
   // v2 on Gamma = u - X_Gamma (mu + Lambda u_c) + Y'_Gamma u_c (equal to
   // u - X_Gamma mu + Phi_Gamma u_c, as Phi = Y' - X Lambda)
@@ -160,7 +161,6 @@ struct Kern {
   static void lam_uc(const PlanDev& P, const T* Lam, const double* uc, T* lu, int nrhs, hipStream_t s);
   // pinned subdomains (SubDev::pin): the constant of the local kernel
   static void float_setup(const PlanDev& P, const T* Sc, T* Lam, double* eps, double* fdelta, hipStream_t s);
-  static void float_phi(const PlanDev& P, const double* eps, T* PhiG, hipStream_t s);
   static void float_mu(const PlanDev& P, const T* gv, T* mu_io, const double* eps, const double* fdelta,
                        double* fc, int nrhs, hipStream_t s);
   static void float_v2(const PlanDev& P, const double* uc, const double* eps, const double* fc, T* v2, int nrhs,

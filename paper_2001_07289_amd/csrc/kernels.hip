@@ -2188,11 +2188,19 @@ __global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __rest
   }
 }
 
-// Rows of X at the selected rows (0 at a Gamma entry that is a primal vertex).
+// Rows of X at the selected rows (0 at a Gamma entry that is a primal vertex),
+// and Lambda's vertex columns packed (n_a x n_v, ld n_a, in the right-hand
+// side buffer, which is free once Lambda is formed): the operands of the
+// product -X Lambda, which only Phi's vertex columns need.
 template <typename T>
-__global__ void k_sel_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__ XS) {
+__global__ void k_sel_gather(PlanDev P, const T* __restrict__ Z, const T* __restrict__ Lam, T* __restrict__ XS,
+                             T* __restrict__ LV) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < S.n_a * S.n_v; idx += gridDim.x * blockDim.x) {
+    const int a = idx % S.n_a, v = idx / S.n_a;
+    LV[S.T_off + idx] = Lam[S.T_off + a + (int64_t)S.n_a * P.v_c[S.v_off + v]];
+  }
   // thread (row e, 8 columns): one index load, eight gathers in flight
   const int na8 = (S.n_a + 7) / 8, tot = S.n_s * na8;  // per subdomain: 32-bit index math
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
@@ -2208,10 +2216,12 @@ __global__ void k_sel_gather(PlanDev P, const T* __restrict__ Z, T* __restrict__
   }
 }
 
-// Phi = Y' - X Lambda at the selected rows: after the product has written
-// -X Lambda, add Y' = -K_rr^{-1} K_rv (nonzero only in the vertex columns) and
-// put the unit entry of the vertex's coarse dof in the rows of Gamma entries
-// that are primal vertices (X is 0 there).  The Gamma entries are the first
+// Phi's vertex columns at the selected rows (n_s x n_v, column v for vertex
+// v): after the product has written -X Lambda there, add
+// Y' = -K_rr^{-1} K_rv and put the unit entry of the vertex's coarse dof in
+// the rows of Gamma entries that are primal vertices (X is 0 there).  Phi's
+// average columns are -X Lambda (plus 1 e^T / delta on a pinned subdomain)
+// and are never formed: the application reads X and Lambda instead.  The Gamma entries are the first
 // n_g selected rows, so the same pass also stores Y' there (YG, with the
 // same unit entries) for the preconditioner's application.
 template <typename T>
@@ -2222,8 +2232,7 @@ __global__ void k_phi_add(PlanDev P, const T* __restrict__ Z, T* __restrict__ PS
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
     const int e = idx % S.n_s, v = idx / S.n_s;
     const int r = P.sel_r[S.sel_off + e];
-    const int c = P.v_c[S.v_off + v];
-    T* dst = PS + S.PhiG_off + e + (int64_t)S.n_s * c;
+    T* dst = PS + S.PhiG_off + e + (int64_t)S.n_s * v;
     T y;
     if (r >= 0) {
       y = Z[S.Z_off + r + (int64_t)S.n_r * P.z_col[S.c_off + S.n_a + v]];
@@ -2271,8 +2280,8 @@ __global__ void k_vertex_stencil(PlanDev P, Geo g, const double* __restrict__ rh
 }
 
 // K_c's vertex rows in its vertex columns, from the rows' equations: one
-// workgroup per (chunk of vertex columns, subdomain).  The chunk's columns
-// of Phi (all selected rows) and the subdomain's vertex stencils are staged
+// workgroup per (chunk of vertex columns, subdomain).  The chunk's vertex
+// columns of Phi (all selected rows) and the subdomain's vertex stencils are staged
 // in LDS with coalesced loads; an entry is then a 27-term sum over LDS.  The
 // entries in an average row or column are -Lambda (taken by
 // k_kc_symmetrize), so only the vertex columns of Phi are staged.
@@ -2301,7 +2310,7 @@ __global__ __launch_bounds__(256) void k_kc_identity(PlanDev P, const T* __restr
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int i = b0 + threadIdx.x + 256 * u;
-      r[u] = i < tot ? src[(int64_t)ns * vcol[i / ns] + i % ns] : (T)0;
+      r[u] = i < tot ? src[(int64_t)ns * (v0 + i / ns) + i % ns] : (T)0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -3065,37 +3074,132 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// bci = Phi_Gamma^T g_Gamma: one workgroup per (column chunk, subdomain,
-// rhs), one wave per column.
+// bci = Phi_Gamma^T g_Gamma.  Phi = Y' - X Lambda, and only its vertex
+// columns are stored, so the products with g run over the n_a columns of X
+// and the n_v vertex columns of Phi (n_c in all, as for Phi alone): a
+// vertex column's product is its entry of bci; the products w = X_Gamma^T g
+// (per average, in wv) become the average entries -Lambda^T w in
+// k_coarse_rhs_avg.  One workgroup per (column chunk, subdomain, rhs), one
+// wave per column.
 constexpr int CRL_COLS = 16;
 
+// Where product column q goes (X's column q < n_a to w, else the vertex
+// q - n_a's entry of bci).
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_rhs_local(PlanDev P, const T* __restrict__ PhiG,
-                                                          const T* __restrict__ gv, T* __restrict__ bci) {
+__device__ __forceinline__ void crl_store(const PlanDev& P, const SubDev& S, int q, int rhs, T v, T* wv, T* bci) {
+  if (q < S.n_a) wv[(int64_t)rhs * P.tot_a + S.am_off + q] = v;
+  else bci[(int64_t)rhs * P.tot_c + S.c_off + P.v_c[S.v_off + q - S.n_a]] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_rhs_local(PlanDev P, const T* __restrict__ XG,
+                                                          const T* __restrict__ PhiG,
+                                                          const T* __restrict__ gv, T* __restrict__ wv,
+                                                          T* __restrict__ bci) {
   extern __shared__ char smem_raw[];
   T* gl = reinterpret_cast<T*>(smem_raw);
   const int sub = blockIdx.y, rhs = blockIdx.z;
   const SubDev S = P.subs[sub];
+  const int nq = S.n_a + S.n_v;
   const int cb = blockIdx.x * CRL_COLS;
-  if (cb >= S.n_c) return;
+  if (cb >= nq) return;
   const T* g = gv + rhs * P.tot_g + S.g_off;
   for (int e = threadIdx.x; e < S.n_g; e += blockDim.x) gl[e] = g[e];
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const T* M = PhiG + S.PhiG_off;
-  for (int c = cb + wave; c < min(S.n_c, cb + CRL_COLS); c += blockDim.x >> 6) {
-    const T* col = M + (int64_t)S.n_s * c;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int qend = min(nq, cb + CRL_COLS);
+  auto column = [&](int q) {
+    return q < S.n_a ? XG + S.XG_off + (int64_t)S.n_s * q : PhiG + S.PhiG_off + (int64_t)S.n_s * (q - S.n_a);
+  };
+  // two columns per wave at a time (q and q + nw), four loads in flight per
+  // lane and column
+  for (int q = cb + wave; q < qend; q += 2 * nw) {
+    const int q2 = q + nw;
+    const bool two = q2 < qend;
+    const T* c1 = column(q);
+    const T* c2 = two ? column(q2) : c1;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
     int e = lane;
-    for (; e + 192 < S.n_g; e += 256) {  // four loads in flight per lane
-      a0 += (double)(col[e] * gl[e]);
-      a1 += (double)(col[e + 64] * gl[e + 64]);
-      a2 += (double)(col[e + 128] * gl[e + 128]);
-      a3 += (double)(col[e + 192] * gl[e + 192]);
+    for (; e + 192 < S.n_g; e += 256) {
+      const T x0 = c1[e], x1 = c1[e + 64], x2 = c1[e + 128], x3 = c1[e + 192];
+      const T y0 = c2[e], y1 = c2[e + 64], y2 = c2[e + 128], y3 = c2[e + 192];
+      a0 += (double)(x0 * gl[e]);
+      a1 += (double)(x1 * gl[e + 64]);
+      a2 += (double)(x2 * gl[e + 128]);
+      a3 += (double)(x3 * gl[e + 192]);
+      b0 += (double)(y0 * gl[e]);
+      b1 += (double)(y1 * gl[e + 64]);
+      b2 += (double)(y2 * gl[e + 128]);
+      b3 += (double)(y3 * gl[e + 192]);
     }
-    for (; e < S.n_g; e += 64) a0 += (double)(col[e] * gl[e]);
-    const double acc = wave_sum((a0 + a1) + (a2 + a3));
-    if (lane == 0) bci[rhs * P.tot_c + S.c_off + c] = (T)acc;
+    for (; e < S.n_g; e += 64) {
+      const T x0 = c1[e], y0 = c2[e];
+      a0 += (double)(x0 * gl[e]);
+      b0 += (double)(y0 * gl[e]);
+    }
+    const double acc1 = wave_sum((a0 + a1) + (a2 + a3));
+    const double acc2 = wave_sum((b0 + b1) + (b2 + b3));
+    if (lane == 0) {
+      crl_store(P, S, q, rhs, (T)acc1, wv, bci);
+      if (two) crl_store(P, S, q2, rhs, (T)acc2, wv, bci);
+    }
+  }
+}
+
+// The average entries of bci: -Lambda^T w with w = X_Gamma^T g, plus
+// eps (sum of g over Gamma) on a pinned subdomain, whose Phi_r has the extra
+// term 1 e^T / delta (eps = e / delta).  One workgroup per (chunk of 16
+// averages, subdomain, rhs); each wave takes four columns of Lambda at once
+// and loads w beside them (one round of loads).
+constexpr int CRA_COLS = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_rhs_avg(PlanDev P, const T* __restrict__ Lam,
+                                                        const double* __restrict__ eps, const T* __restrict__ gv,
+                                                        const T* __restrict__ wv, T* __restrict__ bci) {
+  __shared__ double red[256];
+  const int sub = blockIdx.y, rhs = blockIdx.z;
+  const SubDev S = P.subs[sub];
+  const int na = S.n_a, j0 = blockIdx.x * CRA_COLS;
+  if (j0 >= na) return;
+  const T* ws = wv + (int64_t)rhs * P.tot_a + S.am_off;
+  const bool pinned = S.pin >= 0;  // uniform over the workgroup
+  double gsum = 0.0;
+  if (pinned) {
+    const T* g = gv + (int64_t)rhs * P.tot_g + S.g_off;
+    double part = 0.0;
+    for (int e = threadIdx.x; e < S.n_g; e += blockDim.x) part += (double)g[e];
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    gsum = red[0];
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const T* L = Lam + S.T_off;
+  int cc[4];
+  double acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + 4 * wave + u;
+    cc[u] = j < na ? P.a_c[S.am_off + j] : -1;
+    acc[u] = 0.0;
+  }
+  for (int a = lane; a < na; a += 64) {
+    T lv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) lv[u] = cc[u] >= 0 ? L[a + (int64_t)na * cc[u]] : (T)0;
+    const double wa = (double)ws[a];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += (double)lv[u] * wa;
+  }
+  T* b = bci + (int64_t)rhs * P.tot_c + S.c_off;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double sum = wave_sum(acc[u]);
+    if (lane == 0 && cc[u] >= 0) b[cc[u]] = (T)(pinned ? eps[S.am_off + cc[u]] * gsum - sum : -sum);
   }
 }
 
@@ -3217,19 +3321,6 @@ __global__ __launch_bounds__(256) void k_float_setup(PlanDev P, const T* __restr
   for (int idx = threadIdx.x; idx < na * na; idx += blockDim.x) {
     const int a = idx % na, c = idx / na;
     L[idx] = (T)((double)L[idx] + e[a] * e[c] / delta);
-  }
-}
-
-// Setup, after Phi = -X Lambda at the selected rows: add 1 e^T / delta.
-template <typename T>
-__global__ void k_float_phi(PlanDev P, const double* __restrict__ eps, T* __restrict__ PhiG) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  if (S.pin < 0) return;
-  const int tot = S.n_s * S.n_c;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
-    const int c = idx / S.n_s;
-    PhiG[S.PhiG_off + idx] = (T)((double)PhiG[S.PhiG_off + idx] + eps[S.am_off + c]);
   }
 }
 
@@ -3521,21 +3612,25 @@ __device__ __forceinline__ void mr_accum(AF a_of, bool rok, int kn, const T (*Bs
   }
 }
 
-// Coarse right-hand side of each subdomain: bci[c] = sum_e PhiG[e][c] g[e].
+// The products of k_coarse_rhs_local for many right-hand sides: column q of
+// [X_Gamma | Phi_Gamma's vertex columns] times g, stored by crl_store.
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_rhs_local_mr(PlanDev P, const T* __restrict__ PhiG,
-                                                             const T* __restrict__ gv, T* __restrict__ bci,
-                                                             int nrhs) {
+__global__ __launch_bounds__(256) void k_coarse_rhs_local_mr(PlanDev P, const T* __restrict__ XG,
+                                                             const T* __restrict__ PhiG,
+                                                             const T* __restrict__ gv, T* __restrict__ wv,
+                                                             T* __restrict__ bci, int nrhs) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T Bs[MR_KC][MR_COLS + 1];
   const int sub = blockIdx.y, r0 = blockIdx.z * MR_COLS, nr = min(MR_COLS, nrhs - r0);
   const SubDev S = P.subs[sub];
+  const int nq = S.n_a + S.n_v;
   const int c0 = blockIdx.x * 64;
-  if (c0 >= S.n_c) return;
+  if (c0 >= nq) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kq = lane >> 4, rr = lane & 15;
-  const int c = c0 + wave * 16 + rr;
-  const bool rok = c < S.n_c;
-  const T* M = PhiG + S.PhiG_off + (int64_t)S.n_s * c;
+  const int qc = c0 + wave * 16 + rr;  // this lane's product column
+  const bool rok = qc < nq;
+  const T* M = !rok ? XG : qc < S.n_a ? XG + S.XG_off + (int64_t)S.n_s * qc
+                                      : PhiG + S.PhiG_off + (int64_t)S.n_s * (qc - S.n_a);
   acc_t acc[MR_COLS / 16];
 #pragma unroll
   for (int q = 0; q < MR_COLS / 16; ++q) acc[q] = acc_t{0, 0, 0, 0};
@@ -3555,7 +3650,7 @@ __global__ __launch_bounds__(256) void k_coarse_rhs_local_mr(PlanDev P, const T*
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int cc = c0 + wave * 16 + Mfma<T>::row(kq, e), r = 16 * q + rr;
-      if (cc < S.n_c && r < nr) bci[(int64_t)(r0 + r) * P.tot_c + S.c_off + cc] = acc[q][e];
+      if (cc < nq && r < nr) crl_store(P, S, cc, r0 + r, (T)acc[q][e], wv, bci);
     }
 }
 
@@ -4165,10 +4260,10 @@ void Kern<T>::object_means(const PlanDev& P, const T* Z, T* Sc, T* Tm, hipStream
 }
 
 template <typename T>
-void Kern<T>::sel_gather(const PlanDev& P, const T* Z, T* XS, hipStream_t s) {
+void Kern<T>::sel_gather(const PlanDev& P, const T* Z, const T* Lam, T* XS, T* LV, hipStream_t s) {
   const int64_t tot = (int64_t)P.max_ns * cdiv(P.max_na, 8);
   if (tot == 0) return;
-  k_sel_gather<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, XS);
+  k_sel_gather<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, Lam, XS, LV);
 }
 
 template <typename T>
@@ -4264,15 +4359,18 @@ void Kern<T>::mu(const PlanDev& P, const T* vR, const T* Sc, T* mu_out, int nrhs
 }
 
 template <typename T>
-void Kern<T>::coarse_rhs_local(const PlanDev& P, const T* PhiG, const T* gv, T* bci, int nrhs, hipStream_t s) {
+void Kern<T>::coarse_rhs_local(const PlanDev& P, const T* XG, const T* PhiG, const T* Lam, const double* eps,
+                               const T* gv, T* wv, T* bci, int nrhs, hipStream_t s) {
   if (P.max_nc == 0) return;
-  if (nrhs >= P.mr_min) {
-    k_coarse_rhs_local_mr<T><<<dim3(cdiv(P.max_nc, 64), P.n_sub, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, PhiG, gv, bci,
-                                                                                                  nrhs);
-    return;
-  }
-  k_coarse_rhs_local<T><<<dim3(cdiv(P.max_nc, CRL_COLS), P.n_sub, nrhs), 256, (size_t)hmax(P.max_ng, 1) * sizeof(T), s>>>(
-      P, PhiG, gv, bci);
+  // n_a + n_v = n_c: every local coarse dof is an average or a vertex
+  if (nrhs >= P.mr_min)
+    k_coarse_rhs_local_mr<T><<<dim3(cdiv(P.max_nc, 64), P.n_sub, cdiv(nrhs, MR_COLS)), 256, 0, s>>>(P, XG, PhiG, gv,
+                                                                                                  wv, bci, nrhs);
+  else
+    k_coarse_rhs_local<T><<<dim3(cdiv(P.max_nc, CRL_COLS), P.n_sub, nrhs), 256, (size_t)hmax(P.max_ng, 1) * sizeof(T),
+                            s>>>(P, XG, PhiG, gv, wv, bci);
+  if (P.max_na > 0)
+    k_coarse_rhs_avg<T><<<dim3(cdiv(P.max_na, CRA_COLS), P.n_sub, nrhs), 256, 0, s>>>(P, Lam, eps, gv, wv, bci);
 }
 
 template <typename T>
@@ -4292,11 +4390,6 @@ template <typename T>
 void Kern<T>::float_setup(const PlanDev& P, const T* Sc, T* Lam, double* eps, double* fdelta, hipStream_t s) {
   if (P.n_pinned == 0) return;
   k_float_setup<T><<<P.n_sub, 256, (size_t)hmax(P.max_na, 1) * sizeof(double), s>>>(P, Sc, Lam, eps, fdelta);
-}
-template <typename T>
-void Kern<T>::float_phi(const PlanDev& P, const double* eps, T* PhiG, hipStream_t s) {
-  if (P.n_pinned == 0 || P.max_nc == 0) return;
-  k_float_phi<T><<<dim3(cdiv((int64_t)P.max_ns * P.max_nc, 256), P.n_sub), 256, 0, s>>>(P, eps, PhiG);
 }
 template <typename T>
 void Kern<T>::float_mu(const PlanDev& P, const T* gv, T* mu_io, const double* eps, const double* fdelta,

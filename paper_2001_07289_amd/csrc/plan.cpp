@@ -764,7 +764,7 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
     S.T_off = T_off;
     T_off += (int64_t)S.n_a * S.n_c;
     S.PhiG_off = PhiG_off;
-    PhiG_off += (int64_t)S.n_s * S.n_c;
+    PhiG_off += (int64_t)S.n_s * S.n_v;
     S.YG_off = YG_off;
     YG_off += (int64_t)S.n_g * S.n_v;
     S.Kc_off = Kc_off;

@@ -40,9 +40,10 @@ struct SubDev {
   int64_t sel_off;   // offset of the selected-row table
   int64_t XG_off;    // n_s x n_a (ld n_s): rows of X at the selected rows (0 at vertices)
   int64_t Sc_off;    // n_a x n_a: constraint Schur complement, swept
-  int64_t T_off;     // n_a x n_c: C_r Y - [0 I], then Lambda
-  int64_t PhiG_off;  // n_s x n_c (ld n_s): rows of Phi at the selected rows (the first
-                     // n_g are the Gamma entries)
+  int64_t T_off;     // n_a x n_c: C_r Y - [0 I] (then Lambda's vertex columns packed,
+                     // n_a x n_v), and Lambda in a buffer of its own
+  int64_t PhiG_off;  // n_s x n_v (ld n_s): Phi's vertex columns at the selected rows (the
+                     // first n_g are the Gamma entries)
   int64_t YG_off;    // n_g x n_v (ld n_g): Y' at the Gamma entries (the unit entry of
                      // its coarse dof at a Gamma entry that is a primal vertex)
   int64_t Kc_off;    // n_c x n_c local coarse matrix
