@@ -252,7 +252,7 @@ struct bddcso_precond {
   double* vcoef = nullptr;    // stencil rows of the primal vertices (27 per vertex)
   int32_t* vcode = nullptr;
   int max_nv = 0;
-  double *fpool = nullptr, *fsw = nullptr, *bc = nullptr, *uc = nullptr, *fvec = nullptr, *xh = nullptr;
+  double *fpool = nullptr, *fsw = nullptr, *uc = nullptr, *fvec = nullptr, *xh = nullptr;
   double* fpart = nullptr;  // partial products of the split forward front step (few right-hand sides)
   int64_t fsw_stride = 0;
   int32_t* status = nullptr;
@@ -830,12 +830,14 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   pc->coarse_pending = leave_coarse;
 }
 
-void coarse_solve(bddcso_precond* pc, int nrhs, hipStream_t s) {
+// The coarse solve of the local right-hand sides bci (FP64 or FP32: one is
+// null), assembled into the fronts' vectors as the forward solve starts.
+void coarse_solve(bddcso_precond* pc, const double* bci_d, const float* bci_f, int nrhs, hipStream_t s) {
   const PlanDev& P = pc->P;
   const Plan& pl = *pc->plan;
   const int nlev = (int)pc->level_dev.size();
   const int64_t stride = pl.front_vec;
-  launch_front_vec_init(P, pc->all_fronts, pc->all_n, pc->all_maxn, pc->bc, pc->fvec, stride, nrhs, s);
+  launch_front_vec_init(P, pc->all_fronts, pc->all_n, pc->all_maxn, bci_d, bci_f, pc->fvec, stride, nrhs, s);
   double* part = nrhs < pc->P.mr_min ? pc->fpart : nullptr;
   const bool pull = part && P.front_pull;  // the chunked forward step gathers the children's values itself
   for (int L = 0; L < nlev; ++L) {
@@ -884,10 +886,9 @@ void apply_B(bddcso_precond* pc, const double* r, double* z, int nrhs, hipStream
   // X_Gamma^T g per average goes through lu, which lam_uc below refills
   // and only v2 (after the join) reads
   Kern<T>::coarse_rhs_local(P, N.XG, N.PhiG, N.Lam, pc->feps, N.gv, N.lu, N.bci, nrhs, pc->s2);
-  if (sizeof(T) == 8) launch_coarse_rhs_gather(P, (const double*)N.bci, nullptr, pc->bc, nrhs, pc->s2);
-  else launch_coarse_rhs_gather(P, nullptr, (const float*)N.bci, pc->bc, nrhs, pc->s2);
   if (pc->coarse_pending) HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_coarse, 0));
-  coarse_solve(pc, nrhs, pc->s2);
+  if (sizeof(T) == 8) coarse_solve(pc, (const double*)N.bci, nullptr, nrhs, pc->s2);
+  else coarse_solve(pc, nullptr, (const float*)N.bci, nrhs, pc->s2);
   Kern<T>::lam_uc(P, N.Lam, pc->uc, N.lu, nrhs, pc->s2);
   HIPCHK(hipEventRecord(pc->ev_cjoin, pc->s2));
   HIPCHK(hipStreamWaitEvent(s, pc->ev_cjoin, 0));
@@ -1085,7 +1086,6 @@ void layout(bddcso_precond* pc, hipStream_t s) {
   pc->status = m.alloc<int32_t>(1);
   pc->fpool = m.alloc<double>(pl.front_pool);
   const int nr = pc->max_nrhs;
-  pc->bc = m.alloc<double>(pl.n_coarse * nr);
   pc->uc = m.alloc<double>(pl.n_coarse * nr);
   pc->fvec = m.alloc<double>(pl.front_vec * nr);
   pc->xh = m.alloc<double>(pl.front_vec * nr);

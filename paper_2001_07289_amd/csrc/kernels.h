@@ -171,16 +171,14 @@ struct Kern {
   static void scatter_I(const PlanDev& P, const Geo& g, const T* vI, double* z, int nrhs, hipStream_t s);
 };
 
-void launch_coarse_rhs_gather(const PlanDev& P, const double* bci_d, const float* bci_f,
-                              double* bc, int nrhs, hipStream_t s);
 void launch_gamma_w(const PlanDev& P, const Geo& g, const double* v2_d, const float* v2_f,
                     const double* delta, double* z, int nrhs, hipStream_t s);
 void launch_front_zero_lower(const PlanDev& P, const int32_t* fronts, int nfr, int maxn, double* fpool,
                              hipStream_t s);
 void launch_front_child_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
                                 double* fpool, hipStream_t s);
-void launch_front_vec_init(const PlanDev& P, const int32_t* fr, int nfr, int maxn, const double* bc,
-                           double* fvec, int64_t fvec_stride, int nrhs, hipStream_t s);
+void launch_front_vec_init(const PlanDev& P, const int32_t* fr, int nfr, int maxn, const double* bci_d,
+                           const float* bci_f, double* fvec, int64_t fvec_stride, int nrhs, hipStream_t s);
 void launch_front_vec_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
                               double* fvec, int64_t fvec_stride, int nrhs, hipStream_t s);
 // pull: with part (the chunked single-RHS form), the entries take their

@@ -3414,16 +3414,6 @@ __global__ void k_scatter_I(PlanDev P, Geo g, const T* __restrict__ vI, double* 
       (double)vI[rhs * P.tot_I + S.I_off + i];
 }
 
-template <typename T>
-__global__ void k_coarse_rhs_gather(PlanDev P, const T* __restrict__ bci, double* __restrict__ bc) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int rhs = blockIdx.y;
-  if (c >= P.n_coarse) return;
-  double s = 0.0;
-  for (int k = P.crs_eptr[c]; k < P.crs_eptr[c + 1]; ++k) s += (double)bci[rhs * P.tot_c + P.crs_ent[k]];
-  bc[rhs * P.n_coarse + c] = s;
-}
-
 // w = E v2 on Gamma (weighted sum over the subdomains sharing each node).
 template <typename T>
 __global__ void k_gamma_w(PlanDev P, Geo g, const T* __restrict__ v2, const double* __restrict__ delta,
@@ -3441,13 +3431,23 @@ __global__ void k_gamma_w(PlanDev P, Geo g, const T* __restrict__ v2, const doub
 
 // ---- coarse multifrontal solve ------------------------------------------
 
-__global__ void k_front_vec_init(PlanDev P, const int32_t* __restrict__ fr, const double* __restrict__ bc,
+// Forward-solve vectors of every front: a pivot's entry is the coarse
+// right-hand side of its coarse dof, summed over the subdomains that share
+// the dof (b_c = sum_i R_ci^T bci), the other entries 0.  Every coarse dof
+// is the pivot of exactly one front.
+template <typename T>
+__global__ void k_front_vec_init(PlanDev P, const int32_t* __restrict__ fr, const T* __restrict__ bci,
                                  double* __restrict__ fvec, int64_t stride) {
   const FrontDev F = P.fronts[fr[blockIdx.y]];
   const int rhs = blockIdx.z;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= F.n) return;
-  fvec[rhs * stride + F.voff + k] = k < F.p ? bc[rhs * P.n_coarse + P.front_idx[F.idx_off + k]] : 0.0;
+  double v = 0.0;
+  if (k < F.p) {
+    const int c = P.front_idx[F.idx_off + k];
+    for (int e = P.crs_eptr[c]; e < P.crs_eptr[c + 1]; ++e) v += (double)bci[rhs * P.tot_c + P.crs_ent[e]];
+  }
+  fvec[rhs * stride + F.voff + k] = v;
 }
 
 __global__ void k_front_vec_scatter(PlanDev P, const int32_t* __restrict__ ch, double* __restrict__ fvec,
@@ -4433,14 +4433,6 @@ void launch_gamma_w(const PlanDev& P, const Geo& g, const double* v2_d, const fl
   else k_gamma_w<float><<<grid, 256, 0, s>>>(P, g, v2_f, delta, z);
 }
 
-void launch_coarse_rhs_gather(const PlanDev& P, const double* bci_d, const float* bci_f, double* bc,
-                              int nrhs, hipStream_t s) {
-  if (P.n_coarse == 0) return;
-  dim3 grid(cdiv(P.n_coarse, 256), nrhs);
-  if (bci_d) k_coarse_rhs_gather<double><<<grid, 256, 0, s>>>(P, bci_d, bc);
-  else k_coarse_rhs_gather<float><<<grid, 256, 0, s>>>(P, bci_f, bc);
-}
-
 void launch_front_zero_lower(const PlanDev& P, const int32_t* fronts, int nfr, int maxn, double* fpool,
                              hipStream_t s) {
   if (nfr == 0 || maxn == 0) return;
@@ -4455,10 +4447,12 @@ void launch_front_child_scatter(const PlanDev& P, const int32_t* children, int n
   if (nchild == 0 || maxn == 0) return;
   k_front_child_scatter<<<dim3(cdiv(maxn, 4), nchild), 256, 0, s>>>(P, children, fpool);
 }
-void launch_front_vec_init(const PlanDev& P, const int32_t* fr, int nfr, int maxn, const double* bc,
-                           double* fvec, int64_t stride, int nrhs, hipStream_t s) {
+void launch_front_vec_init(const PlanDev& P, const int32_t* fr, int nfr, int maxn, const double* bci_d,
+                           const float* bci_f, double* fvec, int64_t stride, int nrhs, hipStream_t s) {
   if (nfr == 0 || maxn == 0) return;
-  k_front_vec_init<<<dim3(cdiv(maxn, 256), nfr, nrhs), 256, 0, s>>>(P, fr, bc, fvec, stride);
+  const dim3 grid(cdiv(maxn, 256), nfr, nrhs);
+  if (bci_d) k_front_vec_init<double><<<grid, 256, 0, s>>>(P, fr, bci_d, fvec, stride);
+  else k_front_vec_init<float><<<grid, 256, 0, s>>>(P, fr, bci_f, fvec, stride);
 }
 void launch_front_vec_scatter(const PlanDev& P, const int32_t* children, int nchild, int maxn,
                               double* fvec, int64_t stride, int nrhs, hipStream_t s) {
