@@ -767,7 +767,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   // the banded forward and backward solves the block GEMMs stand for
   if (pc->P_()) pc->prof.ref(3, pc->ref_basis_flops, 0.0);
   // constraint Schur complement and the coarse basis
-  Kern<T>::object_means(P, N.Z, N.Sc, N.Tm, s);  // S_c and the right-hand sides of Lambda
+  Kern<T>::object_means(P, N.Z, N.XG, N.Sc, N.Tm, s);  // X at the selected rows, S_c, Lambda's right-hand sides
   for (const Batch& b : pc->swSc) {
     Kern<T>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, N.Sc, N.sw, N.sw_stride, pc->status, 3, s,
                    pc->P_(), nullptr, pc->opt.sweep_reg_rows, pc->opt.slab_lookahead, pc->opt.update_tile, pc->opt.slab_width);
@@ -779,7 +779,7 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   Kern<T>::float_setup(P, N.Sc, N.Lam, pc->feps, pc->fdelta, s);
   // Phi = Y' - X Lambda, only at the selected rows (Gamma and the vertices'
   // stencils) and only in the vertex columns
-  Kern<T>::sel_gather(P, N.Z, N.Lam, N.XG, N.Tm, s);
+  Kern<T>::lam_vertex_cols(P, N.Lam, N.Tm, s);
   Kern<T>::gemm((GemmDesc*)pc->gSel.desc, pc->gSel.hg.data(), pc->gSel.n, pc->gSel.maxm, pc->gSel.maxn, N.XG, 0,
                 N.Tm, 0, N.PhiG, (T)-1, (T)0, s, pc->P_());
   ref_gemm_batch(pc, pc->gSel);
@@ -990,6 +990,7 @@ void layout(bddcso_precond* pc, hipStream_t s) {
   P.v_c = m.upload(pl.v_c, s);
   P.a_ptr = m.upload(pl.a_ptr, s);
   P.a_r = m.upload(pl.a_r, s);
+  P.a_g = m.upload(pl.a_g, s);
   P.a_c = m.upload(pl.a_c, s);
   P.c_glob = m.upload(pl.c_glob, s);
   P.c_kind = m.upload(pl.c_kind, s);

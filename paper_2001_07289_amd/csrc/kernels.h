@@ -64,7 +64,7 @@ struct PlanDev {
   const int32_t *g_loc, *g_gam, *g_r, *g_v, *g_sub;
   const int32_t *loc_sel, *sel_r;
   const int32_t *v_loc, *v_c;
-  const int32_t *a_ptr, *a_r, *a_c;
+  const int32_t *a_ptr, *a_r, *a_g, *a_c;  // a_g: selected row (Gamma entry) of each a_r node
   const int32_t *c_glob, *c_kind;
   const int32_t *gam_eptr, *gam_ent;
   const int64_t* gam_node;
@@ -127,9 +127,9 @@ struct Kern {
   static void rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, hipStream_t s);
   static void couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
                            int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s, int sub0, int nsub);
-  static void object_means(const PlanDev& P, const T* Z, T* Sc, T* Tm, hipStream_t s);
+  static void object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tm, hipStream_t s);
   // rows of [X | Phi initialised to Y'] at the selected rows
-  static void sel_gather(const PlanDev& P, const T* Z, const T* Lam, T* XS, T* LV, hipStream_t s);
+  static void lam_vertex_cols(const PlanDev& P, const T* Lam, T* LV, hipStream_t s);
   // also writes Y' at the Gamma entries (YG)
   static void phi_add(const PlanDev& P, const T* Z, T* PS, T* YG, int max_nv, hipStream_t s);
   static void kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PS,

@@ -2115,52 +2115,69 @@ __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd,
   }
 }
 
-// S_c = C_r X (lower triangle) and T = C_r Y - [0 I] in one pass.  C_r takes
-// the mean of a column over each average's r-set nodes (the objects own
-// disjoint node ranges a_r[a_ptr[a]..a_ptr[a+1])).  The column space is S_c's
-// n_a columns followed by T's n_c columns; a workgroup takes C of them,
-// stages their values at the objects' nodes in LDS (Z column b of X for S_c
-// column b, the vertex's column of Y' for a vertex column of T; an average
-// column of T is -e_a and reads nothing), then forms every mean of those
-// columns from LDS, summed in node order.  S_c = C_r K_rr^{-1} C_r^T is
+// X at the selected rows, S_c = C_r X (lower triangle) and
+// T = C_r Y - [0 I], in one pass over Z's columns.  The column space is
+// S_c's n_a columns (X's columns) followed by T's n_c columns; a workgroup
+// takes C of them and stages each one's values at the selected rows in LDS
+// (X's column b for S_c column b, also stored as XG's column b, 0 at a Gamma
+// entry that is a primal vertex; the vertex's column of Y' for a vertex
+// column of T; an average column of T is -e_a and reads nothing).  C_r
+// takes the mean of a column over each average's nodes, which are Gamma
+// entries, so selected rows (a_g over the ranges a_ptr[a]..a_ptr[a+1]);
+// every mean is summed from LDS in node order.  S_c = C_r K_rr^{-1} C_r^T is
 // symmetric and its sweep reads only the lower triangle, so only a >= b is
 // formed there.
 template <typename T, int C>
-__global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __restrict__ Z, T* __restrict__ Sc,
-                                                      T* __restrict__ Tm, int ld) {
+__global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __restrict__ Z, T* __restrict__ XG,
+                                                      T* __restrict__ Sc, T* __restrict__ Tm, int ld) {
   extern __shared__ unsigned char om_smem[];
-  T* zs = (T*)om_smem;  // [C][ld]
+  T* zs = (T*)om_smem;                                    // [C][ld]: the columns at the selected rows
+  int* ag = (int*)(om_smem + (size_t)C * ld * sizeof(T));  // selected row of each average node
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
-  const int na = S.n_a, ncol = na + S.n_c;
+  const int na = S.n_a, ncol = na + S.n_c, ns = S.n_s;
   const int j0 = blockIdx.x * C;
   if (j0 >= ncol) return;
   const int a0 = P.a_ptr[S.a_off], nar = P.a_ptr[S.a_off + na] - a0;
   int zc[C];  // Z column staged for each local column, -1: none
-  int tb[C];  // first staged node: S_c column b needs only the objects a >= b
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     const int jj = j0 + j;
     zc[j] = -1;
-    tb[j] = 0;
     if (jj < na) {
       zc[j] = P.z_col[S.c_off + jj];
-      tb[j] = P.a_ptr[S.a_off + jj] - a0;
     } else if (jj < ncol) {
       const int kind = P.c_kind[S.c_off + jj - na];
       if (kind >= 0) zc[j] = P.z_col[S.c_off + na + kind];
     }
   }
-  int tmin = nar;
-#pragma unroll
-  for (int j = 0; j < C; ++j)
-    if (zc[j] >= 0) tmin = min(tmin, tb[j]);
+  for (int t = threadIdx.x; t < nar; t += blockDim.x) ag[t] = P.a_g[a0 + t];
   const T* z = Z + S.Z_off;
-  for (int t = tmin + threadIdx.x; t < nar; t += blockDim.x) {
-    const int64_t r = P.a_r[a0 + t];
+  // four rows per thread at a time: their row indices first, then all the
+  // gathers (4 C loads in flight)
+  for (int t0 = 0; t0 < ns; t0 += 4 * (int)blockDim.x) {
+    int r[4];
 #pragma unroll
-    for (int j = 0; j < C; ++j)
-      if (zc[j] >= 0 && t >= tb[j]) zs[j * ld + t] = z[r + S.n_r * (int64_t)zc[j]];
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + threadIdx.x + u * blockDim.x;
+      r[u] = t < ns ? P.sel_r[S.sel_off + t] : -1;
+    }
+    T v[4][C];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < C; ++j) v[u][j] = (zc[j] >= 0 && r[u] >= 0) ? z[r[u] + S.n_r * (int64_t)zc[j]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + threadIdx.x + u * blockDim.x;
+      if (t >= ns) continue;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        if (zc[j] < 0) continue;
+        zs[j * ld + t] = v[u][j];
+        if (j0 + j < na) XG[S.XG_off + t + (int64_t)ns * (j0 + j)] = v[u][j];
+      }
+    }
   }
   __syncthreads();
   const int nj = min(C, ncol - j0);
@@ -2176,7 +2193,7 @@ __global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __rest
       const int pb = P.a_ptr[S.a_off + a] - a0, pe = P.a_ptr[S.a_off + a + 1] - a0;
       const T* col = zs + j * ld;
       double acc = 0.0;
-      for (int t = pb; t < pe; ++t) acc += (double)col[t];
+      for (int t = pb; t < pe; ++t) acc += (double)col[ag[t]];
       v = acc / (double)(pe - pb);
     } else {
       v = (-P.c_kind[S.c_off + jj - na] - 1 == a) ? -1.0 : 0.0;
@@ -2188,32 +2205,17 @@ __global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __rest
   }
 }
 
-// Rows of X at the selected rows (0 at a Gamma entry that is a primal vertex),
-// and Lambda's vertex columns packed (n_a x n_v, ld n_a, in the right-hand
-// side buffer, which is free once Lambda is formed): the operands of the
+// Lambda's vertex columns packed (n_a x n_v, ld n_a, in the right-hand side
+// buffer, which is free once Lambda is formed): the right operand of the
 // product -X Lambda, which only Phi's vertex columns need.
 template <typename T>
-__global__ void k_sel_gather(PlanDev P, const T* __restrict__ Z, const T* __restrict__ Lam, T* __restrict__ XS,
-                             T* __restrict__ LV) {
+__global__ void k_lam_vertex_cols(PlanDev P, const T* __restrict__ Lam, T* __restrict__ LV) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < S.n_a * S.n_v; idx += gridDim.x * blockDim.x) {
-    const int a = idx % S.n_a, v = idx / S.n_a;
-    LV[S.T_off + idx] = Lam[S.T_off + a + (int64_t)S.n_a * P.v_c[S.v_off + v]];
-  }
-  // thread (row e, 8 columns): one index load, eight gathers in flight
-  const int na8 = (S.n_a + 7) / 8, tot = S.n_s * na8;  // per subdomain: 32-bit index math
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
-    const int e = idx % S.n_s, a0 = (idx / S.n_s) * 8;
-    const int r = P.sel_r[S.sel_off + e];
-    T xv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      xv[u] = (r >= 0 && a0 + u < S.n_a) ? Z[S.Z_off + r + (int64_t)S.n_r * P.z_col[S.c_off + a0 + u]] : (T)0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (a0 + u < S.n_a) XS[S.XG_off + e + (int64_t)S.n_s * (a0 + u)] = xv[u];
-  }
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= S.n_a * S.n_v) return;
+  const int a = idx % S.n_a, v = idx / S.n_a;
+  LV[S.T_off + idx] = Lam[S.T_off + a + (int64_t)S.n_a * P.v_c[S.v_off + v]];
 }
 
 // Phi's vertex columns at the selected rows (n_s x n_v, column v for vertex
@@ -3971,7 +3973,7 @@ int64_t max_lds_bytes(const PlanDev& P, int elt, int max_nrhs) {
   if (max_nrhs >= P.mr_min) need = hmax(need, (int64_t)hmax(P.max_block, 1) * (MR_COLS + 1) * elt);  // many-rhs block solve
   need = hmax(need, (int64_t)(P.max_na + P.max_nc + 1) * elt);                         // v2
   need = hmax(need, (int64_t)hmax(P.max_ng, 1) * elt);                                 // coarse rhs
-  need = hmax(need, (int64_t)hmax(P.max_nar, 1) * elt);                                // object means
+  need = hmax(need, (int64_t)hmax(P.max_ns, 1) * elt + (int64_t)P.max_nar * 4);        // object means
   need = hmax(need, kc_lds_bytes(P));                                                  // local coarse matrices
   need = hmax(need, (int64_t)SWEEP_ROWS * (SWEEP_NB + 1) * elt + 2 * 32 * 33 * 8);   // sweep panel
   return need;
@@ -4246,24 +4248,28 @@ void Kern<T>::couple_multi(const PlanDev& P, const Geo& g, const double* rho, in
 }
 
 template <typename T>
-void Kern<T>::object_means(const PlanDev& P, const T* Z, T* Sc, T* Tm, hipStream_t s) {
+void Kern<T>::object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tm, hipStream_t s) {
   if (P.n_sub == 0 || P.max_na == 0) return;
-  const int ld = hmax(P.max_nar, 1);
-  const int64_t col = (int64_t)ld * sizeof(T);
+  const int ld = hmax(P.max_ns, 1);
+  const int64_t col = (int64_t)ld * sizeof(T), idx = (int64_t)P.max_nar * 4;
   const int ncol = P.max_na + P.max_nc;
-  if (8 * col <= 32 * 1024)
-    k_object_means<T, 8><<<dim3(cdiv(ncol, 8), P.n_sub), 256, 8 * col, s>>>(P, Z, Sc, Tm, ld);
-  else if (4 * col <= 32 * 1024)
-    k_object_means<T, 4><<<dim3(cdiv(ncol, 4), P.n_sub), 256, 4 * col, s>>>(P, Z, Sc, Tm, ld);
+  // at most 24 KB of LDS per workgroup: more resident workgroups (gathers
+  // in flight) count for more than fewer re-reads of the index arrays
+  if (8 * col + idx <= 24 * 1024)
+    k_object_means<T, 8><<<dim3(cdiv(ncol, 8), P.n_sub), 256, 8 * col + idx, s>>>(P, Z, XG, Sc, Tm, ld);
+  else if (4 * col + idx <= 24 * 1024)
+    k_object_means<T, 4><<<dim3(cdiv(ncol, 4), P.n_sub), 256, 4 * col + idx, s>>>(P, Z, XG, Sc, Tm, ld);
+  else if (2 * col + idx <= 24 * 1024)
+    k_object_means<T, 2><<<dim3(cdiv(ncol, 2), P.n_sub), 256, 2 * col + idx, s>>>(P, Z, XG, Sc, Tm, ld);
   else
-    k_object_means<T, 1><<<dim3(ncol, P.n_sub), 256, col, s>>>(P, Z, Sc, Tm, ld);
+    k_object_means<T, 1><<<dim3(ncol, P.n_sub), 256, col + idx, s>>>(P, Z, XG, Sc, Tm, ld);
 }
 
 template <typename T>
-void Kern<T>::sel_gather(const PlanDev& P, const T* Z, const T* Lam, T* XS, T* LV, hipStream_t s) {
-  const int64_t tot = (int64_t)P.max_ns * cdiv(P.max_na, 8);
+void Kern<T>::lam_vertex_cols(const PlanDev& P, const T* Lam, T* LV, hipStream_t s) {
+  const int64_t tot = (int64_t)P.max_na * P.max_nv;
   if (tot == 0) return;
-  k_sel_gather<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, Lam, XS, LV);
+  k_lam_vertex_cols<T><<<dim3(cdiv(tot, 256), P.n_sub), 256, 0, s>>>(P, Lam, LV);
 }
 
 template <typename T>

@@ -637,6 +637,7 @@ bool build_plan(const Classification& c, int primal_mask, int block_target, int 
         c.node_coords(c.gam_node[q], gcoord);
         int l = (gcoord[0] - S.lo[0]) + S.m[0] * ((gcoord[1] - S.lo[1]) + S.m[1] * (gcoord[2] - S.lo[2]));
         plan.a_r.push_back(lr[l]);
+        plan.a_g.push_back(lg[l]);
       }
       plan.a_c.push_back(k);
       plan.a_ptr.push_back((int32_t)plan.a_r.size());

@@ -80,6 +80,7 @@ struct Plan {
   std::vector<int32_t> sel_r;     // per selected row: r rank (-1 at primal vertices)
   std::vector<int32_t> v_loc, v_c;            // per vertex: local node, local coarse index
   std::vector<int32_t> a_ptr, a_r, a_c;       // averages: CSR of r ranks; local coarse index
+  std::vector<int32_t> a_g;                   // per a_r entry: its Gamma-local index (= selected row)
   std::vector<int32_t> c_glob, c_kind;        // per local coarse: global id; vertex idx or -(a+1)
   std::vector<BlockDev> blocks;
   // plane couplings between consecutive blocks: per row (a node of a block's
