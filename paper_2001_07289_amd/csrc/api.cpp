@@ -767,7 +767,9 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   // the banded forward and backward solves the block GEMMs stand for
   if (pc->P_()) pc->prof.ref(3, pc->ref_basis_flops, 0.0);
   // constraint Schur complement and the coarse basis
-  Kern<T>::object_means(P, N.Z, N.XG, N.Sc, N.Tm, s);  // X at the selected rows, S_c, Lambda's right-hand sides
+  // X at the selected rows, S_c, Lambda's right-hand sides, and Y' in Phi's
+  // vertex columns and at the Gamma entries
+  Kern<T>::object_means(P, N.Z, N.XG, N.Sc, N.Tm, N.PhiG, N.YG, s);
   for (const Batch& b : pc->swSc) {
     Kern<T>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, N.Sc, N.sw, N.sw_stride, pc->status, 3, s,
                    pc->P_(), nullptr, pc->opt.sweep_reg_rows, pc->opt.slab_lookahead, pc->opt.update_tile, pc->opt.slab_width);
@@ -781,9 +783,8 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   // stencils) and only in the vertex columns
   Kern<T>::lam_vertex_cols(P, N.Lam, N.Tm, s);
   Kern<T>::gemm((GemmDesc*)pc->gSel.desc, pc->gSel.hg.data(), pc->gSel.n, pc->gSel.maxm, pc->gSel.maxn, N.XG, 0,
-                N.Tm, 0, N.PhiG, (T)-1, (T)0, s, pc->P_());
+                N.Tm, 0, N.PhiG, (T)-1, (T)1, s, pc->P_());  // added to Y' (and the unit rows) already there
   ref_gemm_batch(pc, pc->gSel);
-  Kern<T>::phi_add(P, N.Z, N.PhiG, N.YG, pc->max_nv, s);  // and Y' at the Gamma entries
   Kern<T>::kc_identity(P, g, rho, N.PhiG, N.Lam, N.Kc, pc->vcoef, pc->vcode, pc->max_nv, s);
   // The interior (Dirichlet) factors are needed only when the preconditioner
   // is applied, so they are built on a third stream while the coarse

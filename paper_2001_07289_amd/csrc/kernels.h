@@ -127,11 +127,10 @@ struct Kern {
   static void rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, hipStream_t s);
   static void couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
                            int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s, int sub0, int nsub);
-  static void object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tm, hipStream_t s);
+  static void object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tm, T* PhiG, T* YG, hipStream_t s);
   // rows of [X | Phi initialised to Y'] at the selected rows
   static void lam_vertex_cols(const PlanDev& P, const T* Lam, T* LV, hipStream_t s);
   // also writes Y' at the Gamma entries (YG)
-  static void phi_add(const PlanDev& P, const T* Z, T* PS, T* YG, int max_nv, hipStream_t s);
   static void kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PS,
                           const T* Lam, T* Kc, double* vcoef, int32_t* vcode, int max_nv, hipStream_t s);
   static void kc_to_front(const PlanDev& P, const int32_t* subs_of_color, int ns, const T* Kc,

@@ -2126,10 +2126,15 @@ __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd,
 // entries, so selected rows (a_g over the ranges a_ptr[a]..a_ptr[a+1]);
 // every mean is summed from LDS in node order.  S_c = C_r K_rr^{-1} C_r^T is
 // symmetric and its sweep reads only the lower triangle, so only a >= b is
-// formed there.
+// formed there.  A vertex's column of Y' is also stored at the selected rows
+// as Phi's column of that vertex (the product then adds -X Lambda_v), with
+// the unit entry of the vertex's coarse dof in the rows of Gamma entries
+// that are primal vertices, and its Gamma rows as YG, for the
+// preconditioner's application.
 template <typename T, int C>
 __global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __restrict__ Z, T* __restrict__ XG,
-                                                      T* __restrict__ Sc, T* __restrict__ Tm, int ld) {
+                                                      T* __restrict__ Sc, T* __restrict__ Tm,
+                                                      T* __restrict__ PhiG, T* __restrict__ YG, int ld) {
   extern __shared__ unsigned char om_smem[];
   T* zs = (T*)om_smem;                                    // [C][ld]: the columns at the selected rows
   int* ag = (int*)(om_smem + (size_t)C * ld * sizeof(T));  // selected row of each average node
@@ -2140,15 +2145,20 @@ __global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __rest
   if (j0 >= ncol) return;
   const int a0 = P.a_ptr[S.a_off], nar = P.a_ptr[S.a_off + na] - a0;
   int zc[C];  // Z column staged for each local column, -1: none
+  int vx[C];  // the vertex of a vertex column of T, -1: none
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     const int jj = j0 + j;
     zc[j] = -1;
+    vx[j] = -1;
     if (jj < na) {
       zc[j] = P.z_col[S.c_off + jj];
     } else if (jj < ncol) {
       const int kind = P.c_kind[S.c_off + jj - na];
-      if (kind >= 0) zc[j] = P.z_col[S.c_off + na + kind];
+      if (kind >= 0) {
+        zc[j] = P.z_col[S.c_off + na + kind];
+        vx[j] = kind;
+      }
     }
   }
   for (int t = threadIdx.x; t < nar; t += blockDim.x) ag[t] = P.a_g[a0 + t];
@@ -2176,6 +2186,11 @@ __global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __rest
         if (zc[j] < 0) continue;
         zs[j * ld + t] = v[u][j];
         if (j0 + j < na) XG[S.XG_off + t + (int64_t)ns * (j0 + j)] = v[u][j];
+        if (vx[j] >= 0) {
+          const T y = r[u] >= 0 ? v[u][j] : (P.g_v[S.g_off + t] == vx[j] ? (T)1 : (T)0);
+          PhiG[S.PhiG_off + t + (int64_t)ns * vx[j]] = y;
+          if (t < S.n_g) YG[S.YG_off + t + (int64_t)S.n_g * vx[j]] = y;
+        }
       }
     }
   }
@@ -2216,35 +2231,6 @@ __global__ void k_lam_vertex_cols(PlanDev P, const T* __restrict__ Lam, T* __res
   if (idx >= S.n_a * S.n_v) return;
   const int a = idx % S.n_a, v = idx / S.n_a;
   LV[S.T_off + idx] = Lam[S.T_off + a + (int64_t)S.n_a * P.v_c[S.v_off + v]];
-}
-
-// Phi's vertex columns at the selected rows (n_s x n_v, column v for vertex
-// v): after the product has written -X Lambda there, add
-// Y' = -K_rr^{-1} K_rv and put the unit entry of the vertex's coarse dof in
-// the rows of Gamma entries that are primal vertices (X is 0 there).  Phi's
-// average columns are -X Lambda (plus 1 e^T / delta on a pinned subdomain)
-// and are never formed: the application reads X and Lambda instead.  The Gamma entries are the first
-// n_g selected rows, so the same pass also stores Y' there (YG, with the
-// same unit entries) for the preconditioner's application.
-template <typename T>
-__global__ void k_phi_add(PlanDev P, const T* __restrict__ Z, T* __restrict__ PS, T* __restrict__ YG) {
-  const int sub = blockIdx.y;
-  const SubDev S = P.subs[sub];
-  const int tot = S.n_s * S.n_v;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
-    const int e = idx % S.n_s, v = idx / S.n_s;
-    const int r = P.sel_r[S.sel_off + e];
-    T* dst = PS + S.PhiG_off + e + (int64_t)S.n_s * v;
-    T y;
-    if (r >= 0) {
-      y = Z[S.Z_off + r + (int64_t)S.n_r * P.z_col[S.c_off + S.n_a + v]];
-      *dst = y + *dst;
-    } else {
-      y = P.g_v[S.g_off + e] == v ? (T)1 : (T)0;
-      if (y != (T)0) *dst = y;
-    }
-    if (e < S.n_g) YG[S.YG_off + e + (int64_t)S.n_g * v] = y;
-  }
 }
 
 // Local coarse matrix from the equations that define Phi.  With the
@@ -4248,21 +4234,21 @@ void Kern<T>::couple_multi(const PlanDev& P, const Geo& g, const double* rho, in
 }
 
 template <typename T>
-void Kern<T>::object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tm, hipStream_t s) {
-  if (P.n_sub == 0 || P.max_na == 0) return;
+void Kern<T>::object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tm, T* PhiG, T* YG, hipStream_t s) {
+  if (P.n_sub == 0 || P.max_nc == 0) return;
   const int ld = hmax(P.max_ns, 1);
   const int64_t col = (int64_t)ld * sizeof(T), idx = (int64_t)P.max_nar * 4;
   const int ncol = P.max_na + P.max_nc;
   // at most 24 KB of LDS per workgroup: more resident workgroups (gathers
   // in flight) count for more than fewer re-reads of the index arrays
   if (8 * col + idx <= 24 * 1024)
-    k_object_means<T, 8><<<dim3(cdiv(ncol, 8), P.n_sub), 256, 8 * col + idx, s>>>(P, Z, XG, Sc, Tm, ld);
+    k_object_means<T, 8><<<dim3(cdiv(ncol, 8), P.n_sub), 256, 8 * col + idx, s>>>(P, Z, XG, Sc, Tm, PhiG, YG, ld);
   else if (4 * col + idx <= 24 * 1024)
-    k_object_means<T, 4><<<dim3(cdiv(ncol, 4), P.n_sub), 256, 4 * col + idx, s>>>(P, Z, XG, Sc, Tm, ld);
+    k_object_means<T, 4><<<dim3(cdiv(ncol, 4), P.n_sub), 256, 4 * col + idx, s>>>(P, Z, XG, Sc, Tm, PhiG, YG, ld);
   else if (2 * col + idx <= 24 * 1024)
-    k_object_means<T, 2><<<dim3(cdiv(ncol, 2), P.n_sub), 256, 2 * col + idx, s>>>(P, Z, XG, Sc, Tm, ld);
+    k_object_means<T, 2><<<dim3(cdiv(ncol, 2), P.n_sub), 256, 2 * col + idx, s>>>(P, Z, XG, Sc, Tm, PhiG, YG, ld);
   else
-    k_object_means<T, 1><<<dim3(ncol, P.n_sub), 256, col + idx, s>>>(P, Z, XG, Sc, Tm, ld);
+    k_object_means<T, 1><<<dim3(ncol, P.n_sub), 256, col + idx, s>>>(P, Z, XG, Sc, Tm, PhiG, YG, ld);
 }
 
 template <typename T>
@@ -4270,13 +4256,6 @@ void Kern<T>::lam_vertex_cols(const PlanDev& P, const T* Lam, T* LV, hipStream_t
   const int64_t tot = (int64_t)P.max_na * P.max_nv;
   if (tot == 0) return;
   k_lam_vertex_cols<T><<<dim3(cdiv(tot, 256), P.n_sub), 256, 0, s>>>(P, Lam, LV);
-}
-
-template <typename T>
-void Kern<T>::phi_add(const PlanDev& P, const T* Z, T* PS, T* YG, int max_nv, hipStream_t s) {
-  const int64_t tot = (int64_t)P.max_ns * max_nv;
-  if (tot == 0) return;
-  k_phi_add<T><<<dim3(hmin(cdiv(tot, 256), 2048), P.n_sub), 256, 0, s>>>(P, Z, PS, YG);
 }
 
 template <typename T>
