@@ -494,7 +494,9 @@ void build_batches(bddcso_precond* pc, hipStream_t s) {
       const SubDev& S = pl.subs[sidx];
       if (S.n_a > 0) {
         d.push_back({S.Sc_off, S.n_a, S.n_a, S.n_a});
-        if (S.n_c > 0) lam.push_back({S.Sc_off, S.T_off, S.T_off, S.n_a, S.n_c, S.n_a, S.n_a, S.n_a, S.n_a});
+        // only Lambda's vertex columns need the product (T_v packed in the
+        // Lambda buffer, Lambda_v packed in the right-hand side buffer)
+        if (S.n_v > 0) lam.push_back({S.Sc_off, S.T_off, S.T_off, S.n_a, S.n_v, S.n_a, S.n_a, S.n_a, S.n_a});
       }
       // every subdomain with vertices: the product writes Phi's vertex
       // columns at all selected rows (-X Lambda_v, 0 when there are no
@@ -767,21 +769,22 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   // the banded forward and backward solves the block GEMMs stand for
   if (pc->P_()) pc->prof.ref(3, pc->ref_basis_flops, 0.0);
   // constraint Schur complement and the coarse basis
-  // X at the selected rows, S_c, Lambda's right-hand sides, and Y' in Phi's
+  // X at the selected rows, S_c, the vertex columns of Lambda's right-hand
+  // sides (packed in Lambda's buffer until the product), and Y' in Phi's
   // vertex columns and at the Gamma entries
-  Kern<T>::object_means(P, N.Z, N.XG, N.Sc, N.Tm, N.PhiG, N.YG, s);
+  Kern<T>::object_means(P, N.Z, N.XG, N.Sc, N.Lam, N.PhiG, N.YG, s);
   for (const Batch& b : pc->swSc) {
     Kern<T>::sweep((SweepDesc*)b.desc, b.hs.data(), b.n, b.maxn, b.maxp, N.Sc, N.sw, N.sw_stride, pc->status, 3, s,
                    pc->P_(), nullptr, pc->opt.sweep_reg_rows, pc->opt.slab_lookahead, pc->opt.update_tile, pc->opt.slab_width);
     ref_sweep_batch(pc, b);
   }
   Kern<T>::gemm((GemmDesc*)pc->gLam.desc, pc->gLam.hg.data(), pc->gLam.n, pc->gLam.maxm, pc->gLam.maxn, N.Sc, 0,
-                N.Tm, 0, N.Lam, (T)-1, (T)0, s, pc->P_());
+                N.Lam, 0, N.Tm, (T)-1, (T)0, s, pc->P_());
   ref_gemm_batch(pc, pc->gLam);
+  Kern<T>::lam_assemble(P, N.Sc, N.Tm, N.Lam, s);
   Kern<T>::float_setup(P, N.Sc, N.Lam, pc->feps, pc->fdelta, s);
   // Phi = Y' - X Lambda, only at the selected rows (Gamma and the vertices'
   // stencils) and only in the vertex columns
-  Kern<T>::lam_vertex_cols(P, N.Lam, N.Tm, s);
   Kern<T>::gemm((GemmDesc*)pc->gSel.desc, pc->gSel.hg.data(), pc->gSel.n, pc->gSel.maxm, pc->gSel.maxn, N.XG, 0,
                 N.Tm, 0, N.PhiG, (T)-1, (T)1, s, pc->P_());  // added to Y' (and the unit rows) already there
   ref_gemm_batch(pc, pc->gSel);

@@ -127,9 +127,9 @@ struct Kern {
   static void rhs_fill(const PlanDev& P, const Geo& g, const double* rho, T* Z, hipStream_t s);
   static void couple_multi(const PlanDev& P, const Geo& g, const double* rho, int k, int fwd,
                            int ncols_max, T* Z, T* tmp, int64_t tmp_stride, hipStream_t s, int sub0, int nsub);
-  static void object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tm, T* PhiG, T* YG, hipStream_t s);
+  static void object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tv, T* PhiG, T* YG, hipStream_t s);
   // rows of [X | Phi initialised to Y'] at the selected rows
-  static void lam_vertex_cols(const PlanDev& P, const T* Lam, T* LV, hipStream_t s);
+  static void lam_assemble(const PlanDev& P, const T* Sc, const T* LV, T* Lam, hipStream_t s);
   // also writes Y' at the Gamma entries (YG)
   static void kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PS,
                           const T* Lam, T* Kc, double* vcoef, int32_t* vcode, int max_nv, hipStream_t s);

@@ -2126,14 +2126,17 @@ __global__ __launch_bounds__(256) void k_couple_multi(PlanDev P, int k, int fwd,
 // entries, so selected rows (a_g over the ranges a_ptr[a]..a_ptr[a+1]);
 // every mean is summed from LDS in node order.  S_c = C_r K_rr^{-1} C_r^T is
 // symmetric and its sweep reads only the lower triangle, so only a >= b is
-// formed there.  A vertex's column of Y' is also stored at the selected rows
+// formed there.  T's vertex columns are stored packed (n_a x n_v, ld n_a,
+// column v for vertex v): its average columns -e_a are not stored, since
+// Lambda's average columns are columns of the swept S_c (k_lam_assemble).
+// A vertex's column of Y' is also stored at the selected rows
 // as Phi's column of that vertex (the product then adds -X Lambda_v), with
 // the unit entry of the vertex's coarse dof in the rows of Gamma entries
 // that are primal vertices, and its Gamma rows as YG, for the
 // preconditioner's application.
 template <typename T, int C>
 __global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __restrict__ Z, T* __restrict__ XG,
-                                                      T* __restrict__ Sc, T* __restrict__ Tm,
+                                                      T* __restrict__ Sc, T* __restrict__ Tv,
                                                       T* __restrict__ PhiG, T* __restrict__ YG, int ld) {
   extern __shared__ unsigned char om_smem[];
   T* zs = (T*)om_smem;                                    // [C][ld]: the columns at the selected rows
@@ -2199,38 +2202,39 @@ __global__ __launch_bounds__(256) void k_object_means(PlanDev P, const T* __rest
   for (int e = threadIdx.x; e < nj * na; e += blockDim.x) {
     const int j = e / na, a = e - j * na, jj = j0 + j;
     if (jj < na && a < jj) continue;  // S_c: lower triangle only
-    int zcj = -1;
+    int zcj = -1, vxj = -1;
 #pragma unroll
     for (int q = 0; q < C; ++q)
-      if (q == j) zcj = zc[q];
-    double v;
-    if (zcj >= 0) {
-      const int pb = P.a_ptr[S.a_off + a] - a0, pe = P.a_ptr[S.a_off + a + 1] - a0;
-      const T* col = zs + j * ld;
-      double acc = 0.0;
-      for (int t = pb; t < pe; ++t) acc += (double)col[ag[t]];
-      v = acc / (double)(pe - pb);
-    } else {
-      v = (-P.c_kind[S.c_off + jj - na] - 1 == a) ? -1.0 : 0.0;
-    }
+      if (q == j) {
+        zcj = zc[q];
+        vxj = vx[q];
+      }
+    if (zcj < 0) continue;  // an average column of T: -e_a, never stored
+    const int pb = P.a_ptr[S.a_off + a] - a0, pe = P.a_ptr[S.a_off + a + 1] - a0;
+    const T* col = zs + j * ld;
+    double acc = 0.0;
+    for (int t = pb; t < pe; ++t) acc += (double)col[ag[t]];
+    const double v = acc / (double)(pe - pb);
     if (jj < na)
       Sc[S.Sc_off + a + (int64_t)na * jj] = (T)v;
     else
-      Tm[S.T_off + a + (int64_t)na * (jj - na)] = (T)v;
+      Tv[S.T_off + a + (int64_t)na * vxj] = (T)v;
   }
 }
 
-// Lambda's vertex columns packed (n_a x n_v, ld n_a, in the right-hand side
-// buffer, which is free once Lambda is formed): the right operand of the
-// product -X Lambda, which only Phi's vertex columns need.
+// Lambda = -S_c^{-1} T in coarse order.  The swept S_c holds -S_c^{-1} (both
+// triangles), and T's average column of average a' is -e_a', so Lambda's
+// column there is the swept S_c's column a'; the vertex columns are the
+// product's output, packed (n_a x n_v, ld n_a).
 template <typename T>
-__global__ void k_lam_vertex_cols(PlanDev P, const T* __restrict__ Lam, T* __restrict__ LV) {
+__global__ void k_lam_assemble(PlanDev P, const T* __restrict__ Sc, const T* __restrict__ LV, T* __restrict__ Lam) {
   const int sub = blockIdx.y;
   const SubDev S = P.subs[sub];
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= S.n_a * S.n_v) return;
-  const int a = idx % S.n_a, v = idx / S.n_a;
-  LV[S.T_off + idx] = Lam[S.T_off + a + (int64_t)S.n_a * P.v_c[S.v_off + v]];
+  if (idx >= S.n_a * S.n_c) return;
+  const int a = idx % S.n_a, c = idx / S.n_a;
+  const int kind = P.c_kind[S.c_off + c];
+  Lam[S.T_off + idx] = kind < 0 ? Sc[S.Sc_off + a + (int64_t)S.n_a * (-kind - 1)] : LV[S.T_off + a + (int64_t)S.n_a * kind];
 }
 
 // Local coarse matrix from the equations that define Phi.  With the
@@ -4234,7 +4238,7 @@ void Kern<T>::couple_multi(const PlanDev& P, const Geo& g, const double* rho, in
 }
 
 template <typename T>
-void Kern<T>::object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tm, T* PhiG, T* YG, hipStream_t s) {
+void Kern<T>::object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tv, T* PhiG, T* YG, hipStream_t s) {
   if (P.n_sub == 0 || P.max_nc == 0) return;
   const int ld = hmax(P.max_ns, 1);
   const int64_t col = (int64_t)ld * sizeof(T), idx = (int64_t)P.max_nar * 4;
@@ -4242,20 +4246,20 @@ void Kern<T>::object_means(const PlanDev& P, const T* Z, T* XG, T* Sc, T* Tm, T*
   // at most 24 KB of LDS per workgroup: more resident workgroups (gathers
   // in flight) count for more than fewer re-reads of the index arrays
   if (8 * col + idx <= 24 * 1024)
-    k_object_means<T, 8><<<dim3(cdiv(ncol, 8), P.n_sub), 256, 8 * col + idx, s>>>(P, Z, XG, Sc, Tm, PhiG, YG, ld);
+    k_object_means<T, 8><<<dim3(cdiv(ncol, 8), P.n_sub), 256, 8 * col + idx, s>>>(P, Z, XG, Sc, Tv, PhiG, YG, ld);
   else if (4 * col + idx <= 24 * 1024)
-    k_object_means<T, 4><<<dim3(cdiv(ncol, 4), P.n_sub), 256, 4 * col + idx, s>>>(P, Z, XG, Sc, Tm, PhiG, YG, ld);
+    k_object_means<T, 4><<<dim3(cdiv(ncol, 4), P.n_sub), 256, 4 * col + idx, s>>>(P, Z, XG, Sc, Tv, PhiG, YG, ld);
   else if (2 * col + idx <= 24 * 1024)
-    k_object_means<T, 2><<<dim3(cdiv(ncol, 2), P.n_sub), 256, 2 * col + idx, s>>>(P, Z, XG, Sc, Tm, PhiG, YG, ld);
+    k_object_means<T, 2><<<dim3(cdiv(ncol, 2), P.n_sub), 256, 2 * col + idx, s>>>(P, Z, XG, Sc, Tv, PhiG, YG, ld);
   else
-    k_object_means<T, 1><<<dim3(ncol, P.n_sub), 256, col + idx, s>>>(P, Z, XG, Sc, Tm, PhiG, YG, ld);
+    k_object_means<T, 1><<<dim3(ncol, P.n_sub), 256, col + idx, s>>>(P, Z, XG, Sc, Tv, PhiG, YG, ld);
 }
 
 template <typename T>
-void Kern<T>::lam_vertex_cols(const PlanDev& P, const T* Lam, T* LV, hipStream_t s) {
-  const int64_t tot = (int64_t)P.max_na * P.max_nv;
+void Kern<T>::lam_assemble(const PlanDev& P, const T* Sc, const T* LV, T* Lam, hipStream_t s) {
+  const int64_t tot = (int64_t)P.max_na * P.max_nc;
   if (tot == 0) return;
-  k_lam_vertex_cols<T><<<dim3(cdiv(tot, 256), P.n_sub), 256, 0, s>>>(P, Lam, LV);
+  k_lam_assemble<T><<<dim3(cdiv(tot, 256), P.n_sub), 256, 0, s>>>(P, Sc, LV, Lam);
 }
 
 template <typename T>
