@@ -686,6 +686,8 @@ void numeric_setup(bddcso_precond* pc, hipStream_t s, bool leave_coarse) {
   HIPCHK(hipEventRecord(pc->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(pc->s2, pc->ev_fork, 0));
   launch_coupling_coefs(P, g, rho, pc->cpl_coef, pc->ipl_coef, pc->s2);
+  // the vertex stencils depend on rho only; the second stream has slack here
+  launch_vertex_stencil(P, g, rho, pc->vcoef, pc->vcode, pc->max_nv, pc->s2);
   HIPCHK(hipEventRecord(pc->ev_cpl, pc->s2));
   launch_alpha(P, pc->prob->c.n_ss, rho, pc->opt.weighting, pc->alpha, s);
   launch_kig_fill(P, g, rho, s);

@@ -93,6 +93,9 @@ struct PlanDev {
 // ---- launchers (defined in kernels.hip) ---------------------------------
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s, int max_blocks = 65536);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+// the primal vertices' stencil coefficients and codes (k_kc_identity's input)
+void launch_vertex_stencil(const PlanDev& P, const Geo& g, const double* rho, double* vcoef, int32_t* vcode,
+                           int max_nv, hipStream_t s);
 // the K_{I Gamma} entries of every interior node (free index of the Gamma
 // neighbour and the stiffness entry from rho) and the K_{Gamma I} entries of
 // every Gamma entry (interior index of the neighbour and the entry)

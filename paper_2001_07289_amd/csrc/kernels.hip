@@ -4265,15 +4265,21 @@ void Kern<T>::lam_assemble(const PlanDev& P, const T* Sc, const T* LV, T* Lam, h
 template <typename T>
 void Kern<T>::kc_identity(const PlanDev& P, const Geo& g, const double* rho, const T* PhiR, const T* Lam, T* Kc,
                           double* vcoef, int32_t* vcode, int max_nv, hipStream_t s) {
+  (void)g;
+  (void)rho;
   if (P.max_nc == 0) return;
-  if (max_nv > 0)
-    k_vertex_stencil<<<dim3(cdiv((int64_t)max_nv * 27, 256), P.n_sub), 256, 0, s>>>(P, g, rho, nullptr, vcoef, vcode);
   const int cols = kc_cols(P);
   if (max_nv > 0)
     k_kc_identity<T><<<dim3(cdiv(max_nv, cols), P.n_sub), 256, (size_t)kc_lds_bytes(P), s>>>(
         P, PhiR, vcoef, vcode, Kc, cols, kc_stage_stencils(P) ? 1 : 0);
   const int nt = cdiv(P.max_nc, 32);
   k_kc_symmetrize<T><<<dim3(nt * (nt + 1) / 2, P.n_sub), 256, 0, s>>>(P, Lam, Kc);
+}
+
+void launch_vertex_stencil(const PlanDev& P, const Geo& g, const double* rho, double* vcoef, int32_t* vcode,
+                           int max_nv, hipStream_t s) {
+  if (max_nv > 0)
+    k_vertex_stencil<<<dim3(cdiv((int64_t)max_nv * 27, 256), P.n_sub), 256, 0, s>>>(P, g, rho, nullptr, vcoef, vcode);
 }
 
 template <typename T>
