@@ -3249,8 +3249,9 @@ __global__ __launch_bounds__(256) void k_v2(PlanDev P, const T* __restrict__ vR,
 }
 
 // lu = Lambda u_c per subdomain and right-hand side: one workgroup per
-// (subdomain, rhs), the local coarse values staged in LDS, one thread per
-// average row (Lambda read along its columns).
+// (subdomain, rhs, 64 rows of Lambda), the local coarse values staged in
+// LDS, one lane per average row (Lambda read along its columns, four waves
+// over the columns).
 template <typename T>
 __global__ __launch_bounds__(256) void k_lam_uc(PlanDev P, const T* __restrict__ Lam,
                                                 const double* __restrict__ uc, T* __restrict__ lu) {
@@ -3258,14 +3259,16 @@ __global__ __launch_bounds__(256) void k_lam_uc(PlanDev P, const T* __restrict__
   double* ucl = reinterpret_cast<double*>(smem_raw);
   const int sub = blockIdx.x, rhs = blockIdx.y;
   const SubDev S = P.subs[sub];
+  const int r0 = blockIdx.z * 64;  // this workgroup's 64 rows of Lambda
+  if (r0 >= S.n_a) return;
+  const int nr = min(64, S.n_a - r0);
   for (int c = threadIdx.x; c < S.n_c; c += blockDim.x) ucl[c] = uc[rhs * P.n_coarse + P.c_glob[S.c_off + c]];
   __syncthreads();
-  const T* L = Lam + S.T_off;
+  const T* L = Lam + S.T_off + r0;
   double* part = ucl + P.max_nc;
-  gemv_split4<double>(L, S.n_a, S.n_a, S.n_c, ucl, part, P.max_na);
-  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x)
-    lu[rhs * P.tot_a + S.am_off + a] =
-        (T)((part[a] + part[P.max_na + a]) + (part[2 * P.max_na + a] + part[3 * P.max_na + a]));
+  gemv_split4<double>(L, S.n_a, nr, S.n_c, ucl, part, 64);
+  for (int a = threadIdx.x; a < nr; a += blockDim.x)
+    lu[rhs * P.tot_a + S.am_off + r0 + a] = (T)((part[a] + part[64 + a]) + (part[128 + a] + part[192 + a]));
 }
 
 // ---------------------------------------------------------------------------
@@ -4402,8 +4405,8 @@ void Kern<T>::float_v2(const PlanDev& P, const double* uc, const double* eps, co
 template <typename T>
 void Kern<T>::lam_uc(const PlanDev& P, const T* Lam, const double* uc, T* lu, int nrhs, hipStream_t s) {
   if (P.max_na == 0) return;
-  k_lam_uc<T><<<dim3(P.n_sub, nrhs), 256, (size_t)(hmax(P.max_nc, 1) + 4 * (size_t)P.max_na) * sizeof(double), s>>>(
-      P, Lam, uc, lu);
+  k_lam_uc<T><<<dim3(P.n_sub, nrhs, cdiv(P.max_na, 64)), 256, (size_t)(hmax(P.max_nc, 1) + 4 * 64) * sizeof(double),
+                 s>>>(P, Lam, uc, lu);
 }
 
 template <typename T>
