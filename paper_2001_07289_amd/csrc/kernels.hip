@@ -3001,7 +3001,7 @@ __global__ void k_neumann_rhs(PlanDev P, const T* __restrict__ gv, T* __restrict
   if (r >= 0) vR[rhs * P.tot_r + S.r_off + r] = gv[rhs * P.tot_g + S.g_off + e];
 }
 
-// mu = S_c^{-1} C_r u, one workgroup per (subdomain, rhs).  Sc holds the
+// mu = S_c^{-1} C_r u, one workgroup per (subdomain, rhs, 64 rows).  Sc holds the
 // swept matrix -S_c^{-1}.
 // Partial sums of y = M x (M: nrow x ncol, column-major with leading
 // dimension ld; x in LDS), accumulated in A, by a 256-thread workgroup: lane
@@ -3037,6 +3037,9 @@ __global__ __launch_bounds__(256) void k_mu(PlanDev P, const T* __restrict__ vR,
   T* av = reinterpret_cast<T*>(smem_raw);
   const int sub = blockIdx.x, rhs = blockIdx.y;
   const SubDev S = P.subs[sub];
+  const int r0 = blockIdx.z * 64;  // this workgroup's 64 rows of S_c
+  if (r0 >= S.n_a) return;
+  const int nr = min(64, S.n_a - r0);
   const T* u = vR + rhs * P.tot_r + S.r_off;
   for (int a = threadIdx.x; a < S.n_a; a += blockDim.x) {
     const int pb = P.a_ptr[S.a_off + a], pe = P.a_ptr[S.a_off + a + 1];
@@ -3045,13 +3048,13 @@ __global__ __launch_bounds__(256) void k_mu(PlanDev P, const T* __restrict__ vR,
     av[a] = (T)(s / (double)(pe - pb));
   }
   __syncthreads();
-  // the product with S_c: 64 rows per pass, the columns in four groups (one
-  // per wave), partial sums combined in a fixed order
-  const T* M = Sc + S.Sc_off;
+  // the product with this workgroup's 64 rows of S_c, the columns in four
+  // groups (one per wave), partial sums combined in a fixed order
+  const T* M = Sc + S.Sc_off + r0;
   T* part = av + P.max_na;
-  gemv_split4<T>(M, S.n_a, S.n_a, S.n_a, av, part, P.max_na);
-  for (int a = threadIdx.x; a < S.n_a; a += blockDim.x)
-    mu[rhs * P.tot_a + S.am_off + a] = -((part[a] + part[P.max_na + a]) + (part[2 * P.max_na + a] + part[3 * P.max_na + a]));
+  gemv_split4<T>(M, S.n_a, nr, S.n_a, av, part, 64);
+  for (int a = threadIdx.x; a < nr; a += blockDim.x)
+    mu[rhs * P.tot_a + S.am_off + r0 + a] = -((part[a] + part[64 + a]) + (part[128 + a] + part[192 + a]));
 }
 
 // Sum over the wave (every lane gets it; lane 0's pairing is that of the
@@ -4353,7 +4356,8 @@ void Kern<T>::neumann_rhs(const PlanDev& P, const T* gv, T* vR, int nrhs, hipStr
 template <typename T>
 void Kern<T>::mu(const PlanDev& P, const T* vR, const T* Sc, T* mu_out, int nrhs, hipStream_t s) {
   if (P.max_na == 0) return;
-  k_mu<T><<<dim3(P.n_sub, nrhs), 256, (size_t)5 * P.max_na * sizeof(T), s>>>(P, vR, Sc, mu_out);
+  k_mu<T><<<dim3(P.n_sub, nrhs, cdiv(P.max_na, 64)), 256, ((size_t)P.max_na + 4 * 64) * sizeof(T), s>>>(P, vR, Sc,
+                                                                                                    mu_out);
 }
 
 template <typename T>
